@@ -1,0 +1,171 @@
+"""CPU oracle for the recombination solver -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check in ``__graft_entry__`` and the CPU-baseline
+leg of ``bench.py`` may import this package.  The product path (the GPU
+library and its Python binding) never imports, links or runs it.
+
+* ``oracle.c`` (built to ``liboracle.so`` with plain gcc, no fast-math) holds
+  the solver itself, in FP64, written as plain loops from the paper.
+* ``closed_forms.py`` holds the paper's analytic theories (Jaffe, Boag) used to
+  pin the solver.
+* ``mlp.py`` holds the FP64 reference network for the surrogate kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
+          "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge")
+R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
+          "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
+          "col_neg_cathode", "dt", "steps", "flags", "max_beta_n")
+TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
+              "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released")
+NT = len(TRACE_KEYS)
+
+FLAG_MAX_STEPS, FLAG_NONFINITE, FLAG_REACTION, FLAG_EMPTY = 1, 2, 4, 8
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, IEEE arithmetic, no FMA)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        L.orc_dt.argtypes = [dp, i64, dp]
+        L.orc_dt.restype = ctypes.c_int
+        L.orc_weights.argtypes = [dp, i64, ctypes.c_double, ctypes.c_int, dp]
+        L.orc_weights.restype = None
+        L.orc_deposit.argtypes = [dp, i64, i64, i64, dp, i64, i64, ctypes.c_double, dp, dp]
+        L.orc_deposit.restype = ctypes.c_double
+        L.orc_uniform.argtypes = [dp, i64, i64, i64, ctypes.c_double, dp, dp]
+        L.orc_uniform.restype = ctypes.c_double
+        L.orc_step.argtypes = [dp, i64, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp]
+        L.orc_step.restype = None
+        L.orc_solve.argtypes = [dp, i64, i64, i64, dp, i64, i64, dp, dp, dp, dp]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_advance.argtypes = [dp, i64, i64, i64, ctypes.c_double, i64, dp, dp, dp]
+        L.orc_advance.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _params(ch):
+    return np.array([float(ch[k]) for k in P_KEYS], dtype=np.float64)
+
+
+def _shape(ch):
+    return (ch["nz"] + 1, ch["ny"], ch["nx"])
+
+
+def dt(ch) -> float:
+    out = np.zeros(1)
+    rc = lib().orc_dt(_ptr(_params(ch)), ch["nz"], _ptr(out))
+    if rc:
+        raise ValueError("no stable time step: neither drift nor diffusion constrains dt")
+    return float(out[0])
+
+
+def weights(ch, dt_, species: int):
+    """(c, sx, sy, sz) of the Appendix for species 0 (positive) or 1 (negative)."""
+    out = np.zeros(4)
+    lib().orc_weights(_ptr(_params(ch)), ch["nz"], dt_, species, _ptr(out))
+    return tuple(out)
+
+
+def deposit(ch, tracks, step: int, dt_, pos=None, neg=None):
+    """Deposit the tracks due at ``step`` into (pos, neg); returns (pos, neg, released)."""
+    shape = _shape(ch)
+    pos = np.zeros(shape) if pos is None else pos
+    neg = np.zeros(shape) if neg is None else neg
+    tr = np.ascontiguousarray(tracks, dtype=np.float64).reshape(-1, 7)
+    rel = lib().orc_deposit(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr),
+                            tr.shape[0], int(step), dt_, _ptr(pos), _ptr(neg))
+    return pos, neg, rel
+
+
+def uniform(ch, n0, pos=None, neg=None):
+    shape = _shape(ch)
+    pos = np.zeros(shape) if pos is None else pos
+    neg = np.zeros(shape) if neg is None else neg
+    rel = lib().orc_uniform(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], float(n0),
+                            _ptr(pos), _ptr(neg))
+    return pos, neg, rel
+
+
+def step(ch, dt_, pos, neg):
+    """One step; returns (new_pos, new_neg, tally dict)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    neg = np.ascontiguousarray(neg, dtype=np.float64)
+    npos, nneg = np.zeros_like(pos), np.zeros_like(neg)
+    tally = np.zeros(NT)
+    lib().orc_step(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], dt_, _ptr(pos), _ptr(neg),
+                   _ptr(npos), _ptr(nneg), _ptr(tally))
+    return npos, nneg, dict(zip(TRACE_KEYS, tally))
+
+
+def advance(ch, dt_, pos, neg, nsteps: int, with_trace: bool = False):
+    """Advance copies of (pos, neg) by nsteps without deposits."""
+    pos = np.array(pos, dtype=np.float64, order="C", copy=True)
+    neg = np.array(neg, dtype=np.float64, order="C", copy=True)
+    trace = np.zeros((nsteps, NT)) if with_trace else None
+    rc = lib().orc_advance(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], dt_, int(nsteps),
+                           _ptr(pos), _ptr(neg), _ptr(trace))
+    if rc:
+        raise MemoryError("oracle advance failed")
+    return (pos, neg, trace) if with_trace else (pos, neg)
+
+
+def solve(ch, tracks, with_trace: bool = False, with_fields: bool = True):
+    """Full run; returns a dict of the result, plus 'trace' [steps, NT] and
+    the final fields 'pos', 'neg' of shape (nz+1, ny, nx).  Trace columns are
+    ``TRACE_KEYS``."""
+    tr = np.ascontiguousarray(tracks, dtype=np.float64).reshape(-1, 7)
+    shape = _shape(ch)
+    pos, neg = np.zeros(shape), np.zeros(shape)
+    ms = int(ch["max_steps"])
+    trace = np.zeros((ms, NT)) if with_trace else None
+    res = np.zeros(len(R_KEYS))
+    rc = lib().orc_solve(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr), tr.shape[0],
+                         ms, _ptr(pos), _ptr(neg), _ptr(trace), _ptr(res))
+    if rc == -2:
+        raise ValueError("no stable time step")
+    if rc:
+        raise MemoryError("oracle solve failed")
+    out = dict(zip(R_KEYS, res.tolist()))
+    out["steps"] = int(out["steps"])
+    out["flags"] = int(out["flags"])
+    if with_trace:
+        out["trace"] = trace[: out["steps"]].copy()
+    if with_fields:
+        out["pos"], out["neg"] = pos, neg
+    return out

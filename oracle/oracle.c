@@ -1,0 +1,408 @@
+/*
+ * Plain FP64 CPU oracle of the IonTracks recombination solver.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call this code:
+ * only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * load it.  It shares no source, header or table with the GPU library; the two
+ * only see the same input dictionaries and track arrays.
+ *
+ * The arithmetic follows the paper step by step, written for clarity, not
+ * speed: single-threaded triple loops, no blocking, no fusion.
+ *
+ *   - linear ion-pair density N0 = LET / W                    (eq. linear_density)
+ *   - Gaussian radial track profile n0(r) = N0/(pi b^2) e^{-r^2/b^2}   (eq. Gaussian)
+ *   - transport  dn/dt = D lap n -/+ mu E . grad n - alpha n+ n-       (eq. theEquation,
+ *     with the uniform applied field, so div E = 0)
+ *   - grid x_i = i dx, ..., t_l = l dt and the weights c = mu E dt/dz,
+ *     s = D dt/dx^2                                            (Appendix)
+ *   - forward time difference, the drift derivative that blends a backward
+ *     and a central difference with weight c, the 3-point second difference
+ *                                                             (Appendix)
+ *   - the largest dt obeying 2(sx+sy+sz) + cx^2+cy^2+cz^2 <= 1 and
+ *     cx^2 cy^2 cz^2 <= 8 sx sy sz for both species           (eq. vNeum)
+ *   - electrodes at z=0 and z=d hold zero density; charge reaching them is
+ *     collected                                                 (Methods, Implementation)
+ *   - f = N_collected / N_released                              (eq. collection_efficiency)
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - x and y are periodic; the transverse cell is nx*dx by ny*dy.
+ *   - c carries the sign of the drift velocity (+mu E for positive ions,
+ *     -mu E for negative ions).  With that sign the paper's blended drift
+ *     derivative is exactly the Lax-Wendroff update.
+ *   - both species are updated from the old densities (Jacobi), so each node
+ *     removes the same beta n+ n- from both species (beta = alpha dt).
+ *   - "collected" in step l is what the pinned electrode plane would have
+ *     received from its interior neighbour in that step.
+ *   - N_released is the discrete sum of the deposited density times the
+ *     voxel volume.
+ *   - a track is deposited at the start of step floor(t/dt); the axis passes
+ *     through (x0, y0, d/2) with direction (sin th cos ph, sin th sin ph, cos th);
+ *     the transverse offset is wrapped to the nearest periodic image and the
+ *     profile is cut at r <= 8b.
+ *   - the run stops after the first step at which every track has been
+ *     deposited and, for both species, the sum of |n| dV over the grid is
+ *     <= stop_tol * N_released (the signed sum can dip below zero while
+ *     Lax-Wendroff undershoots are still in flight, so it is not used).
+ *
+ * Layout: each species is an array [nz+1][ny][nx] (x fastest) whose planes
+ * k = 0 and k = nz are the electrodes and always hold zero.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* parameter vector (mirrors the chamber dictionary) */
+enum {
+  P_DX, P_DY, P_GAP, P_VOLT, P_MU_POS, P_MU_NEG, P_D_POS, P_D_NEG,
+  P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_COUNT
+};
+/* result vector */
+enum {
+  R_F, R_KS, R_F_RECOMB, R_RELEASED, R_RECOMBINED, R_INFLIGHT_POS, R_INFLIGHT_NEG,
+  R_COL_POS_ANODE, R_COL_POS_CATHODE, R_COL_NEG_ANODE, R_COL_NEG_CATHODE,
+  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_COUNT
+};
+/* per-step record */
+enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_INFLIGHT, T_NEG_INFLIGHT,
+       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_COUNT };
+
+#define FLAG_MAX_STEPS 1
+#define FLAG_NONFINITE 2
+#define FLAG_REACTION 4
+#define FLAG_EMPTY 8
+
+#define IDX(k, j, i) (((size_t)(k) * (size_t)ny + (size_t)(j)) * (size_t)nx + (size_t)(i))
+
+/* Largest dt satisfying eq. vNeum for both species, times the safety factor.
+ * With the field along z only, cx = cy = 0: the product condition holds
+ * trivially and the first condition is A dt + B dt^2 <= 1 with
+ * A = 2 D (1/dx^2 + 1/dy^2 + 1/dz^2) and B = (mu E / dz)^2.
+ * Returns 0, or -2 if neither species constrains dt (no drift, no diffusion). */
+int orc_dt(const double *p, int64_t nz, double *dt)
+{
+  const double dz = p[P_GAP] / (double)nz;
+  const double E = p[P_VOLT] / p[P_GAP];
+  const double inv2 = 1.0 / (p[P_DX] * p[P_DX]) + 1.0 / (p[P_DY] * p[P_DY]) + 1.0 / (dz * dz);
+  const double mus[2] = {p[P_MU_POS], p[P_MU_NEG]};
+  const double Ds[2] = {p[P_D_POS], p[P_D_NEG]};
+  double best = INFINITY;
+  for (int s = 0; s < 2; ++s) {
+    const double A = 2.0 * Ds[s] * inv2;
+    const double v = mus[s] * E / dz;
+    const double B = v * v;
+    double root;
+    if (B > 0.0)
+      root = 2.0 / (A + sqrt(A * A + 4.0 * B)); /* positive root of B t^2 + A t - 1 */
+    else if (A > 0.0)
+      root = 1.0 / A;
+    else
+      continue;
+    if (root < best) best = root;
+  }
+  if (!(best < INFINITY)) return -2;
+  *dt = p[P_KAPPA] * best;
+  return 0;
+}
+
+/* Weights of the Appendix for species s (0 = positive, 1 = negative):
+ * w = {c, sx, sy, sz}, c signed with the drift velocity along +z. */
+void orc_weights(const double *p, int64_t nz, double dt, int s, double *w)
+{
+  const double dz = p[P_GAP] / (double)nz;
+  const double E = p[P_VOLT] / p[P_GAP];
+  const double mu = s == 0 ? p[P_MU_POS] : p[P_MU_NEG];
+  const double D = s == 0 ? p[P_D_POS] : p[P_D_NEG];
+  const double v = s == 0 ? mu * E : -mu * E;
+  w[0] = v * dt / dz;
+  w[1] = D * dt / (p[P_DX] * p[P_DX]);
+  w[2] = D * dt / (p[P_DY] * p[P_DY]);
+  w[3] = D * dt / (dz * dz);
+}
+
+static double wrap(double d, double L)
+{
+  return d - L * floor(d / L + 0.5);
+}
+
+/* Gaussian track profile of eq. Gaussian at node (i,j,k), 0 beyond 8b.
+ * tr = {let_keV_um, b, x0, y0, theta, phi, t}. */
+static double track_density(const double *p, int64_t nx, int64_t ny, int64_t nz,
+                            const double *tr, int64_t i, int64_t j, int64_t k)
+{
+  const double dz = p[P_GAP] / (double)nz;
+  const double N0 = tr[0] * 1.0e7 / p[P_W]; /* keV/um -> eV/cm, divided by W: pairs/cm */
+  const double b = tr[1];
+  const double ux = sin(tr[4]) * cos(tr[5]);
+  const double uy = sin(tr[4]) * sin(tr[5]);
+  const double uz = cos(tr[4]);
+  const double wx = wrap((double)i * p[P_DX] - tr[2], (double)nx * p[P_DX]);
+  const double wy = wrap((double)j * p[P_DY] - tr[3], (double)ny * p[P_DY]);
+  const double wz = (double)k * dz - 0.5 * p[P_GAP];
+  /* squared distance from the axis: |w x u|^2 */
+  const double cx = wy * uz - wz * uy;
+  const double cy = wz * ux - wx * uz;
+  const double cz = wx * uy - wy * ux;
+  const double r2 = cx * cx + cy * cy + cz * cz;
+  if (r2 > 64.0 * b * b) return 0.0;
+  return N0 / (M_PI * b * b) * exp(-r2 / (b * b));
+}
+
+int64_t orc_deposit_step(double dt, const double *tr)
+{
+  const double s = floor(tr[6] / dt);
+  if (s > 4.0e18) return INT64_MAX;
+  return (int64_t)s;
+}
+
+/* Add every track due at step `step` (list order) to both species.
+ * Returns the number of ion pairs released (sum of density times dV). */
+double orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
+                   const double *trk, int64_t ntr, int64_t step, double dt,
+                   double *pos, double *neg)
+{
+  const double dV = p[P_DX] * p[P_DY] * (p[P_GAP] / (double)nz);
+  double released = 0.0;
+  for (int64_t t = 0; t < ntr; ++t) {
+    const double *tr = trk + 7 * t;
+    if (orc_deposit_step(dt, tr) != step) continue;
+    double sum = 0.0;
+    for (int64_t k = 1; k < nz; ++k)
+      for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+          const double d = track_density(p, nx, ny, nz, tr, i, j, k);
+          pos[IDX(k, j, i)] += d;
+          neg[IDX(k, j, i)] += d;
+          sum += d;
+        }
+    released += sum * dV;
+  }
+  return released;
+}
+
+/* Uniform pre-ionisation n0 of both species at every interior node. */
+double orc_uniform(const double *p, int64_t nx, int64_t ny, int64_t nz, double n0,
+                   double *pos, double *neg)
+{
+  const double dV = p[P_DX] * p[P_DY] * (p[P_GAP] / (double)nz);
+  for (int64_t k = 1; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        pos[IDX(k, j, i)] += n0;
+        neg[IDX(k, j, i)] += n0;
+      }
+  return n0 * dV * (double)(nx * ny * (nz - 1));
+}
+
+/* One explicit step of eq. theEquation for both species from the old
+ * densities (pos, neg) into (npos, nneg).  tally receives the per-step
+ * record (T_*), all in ion counts (density times dV): recombined pairs,
+ * collected at each electrode per species, in-flight per species (signed
+ * sum of the new densities) and the sum of the new |n| per species.  The
+ * last slot (released before this step) is left at 0 here; the run fills it.
+ *
+ * For every interior node and species, with the Appendix's derivatives:
+ *   dn/dz  ~ c (n_k - n_{k-1})/dz + (1-c)(n_{k+1} - n_{k-1})/(2 dz)
+ *   d2n/dx2 ~ (n_{i+1} - 2 n_i + n_{i-1})/dx^2 (and y, z)
+ *   n' = n + dt [D lap n - v dn/dz] - alpha dt n+ n-
+ * where v is the signed drift velocity and c = v dt/dz. */
+void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
+              const double *pos, const double *neg, double *npos, double *nneg,
+              double *tally)
+{
+  const double dz = p[P_GAP] / (double)nz;
+  const double dV = p[P_DX] * p[P_DY] * dz;
+  const double beta = p[P_ALPHA] * dt;
+  double w[2][4];
+  orc_weights(p, nz, dt, 0, w[0]);
+  orc_weights(p, nz, dt, 1, w[1]);
+  const double *in[2] = {pos, neg};
+  double *out[2] = {npos, nneg};
+  double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0};
+
+  for (int64_t k = 1; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        const int64_t ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+        const int64_t jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+        const double np_ = pos[IDX(k, j, i)], nn_ = neg[IDX(k, j, i)];
+        const double sink = beta * np_ * nn_;
+        recomb += sink;
+        for (int s = 0; s < 2; ++s) {
+          const double *n = in[s];
+          const double c = w[s][0], sx = w[s][1], sy = w[s][2], sz = w[s][3];
+          const double nc = n[IDX(k, j, i)];
+          const double lap_x = n[IDX(k, j, ip)] - 2.0 * nc + n[IDX(k, j, im)];
+          const double lap_y = n[IDX(k, jp, i)] - 2.0 * nc + n[IDX(k, jm, i)];
+          const double lap_z = n[IDX(k + 1, j, i)] - 2.0 * nc + n[IDX(k - 1, j, i)];
+          /* c * dz * (dn/dz) with the blended derivative */
+          const double drift = c * (c * (nc - n[IDX(k - 1, j, i)])
+                                    + (1.0 - c) * 0.5 * (n[IDX(k + 1, j, i)] - n[IDX(k - 1, j, i)]));
+          const double v = nc + sx * lap_x + sy * lap_y + sz * lap_z - drift - sink;
+          out[s][IDX(k, j, i)] = v;
+          inflight[s] += v;
+          absolute[s] += fabs(v);
+        }
+      }
+
+  /* Collected in this step: what the electrode planes would receive from
+   * their interior neighbours.  Plane 0 gets the weight of n_{k+1} from node
+   * k=1; plane nz gets the weight of n_{k-1} from node k=nz-1. */
+  double col[2][2];
+  for (int s = 0; s < 2; ++s) {
+    const double c = w[s][0], sz = w[s][3];
+    const double w_up = sz + 0.5 * c * c - 0.5 * c;   /* weight of n_{k+1} */
+    const double w_down = sz + 0.5 * c * c + 0.5 * c; /* weight of n_{k-1} */
+    double a = 0.0, b = 0.0;
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        a += in[s][IDX(1, j, i)];
+        b += in[s][IDX(nz - 1, j, i)];
+      }
+    col[s][0] = w_up * a * dV;
+    col[s][1] = w_down * b * dV;
+  }
+  tally[T_RECOMB] = recomb * dV;
+  tally[T_POS_ANODE] = col[0][0];
+  tally[T_POS_CATHODE] = col[0][1];
+  tally[T_NEG_ANODE] = col[1][0];
+  tally[T_NEG_CATHODE] = col[1][1];
+  tally[T_POS_INFLIGHT] = inflight[0] * dV;
+  tally[T_NEG_INFLIGHT] = inflight[1] * dV;
+  tally[T_POS_ABS] = absolute[0] * dV;
+  tally[T_NEG_ABS] = absolute[1] * dV;
+  tally[T_RELEASED] = 0.0;
+}
+
+static double field_max(int64_t n, const double *a, const double *b)
+{
+  double m = 0.0;
+  for (int64_t q = 0; q < n; ++q) {
+    if (a[q] > m) m = a[q];
+    if (b[q] > m) m = b[q];
+  }
+  return m;
+}
+
+/* Full run: deposit, step, tally, stop (see the file header).
+ * pos/neg: caller-provided (nz+1)*ny*nx arrays, overwritten; hold the final
+ * densities on return.  trace: NULL or max_steps*T_COUNT doubles.
+ * res: R_COUNT doubles.  Returns 0 or a negative error. */
+int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
+              const double *trk, int64_t ntr, int64_t max_steps,
+              double *pos, double *neg, double *trace, double *res)
+{
+  double dt;
+  int rc = orc_dt(p, nz, &dt);
+  if (rc) return rc;
+  const int64_t n = (nz + 1) * ny * nx;
+  double *npos = (double *)calloc((size_t)n, sizeof(double));
+  double *nneg = (double *)calloc((size_t)n, sizeof(double));
+  if (!npos || !nneg) { free(npos); free(nneg); return -1; }
+  memset(pos, 0, (size_t)n * sizeof(double));
+  memset(neg, 0, (size_t)n * sizeof(double));
+
+  int64_t last_deposit = -1;
+  for (int64_t t = 0; t < ntr; ++t) {
+    int64_t s = orc_deposit_step(dt, trk + 7 * t);
+    if (s < max_steps && s > last_deposit) last_deposit = s;
+  }
+  const double beta = p[P_ALPHA] * dt;
+  double released = 0.0, sums[5] = {0, 0, 0, 0, 0}, last[T_COUNT] = {0};
+  double max_beta_n = 0.0;
+  int flags = 0;
+  int64_t steps = 0;
+  for (int64_t l = 0; l < max_steps; ++l) {
+    int deposited = 0;
+    double released_now = 0.0;
+    if (l == 0 && p[P_UNIFORM_N0] != 0.0) {
+      released_now += orc_uniform(p, nx, ny, nz, p[P_UNIFORM_N0], pos, neg);
+      deposited = 1;
+    }
+    for (int64_t t = 0; t < ntr; ++t)
+      if (orc_deposit_step(dt, trk + 7 * t) == l) { deposited = 1; break; }
+    if (deposited) {
+      released_now += orc_deposit(p, nx, ny, nz, trk, ntr, l, dt, pos, neg);
+      const double m = beta * field_max(n, pos, neg);
+      if (m > max_beta_n) max_beta_n = m;
+    }
+    released += released_now;
+    double tally[T_COUNT];
+    orc_step(p, nx, ny, nz, dt, pos, neg, npos, nneg, tally);
+    tally[T_RELEASED] = released_now;
+    double *tmp = pos; pos = npos; npos = tmp;
+    tmp = neg; neg = nneg; nneg = tmp;
+    for (int q = 0; q < 5; ++q) sums[q] += tally[q];
+    memcpy(last, tally, sizeof(last));
+    if (trace) memcpy(trace + T_COUNT * l, tally, sizeof(tally));
+    steps = l + 1;
+    int finite = 1;
+    for (int q = 0; q < T_COUNT; ++q) finite &= isfinite(tally[q]) != 0;
+    if (!finite) { flags |= FLAG_NONFINITE; break; }
+    if (l >= last_deposit && tally[T_POS_ABS] <= p[P_STOP_TOL] * released &&
+        tally[T_NEG_ABS] <= p[P_STOP_TOL] * released)
+      break;
+    if (steps == max_steps) flags |= FLAG_MAX_STEPS;
+  }
+  /* after an odd number of swaps the final fields sit in the scratch arrays */
+  if (steps % 2 == 1) {
+    memcpy(npos, pos, (size_t)n * sizeof(double));
+    memcpy(nneg, neg, (size_t)n * sizeof(double));
+    double *tmp = pos; pos = npos; npos = tmp;
+    tmp = neg; neg = nneg; nneg = tmp;
+  }
+  free(npos);
+  free(nneg);
+
+  if (max_beta_n > 1.0) flags |= FLAG_REACTION;
+  const double collected = sums[1] + sums[2] + sums[3] + sums[4];
+  double f;
+  if (released > 0.0) {
+    f = collected / (2.0 * released);
+  } else {
+    f = 1.0;
+    flags |= FLAG_EMPTY;
+  }
+  res[R_F] = f;
+  res[R_KS] = 1.0 / f;
+  res[R_F_RECOMB] = released > 0.0 ? 1.0 - sums[0] / released : 1.0;
+  res[R_RELEASED] = released;
+  res[R_RECOMBINED] = sums[0];
+  res[R_INFLIGHT_POS] = last[T_POS_INFLIGHT];
+  res[R_INFLIGHT_NEG] = last[T_NEG_INFLIGHT];
+  res[R_COL_POS_ANODE] = sums[1];
+  res[R_COL_POS_CATHODE] = sums[2];
+  res[R_COL_NEG_ANODE] = sums[3];
+  res[R_COL_NEG_CATHODE] = sums[4];
+  res[R_DT] = dt;
+  res[R_STEPS] = (double)steps;
+  res[R_FLAGS] = (double)flags;
+  res[R_MAX_BETA_N] = max_beta_n;
+  return 0;
+}
+
+/* Advance given densities by nsteps without deposits (tests of the stepping
+ * alone).  trace: NULL or nsteps*T_COUNT. */
+int orc_advance(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
+                int64_t nsteps, double *pos, double *neg, double *trace)
+{
+  const int64_t n = (nz + 1) * ny * nx;
+  double *npos = (double *)calloc((size_t)n, sizeof(double));
+  double *nneg = (double *)calloc((size_t)n, sizeof(double));
+  if (!npos || !nneg) { free(npos); free(nneg); return -1; }
+  double *a = pos, *b = neg, *c = npos, *d = nneg;
+  for (int64_t l = 0; l < nsteps; ++l) {
+    double tally[T_COUNT];
+    orc_step(p, nx, ny, nz, dt, a, b, c, d, tally);
+    if (trace) memcpy(trace + T_COUNT * l, tally, sizeof(tally));
+    double *t = a; a = c; c = t;
+    t = b; b = d; d = t;
+  }
+  if (a != pos) {
+    memcpy(pos, a, (size_t)n * sizeof(double));
+    memcpy(neg, b, (size_t)n * sizeof(double));
+  }
+  free(npos);
+  free(nneg);
+  return 0;
+}

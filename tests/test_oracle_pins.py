@@ -1,0 +1,450 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each checks it against
+a closed form, an exact invariant of the discrete scheme, an independent
+(dense-matrix) formulation, or a library routine.  They run on the CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import closed_forms as cf
+
+AIR_MU = 0.5 * (1.73 + 1.87)
+
+
+# ---------------------------------------------------------------------------
+# time step: eq. vNeum
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ch", [
+    W.single_track()[0],
+    W.pulsed_beam()[0],
+    W.chamber(10, 12, 30, 3e-4, 0.03, 100.0, dy=7e-4, D_pos=0.02, D_neg=0.07),
+    W.chamber(4, 4, 8, 1e-3, 0.08, 0.0),                       # no field: diffusion only
+    W.chamber(4, 4, 8, 1e-3, 0.08, 50.0, D_pos=0.0, D_neg=0.0),  # no diffusion: drift only
+])
+def test_dt_is_largest_step_satisfying_von_neumann(orc, ch):
+    dt = orc.dt(ch)
+    lhs = []
+    for s in (0, 1):
+        c, sx, sy, sz = orc.weights(ch, dt, s)
+        # eq. vNeum with c_x = c_y = 0: both inequalities, written out
+        assert 0.0 <= 8 * sx * sy * sz + 1e-300
+        lhs.append(2 * (sx + sy + sz) + c * c)
+    assert max(lhs) <= 1.0 + 1e-14
+    assert max(lhs) == pytest.approx(1.0, abs=1e-13)   # largest: the bound is tight
+    # 0.1% more would violate the bound for the limiting species
+    for s in (0, 1):
+        c, sx, sy, sz = orc.weights(ch, dt * 1.001, s)
+        lhs[s] = 2 * (sx + sy + sz) + c * c
+    assert max(lhs) > 1.0
+
+
+def test_dt_single_track_value(orc):
+    # E = 1500 V/cm, dz = 2e-4 cm: the negative ions (faster) limit dt.
+    ch, _ = W.single_track()
+    dt = orc.dt(ch)
+    A = 2 * 0.045 * 3 / (2e-4) ** 2
+    B = (1.87 * 1500 / 2e-4) ** 2
+    assert dt == pytest.approx((-A + math.sqrt(A * A + 4 * B)) / (2 * B), rel=1e-14)
+
+
+def test_dt_safety_factor_scales(orc):
+    ch = W.single_track()[0]
+    dt1 = orc.dt(ch)
+    ch["dt_safety"] = 0.5
+    assert orc.dt(ch) == pytest.approx(0.5 * dt1, rel=1e-15)
+
+
+def test_dt_no_transport_is_an_error(orc):
+    ch = W.chamber(4, 4, 8, 1e-3, 0.08, 0.0, D_pos=0.0, D_neg=0.0)
+    with pytest.raises(ValueError):
+        orc.dt(ch)
+
+
+def _checkerboard(ch, amp=1.0):
+    shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
+    k, j, i = np.indices(shape)
+    f = amp * (1.0 + 0.5 * (-1.0) ** (i + j + k))
+    f[0] = 0.0
+    f[-1] = 0.0
+    return np.ascontiguousarray(f)
+
+
+@pytest.mark.parametrize("ch", [
+    # diffusion-limited: no field, the checkerboard stays in the grid
+    W.chamber(8, 8, 40, 2e-4, 40 * 2e-4, 0.0, alpha=0.0),
+    # drift-limited: small diffusion, long gap so the mode stays in flight
+    W.chamber(4, 4, 600, 2e-4, 600 * 2e-4, 30.0, alpha=0.0, D_pos=1e-4, D_neg=1e-4),
+])
+def test_stable_at_kappa_one_unstable_beyond(orc, ch):
+    """The paper's bound is the edge of stability: the most oscillatory mode
+    does not grow at kappa = 1 and blows up with a 5% larger step."""
+    f = _checkerboard(ch)
+    dt = orc.dt(ch)
+    p, n = orc.advance(ch, dt, f, f, 250)
+    # Lax-Wendroff is not monotone, so allow a small overshoot, not growth
+    assert max(np.max(np.abs(p)), np.max(np.abs(n))) <= 2.0
+    p, n = orc.advance(ch, dt * 1.05, f, f, 250)
+    assert max(np.max(np.abs(p)), np.max(np.abs(n))) > 1e3
+
+
+# ---------------------------------------------------------------------------
+# one step against an independent dense-matrix formulation (Appendix)
+# ---------------------------------------------------------------------------
+
+def _dense_step(ch, dt, pos, neg):
+    """n^{l+1} = n^l + dt [ D (Dxx + Dyy + Dzz) n - v Dz n ] - alpha dt n+ n-,
+    with the Appendix's derivative matrices assembled on the full node grid
+    (electrode planes included), then the electrode planes read out as the
+    collected amounts and reset to zero."""
+    nx, ny, nz = ch["nx"], ch["ny"], ch["nz"]
+    dx, dy, dz = ch["dx"], ch["dy"], ch["gap"] / nz
+    E = ch["voltage"] / ch["gap"]
+    Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz + 1)
+
+    def periodic_second(m, h):
+        M = -2 * np.eye(m)
+        for a in range(m):
+            M[a, (a + 1) % m] += 1
+            M[a, (a - 1) % m] += 1
+        return M / h ** 2
+
+    def open_shift(m, off):
+        return np.eye(m, k=off)  # (S n)_a = n_{a+off}, zero outside
+
+    Dxx = np.kron(np.kron(Iz, Iy), periodic_second(nx, dx))
+    Dyy = np.kron(np.kron(Iz, periodic_second(ny, dy)), Ix)
+    up, down = open_shift(nz + 1, 1), open_shift(nz + 1, -1)
+    Dzz1 = (up - 2 * Iz + down) / dz ** 2
+    Dzz = np.kron(np.kron(Dzz1, Iy), Ix)
+    backward = (Iz - down) / dz          # (n_k - n_{k-1})/dz
+    central = (up - down) / (2 * dz)     # (n_{k+1} - n_{k-1})/(2 dz)
+    out, col = [], []
+    for s, (mu, D, sign) in enumerate([(ch["mu_pos"], ch["D_pos"], 1.0), (ch["mu_neg"], ch["D_neg"], -1.0)]):
+        v = sign * mu * E
+        c = v * dt / dz
+        Dz1 = c * backward + (1 - c) * central
+        Dz = np.kron(np.kron(Dz1, Iy), Ix)
+        M = np.eye((nz + 1) * ny * nx) + dt * (D * (Dxx + Dyy + Dzz) - v * Dz)
+        n_old = (pos, neg)[s].ravel()
+        n_new = M @ n_old - ch["alpha"] * dt * pos.ravel() * neg.ravel()
+        n_new = n_new.reshape(nz + 1, ny, nx)
+        dV = dx * dy * dz
+        col.append((n_new[0].sum() * dV, n_new[nz].sum() * dV))
+        n_new[0] = 0.0
+        n_new[nz] = 0.0
+        out.append(n_new)
+    return out[0], out[1], col
+
+
+@pytest.mark.parametrize("geom", [(4, 4, 5), (3, 5, 2), (1, 1, 7)])
+def test_one_step_matches_dense_matrix_scheme(orc, geom):
+    nx, ny, nz = geom
+    ch = W.chamber(nx, ny, nz, 3e-4, nz * 2.5e-4, 40.0, dy=4e-4, D_pos=0.03, D_neg=0.05,
+                   alpha=1.6e-6)
+    dt = orc.dt(ch)
+    pos, neg = W.perturbed_field((nz + 1, ny, nx), seed=7, scale=3e11)
+    p1, n1, tally = orc.step(ch, dt, pos, neg)
+    p2, n2, col = _dense_step(ch, dt, pos, neg)
+    scale = max(np.abs(pos).max(), np.abs(neg).max())
+    assert np.max(np.abs(p1 - p2)) <= 1e-14 * scale
+    assert np.max(np.abs(n1 - n2)) <= 1e-14 * scale
+    dV = ch["dx"] * ch["dy"] * ch["gap"] / nz
+    tot = (pos.sum() + neg.sum()) * dV
+    assert tally["pos_anode"] == pytest.approx(col[0][0], abs=1e-13 * tot)
+    assert tally["pos_cathode"] == pytest.approx(col[0][1], abs=1e-13 * tot)
+    assert tally["neg_anode"] == pytest.approx(col[1][0], abs=1e-13 * tot)
+    assert tally["neg_cathode"] == pytest.approx(col[1][1], abs=1e-13 * tot)
+    rec = ch["alpha"] * dt * np.sum(pos[1:nz] * neg[1:nz]) * dV
+    assert tally["recombined"] == pytest.approx(rec, rel=1e-13)
+    assert tally["pos_inflight"] == pytest.approx(p2.sum() * dV, rel=1e-13)
+    assert tally["neg_abs"] == pytest.approx(np.abs(n2).sum() * dV, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# exact discrete invariants: moments of the scheme (P3, P3c)
+# ---------------------------------------------------------------------------
+
+def _blob(ch, centre, sigma):
+    shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
+    k, j, i = np.indices(shape).astype(float)
+    r2 = ((i - centre[0]) ** 2 + (j - centre[1]) ** 2 + (k - centre[2]) ** 2)
+    f = 1e10 * np.exp(-r2 / (2 * sigma ** 2))
+    f[0] = 0.0
+    f[-1] = 0.0
+    return np.ascontiguousarray(f)
+
+
+def _moments(f, axis_len, axis, h):
+    coords = np.arange(axis_len) * h
+    m0 = f.sum()
+    proj = f.sum(axis=tuple(a for a in range(3) if a != axis))
+    m1 = (proj * coords).sum() / m0
+    var = (proj * (coords - m1) ** 2).sum() / m0
+    return m0, m1, var
+
+
+def test_pure_diffusion_moments_exact(orc):
+    """E = 0, alpha = 0: mass and mean are constant and every axis' variance
+    grows by exactly 2 D dt per step (explicit 3-point diffusion)."""
+    ch = W.chamber(48, 40, 44, 2e-4, 44 * 2.5e-4, 0.0, dy=3e-4, alpha=0.0, D_pos=0.03, D_neg=0.05)
+    dt = orc.dt(ch)
+    f = _blob(ch, (24, 20, 22), 1.6)
+    steps = 12
+    p, n = orc.advance(ch, dt, f, f, steps)
+    for field, D in ((p, 0.03), (n, 0.05)):
+        for axis, L, h in ((2, 48, 2e-4), (1, 40, 3e-4), (0, 45, 2.5e-4)):
+            m0a, m1a, va = _moments(f, L, axis, h)
+            m0b, m1b, vb = _moments(field, L, axis, h)
+            assert m0b == pytest.approx(m0a, rel=1e-13)
+            assert m1b == pytest.approx(m1a, rel=1e-13)
+            assert vb - va == pytest.approx(2 * D * dt * steps, rel=1e-10)
+
+
+def test_drift_diffusion_moments_exact(orc):
+    """alpha = 0, E > 0: the z-mean moves by exactly v dt per step (v = +mu+ E
+    for positive, -mu- E for negative ions) and the z-variance still grows by
+    exactly 2 D dt per step (Lax-Wendroff adds no variance)."""
+    ch = W.chamber(8, 8, 160, 2e-4, 160 * 2e-4, 40.0, alpha=0.0, D_pos=0.02, D_neg=0.04)
+    dt = orc.dt(ch)
+    E = ch["voltage"] / ch["gap"]
+    f = _blob(ch, (4, 4, 80), 3.0)
+    steps = 10
+    p, n = orc.advance(ch, dt, f, f, steps)
+    dz = ch["gap"] / ch["nz"]
+    for field, v, D in ((p, 1.73 * E, 0.02), (n, -1.87 * E, 0.04)):
+        m0a, m1a, va = _moments(f, 161, 0, dz)
+        m0b, m1b, vb = _moments(field, 161, 0, dz)
+        assert m0b == pytest.approx(m0a, rel=1e-13)
+        assert m1b - m1a == pytest.approx(v * dt * steps, rel=1e-10)
+        assert vb - va == pytest.approx(2 * D * dt * steps, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# deposition: eqs. linear_density, Gaussian, created; requirement (i)
+# ---------------------------------------------------------------------------
+
+def _lattice_sum(b, h, x0):
+    """h/(b sqrt(pi)) sum_m exp(-(m h - x0)^2 / b^2) by Poisson summation:
+    1 + 2 sum_k exp(-pi^2 k^2 b^2/h^2) cos(2 pi k x0/h)."""
+    return 1.0 + 2.0 * sum(math.exp(-(math.pi * k * b / h) ** 2) * math.cos(2 * math.pi * k * x0 / h)
+                           for k in range(1, 8))
+
+
+@pytest.mark.parametrize("b_over_h,frac", [(1.0, 0.0), (1.0, 0.37), (0.8, 0.5), (1.5, 0.21), (5.0, 0.0)])
+def test_released_count_matches_poisson_summation(orc, b_over_h, frac):
+    """I0 = dx dy sum n0 = N0 * Sx * Sy exactly, where S is the Gaussian's
+    lattice sum; a coarse grid makes S measurably differ from 1."""
+    h = 2e-4
+    b = b_over_h * h
+    n_cells = int(math.ceil(24 * b / h)) + 2
+    ch = W.chamber(n_cells, n_cells, 6, h, 6 * 2e-4, 10.0)
+    x0 = (n_cells // 2 + frac) * h
+    y0 = (n_cells // 2 + 0.5 * frac) * h
+    let = 7.5
+    tr = W.tracks([[let, b, x0, y0, 0.0, 0.0, 0.0]])
+    dt = orc.dt(ch)
+    _, _, rel = orc.deposit(ch, tr, 0, dt)
+    N0 = let * 1e7 / 34.0
+    expect = N0 * (ch["nz"] - 1) * (ch["gap"] / ch["nz"]) * _lattice_sum(b, h, frac * h) * \
+        _lattice_sum(b, h, 0.5 * frac * h)
+    assert rel == pytest.approx(expect, rel=1e-13)
+
+
+@pytest.mark.parametrize("theta,phi", [(math.radians(20), 0.3), (math.radians(30), 2.2), (math.radians(55), 4.0)])
+def test_tilted_track_line_density(orc, theta, phi):
+    """A track at angle theta crosses every plane z = const with N0/cos(theta)
+    ion pairs per unit height (eq. created with l = d/cos theta)."""
+    h = 2e-4
+    b = 5 * h
+    ch = W.chamber(96, 96, 20, h, 20 * 2e-4, 10.0)
+    tr = W.tracks([[2.0, b, 48 * h + 1e-5, 47 * h, theta, phi, 0.0]])
+    _, _, rel = orc.deposit(ch, tr, 0, orc.dt(ch))
+    N0 = 2.0 * 1e7 / 34.0
+    assert rel == pytest.approx(N0 * (ch["nz"] - 1) * (ch["gap"] / ch["nz"]) / math.cos(theta), rel=1e-12)
+
+
+def test_deposit_profile_is_gaussian_in_perpendicular_distance(orc):
+    ch = W.chamber(32, 32, 10, 2e-4, 10 * 2e-4, 10.0)
+    th, ph = 0.4, 1.1
+    x0, y0 = 16 * 2e-4 + 3e-5, 15 * 2e-4
+    b = 1.2e-3
+    tr = W.tracks([[3.0, b, x0, y0, th, ph, 0.0]])
+    pos, neg, _ = orc.deposit(ch, tr, 0, orc.dt(ch))
+    u = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    N0 = 3.0 * 1e7 / 34.0
+    for (k, j, i) in [(5, 16, 16), (3, 14, 19), (8, 20, 12), (1, 16, 16), (9, 10, 22)]:
+        p = np.array([i * 2e-4 - x0, j * 2e-4 - y0, k * 2e-4 - 1e-3])
+        r2 = float(p @ p - (p @ u) ** 2)
+        val = N0 / (math.pi * b * b) * math.exp(-r2 / b ** 2) if r2 <= 64 * b * b else 0.0
+        assert pos[k, j, i] == pytest.approx(val, rel=1e-12, abs=1e-300)
+        assert neg[k, j, i] == pos[k, j, i]
+    assert np.all(pos[0] == 0) and np.all(pos[-1] == 0)
+
+
+def test_track_deposited_at_floor_of_time_over_dt(orc):
+    ch, _ = W.single_track(max_steps=6, stop_tol=0.0)
+    dt = orc.dt(ch)
+    tr = W.tracks([[1.0, 1e-3, 32 * 2e-4, 32 * 2e-4, 0.0, 0.0, 2.999 * dt],
+                   [1.0, 1e-3, 32 * 2e-4, 32 * 2e-4, 0.0, 0.0, 40 * dt]])   # beyond max_steps
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    tr_ = r["trace"]
+    assert np.all(tr_[:2, 5] == 0.0) and tr_[2, 5] > 0.0
+    one = orc.deposit(ch, tr[:1], 2, dt)[2]
+    assert r["n_released"] == pytest.approx(one, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# conservation (P1), alpha -> 0 (P2)
+# ---------------------------------------------------------------------------
+
+def _check_conservation(r, tol=1e-12):
+    """released = collected + recombined + in flight, step by step and species
+    by species (the released column holds what was deposited before each step)."""
+    tr = r["trace"]
+    N = r["n_released"]
+    assert tr[:, 9].sum() == pytest.approx(N, rel=1e-14)
+    for s, (a, c, S) in enumerate(((1, 2, 5), (3, 4, 6))):
+        prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, 9]
+        err = prev - tr[:, a] - tr[:, c] - tr[:, 0] - tr[:, S]
+        assert np.max(np.abs(err)) <= tol * N
+
+
+def test_conservation_single_track(orc):
+    ch, tr = W.single_track()
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    _check_conservation(r)
+    assert r["flags"] == 0
+    assert r["f"] == pytest.approx(r["f_R"], abs=2e-12)
+
+
+def test_conservation_tilted_tracks_and_uniform(orc):
+    ch = W.chamber(24, 20, 30, 3e-4, 30 * 3e-4, 20.0, uniform_n0=3e9)
+    tr = W.tracks([[20.0, 8e-4, 1e-3, 2e-3, 0.4, 1.0, 0.0],
+                   [5.0, 6e-4, 5e-3, 1e-3, 0.2, 4.0, 1e-7]])
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    _check_conservation(r)
+
+
+def test_no_recombination_collects_everything(orc):
+    ch, tr = W.single_track(alpha=0.0)
+    r = orc.solve(ch, tr, with_fields=False)
+    assert abs(1.0 - r["f"]) <= 2e-12
+    assert r["n_recombined"] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# exact symmetries and linearity (P6-P8)
+# ---------------------------------------------------------------------------
+
+def test_species_swap_mirror_symmetry(orc):
+    base = dict(mu_pos=1.73, mu_neg=1.87, D_pos=0.045, D_neg=0.06)
+    swap = dict(mu_pos=1.87, mu_neg=1.73, D_pos=0.06, D_neg=0.045)
+    ch1, tr = W.single_track(**base)
+    ch2, _ = W.single_track(**swap)
+    tr[0, 0] = 20.0
+    ch1["max_steps"] = ch2["max_steps"] = 60        # both species still in flight
+    ch1["stop_tol"] = ch2["stop_tol"] = 0.0
+    r1 = orc.solve(ch1, tr)
+    r2 = orc.solve(ch2, tr)
+    assert r2["f"] == pytest.approx(r1["f"], rel=1e-12)
+    assert r2["col_pos_anode"] == pytest.approx(r1["col_neg_cathode"], rel=1e-10)
+    assert r2["col_pos_cathode"] == pytest.approx(r1["col_neg_anode"], rel=1e-10)
+    scale = max(r1["neg"].max(), r1["pos"].max())
+    assert np.max(np.abs(r2["pos"] - r1["neg"][::-1])) <= 1e-12 * scale
+    assert np.max(np.abs(r2["neg"] - r1["pos"][::-1])) <= 1e-12 * scale
+
+
+def test_periodic_translation_invariance(orc):
+    ch, tr = W.single_track(max_steps=60, stop_tol=0.0)
+    tr[0, 0] = 30.0
+    tr[0, 2] += 0.3e-4
+    r1 = orc.solve(ch, tr)
+    tr2 = tr.copy()
+    tr2[0, 2] += 7 * ch["dx"]
+    tr2[0, 3] -= 11 * ch["dy"]
+    r2 = orc.solve(ch, tr2)
+    assert r2["f"] == pytest.approx(r1["f"], rel=1e-12)
+    shifted = np.roll(np.roll(r1["pos"], 7, axis=2), -11, axis=1)
+    assert np.max(np.abs(r2["pos"] - shifted)) <= 1e-10 * r1["pos"].max()
+
+
+def test_linear_superposition_without_recombination(orc):
+    ch = W.chamber(20, 18, 24, 3e-4, 24 * 3e-4, 20.0, alpha=0.0, max_steps=25, stop_tol=0.0)
+    A = W.tracks([[5.0, 9e-4, 2e-3, 3e-3, 0.3, 0.5, 0.0]])
+    B = W.tracks([[9.0, 6e-4, 4e-3, 1e-3, 0.0, 0.0, 0.0]])
+    ra, rb = orc.solve(ch, A), orc.solve(ch, B)
+    rab = orc.solve(ch, np.concatenate([A, B]))
+    scale = rab["pos"].max()
+    assert np.max(np.abs(rab["pos"] - ra["pos"] - rb["pos"])) <= 1e-13 * scale
+    assert np.max(np.abs(rab["neg"] - ra["neg"] - rb["neg"])) <= 1e-13 * scale
+
+
+# ---------------------------------------------------------------------------
+# physics: Boag (pulsed general recombination) and Jaffe (initial recombination)
+# ---------------------------------------------------------------------------
+
+def _boag_run(orc, u, nz, D):
+    V, d = 200.0, 0.1
+    n0 = u * (1.73 + 1.87) * V / (1.6e-6 * d * d)
+    ch = W.chamber(1, 1, nz, 1e-3, d, V, uniform_n0=n0, D_pos=D, D_neg=D)
+    r = orc.solve(ch, W.no_tracks(), with_fields=False)
+    return r["f"], cf.boag(cf.boag_u(n0, d, V, 1.73, 1.87, 1.6e-6))
+
+
+@pytest.mark.parametrize("u", [0.1, 1.0, 10.0])
+def test_boag_pulsed_general_recombination(orc, u):
+    """Uniform pre-ionisation between the plates, no diffusion to speak of:
+    the solver converges to f = ln(1+u)/u at first order in dz."""
+    errs = []
+    for nz in (400, 800, 1600):
+        f, fb = _boag_run(orc, u, nz, 1e-4)
+        errs.append((f - fb) / fb)
+    assert abs(errs[-1]) < 2.5e-3 * max(u, 0.1) ** 0.5 + 1e-5
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert 0.4 < b / a < 0.6          # first-order convergence toward Boag
+
+
+def test_boag_with_air_diffusion_two_percent(orc):
+    for u in (0.1, 1.0, 10.0):
+        f, fb = _boag_run(orc, u, 200, 0.045)
+        assert abs(f - fb) / fb < 0.02
+
+
+@pytest.mark.parametrize("let", [0.1, 0.3, 1.0])
+def test_jaffe_parallel_track(orc, let):
+    """A single track parallel to the field in the weak-recombination regime
+    Jaffe's theory describes: the recombined fraction agrees within 5%."""
+    ch, tr = W.single_track()
+    tr[0, 0] = let
+    r = orc.solve(ch, tr, with_fields=False)
+    fj = cf.jaffe_parallel(let, 1e-3, ch["voltage"] / ch["gap"], ch["gap"], 0.045, AIR_MU, 1.6e-6)
+    assert abs((1 - r["f"]) / (1 - fj) - 1) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# degenerate inputs
+# ---------------------------------------------------------------------------
+
+def test_empty_track_list(orc):
+    ch = W.chamber(4, 4, 6, 1e-3, 6e-3, 10.0)
+    r = orc.solve(ch, W.no_tracks(), with_fields=False)
+    assert r["f"] == 1.0 and r["flags"] & 8 and r["steps"] == 1
+
+
+def test_single_interior_plane(orc):
+    ch = W.chamber(6, 6, 2, 2e-4, 4e-4, 5.0)
+    tr = W.tracks([[10.0, 4e-4, 6e-4, 6e-4, 0.0, 0.0, 0.0]])
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    _check_conservation(r)
+    assert 0.0 < r["f"] <= 1.0
+
+
+def test_max_steps_flag(orc):
+    ch, tr = W.single_track(max_steps=10)
+    r = orc.solve(ch, tr, with_fields=False)
+    assert r["steps"] == 10 and r["flags"] & 1

@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs for the recombination solver.
+
+This module only *describes* chambers and draws track lists.  It holds none of
+the method's arithmetic (no time step, no deposition, no transport), so the
+CPU oracle and the GPU library can both take their inputs from here without
+sharing any code of the method.
+
+A chamber is a plain ``dict`` whose keys mirror the C struct ``it_chamber``:
+
+    nx, ny      transverse node counts (periodic lateral boundaries)
+    nz          number of gap intervals; planes k=0 (anode) and k=nz (cathode)
+                are the electrodes, interior planes are 1..nz-1
+    dx, dy      transverse node spacing [cm]; the gap spacing is gap/nz
+    gap         electrode distance d [cm]
+    voltage     polarisation voltage V [V]; the field E = V/d points from the
+                anode (z=0) to the cathode (z=d)
+    mu_pos, mu_neg   ion mobilities [cm^2/(V s)]
+    D_pos, D_neg     ion diffusion constants [cm^2/s]
+    alpha       recombination constant [cm^3/s]
+    W_eV        mean energy per ion pair [eV]
+    dt_safety   factor kappa in (0,1] applied to the largest stable time step
+    stop_tol    stop once both in-flight counts are <= stop_tol * released
+    max_steps   hard limit on the number of time steps
+    uniform_n0  uniform ion-pair density added to both species at t=0 [cm^-3]
+    space_charge  1 adds the space-charge screening term, 0 leaves it out
+
+A track list is a float64 array of shape (n, 7) with columns
+``[let_keV_um, b_cm, x_cm, y_cm, theta, phi, t_s]``: linear energy transfer,
+Gaussian track radius, the point where the axis crosses mid-gap, the polar
+angle to the field, the azimuth, and the arrival time.
+
+The transport constants of dry air used by every workload here are the ones
+the workloads are specified with (mobilities 1.73/1.87, D = 0.045, alpha
+1.6e-6, W = 34 eV).  The paper's own Table II values are in ``TABLE_II``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TRACK_COLUMNS = ("let_keV_um", "b_cm", "x_cm", "y_cm", "theta", "phi", "t_s")
+
+AIR = dict(mu_pos=1.73, mu_neg=1.87, D_pos=0.045, D_neg=0.045, alpha=1.60e-6, W_eV=34.0)
+
+# Table II of the paper (ion transport constants and recombination constant).
+TABLE_II = dict(D_pos=2.82e-2, D_neg=4.35e-2, mu_pos=1.36, mu_neg=2.10, alpha=1.60e-6)
+
+# Table I of the paper: (LET in air [keV/um], Gaussian track radius [um]).
+TABLE_I = {
+    "Fe40": (1.02, 50.0),
+    "Ne60": (0.115, 20.0),
+    "C90": (3.03e-2, 10.5),
+    "p100": (7.76e-4, 10.0),
+}
+
+# Ion pairs per cm^3 released in air by 1 mGy: dose * rho_air / (W q).
+RHO_AIR_G_CM3 = 1.205e-3
+Q_E = 1.602176634e-19
+SEED_BASE = 1610067490
+
+
+def ion_pairs_per_mGy(W_eV: float = 34.0) -> float:
+    """Uniform ion-pair density [cm^-3] that 1 mGy releases in air."""
+    energy_j_per_cm3 = 1e-3 * RHO_AIR_G_CM3 * 1e-3  # J/kg * kg/cm^3
+    return energy_j_per_cm3 / (W_eV * Q_E)
+
+
+def chamber(nx, ny, nz, dx, gap, voltage, dy=None, *, dt_safety=1.0, stop_tol=1e-12,
+            max_steps=1_000_000, uniform_n0=0.0, space_charge=0, **consts) -> dict:
+    c = dict(AIR)
+    c.update(consts)
+    return dict(nx=int(nx), ny=int(ny), nz=int(nz), dx=float(dx),
+                dy=float(dx if dy is None else dy), gap=float(gap), voltage=float(voltage),
+                mu_pos=float(c["mu_pos"]), mu_neg=float(c["mu_neg"]),
+                D_pos=float(c["D_pos"]), D_neg=float(c["D_neg"]),
+                alpha=float(c["alpha"]), W_eV=float(c["W_eV"]),
+                dt_safety=float(dt_safety), stop_tol=float(stop_tol),
+                max_steps=int(max_steps), uniform_n0=float(uniform_n0),
+                space_charge=int(space_charge))
+
+
+def tracks(rows) -> np.ndarray:
+    a = np.asarray(rows, dtype=np.float64).reshape(-1, 7)
+    return np.ascontiguousarray(a)
+
+
+def no_tracks() -> np.ndarray:
+    return np.zeros((0, 7), dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+def single_track(**over):
+    """One Gaussian track parallel to the field in a 64x64x100 grid.
+
+    Gap 0.02 cm at 30 V, spacing 2e-4 cm, LET 100 keV/um, b = 1e-3 cm,
+    axis through the node (32, 32)."""
+    ch = chamber(64, 64, 100, 2e-4, 0.02, 30.0)
+    ch.update(over)
+    tr = tracks([[100.0, 1e-3, 32 * ch["dx"], 32 * ch["dy"], 0.0, 0.0, 0.0]])
+    return ch, tr
+
+
+def pulsed_beam(seed: int = SEED_BASE + 2, ntracks: int = 400, **over):
+    """One instantaneous pulse of 400 parallel tracks in a 256x256x200 grid.
+
+    Gap 0.1 cm at 200 V, spacing 5e-4 cm.  Track positions uniform over the
+    periodic cell, ln LET ~ N(ln 50, 0.5^2), b ~ U[5e-4, 2e-3] cm."""
+    ch = chamber(256, 256, 200, 5e-4, 0.1, 200.0)
+    ch.update(over)
+    rng = np.random.default_rng(seed)
+    lx, ly = ch["nx"] * ch["dx"], ch["ny"] * ch["dy"]
+    x = rng.uniform(0.0, lx, ntracks)
+    y = rng.uniform(0.0, ly, ntracks)
+    let = np.exp(rng.normal(math.log(50.0), 0.5, ntracks))
+    b = rng.uniform(5e-4, 2e-3, ntracks)
+    z = np.zeros(ntracks)
+    return ch, tracks(np.stack([let, b, x, y, z, z, z], axis=1))
+
+
+def continuous_beam(seed: int = SEED_BASE + 3, duration_s: float = 0.0, forced: int = 4,
+                    fluence_rate=2e5, grid=(512, 512, 256), **over):
+    """Continuous beam on a 512x512x256 grid (spacing 4e-4 cm, gap 0.1 cm, 300 V).
+
+    Arrival times form a Poisson process of rate ``fluence_rate`` x (cell
+    area) per second over ``[0, duration_s)``; ``forced`` extra tracks arrive
+    at t = 0 so that a short window already carries a non-trivial field.
+    Tilt theta ~ U[0, 30 deg], azimuth phi ~ U[0, 2 pi), LET log-uniform on
+    [1, 300] keV/um, b ~ U[5e-4, 2e-3] cm, positions uniform over the cell.
+    """
+    nx, ny, nz = grid
+    ch = chamber(nx, ny, nz, 4e-4, 0.1, 300.0)
+    ch.update(over)
+    rng = np.random.default_rng(seed)
+    lx, ly = ch["nx"] * ch["dx"], ch["ny"] * ch["dy"]
+    rate = fluence_rate * lx * ly
+    times = [0.0] * forced
+    t = 0.0
+    while duration_s > 0.0:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration_s:
+            break
+        times.append(t)
+    n = len(times)
+    x = rng.uniform(0.0, lx, n)
+    y = rng.uniform(0.0, ly, n)
+    theta = rng.uniform(0.0, math.radians(30.0), n)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    let = np.exp(rng.uniform(math.log(1.0), math.log(300.0), n))
+    b = rng.uniform(5e-4, 2e-3, n)
+    return ch, tracks(np.stack([let, b, x, y, theta, phi, np.asarray(times)], axis=1))
+
+
+def batched_sweep(seed: int = SEED_BASE + 4, ninst: int = 96, max_tracks: int = 500,
+                  transverse=(64, 256), gap_voxels=(50, 250), spacing=5e-4):
+    """A sweep of ``ninst`` chambers of uneven grids (one pulse each).
+
+    Per instance: nx = ny ~ U{64..256}, nz ~ U{50..250} at spacing 5e-4 cm
+    (gap = nz * spacing); voltages log-spaced over 50..400 V across the
+    instances; one LET per instance, log-uniform on [1, 500] keV/um; b ~
+    U[5e-4, 2e-3] cm; 1..500 parallel tracks at t = 0 uniform over the cell;
+    dose per pulse log-uniform on [0.01, 1] mGy, realised as a uniform
+    pre-ionisation of both species.
+    Returns (list of chambers, list of track arrays)."""
+    rng = np.random.default_rng(seed)
+    volts = np.geomspace(50.0, 400.0, ninst)
+    chs, trs = [], []
+    per_mgy = ion_pairs_per_mGy(AIR["W_eV"])
+    for i in range(ninst):
+        n_t = int(rng.integers(transverse[0], transverse[1] + 1))
+        nz = int(rng.integers(gap_voxels[0], gap_voxels[1] + 1))
+        dose = math.exp(rng.uniform(math.log(0.01), math.log(1.0)))
+        ch = chamber(n_t, n_t, nz, spacing, nz * spacing, float(volts[i]),
+                     uniform_n0=dose * per_mgy)
+        let = math.exp(rng.uniform(math.log(1.0), math.log(500.0)))
+        b = rng.uniform(5e-4, 2e-3)
+        k = int(rng.integers(1, max_tracks + 1))
+        lx = n_t * spacing
+        x = rng.uniform(0.0, lx, k)
+        y = rng.uniform(0.0, lx, k)
+        z = np.zeros(k)
+        trs.append(tracks(np.stack([np.full(k, let), np.full(k, b), x, y, z, z, z], axis=1)))
+        chs.append(ch)
+    return chs, trs
+
+
+def perturbed_field(shape, seed: int, scale: float = 1e9):
+    """Smooth positive random density fields (for stepping tests that start
+    from a given state rather than from deposited tracks).  Returns two
+    arrays of shape (nz+1, ny, nx) with zero electrode planes."""
+    nzp1, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(2):
+        f = rng.uniform(0.0, scale, size=shape)
+        f[0] = 0.0
+        f[-1] = 0.0
+        out.append(np.ascontiguousarray(f))
+    return out[0], out[1]
