@@ -1,0 +1,194 @@
+"""Benchmark of the recombination solver on one MI355X.
+
+One "step" is one whole run of the method on the pulsed-beam chamber
+(256 x 256 x 200 nodes, spacing 5e-4 cm, gap 0.1 cm at 200 V, one
+instantaneous pulse of 400 parallel Gaussian tracks): time step selection,
+track deposition, explicit stepping with per-step tallies until every ion is
+collected (or recombined), and the result f.  Inputs are synthetic and
+seeded; the track list and the workspace are resident before timing.
+
+Printed: one JSON line with voxel-steps/s (one voxel-step = both ion species
+updated at one interior node for one time step), the roofline of the
+stepping kernel (algorithmic bytes per launch over its average launch time,
+measured here with HIP events on the stream the kernel runs on) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-steps/s + % HBM peak; k_s evals/s surrogate vs solver at 0.1% err"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_VOXEL_STEP = 32.0  # read + write of two FP64 species per node and step
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kernel", choices=("auto", "plain", "blocked"), default="auto")
+    ap.add_argument("--T", type=int, default=0, help="steps per pass of the blocked kernel")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--kernel-steps", type=int, default=200,
+                    help="launches in the stepping-kernel timing")
+    return ap.parse_args()
+
+
+def kernel_source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1610_06749_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_name, workload, src_hash):
+    """HBM bytes per launch from the committed counter summary, or None when
+    no summary exists or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_name}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(ch, tr):
+    """The CPU oracle (single-threaded plain C) on a bounded sample of the
+    same workload: deposition of 16 of the 400 tracks and 40 steps of the
+    full grid, scaled to one whole run."""
+    import numpy as np
+
+    import oracle
+    dt = oracle.dt(ch)
+    nint = (ch["nz"] - 1) * ch["nx"] * ch["ny"]
+    t0 = time.perf_counter()
+    pos, neg, _ = oracle.deposit(ch, tr[:16], 0, dt)
+    t_dep = (time.perf_counter() - t0) / 16.0
+    nsteps = 40
+    t0 = time.perf_counter()
+    oracle.advance(ch, dt, pos, neg, nsteps)
+    t_step = (time.perf_counter() - t0) / nsteps
+    return t_dep, t_step, nint, np
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1610_06749_amd as it
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    ch, tr = W.pulsed_beam()
+    kernel = {"auto": it.IT_KERNEL_AUTO, "plain": it.IT_KERNEL_PLAIN, "blocked": it.IT_KERNEL_BLOCKED}[a.kernel]
+    ex = {"kernel": kernel, "steps_per_pass": a.T}
+    ws = it.workspace(ch, tr.shape[0])
+    nint = (ch["nz"] - 1) * ch["nx"] * ch["ny"]
+    stream = torch.cuda.current_stream()
+
+    for _ in range(a.warmup):
+        it.it_solve(ch, tr, exec=ex, ws=ws)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        results.append(it.it_solve(ch, tr, exec=ex, ws=ws))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    voxel_steps = sum(r["steps"] for r in results) * nint
+    r0 = results[0]
+    value = voxel_steps / elapsed
+
+    # Stepping kernel alone: K launches minus 1 launch of it_advance on the
+    # same grid, bracketed by HIP events on the stream the kernel runs on.
+    dt = r0["dt"]
+    pos0, neg0 = W.perturbed_field((ch["nz"] + 1, ch["ny"], ch["nx"]), seed=5, scale=1e9)
+    gp = torch.tensor(pos0, device="cuda")
+    gn = torch.tensor(neg0, device="cuda")
+    chk = dict(ch, max_steps=max(a.kernel_steps, 1))
+    wsk = it.workspace(chk, 0)
+
+    def timed_advance(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        it.it_advance(chk, dt, gp, gn, n, exec=ex, ws=wsk, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    timed_advance(a.kernel_steps)
+    t_many = min(timed_advance(a.kernel_steps) for _ in range(3))
+    t_one = min(timed_advance(1) for _ in range(5))
+    T_pass = 1 if kernel == it.IT_KERNEL_PLAIN or a.T <= 1 else a.T
+    launches = a.kernel_steps // T_pass
+    per_launch = (t_many - t_one) / max(launches - 1, 1)
+    bytes_per_launch = BYTES_PER_VOXEL_STEP * nint  # compulsory traffic of one pass
+    achieved = bytes_per_launch / per_launch / 1e9
+    kname = "step_plain" if T_pass == 1 else f"step_blocked_T{T_pass}"
+    src = ["kernels_plain.hip", "reduce.h", "internal.h"] if T_pass == 1 else \
+        ["kernels_blocked.hip", "reduce.h", "internal.h"]
+    workload_name = "pulsed_256x256x200"
+    traffic = read_traffic(kname, workload_name, kernel_source_hash(src))
+
+    cpu = None
+    if not a.no_cpu:
+        t_dep, t_step, nint_c, _ = cpu_baseline(ch, tr)
+        steps_full = r0["steps"]
+        t_run = t_dep * tr.shape[0] + t_step * steps_full
+        cpu = {"value": nint_c * steps_full / t_run, "unit": "voxel-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"single-threaded C oracle: deposit of 16 of the 400 tracks "
+                         f"({t_dep * 16:.1f} s) and 40 steps of the full 256x256x200 grid "
+                         f"({t_step * 40:.1f} s), scaled to one whole run of {steps_full} steps"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "pulsed beam: 256x256x200 nodes, 400 parallel tracks, one pulse, "
+                               "run to full collection",
+                   "time_steps_per_run": r0["steps"], "f": r0["f"], "ks": r0["ks"],
+                   "kernel": kname},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": kname, "launch_ms": per_launch * 1e3,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

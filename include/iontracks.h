@@ -1,0 +1,174 @@
+/*
+ * iontracks.h -- C ABI of the MI355X recombination solver.
+ *
+ * The library computes the collection efficiency f and the recombination
+ * factor k_s = 1/f of a parallel-plate ionization chamber hit by ion tracks,
+ * following Christensen, Toelli & Bassler, "A general algorithm for
+ * calculation of recombination losses in ionization chambers exposed to ion
+ * beams" (arXiv:1610.06749):
+ *
+ *   - tracks release N0 = LET/W ion pairs per unit length (eq. linear_density)
+ *     with Jaffe's Gaussian radial profile n0(r) = N0/(pi b^2) e^{-r^2/b^2}
+ *     (eq. Gaussian) around an axis tilted by theta to the field;
+ *   - positive and negative ion densities drift in the applied field, diffuse
+ *     and recombine at rate alpha n+ n- (eq. theEquation), stepped by the
+ *     explicit scheme of the Appendix (forward time difference, the drift
+ *     derivative blending backward and central differences with weight c,
+ *     3-point diffusion) at the largest time step allowed by eq. vNeum;
+ *   - the electrodes at z = 0 (anode) and z = d (cathode) hold zero density
+ *     and collect what reaches them (Methods, Implementation);
+ *   - f = N_collected / N_released (eq. collection_efficiency).
+ *
+ * Units: cm, s, V, keV/um for LET, eV for W.  All arithmetic is FP64.
+ *
+ * Grid: nx * ny transverse nodes x_i = i dx, y_j = j dy with periodic lateral
+ * boundaries; nz gap intervals of dz = gap/nz, planes k = 0..nz, of which
+ * k = 1..nz-1 are interior.  Density fields are FP64 arrays [nz+1][ny][nx]
+ * with x fastest; planes 0 and nz always hold zero.
+ *
+ * Conventions of every entry point:
+ *   - return 0 (IT_OK) on success or a negative IT_E* code; nothing is thrown
+ *     across the ABI; it_strerror() names the code;
+ *   - the caller owns every buffer.  "host" pointers are ordinary CPU memory,
+ *     "device" pointers are HIP device memory of the current device;
+ *   - device work runs on the HIP stream passed as `stream` (a hipStream_t,
+ *     NULL = the default stream).  Calls that return host results
+ *     synchronise that stream before returning;
+ *   - the workspace is device memory of at least it_workspace_size() bytes;
+ *     its contents need not be initialised and are clobbered.  Calls that
+ *     share one workspace must not overlap in time.
+ */
+#ifndef IONTRACKS_H
+#define IONTRACKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define IT_OK 0
+#define IT_EINVAL -1      /* invalid argument: a size, a constant or a track is out of range */
+#define IT_ENODT -2       /* neither drift nor diffusion bounds the time step (E = 0 and D = 0) */
+#define IT_EWORKSPACE -3  /* workspace NULL or smaller than it_workspace_size() */
+#define IT_EHIP -4        /* a HIP runtime call failed (no device, launch failure, ...) */
+#define IT_ENOTSUP -5     /* option not supported by this build */
+
+/* ---- result flags ---- */
+#define IT_FLAG_MAX_STEPS 1  /* stopped by max_steps, not by the collection criterion */
+#define IT_FLAG_NONFINITE 2  /* a tally became NaN or Inf; the run stopped there */
+#define IT_FLAG_REACTION 4   /* alpha*dt*max(n) exceeded 1 after a deposit */
+#define IT_FLAG_EMPTY 8      /* nothing was released; f is reported as 1 */
+
+/* ---- per-step trace record: IT_TRACE_COLS doubles per step, in ion counts ---- */
+#define IT_TRACE_COLS 10
+/* 0 recombined pairs, 1/2 positive ions collected at anode/cathode,
+ * 3/4 negative ions collected at anode/cathode, 5/6 positive/negative ions in
+ * flight after the step (signed sum of n dV), 7/8 sum of |n| dV after the
+ * step, 9 ion pairs released by deposits made before the step. */
+
+/* Chamber, field, transport constants and run control. */
+typedef struct {
+  int32_t nx, ny;       /* transverse node counts (>= 1), periodic */
+  int32_t nz;           /* gap intervals (>= 2): interior planes 1..nz-1 */
+  int32_t reserved0;    /* must be 0 */
+  double dx, dy;        /* transverse node spacing [cm] */
+  double gap;           /* electrode distance d [cm]; dz = gap/nz */
+  double voltage;       /* V [V]; E = V/gap along +z, anode z=0 -> cathode z=d */
+  double mu_pos, mu_neg;/* ion mobilities [cm^2/(V s)] (>= 0) */
+  double D_pos, D_neg;  /* ion diffusion constants [cm^2/s] (>= 0) */
+  double alpha;         /* recombination constant [cm^3/s] (>= 0) */
+  double W_eV;          /* mean energy per ion pair [eV] (> 0) */
+  double dt_safety;     /* factor in (0, 1] on the largest stable dt (eq. vNeum) */
+  double stop_tol;      /* stop once sum |n| dV <= stop_tol * released for both species (>= 0) */
+  double uniform_n0;    /* uniform ion-pair density added at t = 0 [cm^-3] (>= 0) */
+  int64_t max_steps;    /* hard step limit (>= 1) */
+} it_chamber;
+
+/* One ion track.  The axis passes through (x, y, gap/2) with direction
+ * (sin theta cos phi, sin theta sin phi, cos theta); theta is the angle to the
+ * field.  The track is deposited at the start of step floor(t/dt).  The
+ * transverse offset of a node from (x, y) is wrapped to the nearest periodic
+ * image and the profile is cut at a perpendicular distance of 8 b. */
+typedef struct {
+  double let_keV_um;    /* LET in air [keV/um] (>= 0) */
+  double b_cm;          /* Gaussian track radius b [cm] (> 0) */
+  double x_cm, y_cm;    /* axis position at mid-gap [cm] */
+  double theta, phi;    /* polar angle to the field and azimuth [rad] */
+  double t_s;           /* arrival time [s] (>= 0) */
+} it_track;
+
+/* Result of a run (all counts in ion pairs / ions). */
+typedef struct {
+  double f;             /* collection efficiency: collected / (2 released), both species */
+  double ks;            /* recombination factor 1/f */
+  double f_R;           /* 1 - recombined / released */
+  double n_released, n_recombined;
+  double n_inflight_pos, n_inflight_neg;  /* signed in-flight counts after the last step */
+  double col_pos_anode, col_pos_cathode, col_neg_anode, col_neg_cathode;
+  double dt;            /* time step [s] */
+  double max_beta_n;    /* max over deposits of alpha*dt*max(n) */
+  int64_t steps;        /* steps counted in the result */
+  int32_t flags;        /* IT_FLAG_* */
+  int32_t passes;       /* stepping kernel launches issued (diagnostic) */
+} it_result;
+
+/* Kernel selection for the stepping.  NULL means "defaults". */
+#define IT_KERNEL_AUTO 0     /* tuned choice (currently the blocked kernel when available) */
+#define IT_KERNEL_PLAIN 1    /* one time step per launch */
+#define IT_KERNEL_BLOCKED 2  /* steps_per_pass fused steps per launch (temporal blocking) */
+typedef struct {
+  int32_t kernel;          /* IT_KERNEL_* */
+  int32_t steps_per_pass;  /* T for the blocked kernel, 1..8 (0 = default) */
+  int32_t tile_y;          /* rows per tile of the blocked kernel (0 = default) */
+  int32_t check_every;     /* steps between host checks of the stop criterion (0 = default) */
+} it_exec;
+
+/* Largest stable time step of eq. vNeum times dt_safety.  Host only: touches
+ * no device.  Errors: IT_EINVAL (bad chamber), IT_ENODT. */
+int it_dt(const it_chamber* ch, double* dt);
+
+/* Checks a chamber and a track list (host arrays; tracks may be NULL when
+ * ntracks == 0).  Host only.  Errors: IT_EINVAL, IT_ENODT. */
+int it_validate(const it_chamber* ch, const it_track* tracks, int64_t ntracks);
+
+/* Device workspace bytes it_solve / it_advance need for this chamber and up
+ * to ntracks tracks (includes the two double-buffered density fields and a
+ * per-step trace of max_steps records).  Host only. */
+int it_workspace_size(const it_chamber* ch, int64_t ntracks, size_t* bytes);
+
+/* Full run of the method: deposit the tracks (host array, any order) and the
+ * uniform pre-ionisation, step until the stop criterion or max_steps, and
+ * fill *out (host).  Optional outputs:
+ *   h_trace      host [max_steps][IT_TRACE_COLS]; the first out->steps rows
+ *                are written;
+ *   d_pos_out,   device [(nz+1)*ny*nx] each: the density fields after the
+ *   d_neg_out    last executed step.  With a blocked kernel the run can
+ *                execute up to steps_per_pass-1 steps beyond out->steps when
+ *                it stops on the collection criterion; with stop_tol = 0 it
+ *                stops exactly at max_steps.
+ * Synchronises `stream` before returning.
+ * Errors: IT_EINVAL, IT_ENODT, IT_EWORKSPACE, IT_EHIP. */
+int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks,
+             const it_exec* exec, void* d_workspace, size_t ws_bytes, void* stream,
+             double* h_trace, double* d_pos_out, double* d_neg_out, it_result* out);
+
+/* Advances given densities by exactly nsteps steps of size dt, without
+ * deposits (the stepping of the Appendix alone).  d_pos, d_neg: device
+ * [(nz+1)*ny*nx], read and overwritten in place; their electrode planes are
+ * treated as zero.  h_trace: NULL or host [nsteps][IT_TRACE_COLS].  Uses the
+ * chamber's constants; ch->max_steps must be >= nsteps.  Synchronises
+ * `stream`.  Errors: IT_EINVAL, IT_EWORKSPACE, IT_EHIP. */
+int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* exec,
+               double* d_pos, double* d_neg, void* d_workspace, size_t ws_bytes,
+               void* stream, double* h_trace);
+
+/* Message for a status code (static string). */
+const char* it_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IONTRACKS_H */

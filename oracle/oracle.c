@@ -125,24 +125,29 @@ static double wrap(double d, double L)
   return d - L * floor(d / L + 0.5);
 }
 
+/* Axis direction of a track: (sin th cos ph, sin th sin ph, cos th). */
+static void track_axis(const double *tr, double *u)
+{
+  u[0] = sin(tr[4]) * cos(tr[5]);
+  u[1] = sin(tr[4]) * sin(tr[5]);
+  u[2] = cos(tr[4]);
+}
+
 /* Gaussian track profile of eq. Gaussian at node (i,j,k), 0 beyond 8b.
- * tr = {let_keV_um, b, x0, y0, theta, phi, t}. */
+ * tr = {let_keV_um, b, x0, y0, theta, phi, t}; u = axis direction. */
 static double track_density(const double *p, int64_t nx, int64_t ny, int64_t nz,
-                            const double *tr, int64_t i, int64_t j, int64_t k)
+                            const double *tr, const double *u, int64_t i, int64_t j, int64_t k)
 {
   const double dz = p[P_GAP] / (double)nz;
   const double N0 = tr[0] * 1.0e7 / p[P_W]; /* keV/um -> eV/cm, divided by W: pairs/cm */
   const double b = tr[1];
-  const double ux = sin(tr[4]) * cos(tr[5]);
-  const double uy = sin(tr[4]) * sin(tr[5]);
-  const double uz = cos(tr[4]);
   const double wx = wrap((double)i * p[P_DX] - tr[2], (double)nx * p[P_DX]);
   const double wy = wrap((double)j * p[P_DY] - tr[3], (double)ny * p[P_DY]);
   const double wz = (double)k * dz - 0.5 * p[P_GAP];
   /* squared distance from the axis: |w x u|^2 */
-  const double cx = wy * uz - wz * uy;
-  const double cy = wz * ux - wx * uz;
-  const double cz = wx * uy - wy * ux;
+  const double cx = wy * u[2] - wz * u[1];
+  const double cy = wz * u[0] - wx * u[2];
+  const double cz = wx * u[1] - wy * u[0];
   const double r2 = cx * cx + cy * cy + cz * cz;
   if (r2 > 64.0 * b * b) return 0.0;
   return N0 / (M_PI * b * b) * exp(-r2 / (b * b));
@@ -166,11 +171,13 @@ double orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
   for (int64_t t = 0; t < ntr; ++t) {
     const double *tr = trk + 7 * t;
     if (orc_deposit_step(dt, tr) != step) continue;
+    double u[3];
+    track_axis(tr, u);
     double sum = 0.0;
     for (int64_t k = 1; k < nz; ++k)
       for (int64_t j = 0; j < ny; ++j)
         for (int64_t i = 0; i < nx; ++i) {
-          const double d = track_density(p, nx, ny, nz, tr, i, j, k);
+          const double d = track_density(p, nx, ny, nz, tr, u, i, j, k);
           pos[IDX(k, j, i)] += d;
           neg[IDX(k, j, i)] += d;
           sum += d;

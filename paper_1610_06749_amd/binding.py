@@ -1,0 +1,201 @@
+"""Thin ctypes binding of ``libiontracks.so`` (the C ABI of include/iontracks.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (workspace and field tensors) and the HIP
+stream.  The functions carry the C names; chambers are the dictionaries of
+``workloads`` and track lists are float64 arrays of shape (n, 7) whose rows
+have the layout of ``it_track``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiontracks.so")
+
+IT_OK, IT_EINVAL, IT_ENODT, IT_EWORKSPACE, IT_EHIP, IT_ENOTSUP = 0, -1, -2, -3, -4, -5
+IT_FLAG_MAX_STEPS, IT_FLAG_NONFINITE, IT_FLAG_REACTION, IT_FLAG_EMPTY = 1, 2, 4, 8
+IT_TRACE_COLS = 10
+IT_KERNEL_AUTO, IT_KERNEL_PLAIN, IT_KERNEL_BLOCKED = 0, 1, 2
+TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
+              "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released")
+
+
+class ItError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {it_strerror(code)} (status {code})")
+
+
+class it_chamber(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("gap", ctypes.c_double),
+                ("voltage", ctypes.c_double), ("mu_pos", ctypes.c_double), ("mu_neg", ctypes.c_double),
+                ("D_pos", ctypes.c_double), ("D_neg", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("W_eV", ctypes.c_double), ("dt_safety", ctypes.c_double), ("stop_tol", ctypes.c_double),
+                ("uniform_n0", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class it_result(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos", "n_inflight_neg",
+        "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "max_beta_n")] + \
+        [("steps", ctypes.c_int64), ("flags", ctypes.c_int32), ("passes", ctypes.c_int32)]
+
+
+class it_exec(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        chp = ctypes.POINTER(it_chamber)
+        L.it_strerror.argtypes = [ctypes.c_int]
+        L.it_strerror.restype = ctypes.c_char_p
+        L.it_dt.argtypes = [chp, dp]
+        L.it_validate.argtypes = [chp, vp, i64]
+        L.it_workspace_size.argtypes = [chp, i64, ctypes.POINTER(ctypes.c_size_t)]
+        L.it_solve.argtypes = [chp, vp, i64, ctypes.POINTER(it_exec), vp, ctypes.c_size_t, vp, vp, vp, vp,
+                               ctypes.POINTER(it_result)]
+        L.it_advance.argtypes = [chp, ctypes.c_double, i64, ctypes.POINTER(it_exec), vp, vp, vp,
+                                 ctypes.c_size_t, vp, vp]
+        for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def it_strerror(code: int) -> str:
+    return lib().it_strerror(int(code)).decode()
+
+
+def _chamber(ch) -> it_chamber:
+    c = it_chamber()
+    for k in ("nx", "ny", "nz", "max_steps"):
+        setattr(c, k, int(ch[k]))
+    for k in ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg", "alpha", "W_eV",
+              "dt_safety", "stop_tol", "uniform_n0"):
+        setattr(c, k, float(ch[k]))
+    if int(ch.get("space_charge", 0)):
+        raise ItError(IT_ENOTSUP, "space_charge")
+    return c
+
+
+def _tracks(tracks):
+    tr = np.ascontiguousarray(np.asarray(tracks, dtype=np.float64).reshape(-1, 7))
+    return tr, (tr.ctypes.data if tr.shape[0] else None)
+
+
+def _exec(ex):
+    if ex is None:
+        return None
+    e = it_exec()
+    for k in ("kernel", "steps_per_pass", "tile_y", "check_every"):
+        setattr(e, k, int(ex.get(k, 0)))
+    return ctypes.byref(e)
+
+
+def _check(rc, where):
+    if rc != IT_OK:
+        raise ItError(rc, where)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def it_dt(ch) -> float:
+    out = ctypes.c_double()
+    _check(lib().it_dt(ctypes.byref(_chamber(ch)), ctypes.byref(out)), "it_dt")
+    return out.value
+
+
+def it_validate(ch, tracks) -> None:
+    tr, ptr = _tracks(tracks)
+    _check(lib().it_validate(ctypes.byref(_chamber(ch)), ptr, tr.shape[0]), "it_validate")
+
+
+def it_workspace_size(ch, ntracks: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().it_workspace_size(ctypes.byref(_chamber(ch)), int(ntracks), ctypes.byref(out)),
+           "it_workspace_size")
+    return out.value
+
+
+def workspace(ch, ntracks: int, device="cuda"):
+    import torch
+    return torch.empty(it_workspace_size(ch, ntracks), dtype=torch.uint8, device=device)
+
+
+def _result(r: it_result) -> dict:
+    out = {k: getattr(r, k) for k, _ in it_result._fields_}
+    out["steps"] = int(out["steps"])
+    out["flags"] = int(out["flags"])
+    out["passes"] = int(out["passes"])
+    return out
+
+
+def it_solve(ch, tracks, exec=None, ws=None, stream=None, trace=False, fields=False) -> dict:
+    """Runs the solver; returns the result dict (keys of ``it_result``),
+    plus 'trace' (numpy [steps, 10]) and 'pos'/'neg' (device tensors of shape
+    (nz+1, ny, nx)) on request."""
+    import torch
+    c = _chamber(ch)
+    tr, ptr = _tracks(tracks)
+    if ws is None:
+        ws = workspace(ch, tr.shape[0])
+    htrace = np.zeros((int(ch["max_steps"]), IT_TRACE_COLS)) if trace else None
+    shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
+    pos = torch.empty(shape, dtype=torch.float64, device=ws.device) if fields else None
+    neg = torch.empty(shape, dtype=torch.float64, device=ws.device) if fields else None
+    res = it_result()
+    rc = lib().it_solve(ctypes.byref(c), ptr, tr.shape[0], _exec(exec), ctypes.c_void_p(ws.data_ptr()),
+                        ws.numel(), _stream(stream),
+                        htrace.ctypes.data if trace else None,
+                        ctypes.c_void_p(pos.data_ptr()) if fields else None,
+                        ctypes.c_void_p(neg.data_ptr()) if fields else None, ctypes.byref(res))
+    _check(rc, "it_solve")
+    out = _result(res)
+    if trace:
+        out["trace"] = htrace[: out["steps"]].copy()
+    if fields:
+        out["pos"], out["neg"] = pos, neg
+    return out
+
+
+def it_advance(ch, dt, pos, neg, nsteps, exec=None, ws=None, stream=None, trace=False):
+    """Advances device tensors pos/neg (float64, (nz+1, ny, nx), contiguous)
+    in place by nsteps steps; returns the trace (numpy) when asked."""
+    import torch
+    c = _chamber(ch)
+    shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
+    for t in (pos, neg):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and tuple(t.shape) == shape and t.is_contiguous()):
+            raise ValueError(f"fields must be contiguous float64 CUDA tensors of shape {shape}")
+    if ws is None:
+        ws = workspace(ch, 0, device=pos.device)
+    htrace = np.zeros((int(nsteps), IT_TRACE_COLS)) if trace else None
+    rc = lib().it_advance(ctypes.byref(c), float(dt), int(nsteps), _exec(exec),
+                          ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(neg.data_ptr()),
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                          htrace.ctypes.data if trace else None)
+    _check(rc, "it_advance")
+    return htrace

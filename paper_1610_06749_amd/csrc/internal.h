@@ -1,0 +1,96 @@
+// Internal declarations of the HIP recombination solver (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "iontracks.h"
+
+namespace it {
+
+// Per-step tally slots accumulated by the stepping kernels (per block, then
+// reduced in a fixed order):
+//   0 sum beta n+ n-            (recombined, before the dV factor)
+//   1 sum n+ on plane k = 1      2 sum n+ on plane k = nz-1
+//   3 sum n- on plane k = 1      4 sum n- on plane k = nz-1
+//   5 sum n+' (new)              6 sum n-'
+//   7 sum |n+'|                  8 sum |n-'|
+constexpr int kAcc = 9;
+constexpr int kMaxT = 8;  // largest number of fused steps per pass
+
+// Coefficients of the explicit update of one species at an interior node:
+//   n' = a0 n + ax (n_{i+1} + n_{i-1}) + ay (n_{j+1} + n_{j-1})
+//        + azp n_{k+1} + azm n_{k-1} - beta n+ n-
+// azp is the weight of the neighbour towards the cathode (k+1); it is also
+// the fraction of n_{k=1} that reaches the anode plane in one step, and azm
+// the fraction of n_{k=nz-1} that reaches the cathode plane.
+struct Coef {
+  double a0, ax, ay, azp, azm;
+};
+
+// Device-resident run state, updated only by the last block of each launch.
+struct RunState {
+  double released;          // ion pairs released so far
+  double released_pending;  // released since the last recorded step
+  double sums[5];           // running recombined, pos anode/cathode, neg anode/cathode
+  double last[4];           // in-flight pos/neg and |n| sums after the last step
+  double max_beta_n;        // max over deposits of beta * max(n)
+  int64_t steps;            // steps recorded so far
+  int32_t done;             // 1 once the stop criterion (or a non-finite tally) is met
+  int32_t flags;            // IT_FLAG_NONFINITE
+  int32_t passes;           // stepping launches that ran (not skipped)
+  int32_t pad;
+};
+
+// Track prepared on the host for the deposit kernel.
+struct DepTrack {
+  double x0, y0;            // axis position at mid-gap
+  double ux, uy, uz;        // axis direction
+  double peak;              // N0 / (pi b^2)
+  double inv_b2;            // 1 / b^2
+  double cut2;              // (8 b)^2
+};
+
+struct StepParams {
+  const double* pin;
+  const double* nin;
+  double* pout;
+  double* nout;
+  int nx, ny, nz;
+  int tiles_x, tiles_y, zchunks, zc;  // tiling of the interior
+  int ntiles;                         // tiles_x * tiles_y * zchunks
+  int per_xcd;                        // tiles per XCD slot (grid = 8 * per_xcd)
+  Coef cp, cn;
+  double beta, dV, stop_tol;
+  int64_t step0;            // index of the step this launch computes
+  int64_t min_stop_step;    // the stop criterion is tested only from this step on
+  double* partials;         // [gridDim][kAcc * T]
+  unsigned* counter;
+  RunState* state;
+  double* trace;            // [max_steps][IT_TRACE_COLS]
+};
+
+struct DepositParams {
+  double* pos;
+  double* neg;
+  int nx, ny, nz;
+  int tiles_x, tiles_y, zchunks, zc, ntiles, per_xcd;
+  double dx, dy, dz, half_gap, Lx, Ly;
+  double uniform;           // uniform density added at this deposit (0 if none)
+  const DepTrack* par;      // tracks parallel to the field
+  int npar;
+  const DepTrack* tilt;     // tilted tracks
+  int ntilt;
+  double dV, beta;
+  double* partials;         // [gridDim][2]
+  unsigned* counter;
+  RunState* state;
+};
+
+struct BlockedParams;
+
+// Launchers (stream-ordered, no synchronisation).
+hipError_t launch_step_plain(const StepParams& p, hipStream_t s);
+hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
+
+}  // namespace it

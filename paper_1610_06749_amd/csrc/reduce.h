@@ -1,0 +1,153 @@
+// Deterministic block reductions and the end-of-launch tally finalisation
+// shared by the stepping kernels.  Every sum is taken in a fixed order
+// (wave butterfly, then waves in index order, then blocks in index order),
+// so a run is bitwise reproducible.
+#pragma once
+
+#include "internal.h"
+
+namespace it {
+
+constexpr int kWave = 64;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Sums N values per thread over a block of NT threads; thread 0 writes the N
+// block totals to out[0..N).  lds must hold (NT/64) * N doubles.
+template <int N, int NT>
+__device__ inline void block_sum_store(double (&acc)[N], double* out, double* lds) {
+  constexpr int W = NT / kWave;
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int wave = tid / kWave, lane = tid % kWave;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double v = wave_sum(acc[q]);
+    if (lane == 0) lds[wave * N + q] = v;
+  }
+  __syncthreads();
+  if (tid < N) {
+    double s = lds[tid];
+#pragma unroll
+    for (int w = 1; w < W; ++w) s += lds[w * N + tid];
+    out[tid] = s;
+  }
+}
+
+// Called by all threads of every block after the block wrote its partials.
+// Returns true in exactly one block: the last to arrive.  That block then
+// sees every other block's partials.
+template <int NT>
+__device__ inline bool arrive_last(unsigned* counter) {
+  __shared__ int last;
+  __syncthreads();
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  if (tid == 0) {
+    __threadfence();
+    const unsigned ticket = atomicAdd(counter, 1u);
+    last = ticket == gridDim.x * gridDim.y * gridDim.z - 1;
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+// In the last block: totals[q] = sum over blocks b (in order) of
+// partials[b * stride + q], q < n.  Each thread owns a fixed subset of the
+// blocks; the per-thread sums are then combined by a fixed tree.
+template <int NT>
+__device__ inline void reduce_partials(const double* partials, int nblocks, int stride, int n,
+                                       double* totals, double* lds /*[NT/64]*/) {
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int wave = tid / kWave, lane = tid % kWave;
+  for (int q = 0; q < n; ++q) {
+    double s = 0.0;
+    for (int b = tid; b < nblocks; b += NT) s += partials[(size_t)b * stride + q];
+    s = wave_sum(s);
+    if (lane == 0) lds[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = lds[0];
+      for (int w = 1; w < NT / kWave; ++w) t += lds[w];
+      totals[q] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Thread 0 of the last block: turns the reduced sums of T consecutive steps
+// (tot[s * kAcc + q]) into trace records and updates the run state and the
+// stop decision.
+__device__ inline void finalize_steps(RunState* st, double* trace, const double* tot, int T,
+                                      int64_t step0, const Coef& cp, const Coef& cn, double dV,
+                                      double stop_tol, int64_t min_stop_step) {
+  st->passes += 1;
+  for (int s = 0; s < T; ++s) {
+    if (st->done) break;
+    const int64_t l = step0 + s;
+    const double* a = tot + s * kAcc;
+    double rec[IT_TRACE_COLS];
+    rec[0] = a[0] * dV;
+    rec[1] = cp.azp * a[1] * dV;
+    rec[2] = cp.azm * a[2] * dV;
+    rec[3] = cn.azp * a[3] * dV;
+    rec[4] = cn.azm * a[4] * dV;
+    rec[5] = a[5] * dV;
+    rec[6] = a[6] * dV;
+    rec[7] = a[7] * dV;
+    rec[8] = a[8] * dV;
+    rec[9] = st->released_pending;
+    st->released_pending = 0.0;
+    bool finite = true;
+    for (int q = 0; q < IT_TRACE_COLS; ++q) {
+      trace[l * IT_TRACE_COLS + q] = rec[q];
+      finite = finite && isfinite(rec[q]);
+    }
+    for (int q = 0; q < 5; ++q) st->sums[q] += rec[q];
+    for (int q = 0; q < 4; ++q) st->last[q] = rec[5 + q];
+    st->steps = l + 1;
+    if (!finite) {
+      st->flags |= IT_FLAG_NONFINITE;
+      st->done = 1;
+      break;
+    }
+    const double lim = stop_tol * st->released;
+    if (l >= min_stop_step && rec[7] <= lim && rec[8] <= lim) {
+      st->done = 1;
+      break;
+    }
+  }
+}
+
+// Tile decode shared by the kernels: tiles are numbered row-of-tiles major
+// (ty, then z-chunk, then tx) and split into 8 contiguous ranges, one per
+// XCD; block b runs on XCD b % 8 (round-robin dispatch), so each XCD works
+// on one slab of rows and finds the halo rows of its tiles in its own L2.
+struct TileCoord {
+  int tx, ty, zc;
+  bool valid;
+};
+
+__device__ inline TileCoord decode_tile(int tiles_x, int zchunks, int ntiles, int per_xcd) {
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per_xcd + (b >> 3);
+  TileCoord t;
+  t.valid = L < ntiles;
+  const int l = t.valid ? L : 0;
+  t.tx = l % tiles_x;
+  const int rest = l / tiles_x;
+  t.zc = rest % zchunks;
+  t.ty = rest / zchunks;
+  return t;
+}
+
+}  // namespace it

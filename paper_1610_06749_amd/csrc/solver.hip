@@ -1,0 +1,575 @@
+// Host side of the C ABI: validation, time step, coefficients, workspace
+// layout, the deposit schedule and the stepping loop with its stop checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace it {
+
+hipError_t launch_step_blocked(const StepParams& p, int T, int tile_y, hipStream_t s);
+int blocked_supported(int T, int tile_y);
+void blocked_tiling(int nx, int ny, int nz, int T, int tile_y, int* grid, int* per_xcd,
+                    int* tiles_x, int* tiles_y, int* ntiles);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultT = 1;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+int check_chamber(const it_chamber* ch) {
+  if (!ch) return IT_EINVAL;
+  if (ch->nx < 1 || ch->ny < 1 || ch->nz < 2 || ch->reserved0 != 0) return IT_EINVAL;
+  const double cells = (double)ch->nx * ch->ny * (double)(ch->nz + 1);
+  if (cells > 4.0e9) return IT_EINVAL;  // 32-bit tile indices and 64-bit offsets suffice below
+  if (!(std::isfinite(ch->dx) && ch->dx > 0 && std::isfinite(ch->dy) && ch->dy > 0)) return IT_EINVAL;
+  if (!(std::isfinite(ch->gap) && ch->gap > 0)) return IT_EINVAL;
+  if (!std::isfinite(ch->voltage)) return IT_EINVAL;
+  if (!finite_nonneg(ch->mu_pos) || !finite_nonneg(ch->mu_neg)) return IT_EINVAL;
+  if (!finite_nonneg(ch->D_pos) || !finite_nonneg(ch->D_neg)) return IT_EINVAL;
+  if (!finite_nonneg(ch->alpha)) return IT_EINVAL;
+  if (!(std::isfinite(ch->W_eV) && ch->W_eV > 0)) return IT_EINVAL;
+  if (!(std::isfinite(ch->dt_safety) && ch->dt_safety > 0 && ch->dt_safety <= 1.0)) return IT_EINVAL;
+  if (!finite_nonneg(ch->stop_tol) || !finite_nonneg(ch->uniform_n0)) return IT_EINVAL;
+  if (ch->max_steps < 1) return IT_EINVAL;
+  return IT_OK;
+}
+
+// Largest dt with 2(sx+sy+sz) + c^2 <= 1 for each species (eq. vNeum with
+// the field along z; the product condition then holds for any dt).
+int compute_dt(const it_chamber* ch, double* dt) {
+  const double dz = ch->gap / ch->nz;
+  const double E = ch->voltage / ch->gap;
+  const double h = 1.0 / (ch->dx * ch->dx) + 1.0 / (ch->dy * ch->dy) + 1.0 / (dz * dz);
+  double best = INFINITY;
+  const double mu[2] = {ch->mu_pos, ch->mu_neg}, D[2] = {ch->D_pos, ch->D_neg};
+  for (int s = 0; s < 2; ++s) {
+    const double a = 2.0 * D[s] * h;          // diffusion part, per unit dt
+    const double vz = mu[s] * E / dz;
+    const double b = vz * vz;                 // drift part, per unit dt^2
+    double root;
+    if (b > 0.0)
+      root = 2.0 / (a + std::sqrt(a * a + 4.0 * b));
+    else if (a > 0.0)
+      root = 1.0 / a;
+    else
+      continue;
+    best = std::min(best, root);
+  }
+  if (!(best < INFINITY)) return IT_ENODT;
+  *dt = ch->dt_safety * best;
+  return IT_OK;
+}
+
+// Per-species update coefficients (see Coef).  c is signed with the drift
+// velocity: +mu+ E for positive ions (towards the cathode at z = d), -mu- E
+// for negative ions.  With a signed c the Appendix's blended drift
+// derivative gives the Lax-Wendroff weights below.
+Coef species_coef(const it_chamber* ch, double dt, int s) {
+  const double dz = ch->gap / ch->nz;
+  const double E = ch->voltage / ch->gap;
+  const double mu = s == 0 ? ch->mu_pos : ch->mu_neg;
+  const double D = s == 0 ? ch->D_pos : ch->D_neg;
+  const double c = (s == 0 ? mu * E : -mu * E) * dt / dz;
+  const double sx = D * dt / (ch->dx * ch->dx);
+  const double sy = D * dt / (ch->dy * ch->dy);
+  const double sz = D * dt / (dz * dz);
+  Coef k;
+  k.ax = sx;
+  k.ay = sy;
+  k.azp = sz + 0.5 * c * c - 0.5 * c;
+  k.azm = sz + 0.5 * c * c + 0.5 * c;
+  k.a0 = 1.0 - 2.0 * (sx + sy + sz) - c * c;
+  return k;
+}
+
+struct Tiling {
+  int tiles_x, tiles_y, zchunks, zc, ntiles, per_xcd, grid;
+};
+
+// 64 x 4 column tiles; z split into chunks so that the grid has about
+// `target` blocks (enough waves to cover HBM latency on 256 CUs).
+Tiling plain_tiling(int nx, int ny, int nz, int target = 2048) {
+  Tiling t;
+  const int nint = nz - 1;
+  t.tiles_x = (nx + 63) / 64;
+  t.tiles_y = (ny + 3) / 4;
+  const long cols = (long)t.tiles_x * t.tiles_y;
+  long want = std::max<long>(1, (target + cols - 1) / cols);
+  want = std::min<long>(want, nint);
+  t.zc = (int)((nint + want - 1) / want);
+  t.zc = std::max(t.zc, std::min(4, nint));
+  t.zchunks = (nint + t.zc - 1) / t.zc;
+  t.ntiles = (int)(cols * t.zchunks);
+  t.per_xcd = (t.ntiles + 7) / 8;
+  t.grid = 8 * t.per_xcd;
+  return t;
+}
+
+struct Layout {
+  size_t field_elems;
+  size_t off_field[4];
+  size_t off_partials, partial_doubles;
+  size_t off_counter;
+  size_t off_state;
+  size_t off_tracks;
+  size_t off_trace;
+  size_t total;
+};
+
+size_t max_grid(const it_chamber* ch) {
+  size_t g = (size_t)plain_tiling(ch->nx, ch->ny, ch->nz).grid;
+  for (int T = 2; T <= kMaxT; ++T) {
+    if (!blocked_supported(T, 0)) continue;
+    int grid, per, tx, ty, nt;
+    blocked_tiling(ch->nx, ch->ny, ch->nz, T, 0, &grid, &per, &tx, &ty, &nt);
+    g = std::max(g, (size_t)grid);
+  }
+  return g;
+}
+
+Layout make_layout(const it_chamber* ch, int64_t ntracks) {
+  Layout L;
+  L.field_elems = (size_t)(ch->nz + 1) * ch->ny * ch->nx;
+  size_t off = 0;
+  for (int f = 0; f < 4; ++f) {
+    L.off_field[f] = off;
+    off = align_up(off + L.field_elems * sizeof(double));
+  }
+  // blocked kernels use up to 16 tile-row variants; reserve for the largest grid
+  L.partial_doubles = max_grid(ch) * 4 * (size_t)kAcc * kMaxT;
+  L.off_partials = off;
+  off = align_up(off + L.partial_doubles * sizeof(double));
+  L.off_counter = off;
+  off = align_up(off + 64 * sizeof(unsigned));
+  L.off_state = off;
+  off = align_up(off + sizeof(RunState));
+  L.off_tracks = off;
+  off = align_up(off + (size_t)std::max<int64_t>(ntracks, 1) * sizeof(DepTrack));
+  L.off_trace = off;
+  off = align_up(off + (size_t)ch->max_steps * IT_TRACE_COLS * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int check_tracks(const it_track* tr, int64_t n) {
+  if (n < 0) return IT_EINVAL;
+  if (n > 0 && !tr) return IT_EINVAL;
+  if (n > (int64_t)1 << 31) return IT_EINVAL;
+  for (int64_t q = 0; q < n; ++q) {
+    const it_track& t = tr[q];
+    if (!finite_nonneg(t.let_keV_um) || !(std::isfinite(t.b_cm) && t.b_cm > 0)) return IT_EINVAL;
+    if (!std::isfinite(t.x_cm) || !std::isfinite(t.y_cm)) return IT_EINVAL;
+    if (!std::isfinite(t.theta) || !std::isfinite(t.phi)) return IT_EINVAL;
+    if (!finite_nonneg(t.t_s)) return IT_EINVAL;
+  }
+  return IT_OK;
+}
+
+int64_t deposit_step(double t, double dt) {
+  const double s = std::floor(t / dt);
+  if (s > 4.0e18) return INT64_MAX;
+  return (int64_t)s;
+}
+
+// Pinned host slots for reading the run state back: 4 per host thread and
+// device, allocated on first use and kept for the life of the process.
+RunState* pinned_slots() {
+  thread_local RunState* slots[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!slots[dev]) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 4 * sizeof(RunState), hipHostMallocDefault) != hipSuccess) return nullptr;
+    slots[dev] = (RunState*)p;
+  }
+  return slots[dev];
+}
+
+#define HIP_TRY(expr)                               \
+  do {                                              \
+    if ((expr) != hipSuccess) return IT_EHIP;       \
+  } while (0)
+
+struct Event {
+  int64_t step;
+  int64_t par_begin, par_count, tilt_begin, tilt_count;
+  bool uniform;
+};
+
+// The stepping loop shared by it_solve and it_advance.  Enqueues passes of
+// up to T steps, cut at deposit steps, and reads the run state back every
+// `check_every` steps (two checks in flight) to stop once the device has
+// flagged completion.
+int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const Layout& L,
+             const std::vector<Event>& events, const std::vector<DepTrack>& dev_tracks,
+             int64_t nsteps, int64_t min_stop_step, double stop_tol, hipStream_t stream,
+             RunState* final_state, int* passes_issued) {
+  const int kernel = ex ? ex->kernel : IT_KERNEL_AUTO;
+  int T = ex && ex->steps_per_pass > 0 ? ex->steps_per_pass : kDefaultT;
+  const int tile_y = ex ? ex->tile_y : 0;
+  if (kernel == IT_KERNEL_PLAIN) T = 1;
+  if (T < 1 || T > kMaxT) return IT_EINVAL;
+  if (T > 1 && !blocked_supported(T, tile_y)) return IT_ENOTSUP;
+  int64_t check_every = ex && ex->check_every > 0 ? ex->check_every : 64;
+
+  double* field[4];
+  for (int f = 0; f < 4; ++f) field[f] = (double*)(ws + L.off_field[f]);
+  double* partials = (double*)(ws + L.off_partials);
+  unsigned* counter = (unsigned*)(ws + L.off_counter);
+  RunState* state = (RunState*)(ws + L.off_state);
+  DepTrack* tracks = (DepTrack*)(ws + L.off_tracks);
+  double* trace = (double*)(ws + L.off_trace);
+  (void)dev_tracks;
+
+  const Coef cp = species_coef(ch, dt, 0), cn = species_coef(ch, dt, 1);
+  const double dz = ch->gap / ch->nz;
+  const double dV = ch->dx * ch->dy * dz;
+  const Tiling tp = plain_tiling(ch->nx, ch->ny, ch->nz);
+
+  RunState* slots = pinned_slots();
+  if (!slots) return IT_EHIP;
+
+  StepParams sp;
+  sp.nx = ch->nx;
+  sp.ny = ch->ny;
+  sp.nz = ch->nz;
+  sp.cp = cp;
+  sp.cn = cn;
+  sp.beta = ch->alpha * dt;
+  sp.dV = dV;
+  sp.stop_tol = stop_tol;
+  sp.min_stop_step = min_stop_step;
+  sp.partials = partials;
+  sp.counter = counter;
+  sp.state = state;
+  sp.trace = trace;
+
+  DepositParams dp;
+  dp.nx = ch->nx;
+  dp.ny = ch->ny;
+  dp.nz = ch->nz;
+  dp.tiles_x = tp.tiles_x;
+  dp.tiles_y = tp.tiles_y;
+  dp.zchunks = tp.zchunks;
+  dp.zc = tp.zc;
+  dp.ntiles = tp.ntiles;
+  dp.per_xcd = tp.per_xcd;
+  dp.dx = ch->dx;
+  dp.dy = ch->dy;
+  dp.dz = dz;
+  dp.half_gap = 0.5 * ch->gap;
+  dp.Lx = ch->nx * ch->dx;
+  dp.Ly = ch->ny * ch->dy;
+  dp.dV = dV;
+  dp.beta = ch->alpha * dt;
+  dp.partials = partials;
+  dp.counter = counter;
+  dp.state = state;
+
+  int cur = 0;  // field pair index: 0 -> (field0, field1), 1 -> (field2, field3)
+  int64_t l = 0;
+  size_t ev = 0;
+  int issued = 0;
+  int64_t since_check = 0;
+  int pending = 0, slot_head = 0;
+  hipEvent_t evs[4];
+  for (int q = 0; q < 4; ++q)
+    if (hipEventCreateWithFlags(&evs[q], hipEventDisableTiming) != hipSuccess) {
+      for (int r = 0; r < q; ++r) (void)hipEventDestroy(evs[r]);
+      return IT_EHIP;
+    }
+  int rc = IT_OK;
+  bool stopped = false;
+  auto fail = [&](int code) {
+    rc = code;
+    return code;
+  };
+  while (l < nsteps && !stopped) {
+    if (ev < events.size() && events[ev].step == l) {
+      const Event& e = events[ev];
+      dp.pos = field[2 * cur];
+      dp.neg = field[2 * cur + 1];
+      dp.uniform = e.uniform ? ch->uniform_n0 : 0.0;
+      dp.par = tracks + e.par_begin;
+      dp.npar = (int)e.par_count;
+      dp.tilt = tracks + e.tilt_begin;
+      dp.ntilt = (int)e.tilt_count;
+      if (launch_deposit(dp, stream) != hipSuccess) { fail(IT_EHIP); break; }
+      ++ev;
+    }
+    const int64_t next_dep = ev < events.size() ? events[ev].step : nsteps;
+    const int64_t todo = std::min<int64_t>(std::min<int64_t>(T, next_dep - l), nsteps - l);
+    sp.pin = field[2 * cur];
+    sp.nin = field[2 * cur + 1];
+    sp.pout = field[2 * (1 - cur)];
+    sp.nout = field[2 * (1 - cur) + 1];
+    sp.step0 = l;
+    hipError_t e;
+    if (todo == 1) {
+      sp.tiles_x = tp.tiles_x;
+      sp.tiles_y = tp.tiles_y;
+      sp.zchunks = tp.zchunks;
+      sp.zc = tp.zc;
+      sp.ntiles = tp.ntiles;
+      sp.per_xcd = tp.per_xcd;
+      e = launch_step_plain(sp, stream);
+    } else {
+      e = launch_step_blocked(sp, (int)todo, tile_y, stream);
+    }
+    if (e != hipSuccess) { fail(IT_EHIP); break; }
+    ++issued;
+    cur = 1 - cur;
+    l += todo;
+    since_check += todo;
+    if (since_check >= check_every || l >= nsteps) {
+      since_check = 0;
+      RunState* slot = &slots[slot_head];
+      if (hipMemcpyAsync(slot, state, sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipEventRecord(evs[slot_head], stream) != hipSuccess) { fail(IT_EHIP); break; }
+      slot_head = (slot_head + 1) & 3;
+      ++pending;
+      if (pending >= 2) {
+        const int oldest = (slot_head + 4 - pending) & 3;
+        if (hipEventSynchronize(evs[oldest]) != hipSuccess) { fail(IT_EHIP); break; }
+        --pending;
+        if (slots[oldest].done) stopped = true;
+      }
+    }
+  }
+  if (rc == IT_OK) {
+    if (hipMemcpyAsync(&slots[slot_head], state, sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      rc = IT_EHIP;
+    else
+      *final_state = slots[slot_head];
+  } else {
+    (void)hipStreamSynchronize(stream);
+  }
+  for (int q = 0; q < 4; ++q) (void)hipEventDestroy(evs[q]);
+  *passes_issued = issued;
+  return rc;
+}
+
+}  // namespace
+}  // namespace it
+
+using namespace it;
+
+extern "C" {
+
+const char* it_strerror(int code) {
+  switch (code) {
+    case IT_OK: return "ok";
+    case IT_EINVAL: return "invalid argument (size, constant or track out of range)";
+    case IT_ENODT: return "no stable time step: neither drift nor diffusion bounds dt";
+    case IT_EWORKSPACE: return "workspace missing or smaller than it_workspace_size()";
+    case IT_EHIP: return "HIP runtime error";
+    case IT_ENOTSUP: return "option not supported by this build";
+    default: return "unknown status code";
+  }
+}
+
+int it_dt(const it_chamber* ch, double* dt) {
+  if (!dt) return IT_EINVAL;
+  int rc = check_chamber(ch);
+  if (rc) return rc;
+  return compute_dt(ch, dt);
+}
+
+int it_validate(const it_chamber* ch, const it_track* tracks, int64_t ntracks) {
+  int rc = check_chamber(ch);
+  if (rc) return rc;
+  double dt;
+  rc = compute_dt(ch, &dt);
+  if (rc) return rc;
+  return check_tracks(tracks, ntracks);
+}
+
+int it_workspace_size(const it_chamber* ch, int64_t ntracks, size_t* bytes) {
+  if (!bytes || ntracks < 0) return IT_EINVAL;
+  int rc = check_chamber(ch);
+  if (rc) return rc;
+  *bytes = make_layout(ch, ntracks).total;
+  return IT_OK;
+}
+
+int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, const it_exec* exec,
+             void* d_workspace, size_t ws_bytes, void* stream_, double* h_trace, double* d_pos_out,
+             double* d_neg_out, it_result* out) {
+  if (!out) return IT_EINVAL;
+  int rc = it_validate(ch, tracks, ntracks);
+  if (rc) return rc;
+  const Layout L = make_layout(ch, ntracks);
+  if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
+  double dt;
+  compute_dt(ch, &dt);
+  hipStream_t stream = (hipStream_t)stream_;
+  char* ws = (char*)d_workspace;
+
+  // Deposit schedule: tracks grouped by step floor(t/dt), parallel ones first.
+  struct Item {
+    int64_t step;
+    int tilted;
+    int64_t index;
+  };
+  std::vector<Item> items;
+  items.reserve(ntracks);
+  for (int64_t q = 0; q < ntracks; ++q) {
+    const int64_t s = deposit_step(tracks[q].t_s, dt);
+    if (s >= ch->max_steps) continue;
+    const double st = std::sin(tracks[q].theta);
+    const bool par = st == 0.0;
+    items.push_back({s, par ? 0 : 1, q});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.step != b.step ? a.step < b.step : a.tilted < b.tilted;
+  });
+  std::vector<DepTrack> dev(items.size());
+  for (size_t q = 0; q < items.size(); ++q) {
+    const it_track& t = tracks[items[q].index];
+    DepTrack& d = dev[q];
+    d.x0 = t.x_cm;
+    d.y0 = t.y_cm;
+    d.ux = std::sin(t.theta) * std::cos(t.phi);
+    d.uy = std::sin(t.theta) * std::sin(t.phi);
+    d.uz = std::cos(t.theta);
+    const double N0 = t.let_keV_um * 1.0e7 / ch->W_eV;  // keV/um -> eV/cm, / W
+    d.peak = N0 / (M_PI * t.b_cm * t.b_cm);
+    d.inv_b2 = 1.0 / (t.b_cm * t.b_cm);
+    d.cut2 = 64.0 * t.b_cm * t.b_cm;
+  }
+  std::vector<Event> events;
+  int64_t last_dep = -1;
+  for (size_t q = 0; q < items.size();) {
+    Event e;
+    e.step = items[q].step;
+    e.uniform = false;
+    e.par_begin = (int64_t)q;
+    size_t r = q;
+    while (r < items.size() && items[r].step == e.step && items[r].tilted == 0) ++r;
+    e.par_count = (int64_t)(r - q);
+    e.tilt_begin = (int64_t)r;
+    while (r < items.size() && items[r].step == e.step) ++r;
+    e.tilt_count = (int64_t)r - e.tilt_begin;
+    events.push_back(e);
+    last_dep = e.step;
+    q = r;
+  }
+  if (ch->uniform_n0 > 0.0) {
+    if (events.empty() || events[0].step != 0) {
+      Event e{0, 0, 0, 0, 0, true};
+      events.insert(events.begin(), e);
+    } else {
+      events[0].uniform = true;
+    }
+    last_dep = std::max<int64_t>(last_dep, 0);
+  }
+
+  for (int f = 0; f < 4; ++f)
+    HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, L.field_elems * sizeof(double), stream));
+  HIP_TRY(hipMemsetAsync(ws + L.off_counter, 0, 64 * sizeof(unsigned), stream));
+  RunState init;
+  std::memset(&init, 0, sizeof(init));
+  HIP_TRY(hipMemcpyAsync(ws + L.off_state, &init, sizeof(init), hipMemcpyHostToDevice, stream));
+  if (!dev.empty())
+    HIP_TRY(hipMemcpyAsync(ws + L.off_tracks, dev.data(), dev.size() * sizeof(DepTrack),
+                           hipMemcpyHostToDevice, stream));
+
+  RunState fin;
+  int issued = 0;
+  rc = run_loop(ch, dt, exec, ws, L, events, dev, ch->max_steps, std::max<int64_t>(last_dep, 0),
+                ch->stop_tol, stream, &fin, &issued);
+  if (rc) return rc;
+
+  std::memset(out, 0, sizeof(*out));
+  const double collected = fin.sums[1] + fin.sums[2] + fin.sums[3] + fin.sums[4];
+  int flags = fin.flags;
+  if (!fin.done && fin.steps >= ch->max_steps) flags |= IT_FLAG_MAX_STEPS;
+  if (fin.max_beta_n > 1.0) flags |= IT_FLAG_REACTION;
+  if (fin.released > 0.0) {
+    out->f = collected / (2.0 * fin.released);
+    out->f_R = 1.0 - fin.sums[0] / fin.released;
+  } else {
+    out->f = 1.0;
+    out->f_R = 1.0;
+    flags |= IT_FLAG_EMPTY;
+  }
+  out->ks = 1.0 / out->f;
+  out->n_released = fin.released;
+  out->n_recombined = fin.sums[0];
+  out->n_inflight_pos = fin.last[0];
+  out->n_inflight_neg = fin.last[1];
+  out->col_pos_anode = fin.sums[1];
+  out->col_pos_cathode = fin.sums[2];
+  out->col_neg_anode = fin.sums[3];
+  out->col_neg_cathode = fin.sums[4];
+  out->dt = dt;
+  out->max_beta_n = fin.max_beta_n;
+  out->steps = fin.steps;
+  out->flags = flags;
+  out->passes = issued;
+
+  if (h_trace && fin.steps > 0)
+    HIP_TRY(hipMemcpy(h_trace, ws + L.off_trace, (size_t)fin.steps * IT_TRACE_COLS * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  const int last = fin.passes & 1;  // field pair holding the latest densities
+  if (d_pos_out)
+    HIP_TRY(hipMemcpyAsync(d_pos_out, ws + L.off_field[2 * last], L.field_elems * sizeof(double),
+                           hipMemcpyDeviceToDevice, stream));
+  if (d_neg_out)
+    HIP_TRY(hipMemcpyAsync(d_neg_out, ws + L.off_field[2 * last + 1], L.field_elems * sizeof(double),
+                           hipMemcpyDeviceToDevice, stream));
+  if (d_pos_out || d_neg_out) HIP_TRY(hipStreamSynchronize(stream));
+  return IT_OK;
+}
+
+int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* exec, double* d_pos,
+               double* d_neg, void* d_workspace, size_t ws_bytes, void* stream_, double* h_trace) {
+  int rc = check_chamber(ch);
+  if (rc) return rc;
+  if (!d_pos || !d_neg || nsteps < 0 || nsteps > ch->max_steps) return IT_EINVAL;
+  if (!(std::isfinite(dt) && dt > 0)) return IT_EINVAL;
+  const Layout L = make_layout(ch, 0);
+  if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
+  if (nsteps == 0) return IT_OK;
+  hipStream_t stream = (hipStream_t)stream_;
+  char* ws = (char*)d_workspace;
+  const size_t plane = (size_t)ch->nx * ch->ny * sizeof(double);
+  const size_t bytes = L.field_elems * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(ws + L.off_field[0], d_pos, bytes, hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(ws + L.off_field[1], d_neg, bytes, hipMemcpyDeviceToDevice, stream));
+  for (int f = 0; f < 2; ++f) {  // electrode planes of the input pair are zero by definition
+    HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, plane, stream));
+    HIP_TRY(hipMemsetAsync(ws + L.off_field[f] + (size_t)ch->nz * plane, 0, plane, stream));
+  }
+  for (int f = 2; f < 4; ++f) HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, bytes, stream));
+  HIP_TRY(hipMemsetAsync(ws + L.off_counter, 0, 64 * sizeof(unsigned), stream));
+  RunState init;
+  std::memset(&init, 0, sizeof(init));
+  HIP_TRY(hipMemcpyAsync(ws + L.off_state, &init, sizeof(init), hipMemcpyHostToDevice, stream));
+  std::vector<Event> none;
+  std::vector<DepTrack> nodev;
+  RunState fin;
+  int issued = 0;
+  rc = run_loop(ch, dt, exec, ws, L, none, nodev, nsteps, INT64_MAX, 0.0, stream, &fin, &issued);
+  if (rc) return rc;
+  const int last = fin.passes & 1;
+  HIP_TRY(hipMemcpyAsync(d_pos, ws + L.off_field[2 * last], bytes, hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(d_neg, ws + L.off_field[2 * last + 1], bytes, hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (h_trace)
+    HIP_TRY(hipMemcpy(h_trace, ws + L.off_trace, (size_t)nsteps * IT_TRACE_COLS * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  return IT_OK;
+}
+
+}  // extern "C"

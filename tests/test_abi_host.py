@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function the header declares, and its host-only entry points agree
+with the oracle's time step and reject bad input."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(it_\w+)\s*\(", src, flags=re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1610_06749_amd as it
+    return it
+
+
+def test_header_declares_the_abi():
+    names = _declared()
+    assert {"it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance", "it_strerror"} <= names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = ctypes.CDLL(lib.binding.LIB_PATH)
+    for name in sorted(_declared()):
+        assert hasattr(L, name), name
+
+
+def test_host_dt_matches_oracle(lib, orc):
+    for ch in (W.single_track()[0], W.pulsed_beam()[0], W.continuous_beam()[0],
+               W.chamber(5, 7, 9, 3e-4, 0.01, 0.0), W.chamber(5, 7, 9, 3e-4, 0.01, 80.0, D_pos=0.0, D_neg=0.0)):
+        assert lib.it_dt(ch) == pytest.approx(orc.dt(ch), rel=1e-15)
+
+
+def test_validate_rejects_bad_input(lib):
+    ch, tr = W.single_track()
+    lib.it_validate(ch, tr)
+    for key, val in (("nz", 1), ("nx", 0), ("dx", -1.0), ("dt_safety", 1.5), ("alpha", -1.0),
+                     ("max_steps", 0), ("W_eV", 0.0), ("D_pos", float("nan"))):
+        with pytest.raises(lib.ItError) as e:
+            lib.it_validate(dict(ch, **{key: val}), tr)
+        assert e.value.code == lib.IT_EINVAL
+    for col, val in ((1, 0.0), (0, -1.0), (6, -1e-9), (2, float("inf"))):
+        bad = tr.copy()
+        bad[0, col] = val
+        with pytest.raises(lib.ItError):
+            lib.it_validate(ch, bad)
+    with pytest.raises(lib.ItError) as e:
+        lib.it_validate(W.chamber(4, 4, 8, 1e-3, 0.08, 0.0, D_pos=0.0, D_neg=0.0), tr)
+    assert e.value.code == lib.IT_ENODT
+
+
+def test_workspace_size_covers_fields_and_trace(lib):
+    ch, _ = W.pulsed_beam()
+    n = lib.it_workspace_size(ch, 400)
+    field = (ch["nz"] + 1) * ch["ny"] * ch["nx"] * 8
+    assert n >= 4 * field + ch["max_steps"] * 10 * 8
+    assert lib.it_workspace_size(dict(ch, max_steps=10), 400) < n
+
+
+def test_strerror_names_codes(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.it_strerror(code) and lib.it_strerror(code) != "unknown status code"
+    assert lib.it_strerror(-99) == "unknown status code"
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1610_06749_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", src, flags=re.M), fn
+                assert "liboracle" not in src and "oracle.c" not in src, fn
