@@ -84,6 +84,7 @@ typedef struct {
   double dt_safety;     /* factor in (0, 1] on the largest stable dt (eq. vNeum) */
   double stop_tol;      /* stop once sum |n| dV <= stop_tol * released for both species (>= 0) */
   double uniform_n0;    /* uniform ion-pair density added at t = 0 [cm^-3] (>= 0) */
+  double reaction_limit;/* rho >= 0: also bound dt by alpha dt n_ref <= rho (0 = off), see it_dt */
   int64_t max_steps;    /* hard step limit (>= 1) */
 } it_chamber;
 
@@ -126,9 +127,16 @@ typedef struct {
   int32_t check_every;     /* steps between host checks of the stop criterion (0 = default) */
 } it_exec;
 
-/* Largest stable time step of eq. vNeum times dt_safety.  Host only: touches
- * no device.  Errors: IT_EINVAL (bad chamber), IT_ENODT. */
-int it_dt(const it_chamber* ch, double* dt);
+/* Time step of a run: dt_safety times the smaller of
+ *   - the largest dt satisfying eq. vNeum for both species (with the field
+ *     along z: 2 D dt (1/dx^2 + 1/dy^2 + 1/dz^2) + (mu E dt/dz)^2 <= 1), and
+ *   - when reaction_limit > 0 and alpha > 0: reaction_limit / (alpha n_ref),
+ *     because the explicit recombination sink diverges once alpha dt n
+ *     exceeds about 1 at dense track cores.  n_ref is uniform_n0 plus the
+ *     largest density found on any track's axis at mid-gap from all tracks
+ *     with the same arrival time (host array; may be NULL if ntracks = 0).
+ * Host only: touches no device.  Errors: IT_EINVAL, IT_ENODT. */
+int it_dt(const it_chamber* ch, const it_track* tracks, int64_t ntracks, double* dt);
 
 /* Checks a chamber and a track list (host arrays; tracks may be NULL when
  * ntracks == 0).  Host only.  Errors: IT_EINVAL, IT_ENODT. */

@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
-          "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge")
+          "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit")
 R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
           "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
           "col_neg_cathode", "dt", "steps", "flags", "max_beta_n")
@@ -54,7 +54,9 @@ def lib():
         L = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64
-        L.orc_dt.argtypes = [dp, i64, dp]
+        L.orc_dt.argtypes = [dp, i64, i64, i64, dp, i64, dp]
+        L.orc_reference_density.argtypes = [dp, i64, i64, dp, i64]
+        L.orc_reference_density.restype = ctypes.c_double
         L.orc_dt.restype = ctypes.c_int
         L.orc_weights.argtypes = [dp, i64, ctypes.c_double, ctypes.c_int, dp]
         L.orc_weights.restype = None
@@ -87,9 +89,23 @@ def _shape(ch):
     return (ch["nz"] + 1, ch["ny"], ch["nx"])
 
 
-def dt(ch) -> float:
+def _trk(tracks):
+    if tracks is None:
+        return np.zeros((0, 7))
+    return np.ascontiguousarray(tracks, dtype=np.float64).reshape(-1, 7)
+
+
+def reference_density(ch, tracks) -> float:
+    tr = _trk(tracks)
+    return lib().orc_reference_density(_ptr(_params(ch)), ch["nx"], ch["ny"], _ptr(tr), tr.shape[0])
+
+
+def dt(ch, tracks=None) -> float:
+    """Time step for this chamber and track list (the track list only
+    matters through the recombination bound)."""
     out = np.zeros(1)
-    rc = lib().orc_dt(_ptr(_params(ch)), ch["nz"], _ptr(out))
+    tr = _trk(tracks)
+    rc = lib().orc_dt(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr), tr.shape[0], _ptr(out))
     if rc:
         raise ValueError("no stable time step: neither drift nor diffusion constrains dt")
     return float(out[0])

@@ -19,7 +19,8 @@
  *     and a central difference with weight c, the 3-point second difference
  *                                                             (Appendix)
  *   - the largest dt obeying 2(sx+sy+sz) + cx^2+cy^2+cz^2 <= 1 and
- *     cx^2 cy^2 cz^2 <= 8 sx sy sz for both species           (eq. vNeum)
+ *     cx^2 cy^2 cz^2 <= 8 sx sy sz for both species           (eq. vNeum),
+ *     optionally also alpha dt n_ref <= rho (see orc_dt)
  *   - electrodes at z=0 and z=d hold zero density; charge reaching them is
  *     collected                                                 (Methods, Implementation)
  *   - f = N_collected / N_released                              (eq. collection_efficiency)
@@ -55,7 +56,7 @@
 /* parameter vector (mirrors the chamber dictionary) */
 enum {
   P_DX, P_DY, P_GAP, P_VOLT, P_MU_POS, P_MU_NEG, P_D_POS, P_D_NEG,
-  P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_COUNT
+  P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_REACTION_LIMIT, P_COUNT
 };
 /* result vector */
 enum {
@@ -74,12 +75,12 @@ enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_I
 
 #define IDX(k, j, i) (((size_t)(k) * (size_t)ny + (size_t)(j)) * (size_t)nx + (size_t)(i))
 
-/* Largest dt satisfying eq. vNeum for both species, times the safety factor.
+/* Largest dt satisfying eq. vNeum for both species (no safety factor).
  * With the field along z only, cx = cy = 0: the product condition holds
  * trivially and the first condition is A dt + B dt^2 <= 1 with
  * A = 2 D (1/dx^2 + 1/dy^2 + 1/dz^2) and B = (mu E / dz)^2.
- * Returns 0, or -2 if neither species constrains dt (no drift, no diffusion). */
-int orc_dt(const double *p, int64_t nz, double *dt)
+ * Returns INFINITY if neither species constrains dt (no drift, no diffusion). */
+static double transport_dt(const double *p, int64_t nz)
 {
   const double dz = p[P_GAP] / (double)nz;
   const double E = p[P_VOLT] / p[P_GAP];
@@ -100,9 +101,7 @@ int orc_dt(const double *p, int64_t nz, double *dt)
       continue;
     if (root < best) best = root;
   }
-  if (!(best < INFINITY)) return -2;
-  *dt = p[P_KAPPA] * best;
-  return 0;
+  return best;
 }
 
 /* Weights of the Appendix for species s (0 = positive, 1 = negative):
@@ -151,6 +150,68 @@ static double track_density(const double *p, int64_t nx, int64_t ny, int64_t nz,
   const double r2 = cx * cx + cy * cy + cz * cz;
   if (r2 > 64.0 * b * b) return 0.0;
   return N0 / (M_PI * b * b) * exp(-r2 / (b * b));
+}
+
+/* Density that track tr deposits at the point (x, y, z) (same rule as at
+ * the nodes: wrapped transverse offset, 8b cut-off). */
+static double track_density_at(const double *p, int64_t nx, int64_t ny, const double *tr,
+                               const double *u, double x, double y, double z)
+{
+  const double N0 = tr[0] * 1.0e7 / p[P_W];
+  const double b = tr[1];
+  const double wx = wrap(x - tr[2], (double)nx * p[P_DX]);
+  const double wy = wrap(y - tr[3], (double)ny * p[P_DY]);
+  const double wz = z - 0.5 * p[P_GAP];
+  const double cx = wy * u[2] - wz * u[1];
+  const double cy = wz * u[0] - wx * u[2];
+  const double cz = wx * u[1] - wy * u[0];
+  const double r2 = cx * cx + cy * cy + cz * cz;
+  if (r2 > 64.0 * b * b) return 0.0;
+  return N0 / (M_PI * b * b) * exp(-r2 / (b * b));
+}
+
+/* Reference peak density for the recombination bound on dt: the uniform
+ * pre-ionisation plus, over all tracks, the largest density found on a
+ * track's axis at mid-gap from every track that arrives at the same time. */
+double orc_reference_density(const double *p, int64_t nx, int64_t ny, const double *trk, int64_t ntr)
+{
+  double best = 0.0;
+  for (int64_t t = 0; t < ntr; ++t) {
+    const double *a = trk + 7 * t;
+    double s = 0.0;
+    for (int64_t q = 0; q < ntr; ++q) {
+      const double *tr = trk + 7 * q;
+      if (tr[6] != a[6]) continue;
+      double u[3];
+      track_axis(tr, u);
+      s += track_density_at(p, nx, ny, tr, u, a[2], a[3], 0.5 * p[P_GAP]);
+    }
+    if (s > best) best = s;
+  }
+  return p[P_UNIFORM_N0] + best;
+}
+
+/* Time step: the largest dt of eq. vNeum, further limited (when the
+ * reaction limit rho > 0) so that alpha dt n_ref <= rho: the explicit
+ * recombination sink n' = n - alpha dt n+ n- diverges once alpha dt n
+ * exceeds about 1, which the transport bound alone does not prevent at
+ * dense track cores.  The safety factor kappa multiplies the result.
+ * Returns 0, or -2 if nothing bounds dt. */
+int orc_dt(const double *p, int64_t nx, int64_t ny, int64_t nz, const double *trk, int64_t ntr,
+           double *dt)
+{
+  double best = transport_dt(p, nz);
+  const double rho = p[P_REACTION_LIMIT];
+  if (rho > 0.0 && p[P_ALPHA] > 0.0) {
+    const double nref = orc_reference_density(p, nx, ny, trk, ntr);
+    if (nref > 0.0) {
+      const double dtr = rho / (p[P_ALPHA] * nref);
+      if (dtr < best) best = dtr;
+    }
+  }
+  if (!(best < INFINITY)) return -2;
+  *dt = p[P_KAPPA] * best;
+  return 0;
 }
 
 int64_t orc_deposit_step(double dt, const double *tr)
@@ -300,7 +361,7 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
               double *pos, double *neg, double *trace, double *res)
 {
   double dt;
-  int rc = orc_dt(p, nz, &dt);
+  int rc = orc_dt(p, nx, ny, nz, trk, ntr, &dt);
   if (rc) return rc;
   const int64_t n = (nz + 1) * ny * nx;
   double *npos = (double *)calloc((size_t)n, sizeof(double));

@@ -37,7 +37,8 @@ class it_chamber(ctypes.Structure):
                 ("voltage", ctypes.c_double), ("mu_pos", ctypes.c_double), ("mu_neg", ctypes.c_double),
                 ("D_pos", ctypes.c_double), ("D_neg", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("W_eV", ctypes.c_double), ("dt_safety", ctypes.c_double), ("stop_tol", ctypes.c_double),
-                ("uniform_n0", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+                ("uniform_n0", ctypes.c_double), ("reaction_limit", ctypes.c_double),
+                ("max_steps", ctypes.c_int64)]
 
 
 class it_result(ctypes.Structure):
@@ -67,7 +68,7 @@ def lib():
         chp = ctypes.POINTER(it_chamber)
         L.it_strerror.argtypes = [ctypes.c_int]
         L.it_strerror.restype = ctypes.c_char_p
-        L.it_dt.argtypes = [chp, dp]
+        L.it_dt.argtypes = [chp, vp, i64, dp]
         L.it_validate.argtypes = [chp, vp, i64]
         L.it_workspace_size.argtypes = [chp, i64, ctypes.POINTER(ctypes.c_size_t)]
         L.it_solve.argtypes = [chp, vp, i64, ctypes.POINTER(it_exec), vp, ctypes.c_size_t, vp, vp, vp, vp,
@@ -89,8 +90,8 @@ def _chamber(ch) -> it_chamber:
     for k in ("nx", "ny", "nz", "max_steps"):
         setattr(c, k, int(ch[k]))
     for k in ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg", "alpha", "W_eV",
-              "dt_safety", "stop_tol", "uniform_n0"):
-        setattr(c, k, float(ch[k]))
+              "dt_safety", "stop_tol", "uniform_n0", "reaction_limit"):
+        setattr(c, k, float(ch.get(k, 0.0)) if k == "reaction_limit" else float(ch[k]))
     if int(ch.get("space_charge", 0)):
         raise ItError(IT_ENOTSUP, "space_charge")
     return c
@@ -121,9 +122,10 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def it_dt(ch) -> float:
+def it_dt(ch, tracks=None) -> float:
+    tr, ptr = _tracks(np.zeros((0, 7)) if tracks is None else tracks)
     out = ctypes.c_double()
-    _check(lib().it_dt(ctypes.byref(_chamber(ch)), ctypes.byref(out)), "it_dt")
+    _check(lib().it_dt(ctypes.byref(_chamber(ch)), ptr, tr.shape[0], ctypes.byref(out)), "it_dt")
     return out.value
 
 

@@ -39,13 +39,14 @@ int check_chamber(const it_chamber* ch) {
   if (!(std::isfinite(ch->W_eV) && ch->W_eV > 0)) return IT_EINVAL;
   if (!(std::isfinite(ch->dt_safety) && ch->dt_safety > 0 && ch->dt_safety <= 1.0)) return IT_EINVAL;
   if (!finite_nonneg(ch->stop_tol) || !finite_nonneg(ch->uniform_n0)) return IT_EINVAL;
+  if (!finite_nonneg(ch->reaction_limit)) return IT_EINVAL;
   if (ch->max_steps < 1) return IT_EINVAL;
   return IT_OK;
 }
 
 // Largest dt with 2(sx+sy+sz) + c^2 <= 1 for each species (eq. vNeum with
 // the field along z; the product condition then holds for any dt).
-int compute_dt(const it_chamber* ch, double* dt) {
+double transport_dt(const it_chamber* ch) {
   const double dz = ch->gap / ch->nz;
   const double E = ch->voltage / ch->gap;
   const double h = 1.0 / (ch->dx * ch->dx) + 1.0 / (ch->dy * ch->dy) + 1.0 / (dz * dz);
@@ -63,6 +64,45 @@ int compute_dt(const it_chamber* ch, double* dt) {
     else
       continue;
     best = std::min(best, root);
+  }
+  return best;
+}
+
+double wrap_near_host(double d, double L) { return d - L * std::floor(d / L + 0.5); }
+
+// Reference density of the recombination bound: uniform_n0 plus the largest
+// sum, over the tracks arriving together, of their Gaussian profiles at one
+// of their axis points (x0, y0, d/2).
+double reference_density(const it_chamber* ch, const it_track* tr, int64_t n) {
+  const double Lx = ch->nx * ch->dx, Ly = ch->ny * ch->dy;
+  double best = 0.0;
+  for (int64_t a = 0; a < n; ++a) {
+    double s = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+      const it_track& t = tr[q];
+      if (t.t_s != tr[a].t_s) continue;
+      const double ux = std::sin(t.theta) * std::cos(t.phi);
+      const double uy = std::sin(t.theta) * std::sin(t.phi);
+      const double uz = std::cos(t.theta);
+      const double wx = wrap_near_host(tr[a].x_cm - t.x_cm, Lx);
+      const double wy = wrap_near_host(tr[a].y_cm - t.y_cm, Ly);
+      const double wz = 0.0;
+      const double cx = wy * uz - wz * uy, cy = wz * ux - wx * uz, cz = wx * uy - wy * ux;
+      const double r2 = cx * cx + cy * cy + cz * cz;
+      const double b2 = t.b_cm * t.b_cm;
+      if (r2 > 64.0 * b2) continue;
+      s += t.let_keV_um * 1.0e7 / ch->W_eV / (M_PI * b2) * std::exp(-r2 / b2);
+    }
+    best = std::max(best, s);
+  }
+  return ch->uniform_n0 + best;
+}
+
+int compute_dt(const it_chamber* ch, const it_track* tr, int64_t n, double* dt) {
+  double best = transport_dt(ch);
+  if (ch->reaction_limit > 0.0 && ch->alpha > 0.0) {
+    const double nref = reference_density(ch, tr, n);
+    if (nref > 0.0) best = std::min(best, ch->reaction_limit / (ch->alpha * nref));
   }
   if (!(best < INFINITY)) return IT_ENODT;
   *dt = ch->dt_safety * best;
@@ -378,20 +418,18 @@ const char* it_strerror(int code) {
   }
 }
 
-int it_dt(const it_chamber* ch, double* dt) {
+int it_dt(const it_chamber* ch, const it_track* tracks, int64_t ntracks, double* dt) {
   if (!dt) return IT_EINVAL;
   int rc = check_chamber(ch);
   if (rc) return rc;
-  return compute_dt(ch, dt);
+  rc = check_tracks(tracks, ntracks);
+  if (rc) return rc;
+  return compute_dt(ch, tracks, ntracks, dt);
 }
 
 int it_validate(const it_chamber* ch, const it_track* tracks, int64_t ntracks) {
-  int rc = check_chamber(ch);
-  if (rc) return rc;
   double dt;
-  rc = compute_dt(ch, &dt);
-  if (rc) return rc;
-  return check_tracks(tracks, ntracks);
+  return it_dt(ch, tracks, ntracks, &dt);
 }
 
 int it_workspace_size(const it_chamber* ch, int64_t ntracks, size_t* bytes) {
@@ -411,7 +449,7 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
   const Layout L = make_layout(ch, ntracks);
   if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
   double dt;
-  compute_dt(ch, &dt);
+  compute_dt(ch, tracks, ntracks, &dt);
   hipStream_t stream = (hipStream_t)stream_;
   char* ws = (char*)d_workspace;
 

@@ -44,6 +44,8 @@ def test_host_dt_matches_oracle(lib, orc):
     for ch in (W.single_track()[0], W.pulsed_beam()[0], W.continuous_beam()[0],
                W.chamber(5, 7, 9, 3e-4, 0.01, 0.0), W.chamber(5, 7, 9, 3e-4, 0.01, 80.0, D_pos=0.0, D_neg=0.0)):
         assert lib.it_dt(ch) == pytest.approx(orc.dt(ch), rel=1e-15)
+    for ch, tr in (W.single_track(), W.pulsed_beam(), W.continuous_beam(duration_s=2e-3)):
+        assert lib.it_dt(ch, tr) == pytest.approx(orc.dt(ch, tr), rel=1e-14)
 
 
 def test_validate_rejects_bad_input(lib):
@@ -60,7 +62,7 @@ def test_validate_rejects_bad_input(lib):
         with pytest.raises(lib.ItError):
             lib.it_validate(ch, bad)
     with pytest.raises(lib.ItError) as e:
-        lib.it_validate(W.chamber(4, 4, 8, 1e-3, 0.08, 0.0, D_pos=0.0, D_neg=0.0), tr)
+        lib.it_validate(W.chamber(4, 4, 8, 1e-3, 0.08, 0.0, D_pos=0.0, D_neg=0.0, reaction_limit=0.0), tr)
     assert e.value.code == lib.IT_ENODT
 
 

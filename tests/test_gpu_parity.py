@@ -68,11 +68,16 @@ def run_both(it, orc, ch, tr, exec=None, fields=True):
 def ragged_case(max_steps=1_000_000, stop_tol=1e-12):
     ch = W.chamber(70, 13, 37, 3e-4, 37 * 3e-4, 25.0, dy=2.5e-4, uniform_n0=2e9,
                    max_steps=max_steps, stop_tol=stop_tol)
-    tr = W.tracks([[30.0, 7e-4, 1.0e-2, 1.5e-3, 0.0, 0.0, 0.0],
+    tr = W.tracks([[10.0, 7e-4, 1.0e-2, 1.5e-3, 0.0, 0.0, 0.0],
                    [12.0, 9e-4, 4.0e-3, 2.0e-3, 0.35, 2.0, 0.0],
-                   [50.0, 5e-4, 1.9e-2, 0.5e-3, 0.5, 5.0, 3.1e-7],
+                   [5.0, 8e-4, 1.9e-2, 0.5e-3, 0.5, 5.0, 3.1e-7],
                    [5.0, 6e-4, 2.0e-2, 3.0e-3, 0.0, 0.0, 9.0e-7]])
     return ch, tr
+
+
+def test_ragged_case_is_physical(orc):
+    r = orc.solve(*ragged_case(), with_fields=False)
+    assert r["flags"] == 0 and r["max_beta_n"] < 1.0
 
 
 def test_single_track_full_run(gpu, orc):
@@ -101,9 +106,9 @@ def test_ragged_grid_full_run(gpu, orc):
 
 
 def test_pulsed_beam_reduced_grid(gpu, orc):
-    ch, tr = W.pulsed_beam(ntracks=60)
-    ch.update(nx=96, ny=80, nz=60, gap=60 * 5e-4, voltage=60.0)
-    lx, ly = 96 * 5e-4, 80 * 5e-4
+    ch, tr = W.pulsed_beam(ntracks=30)
+    ch.update(nx=72, ny=60, nz=40, gap=40 * 5e-4, voltage=40.0)
+    lx, ly = 72 * 5e-4, 60 * 5e-4
     tr[:, 2] = tr[:, 2] % lx
     tr[:, 3] = tr[:, 3] % ly
     run_both(gpu, orc, ch, tr, fields=False)
@@ -128,11 +133,24 @@ def test_empty_run(gpu, orc):
 
 def test_track_after_max_steps_is_not_deposited(gpu, orc):
     ch, tr = W.single_track(max_steps=30)
-    dt = orc.dt(ch)
+    dt = orc.dt(ch, tr)
     tr = np.concatenate([tr, tr])
     tr[1, 6] = 50 * dt
     g, o = run_both(gpu, orc, ch, tr, fields=False)
     assert g["flags"] & gpu.IT_FLAG_MAX_STEPS
+
+
+def test_reaction_blow_up_stops_at_same_step(gpu, orc):
+    # a dense track with alpha dt n >> 1: the explicit sink overshoots, the
+    # densities diverge and both sides stop at the first non-finite tally
+    ch, tr = ragged_case()
+    ch["reaction_limit"] = 0.0
+    tr[2, 0], tr[2, 1] = 50.0, 5e-4
+    g = gpu.it_solve(ch, tr)
+    o = orc.solve(ch, tr, with_fields=False)
+    assert o["flags"] & gpu.IT_FLAG_NONFINITE and o["flags"] & gpu.IT_FLAG_REACTION
+    assert g["flags"] == o["flags"] and g["steps"] == o["steps"]
+    assert g["max_beta_n"] == pytest.approx(o["max_beta_n"], rel=1e-9)
 
 
 def test_advance_from_given_fields(gpu, orc):

@@ -65,6 +65,48 @@ def test_dt_no_transport_is_an_error(orc):
         orc.dt(ch)
 
 
+def test_reaction_limit_single_track(orc):
+    """With the recombination bound active and binding, alpha dt n_ref = rho
+    where n_ref is the track's peak density N0/(pi b^2) (eq. Gaussian)."""
+    ch, tr = W.single_track(reaction_limit=0.5)
+    peak = 100.0 * 1e7 / 34.0 / (math.pi * 1e-6)
+    assert orc.reference_density(ch, tr) == pytest.approx(peak, rel=1e-14)
+    assert orc.dt(ch, tr) == pytest.approx(0.5 / (1.6e-6 * peak), rel=1e-14)
+    assert orc.dt(ch, tr) < orc.dt(ch)
+    ch["reaction_limit"] = 0.0
+    assert orc.dt(ch, tr) == orc.dt(ch)
+
+
+def test_reference_density_sums_simultaneous_tracks(orc):
+    ch = W.chamber(64, 64, 10, 2e-4, 10 * 2e-4, 20.0, uniform_n0=3e9)
+    b1, b2, d = 8e-4, 6e-4, 5e-4
+    tr = W.tracks([[40.0, b1, 6e-3, 6e-3, 0.0, 0.0, 0.0],
+                   [30.0, b2, 6e-3 + d, 6e-3, 0.0, 0.0, 0.0],
+                   [90.0, 6e-4, 6e-3, 6e-3, 0.0, 0.0, 1e-6]])     # later: does not add
+    p1 = 40e7 / 34 / (math.pi * b1 * b1)
+    p2 = 30e7 / 34 / (math.pi * b2 * b2)
+    p3 = 90e7 / 34 / (math.pi * 6e-4 ** 2)
+    at1 = p1 + p2 * math.exp(-d * d / (b2 * b2))
+    at2 = p2 + p1 * math.exp(-d * d / (b1 * b1))
+    expect = 3e9 + max(at1, at2, p3)
+    assert orc.reference_density(ch, tr) == pytest.approx(expect, rel=1e-13)
+
+
+def test_reaction_limit_keeps_dense_pulse_finite(orc):
+    """A dense track core (alpha dt n ~ 4 at the transport bound) diverges
+    with the transport bound alone and stays finite and conservative with
+    the recombination bound."""
+    ch = W.chamber(24, 24, 30, 5e-4, 30 * 5e-4, 30.0, reaction_limit=0.0)
+    tr = W.tracks([[60.0, 5e-4, 6e-3, 6e-3, 0.0, 0.0, 0.0]])
+    r = orc.solve(ch, tr, with_fields=False)
+    assert r["flags"] & 2 and r["max_beta_n"] > 1.0
+    ch["reaction_limit"] = 0.5
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    assert r["flags"] == 0 and r["max_beta_n"] <= 0.5 * (1 + 1e-12)
+    _check_conservation(r)
+    assert 0.0 < r["f"] < 1.0
+
+
 def _checkerboard(ch, amp=1.0):
     shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
     k, j, i = np.indices(shape)
@@ -288,7 +330,7 @@ def test_deposit_profile_is_gaussian_in_perpendicular_distance(orc):
 
 def test_track_deposited_at_floor_of_time_over_dt(orc):
     ch, _ = W.single_track(max_steps=6, stop_tol=0.0)
-    dt = orc.dt(ch)
+    dt = orc.dt(ch, W.tracks([[1.0, 1e-3, 32 * 2e-4, 32 * 2e-4, 0.0, 0.0, 0.0]]))
     tr = W.tracks([[1.0, 1e-3, 32 * 2e-4, 32 * 2e-4, 0.0, 0.0, 2.999 * dt],
                    [1.0, 1e-3, 32 * 2e-4, 32 * 2e-4, 0.0, 0.0, 40 * dt]])   # beyond max_steps
     r = orc.solve(ch, tr, with_trace=True, with_fields=False)

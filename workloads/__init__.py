@@ -23,6 +23,9 @@ A chamber is a plain ``dict`` whose keys mirror the C struct ``it_chamber``:
     max_steps   hard limit on the number of time steps
     uniform_n0  uniform ion-pair density added to both species at t=0 [cm^-3]
     space_charge  1 adds the space-charge screening term, 0 leaves it out
+    reaction_limit  rho >= 0: the time step is also bounded by
+                alpha dt n_ref <= rho, n_ref the reference peak density of
+                the inputs (0 leaves only the transport bound)
 
 A track list is a float64 array of shape (n, 7) with columns
 ``[let_keV_um, b_cm, x_cm, y_cm, theta, phi, t_s]``: linear energy transfer,
@@ -66,8 +69,12 @@ def ion_pairs_per_mGy(W_eV: float = 34.0) -> float:
     return energy_j_per_cm3 / (W_eV * Q_E)
 
 
+REACTION_LIMIT = 0.5
+
+
 def chamber(nx, ny, nz, dx, gap, voltage, dy=None, *, dt_safety=1.0, stop_tol=1e-12,
-            max_steps=1_000_000, uniform_n0=0.0, space_charge=0, **consts) -> dict:
+            max_steps=1_000_000, uniform_n0=0.0, space_charge=0, reaction_limit=REACTION_LIMIT,
+            **consts) -> dict:
     c = dict(AIR)
     c.update(consts)
     return dict(nx=int(nx), ny=int(ny), nz=int(nz), dx=float(dx),
@@ -77,7 +84,7 @@ def chamber(nx, ny, nz, dx, gap, voltage, dy=None, *, dt_safety=1.0, stop_tol=1e
                 alpha=float(c["alpha"]), W_eV=float(c["W_eV"]),
                 dt_safety=float(dt_safety), stop_tol=float(stop_tol),
                 max_steps=int(max_steps), uniform_n0=float(uniform_n0),
-                space_charge=int(space_charge))
+                space_charge=int(space_charge), reaction_limit=float(reaction_limit))
 
 
 def tracks(rows) -> np.ndarray:
