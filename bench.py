@@ -37,9 +37,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel", choices=("auto", "plain", "blocked"), default="auto")
     ap.add_argument("--T", type=int, default=0, help="steps per pass of the blocked kernel")
+    ap.add_argument("--tile-y", type=int, default=0, help="tile rows (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="launches in the stepping-kernel timing")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only run the stepping kernel on the workload grid (for counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy two fields of the workload grid with a plain device copy "
+                         "(reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -103,12 +109,30 @@ def main():
 
     torch.cuda.set_device(0)
     ch, tr = W.pulsed_beam()
+    if a.copy_calibration:
+        shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
+        src = torch.ones((2,) + shape, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+        return
     kernel = {"auto": it.IT_KERNEL_AUTO, "plain": it.IT_KERNEL_PLAIN, "blocked": it.IT_KERNEL_BLOCKED}[a.kernel]
-    ex = {"kernel": kernel, "steps_per_pass": a.T}
+    ex = {"kernel": kernel, "steps_per_pass": a.T, "tile_y": a.tile_y}
     ws = it.workspace(ch, tr.shape[0])
     nint = (ch["nz"] - 1) * ch["nx"] * ch["ny"]
     stream = torch.cuda.current_stream()
 
+    if a.kernel_only:
+        dt = it.it_dt(ch, tr)
+        pos0, neg0 = W.perturbed_field((ch["nz"] + 1, ch["ny"], ch["nx"]), seed=5, scale=1e9)
+        gp, gn = torch.tensor(pos0, device="cuda"), torch.tensor(neg0, device="cuda")
+        chk = dict(ch, max_steps=max(a.kernel_steps, 1))
+        it.it_advance(chk, dt, gp, gn, a.kernel_steps, exec=ex, ws=it.workspace(chk, 0))
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only_steps": a.kernel_steps, "nodes": nint}))
+        return
     for _ in range(a.warmup):
         it.it_solve(ch, tr, exec=ex, ws=ws)
     torch.cuda.synchronize()

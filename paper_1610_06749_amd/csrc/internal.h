@@ -90,7 +90,9 @@ struct DepositParams {
 struct BlockedParams;
 
 // Launchers (stream-ordered, no synchronisation).
-hipError_t launch_step_plain(const StepParams& p, hipStream_t s);
+int plain_tile_rows(int tile_y);
+hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
+hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
 
 }  // namespace it

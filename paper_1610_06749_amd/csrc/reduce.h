@@ -45,7 +45,9 @@ __device__ inline void block_sum_store(double (&acc)[N], double* out, double* ld
 
 // Called by all threads of every block after the block wrote its partials.
 // Returns true in exactly one block: the last to arrive.  That block then
-// sees every other block's partials.
+// sees every other block's partials.  (Used only by the rare deposit launch:
+// the device-scope fence of every block costs an L2 write-back, so the
+// stepping kernels hand their partials to a separate reduction launch.)
 template <int NT>
 __device__ inline bool arrive_last(unsigned* counter) {
   __shared__ int last;
@@ -61,38 +63,46 @@ __device__ inline bool arrive_last(unsigned* counter) {
   return last != 0;
 }
 
-// In the last block: totals[q] = sum over blocks b (in order) of
-// partials[b * stride + q], q < n.  Each thread owns a fixed subset of the
-// blocks; the per-thread sums are then combined by a fixed tree.
+// In the last block: totals[q] = sum over blocks b of partials[b * stride + q]
+// for q < n.  Component q is reduced by wave q % W; its lanes take the blocks
+// in a fixed stride (8 independent loads in flight each) and the wave sums
+// them by a fixed butterfly, so all components finish in a few round trips.
 template <int NT>
 __device__ inline void reduce_partials(const double* partials, int nblocks, int stride, int n,
-                                       double* totals, double* lds /*[NT/64]*/) {
+                                       double* totals) {
+  constexpr int W = NT / kWave;
+  constexpr int kBatch = 8;
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   const int wave = tid / kWave, lane = tid % kWave;
-  for (int q = 0; q < n; ++q) {
+  for (int q = wave; q < n; q += W) {
     double s = 0.0;
-    for (int b = tid; b < nblocks; b += NT) s += partials[(size_t)b * stride + q];
-    s = wave_sum(s);
-    if (lane == 0) lds[wave] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double t = lds[0];
-      for (int w = 1; w < NT / kWave; ++w) t += lds[w];
-      totals[q] = t;
+    for (int b0 = lane; b0 < nblocks; b0 += kWave * kBatch) {
+      double v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int b = b0 + u * kWave;
+        v[u] = b < nblocks ? partials[(size_t)b * stride + q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) s += v[u];
     }
-    __syncthreads();
+    s = wave_sum(s);
+    if (lane == 0) totals[q] = s;
   }
+  __syncthreads();
 }
 
 // Thread 0 of the last block: turns the reduced sums of T consecutive steps
 // (tot[s * kAcc + q]) into trace records and updates the run state and the
-// stop decision.
-__device__ inline void finalize_steps(RunState* st, double* trace, const double* tot, int T,
+// stop decision.  Works on a register copy of the state (one bulk load and
+// one bulk store) to keep the serial tail of the launch short.
+__device__ inline void finalize_steps(RunState* gst, double* trace, const double* tot, int T,
                                       int64_t step0, const Coef& cp, const Coef& cn, double dV,
                                       double stop_tol, int64_t min_stop_step) {
-  st->passes += 1;
+  RunState st = *gst;
+  st.passes += 1;
   for (int s = 0; s < T; ++s) {
-    if (st->done) break;
+    if (st.done) break;
     const int64_t l = step0 + s;
     const double* a = tot + s * kAcc;
     double rec[IT_TRACE_COLS];
@@ -105,27 +115,28 @@ __device__ inline void finalize_steps(RunState* st, double* trace, const double*
     rec[6] = a[6] * dV;
     rec[7] = a[7] * dV;
     rec[8] = a[8] * dV;
-    rec[9] = st->released_pending;
-    st->released_pending = 0.0;
+    rec[9] = st.released_pending;
+    st.released_pending = 0.0;
     bool finite = true;
     for (int q = 0; q < IT_TRACE_COLS; ++q) {
       trace[l * IT_TRACE_COLS + q] = rec[q];
       finite = finite && isfinite(rec[q]);
     }
-    for (int q = 0; q < 5; ++q) st->sums[q] += rec[q];
-    for (int q = 0; q < 4; ++q) st->last[q] = rec[5 + q];
-    st->steps = l + 1;
+    for (int q = 0; q < 5; ++q) st.sums[q] += rec[q];
+    for (int q = 0; q < 4; ++q) st.last[q] = rec[5 + q];
+    st.steps = l + 1;
     if (!finite) {
-      st->flags |= IT_FLAG_NONFINITE;
-      st->done = 1;
+      st.flags |= IT_FLAG_NONFINITE;
+      st.done = 1;
       break;
     }
-    const double lim = stop_tol * st->released;
+    const double lim = stop_tol * st.released;
     if (l >= min_stop_step && rec[7] <= lim && rec[8] <= lim) {
-      st->done = 1;
+      st.done = 1;
       break;
     }
   }
+  *gst = st;
 }
 
 // Tile decode shared by the kernels: tiles are numbered row-of-tiles major

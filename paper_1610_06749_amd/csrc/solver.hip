@@ -14,7 +14,7 @@ namespace it {
 hipError_t launch_step_blocked(const StepParams& p, int T, int tile_y, hipStream_t s);
 int blocked_supported(int T, int tile_y);
 void blocked_tiling(int nx, int ny, int nz, int T, int tile_y, int* grid, int* per_xcd,
-                    int* tiles_x, int* tiles_y, int* ntiles);
+                    int* tiles_x, int* tiles_y, int* ntiles, int* zc, int* zchunks);
 
 namespace {
 
@@ -135,23 +135,38 @@ struct Tiling {
   int tiles_x, tiles_y, zchunks, zc, ntiles, per_xcd, grid;
 };
 
-// 64 x 4 column tiles; z split into chunks so that the grid has about
-// `target` blocks (enough waves to cover HBM latency on 256 CUs).
-Tiling plain_tiling(int nx, int ny, int nz, int target = 2048) {
+// Tiling of the interior: tile_x x tile_y columns by chunks of z planes.
+// The stepping kernel marches 32 planes per block (down to 4 on small grids,
+// to keep several hundred blocks); the deposit kernel aims at ~2048 blocks.
+Tiling make_tiling(int nx, int ny, int nz, int tile_y, int zc) {
   Tiling t;
   const int nint = nz - 1;
   t.tiles_x = (nx + 63) / 64;
-  t.tiles_y = (ny + 3) / 4;
+  t.tiles_y = (ny + tile_y - 1) / tile_y;
   const long cols = (long)t.tiles_x * t.tiles_y;
-  long want = std::max<long>(1, (target + cols - 1) / cols);
-  want = std::min<long>(want, nint);
-  t.zc = (int)((nint + want - 1) / want);
-  t.zc = std::max(t.zc, std::min(4, nint));
+  t.zc = std::max(1, std::min(zc, nint));
   t.zchunks = (nint + t.zc - 1) / t.zc;
   t.ntiles = (int)(cols * t.zchunks);
   t.per_xcd = (t.ntiles + 7) / 8;
   t.grid = 8 * t.per_xcd;
   return t;
+}
+
+Tiling step_tiling(int nx, int ny, int nz, int rows) {
+  const long cols = (long)((nx + 63) / 64) * ((ny + rows - 1) / rows);
+  int zc = 32;
+  while (zc > 4 && cols * ((nz - 1 + zc - 1) / zc) < 512) zc /= 2;
+  return make_tiling(nx, ny, nz, rows, zc);
+}
+
+Tiling deposit_tiling(int nx, int ny, int nz) {
+  const long cols = (long)((nx + 63) / 64) * ((ny + 3) / 4);
+  const int nint = nz - 1;
+  long want = std::max<long>(1, (2048 + cols - 1) / cols);
+  want = std::min<long>(want, nint);
+  int zc = (int)((nint + want - 1) / want);
+  zc = std::max(zc, std::min(4, nint));
+  return make_tiling(nx, ny, nz, 4, zc);
 }
 
 struct Layout {
@@ -166,12 +181,13 @@ struct Layout {
 };
 
 size_t max_grid(const it_chamber* ch) {
-  size_t g = (size_t)plain_tiling(ch->nx, ch->ny, ch->nz).grid;
+  size_t g = std::max((size_t)step_tiling(ch->nx, ch->ny, ch->nz, 8).grid,
+                      (size_t)deposit_tiling(ch->nx, ch->ny, ch->nz).grid);
   for (int T = 2; T <= kMaxT; ++T) {
     if (!blocked_supported(T, 0)) continue;
-    int grid, per, tx, ty, nt;
-    blocked_tiling(ch->nx, ch->ny, ch->nz, T, 0, &grid, &per, &tx, &ty, &nt);
-    g = std::max(g, (size_t)grid);
+    int grid, per, tx, ty, nt, zc, zch;
+    blocked_tiling(ch->nx, ch->ny, ch->nz, T, 0, &grid, &per, &tx, &ty, &nt, &zc, &zch);
+    g = std::max(g, (size_t)grid * T);
   }
   return g;
 }
@@ -184,8 +200,9 @@ Layout make_layout(const it_chamber* ch, int64_t ntracks) {
     L.off_field[f] = off;
     off = align_up(off + L.field_elems * sizeof(double));
   }
-  // blocked kernels use up to 16 tile-row variants; reserve for the largest grid
-  L.partial_doubles = max_grid(ch) * 4 * (size_t)kAcc * kMaxT;
+  // per-block partial tallies: kAcc slots per fused step (max_grid counts
+  // blocks times fused steps)
+  L.partial_doubles = max_grid(ch) * (size_t)kAcc;
   L.off_partials = off;
   off = align_up(off + L.partial_doubles * sizeof(double));
   L.off_counter = off;
@@ -273,7 +290,8 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const Coef cp = species_coef(ch, dt, 0), cn = species_coef(ch, dt, 1);
   const double dz = ch->gap / ch->nz;
   const double dV = ch->dx * ch->dy * dz;
-  const Tiling tp = plain_tiling(ch->nx, ch->ny, ch->nz);
+  const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, plain_tile_rows(tile_y));
+  const Tiling td = deposit_tiling(ch->nx, ch->ny, ch->nz);
 
   RunState* slots = pinned_slots();
   if (!slots) return IT_EHIP;
@@ -297,12 +315,12 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   dp.nx = ch->nx;
   dp.ny = ch->ny;
   dp.nz = ch->nz;
-  dp.tiles_x = tp.tiles_x;
-  dp.tiles_y = tp.tiles_y;
-  dp.zchunks = tp.zchunks;
-  dp.zc = tp.zc;
-  dp.ntiles = tp.ntiles;
-  dp.per_xcd = tp.per_xcd;
+  dp.tiles_x = td.tiles_x;
+  dp.tiles_y = td.tiles_y;
+  dp.zchunks = td.zchunks;
+  dp.zc = td.zc;
+  dp.ntiles = td.ntiles;
+  dp.per_xcd = td.per_xcd;
   dp.dx = ch->dx;
   dp.dy = ch->dy;
   dp.dz = dz;
@@ -361,7 +379,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       sp.zc = tp.zc;
       sp.ntiles = tp.ntiles;
       sp.per_xcd = tp.per_xcd;
-      e = launch_step_plain(sp, stream);
+      e = launch_step_plain(sp, tile_y, stream);
     } else {
       e = launch_step_blocked(sp, (int)todo, tile_y, stream);
     }

@@ -15,6 +15,12 @@ pytestmark = pytest.mark.gpu
 
 RTOL = 1e-9
 
+# every stepping kernel the library offers: the one-step kernel with both
+# tile shapes, and the temporally blocked kernel at each supported depth
+EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16)] + \
+    [dict(kernel=2, steps_per_pass=T) for T in (2, 3, 4, 5)]
+EXEC_IDS = ["plain8", "plain16", "blocked2", "blocked3", "blocked4", "blocked5"]
+
 
 @pytest.fixture(scope="module")
 def gpu():
@@ -35,7 +41,7 @@ def compare_results(g, o, rtol=RTOL):
     for k in ("n_recombined", "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode",
               "n_inflight_pos", "n_inflight_neg"):
         assert abs(g[k] - o[k]) <= rtol * N, (k, g[k], o[k])
-    assert g["dt"] == o["dt"]
+    assert g["dt"] == pytest.approx(o["dt"], rel=1e-14)
 
 
 def compare_trace(gt, ot, N, rtol=RTOL):
@@ -80,49 +86,66 @@ def test_ragged_case_is_physical(orc):
     assert r["flags"] == 0 and r["max_beta_n"] < 1.0
 
 
-def test_single_track_full_run(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_single_track_full_run(gpu, orc, ex):
     ch, tr = W.single_track()
-    g, o = run_both(gpu, orc, ch, tr, fields=False)
+    g, o = run_both(gpu, orc, ch, tr, exec=ex, fields=False)
     assert o["flags"] == 0 and 0.1 < o["f"] < 0.3
 
 
-def test_single_track_fields_fixed_steps(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_single_track_fields_fixed_steps(gpu, orc, ex):
     ch, tr = W.single_track(max_steps=45, stop_tol=0.0)
-    g, o = run_both(gpu, orc, ch, tr)
+    g, o = run_both(gpu, orc, ch, tr, exec=ex)
     compare_fields(g["pos"], o["pos"])
     compare_fields(g["neg"], o["neg"])
 
 
-def test_ragged_grid_fields(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_ragged_grid_fields(gpu, orc, ex):
     ch, tr = ragged_case(max_steps=70, stop_tol=0.0)
-    g, o = run_both(gpu, orc, ch, tr)
+    g, o = run_both(gpu, orc, ch, tr, exec=ex)
     compare_fields(g["pos"], o["pos"])
     compare_fields(g["neg"], o["neg"])
 
 
-def test_ragged_grid_full_run(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_ragged_grid_full_run(gpu, orc, ex):
     ch, tr = ragged_case()
-    run_both(gpu, orc, ch, tr, fields=False)
+    run_both(gpu, orc, ch, tr, exec=ex, fields=False)
 
 
-def test_pulsed_beam_reduced_grid(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_tall_ragged_grid_fields(gpu, orc, ex):
+    # 150 x 37 columns: three 64-wide tiles (last one 22 wide), 3-5 row tiles
+    ch = W.chamber(150, 37, 41, 2.5e-4, 41 * 2.5e-4, 30.0, uniform_n0=1e9, max_steps=35, stop_tol=0.0)
+    tr = W.tracks([[8.0, 8e-4, 1.2e-2, 4.0e-3, 0.2, 1.0, 0.0], [4.0, 6e-4, 3.0e-2, 8.5e-3, 0.0, 0.0, 0.0]])
+    g, o = run_both(gpu, orc, ch, tr, exec=ex)
+    compare_fields(g["pos"], o["pos"])
+    compare_fields(g["neg"], o["neg"])
+
+
+@pytest.mark.parametrize("ex", [None, dict(kernel=2, steps_per_pass=4)], ids=["default", "blocked4"])
+def test_pulsed_beam_reduced_grid(gpu, orc, ex):
     ch, tr = W.pulsed_beam(ntracks=30)
     ch.update(nx=72, ny=60, nz=40, gap=40 * 5e-4, voltage=40.0)
     lx, ly = 72 * 5e-4, 60 * 5e-4
     tr[:, 2] = tr[:, 2] % lx
     tr[:, 3] = tr[:, 3] % ly
-    run_both(gpu, orc, ch, tr, fields=False)
+    run_both(gpu, orc, ch, tr, exec=ex, fields=False)
 
 
-def test_one_dimensional_uniform(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_one_dimensional_uniform(gpu, orc, ex):
     ch = W.chamber(1, 1, 120, 1e-3, 0.05, 100.0, uniform_n0=5e9)
-    run_both(gpu, orc, ch, W.no_tracks())
+    run_both(gpu, orc, ch, W.no_tracks(), exec=ex)
 
 
-def test_single_interior_plane(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_single_interior_plane(gpu, orc, ex):
     ch = W.chamber(6, 6, 2, 2e-4, 4e-4, 5.0)
     tr = W.tracks([[10.0, 4e-4, 6e-4, 6e-4, 0.0, 0.0, 0.0]])
-    run_both(gpu, orc, ch, tr)
+    run_both(gpu, orc, ch, tr, exec=ex)
 
 
 def test_empty_run(gpu, orc):
@@ -153,7 +176,8 @@ def test_reaction_blow_up_stops_at_same_step(gpu, orc):
     assert g["max_beta_n"] == pytest.approx(o["max_beta_n"], rel=1e-9)
 
 
-def test_advance_from_given_fields(gpu, orc):
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_advance_from_given_fields(gpu, orc, ex):
     import torch
     ch = W.chamber(67, 9, 21, 3e-4, 21 * 2e-4, 20.0, dy=4e-4)
     dt = orc.dt(ch)
@@ -161,7 +185,7 @@ def test_advance_from_given_fields(gpu, orc):
     op, on, otr = orc.advance(ch, dt, p0, n0, 9, with_trace=True)
     gp = torch.tensor(p0, device="cuda")
     gn = torch.tensor(n0, device="cuda")
-    gtr = gpu.it_advance(ch, dt, gp, gn, 9, trace=True)
+    gtr = gpu.it_advance(ch, dt, gp, gn, 9, exec=ex, trace=True)
     compare_fields(gp, op)
     compare_fields(gn, on)
     compare_trace(gtr[:, :9], otr[:, :9], np.abs(p0).sum() * ch["dx"] * ch["dy"] * ch["gap"] / 21)
@@ -182,3 +206,4 @@ def test_error_paths(gpu):
     with pytest.raises(gpu.ItError) as e:
         gpu.it_solve(ch, tr, ws=small)
     assert e.value.code == gpu.IT_EWORKSPACE
+
