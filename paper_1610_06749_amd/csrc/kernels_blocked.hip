@@ -81,14 +81,22 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
   }
 
   const int Klo = za - T, Khi = zb + T - 1;
+  // level 0 of plane K is loaded one iteration ahead (planes outside
+  // 0..nz read as zero; their address is clamped to plane 0)
+  auto load0 = [&](int K, double& a, double& b) {
+    const bool in = K >= 0 && K <= p.nz;
+    const size_t off = (size_t)(in ? K : 0) * plane + col;
+    a = pin[off];
+    b = nin[off];
+    if (!in) a = b = 0.0;
+  };
+  double np0, nn0;
+  load0(Klo, np0, nn0);
   for (int K = tc.valid ? Klo : Khi + 1; K <= Khi; ++K) {
     double vp[T + 1], vn[T + 1];
-    if (K >= 0 && K <= p.nz) {
-      vp[0] = pin[(size_t)K * plane + col];
-      vn[0] = nin[(size_t)K * plane + col];
-    } else {
-      vp[0] = vn[0] = 0.0;
-    }
+    vp[0] = np0;
+    vn[0] = nn0;
+    load0(K + 1, np0, nn0);
 #pragma unroll
     for (int t = 1; t <= T; ++t) {
       const int q = K - t;  // plane of level t in this iteration (uniform)
@@ -137,7 +145,7 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
         __builtin_nontemporal_store(vn[T], &nout[c]);
       }
     }
-    __syncthreads();  // every level read its LDS plane of the previous iteration
+    lds_barrier();  // every level read its LDS plane of the previous iteration
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       lp[t][ty][lane] = vp[t];
@@ -147,7 +155,7 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
       mn[t] = cnv[t];
       cnv[t] = vn[t];
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // block reduction of T records of kAcc slots (layout [level][slot])
