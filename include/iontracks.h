@@ -173,6 +173,28 @@ int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* e
                double* d_pos, double* d_neg, void* d_workspace, size_t ws_bytes,
                void* stream, double* h_trace);
 
+/* Device workspace bytes it_solve_batch needs for ninst chambers (host
+ * array ch[ninst]) with track_offsets[ninst+1] as in it_solve_batch.
+ * exec may be NULL (only tile_y matters).  Host only. */
+int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, int32_t ninst,
+                            const it_exec* exec, size_t* bytes);
+
+/* Batched sweep: runs ninst independent chambers (uneven grids, voltages,
+ * tracks, doses) to completion together, each exactly as it_solve would
+ * (same time step rule, deposition, stepping, tallies and stop criterion).
+ * ch: host [ninst]; tracks of instance q are tracks[track_offsets[q] ..
+ * track_offsets[q+1]) (host); every track must be due at step 0 (one pulse
+ * per instance, IT_ENOTSUP otherwise).  Each pass is one launch over the
+ * tiles of all running instances plus one reduction launch; the library
+ * captures exec->check_every passes (default 32, rounded up to even) in a
+ * HIP graph and replays it on `stream` until every instance has stopped.
+ * out: host [ninst].  No per-step traces or fields are kept.
+ * Synchronises `stream`.  Errors: IT_EINVAL, IT_ENODT, IT_ENOTSUP,
+ * IT_EWORKSPACE, IT_EHIP. */
+int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_track* tracks,
+                   int32_t ninst, const it_exec* exec, void* d_workspace, size_t ws_bytes, void* stream,
+                   it_result* out);
+
 /* Message for a status code (static string). */
 const char* it_strerror(int code);
 

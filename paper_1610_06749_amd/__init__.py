@@ -8,5 +8,6 @@ no GPU is present.
 from .binding import (IT_EHIP, IT_EINVAL, IT_ENODT, IT_ENOTSUP, IT_EWORKSPACE, IT_FLAG_EMPTY,  # noqa: F401
                       IT_FLAG_MAX_STEPS, IT_FLAG_NONFINITE, IT_FLAG_REACTION, IT_KERNEL_AUTO,
                       IT_KERNEL_BLOCKED, IT_KERNEL_PLAIN, IT_OK, IT_TRACE_COLS, TRACE_KEYS, ItError,
-                      it_advance, it_dt, it_solve, it_strerror, it_validate, it_workspace_size, lib,
+                      it_advance, it_dt, it_solve, it_solve_batch, it_strerror, it_validate, it_workspace_size,
+                      it_workspace_size_batch, lib,
                       workspace)

@@ -75,7 +75,12 @@ def lib():
                                ctypes.POINTER(it_result)]
         L.it_advance.argtypes = [chp, ctypes.c_double, i64, ctypes.POINTER(it_exec), vp, vp, vp,
                                  ctypes.c_size_t, vp, vp]
-        for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance"):
+        L.it_workspace_size_batch.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(it_exec),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+        L.it_solve_batch.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(it_exec), vp, ctypes.c_size_t,
+                                     vp, vp]
+        for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance",
+                     "it_workspace_size_batch", "it_solve_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -201,3 +206,36 @@ def it_advance(ch, dt, pos, neg, nsteps, exec=None, ws=None, stream=None, trace=
                           htrace.ctypes.data if trace else None)
     _check(rc, "it_advance")
     return htrace
+
+
+def _batch_args(chambers, track_lists):
+    n = len(chambers)
+    chs = (it_chamber * n)(*[_chamber(c) for c in chambers])
+    lists = [np.asarray(t, dtype=np.float64).reshape(-1, 7) for t in track_lists]
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([t.shape[0] for t in lists])
+    tracks = np.ascontiguousarray(np.concatenate(lists) if offsets[-1] else np.zeros((1, 7)))
+    return n, chs, offsets, tracks
+
+
+def it_workspace_size_batch(chambers, track_lists, exec=None) -> int:
+    n, chs, offsets, _ = _batch_args(chambers, track_lists)
+    out = ctypes.c_size_t()
+    _check(lib().it_workspace_size_batch(ctypes.addressof(chs), offsets.ctypes.data, n, _exec(exec),
+                                         ctypes.byref(out)), "it_workspace_size_batch")
+    return out.value
+
+
+def it_solve_batch(chambers, track_lists, exec=None, ws=None, stream=None) -> list:
+    """Runs a sweep of chambers (list of dicts, list of (n_q, 7) track arrays)
+    to completion in batched launches; returns one result dict per chamber."""
+    import torch
+    n, chs, offsets, tracks = _batch_args(chambers, track_lists)
+    if ws is None:
+        ws = torch.empty(it_workspace_size_batch(chambers, track_lists, exec), dtype=torch.uint8,
+                         device="cuda")
+    res = (it_result * n)()
+    rc = lib().it_solve_batch(ctypes.addressof(chs), offsets.ctypes.data, tracks.ctypes.data, n, _exec(exec),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream), ctypes.addressof(res))
+    _check(rc, "it_solve_batch")
+    return [_result(r) for r in res]

@@ -39,7 +39,7 @@ struct RunState {
   int32_t done;             // 1 once the stop criterion (or a non-finite tally) is met
   int32_t flags;            // IT_FLAG_NONFINITE
   int32_t passes;           // stepping launches that ran (not skipped)
-  int32_t pad;
+  int32_t by_limit;         // 1 if a batched run stopped the instance at max_steps
 };
 
 // Track prepared on the host for the deposit kernel.
@@ -87,12 +87,20 @@ struct DepositParams {
   RunState* state;
 };
 
-struct BlockedParams;
+// One chamber of a batched sweep (device table entry).
+struct BatchInstance {
+  StepParams sp[2];  // [parity]: field pair 0 -> pair 1, and pair 1 -> pair 0
+  int tile_begin;    // first entry of this instance in the batch's tile list
+  int ntiles;
+  int64_t max_steps;
+};
 
 // Launchers (stream-ordered, no synchronisation).
 int plain_tile_rows(int tile_y);
 hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int parity,
+                             hipStream_t s);
 
 }  // namespace it

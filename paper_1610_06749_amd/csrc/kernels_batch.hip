@@ -1,0 +1,80 @@
+// Batched stepping: one launch advances every still-running chamber of a
+// sweep by one time step.  The tiles of all instances form one list (each
+// instance keeps its own grid, tiling, coefficients, fields and run state in
+// a device table); a block finds its instance by binary search, skips it
+// once the instance has stopped, and otherwise runs the same tile step as
+// the single-chamber kernel.  A second launch (one block per instance)
+// reduces each instance's partial tallies and takes its stop decision.
+// Kernel boundaries order the passes; the host captures a chain of passes
+// in a HIP graph and replays it until every instance has stopped.
+#include "stencil_plain.h"
+
+namespace it {
+
+namespace {
+
+__device__ inline int find_instance(const BatchInstance* inst, int ninst, int L) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {  // last instance with tile_begin <= L
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].tile_begin <= L) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int SY>
+__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
+                       int parity) {
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per_xcd + (b >> 3);  // XCD-aware order over the whole list
+  if (L >= total_tiles) return;
+  const int q = find_instance(inst, ninst, L);
+  const StepParams& p = inst[q].sp[parity];
+  if (p.state->done) return;
+  const int l = L - inst[q].tile_begin;
+  TileCoord t;
+  t.valid = true;
+  t.tx = l % p.tiles_x;
+  const int rest = l / p.tiles_x;
+  t.zc = rest % p.zchunks;
+  t.ty = rest / p.zchunks;
+  plain_tile_step<SY>(p, t, p.partials + (size_t)l * kAcc);
+}
+
+__global__ __launch_bounds__(1024) void batch_reduce_kernel(const BatchInstance* __restrict__ inst,
+                                                            int parity) {
+  const BatchInstance& bi = inst[blockIdx.x];
+  const StepParams& p = bi.sp[parity];
+  if (p.state->done) return;
+  __shared__ double totals[kAcc];
+  reduce_partials<1024>(p.partials, bi.ntiles, kAcc, kAcc, totals);
+  if (threadIdx.x == 0) {
+    const int64_t step = p.state->steps;
+    finalize_steps(p.state, p.trace, totals, 1, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
+    if (!p.state->done && p.state->steps >= bi.max_steps) {
+      p.state->done = 1;
+      p.state->by_limit = 1;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int parity,
+                             hipStream_t s) {
+  const BatchInstance* inst = (const BatchInstance*)table;
+  const int per_xcd = (total_tiles + 7) / 8;
+  if (plain_tile_rows(tile_y) == 16)
+    hipLaunchKernelGGL(batch_step_kernel<16>, dim3(8 * per_xcd), dim3(kTX, 16), 0, s, inst, ninst,
+                       total_tiles, per_xcd, parity);
+  else
+    hipLaunchKernelGGL(batch_step_kernel<8>, dim3(8 * per_xcd), dim3(kTX, 8), 0, s, inst, ninst,
+                       total_tiles, per_xcd, parity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(ninst), dim3(1024), 0, s, inst, parity);
+  return hipGetLastError();
+}
+
+}  // namespace it

@@ -103,8 +103,9 @@ __device__ inline void reduce_partials(const double* partials, int nblocks, int 
 
 // Thread 0 of the last block: turns the reduced sums of T consecutive steps
 // (tot[s * kAcc + q]) into trace records and updates the run state and the
-// stop decision.  Works on a register copy of the state (one bulk load and
-// one bulk store) to keep the serial tail of the launch short.
+// stop decision (trace may be NULL: no per-step records kept).  Works on a
+// register copy of the state (one bulk load and one bulk store) to keep the
+// serial tail of the launch short.
 __device__ inline void finalize_steps(RunState* gst, double* trace, const double* tot, int T,
                                       int64_t step0, const Coef& cp, const Coef& cn, double dV,
                                       double stop_tol, int64_t min_stop_step) {
@@ -128,7 +129,7 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
     st.released_pending = 0.0;
     bool finite = true;
     for (int q = 0; q < IT_TRACE_COLS; ++q) {
-      trace[l * IT_TRACE_COLS + q] = rec[q];
+      if (trace) trace[l * IT_TRACE_COLS + q] = rec[q];
       finite = finite && isfinite(rec[q]);
     }
     for (int q = 0; q < 5; ++q) st.sums[q] += rec[q];

@@ -256,6 +256,22 @@ RunState* pinned_slots() {
     if ((expr) != hipSuccess) return IT_EHIP;       \
   } while (0)
 
+// Per-track constants of the deposit kernel: axis direction, peak density
+// N0/(pi b^2) with N0 = LET/W (keV/um -> eV/cm), 1/b^2 and the (8b)^2 cut.
+DepTrack prepare_track(const it_chamber* ch, const it_track& t) {
+  DepTrack d;
+  d.x0 = t.x_cm;
+  d.y0 = t.y_cm;
+  d.ux = std::sin(t.theta) * std::cos(t.phi);
+  d.uy = std::sin(t.theta) * std::sin(t.phi);
+  d.uz = std::cos(t.theta);
+  const double N0 = t.let_keV_um * 1.0e7 / ch->W_eV;
+  d.peak = N0 / (M_PI * t.b_cm * t.b_cm);
+  d.inv_b2 = 1.0 / (t.b_cm * t.b_cm);
+  d.cut2 = 64.0 * t.b_cm * t.b_cm;
+  return d;
+}
+
 struct Event {
   int64_t step;
   int64_t par_begin, par_count, tilt_begin, tilt_count;
@@ -417,6 +433,124 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   return rc;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched sweeps
+// ---------------------------------------------------------------------------
+
+struct InstLayout {
+  size_t off_field[4], field_elems;
+  size_t off_partials, off_counter, off_tracks;
+  int ntiles;       // stepping tiles (plain kernel)
+};
+
+struct BatchLayout {
+  std::vector<InstLayout> inst;
+  size_t off_states;  // RunState[ninst], contiguous for one read-back
+  size_t off_table;   // BatchInstance[ninst]
+  size_t total;
+};
+
+BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows) {
+  BatchLayout B;
+  size_t off = 0;
+  B.inst.resize(ninst);
+  for (int q = 0; q < ninst; ++q) {
+    InstLayout& L = B.inst[q];
+    const it_chamber& c = ch[q];
+    L.field_elems = (size_t)(c.nz + 1) * c.ny * c.nx;
+    for (int f = 0; f < 4; ++f) {
+      L.off_field[f] = off;
+      off = align_up(off + L.field_elems * sizeof(double));
+    }
+    const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows);
+    const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
+    L.ntiles = ts.ntiles;
+    L.off_partials = off;
+    off = align_up(off + std::max((size_t)ts.ntiles * kAcc, (size_t)td.grid * 2) * sizeof(double));
+    L.off_counter = off;
+    off = align_up(off + 64 * sizeof(unsigned));
+    L.off_tracks = off;
+    off = align_up(off + (size_t)std::max<int64_t>(toff[q + 1] - toff[q], 1) * sizeof(DepTrack));
+  }
+  B.off_states = off;
+  off = align_up(off + (size_t)ninst * sizeof(RunState));
+  B.off_table = off;
+  off = align_up(off + (size_t)ninst * sizeof(BatchInstance));
+  B.total = off;
+  return B;
+}
+
+int check_batch(const it_chamber* ch, const int64_t* toff, const it_track* tracks, int ninst) {
+  if (!ch || !toff || ninst < 1 || ninst > 65536) return IT_EINVAL;
+  if (toff[0] != 0) return IT_EINVAL;
+  for (int q = 0; q < ninst; ++q) {
+    if (toff[q + 1] < toff[q]) return IT_EINVAL;
+    const int64_t n = toff[q + 1] - toff[q];
+    int rc = check_chamber(&ch[q]);
+    if (rc) return rc;
+    rc = check_tracks(n ? tracks + toff[q] : nullptr, n);
+    if (rc) return rc;
+  }
+  return IT_OK;
+}
+
+// Pinned host buffer for reading all instance states back (grown on demand,
+// kept per host thread for the life of the process).
+RunState* pinned_states(int n) {
+  thread_local RunState* buf = nullptr;
+  thread_local int cap = 0;
+  if (n > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, (size_t)n * 2 * sizeof(RunState), hipHostMallocDefault) != hipSuccess) return nullptr;
+    buf = (RunState*)p;
+    cap = n;
+  }
+  return buf;
+}
+
+hipStream_t capture_stream() {
+  thread_local hipStream_t s[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!s[dev] && hipStreamCreateWithFlags(&s[dev], hipStreamNonBlocking) != hipSuccess) return nullptr;
+  return s[dev];
+}
+
+void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, it_result* out) {
+  std::memset(out, 0, sizeof(*out));
+  const double collected = fin.sums[1] + fin.sums[2] + fin.sums[3] + fin.sums[4];
+  int flags = fin.flags;
+  // stopped by the step limit (the criterion may also fire on the last step)
+  if (fin.steps >= max_steps && (!fin.done || fin.by_limit)) flags |= IT_FLAG_MAX_STEPS;
+  if (fin.max_beta_n > 1.0) flags |= IT_FLAG_REACTION;
+  if (fin.released > 0.0) {
+    out->f = collected / (2.0 * fin.released);
+    out->f_R = 1.0 - fin.sums[0] / fin.released;
+  } else {
+    out->f = 1.0;
+    out->f_R = 1.0;
+    flags |= IT_FLAG_EMPTY;
+  }
+  out->ks = 1.0 / out->f;
+  out->n_released = fin.released;
+  out->n_recombined = fin.sums[0];
+  out->n_inflight_pos = fin.last[0];
+  out->n_inflight_neg = fin.last[1];
+  out->col_pos_anode = fin.sums[1];
+  out->col_pos_cathode = fin.sums[2];
+  out->col_neg_anode = fin.sums[3];
+  out->col_neg_cathode = fin.sums[4];
+  out->dt = dt;
+  out->max_beta_n = fin.max_beta_n;
+  out->steps = fin.steps;
+  out->flags = flags;
+  out->passes = issued;
+}
+
 }  // namespace
 }  // namespace it
 
@@ -490,19 +624,7 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     return a.step != b.step ? a.step < b.step : a.tilted < b.tilted;
   });
   std::vector<DepTrack> dev(items.size());
-  for (size_t q = 0; q < items.size(); ++q) {
-    const it_track& t = tracks[items[q].index];
-    DepTrack& d = dev[q];
-    d.x0 = t.x_cm;
-    d.y0 = t.y_cm;
-    d.ux = std::sin(t.theta) * std::cos(t.phi);
-    d.uy = std::sin(t.theta) * std::sin(t.phi);
-    d.uz = std::cos(t.theta);
-    const double N0 = t.let_keV_um * 1.0e7 / ch->W_eV;  // keV/um -> eV/cm, / W
-    d.peak = N0 / (M_PI * t.b_cm * t.b_cm);
-    d.inv_b2 = 1.0 / (t.b_cm * t.b_cm);
-    d.cut2 = 64.0 * t.b_cm * t.b_cm;
-  }
+  for (size_t q = 0; q < items.size(); ++q) dev[q] = prepare_track(ch, tracks[items[q].index]);
   std::vector<Event> events;
   int64_t last_dep = -1;
   for (size_t q = 0; q < items.size();) {
@@ -546,33 +668,7 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
                 ch->stop_tol, stream, &fin, &issued);
   if (rc) return rc;
 
-  std::memset(out, 0, sizeof(*out));
-  const double collected = fin.sums[1] + fin.sums[2] + fin.sums[3] + fin.sums[4];
-  int flags = fin.flags;
-  if (!fin.done && fin.steps >= ch->max_steps) flags |= IT_FLAG_MAX_STEPS;
-  if (fin.max_beta_n > 1.0) flags |= IT_FLAG_REACTION;
-  if (fin.released > 0.0) {
-    out->f = collected / (2.0 * fin.released);
-    out->f_R = 1.0 - fin.sums[0] / fin.released;
-  } else {
-    out->f = 1.0;
-    out->f_R = 1.0;
-    flags |= IT_FLAG_EMPTY;
-  }
-  out->ks = 1.0 / out->f;
-  out->n_released = fin.released;
-  out->n_recombined = fin.sums[0];
-  out->n_inflight_pos = fin.last[0];
-  out->n_inflight_neg = fin.last[1];
-  out->col_pos_anode = fin.sums[1];
-  out->col_pos_cathode = fin.sums[2];
-  out->col_neg_anode = fin.sums[3];
-  out->col_neg_cathode = fin.sums[4];
-  out->dt = dt;
-  out->max_beta_n = fin.max_beta_n;
-  out->steps = fin.steps;
-  out->flags = flags;
-  out->passes = issued;
+  fill_result(fin, dt, ch->max_steps, issued, out);
 
   if (h_trace && fin.steps > 0)
     HIP_TRY(hipMemcpy(h_trace, ws + L.off_trace, (size_t)fin.steps * IT_TRACE_COLS * sizeof(double),
@@ -585,6 +681,196 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     HIP_TRY(hipMemcpyAsync(d_neg_out, ws + L.off_field[2 * last + 1], L.field_elems * sizeof(double),
                            hipMemcpyDeviceToDevice, stream));
   if (d_pos_out || d_neg_out) HIP_TRY(hipStreamSynchronize(stream));
+  return IT_OK;
+}
+
+int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, int32_t ninst,
+                            const it_exec* exec, size_t* bytes) {
+  if (!bytes || !ch || !track_offsets || ninst < 1 || ninst > 65536) return IT_EINVAL;
+  for (int q = 0; q < ninst; ++q) {
+    const int rc = check_chamber(&ch[q]);
+    if (rc) return rc;
+    if (track_offsets[q + 1] < track_offsets[q]) return IT_EINVAL;
+  }
+  const int rows = plain_tile_rows(exec ? exec->tile_y : 0);
+  *bytes = make_batch_layout(ch, track_offsets, ninst, rows).total;
+  return IT_OK;
+}
+
+int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_track* tracks,
+                   int32_t ninst, const it_exec* exec, void* d_workspace, size_t ws_bytes, void* stream_,
+                   it_result* out) {
+  if (!out) return IT_EINVAL;
+  int rc = check_batch(ch, track_offsets, tracks, ninst);
+  if (rc) return rc;
+  const int tile_y = exec ? exec->tile_y : 0;
+  const int rows = plain_tile_rows(tile_y);
+  int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
+  passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
+  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows);
+  if (!d_workspace || ws_bytes < B.total) return IT_EWORKSPACE;
+  hipStream_t stream = (hipStream_t)stream_;
+  char* ws = (char*)d_workspace;
+  RunState* states = (RunState*)(ws + B.off_states);
+
+  std::vector<double> dts(ninst);
+  std::vector<BatchInstance> table(ninst);
+  int total_tiles = 0;
+  int64_t max_steps_all = 0;
+  for (int q = 0; q < ninst; ++q) {
+    const it_chamber* c = &ch[q];
+    const int64_t n = track_offsets[q + 1] - track_offsets[q];
+    const it_track* tq = n ? tracks + track_offsets[q] : nullptr;
+    rc = compute_dt(c, tq, n, &dts[q]);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n; ++k)
+      if (deposit_step(tq[k].t_s, dts[q]) != 0) return IT_ENOTSUP;  // one pulse per instance
+    const InstLayout& L = B.inst[q];
+    for (int f = 0; f < 4; ++f)
+      HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, L.field_elems * sizeof(double), stream));
+    HIP_TRY(hipMemsetAsync(ws + L.off_counter, 0, 64 * sizeof(unsigned), stream));
+    std::vector<DepTrack> dev(n);
+    for (int64_t k = 0; k < n; ++k) {  // parallel tracks first, as the kernel expects
+      dev[k] = prepare_track(c, tq[k]);
+    }
+    std::stable_partition(dev.begin(), dev.end(), [](const DepTrack& d) { return d.ux == 0.0 && d.uy == 0.0; });
+    int64_t npar = 0;
+    while (npar < n && dev[npar].ux == 0.0 && dev[npar].uy == 0.0) ++npar;
+    if (n) HIP_TRY(hipMemcpyAsync(ws + L.off_tracks, dev.data(), n * sizeof(DepTrack), hipMemcpyHostToDevice, stream));
+
+    const Coef cp = species_coef(c, dts[q], 0), cn = species_coef(c, dts[q], 1);
+    const double dz = c->gap / c->nz, dV = c->dx * c->dy * dz;
+    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows);
+    const Tiling td = deposit_tiling(c->nx, c->ny, c->nz);
+    BatchInstance& bi = table[q];
+    for (int par = 0; par < 2; ++par) {
+      StepParams& sp = bi.sp[par];
+      std::memset(&sp, 0, sizeof(sp));
+      sp.pin = (double*)(ws + L.off_field[2 * par]);
+      sp.nin = (double*)(ws + L.off_field[2 * par + 1]);
+      sp.pout = (double*)(ws + L.off_field[2 * (1 - par)]);
+      sp.nout = (double*)(ws + L.off_field[2 * (1 - par) + 1]);
+      sp.nx = c->nx;
+      sp.ny = c->ny;
+      sp.nz = c->nz;
+      sp.tiles_x = ts.tiles_x;
+      sp.tiles_y = ts.tiles_y;
+      sp.zchunks = ts.zchunks;
+      sp.zc = ts.zc;
+      sp.ntiles = ts.ntiles;
+      sp.per_xcd = ts.per_xcd;
+      sp.cp = cp;
+      sp.cn = cn;
+      sp.beta = c->alpha * dts[q];
+      sp.dV = dV;
+      sp.stop_tol = c->stop_tol;
+      sp.step0 = 0;
+      sp.min_stop_step = 0;
+      sp.partials = (double*)(ws + L.off_partials);
+      sp.counter = (unsigned*)(ws + L.off_counter);
+      sp.state = states + q;
+      sp.trace = nullptr;
+    }
+    bi.tile_begin = total_tiles;
+    bi.ntiles = ts.ntiles;
+    bi.max_steps = c->max_steps;
+    total_tiles += ts.ntiles;
+    max_steps_all = std::max(max_steps_all, c->max_steps);
+    // the pulse: uniform pre-ionisation and the tracks, deposited before step 0
+    RunState init;
+    std::memset(&init, 0, sizeof(init));
+    HIP_TRY(hipMemcpyAsync(states + q, &init, sizeof(init), hipMemcpyHostToDevice, stream));
+    if (n || c->uniform_n0 > 0.0) {
+      DepositParams dp;
+      dp.pos = (double*)(ws + L.off_field[0]);
+      dp.neg = (double*)(ws + L.off_field[1]);
+      dp.nx = c->nx;
+      dp.ny = c->ny;
+      dp.nz = c->nz;
+      dp.tiles_x = td.tiles_x;
+      dp.tiles_y = td.tiles_y;
+      dp.zchunks = td.zchunks;
+      dp.zc = td.zc;
+      dp.ntiles = td.ntiles;
+      dp.per_xcd = td.per_xcd;
+      dp.dx = c->dx;
+      dp.dy = c->dy;
+      dp.dz = dz;
+      dp.half_gap = 0.5 * c->gap;
+      dp.Lx = c->nx * c->dx;
+      dp.Ly = c->ny * c->dy;
+      dp.uniform = c->uniform_n0;
+      dp.par = (const DepTrack*)(ws + L.off_tracks);
+      dp.npar = (int)npar;
+      dp.tilt = (const DepTrack*)(ws + L.off_tracks) + npar;
+      dp.ntilt = (int)(n - npar);
+      dp.dV = dV;
+      dp.beta = c->alpha * dts[q];
+      dp.partials = (double*)(ws + L.off_partials);
+      dp.counter = (unsigned*)(ws + L.off_counter);
+      dp.state = states + q;
+      HIP_TRY(launch_deposit(dp, stream));
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(ws + B.off_table, table.data(), (size_t)ninst * sizeof(BatchInstance),
+                         hipMemcpyHostToDevice, stream));
+
+  // Capture `passes_per_graph` passes (step launch + reduction launch each)
+  // on a private stream and replay the graph on the caller's stream.
+  hipStream_t cs = capture_stream();
+  if (!cs) return IT_EHIP;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec_graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  hipError_t ce = hipSuccess;
+  for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
+    ce = launch_batch_pass(ws + B.off_table, ninst, total_tiles, tile_y, k & 1, cs);
+  const hipError_t ee = hipStreamEndCapture(cs, &graph);
+  if (ce != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return IT_EHIP;
+  }
+  if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return IT_EHIP;
+  }
+  RunState* host = pinned_states(ninst);
+  if (!host) {
+    (void)hipGraphExecDestroy(exec_graph);
+    (void)hipGraphDestroy(graph);
+    return IT_EHIP;
+  }
+  // Replays until every instance has stopped; two replays in flight so the
+  // GPU never idles on the read-back.
+  const int64_t max_replays = (max_steps_all + passes_per_graph - 1) / passes_per_graph;
+  hipEvent_t evs[2];
+  HIP_TRY(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
+  int issued = 0;
+  rc = IT_OK;
+  for (int64_t r = 0; r < max_replays; ++r) {
+    if (hipGraphLaunch(exec_graph, stream) != hipSuccess) { rc = IT_EHIP; break; }
+    issued += passes_per_graph;
+    RunState* slot = host + (r & 1) * ninst;
+    if (hipMemcpyAsync(slot, states, (size_t)ninst * sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipEventRecord(evs[r & 1], stream) != hipSuccess) { rc = IT_EHIP; break; }
+    if (r >= 1) {
+      RunState* prev = host + ((r - 1) & 1) * ninst;
+      if (hipEventSynchronize(evs[(r - 1) & 1]) != hipSuccess) { rc = IT_EHIP; break; }
+      bool all = true;
+      for (int q = 0; q < ninst && all; ++q) all = prev[q].done != 0;
+      if (all) break;
+    }
+  }
+  if (rc == IT_OK && (hipMemcpyAsync(host, states, (size_t)ninst * sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                      hipStreamSynchronize(stream) != hipSuccess))
+    rc = IT_EHIP;
+  (void)hipEventDestroy(evs[0]);
+  (void)hipEventDestroy(evs[1]);
+  (void)hipGraphExecDestroy(exec_graph);
+  (void)hipGraphDestroy(graph);
+  if (rc) return rc;
+  for (int q = 0; q < ninst; ++q) fill_result(host[q], dts[q], ch[q].max_steps, issued, &out[q]);
   return IT_OK;
 }
 

@@ -1,0 +1,81 @@
+"""Batched sweeps on the GPU against the CPU oracle, instance by instance."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_06749_amd as it
+    it.lib()
+    return it
+
+
+def small_sweep(n=7, seed=5):
+    """Uneven small chambers: transverse 20..90 nodes (ragged tiles), 6..40
+    gap intervals, voltages 10..80 V, doses and 1..12 tracks of modest LET,
+    one with no tracks and one with no pre-ionisation."""
+    rng = np.random.default_rng(seed)
+    chs, trs = [], []
+    for q in range(n):
+        nx = int(rng.integers(20, 91))
+        ny = int(rng.integers(12, 70))
+        nz = int(rng.integers(6, 41))
+        ch = W.chamber(nx, ny, nz, 3e-4, nz * 3e-4, float(rng.uniform(10, 80)),
+                       uniform_n0=0.0 if q == 1 else float(rng.uniform(1e8, 5e9)))
+        k = 0 if q == 2 else int(rng.integers(1, 13))
+        lx, ly = nx * 3e-4, ny * 3e-4
+        tr = np.stack([rng.uniform(1, 20, k), rng.uniform(6e-4, 1.5e-3, k), rng.uniform(0, lx, k),
+                       rng.uniform(0, ly, k), np.zeros(k), np.zeros(k), np.zeros(k)], axis=1)
+        chs.append(ch)
+        trs.append(W.tracks(tr))
+    return chs, trs
+
+
+@pytest.mark.parametrize("tile_y", [8, 16])
+def test_batch_matches_oracle_per_instance(gpu, orc, tile_y):
+    chs, trs = small_sweep()
+    res = gpu.it_solve_batch(chs, trs, exec=dict(tile_y=tile_y, check_every=6))
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        assert g["steps"] == o["steps"] and g["flags"] == o["flags"]
+        assert g["f"] == pytest.approx(o["f"], rel=1e-9)
+        N = max(o["n_released"], 1.0)
+        for k in ("n_released", "n_recombined", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
+                  "col_neg_cathode"):
+            assert abs(g[k] - o[k]) <= 1e-9 * N, k
+
+
+def test_batch_equals_single_runs(gpu):
+    chs, trs = small_sweep(n=4, seed=9)
+    res = gpu.it_solve_batch(chs, trs)
+    for ch, tr, g in zip(chs, trs, res):
+        s = gpu.it_solve(ch, tr, exec=dict(kernel=1))
+        assert g["steps"] == s["steps"]
+        assert g["f"] == pytest.approx(s["f"], rel=1e-12)
+
+
+def test_batch_step_limit(gpu, orc):
+    chs, trs = small_sweep(n=3, seed=2)
+    for ch in chs:
+        ch["max_steps"] = 25
+    res = gpu.it_solve_batch(chs, trs, exec=dict(check_every=8))
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        assert g["steps"] == o["steps"] == 25 and g["flags"] == o["flags"]
+        assert g["f"] == pytest.approx(o["f"], rel=1e-9)
+
+
+def test_batch_rejects_later_tracks(gpu):
+    chs, trs = small_sweep(n=2, seed=3)
+    trs[1] = trs[1].copy()
+    trs[1][0, 6] = 1e-3
+    with pytest.raises(gpu.ItError) as e:
+        gpu.it_solve_batch(chs, trs)
+    assert e.value.code == gpu.IT_ENOTSUP
