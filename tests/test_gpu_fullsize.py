@@ -1,0 +1,122 @@
+"""GPU path at the workloads' full sizes, in the launch configuration the
+benchmark times, against stored oracle results.
+
+The stored values come from tests/golden/make_golden.py, which runs only the
+CPU oracle (the full-size oracle runs take minutes to an hour, too long for a
+test).  Fields are compared on sampled nodes (uniform samples plus the 256
+largest nodes of each species) and through their 2-norms; tallies step by
+step.  Properties that hold at any size (conservation) are checked on the
+GPU's own traces.
+"""
+import glob
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RTOL = 1e-9
+EXECS = [None, dict(kernel=1, tile_y=16), dict(kernel=2, steps_per_pass=4)]
+EXEC_IDS = ["default", "plain16", "blocked4"]
+
+
+def load(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated (run tests/golden/make_golden.py {name})")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_06749_amd as it
+    it.lib()
+    return it
+
+
+def check_result(g, o):
+    assert g["steps"] == o["steps"] and g["flags"] == o["flags"]
+    assert g["f"] == pytest.approx(o["f"], rel=RTOL)
+    N = max(o["n_released"], 1.0)
+    for k in ("n_released", "n_recombined", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
+              "col_neg_cathode", "n_inflight_pos", "n_inflight_neg"):
+        assert abs(g[k] - o[k]) <= RTOL * N, (k, g[k], o[k])
+
+
+def check_fields(g, summary):
+    idx = np.asarray(summary["index"])
+    for sp in ("pos", "neg"):
+        f = g[sp].cpu().numpy()
+        vals = f[idx[:, 0], idx[:, 1], idx[:, 2]]
+        ref = np.asarray(summary[sp])
+        assert np.max(np.abs(vals - ref)) <= RTOL * summary[f"{sp}_max"]
+        assert np.linalg.norm(f) == pytest.approx(summary[f"{sp}_norm2"], rel=RTOL)
+        assert np.abs(f).max() == pytest.approx(summary[f"{sp}_max"], rel=RTOL)
+
+
+def check_conservation(trace, N, tol=1e-12):
+    tr = np.asarray(trace)
+    for a, c, S in ((1, 2, 5), (3, 4, 6)):
+        prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, 9]
+        err = prev - tr[:, a] - tr[:, c] - tr[:, 0] - tr[:, S]
+        assert np.max(np.abs(err)) <= tol * N
+
+
+def test_single_track_against_stored(gpu):
+    gd = load("single_track")
+    g = gpu.it_solve(gd["chamber"], np.asarray(gd["tracks"]), trace=True)
+    check_result(g, gd["result"])
+    assert np.max(np.abs(g["trace"] - np.asarray(gd["trace"]))) <= RTOL * gd["result"]["n_released"]
+
+
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_pulsed_beam_fields_at_full_size(gpu, ex):
+    """256 x 256 x 200 nodes, 400 tracks, the first 40 steps."""
+    gd = load("pulsed_fields")
+    g = gpu.it_solve(gd["chamber"], np.asarray(gd["tracks"]), exec=ex, trace=True, fields=True)
+    check_result(g, gd["result"])
+    N = gd["result"]["n_released"]
+    assert np.max(np.abs(g["trace"] - np.asarray(gd["trace"]))) <= RTOL * N
+    check_fields(g, gd["fields"])
+
+
+@pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
+def test_continuous_beam_window_at_full_size(gpu, ex):
+    """512 x 512 x 256 nodes, tilted tracks, three deposit events in 64 steps."""
+    gd = load("continuous_window")
+    g = gpu.it_solve(gd["chamber"], np.asarray(gd["tracks"]), exec=ex, trace=True, fields=True)
+    check_result(g, gd["result"])
+    N = gd["result"]["n_released"]
+    assert np.max(np.abs(g["trace"] - np.asarray(gd["trace"]))) <= RTOL * N
+    check_fields(g, gd["fields"])
+    check_conservation(g["trace"], N)
+
+
+def test_pulsed_beam_full_run(gpu):
+    """The benchmark's workload run to full collection."""
+    gd = load("pulsed_full")
+    g = gpu.it_solve(gd["chamber"], np.asarray(gd["tracks"]), trace=True)
+    check_result(g, gd["result"])
+    check_conservation(g["trace"], gd["result"]["n_released"])
+
+
+def test_batched_sweep_against_stored(gpu):
+    """The 96-chamber sweep in one batched run; every instance whose oracle
+    result is stored is compared."""
+    files = sorted(glob.glob(os.path.join(GOLDEN, "sweep_*.json")))
+    if not files:
+        pytest.skip("no sweep instances generated")
+    chs, trs = W.batched_sweep()
+    res = gpu.it_solve_batch(chs, trs)
+    for fn in files:
+        gd = json.load(open(fn))
+        check_result(res[gd["instance"]], gd["result"])
