@@ -195,6 +195,61 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
                    int32_t ninst, const it_exec* exec, void* d_workspace, size_t ws_bytes, void* stream,
                    it_result* out);
 
+/* ------------------------------------------------------------------------
+ * Surrogate for ln k_s: an ensemble of `members` MLPs 6 -> 128 -> 128 -> 128
+ * -> 1 (SiLU), IT_MLP_PARAMS parameters each, laid out per member as
+ * W1[128][6], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
+ * w4[128], b4.  Inputs per query: the six physical quantities (LET [keV/um],
+ * b [cm], V [V], gap [cm], dose per pulse [mGy], pulse rate [Hz]), all > 0,
+ * standardised on the device as z = (log x - mu)/sigma.  FP32 master
+ * weights; the forward pass uses their BF16 copies (round to nearest even),
+ * MFMA with FP32 accumulation for the 128x128 layers, and BF16 hidden
+ * activations.  The network predicts (ln k_s - t_mu)/t_sigma.
+ * ------------------------------------------------------------------------ */
+#define IT_MLP_PARAMS 34049
+
+/* Device bytes of a model buffer for `members` members (1..64).  Host only. */
+int it_mlp_model_bytes(int32_t members, size_t* bytes);
+
+/* Initialises a model buffer: h_params host [members][IT_MLP_PARAMS] FP32
+ * initial weights; h_norm host [26] = mu[6], sigma[6], box_lo[6], box_hi[6]
+ * (standardised bounds of the training inputs), t_mu, t_sigma.  Clears the
+ * optimiser state.  Synchronises `stream`.  Errors: IT_EINVAL, IT_EHIP. */
+int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, void* stream);
+
+/* Device workspace bytes of it_mlp_train / it_mlp_grad for n samples. */
+int it_mlp_train_ws_bytes(int32_t members, int64_t n, size_t* bytes);
+
+/* Full-batch gradient of the mean squared error of every member on
+ * (d_X [n][6], d_t [n] = ln k_s targets), device buffers; d_grad device
+ * [members][IT_MLP_PARAMS]; h_loss NULL or host [members] (loss before any
+ * update).  The BF16 casts pass gradients straight through.  Synchronises.
+ * Errors: IT_EINVAL, IT_EWORKSPACE, IT_EHIP. */
+int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n,
+                float* d_grad, float* h_loss, void* d_workspace, size_t ws_bytes, void* stream);
+
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, rate lr)
+ * of every member on (d_X, d_t); the BF16 copies follow each update.
+ * h_loss: NULL or host [ceil(steps/log_every)][members], the loss before
+ * every log_every-th step.  Synchronises `stream`.
+ * Errors: IT_EINVAL, IT_EWORKSPACE, IT_EHIP. */
+int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int32_t steps,
+                 float lr, int32_t log_every, float* h_loss, void* d_workspace, size_t ws_bytes, void* stream);
+
+/* Device workspace bytes of it_mlp_query for nq queries. */
+int it_mlp_query_ws_bytes(int64_t nq, size_t* bytes);
+
+/* Ensemble query (device buffers): d_mean[nq] = mean over members of ln k_s,
+ * d_spread[nq] = max - min over members, d_fallback[nq] = 1 where a
+ * standardised input lies outside the training box or the spread exceeds
+ * spread_tol (such queries must be answered by the solver).  d_fallback_idx:
+ * NULL or device [nq]; receives the flagged query indices in increasing
+ * order.  h_nfallback: NULL or host, receives their count (synchronises
+ * `stream` when given).  Errors: IT_EINVAL, IT_EWORKSPACE, IT_EHIP. */
+int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
+                 float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
+                 void* d_workspace, size_t ws_bytes, void* stream);
+
 /* Message for a status code (static string). */
 const char* it_strerror(int code);
 

@@ -79,8 +79,19 @@ def lib():
                                               ctypes.POINTER(ctypes.c_size_t)]
         L.it_solve_batch.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(it_exec), vp, ctypes.c_size_t,
                                      vp, vp]
+        szp = ctypes.POINTER(ctypes.c_size_t)
+        L.it_mlp_model_bytes.argtypes = [ctypes.c_int32, szp]
+        L.it_mlp_init.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.it_mlp_train_ws_bytes.argtypes = [ctypes.c_int32, i64, szp]
+        L.it_mlp_grad.argtypes = [vp, ctypes.c_int32, vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        L.it_mlp_train.argtypes = [vp, ctypes.c_int32, vp, vp, i64, ctypes.c_int32, ctypes.c_float,
+                                   ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
+        L.it_mlp_query_ws_bytes.argtypes = [i64, szp]
+        L.it_mlp_query.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance",
-                     "it_workspace_size_batch", "it_solve_batch"):
+                     "it_workspace_size_batch", "it_solve_batch", "it_mlp_model_bytes", "it_mlp_init",
+                     "it_mlp_train_ws_bytes", "it_mlp_grad", "it_mlp_train", "it_mlp_query_ws_bytes",
+                     "it_mlp_query"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -239,3 +250,79 @@ def it_solve_batch(chambers, track_lists, exec=None, ws=None, stream=None) -> li
                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream), ctypes.addressof(res))
     _check(rc, "it_solve_batch")
     return [_result(r) for r in res]
+
+
+# --------------------------------------------------------------------------
+# Surrogate network
+# --------------------------------------------------------------------------
+IT_MLP_PARAMS = 34049
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def it_mlp_model_bytes(members: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().it_mlp_model_bytes(int(members), ctypes.byref(out)), "it_mlp_model_bytes")
+    return out.value
+
+
+def it_mlp_init(model, members, params, norm, stream=None):
+    """model: device uint8 tensor of it_mlp_model_bytes; params float32
+    [members, IT_MLP_PARAMS]; norm float32 [26]."""
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(members, IT_MLP_PARAMS)
+    nm = np.ascontiguousarray(norm, dtype=np.float32).reshape(26)
+    _check(lib().it_mlp_init(_dptr(model), int(members), p.ctypes.data, nm.ctypes.data, _stream(stream)),
+           "it_mlp_init")
+
+
+def _train_ws(members, n, device):
+    import torch
+    out = ctypes.c_size_t()
+    _check(lib().it_mlp_train_ws_bytes(int(members), int(n), ctypes.byref(out)), "it_mlp_train_ws_bytes")
+    return torch.empty(out.value, dtype=torch.uint8, device=device)
+
+
+def it_mlp_grad(model, members, X, t, stream=None):
+    """Gradient [members, IT_MLP_PARAMS] (device tensor) and losses (numpy)."""
+    import torch
+    n = X.shape[0]
+    ws = _train_ws(members, n, X.device)
+    grad = torch.empty((members, IT_MLP_PARAMS), dtype=torch.float32, device=X.device)
+    loss = np.zeros(members, dtype=np.float32)
+    _check(lib().it_mlp_grad(_dptr(model), int(members), _dptr(X), _dptr(t), int(n), _dptr(grad),
+                             loss.ctypes.data, _dptr(ws), ws.numel(), _stream(stream)), "it_mlp_grad")
+    return grad, loss
+
+
+def it_mlp_train(model, members, X, t, steps, lr, log_every=0, stream=None):
+    n = X.shape[0]
+    ws = _train_ws(members, n, X.device)
+    nlog = (steps + log_every - 1) // log_every if log_every > 0 else 0
+    loss = np.zeros((max(nlog, 1), members), dtype=np.float32)
+    _check(lib().it_mlp_train(_dptr(model), int(members), _dptr(X), _dptr(t), int(n), int(steps), float(lr),
+                              int(log_every), loss.ctypes.data if nlog else None, _dptr(ws), ws.numel(),
+                              _stream(stream)), "it_mlp_train")
+    return loss[:nlog]
+
+
+def it_mlp_query(model, X, spread_tol, stream=None, ws=None, out=None):
+    """Returns (mean, spread, fallback mask, fallback indices, count) with
+    the first four as device tensors."""
+    import torch
+    nq = X.shape[0]
+    dev = X.device
+    if ws is None:
+        need = ctypes.c_size_t()
+        _check(lib().it_mlp_query_ws_bytes(int(nq), ctypes.byref(need)), "it_mlp_query_ws_bytes")
+        ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    if out is None:
+        out = (torch.empty(nq, dtype=torch.float32, device=dev), torch.empty(nq, dtype=torch.float32, device=dev),
+               torch.empty(nq, dtype=torch.uint8, device=dev), torch.empty(nq, dtype=torch.int64, device=dev))
+    mean, spread, fb, idx = out
+    cnt = ctypes.c_int64()
+    _check(lib().it_mlp_query(_dptr(model), _dptr(X), int(nq), float(spread_tol), _dptr(mean), _dptr(spread),
+                              _dptr(fb), _dptr(idx), ctypes.byref(cnt), _dptr(ws), ws.numel(), _stream(stream)),
+           "it_mlp_query")
+    return mean, spread, fb, idx[: cnt.value], cnt.value

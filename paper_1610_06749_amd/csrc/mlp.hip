@@ -1,0 +1,578 @@
+// Surrogate network for ln k_s: an ensemble of MLPs 6 -> 128 -> 128 -> 128 -> 1
+// (SiLU), trained and queried with the kernels below.
+//
+// Numerics: FP32 master weights; BF16 copies (round to nearest even) feed
+// the forward pass.  The two 128x128 layers run on MFMA
+// (v_mfma_f32_16x16x16_bf16: BF16 inputs, FP32 accumulation); the 6-wide
+// input layer and the 128-wide output dot run in FP32.  Hidden activations
+// are rounded to BF16 before entering the next layer.  Inputs are the six
+// physical quantities (LET, b, V, gap, dose per pulse, pulse rate),
+// standardised as (log x - mu) / sigma; the output is the standardised
+// ln k_s.  Training: full-batch mean squared error, backward in FP32 with
+// the BF16 casts passed straight through, Adam.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace it {
+namespace {
+
+constexpr int kH = 128, kIn = 6;
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+              ob3 = oW3 + kH * kH, ow4 = ob3 + kH, ob4 = ow4 + kH, kP = ob4 + 1;  // 34049
+constexpr int kPpad = (kP + 63) / 64 * 64;
+constexpr int kTileS = 64;       // samples per forward block (4 waves x 16)
+constexpr int kActStride = kH + 4;  // padded BF16 row (avoids LDS bank conflicts)
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+struct Header {
+  int32_t members, step;
+  float mu[kIn], sigma[kIn], lo[kIn], hi[kIn];
+  float t_mu, t_sigma;
+};
+
+struct Model {  // device pointers carved from the model buffer
+  Header* hdr;
+  float* master;      // [M][kP]
+  float* m;           // [M][kP]
+  float* v;           // [M][kP]
+  unsigned short* w;  // [M][kPpad] BF16
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t model_bytes(int M) {
+  return align256(sizeof(Header)) + 3 * align256((size_t)M * kP * sizeof(float)) +
+         align256((size_t)M * kPpad * sizeof(unsigned short));
+}
+
+Model carve_model(void* base, int M) {
+  char* p = (char*)base;
+  Model md;
+  md.hdr = (Header*)p;
+  p += align256(sizeof(Header));
+  md.master = (float*)p;
+  p += align256((size_t)M * kP * sizeof(float));
+  md.m = (float*)p;
+  p += align256((size_t)M * kP * sizeof(float));
+  md.v = (float*)p;
+  p += align256((size_t)M * kP * sizeof(float));
+  md.w = (unsigned short*)p;
+  return md;
+}
+
+struct TrainWs {  // per member: [M][n][...]
+  float *z, *a1, *a2, *a3, *h1, *h2, *h3, *y, *dy, *d1, *d2, *d3, *grad, *loss;
+};
+
+size_t train_ws_bytes(int M, int64_t n) {
+  const size_t nh = (size_t)M * n * kH * sizeof(float);
+  return 9 * align256(nh) + align256((size_t)M * n * kIn * 4) + 2 * align256((size_t)M * n * 4) +
+         align256((size_t)M * kP * 4) + align256((size_t)M * 4);
+}
+
+TrainWs carve_train(void* base, int M, int64_t n) {
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    float* r = (float*)p;
+    p += align256(bytes);
+    return r;
+  };
+  const size_t nh = (size_t)M * n * kH * sizeof(float);
+  TrainWs w;
+  w.a1 = take(nh);
+  w.a2 = take(nh);
+  w.a3 = take(nh);
+  w.h1 = take(nh);
+  w.h2 = take(nh);
+  w.h3 = take(nh);
+  w.d1 = take(nh);
+  w.d2 = take(nh);
+  w.d3 = take(nh);
+  w.z = take((size_t)M * n * kIn * 4);
+  w.y = take((size_t)M * n * 4);
+  w.dy = take((size_t)M * n * 4);
+  w.grad = take((size_t)M * kP * 4);
+  w.loss = take((size_t)M * 4);
+  return w;
+}
+
+__device__ inline unsigned short to_bf16(float f) {  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline float silu(float a) { return a / (1.0f + expf(-a)); }
+__device__ inline float dsilu(float a) {
+  const float s = 1.0f / (1.0f + expf(-a));
+  return s * (1.0f + a * (1.0f - s));
+}
+
+struct ForwardOut {  // optional stores of the training forward (member slices)
+  float *z, *a1, *a2, *a3, *h1, *h2, *h3, *y;
+};
+
+// Forward pass of one member over samples [s0, s0 + 64) (256 threads).
+// Leaves the standardised outputs in ys[64] (LDS).
+template <bool STORE>
+__device__ void forward_tile(const Header& H, const float* __restrict__ master,
+                             const unsigned short* __restrict__ w, const float* __restrict__ X, int64_t n,
+                             int64_t s0, float* zs /*[64][6]*/, unsigned short (*act)[kTileS][kActStride],
+                             float* ys, const ForwardOut& st) {
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  // standardised inputs
+  for (int q = tid; q < kTileS * kIn; q += 256) {
+    const int s = q / kIn, i = q % kIn;
+    const int64_t gs = s0 + s;
+    float zv = 0.0f;
+    if (gs < n) zv = (logf(X[gs * kIn + i]) - H.mu[i]) / H.sigma[i];
+    zs[q] = zv;
+    if (STORE && gs < n) st.z[gs * kIn + i] = zv;
+  }
+  __syncthreads();
+  // layer 1 (FP32, BF16 weights)
+  for (int q = tid; q < kTileS * kH; q += 256) {
+    const int s = q / kH, o = q % kH;
+    float a = master[ob1 + o];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) a += from_bf16(w[oW1 + o * kIn + i]) * zs[s * kIn + i];
+    const unsigned short h = to_bf16(silu(a));
+    act[0][s][o] = h;
+    const int64_t gs = s0 + s;
+    if (STORE && gs < n) {
+      st.a1[gs * kH + o] = a;
+      st.h1[gs * kH + o] = from_bf16(h);
+    }
+  }
+  __syncthreads();
+  // layers 2 and 3 on MFMA: wave w owns samples 16w..16w+15
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int oW = layer == 0 ? oW2 : oW3, ob = layer == 0 ? ob2 : ob3;
+    const unsigned short (*in)[kActStride] = act[layer];
+    unsigned short (*out)[kActStride] = act[1 - layer];
+    float* sa = layer == 0 ? st.a2 : st.a3;
+    float* sh = layer == 0 ? st.h2 : st.h3;
+    const int arow = wave * 16 + (lane & 15);  // A: sample row of this lane
+    const int kq = 4 * (lane >> 4);            // A/B: k offset within the 16-wide step
+#pragma unroll 1
+    for (int nt = 0; nt < kH / 16; ++nt) {
+      float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      const int bo = nt * 16 + (lane & 15);  // B: output column of this lane
+#pragma unroll
+      for (int kk = 0; kk < kH / 16; ++kk) {
+        const int k = kk * 16 + kq;
+        short4_t a, b;
+        a[0] = (short)in[arow][k];
+        a[1] = (short)in[arow][k + 1];
+        a[2] = (short)in[arow][k + 2];
+        a[3] = (short)in[arow][k + 3];
+        const unsigned short* wr = w + oW + bo * kH + k;
+        b[0] = (short)wr[0];
+        b[1] = (short)wr[1];
+        b[2] = (short)wr[2];
+        b[3] = (short)wr[3];
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      }
+      // D[i][j]: sample i = 4 (lane/16) + v, output j = lane % 16
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = wave * 16 + 4 * (lane >> 4) + v;
+        const float a = acc[v] + master[ob + bo];
+        const unsigned short h = to_bf16(silu(a));
+        out[s][bo] = h;
+        const int64_t gs = s0 + s;
+        if (STORE && gs < n) {
+          sa[gs * kH + bo] = a;
+          sh[gs * kH + bo] = from_bf16(h);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // output layer (FP32 dot of BF16 values); act[0] holds h3
+  if (tid < kTileS) {
+    float y = master[ob4];
+    for (int i = 0; i < kH; ++i) y += from_bf16(w[ow4 + i]) * from_bf16(act[0][tid][i]);
+    ys[tid] = y;
+    const int64_t gs = s0 + tid;
+    if (STORE && gs < n) st.y[gs] = y;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void forward_train_kernel(Model md, const float* X, int64_t n, TrainWs ws) {
+  __shared__ float zs[kTileS * kIn];
+  __shared__ unsigned short act[2][kTileS][kActStride];
+  __shared__ float ys[kTileS];
+  const int m = blockIdx.y;
+  const size_t nh = (size_t)n * kH;
+  ForwardOut st{ws.z + (size_t)m * n * kIn, ws.a1 + m * nh, ws.a2 + m * nh, ws.a3 + m * nh,
+                ws.h1 + m * nh, ws.h2 + m * nh, ws.h3 + m * nh, ws.y + (size_t)m * n};
+  forward_tile<true>(*md.hdr, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n,
+                     (int64_t)blockIdx.x * kTileS, zs, act, ys, st);
+}
+
+// Per-sample deltas: dy = 2 (y - t)/n, then the pre-activation gradients of
+// the three hidden layers (block of 128 threads = hidden units).
+__global__ __launch_bounds__(128) void delta_kernel(Model md, const float* t, int64_t n, TrainWs ws) {
+  __shared__ float d[kH];
+  const int m = blockIdx.y, o = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const size_t nh = (size_t)n * kH, row = m * nh + (size_t)s * kH;
+  const unsigned short* w = md.w + (size_t)m * kPpad;
+  const float ty = (t[s] - md.hdr->t_mu) / md.hdr->t_sigma;
+  const float dy = 2.0f * (ws.y[(size_t)m * n + s] - ty) / (float)n;
+  if (o == 0) ws.dy[(size_t)m * n + s] = dy;
+  float da = dy * from_bf16(w[ow4 + o]) * dsilu(ws.a3[row + o]);
+  ws.d3[row + o] = da;
+  d[o] = da;
+  __syncthreads();
+  float g = 0.0f;
+  for (int j = 0; j < kH; ++j) g += from_bf16(w[oW3 + j * kH + o]) * d[j];
+  da = g * dsilu(ws.a2[row + o]);
+  ws.d2[row + o] = da;
+  __syncthreads();
+  d[o] = da;
+  __syncthreads();
+  g = 0.0f;
+  for (int j = 0; j < kH; ++j) g += from_bf16(w[oW2 + j * kH + o]) * d[j];
+  ws.d1[row + o] = g * dsilu(ws.a1[row + o]);
+}
+
+// Weight gradients G[o][i] = sum_s delta[s][o] * in[s][i] (in[s][K] = 1
+// gives the bias), one 16 x 16 tile of (o, i) per block, samples in fixed
+// order through LDS: deterministic.
+struct GradJob {
+  const float* delta;  // [n][rows_d]
+  int rows_d;          // width of delta rows (128 or 1)
+  const float* in;     // [n][K]
+  int K;
+  int nO;              // outputs (128 or 1)
+  int w_off, b_off;    // parameter offsets of weights [nO][K] and bias [nO]
+};
+
+__global__ __launch_bounds__(256) void wgrad_kernel(GradJob job, int64_t n, size_t delta_stride,
+                                                    size_t in_stride, float* grad) {
+  __shared__ float sd[64][16], si[64][17];
+  const int m = blockIdx.z;
+  const float* delta = job.delta + m * delta_stride;
+  const float* in = job.in + m * in_stride;
+  const int o0 = blockIdx.y * 16, i0 = blockIdx.x * 16;
+  const int to = threadIdx.x / 16, ti = threadIdx.x % 16;
+  float acc = 0.0f;
+  for (int64_t s0 = 0; s0 < n; s0 += 64) {
+    for (int q = threadIdx.x; q < 64 * 16; q += 256) {
+      const int s = q / 16, c = q % 16;
+      const int64_t gs = s0 + s;
+      const int o = o0 + c, i = i0 + c;
+      sd[s][c] = (gs < n && o < job.nO) ? delta[gs * job.rows_d + o] : 0.0f;
+      si[s][c] = gs < n ? (i < job.K ? in[gs * job.K + i] : (i == job.K ? 1.0f : 0.0f)) : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int s = 0; s < 64; ++s) acc += sd[s][to] * si[s][ti];
+    __syncthreads();
+  }
+  const int o = o0 + to, i = i0 + ti;
+  if (o < job.nO && i <= job.K) {
+    float* g = grad + (size_t)m * kP;
+    if (i < job.K) g[job.w_off + o * job.K + i] = acc;
+    else g[job.b_off + o] = acc;
+  }
+}
+
+__global__ void adam_kernel(Model md, const float* grad, int M, float lr, int step) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)M * kP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float g = grad[q];
+  const float m = b1 * md.m[q] + (1.0f - b1) * g;
+  const float v = b2 * md.v[q] + (1.0f - b2) * g * g;
+  md.m[q] = m;
+  md.v[q] = v;
+  const float mh = m / (1.0f - powf(b1, (float)step));
+  const float vh = v / (1.0f - powf(b2, (float)step));
+  const float p = md.master[q] - lr * mh / (sqrtf(vh) + eps);
+  md.master[q] = p;
+  const int64_t mem = q / kP, k = q % kP;
+  md.w[mem * kPpad + k] = to_bf16(p);
+}
+
+__global__ void to_bf16_kernel(Model md, int M) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)M * kP) return;
+  md.w[(q / kP) * kPpad + q % kP] = to_bf16(md.master[q]);
+}
+
+__global__ __launch_bounds__(1024) void loss_kernel(Model md, const float* t, int64_t n, TrainWs ws) {
+  const int m = blockIdx.x;
+  __shared__ float part[16];
+  float s = 0.0f;
+  for (int64_t q = threadIdx.x; q < n; q += 1024) {
+    const float r = ws.y[(size_t)m * n + q] - (t[q] - md.hdr->t_mu) / md.hdr->t_sigma;
+    s += r * r;
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float tot = 0.0f;
+    for (int w = 0; w < 16; ++w) tot += part[w];
+    ws.loss[m] = tot / (float)n;
+  }
+}
+
+// Ensemble query: mean and spread (max - min) of ln k_s over the members,
+// out-of-box test of the standardised inputs, fallback flag and the number
+// of flagged queries per block.
+__global__ __launch_bounds__(256) void query_kernel(Model md, const float* X, int64_t n, float spread_tol,
+                                                    float* mean, float* spread, unsigned char* fallback,
+                                                    int* block_count) {
+  __shared__ float zs[kTileS * kIn];
+  __shared__ unsigned short act[2][kTileS][kActStride];
+  __shared__ float ys[kTileS], ymin[kTileS], ymax[kTileS], ysum[kTileS];
+  __shared__ int cnt;
+  const Header& H = *md.hdr;
+  const int64_t s0 = (int64_t)blockIdx.x * kTileS;
+  const int tid = threadIdx.x;
+  if (tid == 0) cnt = 0;
+  ForwardOut none{};
+  for (int m = 0; m < H.members; ++m) {
+    forward_tile<false>(H, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n, s0, zs, act, ys,
+                        none);
+    if (tid < kTileS) {
+      const float v = ys[tid] * H.t_sigma + H.t_mu;
+      ysum[tid] = m == 0 ? v : ysum[tid] + v;
+      ymin[tid] = m == 0 ? v : fminf(ymin[tid], v);
+      ymax[tid] = m == 0 ? v : fmaxf(ymax[tid], v);
+    }
+    __syncthreads();
+  }
+  if (tid < kTileS && s0 + tid < n) {
+    const int64_t gs = s0 + tid;
+    bool out = false;
+    for (int i = 0; i < kIn; ++i) {
+      const float z = zs[tid * kIn + i];
+      out = out || !(z >= H.lo[i] && z <= H.hi[i]);
+    }
+    const float sp = ymax[tid] - ymin[tid];
+    mean[gs] = ysum[tid] / (float)H.members;
+    spread[gs] = sp;
+    const bool fb = out || !(sp <= spread_tol);
+    fallback[gs] = fb ? 1 : 0;
+    if (fb) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (tid == 0) block_count[blockIdx.x] = cnt;
+}
+
+// Ordered compaction of the flagged query indices: an exclusive scan of the
+// per-block counts (one block), then each block writes its flagged indices
+// in order.
+__global__ __launch_bounds__(1024) void scan_kernel(const int* block_count, int nblocks, int* block_off,
+                                                    int64_t* total) {
+  __shared__ int buf[1024];
+  int carry = 0;
+  for (int b0 = 0; b0 < nblocks; b0 += 1024) {
+    const int b = b0 + threadIdx.x;
+    const int v = b < nblocks ? block_count[b] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+      const int u = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (b < nblocks) block_off[b] = carry + buf[threadIdx.x] - v;
+    const int last = buf[1023];
+    __syncthreads();
+    carry += last;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kTileS) void scatter_kernel(const unsigned char* fallback, int64_t n,
+                                                         const int* block_off, int64_t* idx) {
+  const int64_t s0 = (int64_t)blockIdx.x * kTileS;
+  const int64_t gs = s0 + threadIdx.x;
+  const bool f = gs < n && fallback[gs];
+  const unsigned long long mask = __ballot(f);
+  if (f) {
+    const unsigned long long below = mask & ((1ull << threadIdx.x) - 1ull);
+    idx[block_off[blockIdx.x] + __popcll(below)] = gs;
+  }
+}
+
+}  // namespace
+}  // namespace it
+
+using namespace it;
+
+extern "C" {
+
+int it_mlp_model_bytes(int32_t members, size_t* bytes) {
+  if (!bytes || members < 1 || members > 64) return IT_EINVAL;
+  *bytes = model_bytes(members);
+  return IT_OK;
+}
+
+int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, void* stream_) {
+  if (!d_model || !h_params || !h_norm || members < 1 || members > 64) return IT_EINVAL;
+  hipStream_t s = (hipStream_t)stream_;
+  Model md = carve_model(d_model, members);
+  Header h;
+  std::memset(&h, 0, sizeof(h));
+  h.members = members;
+  for (int i = 0; i < kIn; ++i) {
+    h.mu[i] = h_norm[i];
+    h.sigma[i] = h_norm[kIn + i];
+    h.lo[i] = h_norm[2 * kIn + i];
+    h.hi[i] = h_norm[3 * kIn + i];
+    if (!(h.sigma[i] > 0.0f) || !(h.lo[i] <= h.hi[i])) return IT_EINVAL;
+  }
+  h.t_mu = h_norm[4 * kIn];
+  h.t_sigma = h_norm[4 * kIn + 1];
+  if (!(h.t_sigma > 0.0f)) return IT_EINVAL;
+  if (hipMemcpyAsync(md.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(md.master, h_params, (size_t)members * kP * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(md.m, 0, (size_t)members * kP * 4, s) != hipSuccess ||
+      hipMemsetAsync(md.v, 0, (size_t)members * kP * 4, s) != hipSuccess)
+    return IT_EHIP;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((members * kP + 255) / 256), dim3(256), 0, s, md, members);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return IT_EHIP;
+  return IT_OK;
+}
+
+int it_mlp_train_ws_bytes(int32_t members, int64_t n, size_t* bytes) {
+  if (!bytes || members < 1 || members > 64 || n < 1) return IT_EINVAL;
+  *bytes = train_ws_bytes(members, n);
+  return IT_OK;
+}
+
+static int launch_grad(const Model& md, int M, const float* X, const float* t, int64_t n, const TrainWs& w,
+                       hipStream_t s) {
+  const int nb = (int)((n + kTileS - 1) / kTileS);
+  hipLaunchKernelGGL(forward_train_kernel, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
+  hipLaunchKernelGGL(delta_kernel, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
+  const size_t nh = (size_t)n * kH;
+  const GradJob jobs[4] = {
+      {w.d3, kH, w.h2, kH, kH, oW3, ob3},
+      {w.d2, kH, w.h1, kH, kH, oW2, ob2},
+      {w.d1, kH, w.z, kIn, kH, oW1, ob1},
+      {w.dy, 1, w.h3, kH, 1, ow4, ob4},
+  };
+  for (int j = 0; j < 4; ++j) {
+    const GradJob& g = jobs[j];
+    const size_t dstride = g.rows_d == 1 ? (size_t)n : nh;
+    const size_t istride = g.K == kIn ? (size_t)n * kIn : nh;
+    dim3 grid((g.K + 1 + 15) / 16, (g.nO + 15) / 16, M);
+    hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, s, g, n, dstride, istride, w.grad);
+  }
+  return hipGetLastError() == hipSuccess ? IT_OK : IT_EHIP;
+}
+
+int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n,
+                float* d_grad, float* h_loss, void* d_ws, size_t ws_bytes, void* stream_) {
+  if (!d_model || !d_X || !d_t || !d_grad || n < 1 || members < 1 || members > 64) return IT_EINVAL;
+  if (!d_ws || ws_bytes < train_ws_bytes(members, n)) return IT_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream_;
+  Model md = carve_model((void*)d_model, members);
+  TrainWs w = carve_train(d_ws, members, n);
+  int rc = launch_grad(md, members, d_X, d_t, n, w, s);
+  if (rc) return rc;
+  if (hipMemcpyAsync(d_grad, w.grad, (size_t)members * kP * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return IT_EHIP;
+  if (h_loss) {
+    hipLaunchKernelGGL(loss_kernel, dim3(members), dim3(1024), 0, s, md, d_t, n, w);
+    if (hipMemcpyAsync(h_loss, w.loss, members * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return IT_EHIP;
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? IT_OK : IT_EHIP;
+}
+
+int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int32_t steps,
+                 float lr, int32_t log_every, float* h_loss, void* d_ws, size_t ws_bytes, void* stream_) {
+  if (!d_model || !d_X || !d_t || n < 1 || steps < 0 || members < 1 || members > 64 || !(lr > 0.0f))
+    return IT_EINVAL;
+  if (!d_ws || ws_bytes < train_ws_bytes(members, n)) return IT_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream_;
+  Model md = carve_model(d_model, members);
+  TrainWs w = carve_train(d_ws, members, n);
+  Header h;
+  if (hipMemcpy(&h, md.hdr, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return IT_EHIP;
+  int nlog = 0;
+  for (int k = 0; k < steps; ++k) {
+    int rc = launch_grad(md, members, d_X, d_t, n, w, s);
+    if (rc) return rc;
+    if (h_loss && log_every > 0 && k % log_every == 0) {
+      hipLaunchKernelGGL(loss_kernel, dim3(members), dim3(1024), 0, s, md, d_t, n, w);
+      if (hipMemcpyAsync(h_loss + (size_t)nlog * members, w.loss, members * 4, hipMemcpyDeviceToHost, s) !=
+          hipSuccess)
+        return IT_EHIP;
+      ++nlog;
+    }
+    hipLaunchKernelGGL(adam_kernel, dim3((members * kP + 255) / 256), dim3(256), 0, s, md, w.grad, members, lr,
+                       h.step + k + 1);
+    if (hipGetLastError() != hipSuccess) return IT_EHIP;
+  }
+  h.step += steps;
+  if (hipMemcpyAsync(md.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) return IT_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? IT_OK : IT_EHIP;
+}
+
+int it_mlp_query_ws_bytes(int64_t nq, size_t* bytes) {
+  if (!bytes || nq < 0) return IT_EINVAL;
+  const int64_t nb = (nq + kTileS - 1) / kTileS;
+  *bytes = align256((size_t)nb * 4) * 2 + 256;
+  return IT_OK;
+}
+
+int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
+                 float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
+                 void* d_ws, size_t ws_bytes, void* stream_) {
+  if (!d_model || nq < 0 || (nq > 0 && (!d_X || !d_mean || !d_spread || !d_fallback))) return IT_EINVAL;
+  size_t need;
+  it_mlp_query_ws_bytes(nq, &need);
+  if (!d_ws || ws_bytes < need) return IT_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream_;
+  if (nq == 0) {
+    if (h_nfallback) *h_nfallback = 0;
+    return IT_OK;
+  }
+  Model md = carve_model((void*)d_model, 1);  // header and first arrays; members read from the header
+  Header h;
+  if (hipMemcpyAsync(&h, md.hdr, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IT_EHIP;
+  md = carve_model((void*)d_model, h.members);
+  const int nb = (int)((nq + kTileS - 1) / kTileS);
+  char* p = (char*)d_ws;
+  int* counts = (int*)p;
+  int* offs = (int*)(p + align256((size_t)nb * 4));
+  int64_t* total = (int64_t*)(p + 2 * align256((size_t)nb * 4));
+  hipLaunchKernelGGL(query_kernel, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
+                     d_fallback, counts);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, nb, offs, total);
+  if (d_fallback_idx)
+    hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(kTileS), 0, s, d_fallback, nq, offs, d_fallback_idx);
+  if (hipGetLastError() != hipSuccess) return IT_EHIP;
+  if (h_nfallback) {
+    if (hipMemcpyAsync(h_nfallback, total, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return IT_EHIP;
+  }
+  return IT_OK;
+}
+
+}  // extern "C"

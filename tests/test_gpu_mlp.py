@@ -1,0 +1,119 @@
+"""Surrogate kernels on the GPU against the FP64 reference network.
+
+Both sides round weights and hidden activations to BF16 at the same points.
+The FP32 (GPU) and FP64 (reference) pre-activations can land on opposite
+sides of a BF16 rounding boundary; such a flip moves one activation by one
+BF16 step (2^-8 relative).  So the forward bar is 2e-4 on the median and
+99th percentile sample and 3e-2 on the worst, and gradients are compared
+per parameter block in the 2-norm.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_06749_amd as it
+    it.lib()
+    return it
+
+
+def make_norm(X, t, margin=1e-3):
+    # the box gets a small margin: the GPU standardises in FP32, so a
+    # training point on the edge can land a rounding step outside
+    L = np.log(X)
+    mu, sd = L.mean(axis=0), L.std(axis=0)
+    Z = (L - mu) / sd
+    return np.concatenate([mu, sd, Z.min(axis=0) - margin, Z.max(axis=0) + margin,
+                           [t.mean(), t.std()]]).astype(np.float32)
+
+
+def setup(gpu, members, n, seed=1, scale=1.0):
+    import torch
+    X = W.surrogate_inputs(seed, n).astype(np.float32)
+    t = (np.sin(np.log(X)).sum(axis=1) * 0.3 + 0.1 * np.log(X[:, 0])).astype(np.float32)
+    norm = make_norm(X.astype(np.float64), t.astype(np.float64))
+    params = W.mlp_init(seed + 10, members) * np.float32(scale)
+    model = torch.empty(gpu.it_mlp_model_bytes(members), dtype=torch.uint8, device="cuda")
+    gpu.it_mlp_init(model, members, params, norm)
+    return model, X, t, norm, params
+
+
+def ref_forward(params, X, norm, members):
+    n = dict(mu=norm[0:6].astype(np.float64), sigma=norm[6:12].astype(np.float64))
+    Z = mlp.standardise(X.astype(np.float64), n)
+    ys = [mlp.forward(params[m].astype(np.float64), Z, cast=True)[0] * float(norm[25]) + float(norm[24])
+          for m in range(members)]
+    return np.stack(ys), Z
+
+
+def test_forward_matches_reference(gpu):
+    import torch
+    members, n = 3, 4000
+    model, X, t, norm, params = setup(gpu, members, n)
+    mean, spread, fb, idx, cnt = gpu.it_mlp_query(model, torch.tensor(X, device="cuda"), 1e30)
+    ys, _ = ref_forward(params, X, norm, members)
+    err = np.abs(mean.cpu().numpy() - ys.mean(axis=0)) / (1 + np.abs(ys.mean(axis=0)))
+    assert np.median(err) < 2e-4 and np.quantile(err, 0.99) < 2e-3 and err.max() < 3e-2
+    sp = spread.cpu().numpy()
+    ref_sp = ys.max(axis=0) - ys.min(axis=0)
+    assert np.quantile(np.abs(sp - ref_sp) / (1 + ref_sp), 0.99) < 2e-3
+    assert cnt == 0  # every input is inside its own training box
+
+
+def test_gradient_matches_reference(gpu):
+    import torch
+    members, n = 2, 2048
+    model, X, t, norm, params = setup(gpu, members, n, seed=3)
+    grad, loss = gpu.it_mlp_grad(model, members, torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"))
+    g = grad.cpu().numpy()
+    _, Z = ref_forward(params, X, norm, members)
+    ts = (t.astype(np.float64) - float(norm[24])) / float(norm[25])
+    for m in range(members):
+        rl, rg = mlp.loss_and_grad(params[m].astype(np.float64), Z, ts, cast=True)
+        assert loss[m] == pytest.approx(rl, rel=2e-3)
+        off = 0
+        for name, shape in mlp.SIZES:
+            k = int(np.prod(shape))
+            a, b = g[m, off:off + k], rg[off:off + k]
+            assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b) + 1e-7, name
+            off += k
+
+
+def test_training_reduces_loss(gpu):
+    import torch
+    members, n = 2, 2048
+    model, X, t, norm, params = setup(gpu, members, n, seed=5)
+    Xd, td = torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda")
+    losses = gpu.it_mlp_train(model, members, Xd, td, steps=300, lr=2e-3, log_every=50)
+    assert losses.shape == (6, members)
+    assert np.all(losses[-1] < 0.2 * losses[0])
+    _, loss_after = gpu.it_mlp_grad(model, members, Xd, td)
+    assert np.all(loss_after < losses[-1] * 1.5)
+
+
+def test_query_fallback_mask_and_indices(gpu):
+    import torch
+    members, n = 2, 1000
+    model, X, t, norm, params = setup(gpu, members, n, seed=7)
+    Xq = X.copy()
+    Xq[::7, 0] *= 1e3       # LET far outside the training box
+    Xq[3::11, 3] *= 0.01    # gap far outside
+    mean, spread, fb, idx, cnt = gpu.it_mlp_query(model, torch.tensor(Xq, device="cuda"), 0.5)
+    f = fb.cpu().numpy().astype(bool)
+    sp = spread.cpu().numpy()
+    out_of_box = np.zeros(n, bool)
+    out_of_box[::7] = True
+    out_of_box[3::11] = True
+    assert np.all(f[out_of_box])
+    assert np.array_equal(f, out_of_box | (sp > 0.5))
+    ix = idx.cpu().numpy()
+    assert cnt == f.sum() and np.array_equal(ix, np.nonzero(f)[0])

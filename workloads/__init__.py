@@ -207,3 +207,62 @@ def perturbed_field(shape, seed: int, scale: float = 1e9):
         f[-1] = 0.0
         out.append(np.ascontiguousarray(f))
     return out[0], out[1]
+
+
+# --------------------------------------------------------------------------
+# Surrogate inputs
+# --------------------------------------------------------------------------
+# Ranges of the six surrogate inputs: LET [keV/um], b [cm], V [V], gap [cm],
+# dose per pulse [mGy], pulse repetition rate [Hz].  The rate range keeps the
+# pulse period (>= 1 ms) longer than the longest ion collection time in this
+# box (~0.2 ms at 50 V over 0.125 cm), so pulses do not overlap and k_s is
+# the single-pulse value at every rate in the box.
+SURROGATE_RANGES = ((1.0, 500.0), (5e-4, 2e-3), (50.0, 400.0), (0.025, 0.125), (0.01, 1.0), (10.0, 1000.0))
+SURROGATE_LOG = (True, False, True, False, True, True)
+MLP_PARAMS = 34049
+MLP_HIDDEN = 128
+
+
+def surrogate_inputs(seed: int, n: int) -> np.ndarray:
+    """n input rows [LET, b, V, gap, dose, rate] (float64), log-uniform or
+    uniform over SURROGATE_RANGES."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for (lo, hi), lg in zip(SURROGATE_RANGES, SURROGATE_LOG):
+        if lg:
+            cols.append(np.exp(rng.uniform(math.log(lo), math.log(hi), n)))
+        else:
+            cols.append(rng.uniform(lo, hi, n))
+    return np.stack(cols, axis=1)
+
+
+def surrogate_chamber(x, cells: int = 24, nz: int = 32, b_over_dx: float = 2.5):
+    """Chamber and track of one surrogate sample: one Gaussian track parallel
+    to the field through the centre of a periodic cell of cells x cells nodes
+    at spacing b / b_over_dx, nz gap intervals, the dose as uniform
+    pre-ionisation, everything at t = 0 (one pulse)."""
+    let, b, V, d, dose, _rate = (float(v) for v in x)
+    dx = b / b_over_dx
+    ch = chamber(cells, cells, nz, dx, d, V, uniform_n0=dose * ion_pairs_per_mGy(AIR["W_eV"]))
+    tr = tracks([[let, b, (cells // 2) * dx, (cells // 2) * dx, 0.0, 0.0, 0.0]])
+    return ch, tr
+
+
+def mlp_init(seed: int, members: int) -> np.ndarray:
+    """Initial weights [members, MLP_PARAMS] (float32): He-style uniform
+    weights, zero biases, in the flat layout W1, b1, W2, b2, W3, b3, w4, b4."""
+    rng = np.random.default_rng(seed)
+    shapes = ((MLP_HIDDEN, 6), (MLP_HIDDEN,), (MLP_HIDDEN, MLP_HIDDEN), (MLP_HIDDEN,),
+              (MLP_HIDDEN, MLP_HIDDEN), (MLP_HIDDEN,), (MLP_HIDDEN,), (1,))
+    out = []
+    for _ in range(members):
+        parts = []
+        for k, shape in enumerate(shapes):
+            if k % 2 == 1:
+                parts.append(np.zeros(shape))
+            else:
+                fan_in = shape[1] if len(shape) == 2 else shape[0]
+                lim = math.sqrt(6.0 / fan_in)
+                parts.append(rng.uniform(-lim, lim, shape))
+        out.append(np.concatenate([p.ravel() for p in parts]))
+    return np.stack(out).astype(np.float32)
