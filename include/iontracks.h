@@ -213,9 +213,19 @@ int it_mlp_model_bytes(int32_t members, size_t* bytes);
 
 /* Initialises a model buffer: h_params host [members][IT_MLP_PARAMS] FP32
  * initial weights; h_norm host [26] = mu[6], sigma[6], box_lo[6], box_hi[6]
- * (standardised bounds of the training inputs), t_mu, t_sigma.  Clears the
+ * (standardised bounds of the training inputs), t_mu, t_sigma.  h_phys:
+ * NULL (the network predicts ln k_s itself) or host [6] = averaged D,
+ * averaged mu, alpha, W [eV], mu+ + mu-, ion pairs per cm^3 and mGy: then the
+ * network predicts the residual of ln k_s over the analytic baseline
+ * -ln f_Jaffe - ln f_Boag (eq. Jaffe_noangle for one track parallel to the
+ * field; ln(1+u)/u for the dose), which the query adds back.  Clears the
  * optimiser state.  Synchronises `stream`.  Errors: IT_EINVAL, IT_EHIP. */
-int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, void* stream);
+int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm,
+                const double* h_phys, void* stream);
+
+/* The analytic baseline of the model (device d_X [n][6] -> d_out [n],
+ * FP64), for checking.  Asynchronous on `stream`. */
+int it_mlp_baseline(const void* d_model, const float* d_X, int64_t n, double* d_out, void* stream);
 
 /* Device workspace bytes of it_mlp_train / it_mlp_grad for n samples. */
 int it_mlp_train_ws_bytes(int32_t members, int64_t n, size_t* bytes);

@@ -81,7 +81,8 @@ def lib():
                                      vp, vp]
         szp = ctypes.POINTER(ctypes.c_size_t)
         L.it_mlp_model_bytes.argtypes = [ctypes.c_int32, szp]
-        L.it_mlp_init.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.it_mlp_init.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
+        L.it_mlp_baseline.argtypes = [vp, vp, i64, vp, vp]
         L.it_mlp_train_ws_bytes.argtypes = [ctypes.c_int32, i64, szp]
         L.it_mlp_grad.argtypes = [vp, ctypes.c_int32, vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
         L.it_mlp_train.argtypes = [vp, ctypes.c_int32, vp, vp, i64, ctypes.c_int32, ctypes.c_float,
@@ -91,7 +92,7 @@ def lib():
         for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance",
                      "it_workspace_size_batch", "it_solve_batch", "it_mlp_model_bytes", "it_mlp_init",
                      "it_mlp_train_ws_bytes", "it_mlp_grad", "it_mlp_train", "it_mlp_query_ws_bytes",
-                     "it_mlp_query"):
+                     "it_mlp_query", "it_mlp_baseline"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -268,13 +269,23 @@ def it_mlp_model_bytes(members: int) -> int:
     return out.value
 
 
-def it_mlp_init(model, members, params, norm, stream=None):
+def it_mlp_init(model, members, params, norm, phys=None, stream=None):
     """model: device uint8 tensor of it_mlp_model_bytes; params float32
-    [members, IT_MLP_PARAMS]; norm float32 [26]."""
+    [members, IT_MLP_PARAMS]; norm float32 [26]; phys None or 6 floats (the
+    analytic-baseline constants)."""
     p = np.ascontiguousarray(params, dtype=np.float32).reshape(members, IT_MLP_PARAMS)
     nm = np.ascontiguousarray(norm, dtype=np.float32).reshape(26)
-    _check(lib().it_mlp_init(_dptr(model), int(members), p.ctypes.data, nm.ctypes.data, _stream(stream)),
-           "it_mlp_init")
+    ph = None if phys is None else np.ascontiguousarray(phys, dtype=np.float64).reshape(6)
+    _check(lib().it_mlp_init(_dptr(model), int(members), p.ctypes.data, nm.ctypes.data,
+                             None if ph is None else ph.ctypes.data, _stream(stream)), "it_mlp_init")
+
+
+def it_mlp_baseline(model, X, stream=None):
+    import torch
+    out = torch.empty(X.shape[0], dtype=torch.float64, device=X.device)
+    _check(lib().it_mlp_baseline(_dptr(model), _dptr(X), int(X.shape[0]), _dptr(out), _stream(stream)),
+           "it_mlp_baseline")
+    return out
 
 
 def _train_ws(members, n, device):

@@ -7,9 +7,13 @@
 // input layer and the 128-wide output dot run in FP32.  Hidden activations
 // are rounded to BF16 before entering the next layer.  Inputs are the six
 // physical quantities (LET, b, V, gap, dose per pulse, pulse rate),
-// standardised as (log x - mu) / sigma; the output is the standardised
-// ln k_s.  Training: full-batch mean squared error, backward in FP32 with
-// the BF16 casts passed straight through, Adam.
+// standardised as (log x - mu) / sigma.  Optionally the network learns the
+// residual of ln k_s over an analytic baseline, -ln f_Jaffe - ln f_Boag:
+// Jaffe's collection efficiency of a track parallel to the field (eq.
+// Jaffe_noangle, with the averaged D and mu) times Boag's ln(1+u)/u for the
+// uniform dose; the baseline is evaluated here in FP64.  The output is the
+// standardised residual.  Training: full-batch mean squared error, backward
+// in FP32 with the BF16 casts passed straight through, Adam.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,10 +37,17 @@ constexpr int kActStride = kH + 4;  // padded BF16 row (avoids LDS bank conflict
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
+constexpr int kGL = 32;  // Gauss-Legendre nodes of the Jaffe integral
+
 struct Header {
   int32_t members, step;
   float mu[kIn], sigma[kIn], lo[kIn], hi[kIn];
   float t_mu, t_sigma;
+  int32_t use_baseline, pad;
+  // averaged diffusion and mobility, alpha, W [eV], mu+ + mu-, ion pairs
+  // per cm^3 and mGy
+  double D, mu_avg, alpha, W, mu_sum, pairs_per_mGy;
+  double gl_x[kGL], gl_w[kGL];  // nodes and weights on [-1, 1]
 };
 
 struct Model {  // device pointers carved from the model buffer
@@ -70,13 +81,13 @@ Model carve_model(void* base, int M) {
 }
 
 struct TrainWs {  // per member: [M][n][...]
-  float *z, *a1, *a2, *a3, *h1, *h2, *h3, *y, *dy, *d1, *d2, *d3, *grad, *loss;
+  float *z, *a1, *a2, *a3, *h1, *h2, *h3, *y, *dy, *d1, *d2, *d3, *grad, *loss, *base;
 };
 
 size_t train_ws_bytes(int M, int64_t n) {
   const size_t nh = (size_t)M * n * kH * sizeof(float);
   return 9 * align256(nh) + align256((size_t)M * n * kIn * 4) + 2 * align256((size_t)M * n * 4) +
-         align256((size_t)M * kP * 4) + align256((size_t)M * 4);
+         align256((size_t)M * kP * 4) + align256((size_t)M * 4) + align256((size_t)n * 4);
 }
 
 TrainWs carve_train(void* base, int M, int64_t n) {
@@ -102,7 +113,32 @@ TrainWs carve_train(void* base, int M, int64_t n) {
   w.dy = take((size_t)M * n * 4);
   w.grad = take((size_t)M * kP * 4);
   w.loss = take((size_t)M * 4);
+  w.base = take((size_t)n * 4);
   return w;
+}
+
+// Analytic baseline of ln k_s for one query (FP64): -ln f_J - ln f_B with
+// f_J = (y1/y2) e^{-y1} [Ei(y1 + ln(1+y2)) - Ei(y1)], written as
+// (y1/y2) int_0^{ln(1 + ln(1+y2)/y1)} exp(y1 (e^w - 1)) dw (no overflow for
+// large y1), y1 = 8 pi D/(alpha N0), y2 = 2 d D/(mu b^2 E), N0 = LET/W, and
+// f_B = ln(1+u)/u with u = alpha/(mu+ + mu-) n0 d^2/V.
+__device__ double baseline(const Header& H, const float* x) {
+  const double let = x[0], b = x[1], V = x[2], d = x[3], dose = x[4];
+  const double E = V / d;
+  const double N0 = let * 1.0e7 / H.W;
+  const double y1 = 8.0 * M_PI * H.D / (H.alpha * N0);
+  const double y2 = 2.0 * d * H.D / (H.mu_avg * b * b * E);
+  const double upper = log1p(log1p(y2) / y1);
+  double integral = 0.0;
+  for (int q = 0; q < kGL; ++q) {
+    const double w = 0.5 * upper * (H.gl_x[q] + 1.0);
+    integral += H.gl_w[q] * exp(y1 * expm1(w));
+  }
+  integral *= 0.5 * upper;
+  const double fJ = y1 / y2 * integral;
+  const double u = H.alpha / H.mu_sum * dose * H.pairs_per_mGy * d * d / V;
+  const double fB = u > 0.0 ? log1p(u) / u : 1.0;
+  return -log(fJ) - log(fB);
 }
 
 __device__ inline unsigned short to_bf16(float f) {  // round to nearest even
@@ -212,6 +248,10 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
 }
 
 __global__ __launch_bounds__(256) void forward_train_kernel(Model md, const float* X, int64_t n, TrainWs ws) {
+  if (blockIdx.y == 0 && threadIdx.x < kTileS) {  // baseline of each sample (member independent)
+    const int64_t gs = (int64_t)blockIdx.x * kTileS + threadIdx.x;
+    if (gs < n) ws.base[gs] = md.hdr->use_baseline ? (float)baseline(*md.hdr, X + gs * kIn) : 0.0f;
+  }
   __shared__ float zs[kTileS * kIn];
   __shared__ unsigned short act[2][kTileS][kActStride];
   __shared__ float ys[kTileS];
@@ -231,7 +271,7 @@ __global__ __launch_bounds__(128) void delta_kernel(Model md, const float* t, in
   const int64_t s = blockIdx.x;
   const size_t nh = (size_t)n * kH, row = m * nh + (size_t)s * kH;
   const unsigned short* w = md.w + (size_t)m * kPpad;
-  const float ty = (t[s] - md.hdr->t_mu) / md.hdr->t_sigma;
+  const float ty = (t[s] - ws.base[s] - md.hdr->t_mu) / md.hdr->t_sigma;
   const float dy = 2.0f * (ws.y[(size_t)m * n + s] - ty) / (float)n;
   if (o == 0) ws.dy[(size_t)m * n + s] = dy;
   float da = dy * from_bf16(w[ow4 + o]) * dsilu(ws.a3[row + o]);
@@ -320,7 +360,7 @@ __global__ __launch_bounds__(1024) void loss_kernel(Model md, const float* t, in
   __shared__ float part[16];
   float s = 0.0f;
   for (int64_t q = threadIdx.x; q < n; q += 1024) {
-    const float r = ws.y[(size_t)m * n + q] - (t[q] - md.hdr->t_mu) / md.hdr->t_sigma;
+    const float r = ws.y[(size_t)m * n + q] - (t[q] - ws.base[q] - md.hdr->t_mu) / md.hdr->t_sigma;
     s += r * r;
   }
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -361,6 +401,10 @@ __global__ __launch_bounds__(256) void query_kernel(Model md, const float* X, in
   }
   if (tid < kTileS && s0 + tid < n) {
     const int64_t gs = s0 + tid;
+    const float base = H.use_baseline ? (float)baseline(H, X + gs * kIn) : 0.0f;
+    ysum[tid] += (float)H.members * base;
+    ymin[tid] += base;
+    ymax[tid] += base;
     bool out = false;
     for (int i = 0; i < kIn; ++i) {
       const float z = zs[tid * kIn + i];
@@ -415,6 +459,34 @@ __global__ __launch_bounds__(kTileS) void scatter_kernel(const unsigned char* fa
   }
 }
 
+__global__ void baseline_kernel(Model md, const float* X, int64_t n, double* out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = baseline(*md.hdr, X + q * kIn);
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
+// Legendre polynomial (three-term recursion).
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
 }  // namespace
 }  // namespace it
 
@@ -428,7 +500,8 @@ int it_mlp_model_bytes(int32_t members, size_t* bytes) {
   return IT_OK;
 }
 
-int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, void* stream_) {
+int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, const double* h_phys,
+                void* stream_) {
   if (!d_model || !h_params || !h_norm || members < 1 || members > 64) return IT_EINVAL;
   hipStream_t s = (hipStream_t)stream_;
   Model md = carve_model(d_model, members);
@@ -445,6 +518,18 @@ int it_mlp_init(void* d_model, int32_t members, const float* h_params, const flo
   h.t_mu = h_norm[4 * kIn];
   h.t_sigma = h_norm[4 * kIn + 1];
   if (!(h.t_sigma > 0.0f)) return IT_EINVAL;
+  if (h_phys) {
+    h.use_baseline = 1;
+    h.D = h_phys[0];
+    h.mu_avg = h_phys[1];
+    h.alpha = h_phys[2];
+    h.W = h_phys[3];
+    h.mu_sum = h_phys[4];
+    h.pairs_per_mGy = h_phys[5];
+    for (int q = 0; q < 6; ++q)
+      if (!(std::isfinite(h_phys[q]) && h_phys[q] > 0.0)) return IT_EINVAL;
+    gauss_legendre(kGL, h.gl_x, h.gl_w);
+  }
   if (hipMemcpyAsync(md.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(md.master, h_params, (size_t)members * kP * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemsetAsync(md.m, 0, (size_t)members * kP * 4, s) != hipSuccess ||
@@ -529,6 +614,15 @@ int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* 
   h.step += steps;
   if (hipMemcpyAsync(md.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) return IT_EHIP;
   return hipStreamSynchronize(s) == hipSuccess ? IT_OK : IT_EHIP;
+}
+
+int it_mlp_baseline(const void* d_model, const float* d_X, int64_t n, double* d_out, void* stream_) {
+  if (!d_model || n < 0 || (n > 0 && (!d_X || !d_out))) return IT_EINVAL;
+  if (n == 0) return IT_OK;
+  hipStream_t s = (hipStream_t)stream_;
+  Model md = carve_model((void*)d_model, 1);  // only the header is read
+  hipLaunchKernelGGL(baseline_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, md, d_X, n, d_out);
+  return hipGetLastError() == hipSuccess ? IT_OK : IT_EHIP;
 }
 
 int it_mlp_query_ws_bytes(int64_t nq, size_t* bytes) {

@@ -117,3 +117,23 @@ def test_query_fallback_mask_and_indices(gpu):
     assert np.array_equal(f, out_of_box | (sp > 0.5))
     ix = idx.cpu().numpy()
     assert cnt == f.sum() and np.array_equal(ix, np.nonzero(f)[0])
+
+
+def test_baseline_matches_closed_forms(gpu):
+    """The device baseline -ln f_Jaffe - ln f_Boag against the oracle's
+    closed forms (eq. Jaffe_noangle, ln(1+u)/u)."""
+    import torch
+    from oracle import closed_forms as cf
+    from paper_1610_06749_amd import surrogate
+    X = W.surrogate_inputs(21, 300)
+    model, _, _, norm, params = setup(gpu, 1, 64)
+    gpu.it_mlp_init(model, 1, params, norm, surrogate.phys_constants())
+    got = gpu.it_mlp_baseline(model, torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
+    Xf = X.astype(np.float32).astype(np.float64)  # the device sees FP32 inputs
+    a = W.AIR
+    D, mu = 0.5 * (a["D_pos"] + a["D_neg"]), 0.5 * (a["mu_pos"] + a["mu_neg"])
+    for x, g in zip(Xf, got):
+        let, b, V, d, dose, _ = x
+        fj = cf.jaffe_parallel(let, b, V / d, d, D, mu, a["alpha"], a["W_eV"])
+        u = cf.boag_u(dose * W.ion_pairs_per_mGy(), d, V, a["mu_pos"], a["mu_neg"], a["alpha"])
+        assert g == pytest.approx(-np.log(fj) - np.log(cf.boag(u)), rel=1e-9, abs=1e-12)

@@ -236,13 +236,16 @@ def surrogate_inputs(seed: int, n: int) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
-def surrogate_chamber(x, cells: int = 24, nz: int = 32, b_over_dx: float = 2.5):
+def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: float = 1.5):
     """Chamber and track of one surrogate sample: one Gaussian track parallel
     to the field through the centre of a periodic cell of cells x cells nodes
-    at spacing b / b_over_dx, nz gap intervals, the dose as uniform
-    pre-ionisation, everything at t = 0 (one pulse)."""
+    at spacing b / b_over_dx, gap intervals of about dz_over_dx times that
+    spacing (much coarser gap intervals let Lax-Wendroff ripples at the ion
+    column fronts drive the recombination sink unstable), the dose as
+    uniform pre-ionisation, everything at t = 0 (one pulse)."""
     let, b, V, d, dose, _rate = (float(v) for v in x)
     dx = b / b_over_dx
+    nz = max(8, int(math.ceil(d / (dz_over_dx * dx))))
     ch = chamber(cells, cells, nz, dx, d, V, uniform_n0=dose * ion_pairs_per_mGy(AIR["W_eV"]))
     tr = tracks([[let, b, (cells // 2) * dx, (cells // 2) * dx, 0.0, 0.0, 0.0]])
     return ch, tr
