@@ -43,6 +43,9 @@ def parse():
                     help="launches in the stepping-kernel timing")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only run the stepping kernel on the workload grid (for counter runs)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched 96-chamber sweep")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
+    ap.add_argument("--surrogate-train", type=int, default=8192)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy two fields of the workload grid with a plain device copy "
                          "(reference for the HBM byte counters)")
@@ -188,6 +191,27 @@ def main():
                          f"({t_dep * 16:.1f} s) and 40 steps of the full 256x256x200 grid "
                          f"({t_step * 40:.1f} s), scaled to one whole run of {steps_full} steps"}
 
+    sweep = None
+    if not a.no_sweep:
+        chs, trs = W.batched_sweep()
+        it.it_solve_batch(chs[:4], trs[:4])  # warm-up (graph instantiation path)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = it.it_solve_batch(chs, trs)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        vs = sum(r["steps"] * c["nx"] * c["ny"] * (c["nz"] - 1) for r, c in zip(res, chs))
+        sweep = {"workload": "96 chambers, transverse 64-256, gap 50-250 intervals, 50-400 V, "
+                             "LET 1-500 keV/um, 1-500 tracks and 0.01-1 mGy per pulse",
+                 "seconds": sec, "voxel_steps": vs, "voxel_steps_per_s": vs / sec,
+                 "ks_evals_per_s": len(chs) / sec, "max_steps": max(r["steps"] for r in res),
+                 "flags": sorted({r["flags"] for r in res})}
+
+    sur = None
+    if not a.no_surrogate:
+        from paper_1610_06749_amd import surrogate
+        sur = surrogate.evaluate(n_train=a.surrogate_train)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -210,6 +234,8 @@ def main():
                      "kernel": kname, "launch_ms": per_launch * 1e3,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
+        "sweep": sweep,
+        "surrogate": sur,
     }
     print(json.dumps(out), flush=True)
 

@@ -123,3 +123,65 @@ class Surrogate:
             sel = idx.cpu().numpy()
             out[sel] = solver_lnks(Xh[sel])[0]
         return out, mask
+
+
+def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4, schedule=None,
+             seed=None):
+    """The surrogate experiment: train on n_train solver runs, judge on
+    n_hold held-out solver runs, time n_query queries.  Returns a dict."""
+    import torch
+    base_seed = W.SEED_BASE + 5 if seed is None else seed
+    Xtr = W.surrogate_inputs(base_seed, n_train)
+    ytr, vs_tr, sec_tr = solver_lnks(Xtr)
+    s = Surrogate(members=members, seed=base_seed + 100)
+    if schedule is None:
+        schedule = ((2e-3, 1500), (6e-4, 1500), (2e-4, 1500))
+    s.fit(Xtr, ytr, schedule=schedule)
+    Xh = W.surrogate_inputs(base_seed + 1, n_hold)
+    yh, vs_h, sec_h = solver_lnks(Xh)
+    mean, spread, fb, idx, n_fb = s.query(Xh, spread_tol)
+    m = mean.double().cpu().numpy()
+    mask = fb.cpu().numpy().astype(bool)
+    rel = np.abs(np.expm1(m - yh))  # relative error of k_s
+    Xhd = torch.tensor(Xh, dtype=torch.float32, device="cuda")
+    base = B.it_mlp_baseline(s.model, Xhd).cpu().numpy()
+    rel_base = np.abs(np.expm1(base - yh))
+    acc = ~mask
+    # query throughput at the full batch (inputs resident, fallback excluded)
+    Xq = torch.tensor(W.surrogate_inputs(base_seed + 2, n_query), dtype=torch.float32, device="cuda")
+    out = (torch.empty(n_query, dtype=torch.float32, device="cuda"),
+           torch.empty(n_query, dtype=torch.float32, device="cuda"),
+           torch.empty(n_query, dtype=torch.uint8, device="cuda"),
+           torch.empty(n_query, dtype=torch.int64, device="cuda"))
+    B.it_mlp_query(s.model, Xq, spread_tol, out=out)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        _, _, _, _, nq_fb = B.it_mlp_query(s.model, Xq, spread_tol, out=out)
+    e1.record()
+    e1.synchronize()
+    q_sec = e0.elapsed_time(e1) * 1e-3 / reps
+    solver_rate = n_hold / sec_h  # k_s evaluations per second by the batched solver
+    fb_frac_q = nq_fb / n_query
+    # surrogate plus solver fallback at equal (solver) accuracy on the flagged part
+    combined = 1.0 / (q_sec / n_query + fb_frac_q / solver_rate)
+    return {
+        "n_train": n_train, "n_holdout": n_hold, "n_query": n_query, "members": members,
+        "spread_tol_ln": spread_tol,
+        "train_data_seconds": sec_tr, "train_data_voxel_steps": vs_tr, "train_seconds": s.train_seconds,
+        "final_loss": float(s.loss_log[-1].max()) if s.loss_log is not None and len(s.loss_log) else None,
+        "holdout_accepted_fraction": float(acc.mean()),
+        "holdout_rel_err_accepted_max": float(rel[acc].max()) if acc.any() else None,
+        "holdout_rel_err_accepted_p99": float(np.quantile(rel[acc], 0.99)) if acc.any() else None,
+        "holdout_rel_err_all_median": float(np.median(rel)),
+        "holdout_rel_err_all_p90": float(np.quantile(rel, 0.9)),
+        "baseline_rel_err_median": float(np.median(rel_base)),
+        "baseline_rel_err_p90": float(np.quantile(rel_base, 0.9)),
+        "query_seconds": q_sec, "query_rate": n_query / q_sec,
+        "query_fallback_fraction": fb_frac_q,
+        "solver_ks_rate": solver_rate,
+        "surrogate_over_solver": (n_query / q_sec) / solver_rate,
+        "surrogate_with_fallback_over_solver": combined / solver_rate,
+    }
