@@ -60,9 +60,10 @@ def kernel_source_hash(names):
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_name, workload, src_hash):
+def read_traffic(kernel_name, workload, src_hash, shape):
     """HBM bytes per launch from the committed counter summary, or None when
-    no summary exists or the kernel source changed since it was taken."""
+    no summary exists, it was taken with another launch shape, or the kernel
+    source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_name}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -71,7 +72,7 @@ def read_traffic(kernel_name, workload, src_hash):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != src_hash:
+    if vals.get("kernel_source_hash") != src_hash or not vals.get("launch_shape", "").startswith(shape):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -158,27 +159,34 @@ def main():
     chk = dict(ch, max_steps=max(a.kernel_steps, 1))
     wsk = it.workspace(chk, 0)
 
-    def timed_advance(n):
+    T_pass = 1 if kernel == it.IT_KERNEL_PLAIN or a.T <= 1 else a.T
+    launches = max(a.kernel_steps // T_pass, 2)
+    kname = "step_plain" if T_pass == 1 else f"step_blocked_T{T_pass}"
+    src = ["kernels_plain.hip", "stencil_plain.h", "reduce.h", "internal.h"] if T_pass == 1 else \
+        ["kernels_blocked.hip", "reduce.h", "internal.h"]
+
+    def timed_advance(n, timer=None):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        exn = dict(ex, timing_events=timer) if timer is not None else ex
         e0.record(stream)
-        it.it_advance(chk, dt, gp, gn, n, exec=ex, ws=wsk, stream=stream)
+        it.it_advance(chk, dt, gp, gn, n, exec=exn, ws=wsk, stream=stream)
         e1.record(stream)
         e1.synchronize()
         return e0.elapsed_time(e1) * 1e-3
 
-    timed_advance(a.kernel_steps)
-    t_many = min(timed_advance(a.kernel_steps) for _ in range(3))
-    t_one = min(timed_advance(1) for _ in range(5))
-    T_pass = 1 if kernel == it.IT_KERNEL_PLAIN or a.T <= 1 else a.T
-    launches = a.kernel_steps // T_pass
-    per_launch = (t_many - t_one) / max(launches - 1, 1)
-    bytes_per_launch = BYTES_PER_VOXEL_STEP * nint  # compulsory traffic of one pass
+    # one pass = the stepping kernel plus its tally reduction; the kernel
+    # itself is bracketed by HIP events recorded on the run's stream
+    timed_advance(launches * T_pass)
+    t_pass = min(timed_advance(launches * T_pass) for _ in range(3)) / launches
+    timer = it.KernelTimer(launches)
+    timed_advance(launches * T_pass, timer)
+    d = timer.durations()[1:]  # the first launch pays the cold start
+    per_launch = float(d.mean())
+    bytes_per_launch = BYTES_PER_VOXEL_STEP * nint * T_pass  # compulsory traffic of one pass
     achieved = bytes_per_launch / per_launch / 1e9
-    kname = "step_plain" if T_pass == 1 else f"step_blocked_T{T_pass}"
-    src = ["kernels_plain.hip", "reduce.h", "internal.h"] if T_pass == 1 else \
-        ["kernels_blocked.hip", "reduce.h", "internal.h"]
     workload_name = "pulsed_256x256x200"
-    traffic = read_traffic(kname, workload_name, kernel_source_hash(src))
+    shape = f"tile_y {16 if a.tile_y == 16 else 8}" if T_pass == 1 else f"T {T_pass}"
+    traffic = read_traffic(kname, workload_name, kernel_source_hash(src), shape)
 
     cpu = None
     if not a.no_cpu:
@@ -231,7 +239,8 @@ def main():
                    "kernel": kname},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": kname, "launch_ms": per_launch * 1e3,
+                     "kernel": kname, "launch_ms": per_launch * 1e3, "launches_timed": int(d.size),
+                     "pass_ms_with_tally_reduction": t_pass * 1e3,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
         "sweep": sweep,

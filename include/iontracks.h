@@ -117,7 +117,7 @@ typedef struct {
 } it_result;
 
 /* Kernel selection for the stepping.  NULL means "defaults". */
-#define IT_KERNEL_AUTO 0     /* tuned choice (currently the blocked kernel when available) */
+#define IT_KERNEL_AUTO 0     /* the default choice: the plain kernel */
 #define IT_KERNEL_PLAIN 1    /* one time step per launch */
 #define IT_KERNEL_BLOCKED 2  /* steps_per_pass fused steps per launch (temporal blocking) */
 typedef struct {
@@ -125,6 +125,16 @@ typedef struct {
   int32_t steps_per_pass;  /* T for the blocked kernel, 1..8 (0 = default) */
   int32_t tile_y;          /* rows per tile of the blocked kernel (0 = default) */
   int32_t check_every;     /* steps between host checks of the stop criterion (0 = default) */
+  /* Optional instrumentation (NULL / 0 = none): caller-created hipEvent_t
+   * handles, created with timing enabled on the device of the run.  it_solve
+   * and it_advance record events[2i] on the run's stream just before and
+   * events[2i+1] just after the i-th stepping-kernel launch of the call, for
+   * i < n_timing_events / 2 (later launches are not instrumented).  The
+   * events bracket the stepping kernel alone, not the tally reduction that
+   * follows it.  The computation is unchanged.  Ignored by it_solve_batch. */
+  void* const* timing_events;
+  int32_t n_timing_events;
+  int32_t reserved0;
 } it_exec;
 
 /* Time step of a run: dt_safety times the smaller of

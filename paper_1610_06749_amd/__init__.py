@@ -11,4 +11,4 @@ from .binding import (IT_EHIP, IT_EINVAL, IT_ENODT, IT_ENOTSUP, IT_EWORKSPACE, I
                       it_advance, it_dt, it_solve, it_solve_batch, it_strerror, it_validate, it_workspace_size,
                       it_workspace_size_batch, lib, IT_MLP_PARAMS, it_mlp_model_bytes, it_mlp_init,
                       it_mlp_grad, it_mlp_train, it_mlp_query, it_mlp_baseline,
-                      workspace)
+                      workspace, KernelTimer)

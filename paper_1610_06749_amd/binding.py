@@ -50,7 +50,9 @@ class it_result(ctypes.Structure):
 
 class it_exec(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("tile_y", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32)]
 
 
 _lib = None
@@ -125,6 +127,10 @@ def _exec(ex):
     e = it_exec()
     for k in ("kernel", "steps_per_pass", "tile_y", "check_every"):
         setattr(e, k, int(ex.get(k, 0)))
+    tev = ex.get("timing_events")
+    if tev is not None:  # a KernelTimer
+        e.timing_events = tev.handles
+        e.n_timing_events = len(tev.handles)
     return ctypes.byref(e)
 
 
@@ -156,6 +162,43 @@ def it_workspace_size(ch, ntracks: int) -> int:
     _check(lib().it_workspace_size(ctypes.byref(_chamber(ch)), int(ntracks), ctypes.byref(out)),
            "it_workspace_size")
     return out.value
+
+
+class KernelTimer:
+    """Timing events for the stepping kernel: pass as ``exec["timing_events"]``
+    to it_solve / it_advance; the library records a pair around each of the
+    first ``launches`` stepping-kernel launches of the call.  ``durations()``
+    returns the measured kernel times in seconds (after the call returned)."""
+
+    def __init__(self, launches):
+        L = lib()
+        self._L = L
+        L.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        L.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.handles = (ctypes.c_void_p * (2 * int(launches)))()
+        for k in range(2 * int(launches)):
+            h = ctypes.c_void_p()
+            if L.hipEventCreateWithFlags(ctypes.byref(h), 0) != 0:
+                raise RuntimeError("hipEventCreateWithFlags failed")
+            self.handles[k] = h
+
+    def durations(self):
+        out = []
+        ms = ctypes.c_float()
+        for k in range(0, len(self.handles), 2):
+            if self._L.hipEventSynchronize(self.handles[k + 1]) != 0:
+                raise RuntimeError("hipEventSynchronize failed")
+            if self._L.hipEventElapsedTime(ctypes.byref(ms), self.handles[k], self.handles[k + 1]) != 0:
+                break  # launches beyond the ones the call issued were not recorded
+            out.append(ms.value * 1e-3)
+        return np.array(out)
+
+    def __del__(self):
+        for h in getattr(self, "handles", []):
+            if h:
+                self._L.hipEventDestroy(h)
 
 
 def workspace(ch, ntracks: int, device="cuda"):

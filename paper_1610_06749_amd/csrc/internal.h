@@ -97,7 +97,10 @@ struct BatchInstance {
 
 // Launchers (stream-ordered, no synchronisation).
 int plain_tile_rows(int tile_y);
-hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s);
+// ev_begin / ev_end (may be null) are recorded around the stepping kernel
+// alone, before the tally reduction is launched.
+hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin = nullptr,
+                             hipEvent_t ev_end = nullptr);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int parity,

@@ -209,7 +209,8 @@ void blocked_tiling(int nx, int ny, int nz, int T, int tile_y, int* grid, int* p
   if (zchunks_out) *zchunks_out = zchunks;
 }
 
-hipError_t launch_step_blocked(const StepParams& p0, int T, int tile_y, hipStream_t s) {
+hipError_t launch_step_blocked(const StepParams& p0, int T, int tile_y, hipStream_t s, hipEvent_t ev_begin,
+                               hipEvent_t ev_end) {
   StepParams p = p0;
   int grid, per, tx, ty, nt, zc, zch;
   blocked_tiling(p.nx, p.ny, p.nz, T, tile_y, &grid, &per, &tx, &ty, &nt, &zc, &zch);
@@ -220,6 +221,8 @@ hipError_t launch_step_blocked(const StepParams& p0, int T, int tile_y, hipStrea
   p.ntiles = nt;
   p.per_xcd = per;
   const dim3 block(kEX, kEY);
+  if (T < 2 || T > 5) return hipErrorInvalidValue;
+  if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
   switch (T) {
     case 2: hipLaunchKernelGGL(step_blocked_kernel<2>, dim3(grid), block, 0, s, p); break;
     case 3: hipLaunchKernelGGL(step_blocked_kernel<3>, dim3(grid), block, 0, s, p); break;
@@ -229,6 +232,7 @@ hipError_t launch_step_blocked(const StepParams& p0, int T, int tile_y, hipStrea
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (ev_end && hipEventRecord(ev_end, s) != hipSuccess) return hipErrorInvalidValue;
   return launch_reduce_steps(p, grid, T, s);
 }
 

@@ -45,14 +45,17 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
 
 int plain_tile_rows(int tile_y) { return tile_y == 16 ? 16 : 8; }
 
-hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s) {
+hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin,
+                             hipEvent_t ev_end) {
   const int grid = 8 * p.per_xcd;
+  if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
   if (plain_tile_rows(tile_y) == 16)
     hipLaunchKernelGGL(step_plain_kernel<16>, dim3(grid), dim3(kTX, 16), 0, s, p);
   else
     hipLaunchKernelGGL(step_plain_kernel<8>, dim3(grid), dim3(kTX, 8), 0, s, p);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (ev_end && hipEventRecord(ev_end, s) != hipSuccess) return hipErrorInvalidValue;
   return launch_reduce_steps(p, grid, 1, s);
 }
 

@@ -11,7 +11,8 @@
 
 namespace it {
 
-hipError_t launch_step_blocked(const StepParams& p, int T, int tile_y, hipStream_t s);
+hipError_t launch_step_blocked(const StepParams& p, int T, int tile_y, hipStream_t s, hipEvent_t ev_begin,
+                               hipEvent_t ev_end);
 int blocked_supported(int T, int tile_y);
 void blocked_tiling(int nx, int ny, int nz, int T, int tile_y, int* grid, int* per_xcd,
                     int* tiles_x, int* tiles_y, int* ntiles, int* zc, int* zchunks);
@@ -293,6 +294,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   if (T < 1 || T > kMaxT) return IT_EINVAL;
   if (T > 1 && !blocked_supported(T, tile_y)) return IT_ENOTSUP;
   int64_t check_every = ex && ex->check_every > 0 ? ex->check_every : 64;
+  const int n_timing = ex && ex->timing_events ? std::max(ex->n_timing_events, 0) / 2 : 0;
 
   double* field[4];
   for (int f = 0; f < 4; ++f) field[f] = (double*)(ws + L.off_field[f]);
@@ -355,6 +357,10 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   int issued = 0;
   int64_t since_check = 0;
   int pending = 0, slot_head = 0;
+  // caller's timing events of the launch about to be issued (null when none)
+  auto ev_pair = [&](int which) -> hipEvent_t {
+    return issued < n_timing ? (hipEvent_t)ex->timing_events[2 * issued + which] : nullptr;
+  };
   hipEvent_t evs[4];
   for (int q = 0; q < 4; ++q)
     if (hipEventCreateWithFlags(&evs[q], hipEventDisableTiming) != hipSuccess) {
@@ -395,9 +401,9 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       sp.zc = tp.zc;
       sp.ntiles = tp.ntiles;
       sp.per_xcd = tp.per_xcd;
-      e = launch_step_plain(sp, tile_y, stream);
+      e = launch_step_plain(sp, tile_y, stream, ev_pair(0), ev_pair(1));
     } else {
-      e = launch_step_blocked(sp, (int)todo, tile_y, stream);
+      e = launch_step_blocked(sp, (int)todo, tile_y, stream, ev_pair(0), ev_pair(1));
     }
     if (e != hipSuccess) { fail(IT_EHIP); break; }
     ++issued;
@@ -812,34 +818,54 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       HIP_TRY(launch_deposit(dp, stream));
     }
   }
-  HIP_TRY(hipMemcpyAsync(ws + B.off_table, table.data(), (size_t)ninst * sizeof(BatchInstance),
-                         hipMemcpyHostToDevice, stream));
-
-  // Capture `passes_per_graph` passes (step launch + reduction launch each)
-  // on a private stream and replay the graph on the caller's stream.
+  // The pass chain runs on the tile list of the running instances only: the
+  // table is rebuilt (and the graph re-captured) whenever a quarter of its
+  // instances have stopped, so finished chambers cost no dispatches.  All
+  // running instances have executed the same number of passes, so they
+  // share the field parity and a rebuilt table keeps the graph's pattern.
+  RunState* host = pinned_states(ninst);
   hipStream_t cs = capture_stream();
-  if (!cs) return IT_EHIP;
+  if (!host || !cs) return IT_EHIP;
+  std::vector<int> active(ninst);
+  for (int q = 0; q < ninst; ++q) active[q] = q;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec_graph = nullptr;
-  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  hipError_t ce = hipSuccess;
-  for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-    ce = launch_batch_pass(ws + B.off_table, ninst, total_tiles, tile_y, k & 1, cs);
-  const hipError_t ee = hipStreamEndCapture(cs, &graph);
-  if (ce != hipSuccess || ee != hipSuccess) {
+  auto release_graph = [&]() {
+    if (exec_graph) (void)hipGraphExecDestroy(exec_graph);
     if (graph) (void)hipGraphDestroy(graph);
-    return IT_EHIP;
+    exec_graph = nullptr;
+    graph = nullptr;
+  };
+  auto build = [&](int parity0) -> int {
+    std::vector<BatchInstance> t;
+    t.reserve(active.size());
+    int tiles = 0;
+    for (int q : active) {
+      BatchInstance bi = table[q];
+      bi.tile_begin = tiles;
+      tiles += bi.ntiles;
+      t.push_back(bi);
+    }
+    if (hipMemcpyAsync(ws + B.off_table, t.data(), t.size() * sizeof(BatchInstance), hipMemcpyHostToDevice,
+                       stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)  // t is pageable and local
+      return IT_EHIP;
+    release_graph();
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
+      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, tile_y, (parity0 + k) & 1, cs);
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
+    if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;
+    return IT_OK;
+  };
+  rc = build(0);
+  if (rc) {
+    release_graph();
+    return rc;
   }
-  if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return IT_EHIP;
-  }
-  RunState* host = pinned_states(ninst);
-  if (!host) {
-    (void)hipGraphExecDestroy(exec_graph);
-    (void)hipGraphDestroy(graph);
-    return IT_EHIP;
-  }
+  (void)total_tiles;
   // Replays until every instance has stopped; two replays in flight so the
   // GPU never idles on the read-back.
   const int64_t max_replays = (max_steps_all + passes_per_graph - 1) / passes_per_graph;
@@ -847,19 +873,36 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   HIP_TRY(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
   int issued = 0;
+  int64_t replays_since_build = 0;
   rc = IT_OK;
   for (int64_t r = 0; r < max_replays; ++r) {
     if (hipGraphLaunch(exec_graph, stream) != hipSuccess) { rc = IT_EHIP; break; }
     issued += passes_per_graph;
+    ++replays_since_build;
     RunState* slot = host + (r & 1) * ninst;
     if (hipMemcpyAsync(slot, states, (size_t)ninst * sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipEventRecord(evs[r & 1], stream) != hipSuccess) { rc = IT_EHIP; break; }
     if (r >= 1) {
       RunState* prev = host + ((r - 1) & 1) * ninst;
       if (hipEventSynchronize(evs[(r - 1) & 1]) != hipSuccess) { rc = IT_EHIP; break; }
-      bool all = true;
-      for (int q = 0; q < ninst && all; ++q) all = prev[q].done != 0;
-      if (all) break;
+      std::vector<int> still;
+      for (int q : active)
+        if (!prev[q].done) still.push_back(q);
+      if (still.empty()) break;
+      // rebuild only once the replay in flight has finished too, so that no
+      // launch still reads the table being replaced
+      if (4 * still.size() <= 3 * active.size() && replays_since_build >= 2) {
+        if (hipStreamSynchronize(stream) != hipSuccess) { rc = IT_EHIP; break; }
+        RunState* now = host + (r & 1) * ninst;
+        still.clear();
+        for (int q : active)
+          if (!now[q].done) still.push_back(q);
+        if (still.empty()) break;
+        active.swap(still);
+        rc = build((int)(((int64_t)issued) & 1));
+        if (rc) break;
+        replays_since_build = 0;
+      }
     }
   }
   if (rc == IT_OK && (hipMemcpyAsync(host, states, (size_t)ninst * sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -867,8 +910,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     rc = IT_EHIP;
   (void)hipEventDestroy(evs[0]);
   (void)hipEventDestroy(evs[1]);
-  (void)hipGraphExecDestroy(exec_graph);
-  (void)hipGraphDestroy(graph);
+  release_graph();
   if (rc) return rc;
   for (int q = 0; q < ninst; ++q) fill_result(host[q], dts[q], ch[q].max_steps, issued, &out[q]);
   return IT_OK;

@@ -207,3 +207,18 @@ def test_error_paths(gpu):
         gpu.it_solve(ch, tr, ws=small)
     assert e.value.code == gpu.IT_EWORKSPACE
 
+
+
+@pytest.mark.parametrize("ex", [dict(kernel=1, tile_y=16), dict(kernel=2, steps_per_pass=3)],
+                         ids=["plain16", "blocked3"])
+def test_timing_events_leave_results_unchanged(gpu, orc, ex):
+    """Kernel timing events recorded by the library bracket the first
+    launches only and do not change the computation."""
+    ch, tr = ragged_case(max_steps=23, stop_tol=0.0)
+    timer = gpu.KernelTimer(4)
+    g = gpu.it_solve(ch, tr, exec=dict(ex, timing_events=timer), trace=True, fields=True)
+    o = orc.solve(ch, tr, with_trace=True, with_fields=True)
+    compare_results(g, o)
+    compare_fields(g["pos"], o["pos"])
+    d = timer.durations()
+    assert d.shape == (4,) and np.all(d > 0.0) and np.all(d < 1.0)
