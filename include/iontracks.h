@@ -134,7 +134,7 @@ typedef struct {
    * follows it.  The computation is unchanged.  Ignored by it_solve_batch. */
   void* const* timing_events;
   int32_t n_timing_events;
-  int32_t reserved0;
+  int32_t z_chunk;         /* planes per tile of the one-step kernel, 4..512 (0 = default) */
 } it_exec;
 
 /* Time step of a run: dt_safety times the smaller of

@@ -33,12 +33,8 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
   const StepParams& p = inst[q].sp[parity];
   if (p.state->done) return;
   const int l = L - inst[q].tile_begin;
-  TileCoord t;
+  TileCoord t = tile_of(l, p.tiles_x, p.tiles_y);
   t.valid = true;
-  t.tx = l % p.tiles_x;
-  const int rest = l / p.tiles_x;
-  t.zc = rest % p.zchunks;
-  t.ty = rest / p.zchunks;
   plain_tile_step<SY>(p, t, p.partials + (size_t)l * kAcc);
 }
 

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
   __shared__ double lds[(kBNT / kWave) * kAcc * T];
 
   const int lane = threadIdx.x, ty = threadIdx.y;
-  const TileCoord tc = decode_tile(p.tiles_x, p.zchunks, p.ntiles, p.per_xcd);
+  const TileCoord tc = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
   const int x0 = tc.tx * OX, y0 = tc.ty * OY;
   // wrapped position of this column
   int xs = x0 - T + lane, ys = y0 - T + ty;

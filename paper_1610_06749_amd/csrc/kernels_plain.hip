@@ -21,7 +21,7 @@ constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 template <int SY>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(8, 8))) void step_plain_kernel(StepParams p) {
   if (p.state->done) return;  // set by an earlier launch: every block skips
-  plain_tile_step<SY>(p, decode_tile(p.tiles_x, p.zchunks, p.ntiles, p.per_xcd),
+  plain_tile_step<SY>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
                       p.partials + (size_t)blockIdx.x * kAcc);
 }
 
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
   __shared__ double lds[(kNT / kWave) * 2];
   __shared__ double totals[2];
   double sum = 0.0, mx = 0.0;
-  const TileCoord t = decode_tile(p.tiles_x, p.zchunks, p.ntiles, p.per_xcd);
+  const TileCoord t = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
   const int i = t.tx * kTX + threadIdx.x;
   const int j = t.ty * kTY + threadIdx.y;
   if (t.valid && i < p.nx && j < p.ny) {

@@ -158,16 +158,28 @@ struct TileCoord {
   bool valid;
 };
 
-__device__ inline TileCoord decode_tile(int tiles_x, int zchunks, int ntiles, int per_xcd) {
-  const int b = blockIdx.x;
-  const int L = (b & 7) * per_xcd + (b >> 3);
+// Tile l of a tiling with tiles_x x tiles_y columns and zchunks chunks, in
+// the order (chunk, row, column): consecutive tiles are lateral neighbours
+// at the same depth, so a run of them on one XCD shares the rim rows and
+// columns through that XCD's L2 while they march up z together.
+__device__ inline TileCoord tile_of(int l, int tiles_x, int tiles_y) {
   TileCoord t;
-  t.valid = L < ntiles;
-  const int l = t.valid ? L : 0;
   t.tx = l % tiles_x;
   const int rest = l / tiles_x;
-  t.zc = rest % zchunks;
-  t.ty = rest / zchunks;
+  t.ty = rest % tiles_y;
+  t.zc = rest / tiles_y;
+  return t;
+}
+
+// Block -> tile, XCD-aware: the dispatcher deals blocks to the 8 XCDs in
+// turn, so block b runs on XCD b % 8; XCD x gets the contiguous tile run
+// [x * per_xcd, (x + 1) * per_xcd).
+__device__ inline TileCoord decode_tile(int tiles_x, int tiles_y, int ntiles, int per_xcd) {
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per_xcd + (b >> 3);
+  const bool valid = L < ntiles;
+  TileCoord t = tile_of(valid ? L : 0, tiles_x, tiles_y);
+  t.valid = valid;
   return t;
 }
 

@@ -31,6 +31,7 @@ int check_chamber(const it_chamber* ch) {
   if (ch->nx < 1 || ch->ny < 1 || ch->nz < 2 || ch->reserved0 != 0) return IT_EINVAL;
   const double cells = (double)ch->nx * ch->ny * (double)(ch->nz + 1);
   if (cells > 4.0e9) return IT_EINVAL;  // 32-bit tile indices and 64-bit offsets suffice below
+  if ((double)ch->nx * ch->ny > (double)(1 << 28)) return IT_EINVAL;  // in-plane byte offsets fit 32 bits
   if (!(std::isfinite(ch->dx) && ch->dx > 0 && std::isfinite(ch->dy) && ch->dy > 0)) return IT_EINVAL;
   if (!(std::isfinite(ch->gap) && ch->gap > 0)) return IT_EINVAL;
   if (!std::isfinite(ch->voltage)) return IT_EINVAL;
@@ -153,11 +154,36 @@ Tiling make_tiling(int nx, int ny, int nz, int tile_y, int zc) {
   return t;
 }
 
-Tiling step_tiling(int nx, int ny, int nz, int rows) {
+// z_chunk > 0: planes per tile as requested.  0: split every column into
+// equal chunks so that the grid holds about 16 waves per CU (4096 waves on
+// 256 CUs), all resident at once: the launch then takes as long as one
+// chunk, so chunks of equal length and as few chunk starts (each re-reads
+// two planes) as the occupancy allows are what count.
+Tiling step_tiling(int nx, int ny, int nz, int rows, int z_chunk) {
+  if (z_chunk > 0) return make_tiling(nx, ny, nz, rows, z_chunk);
+  const int nint = nz - 1;
   const long cols = (long)((nx + 63) / 64) * ((ny + rows - 1) / rows);
-  int zc = 32;
-  while (zc > 4 && cols * ((nz - 1 + zc - 1) / zc) < 512) zc /= 2;
+  const long target = 4096 / rows;  // tiles of `rows` waves
+  long chunks = std::max<long>(1, (target + cols / 2) / cols);
+  chunks = std::min<long>(chunks, std::max(1, nint / 4));  // at least 4 planes per chunk
+  const int zc = (int)((nint + chunks - 1) / chunks);
   return make_tiling(nx, ny, nz, rows, zc);
+}
+
+// Rows of the one-step kernel's tiles: 8 or 16 as requested, else 16 unless
+// the grid has fewer than 16 rows.
+int resolve_rows(int tile_y, int ny) {
+  if (tile_y == 8 || tile_y == 16) return tile_y;
+  return ny >= 16 ? 16 : 8;
+}
+
+constexpr int kMinZChunk = 4, kMaxZChunk = 512;
+
+int exec_z_chunk(const it_exec* ex) { return ex ? ex->z_chunk : 0; }
+
+bool z_chunk_ok(const it_exec* ex) {
+  const int z = exec_z_chunk(ex);
+  return z == 0 || (z >= kMinZChunk && z <= kMaxZChunk);
 }
 
 Tiling deposit_tiling(int nx, int ny, int nz) {
@@ -182,7 +208,8 @@ struct Layout {
 };
 
 size_t max_grid(const it_chamber* ch) {
-  size_t g = std::max((size_t)step_tiling(ch->nx, ch->ny, ch->nz, 8).grid,
+  // the smallest z chunk gives the most stepping blocks of any launch shape
+  size_t g = std::max((size_t)step_tiling(ch->nx, ch->ny, ch->nz, 8, kMinZChunk).grid,
                       (size_t)deposit_tiling(ch->nx, ch->ny, ch->nz).grid);
   for (int T = 2; T <= kMaxT; ++T) {
     if (!blocked_supported(T, 0)) continue;
@@ -308,7 +335,9 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const Coef cp = species_coef(ch, dt, 0), cn = species_coef(ch, dt, 1);
   const double dz = ch->gap / ch->nz;
   const double dV = ch->dx * ch->dy * dz;
-  const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, plain_tile_rows(tile_y));
+  if (!z_chunk_ok(ex)) return IT_EINVAL;
+  const int rows = resolve_rows(tile_y, ch->ny);
+  const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, rows, exec_z_chunk(ex));
   const Tiling td = deposit_tiling(ch->nx, ch->ny, ch->nz);
 
   RunState* slots = pinned_slots();
@@ -401,7 +430,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       sp.zc = tp.zc;
       sp.ntiles = tp.ntiles;
       sp.per_xcd = tp.per_xcd;
-      e = launch_step_plain(sp, tile_y, stream, ev_pair(0), ev_pair(1));
+      e = launch_step_plain(sp, rows, stream, ev_pair(0), ev_pair(1));
     } else {
       e = launch_step_blocked(sp, (int)todo, tile_y, stream, ev_pair(0), ev_pair(1));
     }
@@ -457,7 +486,14 @@ struct BatchLayout {
   size_t total;
 };
 
-BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows) {
+// One tile shape serves every instance of a batch.
+int batch_rows(const it_chamber* ch, int ninst, const it_exec* exec) {
+  int min_ny = ch[0].ny;
+  for (int q = 1; q < ninst; ++q) min_ny = std::min(min_ny, ch[q].ny);
+  return resolve_rows(exec ? exec->tile_y : 0, min_ny);
+}
+
+BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows, int z_chunk) {
   BatchLayout B;
   size_t off = 0;
   B.inst.resize(ninst);
@@ -469,7 +505,7 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
       L.off_field[f] = off;
       off = align_up(off + L.field_elems * sizeof(double));
     }
-    const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows);
+    const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows, z_chunk);
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.ntiles = ts.ntiles;
     L.off_partials = off;
@@ -698,8 +734,9 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
     if (rc) return rc;
     if (track_offsets[q + 1] < track_offsets[q]) return IT_EINVAL;
   }
-  const int rows = plain_tile_rows(exec ? exec->tile_y : 0);
-  *bytes = make_batch_layout(ch, track_offsets, ninst, rows).total;
+  if (!z_chunk_ok(exec)) return IT_EINVAL;
+  const int rows = batch_rows(ch, ninst, exec);
+  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, exec_z_chunk(exec)).total;
   return IT_OK;
 }
 
@@ -709,11 +746,11 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   if (!out) return IT_EINVAL;
   int rc = check_batch(ch, track_offsets, tracks, ninst);
   if (rc) return rc;
-  const int tile_y = exec ? exec->tile_y : 0;
-  const int rows = plain_tile_rows(tile_y);
+  const int rows = batch_rows(ch, ninst, exec);
   int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
-  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows);
+  if (!z_chunk_ok(exec)) return IT_EINVAL;
+  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, exec_z_chunk(exec));
   if (!d_workspace || ws_bytes < B.total) return IT_EWORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
   char* ws = (char*)d_workspace;
@@ -746,7 +783,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 
     const Coef cp = species_coef(c, dts[q], 0), cn = species_coef(c, dts[q], 1);
     const double dz = c->gap / c->nz, dV = c->dx * c->dy * dz;
-    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows);
+    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows, exec_z_chunk(exec));
     const Tiling td = deposit_tiling(c->nx, c->ny, c->nz);
     BatchInstance& bi = table[q];
     for (int par = 0; par < 2; ++par) {
@@ -854,7 +891,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
     hipError_t ce = hipSuccess;
     for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, tile_y, (parity0 + k) & 1, cs);
+      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, (parity0 + k) & 1, cs);
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
     if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;

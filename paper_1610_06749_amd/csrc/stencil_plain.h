@@ -9,6 +9,23 @@ namespace it {
 
 constexpr int kTX = 64;
 
+// Global-memory byte pointer.
+typedef __attribute__((address_space(1))) char gchar;
+
+// A wave-uniform global pointer held in scalar registers.
+__device__ inline gchar* uniform_ptr(const void* ptr) {
+  const uint64_t v = (uint64_t)ptr;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gchar*)(((uint64_t)hi << 32) | lo);
+}
+
+// Per-plane work of the tile step: the own column's values at k-1, k, k+1
+// are in registers, plane k of the tile with its one-node rim in LDS.
+struct PlaneRegs {
+  double p, n;
+};
+
 // Stepping tile: 64 x SY columns (SY = 8 or 16 rows, one wave per row).
 // LDS holds plane k of the tile with a one-node rim: interior (r, x) sits at
 // [r + 1][x + 1]; the rim column/row that follows the last valid column/row
@@ -16,10 +33,16 @@ constexpr int kTX = 64;
 // holds the periodic neighbour, so every active node reads its four lateral
 // neighbours from LDS at fixed offsets.  Waves 0-3 load the rim from global
 // memory (wave-uniform branches), all other loads are unconditional.
+//
+// Pipelining: plane k+2 of the own column is requested while plane k is
+// computed, so two planes of loads are in flight per thread.  The LDS plane is double-buffered, so one barrier per plane
+// suffices: buffer k&1 is rewritten at plane k+2, after every thread has
+// passed the barrier of plane k+1 and hence finished reading plane k.  The
+// barrier orders LDS only; it does not wait for the global loads in flight.
 template <int SY>
 __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, double* partial_out) {
   constexpr int kSNT = kTX * SY;
-  __shared__ double sp[SY + 2][kTX + 2], sn[SY + 2][kTX + 2];
+  __shared__ double sp[2][SY + 2][kTX + 2], sn[2][SY + 2][kTX + 2];
   __shared__ double lds[(kSNT / kWave) * kAcc];
   // per-wave sums of n on the planes next to the electrodes (slots 1-4)
   __shared__ double edge[SY][4];
@@ -35,8 +58,9 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   const int w = min(kTX, p.nx - x0), h = min(SY, p.ny - y0);  // valid extent of the tile
   const int i = x0 + lane, j = y0 + ty;
   const bool active = t.valid && lane < w && ty < h;
+  const int nz = p.nz;
   const int k0 = 1 + t.zc * p.zc;
-  const int k1 = t.valid ? min(k0 + p.zc, p.nz) : k0;
+  const int k1 = t.valid ? min(k0 + p.zc, nz) : k0;
   const size_t plane = (size_t)p.nx * p.ny;
   const int ic = min(i, p.nx - 1), jc = min(j, p.ny - 1);
   // rim sources (periodic wraps)
@@ -44,81 +68,99 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   const int i_right = x0 + w == p.nx ? 0 : x0 + w;
   const int j_top = y0 == 0 ? p.ny - 1 : y0 - 1;
   const int j_bot = y0 + h == p.ny ? 0 : y0 + h;
-  const double* __restrict__ pin = p.pin;
-  const double* __restrict__ nin = p.nin;
-  double* __restrict__ pout = p.pout;
-  double* __restrict__ nout = p.nout;
   const Coef cp = p.cp, cn = p.cn;
   const double beta = p.beta;
-  const size_t own = (size_t)jc * p.nx + ic;
+  // in-plane byte offsets (a plane holds at most 2^28 nodes, checked on the
+  // host, so they fit 32 bits and the loads take a scalar base address)
+  const unsigned own = (unsigned)(jc * p.nx + ic) * 8u;
   // rim element this thread loads (if any): waves 0/1 rows, waves 2/3 columns
-  size_t rim_off = 0;
+  unsigned rim_off = 0;
   int rim_r = -1, rim_c = -1;
-  if (ty == 0 && lane < w) { rim_off = (size_t)j_top * p.nx + i; rim_r = 0; rim_c = lane + 1; }
-  if (ty == 1 && lane < w) { rim_off = (size_t)j_bot * p.nx + i; rim_r = h + 1; rim_c = lane + 1; }
-  if (ty == 2 && lane < h) { rim_off = (size_t)(y0 + lane) * p.nx + i_left; rim_r = lane + 1; rim_c = 0; }
-  if (ty == 3 && lane < h) { rim_off = (size_t)(y0 + lane) * p.nx + i_right; rim_r = lane + 1; rim_c = w + 1; }
+  if (ty == 0 && lane < w) { rim_off = (unsigned)(j_top * p.nx + i) * 8u; rim_r = 0; rim_c = lane + 1; }
+  if (ty == 1 && lane < w) { rim_off = (unsigned)(j_bot * p.nx + i) * 8u; rim_r = h + 1; rim_c = lane + 1; }
+  if (ty == 2 && lane < h) { rim_off = (unsigned)((y0 + lane) * p.nx + i_left) * 8u; rim_r = lane + 1; rim_c = 0; }
+  if (ty == 3 && lane < h) { rim_off = (unsigned)((y0 + lane) * p.nx + i_right) * 8u; rim_r = lane + 1; rim_c = w + 1; }
   const bool rim = t.valid && rim_r >= 0;
-
-  // Loads and arithmetic run unpredicated on clamped addresses (inactive
-  // lanes compute values nobody uses); only LDS interior writes, stores and
-  // tallies depend on `active`.  This keeps the loop free of divergent
-  // branches around loads, so the compiler can overlap them.
   const double am = active ? 1.0 : 0.0;
-  const size_t own_k0 = (size_t)k0 * plane + own;
-  double pm = pin[own_k0 - plane], pc = pin[own_k0];
-  double nm = nin[own_k0 - plane], nc = nin[own_k0];
-  for (int k = k0; k < k1; ++k) {
-    const size_t base = (size_t)k * plane;
-    const size_t c = base + own;
-    const double pp = pin[c + plane], np = nin[c + plane];  // plane k+1 <= nz
-    if (rim) {
-      sp[rim_r][rim_c] = pin[base + rim_off];
-      sn[rim_r][rim_c] = nin[base + rim_off];
+
+  // plane pointers are block-uniform and pinned to scalar registers (else
+  // the compiler turns them into per-thread 64-bit induction variables);
+  // threads add their 32-bit in-plane byte offset
+  auto in_p = [&](int k) { return uniform_ptr(p.pin + (size_t)k * plane); };
+  auto in_n = [&](int k) { return uniform_ptr(p.nin + (size_t)k * plane); };
+  auto ld = [](const gchar* base, unsigned off) {
+    return *(const __attribute__((address_space(1))) double*)(base + off);
+  };
+
+  // One plane.  (m, c, q1): own column at k-1, k, k+1; q2 receives k+2.
+  auto plane_step = [&](int k, int buf, const PlaneRegs& m, const PlaneRegs& c, const PlaneRegs& q1,
+                        PlaneRegs& q2) {
+    const int k2 = min(k + 2, nz);  // plane nz exists (the cathode, zero)
+    q2.p = ld(in_p(k2), own);
+    q2.n = ld(in_n(k2), own);
+    if (rim) {  // (prefetching the rim too would exceed 64 VGPRs and halve the occupancy)
+      sp[buf][rim_r][rim_c] = ld(in_p(k), rim_off);
+      sn[buf][rim_r][rim_c] = ld(in_n(k), rim_off);
     }
     if (active) {  // inactive threads must not touch the rim slots past the valid extent
-      sp[ty + 1][lane + 1] = pc;
-      sn[ty + 1][lane + 1] = nc;
+      sp[buf][ty + 1][lane + 1] = c.p;
+      sn[buf][ty + 1][lane + 1] = c.n;
     }
-    __syncthreads();
-    const double pxl = sp[ty + 1][lane], pxr = sp[ty + 1][lane + 2];
-    const double pyl = sp[ty][lane + 1], pyr = sp[ty + 2][lane + 1];
-    const double nxl = sn[ty + 1][lane], nxr = sn[ty + 1][lane + 2];
-    const double nyl = sn[ty][lane + 1], nyr = sn[ty + 2][lane + 1];
-    const double sink = beta * pc * nc;
-    const double vp = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * pp +
-                      cp.azm * pm - sink;
-    const double vn = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * np +
-                      cn.azm * nm - sink;
+    lds_barrier();
+    const double pxl = sp[buf][ty + 1][lane], pxr = sp[buf][ty + 1][lane + 2];
+    const double pyl = sp[buf][ty][lane + 1], pyr = sp[buf][ty + 2][lane + 1];
+    const double nxl = sn[buf][ty + 1][lane], nxr = sn[buf][ty + 1][lane + 2];
+    const double nyl = sn[buf][ty][lane + 1], nyr = sn[buf][ty + 2][lane + 1];
+    const double sink = beta * c.p * c.n;
+    const double vp = cp.a0 * c.p + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * q1.p +
+                      cp.azm * m.p - sink;
+    const double vn = cn.a0 * c.n + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * q1.n +
+                      cn.azm * m.n - sink;
     if (active) {
-      __builtin_nontemporal_store(vp, &pout[c]);
-      __builtin_nontemporal_store(vn, &nout[c]);
+      const size_t o = (size_t)k * plane;
+      __builtin_nontemporal_store(vp, (__attribute__((address_space(1))) double*)(uniform_ptr(p.pout + o) + own));
+      __builtin_nontemporal_store(vn, (__attribute__((address_space(1))) double*)(uniform_ptr(p.nout + o) + own));
     }
     acc[0] += am * sink;
     acc[5] += am * vp;
     acc[6] += am * vn;
     acc[7] += am * fabs(vp);
     acc[8] += am * fabs(vn);
-    if (k == 1 || k == p.nz - 1) {  // uniform over the block
-      const double sp_ = wave_sum(am * pc), sn_ = wave_sum(am * nc);
+    if (k == 1 || k == nz - 1) {  // uniform over the block
+      const double sp_ = wave_sum(am * c.p), sn_ = wave_sum(am * c.n);
       if (lane == 0) {
         if (k == 1) {  // anode side
           edge[ty][0] += sp_;
           edge[ty][2] += sn_;
         }
-        if (k == p.nz - 1) {  // cathode side (the same plane when nz = 2)
+        if (k == nz - 1) {  // cathode side (the same plane when nz = 2)
           edge[ty][1] += sp_;
           edge[ty][3] += sn_;
         }
       }
     }
-    __syncthreads();
-    pm = pc;
-    pc = pp;
-    nm = nc;
-    nc = np;
+  };
+
+  // Registers rotate with period 4; the loop is unrolled by 4 so that no
+  // value is moved between registers while its load may still be in flight.
+  PlaneRegs r0, r1, r2, r3;
+  r0.p = ld(in_p(k0 - 1), own);
+  r0.n = ld(in_n(k0 - 1), own);
+  r1.p = ld(in_p(k0), own);
+  r1.n = ld(in_n(k0), own);
+  r2.p = ld(in_p(k0 + 1), own);  // k0 + 1 <= nz
+  r2.n = ld(in_n(k0 + 1), own);
+  for (int k = k0; k < k1; k += 4) {
+    plane_step(k, 0, r0, r1, r2, r3);
+    if (k + 1 >= k1) break;
+    plane_step(k + 1, 1, r1, r2, r3, r0);
+    if (k + 2 >= k1) break;
+    plane_step(k + 2, 0, r2, r3, r0, r1);
+    if (k + 3 >= k1) break;
+    plane_step(k + 3, 1, r3, r0, r1, r2);
   }
 
+  __syncthreads();  // edge sums of the last plane
   if (lane == 0) {  // the electrode-plane sums enter the block reduction per wave
     acc[1] = edge[ty][0];
     acc[2] = edge[ty][1];

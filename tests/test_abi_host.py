@@ -74,6 +74,20 @@ def test_workspace_size_covers_fields_and_trace(lib):
     assert lib.it_workspace_size(dict(ch, max_steps=10), 400) < n
 
 
+def test_launch_shape_checks(lib):
+    chs, trs = W.batched_sweep(ninst=3)
+    base = lib.it_workspace_size_batch(chs, trs)
+    assert lib.it_workspace_size_batch(chs, trs, dict(z_chunk=4)) >= base  # more tiles, more partials
+    for z in (1, 3, 513, -2):
+        with pytest.raises(lib.ItError) as e:
+            lib.it_workspace_size_batch(chs, trs, dict(z_chunk=z))
+        assert e.value.code == lib.IT_EINVAL
+    # in-plane offsets are 32-bit byte offsets: planes above 2^28 nodes are refused
+    with pytest.raises(lib.ItError) as e:
+        lib.it_validate(W.chamber(1 << 15, 1 << 14, 2, 1e-4, 2e-4, 10.0), np.zeros((0, 7)))
+    assert e.value.code == lib.IT_EINVAL
+
+
 def test_strerror_names_codes(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.it_strerror(code) and lib.it_strerror(code) != "unknown status code"

@@ -17,9 +17,9 @@ RTOL = 1e-9
 
 # every stepping kernel the library offers: the one-step kernel with both
 # tile shapes, and the temporally blocked kernel at each supported depth
-EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16)] + \
+EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5)] + \
     [dict(kernel=2, steps_per_pass=T) for T in (2, 3, 4, 5)]
-EXEC_IDS = ["plain8", "plain16", "blocked2", "blocked3", "blocked4", "blocked5"]
+EXEC_IDS = ["plain8", "plain16", "plain8z5", "blocked2", "blocked3", "blocked4", "blocked5"]
 
 
 @pytest.fixture(scope="module")
