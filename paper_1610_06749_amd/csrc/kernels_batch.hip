@@ -23,7 +23,7 @@ __device__ inline int find_instance(const BatchInstance* inst, int ninst, int L)
 }
 
 template <int SY>
-__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                        int parity) {
   const int b = blockIdx.x;

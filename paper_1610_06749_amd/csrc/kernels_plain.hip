@@ -19,7 +19,7 @@ namespace it {
 constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 
 template <int SY>
-__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(8, 8))) void step_plain_kernel(StepParams p) {
+__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_plain_kernel(StepParams p) {
   if (p.state->done) return;  // set by an earlier launch: every block skips
   plain_tile_step<SY>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
                       p.partials + (size_t)blockIdx.x * kAcc);

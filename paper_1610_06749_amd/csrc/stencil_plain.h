@@ -34,8 +34,10 @@ struct PlaneRegs {
 // neighbours from LDS at fixed offsets.  Waves 0-3 load the rim from global
 // memory (wave-uniform branches), all other loads are unconditional.
 //
-// Pipelining: plane k+2 of the own column is requested while plane k is
-// computed, so two planes of loads are in flight per thread.  The LDS plane is double-buffered, so one barrier per plane
+// Pipelining: plane k+2 of the own column and the rim of plane k+1 are
+// requested while plane k is computed, so two planes of loads are in flight
+// per thread (about 78 VGPRs: six waves per SIMD, more than the 16 waves per
+// CU the default tiling places).  The LDS plane is double-buffered, so one barrier per plane
 // suffices: buffer k&1 is rewritten at plane k+2, after every thread has
 // passed the barrier of plane k+1 and hence finished reading plane k.  The
 // barrier orders LDS only; it does not wait for the global loads in flight.
@@ -83,9 +85,8 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   const bool rim = t.valid && rim_r >= 0;
   const double am = active ? 1.0 : 0.0;
 
-  // plane pointers are block-uniform and pinned to scalar registers (else
-  // the compiler turns them into per-thread 64-bit induction variables);
-  // threads add their 32-bit in-plane byte offset
+  // plane pointers are block-uniform (scalar registers); threads add their
+  // 32-bit in-plane byte offset
   auto in_p = [&](int k) { return uniform_ptr(p.pin + (size_t)k * plane); };
   auto in_n = [&](int k) { return uniform_ptr(p.nin + (size_t)k * plane); };
   auto ld = [](const gchar* base, unsigned off) {
@@ -93,14 +94,17 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   };
 
   // One plane.  (m, c, q1): own column at k-1, k, k+1; q2 receives k+2.
+  // rc: rim values of plane k; rn receives the rim of plane k+1.
   auto plane_step = [&](int k, int buf, const PlaneRegs& m, const PlaneRegs& c, const PlaneRegs& q1,
-                        PlaneRegs& q2) {
+                        PlaneRegs& q2, const PlaneRegs& rc, PlaneRegs& rn) {
     const int k2 = min(k + 2, nz);  // plane nz exists (the cathode, zero)
     q2.p = ld(in_p(k2), own);
     q2.n = ld(in_n(k2), own);
-    if (rim) {  // (prefetching the rim too would exceed 64 VGPRs and halve the occupancy)
-      sp[buf][rim_r][rim_c] = ld(in_p(k), rim_off);
-      sn[buf][rim_r][rim_c] = ld(in_n(k), rim_off);
+    if (rim) {
+      rn.p = ld(in_p(k + 1), rim_off);
+      rn.n = ld(in_n(k + 1), rim_off);
+      sp[buf][rim_r][rim_c] = rc.p;
+      sn[buf][rim_r][rim_c] = rc.n;
     }
     if (active) {  // inactive threads must not touch the rim slots past the valid extent
       sp[buf][ty + 1][lane + 1] = c.p;
@@ -141,9 +145,15 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
     }
   };
 
-  // Registers rotate with period 4; the loop is unrolled by 4 so that no
-  // value is moved between registers while its load may still be in flight.
-  PlaneRegs r0, r1, r2, r3;
+  // Registers rotate with period 4 (own column) and 2 (rim); the loop is
+  // unrolled by 4 so that no value is moved between registers while its
+  // load may still be in flight.
+  PlaneRegs r0, r1, r2, r3, ra, rb;
+  ra.p = ra.n = rb.p = rb.n = 0.0;
+  if (rim) {
+    ra.p = ld(in_p(k0), rim_off);
+    ra.n = ld(in_n(k0), rim_off);
+  }
   r0.p = ld(in_p(k0 - 1), own);
   r0.n = ld(in_n(k0 - 1), own);
   r1.p = ld(in_p(k0), own);
@@ -151,13 +161,13 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   r2.p = ld(in_p(k0 + 1), own);  // k0 + 1 <= nz
   r2.n = ld(in_n(k0 + 1), own);
   for (int k = k0; k < k1; k += 4) {
-    plane_step(k, 0, r0, r1, r2, r3);
+    plane_step(k, 0, r0, r1, r2, r3, ra, rb);
     if (k + 1 >= k1) break;
-    plane_step(k + 1, 1, r1, r2, r3, r0);
+    plane_step(k + 1, 1, r1, r2, r3, r0, rb, ra);
     if (k + 2 >= k1) break;
-    plane_step(k + 2, 0, r2, r3, r0, r1);
+    plane_step(k + 2, 0, r2, r3, r0, r1, ra, rb);
     if (k + 3 >= k1) break;
-    plane_step(k + 3, 1, r3, r0, r1, r2);
+    plane_step(k + 3, 1, r3, r0, r1, r2, rb, ra);
   }
 
   __syncthreads();  // edge sums of the last plane
