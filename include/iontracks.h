@@ -248,13 +248,20 @@ int it_mlp_train_ws_bytes(int32_t members, int64_t n, size_t* bytes);
 int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n,
                 float* d_grad, float* h_loss, void* d_workspace, size_t ws_bytes, void* stream);
 
-/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, rate lr)
- * of every member on (d_X, d_t); the BF16 copies follow each update.
- * h_loss: NULL or host [ceil(steps/log_every)][members], the loss before
- * every log_every-th step.  Synchronises `stream`.
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) of every member on
+ * (d_X [n][6], d_t [n]), device buffers.  batch: rows per step (0 = all n);
+ * n must be a multiple of it, and step s (counted over the model's life)
+ * uses rows [(s mod n/batch) * batch, ... + batch), so the caller shuffles
+ * the data once beforehand.  The learning rate decays from lr to lr_final
+ * along a half cosine over the steps of the call (lr_final = lr: constant).
+ * The BF16 copies follow each update.  Workspace: it_mlp_train_ws_bytes for
+ * `batch` rows (n when batch is 0).  h_loss: NULL or host
+ * [ceil(steps/log_every)][members], the minibatch loss before every
+ * log_every-th step.  Synchronises `stream`.
  * Errors: IT_EINVAL, IT_EWORKSPACE, IT_EHIP. */
-int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int32_t steps,
-                 float lr, int32_t log_every, float* h_loss, void* d_workspace, size_t ws_bytes, void* stream);
+int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int64_t batch,
+                 int32_t steps, float lr, float lr_final, int32_t log_every, float* h_loss, void* d_workspace,
+                 size_t ws_bytes, void* stream);
 
 /* Device workspace bytes of it_mlp_query for nq queries. */
 int it_mlp_query_ws_bytes(int64_t nq, size_t* bytes);

@@ -87,8 +87,8 @@ def lib():
         L.it_mlp_baseline.argtypes = [vp, vp, i64, vp, vp]
         L.it_mlp_train_ws_bytes.argtypes = [ctypes.c_int32, i64, szp]
         L.it_mlp_grad.argtypes = [vp, ctypes.c_int32, vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
-        L.it_mlp_train.argtypes = [vp, ctypes.c_int32, vp, vp, i64, ctypes.c_int32, ctypes.c_float,
-                                   ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
+        L.it_mlp_train.argtypes = [vp, ctypes.c_int32, vp, vp, i64, i64, ctypes.c_int32, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
         L.it_mlp_query_ws_bytes.argtypes = [i64, szp]
         L.it_mlp_query.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance",
@@ -350,14 +350,18 @@ def it_mlp_grad(model, members, X, t, stream=None):
     return grad, loss
 
 
-def it_mlp_train(model, members, X, t, steps, lr, log_every=0, stream=None):
+def it_mlp_train(model, members, X, t, steps, lr, log_every=0, stream=None, batch=0, lr_final=None):
+    """Adam steps on device data (X [n, 6], t [n]); minibatches of ``batch``
+    rows (0 = full batch), learning rate decaying from lr to lr_final (a
+    half cosine; None = constant).  Returns the logged losses."""
     n = X.shape[0]
-    ws = _train_ws(members, n, X.device)
+    ws = _train_ws(members, batch or n, X.device)
     nlog = (steps + log_every - 1) // log_every if log_every > 0 else 0
     loss = np.zeros((max(nlog, 1), members), dtype=np.float32)
-    _check(lib().it_mlp_train(_dptr(model), int(members), _dptr(X), _dptr(t), int(n), int(steps), float(lr),
-                              int(log_every), loss.ctypes.data if nlog else None, _dptr(ws), ws.numel(),
-                              _stream(stream)), "it_mlp_train")
+    _check(lib().it_mlp_train(_dptr(model), int(members), _dptr(X), _dptr(t), int(n), int(batch), int(steps),
+                              float(lr), float(lr if lr_final is None else lr_final), int(log_every),
+                              loss.ctypes.data if nlog else None, _dptr(ws), ws.numel(), _stream(stream)),
+           "it_mlp_train")
     return loss[:nlog]
 
 

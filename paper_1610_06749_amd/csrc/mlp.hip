@@ -586,28 +586,41 @@ int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const fl
   return hipStreamSynchronize(s) == hipSuccess ? IT_OK : IT_EHIP;
 }
 
-int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int32_t steps,
-                 float lr, int32_t log_every, float* h_loss, void* d_ws, size_t ws_bytes, void* stream_) {
-  if (!d_model || !d_X || !d_t || n < 1 || steps < 0 || members < 1 || members > 64 || !(lr > 0.0f))
+int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int64_t batch,
+                 int32_t steps, float lr, float lr_final, int32_t log_every, float* h_loss, void* d_ws,
+                 size_t ws_bytes, void* stream_) {
+  if (!d_model || !d_X || !d_t || n < 1 || steps < 0 || members < 1 || members > 64 || !(lr > 0.0f) ||
+      !(lr_final > 0.0f) || batch < 0 || batch > n)
     return IT_EINVAL;
-  if (!d_ws || ws_bytes < train_ws_bytes(members, n)) return IT_EWORKSPACE;
+  const int64_t rows = batch ? batch : n;
+  if (n % rows) return IT_EINVAL;  // the minibatches tile the data
+  if (!d_ws || ws_bytes < train_ws_bytes(members, rows)) return IT_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream_;
   Model md = carve_model(d_model, members);
-  TrainWs w = carve_train(d_ws, members, n);
+  TrainWs w = carve_train(d_ws, members, rows);
   Header h;
   if (hipMemcpy(&h, md.hdr, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return IT_EHIP;
+  const int64_t nbatch = n / rows;
   int nlog = 0;
   for (int k = 0; k < steps; ++k) {
-    int rc = launch_grad(md, members, d_X, d_t, n, w, s);
+    // minibatch: the next contiguous window of the data, continuing across calls
+    const int64_t b0 = ((h.step + k) % nbatch) * rows;
+    const float* X = d_X + b0 * kIn;
+    const float* t = d_t + b0;
+    int rc = launch_grad(md, members, X, t, rows, w, s);
     if (rc) return rc;
     if (h_loss && log_every > 0 && k % log_every == 0) {
-      hipLaunchKernelGGL(loss_kernel, dim3(members), dim3(1024), 0, s, md, d_t, n, w);
+      hipLaunchKernelGGL(loss_kernel, dim3(members), dim3(1024), 0, s, md, t, rows, w);
       if (hipMemcpyAsync(h_loss + (size_t)nlog * members, w.loss, members * 4, hipMemcpyDeviceToHost, s) !=
           hipSuccess)
         return IT_EHIP;
       ++nlog;
     }
-    hipLaunchKernelGGL(adam_kernel, dim3((members * kP + 255) / 256), dim3(256), 0, s, md, w.grad, members, lr,
+    // cosine decay from lr to lr_final over the steps of this call
+    const double frac = steps > 1 ? (double)k / (double)(steps - 1) : 0.0;
+    const double lr0 = lr, lr1 = lr_final;  // in FP64: the end points are exact
+    const float lr_k = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(M_PI * frac)));
+    hipLaunchKernelGGL(adam_kernel, dim3((members * kP + 255) / 256), dim3(256), 0, s, md, w.grad, members, lr_k,
                        h.step + k + 1);
     if (hipGetLastError() != hipSuccess) return IT_EHIP;
   }

@@ -78,11 +78,14 @@ class Surrogate:
         self.seed = seed
         self.model = None
 
-    def fit(self, X, lnks, schedule=((2e-3, 1500), (6e-4, 1500), (2e-4, 1500)), log_every=250, margin=1e-3):
+    def fit(self, X, lnks, steps=60000, lr=2e-3, lr_final=1e-5, batch=2048, log_every=1000, margin=1e-3):
         """Standardisation from the training inputs (log space), training box
-        with a small margin, targets standardised around the residual."""
+        with a small margin, targets standardised around the residual; then
+        ``steps`` Adam steps on minibatches of ``batch`` rows of the data
+        shuffled once, the rate decaying from lr to lr_final (half cosine)."""
         import torch
         X = np.asarray(X, dtype=np.float64)
+        lnks = np.asarray(lnks, dtype=np.float64)
         L = np.log(X)
         mu, sd = L.mean(axis=0), L.std(axis=0)
         sd = np.where(sd > 0, sd, 1.0)
@@ -97,13 +100,18 @@ class Surrogate:
         resid = lnks - base
         norm = np.concatenate([mu, sd, Z.min(0) - margin, Z.max(0) + margin, [resid.mean(), resid.std()]])
         B.it_mlp_init(self.model, self.members, params, norm, phys_constants())
-        td = torch.tensor(lnks, dtype=torch.float32, device="cuda")
-        logs = []
+        n = len(X)
+        if batch <= 0 or batch >= n or n % batch:
+            batch = 0  # full batch
+        perm = np.random.default_rng(self.seed + 1).permutation(n)
+        Xd = torch.tensor(X[perm], dtype=torch.float32, device="cuda")
+        td = torch.tensor(lnks[perm], dtype=torch.float32, device="cuda")
         t0 = time.perf_counter()
-        for lr, steps in schedule:
-            logs.append(B.it_mlp_train(self.model, self.members, Xd, td, steps, lr, log_every))
+        self.loss_log = B.it_mlp_train(self.model, self.members, Xd, td, steps, lr, log_every, batch=batch,
+                                       lr_final=lr_final)
         self.train_seconds = time.perf_counter() - t0
-        self.loss_log = np.concatenate(logs) if logs else None
+        self.train_steps = steps
+        self.batch = batch or n
         return self
 
     def query(self, Xq, spread_tol):
@@ -125,8 +133,7 @@ class Surrogate:
         return out, mask
 
 
-def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4, schedule=None,
-             seed=None):
+def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4, steps=60000, seed=None):
     """The surrogate experiment: train on n_train solver runs, judge on
     n_hold held-out solver runs, time n_query queries.  Returns a dict."""
     import torch
@@ -134,9 +141,7 @@ def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4
     Xtr = W.surrogate_inputs(base_seed, n_train)
     ytr, vs_tr, sec_tr = solver_lnks(Xtr)
     s = Surrogate(members=members, seed=base_seed + 100)
-    if schedule is None:
-        schedule = ((2e-3, 1500), (6e-4, 1500), (2e-4, 1500))
-    s.fit(Xtr, ytr, schedule=schedule)
+    s.fit(Xtr, ytr, steps=steps)
     Xh = W.surrogate_inputs(base_seed + 1, n_hold)
     yh, vs_h, sec_h = solver_lnks(Xh)
     mean, spread, fb, idx, n_fb = s.query(Xh, spread_tol)
@@ -171,6 +176,7 @@ def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4
         "n_train": n_train, "n_holdout": n_hold, "n_query": n_query, "members": members,
         "spread_tol_ln": spread_tol,
         "train_data_seconds": sec_tr, "train_data_voxel_steps": vs_tr, "train_seconds": s.train_seconds,
+        "train_steps": s.train_steps, "train_batch": s.batch,
         "final_loss": float(s.loss_log[-1].max()) if s.loss_log is not None and len(s.loss_log) else None,
         "holdout_accepted_fraction": float(acc.mean()),
         "holdout_rel_err_accepted_max": float(rel[acc].max()) if acc.any() else None,

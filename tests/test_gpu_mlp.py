@@ -100,6 +100,44 @@ def test_training_reduces_loss(gpu):
     assert np.all(loss_after < losses[-1] * 1.5)
 
 
+def test_minibatch_steps_equal_full_batch_steps_on_each_window(gpu):
+    """Minibatch step s uses rows [(s mod n/batch) * batch, ...): two steps
+    with batch n/2 equal one full-batch step on each half, bit for bit."""
+    import torch
+    members, n = 2, 1024
+    model_a, X, t, norm, params = setup(gpu, members, n, seed=9)
+    model_b = model_a.clone()
+    Xd, td = torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda")
+    half = n // 2
+    gpu.it_mlp_train(model_a, members, Xd, td, steps=2, lr=1e-3, batch=half)
+    gpu.it_mlp_train(model_b, members, Xd[:half].contiguous(), td[:half].contiguous(), steps=1, lr=1e-3)
+    gpu.it_mlp_train(model_b, members, Xd[half:].contiguous(), td[half:].contiguous(), steps=1, lr=1e-3)
+    assert torch.equal(model_a, model_b)
+    with pytest.raises(gpu.ItError):  # minibatches must tile the data
+        gpu.it_mlp_train(model_a, members, Xd, td, steps=1, lr=1e-3, batch=300)
+
+
+def test_cosine_schedule_ends_at_final_rate(gpu):
+    """A run from lr to lr_final takes the same last step as a constant-rate
+    run at lr_final from the same state (the schedule's end point)."""
+    import torch
+    members, n = 1, 512
+    model_a, X, t, norm, params = setup(gpu, members, n, seed=13)
+    Xd, td = torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda")
+    gpu.it_mlp_train(model_a, members, Xd, td, steps=5, lr=1e-3)
+    model_b = model_a.clone()
+    gpu.it_mlp_train(model_a, members, Xd, td, steps=1, lr=1e-4, lr_final=1e-4)
+    gpu.it_mlp_train(model_b, members, Xd, td, steps=1, lr=1e-4)
+    assert torch.equal(model_a, model_b)
+    model_c = model_b.clone()
+    gpu.it_mlp_train(model_b, members, Xd, td, steps=3, lr=3e-3, lr_final=1e-4)
+    # the schedule's midpoint, as the library rounds it (FP64 sum, FP32 rate)
+    mid = float(np.float32((float(np.float32(3e-3)) + float(np.float32(1e-4))) / 2))
+    gpu.it_mlp_train(model_c, members, Xd, td, steps=2, lr=3e-3, lr_final=mid)
+    gpu.it_mlp_train(model_c, members, Xd, td, steps=1, lr=1e-4)
+    assert torch.equal(model_b, model_c)
+
+
 def test_query_fallback_mask_and_indices(gpu):
     import torch
     members, n = 2, 1000

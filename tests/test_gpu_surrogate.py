@@ -34,7 +34,7 @@ def test_solver_data_match_single_runs(sur):
 def test_small_pipeline(sur):
     Xtr = W.surrogate_inputs(41, 512)
     ytr, _, _ = sur.solver_lnks(Xtr)
-    s = sur.Surrogate(members=4).fit(Xtr, ytr, schedule=((2e-3, 400), (5e-4, 400)))
+    s = sur.Surrogate(members=4).fit(Xtr, ytr, steps=800, batch=128, log_every=100)
     assert s.loss_log[-1].max() < 0.5 * s.loss_log[0].max()
     Xq = W.surrogate_inputs(43, 64)
     yq, _, _ = sur.solver_lnks(Xq)
