@@ -93,6 +93,17 @@ def test_single_track_full_run(gpu, orc, ex):
     assert o["flags"] == 0 and 0.1 < o["f"] < 0.3
 
 
+@pytest.mark.parametrize("deg", [30, 60, 90])
+def test_tilted_single_track_full_run(gpu, orc, deg):
+    """The tilted tracks of the Jaffe angular comparison, run to collection."""
+    import math
+    ch, tr = W.single_track()
+    tr[0, 0] = 1.0
+    tr[0, 4] = math.radians(deg)
+    tr[0, 5] = 0.7  # azimuth off the grid axes
+    run_both(gpu, orc, ch, tr, fields=False)
+
+
 @pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
 def test_single_track_fields_fixed_steps(gpu, orc, ex):
     ch, tr = W.single_track(max_steps=45, stop_tol=0.0)

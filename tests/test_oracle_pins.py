@@ -468,6 +468,35 @@ def test_jaffe_parallel_track(orc, let):
     assert abs((1 - r["f"]) / (1 - fj) - 1) < 0.05
 
 
+def _tilted_single_track(orc, let, deg):
+    ch, tr = W.single_track()
+    tr[0, 0] = let
+    tr[0, 4] = math.radians(deg)
+    return orc.solve(ch, tr, with_fields=False), ch
+
+
+@pytest.mark.parametrize("deg", [30, 45, 60, 90])
+def test_jaffe_angular_formula_for_tilted_tracks(orc, deg):
+    """A single track at angle theta to the field (eq. angle) in the regime
+    the paper compares, theta in [pi/6, pi/2]: the recombined fraction agrees
+    with Jaffe's angular formula within 15%."""
+    r, ch = _tilted_single_track(orc, 1.0, deg)
+    fj = cf.jaffe_angle(1.0, 1e-3, ch["voltage"] / ch["gap"], math.radians(deg), 0.045, AIR_MU, 1.6e-6)
+    assert r["flags"] == 0
+    assert abs((1 - r["f"]) / (1 - fj) - 1) < 0.15
+
+
+def test_tilting_a_track_reduces_recombination(orc):
+    """Columnar recombination falls as the track turns away from the field:
+    f grows monotonically from the parallel track (eq. Jaffe_noangle) to the
+    track parallel to the electrodes, as both of Jaffe's formulas order it."""
+    fs = [_tilted_single_track(orc, 3.0, deg)[0]["f"] for deg in (0, 15, 30, 45, 60, 90)]
+    assert all(b > a for a, b in zip(fs[:-1], fs[1:]))
+    ch, _ = W.single_track()
+    E = ch["voltage"] / ch["gap"]
+    assert fs[0] < cf.jaffe_angle(3.0, 1e-3, E, math.radians(30), 0.045, AIR_MU, 1.6e-6) < fs[-1] + 0.01
+
+
 # ---------------------------------------------------------------------------
 # degenerate inputs
 # ---------------------------------------------------------------------------
