@@ -63,17 +63,23 @@ extern "C" {
 #define IT_FLAG_EMPTY 8      /* nothing was released; f is reported as 1 */
 
 /* ---- per-step trace record: IT_TRACE_COLS doubles per step, in ion counts ---- */
-#define IT_TRACE_COLS 10
+#define IT_TRACE_COLS 12
 /* 0 recombined pairs, 1/2 positive ions collected at anode/cathode,
  * 3/4 negative ions collected at anode/cathode, 5/6 positive/negative ions in
  * flight after the step (signed sum of n dV), 7/8 sum of |n| dV after the
- * step, 9 ion pairs released by deposits made before the step. */
+ * step, 9 ion pairs released by deposits made before the step, 10/11 change
+ * of the positive/negative ions by the space-charge term in the step (0 with
+ * space charge off).  Per species: in flight after = in flight before +
+ * released - collected - recombined + space-charge change. */
 
 /* Chamber, field, transport constants and run control. */
 typedef struct {
   int32_t nx, ny;       /* transverse node counts (>= 1), periodic */
   int32_t nz;           /* gap intervals (>= 2): interior planes 1..nz-1 */
-  int32_t reserved0;    /* must be 0 */
+  int32_t space_charge; /* 1: include the space-charge screening term mu n div E of eq.
+                         * theEquation, with div E = q (n+ - n-)/eps0 at each node
+                         * (Maxwell-Gauss, same section); E in E . grad n stays the
+                         * applied field.  0: leave it out (div E = 0). */
   double dx, dy;        /* transverse node spacing [cm] */
   double gap;           /* electrode distance d [cm]; dz = gap/nz */
   double voltage;       /* V [V]; E = V/gap along +z, anode z=0 -> cathode z=d */
@@ -84,7 +90,7 @@ typedef struct {
   double dt_safety;     /* factor in (0, 1] on the largest stable dt (eq. vNeum) */
   double stop_tol;      /* stop once sum |n| dV <= stop_tol * released for both species (>= 0) */
   double uniform_n0;    /* uniform ion-pair density added at t = 0 [cm^-3] (>= 0) */
-  double reaction_limit;/* rho >= 0: also bound dt by alpha dt n_ref <= rho (0 = off), see it_dt */
+  double reaction_limit;/* rho >= 0: also bound dt by k dt n_ref <= rho (0 = off), see it_dt */
   int64_t max_steps;    /* hard step limit (>= 1) */
 } it_chamber;
 
@@ -111,6 +117,8 @@ typedef struct {
   double col_pos_anode, col_pos_cathode, col_neg_anode, col_neg_cathode;
   double dt;            /* time step [s] */
   double max_beta_n;    /* max over deposits of alpha*dt*max(n) */
+  double n_space_charge_pos, n_space_charge_neg;  /* change of each species by the
+                         * space-charge term over the run (ions; 0 when off) */
   int64_t steps;        /* steps counted in the result */
   int32_t flags;        /* IT_FLAG_* */
   int32_t passes;       /* stepping kernel launches issued (diagnostic) */
@@ -140,9 +148,10 @@ typedef struct {
 /* Time step of a run: dt_safety times the smaller of
  *   - the largest dt satisfying eq. vNeum for both species (with the field
  *     along z: 2 D dt (1/dx^2 + 1/dy^2 + 1/dz^2) + (mu E dt/dz)^2 <= 1), and
- *   - when reaction_limit > 0 and alpha > 0: reaction_limit / (alpha n_ref),
- *     because the explicit recombination sink diverges once alpha dt n
- *     exceeds about 1 at dense track cores.  n_ref is uniform_n0 plus the
+ *   - when reaction_limit > 0 and k > 0: reaction_limit / (k n_ref), with
+ *     k = alpha (+ max(mu+, mu-) q/eps0 with space charge on), because the
+ *     explicit recombination sink (and the screening term) diverges once
+ *     k dt n exceeds about 1 at dense track cores.  n_ref is uniform_n0 plus the
  *     largest density found on any track's axis at mid-gap from all tracks
  *     with the same arrival time (host array; may be NULL if ntracks = 0).
  * Host only: touches no device.  Errors: IT_EINVAL, IT_ENODT. */

@@ -26,9 +26,11 @@ P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
           "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit")
 R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
           "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
-          "col_neg_cathode", "dt", "steps", "flags", "max_beta_n")
+          "col_neg_cathode", "dt", "steps", "flags", "max_beta_n", "n_space_charge_pos",
+          "n_space_charge_neg")
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
-              "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released")
+              "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
+              "neg_space_charge")
 NT = len(TRACE_KEYS)
 
 FLAG_MAX_STEPS, FLAG_NONFINITE, FLAG_REACTION, FLAG_EMPTY = 1, 2, 4, 8

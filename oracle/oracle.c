@@ -11,8 +11,10 @@
  *
  *   - linear ion-pair density N0 = LET / W                    (eq. linear_density)
  *   - Gaussian radial track profile n0(r) = N0/(pi b^2) e^{-r^2/b^2}   (eq. Gaussian)
- *   - transport  dn/dt = D lap n -/+ mu E . grad n - alpha n+ n-       (eq. theEquation,
- *     with the uniform applied field, so div E = 0)
+ *   - transport  dn/dt = D lap n -/+ mu (E . grad n + n div E) - alpha n+ n-
+ *     (eq. theEquation): E in E . grad n is the uniform applied field; with
+ *     space charge on, div E comes from the local net charge by the
+ *     Maxwell-Gauss law, div E = q (n+ - n-) / eps0 (same section), else 0
  *   - grid x_i = i dx, ..., t_l = l dt and the weights c = mu E dt/dz,
  *     s = D dt/dx^2                                            (Appendix)
  *   - forward time difference, the drift derivative that blends a backward
@@ -20,7 +22,7 @@
  *                                                             (Appendix)
  *   - the largest dt obeying 2(sx+sy+sz) + cx^2+cy^2+cz^2 <= 1 and
  *     cx^2 cy^2 cz^2 <= 8 sx sy sz for both species           (eq. vNeum),
- *     optionally also alpha dt n_ref <= rho (see orc_dt)
+ *     optionally also (alpha + sc) dt n_ref <= rho (see orc_dt)
  *   - electrodes at z=0 and z=d hold zero density; charge reaching them is
  *     collected                                                 (Methods, Implementation)
  *   - f = N_collected / N_released                              (eq. collection_efficiency)
@@ -62,11 +64,15 @@ enum {
 enum {
   R_F, R_KS, R_F_RECOMB, R_RELEASED, R_RECOMBINED, R_INFLIGHT_POS, R_INFLIGHT_NEG,
   R_COL_POS_ANODE, R_COL_POS_CATHODE, R_COL_NEG_ANODE, R_COL_NEG_CATHODE,
-  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_COUNT
+  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_COUNT
 };
 /* per-step record */
 enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_INFLIGHT, T_NEG_INFLIGHT,
-       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_COUNT };
+       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_POS_SC, T_NEG_SC, T_COUNT };
+
+/* elementary charge [C] and vacuum permittivity [F/cm] (CODATA 2018) */
+#define Q_E 1.602176634e-19
+#define EPS0 8.8541878128e-14
 
 #define FLAG_MAX_STEPS 1
 #define FLAG_NONFINITE 2
@@ -192,20 +198,28 @@ double orc_reference_density(const double *p, int64_t nx, int64_t ny, const doub
 }
 
 /* Time step: the largest dt of eq. vNeum, further limited (when the
- * reaction limit rho > 0) so that alpha dt n_ref <= rho: the explicit
+ * reaction limit rho > 0) so that (alpha + sc) dt n_ref <= rho: the explicit
  * recombination sink n' = n - alpha dt n+ n- diverges once alpha dt n
  * exceeds about 1, which the transport bound alone does not prevent at
- * dense track cores.  The safety factor kappa multiplies the result.
+ * dense track cores.  With space charge on, sc = max(mu+, mu-) q / eps0 is
+ * the rate constant of the screening term, whose explicit update
+ * n' = n -/+ mu dt (q/eps0) n (n+ - n-) needs the same bound (dielectric
+ * relaxation).  The safety factor kappa multiplies the result.
  * Returns 0, or -2 if nothing bounds dt. */
 int orc_dt(const double *p, int64_t nx, int64_t ny, int64_t nz, const double *trk, int64_t ntr,
            double *dt)
 {
   double best = transport_dt(p, nz);
   const double rho = p[P_REACTION_LIMIT];
-  if (rho > 0.0 && p[P_ALPHA] > 0.0) {
+  double rate = p[P_ALPHA];
+  if (p[P_SPACE_CHARGE] != 0.0) {
+    const double mu_max = p[P_MU_POS] > p[P_MU_NEG] ? p[P_MU_POS] : p[P_MU_NEG];
+    rate += mu_max * Q_E / EPS0;
+  }
+  if (rho > 0.0 && rate > 0.0) {
     const double nref = orc_reference_density(p, nx, ny, trk, ntr);
     if (nref > 0.0) {
-      const double dtr = rho / (p[P_ALPHA] * nref);
+      const double dtr = rho / (rate * nref);
       if (dtr < best) best = dtr;
     }
   }
@@ -266,14 +280,16 @@ double orc_uniform(const double *p, int64_t nx, int64_t ny, int64_t nz, double n
  * densities (pos, neg) into (npos, nneg).  tally receives the per-step
  * record (T_*), all in ion counts (density times dV): recombined pairs,
  * collected at each electrode per species, in-flight per species (signed
- * sum of the new densities) and the sum of the new |n| per species.  The
- * last slot (released before this step) is left at 0 here; the run fills it.
+ * sum of the new densities), the sum of the new |n| per species, and the
+ * change of each species by the space-charge term.  The released slot
+ * (released before this step) is left at 0 here; the run fills it.
  *
  * For every interior node and species, with the Appendix's derivatives:
  *   dn/dz  ~ c (n_k - n_{k-1})/dz + (1-c)(n_{k+1} - n_{k-1})/(2 dz)
  *   d2n/dx2 ~ (n_{i+1} - 2 n_i + n_{i-1})/dx^2 (and y, z)
- *   n' = n + dt [D lap n - v dn/dz] - alpha dt n+ n-
- * where v is the signed drift velocity and c = v dt/dz. */
+ *   n' = n + dt [D lap n - v dn/dz] - alpha dt n+ n- -/+ mu dt n div E
+ * where v is the signed drift velocity, c = v dt/dz, and, with space
+ * charge on, div E = q (n+ - n-)/eps0 at the node (old densities). */
 void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
               const double *pos, const double *neg, double *npos, double *nneg,
               double *tally)
@@ -286,7 +302,10 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   orc_weights(p, nz, dt, 1, w[1]);
   const double *in[2] = {pos, neg};
   double *out[2] = {npos, nneg};
-  double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0};
+  double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0}, screen[2] = {0.0, 0.0};
+  /* mu dt q/eps0 per species, signed as the term enters n' (- for n+, + for n-) */
+  const double sc_on = p[P_SPACE_CHARGE] != 0.0 ? 1.0 : 0.0;
+  const double gsc[2] = {-sc_on * p[P_MU_POS] * dt * Q_E / EPS0, sc_on * p[P_MU_NEG] * dt * Q_E / EPS0};
 
   for (int64_t k = 1; k < nz; ++k)
     for (int64_t j = 0; j < ny; ++j)
@@ -306,8 +325,10 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
           /* c * dz * (dn/dz) with the blended derivative */
           const double drift = c * (c * (nc - n[IDX(k - 1, j, i)])
                                     + (1.0 - c) * 0.5 * (n[IDX(k + 1, j, i)] - n[IDX(k - 1, j, i)]));
-          const double v = nc + sx * lap_x + sy * lap_y + sz * lap_z - drift - sink;
+          const double screening = gsc[s] * nc * (np_ - nn_);
+          const double v = nc + sx * lap_x + sy * lap_y + sz * lap_z - drift - sink + screening;
           out[s][IDX(k, j, i)] = v;
+          screen[s] += screening;
           inflight[s] += v;
           absolute[s] += fabs(v);
         }
@@ -340,6 +361,8 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   tally[T_POS_ABS] = absolute[0] * dV;
   tally[T_NEG_ABS] = absolute[1] * dV;
   tally[T_RELEASED] = 0.0;
+  tally[T_POS_SC] = screen[0] * dV;
+  tally[T_NEG_SC] = screen[1] * dV;
 }
 
 static double field_max(int64_t n, const double *a, const double *b)
@@ -376,7 +399,7 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
     if (s < max_steps && s > last_deposit) last_deposit = s;
   }
   const double beta = p[P_ALPHA] * dt;
-  double released = 0.0, sums[5] = {0, 0, 0, 0, 0}, last[T_COUNT] = {0};
+  double released = 0.0, sums[5] = {0, 0, 0, 0, 0}, screened[2] = {0, 0}, last[T_COUNT] = {0};
   double max_beta_n = 0.0;
   int flags = 0;
   int64_t steps = 0;
@@ -401,6 +424,8 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
     double *tmp = pos; pos = npos; npos = tmp;
     tmp = neg; neg = nneg; nneg = tmp;
     for (int q = 0; q < 5; ++q) sums[q] += tally[q];
+    screened[0] += tally[T_POS_SC];
+    screened[1] += tally[T_NEG_SC];
     memcpy(last, tally, sizeof(last));
     if (trace) memcpy(trace + T_COUNT * l, tally, sizeof(tally));
     steps = l + 1;
@@ -446,6 +471,8 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   res[R_STEPS] = (double)steps;
   res[R_FLAGS] = (double)flags;
   res[R_MAX_BETA_N] = max_beta_n;
+  res[R_SC_POS] = screened[0];
+  res[R_SC_NEG] = screened[1];
   return 0;
 }
 

@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libiontracks.so")
 
 IT_OK, IT_EINVAL, IT_ENODT, IT_EWORKSPACE, IT_EHIP, IT_ENOTSUP = 0, -1, -2, -3, -4, -5
 IT_FLAG_MAX_STEPS, IT_FLAG_NONFINITE, IT_FLAG_REACTION, IT_FLAG_EMPTY = 1, 2, 4, 8
-IT_TRACE_COLS = 10
+IT_TRACE_COLS = 12
 IT_KERNEL_AUTO, IT_KERNEL_PLAIN, IT_KERNEL_BLOCKED = 0, 1, 2
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
-              "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released")
+              "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
+              "neg_space_charge")
 
 
 class ItError(RuntimeError):
@@ -32,7 +33,7 @@ class ItError(RuntimeError):
 
 class it_chamber(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32),
+                ("space_charge", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("gap", ctypes.c_double),
                 ("voltage", ctypes.c_double), ("mu_pos", ctypes.c_double), ("mu_neg", ctypes.c_double),
                 ("D_pos", ctypes.c_double), ("D_neg", ctypes.c_double), ("alpha", ctypes.c_double),
@@ -44,7 +45,8 @@ class it_chamber(ctypes.Structure):
 class it_result(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in (
         "f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos", "n_inflight_neg",
-        "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "max_beta_n")] + \
+        "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "max_beta_n",
+        "n_space_charge_pos", "n_space_charge_neg")] + \
         [("steps", ctypes.c_int64), ("flags", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
 
@@ -111,8 +113,7 @@ def _chamber(ch) -> it_chamber:
     for k in ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg", "alpha", "W_eV",
               "dt_safety", "stop_tol", "uniform_n0", "reaction_limit"):
         setattr(c, k, float(ch.get(k, 0.0)) if k == "reaction_limit" else float(ch[k]))
-    if int(ch.get("space_charge", 0)):
-        raise ItError(IT_ENOTSUP, "space_charge")
+    c.space_charge = int(ch.get("space_charge", 0))
     return c
 
 

@@ -15,7 +15,12 @@ namespace it {
 //   3 sum n- on plane k = 1      4 sum n- on plane k = nz-1
 //   5 sum n+' (new)              6 sum n-'
 //   7 sum |n+'|                  8 sum |n-'|
-constexpr int kAcc = 9;
+//   9 sum of the space-charge change of n+   10 the same of n-
+constexpr int kAcc = 11;
+
+// elementary charge [C] and vacuum permittivity [F/cm] (CODATA 2018)
+constexpr double kElementaryCharge = 1.602176634e-19;
+constexpr double kEpsilon0 = 8.8541878128e-14;
 constexpr int kMaxT = 8;  // largest number of fused steps per pass
 
 // Coefficients of the explicit update of one species at an interior node:
@@ -35,6 +40,7 @@ struct RunState {
   double sums[5];           // running recombined, pos anode/cathode, neg anode/cathode
   double last[4];           // in-flight pos/neg and |n| sums after the last step
   double max_beta_n;        // max over deposits of beta * max(n)
+  double screened[2];       // running space-charge change of n+ and n-
   int64_t steps;            // steps recorded so far
   int32_t done;             // 1 once the stop criterion (or a non-finite tally) is met
   int32_t flags;            // IT_FLAG_NONFINITE
@@ -62,6 +68,10 @@ struct StepParams {
   int per_xcd;                        // tiles per XCD slot (grid = 8 * per_xcd)
   Coef cp, cn;
   double beta, dV, stop_tol;
+  // space-charge screening, signed as it enters the update:
+  //   n+' += gsp n+ (n+ - n-),  n-' += gsn n- (n+ - n-)
+  // gsp = -mu+ dt q/eps0, gsn = +mu- dt q/eps0 (both 0 when off)
+  double gsp, gsn;
   int64_t step0;            // index of the step this launch computes
   int64_t min_stop_step;    // the stop criterion is tested only from this step on
   double* partials;         // [gridDim][kAcc * T]
@@ -103,7 +113,8 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
                              hipEvent_t ev_end = nullptr);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
-hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int parity,
+// sc: some instance has the space-charge term on
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, int parity,
                              hipStream_t s);
 
 }  // namespace it

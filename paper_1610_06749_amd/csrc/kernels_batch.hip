@@ -22,7 +22,7 @@ __device__ inline int find_instance(const BatchInstance* inst, int ninst, int L)
   return lo;
 }
 
-template <int SY>
+template <int SY, bool SC>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                        int parity) {
@@ -35,7 +35,7 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
   const int l = L - inst[q].tile_begin;
   TileCoord t = tile_of(l, p.tiles_x, p.tiles_y);
   t.valid = true;
-  plain_tile_step<SY>(p, t, p.partials + (size_t)l * kAcc);
+  plain_tile_step<SY, SC>(p, t, p.partials + (size_t)l * kAcc);
 }
 
 __global__ __launch_bounds__(1024) void batch_reduce_kernel(const BatchInstance* __restrict__ inst,
@@ -57,16 +57,26 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(const BatchInstance*
 
 }  // namespace
 
-hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int parity,
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, int parity,
                              hipStream_t s) {
   const BatchInstance* inst = (const BatchInstance*)table;
   const int per_xcd = (total_tiles + 7) / 8;
-  if (plain_tile_rows(tile_y) == 16)
-    hipLaunchKernelGGL(batch_step_kernel<16>, dim3(8 * per_xcd), dim3(kTX, 16), 0, s, inst, ninst,
-                       total_tiles, per_xcd, parity);
-  else
-    hipLaunchKernelGGL(batch_step_kernel<8>, dim3(8 * per_xcd), dim3(kTX, 8), 0, s, inst, ninst,
-                       total_tiles, per_xcd, parity);
+  const dim3 g(8 * per_xcd);
+  if (plain_tile_rows(tile_y) == 16) {
+    if (sc)
+      hipLaunchKernelGGL((batch_step_kernel<16, true>), g, dim3(kTX, 16), 0, s, inst, ninst, total_tiles, per_xcd,
+                         parity);
+    else
+      hipLaunchKernelGGL((batch_step_kernel<16, false>), g, dim3(kTX, 16), 0, s, inst, ninst, total_tiles,
+                         per_xcd, parity);
+  } else {
+    if (sc)
+      hipLaunchKernelGGL((batch_step_kernel<8, true>), g, dim3(kTX, 8), 0, s, inst, ninst, total_tiles, per_xcd,
+                         parity);
+    else
+      hipLaunchKernelGGL((batch_step_kernel<8, false>), g, dim3(kTX, 8), 0, s, inst, ninst, total_tiles, per_xcd,
+                         parity);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batch_reduce_kernel, dim3(ninst), dim3(1024), 0, s, inst, parity);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
   const size_t col = (size_t)ys * p.nx + xs;
   const int tyl = ty > 0 ? ty - 1 : 0, tyr = ty + 1 < kEY ? ty + 1 : kEY - 1;
   const Coef cp = p.cp, cn = p.cn;
-  const double beta = p.beta;
+  const double beta = p.beta, gsp = p.gsp, gsn = p.gsn;
   const double* __restrict__ pin = p.pin;
   const double* __restrict__ nin = p.nin;
   double* __restrict__ pout = p.pout;
@@ -72,12 +72,12 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
     if (lane < 4) edge[t][ty][lane] = 0.0;
 
   double mp[T], cpv[T], mn[T], cnv[T];  // levels 0..T-1: planes K-t-1 and K-t
-  double acc[T][5];                      // per level: sink, n+', n-', |n+'|, |n-'|
+  double acc[T][7];  // per level: sink, n+', n-', |n+'|, |n-'|, space-charge change of n+, n-
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     mp[t] = cpv[t] = mn[t] = cnv[t] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) acc[t][q] = 0.0;
+    for (int q = 0; q < 7; ++q) acc[t][q] = 0.0;
   }
 
   const int Klo = za - T, Khi = zb + T - 1;
@@ -108,10 +108,12 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
         const double pyl = lp[t - 1][tyl][lane], pyr = lp[t - 1][tyr][lane];
         const double nyl = ln[t - 1][tyl][lane], nyr = ln[t - 1][tyr][lane];
         const double sink = beta * pc * nc;
+        const double net = pc - nc;
+        const double scp = gsp * pc * net, scn = gsn * nc * net;
         vp[t] = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[t - 1] +
-                cp.azm * mp[t - 1] - sink;
+                cp.azm * mp[t - 1] - sink + scp;
         vn[t] = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[t - 1] +
-                cn.azm * mn[t - 1] - sink;
+                cn.azm * mn[t - 1] - sink + scn;
         const bool mine = owned && q >= za && q < zb;
         if (mine) {
           acc[t - 1][0] += sink;
@@ -119,6 +121,8 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
           acc[t - 1][2] += vn[t];
           acc[t - 1][3] += fabs(vp[t]);
           acc[t - 1][4] += fabs(vn[t]);
+          acc[t - 1][5] += scp;
+          acc[t - 1][6] += scn;
         }
         if ((q == 1 || q == p.nz - 1) && q >= za && q < zb) {  // uniform over the block
           const double ep = wave_sum(owned ? pc : 0.0), en = wave_sum(owned ? nc : 0.0);
@@ -171,6 +175,8 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
     a[t * kAcc + 6] = acc[t][2];
     a[t * kAcc + 7] = acc[t][3];
     a[t * kAcc + 8] = acc[t][4];
+    a[t * kAcc + 9] = acc[t][5];
+    a[t * kAcc + 10] = acc[t][6];
   }
   block_sum_store<kAcc * T, kBNT>(a, p.partials + (size_t)blockIdx.x * kAcc * T, lds);
 }

@@ -18,11 +18,11 @@ namespace it {
 
 constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 
-template <int SY>
+template <int SY, bool SC>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_plain_kernel(StepParams p) {
   if (p.state->done) return;  // set by an earlier launch: every block skips
-  plain_tile_step<SY>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
-                      p.partials + (size_t)blockIdx.x * kAcc);
+  plain_tile_step<SY, SC>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
+                          p.partials + (size_t)blockIdx.x * kAcc);
 }
 
 // One block: sums the per-block partial tallies of a stepping launch in a
@@ -49,10 +49,15 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
                              hipEvent_t ev_end) {
   const int grid = 8 * p.per_xcd;
   if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
-  if (plain_tile_rows(tile_y) == 16)
-    hipLaunchKernelGGL(step_plain_kernel<16>, dim3(grid), dim3(kTX, 16), 0, s, p);
-  else
-    hipLaunchKernelGGL(step_plain_kernel<8>, dim3(grid), dim3(kTX, 8), 0, s, p);
+  const dim3 g(grid);
+  const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
+  if (plain_tile_rows(tile_y) == 16) {
+    if (sc) hipLaunchKernelGGL((step_plain_kernel<16, true>), g, dim3(kTX, 16), 0, s, p);
+    else hipLaunchKernelGGL((step_plain_kernel<16, false>), g, dim3(kTX, 16), 0, s, p);
+  } else {
+    if (sc) hipLaunchKernelGGL((step_plain_kernel<8, true>), g, dim3(kTX, 8), 0, s, p);
+    else hipLaunchKernelGGL((step_plain_kernel<8, false>), g, dim3(kTX, 8), 0, s, p);
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end && hipEventRecord(ev_end, s) != hipSuccess) return hipErrorInvalidValue;

@@ -126,6 +126,8 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
     rec[7] = a[7] * dV;
     rec[8] = a[8] * dV;
     rec[9] = st.released_pending;
+    rec[10] = a[9] * dV;
+    rec[11] = a[10] * dV;
     st.released_pending = 0.0;
     bool finite = true;
     for (int q = 0; q < IT_TRACE_COLS; ++q) {
@@ -134,6 +136,8 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
     }
     for (int q = 0; q < 5; ++q) st.sums[q] += rec[q];
     for (int q = 0; q < 4; ++q) st.last[q] = rec[5 + q];
+    st.screened[0] += rec[10];
+    st.screened[1] += rec[11];
     st.steps = l + 1;
     if (!finite) {
       st.flags |= IT_FLAG_NONFINITE;
@@ -149,10 +153,7 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
   *gst = st;
 }
 
-// Tile decode shared by the kernels: tiles are numbered row-of-tiles major
-// (ty, then z-chunk, then tx) and split into 8 contiguous ranges, one per
-// XCD; block b runs on XCD b % 8 (round-robin dispatch), so each XCD works
-// on one slab of rows and finds the halo rows of its tiles in its own L2.
+// Tile coordinates: column tile (tx, ty) and z chunk.
 struct TileCoord {
   int tx, ty, zc;
   bool valid;

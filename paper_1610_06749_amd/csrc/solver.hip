@@ -28,7 +28,8 @@ bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 int check_chamber(const it_chamber* ch) {
   if (!ch) return IT_EINVAL;
-  if (ch->nx < 1 || ch->ny < 1 || ch->nz < 2 || ch->reserved0 != 0) return IT_EINVAL;
+  if (ch->nx < 1 || ch->ny < 1 || ch->nz < 2) return IT_EINVAL;
+  if (ch->space_charge != 0 && ch->space_charge != 1) return IT_EINVAL;
   const double cells = (double)ch->nx * ch->ny * (double)(ch->nz + 1);
   if (cells > 4.0e9) return IT_EINVAL;  // 32-bit tile indices and 64-bit offsets suffice below
   if ((double)ch->nx * ch->ny > (double)(1 << 28)) return IT_EINVAL;  // in-plane byte offsets fit 32 bits
@@ -100,11 +101,28 @@ double reference_density(const it_chamber* ch, const it_track* tr, int64_t n) {
   return ch->uniform_n0 + best;
 }
 
+// Rate constant of the explicit pointwise terms: recombination, plus the
+// space-charge screening mu q/eps0 (the dielectric relaxation rate per unit
+// density) when that term is on.
+double pointwise_rate(const it_chamber* ch) {
+  double k = ch->alpha;
+  if (ch->space_charge) k += std::max(ch->mu_pos, ch->mu_neg) * kElementaryCharge / kEpsilon0;
+  return k;
+}
+
+// Space-charge coefficients of species s as they enter the update.
+double screening_coef(const it_chamber* ch, double dt, int s) {
+  if (!ch->space_charge) return 0.0;
+  const double g = dt * kElementaryCharge / kEpsilon0;
+  return s == 0 ? -ch->mu_pos * g : ch->mu_neg * g;
+}
+
 int compute_dt(const it_chamber* ch, const it_track* tr, int64_t n, double* dt) {
   double best = transport_dt(ch);
-  if (ch->reaction_limit > 0.0 && ch->alpha > 0.0) {
+  const double rate = pointwise_rate(ch);
+  if (ch->reaction_limit > 0.0 && rate > 0.0) {
     const double nref = reference_density(ch, tr, n);
-    if (nref > 0.0) best = std::min(best, ch->reaction_limit / (ch->alpha * nref));
+    if (nref > 0.0) best = std::min(best, ch->reaction_limit / (rate * nref));
   }
   if (!(best < INFINITY)) return IT_ENODT;
   *dt = ch->dt_safety * best;
@@ -350,6 +368,8 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   sp.cp = cp;
   sp.cn = cn;
   sp.beta = ch->alpha * dt;
+  sp.gsp = screening_coef(ch, dt, 0);
+  sp.gsn = screening_coef(ch, dt, 1);
   sp.dV = dV;
   sp.stop_tol = stop_tol;
   sp.min_stop_step = min_stop_step;
@@ -588,6 +608,8 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   out->col_neg_cathode = fin.sums[4];
   out->dt = dt;
   out->max_beta_n = fin.max_beta_n;
+  out->n_space_charge_pos = fin.screened[0];
+  out->n_space_charge_neg = fin.screened[1];
   out->steps = fin.steps;
   out->flags = flags;
   out->passes = issued;
@@ -747,6 +769,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   int rc = check_batch(ch, track_offsets, tracks, ninst);
   if (rc) return rc;
   const int rows = batch_rows(ch, ninst, exec);
+  bool any_sc = false;
+  for (int q = 0; q < ninst; ++q) any_sc = any_sc || ch[q].space_charge != 0;
   int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
   if (!z_chunk_ok(exec)) return IT_EINVAL;
@@ -805,6 +829,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       sp.cp = cp;
       sp.cn = cn;
       sp.beta = c->alpha * dts[q];
+      sp.gsp = screening_coef(c, dts[q], 0);
+      sp.gsn = screening_coef(c, dts[q], 1);
       sp.dV = dV;
       sp.stop_tol = c->stop_tol;
       sp.step0 = 0;
@@ -891,7 +917,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
     hipError_t ce = hipSuccess;
     for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, (parity0 + k) & 1, cs);
+      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, any_sc, (parity0 + k) & 1, cs);
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
     if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;

@@ -41,7 +41,9 @@ struct PlaneRegs {
 // suffices: buffer k&1 is rewritten at plane k+2, after every thread has
 // passed the barrier of plane k+1 and hence finished reading plane k.  The
 // barrier orders LDS only; it does not wait for the global loads in flight.
-template <int SY>
+// SC: with the space-charge term (its two extra tallies cost registers, so
+// runs without it use the instance without them).
+template <int SY, bool SC>
 __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, double* partial_out) {
   constexpr int kSNT = kTX * SY;
   __shared__ double sp[2][SY + 2][kTX + 2], sn[2][SY + 2][kTX + 2];
@@ -49,7 +51,7 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   // per-wave sums of n on the planes next to the electrodes (slots 1-4)
   __shared__ double edge[SY][4];
 
-  // running sums of slots 0 and 5-8 (slots 1-4 go through `edge`)
+  // running sums of slots 0 and 5-10 (slots 1-4 go through `edge`)
   double acc[kAcc];
 #pragma unroll
   for (int q = 0; q < kAcc; ++q) acc[q] = 0.0;
@@ -71,7 +73,7 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   const int j_top = y0 == 0 ? p.ny - 1 : y0 - 1;
   const int j_bot = y0 + h == p.ny ? 0 : y0 + h;
   const Coef cp = p.cp, cn = p.cn;
-  const double beta = p.beta;
+  const double beta = p.beta, gsp = p.gsp, gsn = p.gsn;
   // in-plane byte offsets (a plane holds at most 2^28 nodes, checked on the
   // host, so they fit 32 bits and the loads take a scalar base address)
   const unsigned own = (unsigned)(jc * p.nx + ic) * 8u;
@@ -116,10 +118,12 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
     const double nxl = sn[buf][ty + 1][lane], nxr = sn[buf][ty + 1][lane + 2];
     const double nyl = sn[buf][ty][lane + 1], nyr = sn[buf][ty + 2][lane + 1];
     const double sink = beta * c.p * c.n;
+    const double net = c.p - c.n;  // div E in units of q/eps0 (space charge)
+    const double scp = SC ? gsp * c.p * net : 0.0, scn = SC ? gsn * c.n * net : 0.0;
     const double vp = cp.a0 * c.p + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * q1.p +
-                      cp.azm * m.p - sink;
+                      cp.azm * m.p - sink + scp;
     const double vn = cn.a0 * c.n + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * q1.n +
-                      cn.azm * m.n - sink;
+                      cn.azm * m.n - sink + scn;
     if (active) {
       const size_t o = (size_t)k * plane;
       __builtin_nontemporal_store(vp, (__attribute__((address_space(1))) double*)(uniform_ptr(p.pout + o) + own));
@@ -130,6 +134,10 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
     acc[6] += am * vn;
     acc[7] += am * fabs(vp);
     acc[8] += am * fabs(vn);
+    if (SC) {
+      acc[9] += am * scp;
+      acc[10] += am * scn;
+    }
     if (k == 1 || k == nz - 1) {  // uniform over the block
       const double sp_ = wave_sum(am * c.p), sn_ = wave_sum(am * c.n);
       if (lane == 0) {

@@ -44,7 +44,8 @@ def test_host_dt_matches_oracle(lib, orc):
     for ch in (W.single_track()[0], W.pulsed_beam()[0], W.continuous_beam()[0],
                W.chamber(5, 7, 9, 3e-4, 0.01, 0.0), W.chamber(5, 7, 9, 3e-4, 0.01, 80.0, D_pos=0.0, D_neg=0.0)):
         assert lib.it_dt(ch) == pytest.approx(orc.dt(ch), rel=1e-15)
-    for ch, tr in (W.single_track(), W.pulsed_beam(), W.continuous_beam(duration_s=2e-3)):
+    for ch, tr in (W.single_track(), W.pulsed_beam(), W.continuous_beam(duration_s=2e-3),
+                   W.single_track(space_charge=1), W.pulsed_beam(space_charge=1)):
         assert lib.it_dt(ch, tr) == pytest.approx(orc.dt(ch, tr), rel=1e-14)
 
 
@@ -72,6 +73,14 @@ def test_workspace_size_covers_fields_and_trace(lib):
     field = (ch["nz"] + 1) * ch["ny"] * ch["nx"] * 8
     assert n >= 4 * field + ch["max_steps"] * 10 * 8
     assert lib.it_workspace_size(dict(ch, max_steps=10), 400) < n
+
+
+def test_space_charge_flag_values(lib):
+    ch, tr = W.single_track(space_charge=1)
+    lib.it_validate(ch, tr)
+    with pytest.raises(lib.ItError) as e:
+        lib.it_validate(dict(ch, space_charge=2), tr)
+    assert e.value.code == lib.IT_EINVAL
 
 
 def test_launch_shape_checks(lib):

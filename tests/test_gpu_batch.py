@@ -52,6 +52,24 @@ def test_batch_matches_oracle_per_instance(gpu, orc, tile_y):
             assert abs(g[k] - o[k]) <= 1e-9 * N, k
 
 
+def test_batch_with_space_charge_on_some_instances(gpu, orc):
+    """Instances with and without the screening term in one batch (the
+    batch then runs the kernel instance with the term, at zero coefficients
+    for the others)."""
+    chs, trs = small_sweep(n=4, seed=12)
+    for q in (0, 1, 3):
+        chs[q]["space_charge"] = 1
+    res = gpu.it_solve_batch(chs, trs, exec=dict(check_every=4))
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        assert g["steps"] == o["steps"] and g["flags"] == o["flags"]
+        assert g["f"] == pytest.approx(o["f"], rel=1e-9)
+        N = max(o["n_released"], 1.0)
+        for k in ("n_recombined", "n_space_charge_pos", "n_space_charge_neg"):
+            assert abs(g[k] - o[k]) <= 1e-9 * N, k
+        assert (o["n_space_charge_pos"] != 0.0) == bool(ch["space_charge"])
+
+
 def test_batch_equals_single_runs(gpu):
     chs, trs = small_sweep(n=4, seed=9)
     res = gpu.it_solve_batch(chs, trs)

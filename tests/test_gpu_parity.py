@@ -93,6 +93,43 @@ def test_single_track_full_run(gpu, orc, ex):
     assert o["flags"] == 0 and 0.1 < o["f"] < 0.3
 
 
+SC_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16, z_chunk=6), dict(kernel=2, steps_per_pass=3)]
+SC_IDS = ["plain8", "plain16z6", "blocked3"]
+
+
+@pytest.mark.parametrize("ex", SC_EXECS, ids=SC_IDS)
+def test_space_charge_single_track_full_run(gpu, orc, ex):
+    """A single track (LET 10) with the space-charge screening term on."""
+    ch, tr = W.single_track(space_charge=1)
+    tr[0, 0] = 10.0
+    g, o = run_both(gpu, orc, ch, tr, exec=ex, fields=False)
+    assert o["flags"] == 0
+    assert o["n_space_charge_pos"] < 0.0
+    for k in ("n_space_charge_pos", "n_space_charge_neg"):
+        assert abs(g[k] - o[k]) <= RTOL * o["n_released"]
+
+
+@pytest.mark.parametrize("ex", SC_EXECS, ids=SC_IDS)
+def test_space_charge_runaway_is_flagged_at_the_same_step(gpu, orc, ex):
+    """The dense track (LET 100) with the screening term: Lax-Wendroff
+    undershoots (negative densities) grow under the term until the run
+    turns non-finite; both sides stop at the same step with the flag."""
+    ch, tr = W.single_track(space_charge=1)
+    g = gpu.it_solve(ch, tr, exec=ex)
+    o = orc.solve(ch, tr, with_fields=False)
+    assert o["flags"] & gpu.IT_FLAG_NONFINITE
+    assert g["flags"] == o["flags"] and g["steps"] == o["steps"]
+
+
+@pytest.mark.parametrize("ex", SC_EXECS, ids=SC_IDS)
+def test_space_charge_ragged_grid_fields(gpu, orc, ex):
+    ch, tr = ragged_case(max_steps=40, stop_tol=0.0)
+    ch["space_charge"] = 1
+    g, o = run_both(gpu, orc, ch, tr, exec=ex)
+    compare_fields(g["pos"], o["pos"])
+    compare_fields(g["neg"], o["neg"])
+
+
 @pytest.mark.parametrize("deg", [30, 60, 90])
 def test_tilted_single_track_full_run(gpu, orc, deg):
     """The tilted tracks of the Jaffe angular comparison, run to collection."""

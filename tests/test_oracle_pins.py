@@ -345,14 +345,15 @@ def test_track_deposited_at_floor_of_time_over_dt(orc):
 # ---------------------------------------------------------------------------
 
 def _check_conservation(r, tol=1e-12):
-    """released = collected + recombined + in flight, step by step and species
-    by species (the released column holds what was deposited before each step)."""
+    """released = collected + recombined + in flight - space-charge change,
+    step by step and species by species (the released column holds what was
+    deposited before each step)."""
     tr = r["trace"]
     N = r["n_released"]
     assert tr[:, 9].sum() == pytest.approx(N, rel=1e-14)
-    for s, (a, c, S) in enumerate(((1, 2, 5), (3, 4, 6))):
+    for s, (a, c, S, Q) in enumerate(((1, 2, 5, 10), (3, 4, 6, 11))):
         prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, 9]
-        err = prev - tr[:, a] - tr[:, c] - tr[:, 0] - tr[:, S]
+        err = prev - tr[:, a] - tr[:, c] - tr[:, 0] + tr[:, Q] - tr[:, S]
         assert np.max(np.abs(err)) <= tol * N
 
 
@@ -370,6 +371,117 @@ def test_conservation_tilted_tracks_and_uniform(orc):
                    [5.0, 6e-4, 5e-3, 1e-3, 0.2, 4.0, 1e-7]])
     r = orc.solve(ch, tr, with_trace=True, with_fields=False)
     _check_conservation(r)
+
+
+def test_conservation_with_space_charge(orc):
+    ch = W.chamber(24, 20, 30, 3e-4, 30 * 3e-4, 20.0, uniform_n0=3e9, space_charge=1)
+    tr = W.tracks([[60.0, 8e-4, 1e-3, 2e-3, 0.4, 1.0, 0.0],
+                   [25.0, 6e-4, 5e-3, 1e-3, 0.0, 0.0, 1e-7]])
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    _check_conservation(r)
+    assert r["flags"] == 0
+    # the screening term removes ions of the charge in excess: n+ where the
+    # positive ions have drifted ahead, n- where the negative ones have
+    assert r["n_space_charge_pos"] < 0.0 and r["n_space_charge_neg"] < 0.0
+    assert r["n_space_charge_pos"] == pytest.approx(r["trace"][:, 10].sum(), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# space-charge screening (eq. theEquation's n div E, div E by Maxwell-Gauss)
+# ---------------------------------------------------------------------------
+
+Q_OVER_EPS0 = 1.602176634e-19 / 8.8541878128e-14   # V cm
+
+
+def _pointwise_case(space_charge=1, **consts):
+    # no field, no diffusion: every node evolves on its own
+    return W.chamber(3, 2, 6, 1e-3, 6e-3, 0.0, D_pos=0.0, D_neg=0.0, space_charge=space_charge, **consts)
+
+
+def test_space_charge_pointwise_map(orc):
+    """With no field and no diffusion the update at each node is the map
+    n+' = n+ - b n+ n- - m+ dt (q/eps0) n+ (n+ - n-) and
+    n-' = n- - b n+ n- + m- dt (q/eps0) n- (n+ - n-), written out here."""
+    ch = _pointwise_case()
+    rng = np.random.default_rng(3)
+    shape = (7, 2, 3)
+    p0 = rng.uniform(1e10, 5e11, shape)
+    n0 = rng.uniform(1e10, 5e11, shape)
+    p0[0] = p0[-1] = n0[0] = n0[-1] = 0.0
+    dt = 2e-8
+    op, on = orc.advance(ch, dt, p0, n0, 5)
+    P, N = p0.copy(), n0.copy()
+    b = ch["alpha"] * dt
+    for _ in range(5):
+        net = P - N
+        P, N = (P - b * P * N - ch["mu_pos"] * dt * Q_OVER_EPS0 * P * net,
+                N - b * P * N + ch["mu_neg"] * dt * Q_OVER_EPS0 * N * net)
+        P[0] = P[-1] = N[0] = N[-1] = 0.0
+    assert np.max(np.abs(op - P)) <= 1e-13 * P.max()
+    assert np.max(np.abs(on - N)) <= 1e-13 * N.max()
+
+
+def test_space_charge_single_species_decay(orc):
+    """One species alone, no field, no diffusion, no recombination: the
+    screening term gives dn/dt = -mu q n^2/eps0, whose solution is
+    n0 / (1 + mu q n0 t / eps0); the explicit update converges to it at
+    first order in dt."""
+    ch = _pointwise_case(alpha=0.0)
+    n0 = 2e11
+    shape = (7, 2, 3)
+    P0 = np.zeros(shape)
+    P0[1:-1] = n0
+    T = 4e-6
+    exact = n0 / (1.0 + ch["mu_pos"] * Q_OVER_EPS0 * n0 * T)
+    errs = []
+    for steps in (50, 100, 200):
+        op, _ = orc.advance(ch, T / steps, P0, np.zeros(shape), steps)
+        errs.append(abs(op[3, 1, 1] - exact) / exact)
+    assert errs[-1] < 1e-2
+    for a, b_ in zip(errs[:-1], errs[1:]):
+        assert 0.45 < b_ / a < 0.55
+
+
+def test_space_charge_vanishes_for_neutral_plasma(orc):
+    """Equal densities of both species carry no net charge: the runs with and
+    without the term are identical."""
+    ch0 = W.chamber(20, 18, 24, 3e-4, 24 * 3e-4, 20.0, uniform_n0=5e9, max_steps=30, stop_tol=0.0)
+    ch1 = dict(ch0, space_charge=1)
+    d0 = orc.dt(ch0)
+    p, n, _ = orc.uniform(ch0, 5e9)
+    a = orc.step(ch0, d0, p, n)
+    b = orc.step(ch1, d0, p, n)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert b[2]["pos_space_charge"] == 0.0 and b[2]["neg_space_charge"] == 0.0
+
+
+def test_space_charge_dt_bound(orc):
+    """With the term on, the reaction bound uses k = alpha + max(mu) q/eps0."""
+    ch, tr = W.single_track(space_charge=1)
+    nref = orc.reference_density(ch, tr)
+    k = ch["alpha"] + max(ch["mu_pos"], ch["mu_neg"]) * Q_OVER_EPS0
+    expect = min(orc.dt(dict(ch, reaction_limit=0.0)), ch["reaction_limit"] / (k * nref))
+    assert orc.dt(ch, tr) == pytest.approx(expect, rel=1e-14)
+    assert orc.dt(ch, tr) < orc.dt(dict(ch, space_charge=0), tr)
+
+
+def test_space_charge_swap_mirror_symmetry(orc):
+    """The term keeps the species-swap symmetry: -mu+ n+ (n+ - n-) for n+ and
+    +mu- n- (n+ - n-) for n- exchange roles when the species do."""
+    base = dict(mu_pos=1.73, mu_neg=1.87, D_pos=0.045, D_neg=0.06, space_charge=1)
+    swap = dict(mu_pos=1.87, mu_neg=1.73, D_pos=0.06, D_neg=0.045, space_charge=1)
+    ch1, tr = W.single_track(**base)
+    ch2, _ = W.single_track(**swap)
+    tr[0, 0] = 20.0
+    ch1["max_steps"] = ch2["max_steps"] = 60
+    ch1["stop_tol"] = ch2["stop_tol"] = 0.0
+    r1 = orc.solve(ch1, tr)
+    r2 = orc.solve(ch2, tr)
+    assert r1["n_space_charge_pos"] != 0.0
+    assert r2["f"] == pytest.approx(r1["f"], rel=1e-12)
+    assert r2["n_space_charge_pos"] == pytest.approx(r1["n_space_charge_neg"], rel=1e-10)
+    scale = max(r1["neg"].max(), r1["pos"].max())
+    assert np.max(np.abs(r2["pos"] - r1["neg"][::-1])) <= 1e-12 * scale
 
 
 def test_no_recombination_collects_everything(orc):
