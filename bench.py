@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -47,6 +48,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 96-chamber sweep")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
     ap.add_argument("--surrogate-train", type=int, default=8192)
+    ap.add_argument("--continuous-ms", type=float, default=0.4,
+                    help="beam-on time of the continuous-beam run (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy two fields of the workload grid with a plain device copy "
                          "(reference for the HBM byte counters)")
@@ -98,6 +101,34 @@ def cpu_baseline(ch, tr):
     oracle.advance(ch, dt, pos, neg, nsteps)
     t_step = (time.perf_counter() - t0) / nsteps
     return t_dep, t_step, nint, np
+
+
+def continuous_run(it, W, beam_s):
+    """The continuous beam (512 x 512 x 256 nodes, tilted tracks arriving as
+    a Poisson process, 4 of them at t = 0) with the beam on for beam_s, then
+    off until every ion is collected: f and the collected current
+    I_l = q (C+_l + C-_l) / (2 dt) (both electrodes, both species)."""
+    import numpy as np
+    import torch
+    ch, tr = W.continuous_beam(duration_s=beam_s)
+    ws = it.workspace(ch, tr.shape[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = it.it_solve(ch, tr, ws=ws, trace=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    trc = r["trace"]
+    dt = r["dt"]
+    q = 1.602176634e-19
+    cur = q * (trc[:, 1] + trc[:, 2] + trc[:, 3] + trc[:, 4]) / (2.0 * dt)
+    on = int(min(len(cur), math.ceil(beam_s / dt)))
+    nint = ch["nx"] * ch["ny"] * (ch["nz"] - 1)
+    return {"workload": f"continuous beam 512x512x256, beam on {beam_s * 1e3:g} ms then off to collection",
+            "tracks": int(tr.shape[0]), "steps": r["steps"], "dt": dt, "f": r["f"], "ks": r["ks"],
+            "flags": r["flags"], "seconds": sec, "voxel_steps_per_s": r["steps"] * nint / sec,
+            "current_mean_beam_on_A": float(cur[:on].mean()) if on else 0.0,
+            "current_peak_A": float(cur.max()), "charge_collected_C": float(cur.sum() * dt),
+            "current_trace_points": int(len(cur))}
 
 
 def main():
@@ -216,6 +247,10 @@ def main():
                  "ks_evals_per_s": len(chs) / sec, "max_steps": max(r["steps"] for r in res),
                  "flags": sorted({r["flags"] for r in res})}
 
+    cont = None
+    if a.continuous_ms > 0:
+        cont = continuous_run(it, W, a.continuous_ms * 1e-3)
+
     sur = None
     if not a.no_surrogate:
         from paper_1610_06749_amd import surrogate
@@ -245,6 +280,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "continuous": cont,
         "surrogate": sur,
     }
     print(json.dumps(out), flush=True)

@@ -39,8 +39,10 @@ __device__ inline double lane_from_right(double v) {  // value of lane + 1
   return __hiloint2double(hi, lo);
 }
 
-template <int T>
+// SC: with the space-charge term (two more tallies per level).
+template <int T, bool SC>
 __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
+  constexpr int NA = SC ? 7 : 5;  // tallies kept per level
   constexpr int OX = kEX - 2 * T, OY = kEY - 2 * T;
   if (p.state->done) return;
   __shared__ double lp[T][kEY][kEX], ln[T][kEY][kEX];
@@ -72,12 +74,12 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
     if (lane < 4) edge[t][ty][lane] = 0.0;
 
   double mp[T], cpv[T], mn[T], cnv[T];  // levels 0..T-1: planes K-t-1 and K-t
-  double acc[T][7];  // per level: sink, n+', n-', |n+'|, |n-'|, space-charge change of n+, n-
+  double acc[T][NA];  // per level: sink, n+', n-', |n+'|, |n-'| (, space-charge change of n+, n-)
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     mp[t] = cpv[t] = mn[t] = cnv[t] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 7; ++q) acc[t][q] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[t][q] = 0.0;
   }
 
   const int Klo = za - T, Khi = zb + T - 1;
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
         const double nyl = ln[t - 1][tyl][lane], nyr = ln[t - 1][tyr][lane];
         const double sink = beta * pc * nc;
         const double net = pc - nc;
-        const double scp = gsp * pc * net, scn = gsn * nc * net;
+        const double scp = SC ? gsp * pc * net : 0.0, scn = SC ? gsn * nc * net : 0.0;
         vp[t] = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[t - 1] +
                 cp.azm * mp[t - 1] - sink + scp;
         vn[t] = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[t - 1] +
@@ -121,8 +123,10 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
           acc[t - 1][2] += vn[t];
           acc[t - 1][3] += fabs(vp[t]);
           acc[t - 1][4] += fabs(vn[t]);
-          acc[t - 1][5] += scp;
-          acc[t - 1][6] += scn;
+          if constexpr (SC) {
+            acc[t - 1][5] += scp;
+            acc[t - 1][6] += scn;
+          }
         }
         if ((q == 1 || q == p.nz - 1) && q >= za && q < zb) {  // uniform over the block
           const double ep = wave_sum(owned ? pc : 0.0), en = wave_sum(owned ? nc : 0.0);
@@ -175,8 +179,13 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
     a[t * kAcc + 6] = acc[t][2];
     a[t * kAcc + 7] = acc[t][3];
     a[t * kAcc + 8] = acc[t][4];
-    a[t * kAcc + 9] = acc[t][5];
-    a[t * kAcc + 10] = acc[t][6];
+    if constexpr (SC) {
+      a[t * kAcc + 9] = acc[t][5];
+      a[t * kAcc + 10] = acc[t][6];
+    } else {
+      a[t * kAcc + 9] = 0.0;
+      a[t * kAcc + 10] = 0.0;
+    }
   }
   block_sum_store<kAcc * T, kBNT>(a, p.partials + (size_t)blockIdx.x * kAcc * T, lds);
 }
@@ -229,11 +238,17 @@ hipError_t launch_step_blocked(const StepParams& p0, int T, int tile_y, hipStrea
   const dim3 block(kEX, kEY);
   if (T < 2 || T > 5) return hipErrorInvalidValue;
   if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
-  switch (T) {
-    case 2: hipLaunchKernelGGL(step_blocked_kernel<2>, dim3(grid), block, 0, s, p); break;
-    case 3: hipLaunchKernelGGL(step_blocked_kernel<3>, dim3(grid), block, 0, s, p); break;
-    case 4: hipLaunchKernelGGL(step_blocked_kernel<4>, dim3(grid), block, 0, s, p); break;
-    case 5: hipLaunchKernelGGL(step_blocked_kernel<5>, dim3(grid), block, 0, s, p); break;
+  const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
+  const dim3 g(grid);
+  switch (T * 2 + (sc ? 1 : 0)) {
+    case 4: hipLaunchKernelGGL((step_blocked_kernel<2, false>), g, block, 0, s, p); break;
+    case 5: hipLaunchKernelGGL((step_blocked_kernel<2, true>), g, block, 0, s, p); break;
+    case 6: hipLaunchKernelGGL((step_blocked_kernel<3, false>), g, block, 0, s, p); break;
+    case 7: hipLaunchKernelGGL((step_blocked_kernel<3, true>), g, block, 0, s, p); break;
+    case 8: hipLaunchKernelGGL((step_blocked_kernel<4, false>), g, block, 0, s, p); break;
+    case 9: hipLaunchKernelGGL((step_blocked_kernel<4, true>), g, block, 0, s, p); break;
+    case 10: hipLaunchKernelGGL((step_blocked_kernel<5, false>), g, block, 0, s, p); break;
+    case 11: hipLaunchKernelGGL((step_blocked_kernel<5, true>), g, block, 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
   const hipError_t e = hipGetLastError();
