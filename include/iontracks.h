@@ -63,13 +63,15 @@ extern "C" {
 #define IT_FLAG_EMPTY 8      /* nothing was released; f is reported as 1 */
 
 /* ---- per-step trace record: IT_TRACE_COLS doubles per step, in ion counts ---- */
-#define IT_TRACE_COLS 12
+#define IT_TRACE_COLS 13
 /* 0 recombined pairs, 1/2 positive ions collected at anode/cathode,
  * 3/4 negative ions collected at anode/cathode, 5/6 positive/negative ions in
  * flight after the step (signed sum of n dV), 7/8 sum of |n| dV after the
- * step, 9 ion pairs released by deposits made before the step, 10/11 change
- * of the positive/negative ions by the space-charge term in the step (0 with
- * space charge off).  Per species: in flight after = in flight before +
+ * step, 9 positive ions released by deposits made before the step, 10/11
+ * change of the positive/negative ions by the space-charge term in the step
+ * (0 with space charge off), 12 negative ions released by deposits made
+ * before the step (equal to column 9 unless tracks give the negative ions
+ * their own radius).  Per species: in flight after = in flight before +
  * released - collected - recombined + space-charge change. */
 
 /* Chamber, field, transport constants and run control. */
@@ -105,13 +107,17 @@ typedef struct {
   double x_cm, y_cm;    /* axis position at mid-gap [cm] */
   double theta, phi;    /* polar angle to the field and azimuth [rad] */
   double t_s;           /* arrival time [s] (>= 0) */
+  double b_neg_cm;      /* Gaussian radius of the negative ions [cm]; 0 = b_cm.  The
+                         * paper notes that the negative ions' track is wider and
+                         * that separate radii are a direct extension of its
+                         * averaged radius (The charge carrier distribution). */
 } it_track;
 
 /* Result of a run (all counts in ion pairs / ions). */
 typedef struct {
-  double f;             /* collection efficiency: collected / (2 released), both species */
+  double f;             /* collection efficiency: ions collected / ions released, both species */
   double ks;            /* recombination factor 1/f */
-  double f_R;           /* 1 - recombined / released */
+  double f_R;           /* 1 - recombined pairs / mean ions released per species */
   double n_released, n_recombined;
   double n_inflight_pos, n_inflight_neg;  /* signed in-flight counts after the last step */
   double col_pos_anode, col_pos_cathode, col_neg_anode, col_neg_cathode;
@@ -119,6 +125,8 @@ typedef struct {
   double max_beta_n;    /* max over deposits of alpha*dt*max(n) */
   double n_space_charge_pos, n_space_charge_neg;  /* change of each species by the
                          * space-charge term over the run (ions; 0 when off) */
+  double n_released_neg;/* negative ions released (n_released counts the positive
+                         * ions; the two differ only with separate track radii) */
   int64_t steps;        /* steps counted in the result */
   int32_t flags;        /* IT_FLAG_* */
   int32_t passes;       /* stepping kernel launches issued (diagnostic) */

@@ -27,10 +27,10 @@ P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
 R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
           "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
           "col_neg_cathode", "dt", "steps", "flags", "max_beta_n", "n_space_charge_pos",
-          "n_space_charge_neg")
+          "n_space_charge_neg", "n_released_neg")
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
               "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
-              "neg_space_charge")
+              "neg_space_charge", "released_neg")
 NT = len(TRACE_KEYS)
 
 FLAG_MAX_STEPS, FLAG_NONFINITE, FLAG_REACTION, FLAG_EMPTY = 1, 2, 4, 8
@@ -62,8 +62,8 @@ def lib():
         L.orc_dt.restype = ctypes.c_int
         L.orc_weights.argtypes = [dp, i64, ctypes.c_double, ctypes.c_int, dp]
         L.orc_weights.restype = None
-        L.orc_deposit.argtypes = [dp, i64, i64, i64, dp, i64, i64, ctypes.c_double, dp, dp]
-        L.orc_deposit.restype = ctypes.c_double
+        L.orc_deposit.argtypes = [dp, i64, i64, i64, dp, i64, i64, ctypes.c_double, dp, dp, dp]
+        L.orc_deposit.restype = None
         L.orc_uniform.argtypes = [dp, i64, i64, i64, ctypes.c_double, dp, dp]
         L.orc_uniform.restype = ctypes.c_double
         L.orc_step.argtypes = [dp, i64, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp]
@@ -91,10 +91,19 @@ def _shape(ch):
     return (ch["nz"] + 1, ch["ny"], ch["nx"])
 
 
+TRACK_COLS = 8  # let, b, x, y, theta, phi, t, b_neg (0: the negative ions share b)
+
+
 def _trk(tracks):
+    """Track rows as the C code reads them: 8 columns (7-column rows get
+    b_neg = 0)."""
     if tracks is None:
-        return np.zeros((0, 7))
-    return np.ascontiguousarray(tracks, dtype=np.float64).reshape(-1, 7)
+        return np.zeros((0, TRACK_COLS))
+    a = np.asarray(tracks, dtype=np.float64)
+    a = a.reshape(-1, a.shape[-1] if a.ndim > 1 else 7)
+    if a.shape[1] == 7:
+        a = np.concatenate([a, np.zeros((a.shape[0], 1))], axis=1)
+    return np.ascontiguousarray(a)
 
 
 def reference_density(ch, tracks) -> float:
@@ -125,10 +134,11 @@ def deposit(ch, tracks, step: int, dt_, pos=None, neg=None):
     shape = _shape(ch)
     pos = np.zeros(shape) if pos is None else pos
     neg = np.zeros(shape) if neg is None else neg
-    tr = np.ascontiguousarray(tracks, dtype=np.float64).reshape(-1, 7)
-    rel = lib().orc_deposit(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr),
-                            tr.shape[0], int(step), dt_, _ptr(pos), _ptr(neg))
-    return pos, neg, rel
+    tr = _trk(tracks)
+    rel = np.zeros(2)
+    lib().orc_deposit(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr),
+                      tr.shape[0], int(step), dt_, _ptr(pos), _ptr(neg), _ptr(rel))
+    return pos, neg, (float(rel[0]) if rel[0] == rel[1] else (float(rel[0]), float(rel[1])))
 
 
 def uniform(ch, n0, pos=None, neg=None):
@@ -167,7 +177,7 @@ def solve(ch, tracks, with_trace: bool = False, with_fields: bool = True):
     """Full run; returns a dict of the result, plus 'trace' [steps, NT] and
     the final fields 'pos', 'neg' of shape (nz+1, ny, nx).  Trace columns are
     ``TRACE_KEYS``."""
-    tr = np.ascontiguousarray(tracks, dtype=np.float64).reshape(-1, 7)
+    tr = _trk(tracks)
     shape = _shape(ch)
     pos, neg = np.zeros(shape), np.zeros(shape)
     ms = int(ch["max_steps"])

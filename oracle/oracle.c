@@ -10,7 +10,9 @@
  * speed: single-threaded triple loops, no blocking, no fusion.
  *
  *   - linear ion-pair density N0 = LET / W                    (eq. linear_density)
- *   - Gaussian radial track profile n0(r) = N0/(pi b^2) e^{-r^2/b^2}   (eq. Gaussian)
+ *   - Gaussian radial track profile n0(r) = N0/(pi b^2) e^{-r^2/b^2}   (eq. Gaussian),
+ *     optionally with a separate radius b- for the negative ions (the paper
+ *     notes b- > b+ and that separate radii are a direct extension)
  *   - transport  dn/dt = D lap n -/+ mu (E . grad n + n div E) - alpha n+ n-
  *     (eq. theEquation): E in E . grad n is the uniform applied field; with
  *     space charge on, div E comes from the local net charge by the
@@ -64,11 +66,15 @@ enum {
 enum {
   R_F, R_KS, R_F_RECOMB, R_RELEASED, R_RECOMBINED, R_INFLIGHT_POS, R_INFLIGHT_NEG,
   R_COL_POS_ANODE, R_COL_POS_CATHODE, R_COL_NEG_ANODE, R_COL_NEG_CATHODE,
-  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_COUNT
+  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_RELEASED_NEG, R_COUNT
 };
 /* per-step record */
 enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_INFLIGHT, T_NEG_INFLIGHT,
-       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_POS_SC, T_NEG_SC, T_COUNT };
+       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_POS_SC, T_NEG_SC, T_RELEASED_NEG, T_COUNT };
+
+/* track record: {let_keV_um, b, x0, y0, theta, phi, t, b_neg}; b_neg = 0
+ * means the negative ions share the radius b */
+#define TRK 8
 
 /* elementary charge [C] and vacuum permittivity [F/cm] (CODATA 2018) */
 #define Q_E 1.602176634e-19
@@ -138,14 +144,20 @@ static void track_axis(const double *tr, double *u)
   u[2] = cos(tr[4]);
 }
 
-/* Gaussian track profile of eq. Gaussian at node (i,j,k), 0 beyond 8b.
- * tr = {let_keV_um, b, x0, y0, theta, phi, t}; u = axis direction. */
+/* Gaussian radius of species s (0 = positive, 1 = negative) of a track. */
+static double track_radius(const double *tr, int s)
+{
+  return s == 1 && tr[7] > 0.0 ? tr[7] : tr[1];
+}
+
+/* Gaussian track profile of eq. Gaussian at node (i,j,k) for species s,
+ * 0 beyond 8b.  u = axis direction. */
 static double track_density(const double *p, int64_t nx, int64_t ny, int64_t nz,
-                            const double *tr, const double *u, int64_t i, int64_t j, int64_t k)
+                            const double *tr, const double *u, int s, int64_t i, int64_t j, int64_t k)
 {
   const double dz = p[P_GAP] / (double)nz;
   const double N0 = tr[0] * 1.0e7 / p[P_W]; /* keV/um -> eV/cm, divided by W: pairs/cm */
-  const double b = tr[1];
+  const double b = track_radius(tr, s);
   const double wx = wrap((double)i * p[P_DX] - tr[2], (double)nx * p[P_DX]);
   const double wy = wrap((double)j * p[P_DY] - tr[3], (double)ny * p[P_DY]);
   const double wz = (double)k * dz - 0.5 * p[P_GAP];
@@ -161,10 +173,10 @@ static double track_density(const double *p, int64_t nx, int64_t ny, int64_t nz,
 /* Density that track tr deposits at the point (x, y, z) (same rule as at
  * the nodes: wrapped transverse offset, 8b cut-off). */
 static double track_density_at(const double *p, int64_t nx, int64_t ny, const double *tr,
-                               const double *u, double x, double y, double z)
+                               const double *u, int s, double x, double y, double z)
 {
   const double N0 = tr[0] * 1.0e7 / p[P_W];
-  const double b = tr[1];
+  const double b = track_radius(tr, s);
   const double wx = wrap(x - tr[2], (double)nx * p[P_DX]);
   const double wy = wrap(y - tr[3], (double)ny * p[P_DY]);
   const double wz = z - 0.5 * p[P_GAP];
@@ -177,22 +189,25 @@ static double track_density_at(const double *p, int64_t nx, int64_t ny, const do
 }
 
 /* Reference peak density for the recombination bound on dt: the uniform
- * pre-ionisation plus, over all tracks, the largest density found on a
- * track's axis at mid-gap from every track that arrives at the same time. */
+ * pre-ionisation plus, over all tracks and both species, the largest density
+ * found on a track's axis at mid-gap from every track that arrives at the
+ * same time. */
 double orc_reference_density(const double *p, int64_t nx, int64_t ny, const double *trk, int64_t ntr)
 {
   double best = 0.0;
   for (int64_t t = 0; t < ntr; ++t) {
-    const double *a = trk + 7 * t;
-    double s = 0.0;
-    for (int64_t q = 0; q < ntr; ++q) {
-      const double *tr = trk + 7 * q;
-      if (tr[6] != a[6]) continue;
-      double u[3];
-      track_axis(tr, u);
-      s += track_density_at(p, nx, ny, tr, u, a[2], a[3], 0.5 * p[P_GAP]);
+    const double *a = trk + TRK * t;
+    for (int sp = 0; sp < 2; ++sp) {
+      double s = 0.0;
+      for (int64_t q = 0; q < ntr; ++q) {
+        const double *tr = trk + TRK * q;
+        if (tr[6] != a[6]) continue;
+        double u[3];
+        track_axis(tr, u);
+        s += track_density_at(p, nx, ny, tr, u, sp, a[2], a[3], 0.5 * p[P_GAP]);
+      }
+      if (s > best) best = s;
     }
-    if (s > best) best = s;
   }
   return p[P_UNIFORM_N0] + best;
 }
@@ -236,30 +251,34 @@ int64_t orc_deposit_step(double dt, const double *tr)
 }
 
 /* Add every track due at step `step` (list order) to both species.
- * Returns the number of ion pairs released (sum of density times dV). */
-double orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
-                   const double *trk, int64_t ntr, int64_t step, double dt,
-                   double *pos, double *neg)
+ * released[0], released[1]: ions of each species released (sum of density
+ * times dV); equal unless the track gives the negative ions their own
+ * radius. */
+void orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
+                 const double *trk, int64_t ntr, int64_t step, double dt,
+                 double *pos, double *neg, double *released)
 {
   const double dV = p[P_DX] * p[P_DY] * (p[P_GAP] / (double)nz);
-  double released = 0.0;
+  released[0] = released[1] = 0.0;
   for (int64_t t = 0; t < ntr; ++t) {
-    const double *tr = trk + 7 * t;
+    const double *tr = trk + TRK * t;
     if (orc_deposit_step(dt, tr) != step) continue;
     double u[3];
     track_axis(tr, u);
-    double sum = 0.0;
+    double sum[2] = {0.0, 0.0};
     for (int64_t k = 1; k < nz; ++k)
       for (int64_t j = 0; j < ny; ++j)
         for (int64_t i = 0; i < nx; ++i) {
-          const double d = track_density(p, nx, ny, nz, tr, u, i, j, k);
-          pos[IDX(k, j, i)] += d;
-          neg[IDX(k, j, i)] += d;
-          sum += d;
+          const double dp = track_density(p, nx, ny, nz, tr, u, 0, i, j, k);
+          const double dn = track_density(p, nx, ny, nz, tr, u, 1, i, j, k);
+          pos[IDX(k, j, i)] += dp;
+          neg[IDX(k, j, i)] += dn;
+          sum[0] += dp;
+          sum[1] += dn;
         }
-    released += sum * dV;
+    released[0] += sum[0] * dV;
+    released[1] += sum[1] * dV;
   }
-  return released;
 }
 
 /* Uniform pre-ionisation n0 of both species at every interior node. */
@@ -361,6 +380,7 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   tally[T_POS_ABS] = absolute[0] * dV;
   tally[T_NEG_ABS] = absolute[1] * dV;
   tally[T_RELEASED] = 0.0;
+  tally[T_RELEASED_NEG] = 0.0;
   tally[T_POS_SC] = screen[0] * dV;
   tally[T_NEG_SC] = screen[1] * dV;
 }
@@ -395,32 +415,40 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
 
   int64_t last_deposit = -1;
   for (int64_t t = 0; t < ntr; ++t) {
-    int64_t s = orc_deposit_step(dt, trk + 7 * t);
+    int64_t s = orc_deposit_step(dt, trk + TRK * t);
     if (s < max_steps && s > last_deposit) last_deposit = s;
   }
   const double beta = p[P_ALPHA] * dt;
-  double released = 0.0, sums[5] = {0, 0, 0, 0, 0}, screened[2] = {0, 0}, last[T_COUNT] = {0};
+  double released = 0.0, released_neg = 0.0, sums[5] = {0, 0, 0, 0, 0}, screened[2] = {0, 0};
+  double last[T_COUNT] = {0};
   double max_beta_n = 0.0;
   int flags = 0;
   int64_t steps = 0;
   for (int64_t l = 0; l < max_steps; ++l) {
     int deposited = 0;
-    double released_now = 0.0;
+    double released_now = 0.0, released_now_neg = 0.0;
     if (l == 0 && p[P_UNIFORM_N0] != 0.0) {
-      released_now += orc_uniform(p, nx, ny, nz, p[P_UNIFORM_N0], pos, neg);
+      const double u0 = orc_uniform(p, nx, ny, nz, p[P_UNIFORM_N0], pos, neg);
+      released_now += u0;
+      released_now_neg += u0;
       deposited = 1;
     }
     for (int64_t t = 0; t < ntr; ++t)
-      if (orc_deposit_step(dt, trk + 7 * t) == l) { deposited = 1; break; }
+      if (orc_deposit_step(dt, trk + TRK * t) == l) { deposited = 1; break; }
     if (deposited) {
-      released_now += orc_deposit(p, nx, ny, nz, trk, ntr, l, dt, pos, neg);
+      double rel[2];
+      orc_deposit(p, nx, ny, nz, trk, ntr, l, dt, pos, neg, rel);
+      released_now += rel[0];
+      released_now_neg += rel[1];
       const double m = beta * field_max(n, pos, neg);
       if (m > max_beta_n) max_beta_n = m;
     }
     released += released_now;
+    released_neg += released_now_neg;
     double tally[T_COUNT];
     orc_step(p, nx, ny, nz, dt, pos, neg, npos, nneg, tally);
     tally[T_RELEASED] = released_now;
+    tally[T_RELEASED_NEG] = released_now_neg;
     double *tmp = pos; pos = npos; npos = tmp;
     tmp = neg; neg = nneg; nneg = tmp;
     for (int q = 0; q < 5; ++q) sums[q] += tally[q];
@@ -433,7 +461,7 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
     for (int q = 0; q < T_COUNT; ++q) finite &= isfinite(tally[q]) != 0;
     if (!finite) { flags |= FLAG_NONFINITE; break; }
     if (l >= last_deposit && tally[T_POS_ABS] <= p[P_STOP_TOL] * released &&
-        tally[T_NEG_ABS] <= p[P_STOP_TOL] * released)
+        tally[T_NEG_ABS] <= p[P_STOP_TOL] * released_neg)
       break;
     if (steps == max_steps) flags |= FLAG_MAX_STEPS;
   }
@@ -450,15 +478,16 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   if (max_beta_n > 1.0) flags |= FLAG_REACTION;
   const double collected = sums[1] + sums[2] + sums[3] + sums[4];
   double f;
-  if (released > 0.0) {
-    f = collected / (2.0 * released);
+  if (released + released_neg > 0.0) {
+    f = collected / (released + released_neg);
   } else {
     f = 1.0;
     flags |= FLAG_EMPTY;
   }
   res[R_F] = f;
   res[R_KS] = 1.0 / f;
-  res[R_F_RECOMB] = released > 0.0 ? 1.0 - sums[0] / released : 1.0;
+  /* recombined pairs against the mean number released per species */
+  res[R_F_RECOMB] = released + released_neg > 0.0 ? 1.0 - 2.0 * sums[0] / (released + released_neg) : 1.0;
   res[R_RELEASED] = released;
   res[R_RECOMBINED] = sums[0];
   res[R_INFLIGHT_POS] = last[T_POS_INFLIGHT];
@@ -471,6 +500,7 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   res[R_STEPS] = (double)steps;
   res[R_FLAGS] = (double)flags;
   res[R_MAX_BETA_N] = max_beta_n;
+  res[R_RELEASED_NEG] = released_neg;
   res[R_SC_POS] = screened[0];
   res[R_SC_NEG] = screened[1];
   return 0;

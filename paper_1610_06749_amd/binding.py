@@ -3,7 +3,7 @@
 Argument marshalling only: every step of the method runs in the HIP library.
 PyTorch provides device memory (workspace and field tensors) and the HIP
 stream.  The functions carry the C names; chambers are the dictionaries of
-``workloads`` and track lists are float64 arrays of shape (n, 7) whose rows
+``workloads`` and track lists are float64 arrays of shape (n, 7) or (n, 8) whose rows
 have the layout of ``it_track``.
 """
 from __future__ import annotations
@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libiontracks.so")
 
 IT_OK, IT_EINVAL, IT_ENODT, IT_EWORKSPACE, IT_EHIP, IT_ENOTSUP = 0, -1, -2, -3, -4, -5
 IT_FLAG_MAX_STEPS, IT_FLAG_NONFINITE, IT_FLAG_REACTION, IT_FLAG_EMPTY = 1, 2, 4, 8
-IT_TRACE_COLS = 12
+IT_TRACE_COLS = 13
 IT_KERNEL_AUTO, IT_KERNEL_PLAIN, IT_KERNEL_BLOCKED = 0, 1, 2
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
               "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
-              "neg_space_charge")
+              "neg_space_charge", "released_neg")
 
 
 class ItError(RuntimeError):
@@ -46,7 +46,7 @@ class it_result(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in (
         "f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos", "n_inflight_neg",
         "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "max_beta_n",
-        "n_space_charge_pos", "n_space_charge_neg")] + \
+        "n_space_charge_pos", "n_space_charge_neg", "n_released_neg")] + \
         [("steps", ctypes.c_int64), ("flags", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
 
@@ -117,8 +117,23 @@ def _chamber(ch) -> it_chamber:
     return c
 
 
+TRACK_COLS = 8  # it_track: let, b, x, y, theta, phi, t, b_neg (0: the negative ions share b)
+
+
+def _track_rows(tracks):
+    """Track rows as the C ABI's it_track: 8 doubles (7-column rows get
+    b_neg = 0)."""
+    a = np.asarray(tracks, dtype=np.float64)
+    a = a.reshape(-1, a.shape[-1] if a.ndim > 1 else 7)
+    if a.shape[1] == 7:
+        a = np.concatenate([a, np.zeros((a.shape[0], 1))], axis=1)
+    if a.shape[1] != TRACK_COLS:
+        raise ValueError("track rows need 7 or 8 columns")
+    return np.ascontiguousarray(a)
+
+
 def _tracks(tracks):
-    tr = np.ascontiguousarray(np.asarray(tracks, dtype=np.float64).reshape(-1, 7))
+    tr = _track_rows(tracks)
     return tr, (tr.ctypes.data if tr.shape[0] else None)
 
 
@@ -267,10 +282,10 @@ def it_advance(ch, dt, pos, neg, nsteps, exec=None, ws=None, stream=None, trace=
 def _batch_args(chambers, track_lists):
     n = len(chambers)
     chs = (it_chamber * n)(*[_chamber(c) for c in chambers])
-    lists = [np.asarray(t, dtype=np.float64).reshape(-1, 7) for t in track_lists]
+    lists = [_track_rows(t) for t in track_lists]
     offsets = np.zeros(n + 1, dtype=np.int64)
     offsets[1:] = np.cumsum([t.shape[0] for t in lists])
-    tracks = np.ascontiguousarray(np.concatenate(lists) if offsets[-1] else np.zeros((1, 7)))
+    tracks = np.ascontiguousarray(np.concatenate(lists) if offsets[-1] else np.zeros((1, TRACK_COLS)))
     return n, chs, offsets, tracks
 
 
@@ -283,7 +298,7 @@ def it_workspace_size_batch(chambers, track_lists, exec=None) -> int:
 
 
 def it_solve_batch(chambers, track_lists, exec=None, ws=None, stream=None) -> list:
-    """Runs a sweep of chambers (list of dicts, list of (n_q, 7) track arrays)
+    """Runs a sweep of chambers (list of dicts, list of (n_q, 7 or 8) track arrays)
     to completion in batched launches; returns one result dict per chamber."""
     import torch
     n, chs, offsets, tracks = _batch_args(chambers, track_lists)

@@ -35,8 +35,10 @@ struct Coef {
 
 // Device-resident run state, updated only by the last block of each launch.
 struct RunState {
-  double released;          // ion pairs released so far
-  double released_pending;  // released since the last recorded step
+  double released;          // positive ions released so far
+  double released_pending;  // positive ions released since the last recorded step
+  double released_neg;      // the same for the negative ions (equal unless the
+  double released_pending_neg;  // tracks give them their own radius)
   double sums[5];           // running recombined, pos anode/cathode, neg anode/cathode
   double last[4];           // in-flight pos/neg and |n| sums after the last step
   double max_beta_n;        // max over deposits of beta * max(n)
@@ -55,6 +57,7 @@ struct DepTrack {
   double peak;              // N0 / (pi b^2)
   double inv_b2;            // 1 / b^2
   double cut2;              // (8 b)^2
+  double peak_n, inv_b2_n, cut2_n;  // the same with the negative ions' radius
 };
 
 struct StepParams {
@@ -92,7 +95,8 @@ struct DepositParams {
   const DepTrack* tilt;     // tilted tracks
   int ntilt;
   double dV, beta;
-  double* partials;         // [gridDim][2]
+  int same_radii;           // 1: every track gives both species the same radius
+  double* partials;         // [gridDim][3]
   unsigned* counter;
   RunState* state;
 };

@@ -76,18 +76,25 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
 
 __device__ inline double wrap_near(double d, double L) { return d - L * floor(d / L + 0.5); }
 
-__device__ inline double track_value(const DepTrack& tr, double wx, double wy, double wz) {
+__device__ inline double axis_r2(const DepTrack& tr, double wx, double wy, double wz) {
   const double cx = wy * tr.uz - wz * tr.uy;
   const double cy = wz * tr.ux - wx * tr.uz;
   const double cz = wx * tr.uy - wy * tr.ux;
-  const double r2 = cx * cx + cy * cy + cz * cz;
-  return r2 > tr.cut2 ? 0.0 : tr.peak * exp(-r2 * tr.inv_b2);
+  return cx * cx + cy * cy + cz * cz;
+}
+
+// Densities of the positive and (with its own radius) negative ions.
+__device__ inline void track_values(const DepTrack& tr, double wx, double wy, double wz, bool same,
+                                    double& dp, double& dn) {
+  const double r2 = axis_r2(tr, wx, wy, wz);
+  dp = r2 > tr.cut2 ? 0.0 : tr.peak * exp(-r2 * tr.inv_b2);
+  dn = same ? dp : (r2 > tr.cut2_n ? 0.0 : tr.peak_n * exp(-r2 * tr.inv_b2_n));
 }
 
 __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
-  __shared__ double lds[(kNT / kWave) * 2];
-  __shared__ double totals[2];
-  double sum = 0.0, mx = 0.0;
+  __shared__ double lds[(kNT / kWave) * 3];
+  double sum_p = 0.0, sum_n = 0.0, mx = 0.0;
+  const bool same = p.same_radii != 0;
   const TileCoord t = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
   const int i = t.tx * kTX + threadIdx.x;
   const int j = t.ty * kTY + threadIdx.y;
@@ -95,76 +102,89 @@ __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
     const int k0 = 1 + t.zc * p.zc;
     const int k1 = min(k0 + p.zc, p.nz);
     const double x = i * p.dx, y = j * p.dy;
-    double g0 = p.uniform;
+    double g0p = p.uniform, g0n = p.uniform;
     for (int q = 0; q < p.npar; ++q) {
       const DepTrack tr = p.par[q];
-      g0 += track_value(tr, wrap_near(x - tr.x0, p.Lx), wrap_near(y - tr.y0, p.Ly), 0.0);
+      double dp, dn;
+      track_values(tr, wrap_near(x - tr.x0, p.Lx), wrap_near(y - tr.y0, p.Ly), 0.0, same, dp, dn);
+      g0p += dp;
+      g0n += dn;
     }
     const size_t plane = (size_t)p.nx * p.ny;
     size_t c = (size_t)k0 * plane + (size_t)j * p.nx + i;
     for (int k = k0; k < k1; ++k, c += plane) {
-      double d = g0;
+      double d_p = g0p, d_n = g0n;
       if (p.ntilt) {
         const double wz = k * p.dz - p.half_gap;
         for (int q = 0; q < p.ntilt; ++q) {
           const DepTrack tr = p.tilt[q];
-          d += track_value(tr, wrap_near(x - tr.x0, p.Lx), wrap_near(y - tr.y0, p.Ly), wz);
+          double dp, dn;
+          track_values(tr, wrap_near(x - tr.x0, p.Lx), wrap_near(y - tr.y0, p.Ly), wz, same, dp, dn);
+          d_p += dp;
+          d_n += dn;
         }
       }
-      const double a = p.pos[c] + d, b = p.neg[c] + d;
+      const double a = p.pos[c] + d_p, b = p.neg[c] + d_n;
       p.pos[c] = a;
       p.neg[c] = b;
-      sum += d;
+      sum_p += d_p;
+      sum_n += d_n;
       mx = fmax(mx, fmax(a, b));
     }
   }
-  // block partials: [sum, max]
+  // block partials: [released+, released-, max]
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   {
-    double s = wave_sum(sum), m = wave_max(mx);
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const double s0 = wave_sum(sum_p), s1 = wave_sum(sum_n), m = wave_max(mx);
     if (tid % kWave == 0) {
-      lds[(tid / kWave) * 2] = s;
-      lds[(tid / kWave) * 2 + 1] = m;
+      lds[(tid / kWave) * 3] = s0;
+      lds[(tid / kWave) * 3 + 1] = s1;
+      lds[(tid / kWave) * 3 + 2] = m;
     }
     __syncthreads();
     if (tid == 0) {
-      double ss = lds[0], mm = lds[1];
+      double a0 = lds[0], a1 = lds[1], mm = lds[2];
       for (int w = 1; w < kNT / kWave; ++w) {
-        ss += lds[w * 2];
-        mm = fmax(mm, lds[w * 2 + 1]);
+        a0 += lds[w * 3];
+        a1 += lds[w * 3 + 1];
+        mm = fmax(mm, lds[w * 3 + 2]);
       }
-      p.partials[(size_t)blockIdx.x * 2] = ss;
-      p.partials[(size_t)blockIdx.x * 2 + 1] = mm;
+      p.partials[(size_t)blockIdx.x * 3] = a0;
+      p.partials[(size_t)blockIdx.x * 3 + 1] = a1;
+      p.partials[(size_t)blockIdx.x * 3 + 2] = mm;
     }
   }
   if (!arrive_last<kNT>(p.counter)) return;
-  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   {
-    double s = 0.0, m = 0.0;
+    double s0 = 0.0, s1 = 0.0, m = 0.0;
     for (int b = tid; b < (int)gridDim.x; b += kNT) {
-      s += p.partials[(size_t)b * 2];
-      m = fmax(m, p.partials[(size_t)b * 2 + 1]);
+      s0 += p.partials[(size_t)b * 3];
+      s1 += p.partials[(size_t)b * 3 + 1];
+      m = fmax(m, p.partials[(size_t)b * 3 + 2]);
     }
-    s = wave_sum(s);
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
     m = wave_max(m);
     __syncthreads();
     if (tid % kWave == 0) {
-      lds[(tid / kWave) * 2] = s;
-      lds[(tid / kWave) * 2 + 1] = m;
+      lds[(tid / kWave) * 3] = s0;
+      lds[(tid / kWave) * 3 + 1] = s1;
+      lds[(tid / kWave) * 3 + 2] = m;
     }
     __syncthreads();
     if (tid == 0) {
-      double ss = lds[0], mm = lds[1];
+      double a0 = lds[0], a1 = lds[1], mm = lds[2];
       for (int w = 1; w < kNT / kWave; ++w) {
-        ss += lds[w * 2];
-        mm = fmax(mm, lds[w * 2 + 1]);
+        a0 += lds[w * 3];
+        a1 += lds[w * 3 + 1];
+        mm = fmax(mm, lds[w * 3 + 2]);
       }
-      totals[0] = ss;
-      totals[1] = mm;
       RunState* st = p.state;
-      const double rel = ss * p.dV;
-      st->released += rel;
-      st->released_pending += rel;
+      const double rp = a0 * p.dV, rn = a1 * p.dV;
+      st->released += rp;
+      st->released_pending += rp;
+      st->released_neg += rn;
+      st->released_pending_neg += rn;
       st->max_beta_n = fmax(st->max_beta_n, p.beta * mm);
       *p.counter = 0u;
     }

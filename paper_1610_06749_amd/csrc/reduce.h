@@ -128,7 +128,9 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
     rec[9] = st.released_pending;
     rec[10] = a[9] * dV;
     rec[11] = a[10] * dV;
+    rec[12] = st.released_pending_neg;
     st.released_pending = 0.0;
+    st.released_pending_neg = 0.0;
     bool finite = true;
     for (int q = 0; q < IT_TRACE_COLS; ++q) {
       if (trace) trace[l * IT_TRACE_COLS + q] = rec[q];
@@ -144,8 +146,7 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
       st.done = 1;
       break;
     }
-    const double lim = stop_tol * st.released;
-    if (l >= min_stop_step && rec[7] <= lim && rec[8] <= lim) {
+    if (l >= min_stop_step && rec[7] <= stop_tol * st.released && rec[8] <= stop_tol * st.released_neg) {
       st.done = 1;
       break;
     }

@@ -80,7 +80,7 @@ double reference_density(const it_chamber* ch, const it_track* tr, int64_t n) {
   const double Lx = ch->nx * ch->dx, Ly = ch->ny * ch->dy;
   double best = 0.0;
   for (int64_t a = 0; a < n; ++a) {
-    double s = 0.0;
+    double s[2] = {0.0, 0.0};
     for (int64_t q = 0; q < n; ++q) {
       const it_track& t = tr[q];
       if (t.t_s != tr[a].t_s) continue;
@@ -92,11 +92,14 @@ double reference_density(const it_chamber* ch, const it_track* tr, int64_t n) {
       const double wz = 0.0;
       const double cx = wy * uz - wz * uy, cy = wz * ux - wx * uz, cz = wx * uy - wy * ux;
       const double r2 = cx * cx + cy * cy + cz * cz;
-      const double b2 = t.b_cm * t.b_cm;
-      if (r2 > 64.0 * b2) continue;
-      s += t.let_keV_um * 1.0e7 / ch->W_eV / (M_PI * b2) * std::exp(-r2 / b2);
+      for (int sp = 0; sp < 2; ++sp) {  // both species' radii
+        const double b = sp == 1 && t.b_neg_cm > 0.0 ? t.b_neg_cm : t.b_cm;
+        const double b2 = b * b;
+        if (r2 > 64.0 * b2) continue;
+        s[sp] += t.let_keV_um * 1.0e7 / ch->W_eV / (M_PI * b2) * std::exp(-r2 / b2);
+      }
     }
-    best = std::max(best, s);
+    best = std::max(best, std::max(s[0], s[1]));
   }
   return ch->uniform_n0 + best;
 }
@@ -273,6 +276,7 @@ int check_tracks(const it_track* tr, int64_t n) {
     if (!std::isfinite(t.x_cm) || !std::isfinite(t.y_cm)) return IT_EINVAL;
     if (!std::isfinite(t.theta) || !std::isfinite(t.phi)) return IT_EINVAL;
     if (!finite_nonneg(t.t_s)) return IT_EINVAL;
+    if (!finite_nonneg(t.b_neg_cm)) return IT_EINVAL;
   }
   return IT_OK;
 }
@@ -302,6 +306,13 @@ RunState* pinned_slots() {
     if ((expr) != hipSuccess) return IT_EHIP;       \
   } while (0)
 
+// 1 when every track gives both species the same radius.
+int same_radii(const it_track* tr, int64_t n) {
+  for (int64_t q = 0; q < n; ++q)
+    if (tr[q].b_neg_cm > 0.0 && tr[q].b_neg_cm != tr[q].b_cm) return 0;
+  return 1;
+}
+
 // Per-track constants of the deposit kernel: axis direction, peak density
 // N0/(pi b^2) with N0 = LET/W (keV/um -> eV/cm), 1/b^2 and the (8b)^2 cut.
 DepTrack prepare_track(const it_chamber* ch, const it_track& t) {
@@ -315,6 +326,10 @@ DepTrack prepare_track(const it_chamber* ch, const it_track& t) {
   d.peak = N0 / (M_PI * t.b_cm * t.b_cm);
   d.inv_b2 = 1.0 / (t.b_cm * t.b_cm);
   d.cut2 = 64.0 * t.b_cm * t.b_cm;
+  const double bn = t.b_neg_cm > 0.0 ? t.b_neg_cm : t.b_cm;
+  d.peak_n = N0 / (M_PI * bn * bn);
+  d.inv_b2_n = 1.0 / (bn * bn);
+  d.cut2_n = 64.0 * bn * bn;
   return d;
 }
 
@@ -329,7 +344,7 @@ struct Event {
 // `check_every` steps (two checks in flight) to stop once the device has
 // flagged completion.
 int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const Layout& L,
-             const std::vector<Event>& events, const std::vector<DepTrack>& dev_tracks,
+             const std::vector<Event>& events, const std::vector<DepTrack>& dev_tracks, int same_r,
              int64_t nsteps, int64_t min_stop_step, double stop_tol, hipStream_t stream,
              RunState* final_state, int* passes_issued) {
   const int kernel = ex ? ex->kernel : IT_KERNEL_AUTO;
@@ -396,6 +411,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   dp.Ly = ch->ny * ch->dy;
   dp.dV = dV;
   dp.beta = ch->alpha * dt;
+  dp.same_radii = same_r;
   dp.partials = partials;
   dp.counter = counter;
   dp.state = state;
@@ -529,7 +545,7 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.ntiles = ts.ntiles;
     L.off_partials = off;
-    off = align_up(off + std::max((size_t)ts.ntiles * kAcc, (size_t)td.grid * 2) * sizeof(double));
+    off = align_up(off + std::max((size_t)ts.ntiles * kAcc, (size_t)td.grid * 3) * sizeof(double));
     L.off_counter = off;
     off = align_up(off + 64 * sizeof(unsigned));
     L.off_tracks = off;
@@ -589,9 +605,10 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   // stopped by the step limit (the criterion may also fire on the last step)
   if (fin.steps >= max_steps && (!fin.done || fin.by_limit)) flags |= IT_FLAG_MAX_STEPS;
   if (fin.max_beta_n > 1.0) flags |= IT_FLAG_REACTION;
-  if (fin.released > 0.0) {
-    out->f = collected / (2.0 * fin.released);
-    out->f_R = 1.0 - fin.sums[0] / fin.released;
+  const double released = fin.released + fin.released_neg;
+  if (released > 0.0) {
+    out->f = collected / released;
+    out->f_R = 1.0 - 2.0 * fin.sums[0] / released;
   } else {
     out->f = 1.0;
     out->f_R = 1.0;
@@ -599,6 +616,7 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   }
   out->ks = 1.0 / out->f;
   out->n_released = fin.released;
+  out->n_released_neg = fin.released_neg;
   out->n_recombined = fin.sums[0];
   out->n_inflight_pos = fin.last[0];
   out->n_inflight_neg = fin.last[1];
@@ -728,7 +746,7 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
 
   RunState fin;
   int issued = 0;
-  rc = run_loop(ch, dt, exec, ws, L, events, dev, ch->max_steps, std::max<int64_t>(last_dep, 0),
+  rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ch->max_steps, std::max<int64_t>(last_dep, 0),
                 ch->stop_tol, stream, &fin, &issued);
   if (rc) return rc;
 
@@ -875,6 +893,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       dp.ntilt = (int)(n - npar);
       dp.dV = dV;
       dp.beta = c->alpha * dts[q];
+      dp.same_radii = same_radii(tq, n);
       dp.partials = (double*)(ws + L.off_partials);
       dp.counter = (unsigned*)(ws + L.off_counter);
       dp.state = states + q;
@@ -1007,7 +1026,7 @@ int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* e
   std::vector<DepTrack> nodev;
   RunState fin;
   int issued = 0;
-  rc = run_loop(ch, dt, exec, ws, L, none, nodev, nsteps, INT64_MAX, 0.0, stream, &fin, &issued);
+  rc = run_loop(ch, dt, exec, ws, L, none, nodev, 1, nsteps, INT64_MAX, 0.0, stream, &fin, &issued);
   if (rc) return rc;
   const int last = fin.passes & 1;
   HIP_TRY(hipMemcpyAsync(d_pos, ws + L.off_field[2 * last], bytes, hipMemcpyDeviceToDevice, stream));

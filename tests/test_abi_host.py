@@ -75,6 +75,18 @@ def test_workspace_size_covers_fields_and_trace(lib):
     assert lib.it_workspace_size(dict(ch, max_steps=10), 400) < n
 
 
+def test_separate_radius_checks_and_dt(lib, orc):
+    ch, tr = W.single_track()
+    t8 = np.concatenate([tr, 0.5 * tr[:, 1:2]], axis=1)  # a narrower negative column: higher peak
+    assert lib.it_dt(ch, t8) == pytest.approx(orc.dt(ch, t8), rel=1e-14)
+    assert lib.it_dt(ch, t8) < lib.it_dt(ch, tr)
+    bad = t8.copy()
+    bad[0, 7] = -1e-3
+    with pytest.raises(lib.ItError) as e:
+        lib.it_validate(ch, bad)
+    assert e.value.code == lib.IT_EINVAL
+
+
 def test_space_charge_flag_values(lib):
     ch, tr = W.single_track(space_charge=1)
     lib.it_validate(ch, tr)

@@ -70,6 +70,18 @@ def test_batch_with_space_charge_on_some_instances(gpu, orc):
         assert (o["n_space_charge_pos"] != 0.0) == bool(ch["space_charge"])
 
 
+def test_batch_with_separate_radii(gpu, orc):
+    chs, trs = small_sweep(n=3, seed=14)
+    t = trs[0]
+    trs[0] = np.concatenate([t, 1.4 * t[:, 1:2]], axis=1)  # b- = 1.4 b
+    res = gpu.it_solve_batch(chs, trs)
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        assert g["steps"] == o["steps"] and g["flags"] == o["flags"]
+        assert g["f"] == pytest.approx(o["f"], rel=1e-9)
+        assert g["n_released_neg"] == pytest.approx(o["n_released_neg"], rel=1e-9)
+
+
 def test_batch_equals_single_runs(gpu):
     chs, trs = small_sweep(n=4, seed=9)
     res = gpu.it_solve_batch(chs, trs)

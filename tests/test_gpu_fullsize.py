@@ -65,20 +65,24 @@ def check_fields(g, summary):
 
 def check_conservation(trace, N, tol=1e-12):
     tr = np.asarray(trace)
-    for a, c, S, Q in ((1, 2, 5, 10), (3, 4, 6, 11)):
-        prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, 9]
+    for a, c, S, Q, rel in ((1, 2, 5, 10, 9), (3, 4, 6, 11, 12)):
+        prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, rel]
         err = prev - tr[:, a] - tr[:, c] - tr[:, 0] + tr[:, Q] - tr[:, S]
         assert np.max(np.abs(err)) <= tol * N
 
 
 def check_trace(got, stored, N):
-    # stored traces may hold only the leading columns (those without the
-    # space-charge term); the others must then be zero
+    # stored traces may hold only the leading ten columns (written before the
+    # space-charge and negative-release columns existed): the space-charge
+    # columns must then be zero and the negative-release column equal the
+    # positive one (one radius per track)
     ref = np.asarray(stored)
     k = ref.shape[1]
     assert got.shape[0] == ref.shape[0]
     assert np.max(np.abs(got[:, :k] - ref)) <= RTOL * N
-    assert np.all(got[:, k:] == 0.0)
+    if k == 10:
+        assert np.all(got[:, 10:12] == 0.0)
+        assert np.array_equal(got[:, 12], got[:, 9])
 
 
 def test_single_track_against_stored(gpu):

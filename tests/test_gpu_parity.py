@@ -130,6 +130,30 @@ def test_space_charge_ragged_grid_fields(gpu, orc, ex):
     compare_fields(g["neg"], o["neg"])
 
 
+def with_bneg(tr, factors):
+    out = np.concatenate([tr, np.zeros((tr.shape[0], 1))], axis=1)
+    out[:, 7] = np.asarray(factors) * tr[:, 1]
+    return out
+
+
+@pytest.mark.parametrize("ex", SC_EXECS, ids=SC_IDS)
+def test_separate_radii_single_track_full_run(gpu, orc, ex):
+    """The negative ions' column 1.5 times wider than the positive ions'."""
+    ch, tr = W.single_track()
+    tr[0, 0] = 20.0
+    g, o = run_both(gpu, orc, ch, with_bneg(tr, [1.5]), exec=ex, fields=False)
+    assert g["n_released_neg"] == pytest.approx(o["n_released_neg"], rel=RTOL)
+    assert o["n_released_neg"] != o["n_released"]
+
+
+@pytest.mark.parametrize("ex", SC_EXECS, ids=SC_IDS)
+def test_separate_radii_ragged_grid_fields(gpu, orc, ex):
+    ch, tr = ragged_case(max_steps=40, stop_tol=0.0)
+    g, o = run_both(gpu, orc, ch, with_bneg(tr, [1.3, 0.0, 1.6, 1.0]), exec=ex)
+    compare_fields(g["pos"], o["pos"])
+    compare_fields(g["neg"], o["neg"])
+
+
 @pytest.mark.parametrize("deg", [30, 60, 90])
 def test_tilted_single_track_full_run(gpu, orc, deg):
     """The tilted tracks of the Jaffe angular comparison, run to collection."""

@@ -351,8 +351,9 @@ def _check_conservation(r, tol=1e-12):
     tr = r["trace"]
     N = r["n_released"]
     assert tr[:, 9].sum() == pytest.approx(N, rel=1e-14)
-    for s, (a, c, S, Q) in enumerate(((1, 2, 5, 10), (3, 4, 6, 11))):
-        prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, 9]
+    assert tr[:, 12].sum() == pytest.approx(r["n_released_neg"], rel=1e-14)
+    for s, (a, c, S, Q, rel) in enumerate(((1, 2, 5, 10, 9), (3, 4, 6, 11, 12))):
+        prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, rel]
         err = prev - tr[:, a] - tr[:, c] - tr[:, 0] + tr[:, Q] - tr[:, S]
         assert np.max(np.abs(err)) <= tol * N
 
@@ -384,6 +385,74 @@ def test_conservation_with_space_charge(orc):
     # positive ions have drifted ahead, n- where the negative ones have
     assert r["n_space_charge_pos"] < 0.0 and r["n_space_charge_neg"] < 0.0
     assert r["n_space_charge_pos"] == pytest.approx(r["trace"][:, 10].sum(), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# separate track radii of the two species (b- > b+, "The charge carrier
+# distribution in the track")
+# ---------------------------------------------------------------------------
+
+def _with_bneg(tr, factor):
+    out = np.concatenate([tr, np.zeros((tr.shape[0], 1))], axis=1)
+    out[:, 7] = factor * tr[:, 1]
+    return out
+
+
+def test_equal_radii_reproduce_the_shared_radius(orc):
+    ch, tr = W.single_track(max_steps=40, stop_tol=0.0)
+    tr[0, 0] = 20.0
+    a = orc.solve(ch, tr)
+    b = orc.solve(ch, _with_bneg(tr, 1.0))
+    assert a["f"] == b["f"] and np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["neg"], b["neg"])
+
+
+def test_separate_radii_conservation_and_released(orc):
+    ch, tr = W.single_track()
+    tr[0, 0] = 20.0
+    r = orc.solve(ch, _with_bneg(tr, 1.5), with_trace=True, with_fields=False)
+    _check_conservation(r)
+    # both species carry N0 per unit length (Poisson summation of the
+    # columns); the wider one loses the Gaussian's mass beyond the minimum
+    # image, half a cell = 4.3 b- away: e^{-4.3^2} ~ 1e-8
+    N0l = 20.0 * 1e7 / ch["W_eV"] * ch["gap"] * (ch["nz"] - 1) / ch["nz"]
+    assert r["n_released"] == pytest.approx(N0l, rel=1e-9)
+    assert r["n_released_neg"] == pytest.approx(N0l, rel=1e-7)
+    assert r["f"] == pytest.approx((r["col_pos_anode"] + r["col_pos_cathode"] + r["col_neg_anode"]
+                                    + r["col_neg_cathode"]) / (r["n_released"] + r["n_released_neg"]), rel=1e-14)
+
+
+def test_wider_negative_track_recombines_less(orc):
+    """A wider negative-ion column overlaps the positive one less densely:
+    f rises from (b, b) to (b, 1.5 b), and stays below (1.5 b, 1.5 b)."""
+    ch, tr = W.single_track()
+    tr[0, 0] = 20.0
+    f_bb = orc.solve(ch, tr, with_fields=False)["f"]
+    f_bw = orc.solve(ch, _with_bneg(tr, 1.5), with_fields=False)["f"]
+    wide = tr.copy()
+    wide[0, 1] *= 1.5
+    f_ww = orc.solve(ch, wide, with_fields=False)["f"]
+    assert f_bb < f_bw < f_ww
+
+
+def test_separate_radii_swap_mirror_symmetry(orc):
+    """Exchanging the species (mobilities, diffusion constants and radii)
+    and mirroring z maps the run onto itself."""
+    base = dict(mu_pos=1.73, mu_neg=1.87, D_pos=0.045, D_neg=0.06)
+    swap = dict(mu_pos=1.87, mu_neg=1.73, D_pos=0.06, D_neg=0.045)
+    ch1, tr = W.single_track(**base)
+    ch2, _ = W.single_track(**swap)
+    tr[0, 0] = 20.0
+    t1 = _with_bneg(tr, 1.4)
+    t2 = t1.copy()
+    t2[0, 1], t2[0, 7] = t1[0, 7], t1[0, 1]
+    ch1["max_steps"] = ch2["max_steps"] = 60
+    ch1["stop_tol"] = ch2["stop_tol"] = 0.0
+    r1 = orc.solve(ch1, t1)
+    r2 = orc.solve(ch2, t2)
+    assert r2["f"] == pytest.approx(r1["f"], rel=1e-12)
+    scale = max(r1["neg"].max(), r1["pos"].max())
+    assert np.max(np.abs(r2["pos"] - r1["neg"][::-1])) <= 1e-12 * scale
+    assert np.max(np.abs(r2["neg"] - r1["pos"][::-1])) <= 1e-12 * scale
 
 
 # ---------------------------------------------------------------------------
