@@ -154,6 +154,21 @@ def test_separate_radii_ragged_grid_fields(gpu, orc, ex):
     compare_fields(g["neg"], o["neg"])
 
 
+@pytest.mark.parametrize("ex", [dict(kernel=1, tile_y=8), dict(kernel=2, steps_per_pass=4)], ids=["plain8", "blocked4"])
+def test_shaped_pulse_full_run(gpu, orc, ex):
+    """A pulse of finite length: tracks arriving over about 30 steps with a
+    triangular rate g(t), tilted, at many different deposit steps."""
+    ch = W.chamber(48, 40, 30, 3e-4, 30 * 3e-4, 20.0)
+    dt0 = orc.dt(ch, W.tracks([[30.0, 8e-4, 0.0, 0.0, 0.0, 0.0, 0.0]]))
+    T = 30 * dt0
+    g = lambda t: (4.0 / T**2) * (t if t < T / 2 else T - t)
+    tr = W.shaped_pulse(ch, 7, 1e5, g, T, 2.0 / T, let=lambda rng, n: rng.uniform(5, 30, n), b=8e-4,
+                        theta=0.3)
+    assert len(tr) > 8
+    g_, o = run_both(gpu, orc, ch, tr, exec=ex, fields=False)
+    assert len(np.unique(np.floor(tr[:, 6] / o["dt"]))) > 5  # several deposit events
+
+
 @pytest.mark.parametrize("deg", [30, 60, 90])
 def test_tilted_single_track_full_run(gpu, orc, deg):
     """The tilted tracks of the Jaffe angular comparison, run to collection."""

@@ -1,0 +1,46 @@
+"""Input generators: the shaped pulse's arrival process and placement."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _tri(T):
+    # triangular pulse on [0, T], unit integral, peak 2/T at T/2
+    return lambda t: (4.0 / T**2) * (t if t < T / 2 else T - t), 2.0 / T
+
+
+def test_shaped_pulse_counts_and_mean_time():
+    """Counts are Poisson with mean fluence * area; arrival times follow
+    g(t): the triangular pulse's mean time is T/2 and its variance T^2/24."""
+    ch = W.chamber(64, 64, 10, 5e-4, 5e-3, 100.0)
+    area = 64 * 5e-4 * 64 * 5e-4
+    T = 2e-6
+    g, gmax = _tri(T)
+    counts, times = [], []
+    for seed in range(200):
+        tr = W.shaped_pulse(ch, seed, 3e6, g, T, gmax)
+        counts.append(len(tr))
+        times.extend(tr[:, 6])
+    mean = 3e6 * area
+    assert np.mean(counts) == pytest.approx(mean, rel=4 * math.sqrt(mean / 200) / mean)
+    times = np.asarray(times)
+    n = len(times)
+    assert times.mean() == pytest.approx(T / 2, abs=4 * T / math.sqrt(24 * n))
+    assert times.var() == pytest.approx(T**2 / 24, rel=0.1)
+    assert np.all((times >= 0) & (times < T))
+
+
+def test_shaped_pulse_disc_region_and_values():
+    ch = W.chamber(64, 64, 10, 5e-4, 5e-3, 100.0)
+    r = 5e-3
+    tr = W.shaped_pulse(ch, 3, 2e7, lambda t: 1e6, 1e-6, 1e6, let=lambda rng, n: rng.uniform(1, 2, n),
+                        b=8e-4, theta=0.3, region="disc", r_min=r)
+    cx, cy = 32 * 5e-4, 32 * 5e-4
+    d = np.hypot(tr[:, 2] - cx, tr[:, 3] - cy)
+    assert len(tr) > 100 and np.all(d <= r)
+    # uniform over the disc: the mean squared radius is r^2/2
+    assert np.mean(d**2) == pytest.approx(r * r / 2, rel=0.15)
+    assert np.all((tr[:, 0] >= 1) & (tr[:, 0] <= 2)) and np.all(tr[:, 1] == 8e-4) and np.all(tr[:, 4] == 0.3)

@@ -161,6 +161,50 @@ def continuous_beam(seed: int = SEED_BASE + 3, duration_s: float = 0.0, forced: 
     return ch, tracks(np.stack([let, b, x, y, theta, phi, np.asarray(times)], axis=1))
 
 
+def shaped_pulse(ch, seed: int, fluence_cm2: float, shape, t_end: float, shape_max: float, let=50.0,
+                 b=1e-3, theta=0.0, region: str = "cell", r_min: float | None = None) -> np.ndarray:
+    """Tracks of a pulse of finite length (section "Distribution of ion
+    tracks"): arrival times form a Poisson process of rate
+    fluence_cm2 * area * shape(t) on [0, t_end), where shape(t) [1/s] is the
+    pulse shape g(t) normalised to unit integral and shape_max bounds it
+    (sampled by thinning a homogeneous process of rate fluence * area *
+    shape_max).  Positions are uniform over the transverse cell
+    (region="cell") or over a centred disc of radius r_min (region="disc",
+    area pi r_min^2).  let, b: scalars or callables of the generator (one
+    value per track); theta: tilt to the field, azimuths uniform."""
+    rng = np.random.default_rng(seed)
+    lx, ly = ch["nx"] * ch["dx"], ch["ny"] * ch["dy"]
+    if region == "cell":
+        area = lx * ly
+    elif region == "disc":
+        area = math.pi * r_min * r_min
+    else:
+        raise ValueError("region is 'cell' or 'disc'")
+    rate_max = fluence_cm2 * area * shape_max
+    times = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_max)
+        if t >= t_end:
+            break
+        if rng.uniform() * shape_max < shape(t):
+            times.append(t)
+    n = len(times)
+    if region == "cell":
+        x = rng.uniform(0.0, lx, n)
+        y = rng.uniform(0.0, ly, n)
+    else:
+        rad = r_min * np.sqrt(rng.uniform(0.0, 1.0, n))
+        ang = rng.uniform(0.0, 2.0 * math.pi, n)
+        x = 0.5 * lx + rad * np.cos(ang)
+        y = 0.5 * ly + rad * np.sin(ang)
+    lets = let(rng, n) if callable(let) else np.full(n, float(let))
+    bs = b(rng, n) if callable(b) else np.full(n, float(b))
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    return tracks(np.stack([lets, bs, x, y, np.full(n, float(theta)), phi, np.asarray(times, dtype=float)],
+                           axis=1))
+
+
 def batched_sweep(seed: int = SEED_BASE + 4, ninst: int = 96, max_tracks: int = 500,
                   transverse=(64, 256), gap_voxels=(50, 250), spacing=5e-4):
     """A sweep of ``ninst`` chambers of uneven grids (one pulse each).
