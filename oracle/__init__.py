@@ -23,7 +23,14 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
-          "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit")
+          "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit",
+          "attach_coeff", "mu_e", "D_e")
+_OPTIONAL = ("space_charge", "reaction_limit", "attach_coeff", "mu_e", "D_e")
+E_KEYS = ("e_released", "e_collected_anode", "e_collected_cathode", "e_recombined", "e_steps", "e_dt",
+          "e_left", "released_neg_charge")
+E_TRACE_KEYS = ("recombined_pn", "recombined_pe", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
+                "e_anode", "e_cathode", "pos_inflight", "neg_inflight", "e_inflight", "pos_abs", "neg_abs",
+                "e_abs")
 R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
           "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
           "col_neg_cathode", "dt", "steps", "flags", "max_beta_n", "n_space_charge_pos",
@@ -72,6 +79,10 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_advance.argtypes = [dp, i64, i64, i64, ctypes.c_double, i64, dp, dp, dp]
         L.orc_advance.restype = ctypes.c_int
+        L.orc_solve_free_electrons.argtypes = [dp, i64, i64, i64, dp, i64, i64, dp, dp, dp, dp, dp, dp]
+        L.orc_solve_free_electrons.restype = ctypes.c_int
+        L.orc_free_fraction.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_free_fraction.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -84,7 +95,8 @@ def _ptr(a):
 
 
 def _params(ch):
-    return np.array([float(ch[k]) for k in P_KEYS], dtype=np.float64)
+    return np.array([float(ch.get(k, 0.0)) if k in _OPTIONAL else float(ch[k]) for k in P_KEYS],
+                    dtype=np.float64)
 
 
 def _shape(ch):
@@ -120,6 +132,11 @@ def dt(ch, tracks=None) -> float:
     if rc:
         raise ValueError("no stable time step: neither drift nor diffusion constrains dt")
     return float(out[0])
+
+
+def free_fraction(a, d) -> float:
+    """p of eq. free_elec."""
+    return lib().orc_free_fraction(float(a), float(d))
 
 
 def weights(ch, dt_, species: int):
@@ -183,13 +200,28 @@ def solve(ch, tracks, with_trace: bool = False, with_fields: bool = True):
     ms = int(ch["max_steps"])
     trace = np.zeros((ms, NT)) if with_trace else None
     res = np.zeros(len(R_KEYS))
-    rc = lib().orc_solve(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr), tr.shape[0],
-                         ms, _ptr(pos), _ptr(neg), _ptr(trace), _ptr(res))
+    fe = float(ch.get("mu_e", 0.0)) > 0.0
+    if fe:  # free-electron component: electron phase, then the ions
+        res_e = np.zeros(len(E_KEYS))
+        trace_e = np.zeros((ms, len(E_TRACE_KEYS))) if with_trace else None
+        rc = lib().orc_solve_free_electrons(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr),
+                                            tr.shape[0], ms, _ptr(pos), _ptr(neg), _ptr(trace), _ptr(res),
+                                            _ptr(res_e), _ptr(trace_e))
+    else:
+        rc = lib().orc_solve(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], _ptr(tr), tr.shape[0],
+                             ms, _ptr(pos), _ptr(neg), _ptr(trace), _ptr(res))
     if rc == -2:
         raise ValueError("no stable time step")
+    if rc == -3:
+        raise ValueError("free electrons need an instantaneous pulse and no space charge")
     if rc:
         raise MemoryError("oracle solve failed")
     out = dict(zip(R_KEYS, res.tolist()))
+    if fe:
+        out.update(zip(E_KEYS, res_e.tolist()))
+        out["e_steps"] = int(out["e_steps"])
+        if with_trace:
+            out["trace_e"] = trace_e[: out["e_steps"]].copy()
     out["steps"] = int(out["steps"])
     out["flags"] = int(out["flags"])
     if with_trace:

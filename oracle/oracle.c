@@ -60,7 +60,8 @@
 /* parameter vector (mirrors the chamber dictionary) */
 enum {
   P_DX, P_DY, P_GAP, P_VOLT, P_MU_POS, P_MU_NEG, P_D_POS, P_D_NEG,
-  P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_REACTION_LIMIT, P_COUNT
+  P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_REACTION_LIMIT,
+  P_ATTACH, P_MU_E, P_D_E, P_COUNT
 };
 /* result vector */
 enum {
@@ -529,5 +530,270 @@ int orc_advance(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   }
   free(npos);
   free(nneg);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Free-electron component (sections "The free-electron component" and
+ * "Implementation of the free-electron models").
+ *
+ *   - fraction of electrons that stay free p = (1 - e^{-a d})/(a d)
+ *                                                              (eq. free_elec)
+ *   - initial densities: n+ as deposited; n-(z) = n+ (1 - e^{-a z}) and
+ *     n_e = n+ p, z measured from the anode                (eq. ion_elec_distribution)
+ *     (applied at every node to the negative charge the deposit releases)
+ *   - phase 1: the step is the largest stable one for the electrons (eq.
+ *     vNeum with mu_e, D_e), all three carriers move, the positive ions
+ *     recombine with both negative carriers (alpha n+ (n- + n_e)); it ends
+ *     once the electrons are collected (sum |n_e| dV <= stop_tol N_e)
+ *   - phase 2: the ions continue with their own step (orc_step) until
+ *     collection, as without electrons
+ * Only instantaneous pulses (every track at t = 0) are allowed; the
+ * space-charge term is not combined with free electrons.
+ * ------------------------------------------------------------------------ */
+
+enum { E_RPN, E_RPE, E_PA, E_PC, E_NA, E_NC, E_EA, E_EC, E_SP, E_SN, E_SE, E_AP, E_AN, E_AE, E_COUNT };
+enum { RE_RELEASED, RE_COLLECTED_ANODE, RE_COLLECTED_CATHODE, RE_RECOMBINED, RE_STEPS, RE_DT,
+       RE_LEFT, RE_RELEASED_NEG_CHARGE, RE_COUNT };
+
+/* p of eq. free_elec for attachment coefficient a over gap d */
+double orc_free_fraction(double a, double d)
+{
+  const double x = a * d;
+  return x == 0.0 ? 1.0 : -expm1(-x) / x;
+}
+
+/* Largest dt of eq. vNeum for the electrons (field along z). */
+static double electron_dt(const double *p, int64_t nz)
+{
+  const double dz = p[P_GAP] / (double)nz;
+  const double E = p[P_VOLT] / p[P_GAP];
+  const double A = 2.0 * p[P_D_E] * (1.0 / (p[P_DX] * p[P_DX]) + 1.0 / (p[P_DY] * p[P_DY]) + 1.0 / (dz * dz));
+  const double v = p[P_MU_E] * E / dz;
+  const double B = v * v;
+  if (B > 0.0) return 2.0 / (A + sqrt(A * A + 4.0 * B));
+  if (A > 0.0) return 1.0 / A;
+  return INFINITY;
+}
+
+/* One phase-1 step of the three carriers from the old densities. */
+static void step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
+                  const double *pos, const double *neg, const double *ele,
+                  double *npos, double *nneg, double *nele, double *tally)
+{
+  const double dz = p[P_GAP] / (double)nz;
+  const double dV = p[P_DX] * p[P_DY] * dz;
+  const double beta = p[P_ALPHA] * dt;
+  const double E = p[P_VOLT] / p[P_GAP];
+  /* c (signed drift), sx, sy, sz for n+, n-, n_e */
+  const double mus[3] = {p[P_MU_POS], -p[P_MU_NEG], -p[P_MU_E]};
+  const double Ds[3] = {p[P_D_POS], p[P_D_NEG], p[P_D_E]};
+  double w[3][4];
+  for (int s = 0; s < 3; ++s) {
+    w[s][0] = mus[s] * E * dt / dz;
+    w[s][1] = Ds[s] * dt / (p[P_DX] * p[P_DX]);
+    w[s][2] = Ds[s] * dt / (p[P_DY] * p[P_DY]);
+    w[s][3] = Ds[s] * dt / (dz * dz);
+  }
+  const double *in[3] = {pos, neg, ele};
+  double *out[3] = {npos, nneg, nele};
+  double rpn = 0.0, rpe = 0.0, inflight[3] = {0, 0, 0}, absolute[3] = {0, 0, 0};
+  for (int64_t k = 1; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        const int64_t ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+        const int64_t jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+        const double np_ = pos[IDX(k, j, i)], nn_ = neg[IDX(k, j, i)], ne_ = ele[IDX(k, j, i)];
+        const double sink_n = beta * np_ * nn_, sink_e = beta * np_ * ne_;
+        rpn += sink_n;
+        rpe += sink_e;
+        const double sinks[3] = {sink_n + sink_e, sink_n, sink_e};
+        for (int s = 0; s < 3; ++s) {
+          const double *n = in[s];
+          const double c = w[s][0], sx = w[s][1], sy = w[s][2], sz = w[s][3];
+          const double nc = n[IDX(k, j, i)];
+          const double lap_x = n[IDX(k, j, ip)] - 2.0 * nc + n[IDX(k, j, im)];
+          const double lap_y = n[IDX(k, jp, i)] - 2.0 * nc + n[IDX(k, jm, i)];
+          const double lap_z = n[IDX(k + 1, j, i)] - 2.0 * nc + n[IDX(k - 1, j, i)];
+          const double drift = c * (c * (nc - n[IDX(k - 1, j, i)])
+                                    + (1.0 - c) * 0.5 * (n[IDX(k + 1, j, i)] - n[IDX(k - 1, j, i)]));
+          const double v = nc + sx * lap_x + sy * lap_y + sz * lap_z - drift - sinks[s];
+          out[s][IDX(k, j, i)] = v;
+          inflight[s] += v;
+          absolute[s] += fabs(v);
+        }
+      }
+  for (int s = 0; s < 3; ++s) {
+    const double c = w[s][0], sz = w[s][3];
+    const double w_up = sz + 0.5 * c * c - 0.5 * c, w_down = sz + 0.5 * c * c + 0.5 * c;
+    double a = 0.0, b = 0.0;
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        a += in[s][IDX(1, j, i)];
+        b += in[s][IDX(nz - 1, j, i)];
+      }
+    tally[E_PA + 2 * s] = w_up * a * dV;
+    tally[E_PC + 2 * s] = w_down * b * dV;
+    tally[E_SP + s] = inflight[s] * dV;
+    tally[E_AP + s] = absolute[s] * dV;
+  }
+  tally[E_RPN] = rpn * dV;
+  tally[E_RPE] = rpe * dV;
+}
+
+/* Run with a free-electron component (attachment coefficient p[P_ATTACH],
+ * electron mobility p[P_MU_E] > 0 and diffusion p[P_D_E]).  pos_out,
+ * neg_out: the final ion densities.  res as orc_solve (phase-2 tallies plus
+ * the phase-1 ion tallies; f counts the collected electrons too, against
+ * the positive plus negative charge released); res_e: RE_COUNT values of the
+ * electron phase; trace: NULL or max_steps * T_COUNT phase-2 records;
+ * trace_e: NULL or max_steps * E_COUNT phase-1 records.  Returns 0, -2 (no
+ * step), -3 (a track not at t = 0, or space charge on) or -1. */
+int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz,
+                             const double *trk, int64_t ntr, int64_t max_steps,
+                             double *pos_out, double *neg_out, double *trace, double *res,
+                             double *res_e, double *trace_e)
+{
+  for (int64_t t = 0; t < ntr; ++t)
+    if (trk[TRK * t + 6] != 0.0) return -3;
+  if (p[P_SPACE_CHARGE] != 0.0) return -3;
+  double dt;
+  int rc = orc_dt(p, nx, ny, nz, trk, ntr, &dt);
+  if (rc) return rc;
+  double dt1 = p[P_KAPPA] * electron_dt(p, nz);
+  if (dt < dt1) dt1 = dt;
+  const int64_t n = (nz + 1) * ny * nx;
+  const double dz = p[P_GAP] / (double)nz;
+  const double dV = p[P_DX] * p[P_DY] * dz;
+  const double pf = orc_free_fraction(p[P_ATTACH], p[P_GAP]);
+  double *dep = (double *)calloc((size_t)n, sizeof(double));
+  double *a[6];
+  int bad = !dep;
+  for (int q = 0; q < 6; ++q) {
+    a[q] = (double *)calloc((size_t)n, sizeof(double));
+    bad |= !a[q];
+  }
+  if (bad) {
+    free(dep);
+    for (int q = 0; q < 6; ++q) free(a[q]);
+    return -1;
+  }
+  /* deposit: positive ions into a[0], the negative charge into dep, then
+   * split dep into negative ions a[1] and free electrons a[2] */
+  double rel_pos = 0.0, rel_negq = 0.0;
+  if (p[P_UNIFORM_N0] != 0.0) {
+    const double u = orc_uniform(p, nx, ny, nz, p[P_UNIFORM_N0], a[0], dep);
+    rel_pos += u;
+    rel_negq += u;
+  }
+  double rel[2];
+  orc_deposit(p, nx, ny, nz, trk, ntr, 0, dt, a[0], dep, rel);
+  rel_pos += rel[0];
+  rel_negq += rel[1];
+  double rel_neg = 0.0, rel_e = 0.0;
+  for (int64_t k = 1; k < nz; ++k) {
+    const double att = -expm1(-p[P_ATTACH] * (double)k * dz); /* 1 - e^{-a z} */
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        const double d = dep[IDX(k, j, i)];
+        a[1][IDX(k, j, i)] = d * att;
+        a[2][IDX(k, j, i)] = d * pf;
+        rel_neg += d * att;
+        rel_e += d * pf;
+      }
+  }
+  free(dep);
+  rel_neg *= dV;
+  rel_e *= dV;
+  const double beta = p[P_ALPHA] * dt;
+  double max_beta_n = 0.0;
+  for (int64_t q = 0; q < n; ++q) {
+    const double m = a[0][q] > a[1][q] + a[2][q] ? a[0][q] : a[1][q] + a[2][q];
+    if (beta * m > max_beta_n) max_beta_n = beta * m;
+  }
+
+  /* phase 1: the three carriers at the electron step */
+  double sums[5] = {0, 0, 0, 0, 0}; /* R, C+a, C+c, C-a, C-c (ions) */
+  double e_col[2] = {0, 0}, e_rec = 0.0, e_left = rel_e;
+  int64_t steps_e = 0;
+  int flags = 0;
+  int cur = 0;
+  while (rel_e > 0.0 && steps_e < max_steps) {
+    double tally[E_COUNT];
+    step3(p, nx, ny, nz, dt1, a[3 * cur], a[3 * cur + 1], a[3 * cur + 2],
+          a[3 * (1 - cur)], a[3 * (1 - cur) + 1], a[3 * (1 - cur) + 2], tally);
+    cur = 1 - cur;
+    if (trace_e) memcpy(trace_e + E_COUNT * steps_e, tally, sizeof(tally));
+    ++steps_e;
+    sums[0] += tally[E_RPN];
+    sums[1] += tally[E_PA];
+    sums[2] += tally[E_PC];
+    sums[3] += tally[E_NA];
+    sums[4] += tally[E_NC];
+    e_col[0] += tally[E_EA];
+    e_col[1] += tally[E_EC];
+    e_rec += tally[E_RPE];
+    e_left = tally[E_SE];
+    int finite = 1;
+    for (int q = 0; q < E_COUNT; ++q) finite &= isfinite(tally[q]) != 0;
+    if (!finite) { flags |= FLAG_NONFINITE; break; }
+    if (tally[E_AE] <= p[P_STOP_TOL] * rel_e) break;
+  }
+
+  /* phase 2: the ions alone at their own step, from the state after phase 1 */
+  double *P = a[3 * cur], *N = a[3 * cur + 1], *Q = a[3 * (1 - cur)], *M = a[3 * (1 - cur) + 1];
+  double last[T_COUNT] = {0};
+  int64_t steps = 0;
+  if (!(flags & FLAG_NONFINITE)) {
+    for (int64_t l = 0; steps_e + l < max_steps; ++l) {
+      double t2[T_COUNT];
+      orc_step(p, nx, ny, nz, dt, P, N, Q, M, t2);
+      double *tmp = P; P = Q; Q = tmp;
+      tmp = N; N = M; M = tmp;
+      for (int q = 0; q < 5; ++q) sums[q] += t2[q];
+      memcpy(last, t2, sizeof(last));
+      if (trace) memcpy(trace + T_COUNT * l, t2, sizeof(t2));
+      steps = l + 1;
+      int finite = 1;
+      for (int q = 0; q < T_COUNT; ++q) finite &= isfinite(t2[q]) != 0;
+      if (!finite) { flags |= FLAG_NONFINITE; break; }
+      if (t2[T_POS_ABS] <= p[P_STOP_TOL] * rel_pos && t2[T_NEG_ABS] <= p[P_STOP_TOL] * rel_neg) break;
+      if (steps_e + steps == max_steps) flags |= FLAG_MAX_STEPS;
+    }
+  }
+  memcpy(pos_out, P, (size_t)n * sizeof(double));
+  memcpy(neg_out, N, (size_t)n * sizeof(double));
+  for (int q = 0; q < 6; ++q) free(a[q]);
+
+  if (max_beta_n > 1.0) flags |= FLAG_REACTION;
+  const double collected_ions = sums[1] + sums[2] + sums[3] + sums[4];
+  const double released_q = rel_pos + rel_negq; /* positive + negative charge released */
+  if (!(released_q > 0.0)) flags |= FLAG_EMPTY;
+  res[R_F] = released_q > 0.0 ? (collected_ions + e_col[0] + e_col[1]) / released_q : 1.0;
+  res[R_KS] = 1.0 / res[R_F];
+  res[R_F_RECOMB] = released_q > 0.0 ? 1.0 - 2.0 * (sums[0] + e_rec) / released_q : 1.0;
+  res[R_RELEASED] = rel_pos;
+  res[R_RECOMBINED] = sums[0];
+  res[R_INFLIGHT_POS] = last[T_POS_INFLIGHT];
+  res[R_INFLIGHT_NEG] = last[T_NEG_INFLIGHT];
+  res[R_COL_POS_ANODE] = sums[1];
+  res[R_COL_POS_CATHODE] = sums[2];
+  res[R_COL_NEG_ANODE] = sums[3];
+  res[R_COL_NEG_CATHODE] = sums[4];
+  res[R_DT] = dt;
+  res[R_STEPS] = (double)steps;
+  res[R_FLAGS] = (double)flags;
+  res[R_MAX_BETA_N] = max_beta_n;
+  res[R_SC_POS] = 0.0;
+  res[R_SC_NEG] = 0.0;
+  res[R_RELEASED_NEG] = rel_neg;
+  res_e[RE_RELEASED] = rel_e;
+  res_e[RE_COLLECTED_ANODE] = e_col[0];
+  res_e[RE_COLLECTED_CATHODE] = e_col[1];
+  res_e[RE_RECOMBINED] = e_rec;
+  res_e[RE_STEPS] = (double)steps_e;
+  res_e[RE_DT] = dt1;
+  res_e[RE_LEFT] = e_left;
+  res_e[RE_RELEASED_NEG_CHARGE] = rel_negq;
   return 0;
 }

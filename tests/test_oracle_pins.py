@@ -700,3 +700,92 @@ def test_max_steps_flag(orc):
     ch, tr = W.single_track(max_steps=10)
     r = orc.solve(ch, tr, with_fields=False)
     assert r["steps"] == 10 and r["flags"] & 1
+
+
+# ---------------------------------------------------------------------------
+# free-electron component (eqs. free_elec, ion_elec_distribution, model1-3)
+# ---------------------------------------------------------------------------
+
+def _attach_for(p_target, d):
+    lo, hi = 1e-9, 1e7
+    for _ in range(200):
+        mid = math.sqrt(lo * hi)
+        if cf.free_electron_fraction(mid, d) > p_target:
+            lo = mid
+        else:
+            hi = mid
+    return mid
+
+
+def _fe_chamber(p_target, V, n0=3e9, d=0.1, nz=100, mu_e=1500.0):
+    ch = W.chamber(2, 2, nz, 1e-3, d, V, uniform_n0=n0)
+    ch.update(attach_coeff=_attach_for(p_target, d), mu_e=mu_e, D_e=mu_e * 0.02526)
+    return ch
+
+
+def test_free_electron_initial_split(orc):
+    """The negative charge of the pulse splits into electrons, p of it
+    (eq. free_elec), and negative ions n+ (1 - e^{-a z}) (eq.
+    ion_elec_distribution): for a uniform dose both sums have closed forms."""
+    ch = _fe_chamber(0.3, 200.0)
+    r = orc.solve(dict(ch, max_steps=1), W.no_tracks(), with_fields=False)
+    a, d, nz = ch["attach_coeff"], ch["gap"], ch["nz"]
+    p = cf.free_electron_fraction(a, d)
+    assert orc.free_fraction(a, d) == pytest.approx(p, rel=1e-15)
+    Q = r["released_neg_charge"]
+    assert Q == pytest.approx(r["n_released"], rel=1e-15)
+    assert r["e_released"] == pytest.approx(p * Q, rel=1e-13)
+    dz = d / nz
+    k = np.arange(1, nz)
+    col = ch["uniform_n0"] * ch["dx"] * ch["dy"] * dz * ch["nx"] * ch["ny"]
+    assert r["n_released_neg"] == pytest.approx(col * np.sum(-np.expm1(-a * k * dz)), rel=1e-13)
+
+
+def test_free_electron_phase_conservation(orc):
+    """Phase 1 keeps every carrier's books step by step: in flight before =
+    collected + recombined + in flight after (positive ions recombine with
+    both negative carriers)."""
+    ch = _fe_chamber(0.5, 100.0)
+    r = orc.solve(ch, W.no_tracks(), with_trace=True, with_fields=False)
+    t = r["trace_e"]
+    N = r["n_released"]
+    prev = lambda col, first: np.concatenate([[first], t[:-1, col]])
+    err_p = prev(8, r["n_released"]) - t[:, 2] - t[:, 3] - t[:, 0] - t[:, 1] - t[:, 8]
+    err_n = prev(9, r["n_released_neg"]) - t[:, 4] - t[:, 5] - t[:, 0] - t[:, 9]
+    err_e = prev(10, r["e_released"]) - t[:, 6] - t[:, 7] - t[:, 1] - t[:, 10]
+    for e in (err_p, err_n, err_e):
+        assert np.max(np.abs(e)) <= 1e-12 * N
+    # the electrons leave within the phase; the ions have hardly moved
+    assert r["e_left"] <= 1e-9 * N and r["e_steps"] > 10
+
+
+@pytest.mark.parametrize("p", [0.1, 0.5])
+def test_free_electron_boag_models(orc, p):
+    """Boag's free-electron models (eqs. model1-3) against the solver for a
+    uniform instantaneous dose: within 2.5 % at 100 V and 1 % at 300 V, all
+    three converging as the field grows (the paper's comparison); at p = 0.1
+    model 1 is the closest, as the paper found."""
+    dev = {}
+    for V in (100.0, 300.0):
+        ch = _fe_chamber(p, V)
+        r = orc.solve(ch, W.no_tracks(), with_fields=False)
+        assert r["flags"] == 0
+        u = cf.boag_u(ch["uniform_n0"], ch["gap"], V, ch["mu_pos"], ch["mu_neg"], ch["alpha"])
+        pp = cf.free_electron_fraction(ch["attach_coeff"], ch["gap"])
+        dev[V] = [abs(m(u, pp) / r["f"] - 1) for m in (cf.boag_model1, cf.boag_model2, cf.boag_model3)]
+        assert max(dev[V]) < (0.025 if V == 100.0 else 0.01)
+        # free electrons escape recombination: f above the ions-only result
+        assert r["f"] > orc.solve(dict(ch, mu_e=0.0), W.no_tracks(), with_fields=False)["f"]
+        # electron-ion recombination is tiny next to the ionic one
+        assert r["e_recombined"] < 1e-2 * r["n_recombined"]
+    assert all(b < a for a, b in zip(dev[100.0], dev[300.0]))
+    if p == 0.1:
+        assert dev[100.0][0] == min(dev[100.0])
+
+
+def test_all_electrons_free_collects_almost_everything(orc):
+    """p -> 1: no negative ions form, the electrons leave before they can
+    recombine, and f -> 1 as every model gives."""
+    ch = _fe_chamber(0.9999, 100.0)
+    r = orc.solve(ch, W.no_tracks(), with_fields=False)
+    assert r["f"] > 0.999
