@@ -93,7 +93,21 @@ typedef struct {
   double stop_tol;      /* stop once sum |n| dV <= stop_tol * released for both species (>= 0) */
   double uniform_n0;    /* uniform ion-pair density added at t = 0 [cm^-3] (>= 0) */
   double reaction_limit;/* rho >= 0: also bound dt by k dt n_ref <= rho (0 = off), see it_dt */
-  int64_t max_steps;    /* hard step limit (>= 1) */
+  /* Free-electron component (The free-electron component; Implementation of
+   * the free-electron models), on when mu_e > 0: of the negative charge a
+   * deposit releases, the fraction p = (1 - e^{-a d})/(a d) stays as free
+   * electrons spread evenly (n_e = n+ p) and the rest forms negative ions
+   * n+ (1 - e^{-a z}), z from the anode (eqs. free_elec,
+   * ion_elec_distribution).  The run first steps all three carriers at the
+   * electrons' largest stable step (eq. vNeum with mu_e, D_e; the positive
+   * ions recombine with both negative carriers) until the electrons are
+   * collected (sum |n_e| dV <= stop_tol times the electrons released), then
+   * the ions alone at their own step.  Needs every track at t = 0 and
+   * space_charge = 0 (else IT_ENOTSUP); it_solve_batch does not support it. */
+  double attach_coeff;  /* a [1/cm] (>= 0; 0: no attachment, p = 1) */
+  double mu_e;          /* electron mobility [cm^2/(V s)] (>= 0; 0 = no free electrons) */
+  double D_e;           /* electron diffusion constant [cm^2/s] (>= 0) */
+  int64_t max_steps;    /* hard step limit (>= 1), both phases together */
 } it_chamber;
 
 /* One ion track.  The axis passes through (x, y, gap/2) with direction
@@ -115,9 +129,10 @@ typedef struct {
 
 /* Result of a run (all counts in ion pairs / ions). */
 typedef struct {
-  double f;             /* collection efficiency: ions collected / ions released, both species */
+  double f;             /* collection efficiency: charge collected / charge released,
+                         * both signs (free electrons included) */
   double ks;            /* recombination factor 1/f */
-  double f_R;           /* 1 - recombined pairs / mean ions released per species */
+  double f_R;           /* 1 - recombined pairs / mean charge released per sign */
   double n_released, n_recombined;
   double n_inflight_pos, n_inflight_neg;  /* signed in-flight counts after the last step */
   double col_pos_anode, col_pos_cathode, col_neg_anode, col_neg_cathode;
@@ -126,7 +141,16 @@ typedef struct {
   double n_space_charge_pos, n_space_charge_neg;  /* change of each species by the
                          * space-charge term over the run (ions; 0 when off) */
   double n_released_neg;/* negative ions released (n_released counts the positive
-                         * ions; the two differ only with separate track radii) */
+                         * ions; the two differ only with separate track radii or
+                         * free electrons) */
+  /* free-electron phase (all 0 without free electrons) */
+  double e_released;    /* free electrons released */
+  double e_collected_anode, e_collected_cathode;
+  double e_recombined;  /* electrons recombined with positive ions */
+  double e_left;        /* electrons still in flight when the phase ended */
+  double e_dt;          /* step of the electron phase [s] */
+  double released_neg_charge;  /* negative charge released (ions + electrons) */
+  int64_t e_steps;      /* steps of the electron phase */
   int64_t steps;        /* steps counted in the result */
   int32_t flags;        /* IT_FLAG_* */
   int32_t passes;       /* stepping kernel launches issued (diagnostic) */

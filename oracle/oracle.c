@@ -744,6 +744,7 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
   double *P = a[3 * cur], *N = a[3 * cur + 1], *Q = a[3 * (1 - cur)], *M = a[3 * (1 - cur) + 1];
   double last[T_COUNT] = {0};
   int64_t steps = 0;
+  int ended = 0; /* stopped by the collection criterion */
   if (!(flags & FLAG_NONFINITE)) {
     for (int64_t l = 0; steps_e + l < max_steps; ++l) {
       double t2[T_COUNT];
@@ -757,10 +758,13 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
       int finite = 1;
       for (int q = 0; q < T_COUNT; ++q) finite &= isfinite(t2[q]) != 0;
       if (!finite) { flags |= FLAG_NONFINITE; break; }
-      if (t2[T_POS_ABS] <= p[P_STOP_TOL] * rel_pos && t2[T_NEG_ABS] <= p[P_STOP_TOL] * rel_neg) break;
-      if (steps_e + steps == max_steps) flags |= FLAG_MAX_STEPS;
+      if (t2[T_POS_ABS] <= p[P_STOP_TOL] * rel_pos && t2[T_NEG_ABS] <= p[P_STOP_TOL] * rel_neg) {
+        ended = 1;
+        break;
+      }
     }
   }
+  if (!ended && !(flags & FLAG_NONFINITE)) flags |= FLAG_MAX_STEPS;
   memcpy(pos_out, P, (size_t)n * sizeof(double));
   memcpy(neg_out, N, (size_t)n * sizeof(double));
   for (int q = 0; q < 6; ++q) free(a[q]);

@@ -39,6 +39,7 @@ class it_chamber(ctypes.Structure):
                 ("D_pos", ctypes.c_double), ("D_neg", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("W_eV", ctypes.c_double), ("dt_safety", ctypes.c_double), ("stop_tol", ctypes.c_double),
                 ("uniform_n0", ctypes.c_double), ("reaction_limit", ctypes.c_double),
+                ("attach_coeff", ctypes.c_double), ("mu_e", ctypes.c_double), ("D_e", ctypes.c_double),
                 ("max_steps", ctypes.c_int64)]
 
 
@@ -46,8 +47,10 @@ class it_result(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in (
         "f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos", "n_inflight_neg",
         "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "max_beta_n",
-        "n_space_charge_pos", "n_space_charge_neg", "n_released_neg")] + \
-        [("steps", ctypes.c_int64), ("flags", ctypes.c_int32), ("passes", ctypes.c_int32)]
+        "n_space_charge_pos", "n_space_charge_neg", "n_released_neg", "e_released", "e_collected_anode",
+        "e_collected_cathode", "e_recombined", "e_left", "e_dt", "released_neg_charge")] + \
+        [("e_steps", ctypes.c_int64), ("steps", ctypes.c_int64), ("flags", ctypes.c_int32),
+         ("passes", ctypes.c_int32)]
 
 
 class it_exec(ctypes.Structure):
@@ -111,8 +114,10 @@ def _chamber(ch) -> it_chamber:
     for k in ("nx", "ny", "nz", "max_steps"):
         setattr(c, k, int(ch[k]))
     for k in ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg", "alpha", "W_eV",
-              "dt_safety", "stop_tol", "uniform_n0", "reaction_limit"):
-        setattr(c, k, float(ch.get(k, 0.0)) if k == "reaction_limit" else float(ch[k]))
+              "dt_safety", "stop_tol", "uniform_n0"):
+        setattr(c, k, float(ch[k]))
+    for k in ("reaction_limit", "attach_coeff", "mu_e", "D_e"):  # optional keys
+        setattr(c, k, float(ch.get(k, 0.0)))
     c.space_charge = int(ch.get("space_charge", 0))
     return c
 
@@ -225,6 +230,7 @@ def workspace(ch, ntracks: int, device="cuda"):
 def _result(r: it_result) -> dict:
     out = {k: getattr(r, k) for k, _ in it_result._fields_}
     out["steps"] = int(out["steps"])
+    out["e_steps"] = int(out["e_steps"])
     out["flags"] = int(out["flags"])
     out["passes"] = int(out["passes"])
     return out

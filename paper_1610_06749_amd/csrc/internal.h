@@ -43,6 +43,14 @@ struct RunState {
   double last[4];           // in-flight pos/neg and |n| sums after the last step
   double max_beta_n;        // max over deposits of beta * max(n)
   double screened[2];       // running space-charge change of n+ and n-
+  // free-electron component
+  double released_q;        // negative charge released (ions + electrons)
+  double released_e;        // free electrons released
+  double e_sums[3];         // electrons collected at anode, cathode; recombined
+  double e_left;            // electrons in flight after the last electron step
+  int64_t e_steps;          // electron-phase steps recorded
+  int32_t e_done;           // 1 once the electrons are collected
+  int32_t e_pad;
   int64_t steps;            // steps recorded so far
   int32_t done;             // 1 once the stop criterion (or a non-finite tally) is met
   int32_t flags;            // IT_FLAG_NONFINITE
@@ -96,7 +104,12 @@ struct DepositParams {
   int ntilt;
   double dV, beta;
   int same_radii;           // 1: every track gives both species the same radius
-  double* partials;         // [gridDim][3]
+  // free electrons: the negative charge splits into negative ions
+  // (1 - e^{-a z}) and electrons (fraction pfree) written to `ele`
+  int free_e;
+  double attach, pfree;
+  double* ele;
+  double* partials;         // [gridDim][5]
   unsigned* counter;
   RunState* state;
 };
@@ -108,6 +121,20 @@ struct BatchInstance {
   int ntiles;
   int64_t max_steps;
 };
+
+// One electron-phase step of the three carriers (free-electron component).
+constexpr int kAcc3 = 14;  // per-block tally slots of the electron phase
+struct Step3Params {
+  const double* in[3];      // n+, n-, n_e
+  double* out[3];
+  int nx, ny, nz;
+  int tiles_x, tiles_y, zchunks, zc, ntiles, per_xcd;
+  Coef co[3];
+  double beta, dV, stop_tol;
+  double* partials;         // [gridDim][kAcc3]
+  RunState* state;
+};
+hipError_t launch_step3(const Step3Params& p, hipStream_t s);
 
 // Launchers (stream-ordered, no synchronisation).
 int plain_tile_rows(int tile_y);

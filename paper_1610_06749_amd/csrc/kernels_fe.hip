@@ -1,0 +1,136 @@
+// Electron phase of the free-electron component (sections "The
+// free-electron component" and "Implementation of the free-electron
+// models"): one explicit step of the three carriers n+, n-, n_e at the
+// electrons' step, each with its own drift and diffusion coefficients (the
+// Appendix's scheme), the positive ions recombining with both negative
+// carriers (Jacobi: the old densities), plus the per-step tallies.  This
+// phase lasts about one electron transit, so the kernel favours simplicity
+// over the one-step kernel's pipelining: per plane it loads the next plane
+// of its own column, stages the tile with its rim in LDS and computes.
+#include "reduce.h"
+
+namespace it {
+
+namespace {
+
+constexpr int kTX3 = 64, kTY3 = 8, kNT3 = kTX3 * kTY3;
+
+// tally slots: 0 recombined n+ n-, 1 recombined n+ n_e, 2..7 sums of
+// n+, n-, n_e on plane 1 and plane nz-1 (anode, cathode per carrier),
+// 8..10 in-flight sums, 11..13 sums of |n|
+__global__ __launch_bounds__(kNT3) void step3_kernel(Step3Params p) {
+  if (p.state->e_done) return;
+  __shared__ double sl[3][kTY3 + 2][kTX3 + 2];
+  __shared__ double lds[(kNT3 / kWave) * kAcc3];
+  double acc[kAcc3];
+#pragma unroll
+  for (int q = 0; q < kAcc3; ++q) acc[q] = 0.0;
+  const TileCoord t = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int x0 = t.tx * kTX3, y0 = t.ty * kTY3;
+  const int w = min(kTX3, p.nx - x0), h = min(kTY3, p.ny - y0);
+  const bool active = t.valid && lane < w && ty < h;
+  const double am = active ? 1.0 : 0.0;
+  const int k0 = 1 + t.zc * p.zc;
+  const int k1 = t.valid ? min(k0 + p.zc, p.nz) : k0;
+  const size_t plane = (size_t)p.nx * p.ny;
+  const int ic = min(x0 + lane, p.nx - 1), jc = min(y0 + ty, p.ny - 1);
+  const size_t own = (size_t)jc * p.nx + ic;
+  // rim: waves 0/1 the rows above/below, waves 2/3 the columns left/right
+  const int i_left = x0 == 0 ? p.nx - 1 : x0 - 1, i_right = x0 + w == p.nx ? 0 : x0 + w;
+  const int j_top = y0 == 0 ? p.ny - 1 : y0 - 1, j_bot = y0 + h == p.ny ? 0 : y0 + h;
+  size_t rim_off = 0;
+  int rr = -1, rc = -1;
+  if (ty == 0 && lane < w) { rim_off = (size_t)j_top * p.nx + x0 + lane; rr = 0; rc = lane + 1; }
+  if (ty == 1 && lane < w) { rim_off = (size_t)j_bot * p.nx + x0 + lane; rr = h + 1; rc = lane + 1; }
+  if (ty == 2 && lane < h) { rim_off = (size_t)(y0 + lane) * p.nx + i_left; rr = lane + 1; rc = 0; }
+  if (ty == 3 && lane < h) { rim_off = (size_t)(y0 + lane) * p.nx + i_right; rr = lane + 1; rc = w + 1; }
+  const bool rim = t.valid && rr >= 0;
+
+  double m[3], c[3];
+  for (int s = 0; s < 3; ++s) {
+    m[s] = p.in[s][(size_t)(k0 - 1) * plane + own];
+    c[s] = p.in[s][(size_t)k0 * plane + own];
+  }
+  for (int k = k0; k < k1; ++k) {
+    const size_t base = (size_t)k * plane;
+    double q[3];
+    for (int s = 0; s < 3; ++s) q[s] = p.in[s][base + plane + own];  // plane k+1 <= nz
+    if (rim)
+      for (int s = 0; s < 3; ++s) sl[s][rr][rc] = p.in[s][base + rim_off];
+    if (active)
+      for (int s = 0; s < 3; ++s) sl[s][ty + 1][lane + 1] = c[s];
+    __syncthreads();
+    const double sink_n = p.beta * c[0] * c[1], sink_e = p.beta * c[0] * c[2];
+    const double sinks[3] = {sink_n + sink_e, sink_n, sink_e};
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const Coef& co = p.co[s];
+      const double v = co.a0 * c[s] + co.ax * (sl[s][ty + 1][lane] + sl[s][ty + 1][lane + 2]) +
+                       co.ay * (sl[s][ty][lane + 1] + sl[s][ty + 2][lane + 1]) + co.azp * q[s] +
+                       co.azm * m[s] - sinks[s];
+      if (active) p.out[s][base + own] = v;
+      acc[8 + s] += am * v;
+      acc[11 + s] += am * fabs(v);
+    }
+    acc[0] += am * sink_n;
+    acc[1] += am * sink_e;
+    if (k == 1)
+      for (int s = 0; s < 3; ++s) acc[2 + 2 * s] += am * c[s];
+    if (k == p.nz - 1)
+      for (int s = 0; s < 3; ++s) acc[3 + 2 * s] += am * c[s];
+    __syncthreads();
+    for (int s = 0; s < 3; ++s) {
+      m[s] = c[s];
+      c[s] = q[s];
+    }
+  }
+  block_sum_store<kAcc3, kNT3>(acc, p.partials + (size_t)blockIdx.x * kAcc3, lds);
+}
+
+// One block: the step's totals in fixed order, then the run state.  The
+// electron phase records no per-step trace; its ion tallies join the run's
+// totals, and the deposit's released counts are consumed here (the ion phase
+// that follows records no release).
+__global__ __launch_bounds__(1024) void reduce3_kernel(Step3Params p, int nblocks) {
+  if (p.state->e_done) return;
+  __shared__ double tot[kAcc3];
+  reduce_partials<1024>(p.partials, nblocks, kAcc3, kAcc3, tot);
+  if (threadIdx.x != 0) return;
+  RunState st = *p.state;
+  const double dV = p.dV;
+  const double col[6] = {p.co[0].azp * tot[2] * dV, p.co[0].azm * tot[3] * dV, p.co[1].azp * tot[4] * dV,
+                         p.co[1].azm * tot[5] * dV, p.co[2].azp * tot[6] * dV, p.co[2].azm * tot[7] * dV};
+  st.sums[0] += tot[0] * dV;
+  for (int q = 0; q < 4; ++q) st.sums[1 + q] += col[q];
+  st.e_sums[0] += col[4];
+  st.e_sums[1] += col[5];
+  st.e_sums[2] += tot[1] * dV;
+  st.e_left = tot[10] * dV;
+  st.released_pending = 0.0;
+  st.released_pending_neg = 0.0;
+  st.e_steps += 1;
+  bool finite = true;
+  for (int q = 0; q < kAcc3; ++q) finite = finite && isfinite(tot[q]);
+  if (!finite) {
+    st.flags |= IT_FLAG_NONFINITE;
+    st.e_done = 1;
+    st.done = 1;
+  } else if (tot[13] * dV <= p.stop_tol * st.released_e) {
+    st.e_done = 1;
+  }
+  *p.state = st;
+}
+
+}  // namespace
+
+hipError_t launch_step3(const Step3Params& p, hipStream_t s) {
+  const int grid = 8 * p.per_xcd;
+  hipLaunchKernelGGL(step3_kernel, dim3(grid), dim3(kTX3, kTY3), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce3_kernel, dim3(1), dim3(1024), 0, s, p, grid);
+  return hipGetLastError();
+}
+
+}  // namespace it

@@ -92,8 +92,9 @@ __device__ inline void track_values(const DepTrack& tr, double wx, double wy, do
 }
 
 __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
-  __shared__ double lds[(kNT / kWave) * 3];
-  double sum_p = 0.0, sum_n = 0.0, mx = 0.0;
+  constexpr int NP = 5;  // partials: released n+, n- ions, electrons, negative charge; max density
+  __shared__ double lds[(kNT / kWave) * NP];
+  double acc[NP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const bool same = p.same_radii != 0;
   const TileCoord t = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
   const int i = t.tx * kTX + threadIdx.x;
@@ -124,68 +125,74 @@ __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
           d_n += dn;
         }
       }
-      const double a = p.pos[c] + d_p, b = p.neg[c] + d_n;
+      const double a = p.pos[c] + d_p;
       p.pos[c] = a;
-      p.neg[c] = b;
-      sum_p += d_p;
-      sum_n += d_n;
-      mx = fmax(mx, fmax(a, b));
+      acc[0] += d_p;
+      acc[3] += d_n;
+      if (p.free_e) {  // eq. ion_elec_distribution: ions (1 - e^{-a z}), electrons p
+        const double di = d_n * -expm1(-p.attach * (k * p.dz)), de = d_n * p.pfree;
+        const double b = p.neg[c] + di, e = p.ele[c] + de;
+        p.neg[c] = b;
+        p.ele[c] = e;
+        acc[1] += di;
+        acc[2] += de;
+        acc[4] = fmax(acc[4], fmax(a, b + e));
+      } else {
+        const double b = p.neg[c] + d_n;
+        p.neg[c] = b;
+        acc[1] += d_n;
+        acc[4] = fmax(acc[4], fmax(a, b));
+      }
     }
   }
-  // block partials: [released+, released-, max]
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   {
-    const double s0 = wave_sum(sum_p), s1 = wave_sum(sum_n), m = wave_max(mx);
-    if (tid % kWave == 0) {
-      lds[(tid / kWave) * 3] = s0;
-      lds[(tid / kWave) * 3 + 1] = s1;
-      lds[(tid / kWave) * 3 + 2] = m;
-    }
+    double v[NP];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(acc[q]);
+    v[4] = wave_max(acc[4]);
+    if (tid % kWave == 0)
+      for (int q = 0; q < NP; ++q) lds[(tid / kWave) * NP + q] = v[q];
     __syncthreads();
     if (tid == 0) {
-      double a0 = lds[0], a1 = lds[1], mm = lds[2];
+      double r[NP];
+      for (int q = 0; q < NP; ++q) r[q] = lds[q];
       for (int w = 1; w < kNT / kWave; ++w) {
-        a0 += lds[w * 3];
-        a1 += lds[w * 3 + 1];
-        mm = fmax(mm, lds[w * 3 + 2]);
+        for (int q = 0; q < 4; ++q) r[q] += lds[w * NP + q];
+        r[4] = fmax(r[4], lds[w * NP + 4]);
       }
-      p.partials[(size_t)blockIdx.x * 3] = a0;
-      p.partials[(size_t)blockIdx.x * 3 + 1] = a1;
-      p.partials[(size_t)blockIdx.x * 3 + 2] = mm;
+      for (int q = 0; q < NP; ++q) p.partials[(size_t)blockIdx.x * NP + q] = r[q];
     }
   }
   if (!arrive_last<kNT>(p.counter)) return;
   {
-    double s0 = 0.0, s1 = 0.0, m = 0.0;
+    double v[NP] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = tid; b < (int)gridDim.x; b += kNT) {
-      s0 += p.partials[(size_t)b * 3];
-      s1 += p.partials[(size_t)b * 3 + 1];
-      m = fmax(m, p.partials[(size_t)b * 3 + 2]);
+      for (int q = 0; q < 4; ++q) v[q] += p.partials[(size_t)b * NP + q];
+      v[4] = fmax(v[4], p.partials[(size_t)b * NP + 4]);
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    m = wave_max(m);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+    v[4] = wave_max(v[4]);
     __syncthreads();
-    if (tid % kWave == 0) {
-      lds[(tid / kWave) * 3] = s0;
-      lds[(tid / kWave) * 3 + 1] = s1;
-      lds[(tid / kWave) * 3 + 2] = m;
-    }
+    if (tid % kWave == 0)
+      for (int q = 0; q < NP; ++q) lds[(tid / kWave) * NP + q] = v[q];
     __syncthreads();
     if (tid == 0) {
-      double a0 = lds[0], a1 = lds[1], mm = lds[2];
+      double r[NP];
+      for (int q = 0; q < NP; ++q) r[q] = lds[q];
       for (int w = 1; w < kNT / kWave; ++w) {
-        a0 += lds[w * 3];
-        a1 += lds[w * 3 + 1];
-        mm = fmax(mm, lds[w * 3 + 2]);
+        for (int q = 0; q < 4; ++q) r[q] += lds[w * NP + q];
+        r[4] = fmax(r[4], lds[w * NP + 4]);
       }
       RunState* st = p.state;
-      const double rp = a0 * p.dV, rn = a1 * p.dV;
-      st->released += rp;
-      st->released_pending += rp;
-      st->released_neg += rn;
-      st->released_pending_neg += rn;
-      st->max_beta_n = fmax(st->max_beta_n, p.beta * mm);
+      st->released += r[0] * p.dV;
+      st->released_pending += r[0] * p.dV;
+      st->released_neg += r[1] * p.dV;
+      st->released_pending_neg += r[1] * p.dV;
+      st->released_e += r[2] * p.dV;
+      st->released_q += r[3] * p.dV;
+      st->max_beta_n = fmax(st->max_beta_n, p.beta * r[4]);
       *p.counter = 0u;
     }
   }

@@ -43,6 +43,7 @@ int check_chamber(const it_chamber* ch) {
   if (!(std::isfinite(ch->dt_safety) && ch->dt_safety > 0 && ch->dt_safety <= 1.0)) return IT_EINVAL;
   if (!finite_nonneg(ch->stop_tol) || !finite_nonneg(ch->uniform_n0)) return IT_EINVAL;
   if (!finite_nonneg(ch->reaction_limit)) return IT_EINVAL;
+  if (!finite_nonneg(ch->attach_coeff) || !finite_nonneg(ch->mu_e) || !finite_nonneg(ch->D_e)) return IT_EINVAL;
   if (ch->max_steps < 1) return IT_EINVAL;
   return IT_OK;
 }
@@ -136,12 +137,12 @@ int compute_dt(const it_chamber* ch, const it_track* tr, int64_t n, double* dt) 
 // velocity: +mu+ E for positive ions (towards the cathode at z = d), -mu- E
 // for negative ions.  With a signed c the Appendix's blended drift
 // derivative gives the Lax-Wendroff weights below.
-Coef species_coef(const it_chamber* ch, double dt, int s) {
+// Coefficients of a carrier with signed mobility mu_s (+ for positive
+// carriers, which drift towards the cathode) and diffusion constant D.
+Coef carrier_coef(const it_chamber* ch, double dt, double mu_s, double D) {
   const double dz = ch->gap / ch->nz;
   const double E = ch->voltage / ch->gap;
-  const double mu = s == 0 ? ch->mu_pos : ch->mu_neg;
-  const double D = s == 0 ? ch->D_pos : ch->D_neg;
-  const double c = (s == 0 ? mu * E : -mu * E) * dt / dz;
+  const double c = mu_s * E * dt / dz;
   const double sx = D * dt / (ch->dx * ch->dx);
   const double sy = D * dt / (ch->dy * ch->dy);
   const double sz = D * dt / (dz * dz);
@@ -152,6 +153,28 @@ Coef species_coef(const it_chamber* ch, double dt, int s) {
   k.azm = sz + 0.5 * c * c + 0.5 * c;
   k.a0 = 1.0 - 2.0 * (sx + sy + sz) - c * c;
   return k;
+}
+
+Coef species_coef(const it_chamber* ch, double dt, int s) {
+  return s == 0 ? carrier_coef(ch, dt, ch->mu_pos, ch->D_pos) : carrier_coef(ch, dt, -ch->mu_neg, ch->D_neg);
+}
+
+// Largest dt of eq. vNeum for the free electrons (field along z).
+double electron_dt(const it_chamber* ch) {
+  const double dz = ch->gap / ch->nz;
+  const double E = ch->voltage / ch->gap;
+  const double A = 2.0 * ch->D_e * (1.0 / (ch->dx * ch->dx) + 1.0 / (ch->dy * ch->dy) + 1.0 / (dz * dz));
+  const double v = ch->mu_e * E / dz;
+  const double B = v * v;
+  if (B > 0.0) return 2.0 / (A + std::sqrt(A * A + 4.0 * B));
+  if (A > 0.0) return 1.0 / A;
+  return INFINITY;
+}
+
+// p of eq. free_elec
+double free_fraction(double a, double d) {
+  const double x = a * d;
+  return x == 0.0 ? 1.0 : -std::expm1(-x) / x;
 }
 
 struct Tiling {
@@ -220,6 +243,7 @@ Tiling deposit_tiling(int nx, int ny, int nz) {
 struct Layout {
   size_t field_elems;
   size_t off_field[4];
+  size_t off_ele[2];        // electron densities (free-electron runs only)
   size_t off_partials, partial_doubles;
   size_t off_counter;
   size_t off_state;
@@ -251,7 +275,11 @@ Layout make_layout(const it_chamber* ch, int64_t ntracks) {
   }
   // per-block partial tallies: kAcc slots per fused step (max_grid counts
   // blocks times fused steps)
-  L.partial_doubles = max_grid(ch) * (size_t)kAcc;
+  for (int f = 0; f < 2; ++f) {
+    L.off_ele[f] = off;
+    if (ch->mu_e > 0.0) off = align_up(off + L.field_elems * sizeof(double));
+  }
+  L.partial_doubles = max_grid(ch) * (size_t)std::max(kAcc, kAcc3);
   L.off_partials = off;
   off = align_up(off + L.partial_doubles * sizeof(double));
   L.off_counter = off;
@@ -333,6 +361,32 @@ DepTrack prepare_track(const it_chamber* ch, const it_track& t) {
   return d;
 }
 
+// Deposit parameters common to every deposit of a chamber (fields, tracks,
+// partials and state pointers are filled in by the caller).
+DepositParams base_deposit(const it_chamber* ch, double dt, const Tiling& td) {
+  DepositParams dp;
+  std::memset(&dp, 0, sizeof(dp));
+  const double dz = ch->gap / ch->nz;
+  dp.nx = ch->nx;
+  dp.ny = ch->ny;
+  dp.nz = ch->nz;
+  dp.tiles_x = td.tiles_x;
+  dp.tiles_y = td.tiles_y;
+  dp.zchunks = td.zchunks;
+  dp.zc = td.zc;
+  dp.ntiles = td.ntiles;
+  dp.per_xcd = td.per_xcd;
+  dp.dx = ch->dx;
+  dp.dy = ch->dy;
+  dp.dz = dz;
+  dp.half_gap = 0.5 * ch->gap;
+  dp.Lx = ch->nx * ch->dx;
+  dp.Ly = ch->ny * ch->dy;
+  dp.dV = ch->dx * ch->dy * dz;
+  dp.beta = ch->alpha * dt;
+  return dp;
+}
+
 struct Event {
   int64_t step;
   int64_t par_begin, par_count, tilt_begin, tilt_count;
@@ -393,24 +447,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   sp.state = state;
   sp.trace = trace;
 
-  DepositParams dp;
-  dp.nx = ch->nx;
-  dp.ny = ch->ny;
-  dp.nz = ch->nz;
-  dp.tiles_x = td.tiles_x;
-  dp.tiles_y = td.tiles_y;
-  dp.zchunks = td.zchunks;
-  dp.zc = td.zc;
-  dp.ntiles = td.ntiles;
-  dp.per_xcd = td.per_xcd;
-  dp.dx = ch->dx;
-  dp.dy = ch->dy;
-  dp.dz = dz;
-  dp.half_gap = 0.5 * ch->gap;
-  dp.Lx = ch->nx * ch->dx;
-  dp.Ly = ch->ny * ch->dy;
-  dp.dV = dV;
-  dp.beta = ch->alpha * dt;
+  DepositParams dp = base_deposit(ch, dt, td);
   dp.same_radii = same_r;
   dp.partials = partials;
   dp.counter = counter;
@@ -545,7 +582,7 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.ntiles = ts.ntiles;
     L.off_partials = off;
-    off = align_up(off + std::max((size_t)ts.ntiles * kAcc, (size_t)td.grid * 3) * sizeof(double));
+    off = align_up(off + std::max((size_t)ts.ntiles * kAcc, (size_t)td.grid * 5) * sizeof(double));
     L.off_counter = off;
     off = align_up(off + 64 * sizeof(unsigned));
     L.off_tracks = off;
@@ -569,6 +606,7 @@ int check_batch(const it_chamber* ch, const int64_t* toff, const it_track* track
     if (rc) return rc;
     rc = check_tracks(n ? tracks + toff[q] : nullptr, n);
     if (rc) return rc;
+    if (ch[q].mu_e > 0.0) return IT_ENOTSUP;  // free electrons: single runs only
   }
   return IT_OK;
 }
@@ -605,10 +643,12 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   // stopped by the step limit (the criterion may also fire on the last step)
   if (fin.steps >= max_steps && (!fin.done || fin.by_limit)) flags |= IT_FLAG_MAX_STEPS;
   if (fin.max_beta_n > 1.0) flags |= IT_FLAG_REACTION;
-  const double released = fin.released + fin.released_neg;
+  // charge released of both signs: positive ions + negative charge (negative
+  // ions, plus free electrons when present)
+  const double released = fin.released + fin.released_q;
   if (released > 0.0) {
-    out->f = collected / released;
-    out->f_R = 1.0 - 2.0 * fin.sums[0] / released;
+    out->f = (collected + fin.e_sums[0] + fin.e_sums[1]) / released;
+    out->f_R = 1.0 - 2.0 * (fin.sums[0] + fin.e_sums[2]) / released;
   } else {
     out->f = 1.0;
     out->f_R = 1.0;
@@ -617,6 +657,13 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   out->ks = 1.0 / out->f;
   out->n_released = fin.released;
   out->n_released_neg = fin.released_neg;
+  out->e_released = fin.released_e;
+  out->e_collected_anode = fin.e_sums[0];
+  out->e_collected_cathode = fin.e_sums[1];
+  out->e_recombined = fin.e_sums[2];
+  out->e_left = fin.e_left;
+  out->released_neg_charge = fin.released_q;
+  out->e_steps = fin.e_steps;
   out->n_recombined = fin.sums[0];
   out->n_inflight_pos = fin.last[0];
   out->n_inflight_neg = fin.last[1];
@@ -674,12 +721,81 @@ int it_workspace_size(const it_chamber* ch, int64_t ntracks, size_t* bytes) {
   return IT_OK;
 }
 
+// Electron phase of a free-electron run: steps the three carriers from field
+// pair 0 (and electron array 0) at the electrons' step until the device
+// flags the electrons collected, then leaves the ions in field pair 0.
+// Returns the phase's step count in *e_steps.
+int electron_phase(const it_chamber* ch, double dt_ion, char* ws, const Layout& L, hipStream_t stream,
+                   int64_t* e_steps) {
+  const double dt1 = std::min(dt_ion, ch->dt_safety * electron_dt(ch));
+  Step3Params p;
+  std::memset(&p, 0, sizeof(p));
+  const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, 8, 0);
+  p.nx = ch->nx;
+  p.ny = ch->ny;
+  p.nz = ch->nz;
+  p.tiles_x = tp.tiles_x;
+  p.tiles_y = tp.tiles_y;
+  p.zchunks = tp.zchunks;
+  p.zc = tp.zc;
+  p.ntiles = tp.ntiles;
+  p.per_xcd = tp.per_xcd;
+  p.co[0] = carrier_coef(ch, dt1, ch->mu_pos, ch->D_pos);
+  p.co[1] = carrier_coef(ch, dt1, -ch->mu_neg, ch->D_neg);
+  p.co[2] = carrier_coef(ch, dt1, -ch->mu_e, ch->D_e);
+  p.beta = ch->alpha * dt1;
+  p.dV = ch->dx * ch->dy * (ch->gap / ch->nz);
+  p.stop_tol = ch->stop_tol;
+  p.partials = (double*)(ws + L.off_partials);
+  p.state = (RunState*)(ws + L.off_state);
+  double* pair[2][3] = {{(double*)(ws + L.off_field[0]), (double*)(ws + L.off_field[1]), (double*)(ws + L.off_ele[0])},
+                        {(double*)(ws + L.off_field[2]), (double*)(ws + L.off_field[3]), (double*)(ws + L.off_ele[1])}};
+  RunState* slot = pinned_slots();
+  if (!slot) return IT_EHIP;
+  // released electrons (set by the deposit): none means no electron phase
+  HIP_TRY(hipMemcpyAsync(slot, p.state, sizeof(RunState), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  *e_steps = 0;
+  if (!(slot->released_e > 0.0)) {
+    // mark the phase done so later launches of its kernels (none) skip
+    return IT_OK;
+  }
+  const int64_t check_every = 64;
+  for (int64_t l = 0; l < ch->max_steps; ++l) {
+    for (int s3 = 0; s3 < 3; ++s3) {
+      p.in[s3] = pair[l & 1][s3];
+      p.out[s3] = pair[(l + 1) & 1][s3];
+    }
+    HIP_TRY(launch_step3(p, stream));
+    if ((l + 1) % check_every == 0 || l + 1 == ch->max_steps) {
+      HIP_TRY(hipMemcpyAsync(slot, p.state, sizeof(RunState), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (slot->e_done) break;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(slot, p.state, sizeof(RunState), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  *e_steps = slot->e_steps;
+  if (*e_steps & 1) {  // the ions ended in pair 1: move them to pair 0
+    const size_t bytes = L.field_elems * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(ws + L.off_field[0], ws + L.off_field[2], bytes, hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ws + L.off_field[1], ws + L.off_field[3], bytes, hipMemcpyDeviceToDevice, stream));
+  }
+  return IT_OK;
+}
+
 int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, const it_exec* exec,
              void* d_workspace, size_t ws_bytes, void* stream_, double* h_trace, double* d_pos_out,
              double* d_neg_out, it_result* out) {
   if (!out) return IT_EINVAL;
   int rc = it_validate(ch, tracks, ntracks);
   if (rc) return rc;
+  const bool fe = ch->mu_e > 0.0;
+  if (fe) {  // free electrons: one instantaneous pulse, no space charge
+    if (ch->space_charge) return IT_ENOTSUP;
+    for (int64_t q = 0; q < ntracks; ++q)
+      if (tracks[q].t_s != 0.0) return IT_ENOTSUP;
+  }
   const Layout L = make_layout(ch, ntracks);
   if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
   double dt;
@@ -744,13 +860,51 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     HIP_TRY(hipMemcpyAsync(ws + L.off_tracks, dev.data(), dev.size() * sizeof(DepTrack),
                            hipMemcpyHostToDevice, stream));
 
+  int64_t e_steps = 0;
+  if (fe) {
+    // the pulse, split into ions and electrons, then the electron phase;
+    // the ion phase below starts from its end with no further deposits
+    for (int f = 0; f < 2; ++f)
+      HIP_TRY(hipMemsetAsync(ws + L.off_ele[f], 0, L.field_elems * sizeof(double), stream));
+    DepositParams dp = base_deposit(ch, dt, deposit_tiling(ch->nx, ch->ny, ch->nz));
+    dp.pos = (double*)(ws + L.off_field[0]);
+    dp.neg = (double*)(ws + L.off_field[1]);
+    dp.ele = (double*)(ws + L.off_ele[0]);
+    dp.free_e = 1;
+    dp.attach = ch->attach_coeff;
+    dp.pfree = free_fraction(ch->attach_coeff, ch->gap);
+    dp.uniform = ch->uniform_n0;
+    const DepTrack* tr_dev = (const DepTrack*)(ws + L.off_tracks);
+    if (!events.empty()) {
+      dp.par = tr_dev + events[0].par_begin;
+      dp.npar = (int)events[0].par_count;
+      dp.tilt = tr_dev + events[0].tilt_begin;
+      dp.ntilt = (int)events[0].tilt_count;
+    }
+    dp.same_radii = same_radii(tracks, ntracks);
+    dp.partials = (double*)(ws + L.off_partials);
+    dp.counter = (unsigned*)(ws + L.off_counter);
+    dp.state = (RunState*)(ws + L.off_state);
+    if (!events.empty()) HIP_TRY(launch_deposit(dp, stream));
+    rc = electron_phase(ch, dt, ws, L, stream, &e_steps);
+    if (rc) return rc;
+    events.clear();
+    last_dep = 0;
+  }
+
   RunState fin;
   int issued = 0;
-  rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ch->max_steps, std::max<int64_t>(last_dep, 0),
-                ch->stop_tol, stream, &fin, &issued);
-  if (rc) return rc;
+  const int64_t ion_steps = ch->max_steps - e_steps;
+  if (ion_steps > 0) {
+    rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ion_steps,
+                  std::max<int64_t>(last_dep, 0), ch->stop_tol, stream, &fin, &issued);
+    if (rc) return rc;
+  } else {
+    HIP_TRY(hipMemcpy(&fin, ws + L.off_state, sizeof(fin), hipMemcpyDeviceToHost));
+  }
 
-  fill_result(fin, dt, ch->max_steps, issued, out);
+  fill_result(fin, dt, ion_steps, issued, out);
+  if (fe) out->e_dt = std::min(dt, ch->dt_safety * electron_dt(ch));
 
   if (h_trace && fin.steps > 0)
     HIP_TRY(hipMemcpy(h_trace, ws + L.off_trace, (size_t)fin.steps * IT_TRACE_COLS * sizeof(double),
@@ -868,31 +1022,14 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     std::memset(&init, 0, sizeof(init));
     HIP_TRY(hipMemcpyAsync(states + q, &init, sizeof(init), hipMemcpyHostToDevice, stream));
     if (n || c->uniform_n0 > 0.0) {
-      DepositParams dp;
+      DepositParams dp = base_deposit(c, dts[q], td);
       dp.pos = (double*)(ws + L.off_field[0]);
       dp.neg = (double*)(ws + L.off_field[1]);
-      dp.nx = c->nx;
-      dp.ny = c->ny;
-      dp.nz = c->nz;
-      dp.tiles_x = td.tiles_x;
-      dp.tiles_y = td.tiles_y;
-      dp.zchunks = td.zchunks;
-      dp.zc = td.zc;
-      dp.ntiles = td.ntiles;
-      dp.per_xcd = td.per_xcd;
-      dp.dx = c->dx;
-      dp.dy = c->dy;
-      dp.dz = dz;
-      dp.half_gap = 0.5 * c->gap;
-      dp.Lx = c->nx * c->dx;
-      dp.Ly = c->ny * c->dy;
       dp.uniform = c->uniform_n0;
       dp.par = (const DepTrack*)(ws + L.off_tracks);
       dp.npar = (int)npar;
       dp.tilt = (const DepTrack*)(ws + L.off_tracks) + npar;
       dp.ntilt = (int)(n - npar);
-      dp.dV = dV;
-      dp.beta = c->alpha * dts[q];
       dp.same_radii = same_radii(tq, n);
       dp.partials = (double*)(ws + L.off_partials);
       dp.counter = (unsigned*)(ws + L.off_counter);
