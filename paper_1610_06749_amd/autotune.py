@@ -118,10 +118,11 @@ def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
     return dict(ex_best)
 
 
-def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), cache=None, verbose=False):
-    """Best ``exec`` for it_solve_batch on these chambers: tile rows and the
-    passes per captured graph, each timed on the batch with every instance's
-    step count capped at ``steps``."""
+def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), z_chunks=(8, 16, 32),
+               cache=None, verbose=False):
+    """Best ``exec`` for it_solve_batch on these chambers: tile rows, planes
+    per tile and the passes per captured graph, each timed on the batch with
+    every instance's step count capped at ``steps``."""
     import torch
     sig = "|".join(f"{c['nx']}x{c['ny']}x{c['nz']}" for c in chs)
     key = f"batch:{len(chs)}:{hashlib.sha256(sig.encode()).hexdigest()[:12]}@{_device_name()}"
@@ -134,18 +135,17 @@ def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), cach
     capped = [dict(c, max_steps=steps) for c in chs]
     vs = sum(c["nx"] * c["ny"] * (c["nz"] - 1) for c in chs) * steps
     timings = []
-    for r in rows:
-        for g in graph_passes:
-            ex = dict(kernel=B.IT_KERNEL_PLAIN, tile_y=r, check_every=g)
-            B.it_solve_batch(capped, trs, exec=ex)  # warm-up
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            B.it_solve_batch(capped, trs, exec=ex)
-            torch.cuda.synchronize()
-            t = (time.perf_counter() - t0) / vs
-            timings.append((t, ex))
-            if verbose:
-                print(f"autotune {key}: {ex} -> {1.0 / t:.4g} voxel-steps/s", flush=True)
+    for r, g, z in ((r, g, z) for r in rows for g in graph_passes for z in z_chunks):
+        ex = dict(kernel=B.IT_KERNEL_PLAIN, tile_y=r, check_every=g, z_chunk=z)
+        B.it_solve_batch(capped, trs, exec=ex)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.it_solve_batch(capped, trs, exec=ex)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / vs
+        timings.append((t, ex))
+        if verbose:
+            print(f"autotune {key}: {ex} -> {1.0 / t:.4g} voxel-steps/s", flush=True)
     t_best, ex_best = min(timings, key=lambda p: p[0])
     _memo[key] = dict(ex_best)
     table[key] = {"exec": dict(ex_best), "voxel_steps_per_s": 1.0 / t_best,

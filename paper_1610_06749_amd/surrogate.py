@@ -78,7 +78,7 @@ class Surrogate:
         self.seed = seed
         self.model = None
 
-    def fit(self, X, lnks, steps=60000, lr=2e-3, lr_final=1e-5, batch=2048, log_every=1000, margin=1e-3):
+    def fit(self, X, lnks, steps=150000, lr=2e-3, lr_final=1e-5, batch=2048, log_every=1000, margin=1e-3):
         """Standardisation from the training inputs (log space), training box
         with a small margin, targets standardised around the residual; then
         ``steps`` Adam steps on minibatches of ``batch`` rows of the data
@@ -133,7 +133,7 @@ class Surrogate:
         return out, mask
 
 
-def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4, steps=60000, seed=None):
+def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4, steps=150000, seed=None):
     """The surrogate experiment: train on n_train solver runs, judge on
     n_hold held-out solver runs, time n_query queries.  Returns a dict."""
     import torch
@@ -181,6 +181,7 @@ def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4
         "holdout_accepted_fraction": float(acc.mean()),
         "holdout_rel_err_accepted_max": float(rel[acc].max()) if acc.any() else None,
         "holdout_rel_err_accepted_p99": float(np.quantile(rel[acc], 0.99)) if acc.any() else None,
+        "holdout_frac_within_0.1pct_all": float(np.mean(rel < 1e-3)),
         "holdout_rel_err_all_median": float(np.median(rel)),
         "holdout_rel_err_all_p90": float(np.quantile(rel, 0.9)),
         "baseline_rel_err_median": float(np.median(rel_base)),
