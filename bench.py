@@ -45,6 +45,9 @@ def parse():
                     help="launches in the stepping-kernel timing")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only run the stepping kernel on the workload grid (for counter runs)")
+    ap.add_argument("--variant", choices=("none", "space-charge", "free-electrons"), default="none",
+                    help="with --kernel-only: the space-charge stepping instance, or a free-electron run "
+                         "(uniform dose, electron phase then ions) on the workload grid")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 96-chamber sweep")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
     ap.add_argument("--surrogate-train", type=int, default=8192)
@@ -160,6 +163,15 @@ def main():
     nint = (ch["nz"] - 1) * ch["nx"] * ch["ny"]
     stream = torch.cuda.current_stream()
 
+    if a.kernel_only and a.variant == "free-electrons":
+        che = dict(ch, uniform_n0=3e9, attach_coeff=5.0, mu_e=1500.0, D_e=1500.0 * 0.02526,
+                   max_steps=max(a.kernel_steps, 1))
+        r = it.it_solve(che, W.no_tracks())
+        torch.cuda.synchronize()
+        print(json.dumps({"free_electron_run": {k: r[k] for k in ("e_steps", "steps", "flags", "f")}}))
+        return
+    if a.kernel_only and a.variant == "space-charge":
+        ch = dict(ch, space_charge=1)
     if a.kernel_only:
         dt = it.it_dt(ch, tr)
         pos0, neg0 = W.perturbed_field((ch["nz"] + 1, ch["ny"], ch["nx"]), seed=5, scale=1e9)
