@@ -302,33 +302,59 @@ struct GradJob {
   int w_off, b_off;    // parameter offsets of weights [nO][K] and bias [nO]
 };
 
+// One 16 x 16 tile of G per block on FP32 MFMA (v_mfma_f32_16x16x4f32,
+// A[i][k]: lane i + 16 k, B[k][j]: lane j + 16 k, D[i][j]: lane j + 16 (i/4),
+// item i % 4): A = delta (outputs x samples), B = inputs (samples x inputs,
+// the column after the last input is 1 for the bias).  The block's 4 waves
+// take interleaved groups of 4 samples, sum them in fixed order through LDS:
+// deterministic.
 __global__ __launch_bounds__(256) void wgrad_kernel(GradJob job, int64_t n, size_t delta_stride,
                                                     size_t in_stride, float* grad) {
-  __shared__ float sd[64][16], si[64][17];
+  __shared__ float part[4][16][16];
   const int m = blockIdx.z;
-  const float* delta = job.delta + m * delta_stride;
-  const float* in = job.in + m * in_stride;
+  const float* __restrict__ delta = job.delta + m * delta_stride;
+  const float* __restrict__ in = job.in + m * in_stride;
   const int o0 = blockIdx.y * 16, i0 = blockIdx.x * 16;
-  const int to = threadIdx.x / 16, ti = threadIdx.x % 16;
-  float acc = 0.0f;
-  for (int64_t s0 = 0; s0 < n; s0 += 64) {
-    for (int q = threadIdx.x; q < 64 * 16; q += 256) {
-      const int s = q / 16, c = q % 16;
-      const int64_t gs = s0 + s;
-      const int o = o0 + c, i = i0 + c;
-      sd[s][c] = (gs < n && o < job.nO) ? delta[gs * job.rows_d + o] : 0.0f;
-      si[s][c] = gs < n ? (i < job.K ? in[gs * job.K + i] : (i == job.K ? 1.0f : 0.0f)) : 0.0f;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = lane & 15, k = lane >> 4;
+  const int o = o0 + r, i = i0 + r;  // A row (output) and B column (input) of this lane
+  const bool o_ok = o < job.nO;
+  const float bias_one = i == job.K ? 1.0f : 0.0f;
+  float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  // samples sb + k with the wave-uniform base sb = 16 g + 4 wave, g = 0, 1,
+  // ...: each MFMA takes 4 samples; loop bounds are uniform over the wave
+  constexpr int kU = 4;  // MFMAs per unrolled group (loads issued ahead)
+  int64_t sb = 4 * wave;
+  for (; sb + 16 * (kU - 1) + 3 < n; sb += 16 * kU) {
+    float a[kU], b[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t su = sb + 16 * u + k;
+      a[u] = o_ok ? delta[su * job.rows_d + o] : 0.0f;
+      b[u] = i < job.K ? in[su * job.K + i] : bias_one;
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int s = 0; s < 64; ++s) acc += sd[s][to] * si[s][ti];
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
   }
-  const int o = o0 + to, i = i0 + ti;
-  if (o < job.nO && i <= job.K) {
-    float* g = grad + (size_t)m * kP;
-    if (i < job.K) g[job.w_off + o * job.K + i] = acc;
-    else g[job.b_off + o] = acc;
+  for (; sb < n; sb += 16) {  // the tail: one group of 4 samples per MFMA, missing samples as zeros
+    const int64_t su = sb + k;
+    const bool in_range = su < n;
+    const float a = in_range && o_ok ? delta[su * job.rows_d + o] : 0.0f;
+    const float b = in_range ? (i < job.K ? in[su * job.K + i] : bias_one) : 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[wave][4 * k + v][r] = acc[v];  // D[4k + v][r]
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int oo = threadIdx.x / 16, ii = threadIdx.x % 16;
+    const float g = ((part[0][oo][ii] + part[1][oo][ii]) + part[2][oo][ii]) + part[3][oo][ii];
+    const int og = o0 + oo, ig = i0 + ii;
+    if (og < job.nO && ig <= job.K) {
+      float* gm = grad + (size_t)m * kP;
+      if (ig < job.K) gm[job.w_off + og * job.K + ig] = g;
+      else gm[job.b_off + og] = g;
+    }
   }
 }
 
