@@ -89,6 +89,12 @@ struct StepParams {
   unsigned* counter;
   RunState* state;
   double* trace;            // [max_steps][IT_TRACE_COLS]
+  // one-step kernel only: when set, one extra block of the launch reduces
+  // the partials of the previous step (prev_nblocks blocks) and records step
+  // prev_step, overlapping the reduction with this step's stencil
+  const double* prev_partials;
+  int prev_nblocks;
+  int64_t prev_step;
 };
 
 struct DepositParams {
@@ -140,8 +146,10 @@ hipError_t launch_step3(const Step3Params& p, hipStream_t s);
 int plain_tile_rows(int tile_y);
 // ev_begin / ev_end (may be null) are recorded around the stepping kernel
 // alone, before the tally reduction is launched.
+// fused: leave this step's partials to the next launch's extra block (or a
+// closing launch_reduce_steps) instead of launching the reduction now.
 hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin = nullptr,
-                             hipEvent_t ev_end = nullptr);
+                             hipEvent_t ev_end = nullptr, bool fused = false);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
 // sc: some instance has the space-charge term on

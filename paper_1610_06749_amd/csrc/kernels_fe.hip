@@ -30,7 +30,6 @@ __global__ __launch_bounds__(kNT3) void step3_kernel(Step3Params p) {
   const int x0 = t.tx * kTX3, y0 = t.ty * kTY3;
   const int w = min(kTX3, p.nx - x0), h = min(kTY3, p.ny - y0);
   const bool active = t.valid && lane < w && ty < h;
-  const double am = active ? 1.0 : 0.0;
   const int k0 = 1 + t.zc * p.zc;
   const int k1 = t.valid ? min(k0 + p.zc, p.nz) : k0;
   const size_t plane = (size_t)p.nx * p.ny;
@@ -70,15 +69,18 @@ __global__ __launch_bounds__(kNT3) void step3_kernel(Step3Params p) {
                        co.ay * (sl[s][ty][lane + 1] + sl[s][ty + 2][lane + 1]) + co.azp * q[s] +
                        co.azm * m[s] - sinks[s];
       if (active) p.out[s][base + own] = v;
-      acc[8 + s] += am * v;
-      acc[11 + s] += am * fabs(v);
+      // outside the valid extent v comes from unwritten LDS slots (possibly
+      // NaN): select it away rather than multiply by zero
+      const double va = active ? v : 0.0;
+      acc[8 + s] += va;
+      acc[11 + s] += fabs(va);
     }
-    acc[0] += am * sink_n;
-    acc[1] += am * sink_e;
+    acc[0] += active ? sink_n : 0.0;
+    acc[1] += active ? sink_e : 0.0;
     if (k == 1)
-      for (int s = 0; s < 3; ++s) acc[2 + 2 * s] += am * c[s];
+      for (int s = 0; s < 3; ++s) acc[2 + 2 * s] += active ? c[s] : 0.0;
     if (k == p.nz - 1)
-      for (int s = 0; s < 3; ++s) acc[3 + 2 * s] += am * c[s];
+      for (int s = 0; s < 3; ++s) acc[3 + 2 * s] += active ? c[s] : 0.0;
     __syncthreads();
     for (int s = 0; s < 3; ++s) {
       m[s] = c[s];

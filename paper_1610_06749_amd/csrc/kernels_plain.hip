@@ -18,8 +18,23 @@ namespace it {
 
 constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 
+// With p.prev_partials set, the launch has one block more than tiles: that
+// block sums the previous step's partials in a fixed order and records the
+// step (finalize_steps), while the others compute this step.  The kernel
+// boundary before this launch makes the previous partials visible; the
+// state it writes is read by the next launch.  Stepping blocks that read
+// `done` while it is being set only decide whether to compute a step past
+// the stop, whose output goes to the field pair not holding the stop step.
 template <int SY, bool SC>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_plain_kernel(StepParams p) {
+  if (p.prev_partials && blockIdx.x == gridDim.x - 1) {
+    if (p.state->done) return;
+    __shared__ double totals[kAcc];
+    reduce_partials<kTX * SY>(p.prev_partials, p.prev_nblocks, kAcc, kAcc, totals);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+      finalize_steps(p.state, p.trace, totals, 1, p.prev_step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
+    return;
+  }
   if (p.state->done) return;  // set by an earlier launch: every block skips
   plain_tile_step<SY, SC>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
                           p.partials + (size_t)blockIdx.x * kAcc);
@@ -46,10 +61,10 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
 int plain_tile_rows(int tile_y) { return tile_y == 16 ? 16 : 8; }
 
 hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin,
-                             hipEvent_t ev_end) {
+                             hipEvent_t ev_end, bool fused) {
   const int grid = 8 * p.per_xcd;
   if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
-  const dim3 g(grid);
+  const dim3 g(grid + (p.prev_partials ? 1 : 0));
   const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
   if (plain_tile_rows(tile_y) == 16) {
     if (sc) hipLaunchKernelGGL((step_plain_kernel<16, true>), g, dim3(kTX, 16), 0, s, p);
@@ -61,6 +76,7 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end && hipEventRecord(ev_end, s) != hipSuccess) return hipErrorInvalidValue;
+  if (fused) return hipSuccess;  // the next launch (or a closing reduction) records this step
   return launch_reduce_steps(p, grid, 1, s);
 }
 

@@ -279,7 +279,9 @@ Layout make_layout(const it_chamber* ch, int64_t ntracks) {
     L.off_ele[f] = off;
     if (ch->mu_e > 0.0) off = align_up(off + L.field_elems * sizeof(double));
   }
-  L.partial_doubles = max_grid(ch) * (size_t)std::max(kAcc, kAcc3);
+  // two halves: the one-step kernel alternates between them (a step's
+  // partials are reduced during the next step)
+  L.partial_doubles = 2 * max_grid(ch) * (size_t)std::max(kAcc, kAcc3);
   L.off_partials = off;
   off = align_up(off + L.partial_doubles * sizeof(double));
   L.off_counter = off;
@@ -446,6 +448,9 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   sp.counter = counter;
   sp.state = state;
   sp.trace = trace;
+  sp.prev_partials = nullptr;
+  sp.prev_nblocks = 0;
+  sp.prev_step = 0;
 
   DepositParams dp = base_deposit(ch, dt, td);
   dp.same_radii = same_r;
@@ -475,9 +480,29 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
     rc = code;
     return code;
   };
+  // One-step runs record step l during launch l+1 (an extra block reduces
+  // step l's partials while the others compute step l+1); the partials
+  // alternate between two buffers.  A step still unrecorded is closed by a
+  // reduction launch before a deposit (so that its record does not count the
+  // deposit) and at the end.
+  const bool fused = T == 1;
+  const int grid_plain = 8 * tp.per_xcd;
+  double* part_buf[2] = {partials, partials + L.partial_doubles / 2};
+  bool unrecorded = false;
+  int64_t unrecorded_step = 0;
+  auto close_step = [&]() -> hipError_t {
+    if (!unrecorded) return hipSuccess;
+    unrecorded = false;
+    StepParams q = sp;
+    q.partials = part_buf[unrecorded_step & 1];
+    q.step0 = unrecorded_step;
+    q.prev_partials = nullptr;
+    return launch_reduce_steps(q, grid_plain, 1, stream);
+  };
   while (l < nsteps && !stopped) {
     if (ev < events.size() && events[ev].step == l) {
       const Event& e = events[ev];
+      if (close_step() != hipSuccess) { fail(IT_EHIP); break; }
       dp.pos = field[2 * cur];
       dp.neg = field[2 * cur + 1];
       dp.uniform = e.uniform ? ch->uniform_n0 : 0.0;
@@ -503,7 +528,17 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       sp.zc = tp.zc;
       sp.ntiles = tp.ntiles;
       sp.per_xcd = tp.per_xcd;
-      e = launch_step_plain(sp, rows, stream, ev_pair(0), ev_pair(1));
+      if (fused) {
+        sp.partials = part_buf[l & 1];
+        sp.prev_partials = unrecorded ? part_buf[unrecorded_step & 1] : nullptr;
+        sp.prev_nblocks = grid_plain;
+        sp.prev_step = unrecorded_step;
+        e = launch_step_plain(sp, rows, stream, ev_pair(0), ev_pair(1), true);
+        unrecorded = true;
+        unrecorded_step = l;
+      } else {
+        e = launch_step_plain(sp, rows, stream, ev_pair(0), ev_pair(1));
+      }
     } else {
       e = launch_step_blocked(sp, (int)todo, tile_y, stream, ev_pair(0), ev_pair(1));
     }
@@ -527,6 +562,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       }
     }
   }
+  if (rc == IT_OK && close_step() != hipSuccess) fail(IT_EHIP);
   if (rc == IT_OK) {
     if (hipMemcpyAsync(&slots[slot_head], state, sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)

@@ -85,7 +85,6 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   if (ty == 2 && lane < h) { rim_off = (unsigned)((y0 + lane) * p.nx + i_left) * 8u; rim_r = lane + 1; rim_c = 0; }
   if (ty == 3 && lane < h) { rim_off = (unsigned)((y0 + lane) * p.nx + i_right) * 8u; rim_r = lane + 1; rim_c = w + 1; }
   const bool rim = t.valid && rim_r >= 0;
-  const double am = active ? 1.0 : 0.0;
 
   // plane pointers are block-uniform (scalar registers); threads add their
   // 32-bit in-plane byte offset
@@ -129,17 +128,21 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
       __builtin_nontemporal_store(vp, (__attribute__((address_space(1))) double*)(uniform_ptr(p.pout + o) + own));
       __builtin_nontemporal_store(vn, (__attribute__((address_space(1))) double*)(uniform_ptr(p.nout + o) + own));
     }
-    acc[0] += am * sink;
-    acc[5] += am * vp;
-    acc[6] += am * vn;
-    acc[7] += am * fabs(vp);
-    acc[8] += am * fabs(vn);
+    // Threads outside the tile's valid extent read LDS slots that this
+    // block never wrote (whatever an earlier workgroup left, possibly NaN),
+    // so their values are selected away, never multiplied by zero.
+    const double vpa = active ? vp : 0.0, vna = active ? vn : 0.0;
+    acc[0] += active ? sink : 0.0;
+    acc[5] += vpa;
+    acc[6] += vna;
+    acc[7] += fabs(vpa);
+    acc[8] += fabs(vna);
     if (SC) {
-      acc[9] += am * scp;
-      acc[10] += am * scn;
+      acc[9] += active ? scp : 0.0;
+      acc[10] += active ? scn : 0.0;
     }
     if (k == 1 || k == nz - 1) {  // uniform over the block
-      const double sp_ = wave_sum(am * c.p), sn_ = wave_sum(am * c.n);
+      const double sp_ = wave_sum(active ? c.p : 0.0), sn_ = wave_sum(active ? c.n : 0.0);
       if (lane == 0) {
         if (k == 1) {  // anode side
           edge[ty][0] += sp_;

@@ -263,6 +263,32 @@ def test_reaction_blow_up_stops_at_same_step(gpu, orc):
     assert g["max_beta_n"] == pytest.approx(o["max_beta_n"], rel=1e-9)
 
 
+@pytest.mark.parametrize("ex", [dict(kernel=1, tile_y=8, check_every=1), dict(kernel=1, tile_y=16)],
+                         ids=["plain8_check1", "plain16"])
+def test_ragged_tallies_after_nonfinite_run(gpu, orc, ex):
+    # A run that diverges leaves NaN in LDS of the CUs it ran on.  Threads
+    # outside a ragged tile's valid extent read such stale slots, so the
+    # tallies of a later run are only exact if those values are discarded
+    # (selected away, not multiplied by zero).
+    import torch
+    ch, tr = ragged_case()
+    ch["reaction_limit"] = 0.0
+    tr[2, 0], tr[2, 1] = 50.0, 5e-4
+    assert gpu.it_solve(ch, tr)["flags"] & gpu.IT_FLAG_NONFINITE
+    ch = W.chamber(67, 9, 21, 3e-4, 21 * 2e-4, 20.0, dy=4e-4)
+    dt = orc.dt(ch)
+    p0, n0 = W.perturbed_field((22, 9, 67), seed=11, scale=1e11)
+    op, on, otr = orc.advance(ch, dt, p0, n0, 5, with_trace=True)
+    for _ in range(2):
+        gp = torch.tensor(p0, device="cuda")
+        gn = torch.tensor(n0, device="cuda")
+        gtr = gpu.it_advance(ch, dt, gp, gn, 5, exec=ex, trace=True)
+        assert np.isfinite(gtr).all()
+        compare_fields(gp, op)
+        compare_fields(gn, on)
+        compare_trace(gtr[:, :9], otr[:, :9], np.abs(p0).sum() * ch["dx"] * ch["dy"] * ch["gap"] / 21)
+
+
 @pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
 def test_advance_from_given_fields(gpu, orc, ex):
     import torch
