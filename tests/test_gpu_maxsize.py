@@ -1,0 +1,116 @@
+"""The largest chamber plane the library accepts (nx * ny = 2^28 nodes; the
+stepping kernels address a plane with 32-bit byte offsets), on the GPU,
+against the oracle on a small window.
+
+The densities are zero except near one spot, placed on the corner where the
+periodic x and y wraps meet.  A step spreads the support by one node, and a
+track's profile is cut at 8 b, so after s steps everything outside a window
+with a wide enough margin is exactly zero, and the window evolves as the same
+window stepped as a chamber of its own (whose own wraps then only meet
+zeros).  The oracle steps that small chamber; the GPU steps the full plane.
+The window is compared node by node, and everything outside it must be
+exactly zero.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+NX = NY = 1 << 14  # 2^28 nodes per plane
+NZ = 3
+WIN = 64           # window edge (nodes); the spot sits at its centre
+DX = 2e-4
+C = WIN // 2
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_06749_amd as it
+    it.lib()
+    yield it
+    torch.cuda.empty_cache()
+
+
+def big_chamber(**kw):
+    return W.chamber(NX, NY, NZ, DX, NZ * DX, 3.0, **kw)
+
+
+def small_chamber(**kw):
+    return W.chamber(WIN, WIN, NZ, DX, NZ * DX, 3.0, **kw)
+
+
+def window_index(torch):
+    # small-window node i <-> full-plane node (i - C) mod N
+    idx = torch.tensor((np.arange(WIN) - C) % NX, device="cuda")
+    return idx[:, None], idx[None, :]
+
+
+def check_window(torch, g, ref):
+    """g: full-plane device field; ref: oracle field of the window."""
+    ys, xs = window_index(torch)
+    win = g[:, ys, xs].cpu().numpy()
+    assert np.max(np.abs(win - ref)) <= RTOL * np.max(np.abs(ref))
+    assert np.linalg.norm(win - ref) <= RTOL * np.linalg.norm(ref)
+    g[:, ys, xs] = 0.0
+    assert float(g.abs().max()) == 0.0  # nothing outside the window
+
+
+@pytest.mark.parametrize("ex", [None, dict(kernel=1, tile_y=16), dict(kernel=2, steps_per_pass=4)],
+                         ids=["default", "plain16", "blocked4"])
+def test_advance_on_largest_plane(gpu, orc, ex):
+    import torch
+    steps = 8
+    ch_s = small_chamber()
+    dt = orc.dt(ch_s)
+    rng = np.random.default_rng(2024)
+    p0 = np.zeros((NZ + 1, WIN, WIN))
+    n0 = np.zeros((NZ + 1, WIN, WIN))
+    spot = (slice(1, NZ), slice(C - 8, C + 8), slice(C - 8, C + 8))
+    p0[spot] = rng.uniform(0.0, 1e10, size=(NZ - 1, 16, 16))
+    n0[spot] = rng.uniform(0.0, 1e10, size=(NZ - 1, 16, 16))
+    op, on, otr = orc.advance(ch_s, dt, p0, n0, steps, with_trace=True)
+
+    ch = big_chamber()
+    ys, xs = window_index(torch)
+    gp = torch.zeros((NZ + 1, NY, NX), dtype=torch.float64, device="cuda")
+    gn = torch.zeros_like(gp)
+    gp[:, ys, xs] = torch.tensor(p0, device="cuda")
+    gn[:, ys, xs] = torch.tensor(n0, device="cuda")
+    ws = gpu.workspace(ch, 0)
+    gtr = gpu.it_advance(ch, dt, gp, gn, steps, exec=ex, ws=ws, trace=True)
+    del ws
+    N = np.abs(p0).sum() * DX * DX * DX
+    assert np.max(np.abs(gtr[:, :9] - otr[:, :9])) <= RTOL * N
+    check_window(torch, gp, op)
+    check_window(torch, gn, on)
+    del gp, gn
+    torch.cuda.empty_cache()
+
+
+def test_track_on_largest_plane(gpu, orc):
+    """One track through the wrap corner: deposit and ten steps."""
+    import torch
+    b = 2 * DX  # profile cut at 8 b = 16 nodes; 10 steps spread it 10 more
+    x0, y0 = 0.3 * DX, 0.6 * DX
+    tr_big = W.tracks([[20.0, b, x0, y0, 0.0, 0.0, 0.0]])
+    tr_small = W.tracks([[20.0, b, x0 + C * DX, y0 + C * DX, 0.0, 0.0, 0.0]])
+    o = orc.solve(small_chamber(max_steps=10), tr_small, with_trace=True, with_fields=True)
+    g = gpu.it_solve(big_chamber(max_steps=10), tr_big, trace=True, fields=True)
+    assert g["steps"] == o["steps"] == 10 and g["flags"] == o["flags"]
+    N = o["n_released"]
+    assert g["n_released"] == pytest.approx(N, rel=RTOL)
+    assert g["dt"] == pytest.approx(o["dt"], rel=1e-14)
+    for k in ("n_recombined", "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode",
+              "n_inflight_pos", "n_inflight_neg"):
+        assert abs(g[k] - o[k]) <= RTOL * N, (k, g[k], o[k])
+    assert np.max(np.abs(g["trace"] - o["trace"])) <= RTOL * N
+    check_window(torch, g["pos"], o["pos"])
+    check_window(torch, g["neg"], o["neg"])
+    del g
+    torch.cuda.empty_cache()
