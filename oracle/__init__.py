@@ -24,8 +24,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
           "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit",
-          "attach_coeff", "mu_e", "D_e")
-_OPTIONAL = ("space_charge", "reaction_limit", "attach_coeff", "mu_e", "D_e")
+          "attach_coeff", "mu_e", "D_e", "lateral_bc")
+_OPTIONAL = ("space_charge", "reaction_limit", "attach_coeff", "mu_e", "D_e", "lateral_bc")
 E_KEYS = ("e_released", "e_collected_anode", "e_collected_cathode", "e_recombined", "e_steps", "e_dt",
           "e_left", "released_neg_charge")
 E_TRACE_KEYS = ("recombined_pn", "recombined_pe", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
@@ -34,10 +34,10 @@ E_TRACE_KEYS = ("recombined_pn", "recombined_pe", "pos_anode", "pos_cathode", "n
 R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
           "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
           "col_neg_cathode", "dt", "steps", "flags", "max_beta_n", "n_space_charge_pos",
-          "n_space_charge_neg", "n_released_neg")
+          "n_space_charge_neg", "n_released_neg", "n_escaped_pos", "n_escaped_neg")
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
               "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
-              "neg_space_charge", "released_neg")
+              "neg_space_charge", "released_neg", "pos_escaped", "neg_escaped")
 NT = len(TRACE_KEYS)
 
 FLAG_MAX_STEPS, FLAG_NONFINITE, FLAG_REACTION, FLAG_EMPTY = 1, 2, 4, 8
@@ -213,7 +213,8 @@ def solve(ch, tracks, with_trace: bool = False, with_fields: bool = True):
     if rc == -2:
         raise ValueError("no stable time step")
     if rc == -3:
-        raise ValueError("free electrons need an instantaneous pulse and no space charge")
+        raise ValueError("free electrons need an instantaneous pulse, no space charge and periodic "
+                         "lateral boundaries")
     if rc:
         raise MemoryError("oracle solve failed")
     out = dict(zip(R_KEYS, res.tolist()))

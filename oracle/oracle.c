@@ -30,7 +30,10 @@
  *   - f = N_collected / N_released                              (eq. collection_efficiency)
  *
  * Readings where the paper is silent (each also listed in the design notes):
- *   - x and y are periodic; the transverse cell is nx*dx by ny*dy.
+ *   - x and y are periodic by default; the transverse cell is nx*dx by
+ *     ny*dy.  Optionally (lateral_bc = 1) they are absorbing instead: the
+ *     nodes just outside the cell hold zero, like the electrodes, and what
+ *     they would receive in a step is tallied as escaped.
  *   - c carries the sign of the drift velocity (+mu E for positive ions,
  *     -mu E for negative ions).  With that sign the paper's blended drift
  *     derivative is exactly the Lax-Wendroff update.
@@ -61,17 +64,17 @@
 enum {
   P_DX, P_DY, P_GAP, P_VOLT, P_MU_POS, P_MU_NEG, P_D_POS, P_D_NEG,
   P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_REACTION_LIMIT,
-  P_ATTACH, P_MU_E, P_D_E, P_COUNT
+  P_ATTACH, P_MU_E, P_D_E, P_LATERAL_BC, P_COUNT
 };
 /* result vector */
 enum {
   R_F, R_KS, R_F_RECOMB, R_RELEASED, R_RECOMBINED, R_INFLIGHT_POS, R_INFLIGHT_NEG,
   R_COL_POS_ANODE, R_COL_POS_CATHODE, R_COL_NEG_ANODE, R_COL_NEG_CATHODE,
-  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_RELEASED_NEG, R_COUNT
+  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_RELEASED_NEG, R_ESC_POS, R_ESC_NEG, R_COUNT
 };
 /* per-step record */
 enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_INFLIGHT, T_NEG_INFLIGHT,
-       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_POS_SC, T_NEG_SC, T_RELEASED_NEG, T_COUNT };
+       T_POS_ABS, T_NEG_ABS, T_RELEASED, T_POS_SC, T_NEG_SC, T_RELEASED_NEG, T_POS_ESC, T_NEG_ESC, T_COUNT };
 
 /* track record: {let_keV_um, b, x0, y0, theta, phi, t, b_neg}; b_neg = 0
  * means the negative ions share the radius b */
@@ -137,6 +140,13 @@ static double wrap(double d, double L)
   return d - L * floor(d / L + 0.5);
 }
 
+/* Transverse offset of a point from a track axis: wrapped to the nearest
+ * periodic image, or as it is with absorbing lateral boundaries. */
+static double lateral_offset(const double *p, double d, double L)
+{
+  return p[P_LATERAL_BC] != 0.0 ? d : wrap(d, L);
+}
+
 /* Axis direction of a track: (sin th cos ph, sin th sin ph, cos th). */
 static void track_axis(const double *tr, double *u)
 {
@@ -159,8 +169,8 @@ static double track_density(const double *p, int64_t nx, int64_t ny, int64_t nz,
   const double dz = p[P_GAP] / (double)nz;
   const double N0 = tr[0] * 1.0e7 / p[P_W]; /* keV/um -> eV/cm, divided by W: pairs/cm */
   const double b = track_radius(tr, s);
-  const double wx = wrap((double)i * p[P_DX] - tr[2], (double)nx * p[P_DX]);
-  const double wy = wrap((double)j * p[P_DY] - tr[3], (double)ny * p[P_DY]);
+  const double wx = lateral_offset(p, (double)i * p[P_DX] - tr[2], (double)nx * p[P_DX]);
+  const double wy = lateral_offset(p, (double)j * p[P_DY] - tr[3], (double)ny * p[P_DY]);
   const double wz = (double)k * dz - 0.5 * p[P_GAP];
   /* squared distance from the axis: |w x u|^2 */
   const double cx = wy * u[2] - wz * u[1];
@@ -178,8 +188,8 @@ static double track_density_at(const double *p, int64_t nx, int64_t ny, const do
 {
   const double N0 = tr[0] * 1.0e7 / p[P_W];
   const double b = track_radius(tr, s);
-  const double wx = wrap(x - tr[2], (double)nx * p[P_DX]);
-  const double wy = wrap(y - tr[3], (double)ny * p[P_DY]);
+  const double wx = lateral_offset(p, x - tr[2], (double)nx * p[P_DX]);
+  const double wy = lateral_offset(p, y - tr[3], (double)ny * p[P_DY]);
   const double wz = z - 0.5 * p[P_GAP];
   const double cx = wy * u[2] - wz * u[1];
   const double cy = wz * u[0] - wx * u[2];
@@ -296,13 +306,29 @@ double orc_uniform(const double *p, int64_t nx, int64_t ny, int64_t nz, double n
   return n0 * dV * (double)(nx * ny * (nz - 1));
 }
 
+/* Density of n at interior node (k, j, i) displaced by (dj, di) laterally:
+ * the periodic image, or 0 beyond an absorbing lateral boundary. */
+static double lateral_neighbour(const double *p, int64_t nx, int64_t ny, const double *n,
+                                int64_t k, int64_t j, int64_t i, int64_t dj, int64_t di)
+{
+  int64_t jj = j + dj, ii = i + di;
+  if (p[P_LATERAL_BC] != 0.0) {
+    if (jj < 0 || jj >= ny || ii < 0 || ii >= nx) return 0.0;
+  } else {
+    jj = (jj + ny) % ny;
+    ii = (ii + nx) % nx;
+  }
+  return n[IDX(k, jj, ii)];
+}
+
 /* One explicit step of eq. theEquation for both species from the old
  * densities (pos, neg) into (npos, nneg).  tally receives the per-step
  * record (T_*), all in ion counts (density times dV): recombined pairs,
  * collected at each electrode per species, in-flight per species (signed
- * sum of the new densities), the sum of the new |n| per species, and the
- * change of each species by the space-charge term.  The released slot
- * (released before this step) is left at 0 here; the run fills it.
+ * sum of the new densities), the sum of the new |n| per species, the
+ * change of each species by the space-charge term, and, with absorbing
+ * lateral boundaries, what left each species through them.  The released
+ * slot (released before this step) is left at 0 here; the run fills it.
  *
  * For every interior node and species, with the Appendix's derivatives:
  *   dn/dz  ~ c (n_k - n_{k-1})/dz + (1-c)(n_{k+1} - n_{k-1})/(2 dz)
@@ -323,6 +349,8 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   const double *in[2] = {pos, neg};
   double *out[2] = {npos, nneg};
   double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0}, screen[2] = {0.0, 0.0};
+  double escaped[2] = {0.0, 0.0};
+  const int absorbing = p[P_LATERAL_BC] != 0.0;
   /* mu dt q/eps0 per species, signed as the term enters n' (- for n+, + for n-) */
   const double sc_on = p[P_SPACE_CHARGE] != 0.0 ? 1.0 : 0.0;
   const double gsc[2] = {-sc_on * p[P_MU_POS] * dt * Q_E / EPS0, sc_on * p[P_MU_NEG] * dt * Q_E / EPS0};
@@ -330,17 +358,23 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   for (int64_t k = 1; k < nz; ++k)
     for (int64_t j = 0; j < ny; ++j)
       for (int64_t i = 0; i < nx; ++i) {
-        const int64_t ip = (i + 1) % nx, im = (i + nx - 1) % nx;
-        const int64_t jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
         const double np_ = pos[IDX(k, j, i)], nn_ = neg[IDX(k, j, i)];
         const double sink = beta * np_ * nn_;
         recomb += sink;
+        /* lateral neighbours missing beyond an absorbing boundary (a node
+         * of a one-node-wide cell misses both) */
+        const double miss_x = absorbing ? (double)((i == 0) + (i == nx - 1)) : 0.0;
+        const double miss_y = absorbing ? (double)((j == 0) + (j == ny - 1)) : 0.0;
         for (int s = 0; s < 2; ++s) {
           const double *n = in[s];
           const double c = w[s][0], sx = w[s][1], sy = w[s][2], sz = w[s][3];
           const double nc = n[IDX(k, j, i)];
-          const double lap_x = n[IDX(k, j, ip)] - 2.0 * nc + n[IDX(k, j, im)];
-          const double lap_y = n[IDX(k, jp, i)] - 2.0 * nc + n[IDX(k, jm, i)];
+          const double lap_x = lateral_neighbour(p, nx, ny, n, k, j, i, 0, 1) - 2.0 * nc
+                               + lateral_neighbour(p, nx, ny, n, k, j, i, 0, -1);
+          const double lap_y = lateral_neighbour(p, nx, ny, n, k, j, i, 1, 0) - 2.0 * nc
+                               + lateral_neighbour(p, nx, ny, n, k, j, i, -1, 0);
+          /* a missing neighbour would have received sx n (or sy n) */
+          escaped[s] += (sx * miss_x + sy * miss_y) * nc;
           const double lap_z = n[IDX(k + 1, j, i)] - 2.0 * nc + n[IDX(k - 1, j, i)];
           /* c * dz * (dn/dz) with the blended derivative */
           const double drift = c * (c * (nc - n[IDX(k - 1, j, i)])
@@ -384,6 +418,8 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   tally[T_RELEASED_NEG] = 0.0;
   tally[T_POS_SC] = screen[0] * dV;
   tally[T_NEG_SC] = screen[1] * dV;
+  tally[T_POS_ESC] = escaped[0] * dV;
+  tally[T_NEG_ESC] = escaped[1] * dV;
 }
 
 static double field_max(int64_t n, const double *a, const double *b)
@@ -421,6 +457,7 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   }
   const double beta = p[P_ALPHA] * dt;
   double released = 0.0, released_neg = 0.0, sums[5] = {0, 0, 0, 0, 0}, screened[2] = {0, 0};
+  double esc[2] = {0, 0};
   double last[T_COUNT] = {0};
   double max_beta_n = 0.0;
   int flags = 0;
@@ -455,6 +492,8 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
     for (int q = 0; q < 5; ++q) sums[q] += tally[q];
     screened[0] += tally[T_POS_SC];
     screened[1] += tally[T_NEG_SC];
+    esc[0] += tally[T_POS_ESC];
+    esc[1] += tally[T_NEG_ESC];
     memcpy(last, tally, sizeof(last));
     if (trace) memcpy(trace + T_COUNT * l, tally, sizeof(tally));
     steps = l + 1;
@@ -504,6 +543,8 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   res[R_RELEASED_NEG] = released_neg;
   res[R_SC_POS] = screened[0];
   res[R_SC_NEG] = screened[1];
+  res[R_ESC_POS] = esc[0];
+  res[R_ESC_NEG] = esc[1];
   return 0;
 }
 
@@ -648,7 +689,8 @@ static void step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt
  * the positive plus negative charge released); res_e: RE_COUNT values of the
  * electron phase; trace: NULL or max_steps * T_COUNT phase-2 records;
  * trace_e: NULL or max_steps * E_COUNT phase-1 records.  Returns 0, -2 (no
- * step), -3 (a track not at t = 0, or space charge on) or -1. */
+ * step), -3 (a track not at t = 0, space charge on, or absorbing lateral
+ * boundaries) or -1. */
 int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz,
                              const double *trk, int64_t ntr, int64_t max_steps,
                              double *pos_out, double *neg_out, double *trace, double *res,
@@ -656,7 +698,7 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
 {
   for (int64_t t = 0; t < ntr; ++t)
     if (trk[TRK * t + 6] != 0.0) return -3;
-  if (p[P_SPACE_CHARGE] != 0.0) return -3;
+  if (p[P_SPACE_CHARGE] != 0.0 || p[P_LATERAL_BC] != 0.0) return -3;
   double dt;
   int rc = orc_dt(p, nx, ny, nz, trk, ntr, &dt);
   if (rc) return rc;
@@ -790,6 +832,8 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
   res[R_MAX_BETA_N] = max_beta_n;
   res[R_SC_POS] = 0.0;
   res[R_SC_NEG] = 0.0;
+  res[R_ESC_POS] = 0.0;
+  res[R_ESC_NEG] = 0.0;
   res[R_RELEASED_NEG] = rel_neg;
   res_e[RE_RELEASED] = rel_e;
   res_e[RE_COLLECTED_ANODE] = e_col[0];

@@ -352,9 +352,9 @@ def _check_conservation(r, tol=1e-12):
     N = r["n_released"]
     assert tr[:, 9].sum() == pytest.approx(N, rel=1e-14)
     assert tr[:, 12].sum() == pytest.approx(r["n_released_neg"], rel=1e-14)
-    for s, (a, c, S, Q, rel) in enumerate(((1, 2, 5, 10, 9), (3, 4, 6, 11, 12))):
+    for s, (a, c, S, Q, rel, X) in enumerate(((1, 2, 5, 10, 9, 13), (3, 4, 6, 11, 12, 14))):
         prev = np.concatenate([[0.0], tr[:-1, S]]) + tr[:, rel]
-        err = prev - tr[:, a] - tr[:, c] - tr[:, 0] + tr[:, Q] - tr[:, S]
+        err = prev - tr[:, a] - tr[:, c] - tr[:, 0] + tr[:, Q] - tr[:, X] - tr[:, S]
         assert np.max(np.abs(err)) <= tol * N
 
 
@@ -789,3 +789,183 @@ def test_all_electrons_free_collects_almost_everything(orc):
     ch = _fe_chamber(0.9999, 100.0)
     r = orc.solve(ch, W.no_tracks(), with_fields=False)
     assert r["f"] > 0.999
+
+
+# ---------------------------------------------------------------------------
+# absorbing lateral boundaries (the option to the periodic reading): the
+# nodes just outside the cell hold zero and what they would receive is
+# tallied as escaped
+# ---------------------------------------------------------------------------
+
+def _dense_step_absorbing(ch, dt, pos, neg):
+    """One step as a dense matrix on the grid padded by one ghost node on
+    every lateral side (ghosts start at zero and have no wrap), so the
+    ghosts' new values are what left through the lateral boundaries."""
+    nx, ny, nz = ch["nx"], ch["ny"], ch["nz"]
+    dx, dy, dz = ch["dx"], ch["dy"], ch["gap"] / nz
+    E = ch["voltage"] / ch["gap"]
+    X, Y = nx + 2, ny + 2
+    Ix, Iy, Iz = np.eye(X), np.eye(Y), np.eye(nz + 1)
+
+    def open_second(m, h):
+        return (np.eye(m, k=1) - 2 * np.eye(m) + np.eye(m, k=-1)) / h ** 2
+
+    def pad(f):
+        g = np.zeros((nz + 1, Y, X))
+        g[:, 1:-1, 1:-1] = f
+        return g
+
+    Dxx = np.kron(np.kron(Iz, Iy), open_second(X, dx))
+    Dyy = np.kron(np.kron(Iz, open_second(Y, dy)), Ix)
+    up, down = np.eye(nz + 1, k=1), np.eye(nz + 1, k=-1)
+    Dzz = np.kron(np.kron((up - 2 * Iz + down) / dz ** 2, Iy), Ix)
+    backward = (Iz - down) / dz
+    central = (up - down) / (2 * dz)
+    P, N = pad(pos), pad(neg)
+    out, esc = [], []
+    for s, (mu, D, sign) in enumerate([(ch["mu_pos"], ch["D_pos"], 1.0), (ch["mu_neg"], ch["D_neg"], -1.0)]):
+        v = sign * mu * E
+        c = v * dt / dz
+        Dz = np.kron(np.kron(c * backward + (1 - c) * central, Iy), Ix)
+        M = np.eye((nz + 1) * Y * X) + dt * (D * (Dxx + Dyy + Dzz) - v * Dz)
+        n_new = (M @ (P, N)[s].ravel() - ch["alpha"] * dt * P.ravel() * N.ravel()).reshape(nz + 1, Y, X)
+        ghost = n_new[1:nz].sum() - n_new[1:nz, 1:-1, 1:-1].sum()
+        esc.append(ghost * dx * dy * dz)
+        out.append(n_new[:, 1:-1, 1:-1].copy())
+        out[-1][0] = 0.0
+        out[-1][nz] = 0.0
+    return out[0], out[1], esc
+
+
+@pytest.mark.parametrize("geom", [(4, 4, 5), (3, 5, 2), (1, 1, 7), (6, 2, 4)])
+def test_absorbing_step_matches_dense_matrix_scheme(orc, geom):
+    nx, ny, nz = geom
+    ch = W.chamber(nx, ny, nz, 3e-4, nz * 2.5e-4, 40.0, dy=4e-4, D_pos=0.03, D_neg=0.05,
+                   alpha=1.6e-6, lateral_bc=1)
+    dt = orc.dt(ch)
+    pos, neg = W.perturbed_field((nz + 1, ny, nx), seed=8, scale=3e11)
+    p1, n1, tally = orc.step(ch, dt, pos, neg)
+    p2, n2, esc = _dense_step_absorbing(ch, dt, pos, neg)
+    scale = max(np.abs(pos).max(), np.abs(neg).max())
+    assert np.max(np.abs(p1 - p2)) <= 1e-14 * scale
+    assert np.max(np.abs(n1 - n2)) <= 1e-14 * scale
+    tot = (pos.sum() + neg.sum()) * ch["dx"] * ch["dy"] * ch["gap"] / nz
+    assert esc[0] > 0 and esc[1] > 0
+    assert tally["pos_escaped"] == pytest.approx(esc[0], abs=1e-13 * tot)
+    assert tally["neg_escaped"] == pytest.approx(esc[1], abs=1e-13 * tot)
+
+
+def test_absorbing_pure_diffusion_eigenmode(orc):
+    """E = 0, alpha = 0: a product of sines vanishing on the ghost nodes and
+    on the electrodes is an eigenvector of the explicit scheme, so after m
+    steps the field is lambda^m times the initial one, and the escaped
+    tally follows the boundary nodes of that closed form."""
+    nx, ny, nz = 9, 6, 8
+    dx, dy, dz = 3e-4, 4e-4, 2.5e-4
+    D = 0.04
+    ch = W.chamber(nx, ny, nz, dx, nz * dz, 0.0, dy=dy, alpha=0.0, D_pos=D, D_neg=D, lateral_bc=1)
+    dt = orc.dt(ch)
+    a, b, c = 2, 1, 3
+    i = np.arange(nx)
+    j = np.arange(ny)
+    k = np.arange(nz + 1)
+    f0 = 1e10 * (np.sin(np.pi * c * k / nz)[:, None, None] * np.sin(np.pi * b * (j + 1) / (ny + 1))[None, :, None]
+                 * np.sin(np.pi * a * (i + 1) / (nx + 1))[None, None, :])
+    f0[0] = 0.0
+    f0[nz] = 0.0
+    sx, sy, sz = D * dt / dx ** 2, D * dt / dy ** 2, D * dt / dz ** 2
+    lam = (1 - 4 * sx * np.sin(np.pi * a / (2 * (nx + 1))) ** 2 - 4 * sy * np.sin(np.pi * b / (2 * (ny + 1))) ** 2
+           - 4 * sz * np.sin(np.pi * c / (2 * nz)) ** 2)
+    m = 7
+    p, n, tr = orc.advance(ch, dt, f0, f0, m, with_trace=True)
+    assert np.max(np.abs(p - lam ** m * f0)) <= 1e-12 * np.abs(f0).max()
+    dV = dx * dy * dz
+    edge = sx * (f0[:, :, 0].sum() + f0[:, :, -1].sum()) + sy * (f0[:, 0, :].sum() + f0[:, -1, :].sum())
+    expect = np.array([lam ** l * edge * dV for l in range(m)])
+    got = tr[:, 13]
+    assert np.max(np.abs(got - expect)) <= 1e-12 * np.abs(f0).sum() * dV
+
+
+def test_absorbing_equals_antisymmetric_periodic_extension(orc):
+    """Without recombination the scheme is linear and symmetric in x and y,
+    so the absorbing cell evolves as the odd extension of its field on a
+    periodic cell of 2(nx+1) by 2(ny+1) nodes, whose nodes at the mirror
+    lines stay zero."""
+    nx, ny, nz = 7, 5, 9
+    ch_a = W.chamber(nx, ny, nz, 3e-4, nz * 2.5e-4, 30.0, dy=4e-4, alpha=0.0, D_pos=0.03, D_neg=0.05,
+                     lateral_bc=1)
+    X, Y = 2 * (nx + 1), 2 * (ny + 1)
+    ch_p = dict(ch_a, nx=X, ny=Y, lateral_bc=0)
+    dt = orc.dt(ch_a)
+    assert dt == orc.dt(ch_p)
+    p0, n0 = W.perturbed_field((nz + 1, ny, nx), seed=12, scale=1e10)
+
+    def odd(f):
+        g = np.zeros((nz + 1, Y, X))
+        g[:, 1:ny + 1, 1:nx + 1] = f
+        g[:, 1:ny + 1, nx + 2:] = -f[:, :, ::-1]
+        g[:, ny + 2:, :] = -g[:, 1:ny + 1, :][:, ::-1, :]
+        return g
+
+    steps = 11
+    pa, na = orc.advance(ch_a, dt, p0, n0, steps)
+    pp, nn = orc.advance(ch_p, dt, odd(p0), odd(n0), steps)
+    scale = np.abs(p0).max()
+    assert np.max(np.abs(pp[:, 1:ny + 1, 1:nx + 1] - pa)) <= 1e-13 * scale
+    assert np.max(np.abs(nn[:, 1:ny + 1, 1:nx + 1] - na)) <= 1e-13 * scale
+    assert np.max(np.abs(pp[:, 0, :])) <= 1e-13 * scale and np.max(np.abs(pp[:, :, nx + 1])) <= 1e-13 * scale
+
+
+def test_absorbing_deposit_is_the_unwrapped_profile(orc):
+    """A track inside the cell deposits, on an absorbing cell, what it
+    deposits on the first nx x ny nodes of a periodic cell twice as wide in
+    both directions: there no node of the original cell is closer to a
+    periodic image of the axis than to the axis itself."""
+    nx, ny, nz = 20, 16, 10
+    ch_a = W.chamber(nx, ny, nz, 3e-4, nz * 3e-4, 20.0, lateral_bc=1)
+    ch_p = dict(ch_a, nx=2 * nx, ny=2 * ny, lateral_bc=0)
+    tr = W.tracks([[30.0, 1.5e-3, 0.4e-3, 4.4e-3, 0.5, 0.7, 0.0]])  # near the x = 0 edge
+    dt = orc.dt(ch_a, tr)
+    pa, na, rel_a = orc.deposit(ch_a, tr, 0, dt)
+    pp, npp, rel_p = orc.deposit(ch_p, tr, 0, dt)
+    assert np.array_equal(pa, pp[:, :ny, :nx]) and np.array_equal(na, npp[:, :ny, :nx])
+    # and the periodic deposit on the original cell differs (it wraps)
+    pw, _, rel_w = orc.deposit(dict(ch_a, lateral_bc=0), tr, 0, dt)
+    assert rel_w > rel_a * (1 + 1e-3)
+
+
+def test_absorbing_far_from_the_edges_equals_periodic(orc):
+    """While the densities stay away from the lateral edges the two
+    boundary options step identically and nothing escapes."""
+    ch_a = W.chamber(40, 40, 12, 2e-4, 12 * 2.5e-4, 10.0, lateral_bc=1)
+    ch_p = dict(ch_a, lateral_bc=0)
+    dt = orc.dt(ch_a)
+    f = _blob(ch_a, (20, 20, 6), 1.2)
+    pa, na, ta = orc.advance(ch_a, dt, f, 0.7 * f, 6, with_trace=True)
+    pp, npp, tp = orc.advance(ch_p, dt, f, 0.7 * f, 6, with_trace=True)
+    assert np.max(np.abs(pa - pp)) <= 1e-15 * f.max()
+    assert np.max(np.abs(ta[:, 13:15])) <= 1e-14 * f.sum() * 2e-4 * 2e-4 * 2.5e-4
+
+
+def test_absorbing_conservation_and_escape(orc):
+    """A track at the corner of an absorbing cell: every species balances
+    with the escaped column, charge escapes, and f falls below the
+    recombination-only efficiency f_R."""
+    ch = W.chamber(24, 20, 16, 3e-4, 16 * 3e-4, 15.0, lateral_bc=1)
+    tr = W.tracks([[20.0, 8e-4, 0.2e-3, 0.3e-3, 0.0, 0.0, 0.0],
+                   [10.0, 6e-4, 3.6e-3, 3.0e-3, 0.4, 2.0, 0.0]])
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    assert r["flags"] == 0
+    _check_conservation(r)
+    assert r["n_escaped_pos"] > 1e-3 * r["n_released"] and r["n_escaped_neg"] > 1e-3 * r["n_released"]
+    assert r["n_escaped_pos"] == pytest.approx(r["trace"][:, 13].sum(), rel=1e-12)
+    col = r["col_pos_anode"] + r["col_pos_cathode"] + r["col_neg_anode"] + r["col_neg_cathode"]
+    assert col + r["n_escaped_pos"] + r["n_escaped_neg"] + 2 * r["n_recombined"] == \
+        pytest.approx(2 * r["n_released"], rel=1e-10)
+    assert r["f"] < r["f_R"] - 1e-3
+
+
+def test_absorbing_rejects_free_electrons(orc):
+    ch = dict(W.chamber(8, 8, 6, 3e-4, 6 * 3e-4, 15.0, lateral_bc=1, uniform_n0=1e9), mu_e=1000.0, D_e=25.0)
+    with pytest.raises(ValueError):
+        orc.solve(ch, W.no_tracks())

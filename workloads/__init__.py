@@ -74,7 +74,7 @@ REACTION_LIMIT = 0.5
 
 def chamber(nx, ny, nz, dx, gap, voltage, dy=None, *, dt_safety=1.0, stop_tol=1e-12,
             max_steps=1_000_000, uniform_n0=0.0, space_charge=0, reaction_limit=REACTION_LIMIT,
-            **consts) -> dict:
+            lateral_bc=0, **consts) -> dict:
     c = dict(AIR)
     c.update(consts)
     return dict(nx=int(nx), ny=int(ny), nz=int(nz), dx=float(dx),
@@ -84,7 +84,8 @@ def chamber(nx, ny, nz, dx, gap, voltage, dy=None, *, dt_safety=1.0, stop_tol=1e
                 alpha=float(c["alpha"]), W_eV=float(c["W_eV"]),
                 dt_safety=float(dt_safety), stop_tol=float(stop_tol),
                 max_steps=int(max_steps), uniform_n0=float(uniform_n0),
-                space_charge=int(space_charge), reaction_limit=float(reaction_limit))
+                space_charge=int(space_charge), reaction_limit=float(reaction_limit),
+                lateral_bc=int(lateral_bc))
 
 
 def tracks(rows) -> np.ndarray:
