@@ -22,7 +22,7 @@
  * Units: cm, s, V, keV/um for LET, eV for W.  All arithmetic is FP64.
  *
  * Grid: nx * ny transverse nodes x_i = i dx, y_j = j dy with periodic lateral
- * boundaries; nz gap intervals of dz = gap/nz, planes k = 0..nz, of which
+ * boundaries (or, optionally, absorbing ones); nz gap intervals of dz = gap/nz, planes k = 0..nz, of which
  * k = 1..nz-1 are interior.  Density fields are FP64 arrays [nz+1][ny][nx]
  * with x fastest; planes 0 and nz always hold zero.
  *
@@ -63,7 +63,7 @@ extern "C" {
 #define IT_FLAG_EMPTY 8      /* nothing was released; f is reported as 1 */
 
 /* ---- per-step trace record: IT_TRACE_COLS doubles per step, in ion counts ---- */
-#define IT_TRACE_COLS 13
+#define IT_TRACE_COLS 15
 /* 0 recombined pairs, 1/2 positive ions collected at anode/cathode,
  * 3/4 negative ions collected at anode/cathode, 5/6 positive/negative ions in
  * flight after the step (signed sum of n dV), 7/8 sum of |n| dV after the
@@ -71,8 +71,10 @@ extern "C" {
  * change of the positive/negative ions by the space-charge term in the step
  * (0 with space charge off), 12 negative ions released by deposits made
  * before the step (equal to column 9 unless tracks give the negative ions
- * their own radius).  Per species: in flight after = in flight before +
- * released - collected - recombined + space-charge change. */
+ * their own radius), 13/14 positive/negative ions that left through
+ * absorbing lateral boundaries in the step (0 with periodic ones).  Per
+ * species: in flight after = in flight before + released - collected -
+ * recombined + space-charge change - escaped. */
 
 /* Chamber, field, transport constants and run control. */
 typedef struct {
@@ -108,13 +110,23 @@ typedef struct {
   double mu_e;          /* electron mobility [cm^2/(V s)] (>= 0; 0 = no free electrons) */
   double D_e;           /* electron diffusion constant [cm^2/s] (>= 0) */
   int64_t max_steps;    /* hard step limit (>= 1), both phases together */
+  /* Lateral (x, y) boundaries, which the paper leaves open: 0 = periodic (the
+   * transverse cell repeats), 1 = absorbing: the nodes just outside the cell
+   * hold zero, like the electrodes, and what they would receive in a step
+   * (ax or ay times the density of each node next to the boundary, per
+   * missing neighbour) leaves the chamber and is counted as escaped; track
+   * offsets are then not wrapped.  Absorbing boundaries work with the
+   * one-step kernel (IT_KERNEL_AUTO / IT_KERNEL_PLAIN) and in batches, not
+   * with the blocked kernel or free electrons (IT_ENOTSUP). */
+  int32_t lateral_bc;
 } it_chamber;
 
 /* One ion track.  The axis passes through (x, y, gap/2) with direction
  * (sin theta cos phi, sin theta sin phi, cos theta); theta is the angle to the
  * field.  The track is deposited at the start of step floor(t/dt).  The
  * transverse offset of a node from (x, y) is wrapped to the nearest periodic
- * image and the profile is cut at a perpendicular distance of 8 b. */
+ * image (with periodic lateral boundaries) and the profile is cut at a
+ * perpendicular distance of 8 b. */
 typedef struct {
   double let_keV_um;    /* LET in air [keV/um] (>= 0) */
   double b_cm;          /* Gaussian track radius b [cm] (> 0) */
@@ -130,7 +142,8 @@ typedef struct {
 /* Result of a run (all counts in ion pairs / ions). */
 typedef struct {
   double f;             /* collection efficiency: charge collected / charge released,
-                         * both signs (free electrons included) */
+                         * both signs (free electrons included; charge that escapes
+                         * through absorbing lateral boundaries is not collected) */
   double ks;            /* recombination factor 1/f */
   double f_R;           /* 1 - recombined pairs / mean charge released per sign */
   double n_released, n_recombined;
@@ -150,6 +163,8 @@ typedef struct {
   double e_left;        /* electrons still in flight when the phase ended */
   double e_dt;          /* step of the electron phase [s] */
   double released_neg_charge;  /* negative charge released (ions + electrons) */
+  double n_escaped_pos, n_escaped_neg;  /* ions lost through absorbing lateral
+                         * boundaries over the run (0 with periodic ones) */
   int64_t e_steps;      /* steps of the electron phase */
   int64_t steps;        /* steps counted in the result */
   int32_t flags;        /* IT_FLAG_* */

@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libiontracks.so")
 
 IT_OK, IT_EINVAL, IT_ENODT, IT_EWORKSPACE, IT_EHIP, IT_ENOTSUP = 0, -1, -2, -3, -4, -5
 IT_FLAG_MAX_STEPS, IT_FLAG_NONFINITE, IT_FLAG_REACTION, IT_FLAG_EMPTY = 1, 2, 4, 8
-IT_TRACE_COLS = 13
+IT_TRACE_COLS = 15
 IT_KERNEL_AUTO, IT_KERNEL_PLAIN, IT_KERNEL_BLOCKED = 0, 1, 2
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
               "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
-              "neg_space_charge", "released_neg")
+              "neg_space_charge", "released_neg", "pos_escaped", "neg_escaped")
 
 
 class ItError(RuntimeError):
@@ -40,7 +40,7 @@ class it_chamber(ctypes.Structure):
                 ("W_eV", ctypes.c_double), ("dt_safety", ctypes.c_double), ("stop_tol", ctypes.c_double),
                 ("uniform_n0", ctypes.c_double), ("reaction_limit", ctypes.c_double),
                 ("attach_coeff", ctypes.c_double), ("mu_e", ctypes.c_double), ("D_e", ctypes.c_double),
-                ("max_steps", ctypes.c_int64)]
+                ("max_steps", ctypes.c_int64), ("lateral_bc", ctypes.c_int32)]
 
 
 class it_result(ctypes.Structure):
@@ -48,7 +48,8 @@ class it_result(ctypes.Structure):
         "f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos", "n_inflight_neg",
         "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "max_beta_n",
         "n_space_charge_pos", "n_space_charge_neg", "n_released_neg", "e_released", "e_collected_anode",
-        "e_collected_cathode", "e_recombined", "e_left", "e_dt", "released_neg_charge")] + \
+        "e_collected_cathode", "e_recombined", "e_left", "e_dt", "released_neg_charge", "n_escaped_pos",
+        "n_escaped_neg")] + \
         [("e_steps", ctypes.c_int64), ("steps", ctypes.c_int64), ("flags", ctypes.c_int32),
          ("passes", ctypes.c_int32)]
 
@@ -119,6 +120,7 @@ def _chamber(ch) -> it_chamber:
     for k in ("reaction_limit", "attach_coeff", "mu_e", "D_e"):  # optional keys
         setattr(c, k, float(ch.get(k, 0.0)))
     c.space_charge = int(ch.get("space_charge", 0))
+    c.lateral_bc = int(ch.get("lateral_bc", 0))
     return c
 
 

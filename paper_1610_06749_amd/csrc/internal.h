@@ -16,7 +16,10 @@ namespace it {
 //   5 sum n+' (new)              6 sum n-'
 //   7 sum |n+'|                  8 sum |n-'|
 //   9 sum of the space-charge change of n+   10 the same of n-
-constexpr int kAcc = 11;
+//  11 sum over nodes next to an absorbing lateral boundary of what the
+//     missing neighbours would receive from n+ (ax or ay times n+ per
+//     missing neighbour)                      12 the same of n-
+constexpr int kAcc = 13;
 
 // elementary charge [C] and vacuum permittivity [F/cm] (CODATA 2018)
 constexpr double kElementaryCharge = 1.602176634e-19;
@@ -43,6 +46,7 @@ struct RunState {
   double last[4];           // in-flight pos/neg and |n| sums after the last step
   double max_beta_n;        // max over deposits of beta * max(n)
   double screened[2];       // running space-charge change of n+ and n-
+  double escaped[2];        // running loss of n+ and n- through absorbing lateral boundaries
   // free-electron component
   double released_q;        // negative charge released (ions + electrons)
   double released_e;        // free electrons released
@@ -83,6 +87,7 @@ struct StepParams {
   //   n+' += gsp n+ (n+ - n-),  n-' += gsn n- (n+ - n-)
   // gsp = -mu+ dt q/eps0, gsn = +mu- dt q/eps0 (both 0 when off)
   double gsp, gsn;
+  int absorbing;            // 1: absorbing lateral boundaries (zero beyond the cell), 0: periodic
   int64_t step0;            // index of the step this launch computes
   int64_t min_stop_step;    // the stop criterion is tested only from this step on
   double* partials;         // [gridDim][kAcc * T]
@@ -103,6 +108,7 @@ struct DepositParams {
   int nx, ny, nz;
   int tiles_x, tiles_y, zchunks, zc, ntiles, per_xcd;
   double dx, dy, dz, half_gap, Lx, Ly;
+  int absorbing;            // 1: transverse offsets as they are; 0: nearest periodic image
   double uniform;           // uniform density added at this deposit (0 if none)
   const DepTrack* par;      // tracks parallel to the field
   int npar;
@@ -152,8 +158,9 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
                              hipEvent_t ev_end = nullptr, bool fused = false);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
-// sc: some instance has the space-charge term on
-hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, int parity,
-                             hipStream_t s);
+// sc: some instance has the space-charge term on; ab: some instance has
+// absorbing lateral boundaries
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, bool ab,
+                             int parity, hipStream_t s);
 
 }  // namespace it

@@ -22,7 +22,7 @@ __device__ inline int find_instance(const BatchInstance* inst, int ninst, int L)
   return lo;
 }
 
-template <int SY, bool SC>
+template <int SY, bool SC, bool AB>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                        int parity) {
@@ -35,7 +35,7 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
   const int l = L - inst[q].tile_begin;
   TileCoord t = tile_of(l, p.tiles_x, p.tiles_y);
   t.valid = true;
-  plain_tile_step<SY, SC>(p, t, p.partials + (size_t)l * kAcc);
+  plain_tile_step<SY, SC, AB>(p, t, p.partials + (size_t)l * kAcc);
 }
 
 __global__ __launch_bounds__(1024) void batch_reduce_kernel(const BatchInstance* __restrict__ inst,
@@ -57,25 +57,26 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(const BatchInstance*
 
 }  // namespace
 
-hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, int parity,
-                             hipStream_t s) {
+template <int SY, bool SC, bool AB>
+void launch_batch_instance(const BatchInstance* inst, int ninst, int total_tiles, int per_xcd, int parity,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((batch_step_kernel<SY, SC, AB>), dim3(8 * per_xcd), dim3(kTX, SY), 0, s, inst, ninst,
+                     total_tiles, per_xcd, parity);
+}
+
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, bool ab,
+                             int parity, hipStream_t s) {
   const BatchInstance* inst = (const BatchInstance*)table;
   const int per_xcd = (total_tiles + 7) / 8;
-  const dim3 g(8 * per_xcd);
-  if (plain_tile_rows(tile_y) == 16) {
-    if (sc)
-      hipLaunchKernelGGL((batch_step_kernel<16, true>), g, dim3(kTX, 16), 0, s, inst, ninst, total_tiles, per_xcd,
-                         parity);
-    else
-      hipLaunchKernelGGL((batch_step_kernel<16, false>), g, dim3(kTX, 16), 0, s, inst, ninst, total_tiles,
-                         per_xcd, parity);
-  } else {
-    if (sc)
-      hipLaunchKernelGGL((batch_step_kernel<8, true>), g, dim3(kTX, 8), 0, s, inst, ninst, total_tiles, per_xcd,
-                         parity);
-    else
-      hipLaunchKernelGGL((batch_step_kernel<8, false>), g, dim3(kTX, 8), 0, s, inst, ninst, total_tiles, per_xcd,
-                         parity);
+  switch ((plain_tile_rows(tile_y) == 16 ? 4 : 0) + (sc ? 2 : 0) + (ab ? 1 : 0)) {
+    case 0: launch_batch_instance<8, false, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 1: launch_batch_instance<8, false, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 2: launch_batch_instance<8, true, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 3: launch_batch_instance<8, true, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 4: launch_batch_instance<16, false, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 5: launch_batch_instance<16, false, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 6: launch_batch_instance<16, true, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    default: launch_batch_instance<16, true, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

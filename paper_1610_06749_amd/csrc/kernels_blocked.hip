@@ -186,6 +186,8 @@ __global__ __launch_bounds__(kBNT) void step_blocked_kernel(StepParams p) {
       a[t * kAcc + 9] = 0.0;
       a[t * kAcc + 10] = 0.0;
     }
+    a[t * kAcc + 11] = 0.0;  // escaped: the blocked kernel is periodic only
+    a[t * kAcc + 12] = 0.0;
   }
   block_sum_store<kAcc * T, kBNT>(a, p.partials + (size_t)blockIdx.x * kAcc * T, lds);
 }

@@ -25,7 +25,7 @@ constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 // state it writes is read by the next launch.  Stepping blocks that read
 // `done` while it is being set only decide whether to compute a step past
 // the stop, whose output goes to the field pair not holding the stop step.
-template <int SY, bool SC>
+template <int SY, bool SC, bool AB>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_plain_kernel(StepParams p) {
   if (p.prev_partials && blockIdx.x == gridDim.x - 1) {
     if (p.state->done) return;
@@ -36,8 +36,8 @@ __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))
     return;
   }
   if (p.state->done) return;  // set by an earlier launch: every block skips
-  plain_tile_step<SY, SC>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
-                          p.partials + (size_t)blockIdx.x * kAcc);
+  plain_tile_step<SY, SC, AB>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
+                              p.partials + (size_t)blockIdx.x * kAcc);
 }
 
 // One block: sums the per-block partial tallies of a stepping launch in a
@@ -60,19 +60,38 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
 
 int plain_tile_rows(int tile_y) { return tile_y == 16 ? 16 : 8; }
 
+namespace {
+
+template <int SY, bool SC, bool AB>
+void launch_plain_instance(const StepParams& p, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL((step_plain_kernel<SY, SC, AB>), g, dim3(kTX, SY), 0, s, p);
+}
+
+// the kernel instance for the tile rows, the space-charge term and the
+// lateral boundary option of the run
+void launch_plain_variant(const StepParams& p, int rows, dim3 g, hipStream_t s) {
+  const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
+  const bool ab = p.absorbing != 0;
+  switch ((rows == 16 ? 4 : 0) + (sc ? 2 : 0) + (ab ? 1 : 0)) {
+    case 0: launch_plain_instance<8, false, false>(p, g, s); break;
+    case 1: launch_plain_instance<8, false, true>(p, g, s); break;
+    case 2: launch_plain_instance<8, true, false>(p, g, s); break;
+    case 3: launch_plain_instance<8, true, true>(p, g, s); break;
+    case 4: launch_plain_instance<16, false, false>(p, g, s); break;
+    case 5: launch_plain_instance<16, false, true>(p, g, s); break;
+    case 6: launch_plain_instance<16, true, false>(p, g, s); break;
+    default: launch_plain_instance<16, true, true>(p, g, s); break;
+  }
+}
+
+}  // namespace
+
 hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin,
                              hipEvent_t ev_end, bool fused) {
   const int grid = 8 * p.per_xcd;
   if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
   const dim3 g(grid + (p.prev_partials ? 1 : 0));
-  const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
-  if (plain_tile_rows(tile_y) == 16) {
-    if (sc) hipLaunchKernelGGL((step_plain_kernel<16, true>), g, dim3(kTX, 16), 0, s, p);
-    else hipLaunchKernelGGL((step_plain_kernel<16, false>), g, dim3(kTX, 16), 0, s, p);
-  } else {
-    if (sc) hipLaunchKernelGGL((step_plain_kernel<8, true>), g, dim3(kTX, 8), 0, s, p);
-    else hipLaunchKernelGGL((step_plain_kernel<8, false>), g, dim3(kTX, 8), 0, s, p);
-  }
+  launch_plain_variant(p, plain_tile_rows(tile_y), g, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end && hipEventRecord(ev_end, s) != hipSuccess) return hipErrorInvalidValue;
@@ -87,10 +106,15 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
 // their sum is formed once per column; tilted tracks are evaluated per node.
 // The perpendicular distance is |w x u| with w the node's offset from the
 // axis point (x0, y0, d/2), its transverse part wrapped to the nearest
-// periodic image; the profile is cut at r^2 > (8 b)^2.
+// periodic image (taken as it is with absorbing lateral boundaries); the
+// profile is cut at r^2 > (8 b)^2.
 // ---------------------------------------------------------------------------
 
 __device__ inline double wrap_near(double d, double L) { return d - L * floor(d / L + 0.5); }
+
+__device__ inline double lateral_offset(const DepositParams& p, double d, double L) {
+  return p.absorbing ? d : wrap_near(d, L);
+}
 
 __device__ inline double axis_r2(const DepTrack& tr, double wx, double wy, double wz) {
   const double cx = wy * tr.uz - wz * tr.uy;
@@ -123,7 +147,8 @@ __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
     for (int q = 0; q < p.npar; ++q) {
       const DepTrack tr = p.par[q];
       double dp, dn;
-      track_values(tr, wrap_near(x - tr.x0, p.Lx), wrap_near(y - tr.y0, p.Ly), 0.0, same, dp, dn);
+      track_values(tr, lateral_offset(p, x - tr.x0, p.Lx), lateral_offset(p, y - tr.y0, p.Ly), 0.0, same, dp,
+                   dn);
       g0p += dp;
       g0n += dn;
     }
@@ -136,7 +161,8 @@ __global__ __launch_bounds__(kNT) void deposit_kernel(DepositParams p) {
         for (int q = 0; q < p.ntilt; ++q) {
           const DepTrack tr = p.tilt[q];
           double dp, dn;
-          track_values(tr, wrap_near(x - tr.x0, p.Lx), wrap_near(y - tr.y0, p.Ly), wz, same, dp, dn);
+          track_values(tr, lateral_offset(p, x - tr.x0, p.Lx), lateral_offset(p, y - tr.y0, p.Ly), wz, same,
+                       dp, dn);
           d_p += dp;
           d_n += dn;
         }

@@ -32,15 +32,17 @@ __device__ inline double wave_max(double v) {
 }
 
 // Sums N values per thread over a block of NT threads; thread 0 writes the N
-// block totals to out[0..N).  lds must hold (NT/64) * N doubles.
-template <int N, int NT>
+// block totals to out[0..N).  lds must hold (NT/64) * N doubles.  Slots set
+// in ZERO (bit q for slot q) are known to be zero in every thread: they are
+// stored as zero without the wave reduction.
+template <int N, int NT, uint32_t ZERO = 0u>
 __device__ inline void block_sum_store(double (&acc)[N], double* out, double* lds) {
   constexpr int W = NT / kWave;
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   const int wave = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int q = 0; q < N; ++q) {
-    double v = wave_sum(acc[q]);
+    const double v = (ZERO >> q) & 1u ? 0.0 : wave_sum(acc[q]);
     if (lane == 0) lds[wave * N + q] = v;
   }
   __syncthreads();
@@ -103,16 +105,27 @@ __device__ inline void reduce_partials(const double* partials, int nblocks, int 
 
 // Thread 0 of the last block: turns the reduced sums of T consecutive steps
 // (tot[s * kAcc + q]) into trace records and updates the run state and the
-// stop decision (trace may be NULL: no per-step records kept).  Works on a
-// register copy of the state (one bulk load and one bulk store) to keep the
-// serial tail of the launch short.
+// stop decision (trace may be NULL: no per-step records kept).  Works on
+// register copies of the fields it updates (a whole-struct copy would pass
+// the untouched fields through private memory).
 __device__ inline void finalize_steps(RunState* gst, double* trace, const double* tot, int T,
                                       int64_t step0, const Coef& cp, const Coef& cn, double dV,
                                       double stop_tol, int64_t min_stop_step) {
-  RunState st = *gst;
-  st.passes += 1;
-  for (int s = 0; s < T; ++s) {
-    if (st.done) break;
+  const double released = gst->released, released_neg = gst->released_neg;
+  double pending = gst->released_pending, pending_neg = gst->released_pending_neg;
+  double sums[5], last[4], screened[2], escaped[2];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sums[q] = gst->sums[q];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    screened[q] = gst->screened[q];
+    escaped[q] = gst->escaped[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) last[q] = gst->last[q];
+  int64_t steps = gst->steps;
+  int done = gst->done, flags = gst->flags;
+  for (int s = 0; s < T && !done; ++s) {
     const int64_t l = step0 + s;
     const double* a = tot + s * kAcc;
     double rec[IT_TRACE_COLS];
@@ -125,33 +138,51 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
     rec[6] = a[6] * dV;
     rec[7] = a[7] * dV;
     rec[8] = a[8] * dV;
-    rec[9] = st.released_pending;
+    rec[9] = pending;
     rec[10] = a[9] * dV;
     rec[11] = a[10] * dV;
-    rec[12] = st.released_pending_neg;
-    st.released_pending = 0.0;
-    st.released_pending_neg = 0.0;
+    rec[12] = pending_neg;
+    rec[13] = a[11] * dV;
+    rec[14] = a[12] * dV;
+    pending = 0.0;
+    pending_neg = 0.0;
     bool finite = true;
+#pragma unroll
     for (int q = 0; q < IT_TRACE_COLS; ++q) {
       if (trace) trace[l * IT_TRACE_COLS + q] = rec[q];
       finite = finite && isfinite(rec[q]);
     }
-    for (int q = 0; q < 5; ++q) st.sums[q] += rec[q];
-    for (int q = 0; q < 4; ++q) st.last[q] = rec[5 + q];
-    st.screened[0] += rec[10];
-    st.screened[1] += rec[11];
-    st.steps = l + 1;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sums[q] += rec[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) last[q] = rec[5 + q];
+    screened[0] += rec[10];
+    screened[1] += rec[11];
+    escaped[0] += rec[13];
+    escaped[1] += rec[14];
+    steps = l + 1;
     if (!finite) {
-      st.flags |= IT_FLAG_NONFINITE;
-      st.done = 1;
-      break;
-    }
-    if (l >= min_stop_step && rec[7] <= stop_tol * st.released && rec[8] <= stop_tol * st.released_neg) {
-      st.done = 1;
-      break;
+      flags |= IT_FLAG_NONFINITE;
+      done = 1;
+    } else if (l >= min_stop_step && rec[7] <= stop_tol * released && rec[8] <= stop_tol * released_neg) {
+      done = 1;
     }
   }
-  *gst = st;
+  gst->released_pending = pending;
+  gst->released_pending_neg = pending_neg;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) gst->sums[q] = sums[q];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    gst->screened[q] = screened[q];
+    gst->escaped[q] = escaped[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) gst->last[q] = last[q];
+  gst->steps = steps;
+  gst->done = done;
+  gst->flags = flags;
+  gst->passes += 1;
 }
 
 // Tile coordinates: column tile (tx, ty) and z chunk.

@@ -30,6 +30,7 @@ int check_chamber(const it_chamber* ch) {
   if (!ch) return IT_EINVAL;
   if (ch->nx < 1 || ch->ny < 1 || ch->nz < 2) return IT_EINVAL;
   if (ch->space_charge != 0 && ch->space_charge != 1) return IT_EINVAL;
+  if (ch->lateral_bc != 0 && ch->lateral_bc != 1) return IT_EINVAL;
   const double cells = (double)ch->nx * ch->ny * (double)(ch->nz + 1);
   if (cells > 4.0e9) return IT_EINVAL;  // 32-bit tile indices and 64-bit offsets suffice below
   if ((double)ch->nx * ch->ny > (double)(1 << 28)) return IT_EINVAL;  // in-plane byte offsets fit 32 bits
@@ -88,8 +89,9 @@ double reference_density(const it_chamber* ch, const it_track* tr, int64_t n) {
       const double ux = std::sin(t.theta) * std::cos(t.phi);
       const double uy = std::sin(t.theta) * std::sin(t.phi);
       const double uz = std::cos(t.theta);
-      const double wx = wrap_near_host(tr[a].x_cm - t.x_cm, Lx);
-      const double wy = wrap_near_host(tr[a].y_cm - t.y_cm, Ly);
+      const double dx = tr[a].x_cm - t.x_cm, dy = tr[a].y_cm - t.y_cm;
+      const double wx = ch->lateral_bc ? dx : wrap_near_host(dx, Lx);
+      const double wy = ch->lateral_bc ? dy : wrap_near_host(dy, Ly);
       const double wz = 0.0;
       const double cx = wy * uz - wz * uy, cy = wz * ux - wx * uz, cz = wx * uy - wy * ux;
       const double r2 = cx * cx + cy * cy + cz * cz;
@@ -228,6 +230,23 @@ int exec_z_chunk(const it_exec* ex) { return ex ? ex->z_chunk : 0; }
 bool z_chunk_ok(const it_exec* ex) {
   const int z = exec_z_chunk(ex);
   return z == 0 || (z >= kMinZChunk && z <= kMaxZChunk);
+}
+
+// Steps per launch of an execution choice (1: the one-step kernel).
+int exec_steps_per_pass(const it_exec* ex) {
+  if (ex && ex->kernel == IT_KERNEL_PLAIN) return 1;
+  return ex && ex->steps_per_pass > 0 ? ex->steps_per_pass : kDefaultT;
+}
+
+// Host check of an execution choice for a chamber, made before any device
+// work.
+int check_exec(const it_chamber* ch, const it_exec* ex) {
+  const int T = exec_steps_per_pass(ex);
+  if (T < 1 || T > kMaxT) return IT_EINVAL;
+  if (T > 1 && !blocked_supported(T, ex ? ex->tile_y : 0)) return IT_ENOTSUP;
+  if (T > 1 && ch->lateral_bc) return IT_ENOTSUP;  // the blocked kernel is periodic only
+  if (!z_chunk_ok(ex)) return IT_EINVAL;
+  return IT_OK;
 }
 
 Tiling deposit_tiling(int nx, int ny, int nz) {
@@ -384,6 +403,7 @@ DepositParams base_deposit(const it_chamber* ch, double dt, const Tiling& td) {
   dp.half_gap = 0.5 * ch->gap;
   dp.Lx = ch->nx * ch->dx;
   dp.Ly = ch->ny * ch->dy;
+  dp.absorbing = ch->lateral_bc;
   dp.dV = ch->dx * ch->dy * dz;
   dp.beta = ch->alpha * dt;
   return dp;
@@ -403,12 +423,10 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
              const std::vector<Event>& events, const std::vector<DepTrack>& dev_tracks, int same_r,
              int64_t nsteps, int64_t min_stop_step, double stop_tol, hipStream_t stream,
              RunState* final_state, int* passes_issued) {
-  const int kernel = ex ? ex->kernel : IT_KERNEL_AUTO;
-  int T = ex && ex->steps_per_pass > 0 ? ex->steps_per_pass : kDefaultT;
+  const int exec_rc = check_exec(ch, ex);
+  if (exec_rc) return exec_rc;
+  const int T = exec_steps_per_pass(ex);
   const int tile_y = ex ? ex->tile_y : 0;
-  if (kernel == IT_KERNEL_PLAIN) T = 1;
-  if (T < 1 || T > kMaxT) return IT_EINVAL;
-  if (T > 1 && !blocked_supported(T, tile_y)) return IT_ENOTSUP;
   int64_t check_every = ex && ex->check_every > 0 ? ex->check_every : 64;
   const int n_timing = ex && ex->timing_events ? std::max(ex->n_timing_events, 0) / 2 : 0;
 
@@ -424,7 +442,6 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const Coef cp = species_coef(ch, dt, 0), cn = species_coef(ch, dt, 1);
   const double dz = ch->gap / ch->nz;
   const double dV = ch->dx * ch->dy * dz;
-  if (!z_chunk_ok(ex)) return IT_EINVAL;
   const int rows = resolve_rows(tile_y, ch->ny);
   const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, rows, exec_z_chunk(ex));
   const Tiling td = deposit_tiling(ch->nx, ch->ny, ch->nz);
@@ -441,6 +458,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   sp.beta = ch->alpha * dt;
   sp.gsp = screening_coef(ch, dt, 0);
   sp.gsn = screening_coef(ch, dt, 1);
+  sp.absorbing = ch->lateral_bc;
   sp.dV = dV;
   sp.stop_tol = stop_tol;
   sp.min_stop_step = min_stop_step;
@@ -722,6 +740,8 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   out->max_beta_n = fin.max_beta_n;
   out->n_space_charge_pos = fin.screened[0];
   out->n_space_charge_neg = fin.screened[1];
+  out->n_escaped_pos = fin.escaped[0];
+  out->n_escaped_neg = fin.escaped[1];
   out->steps = fin.steps;
   out->flags = flags;
   out->passes = issued;
@@ -838,11 +858,13 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
   int rc = it_validate(ch, tracks, ntracks);
   if (rc) return rc;
   const bool fe = ch->mu_e > 0.0;
-  if (fe) {  // free electrons: one instantaneous pulse, no space charge
-    if (ch->space_charge) return IT_ENOTSUP;
+  if (fe) {  // free electrons: one instantaneous pulse, no space charge, periodic cell
+    if (ch->space_charge || ch->lateral_bc) return IT_ENOTSUP;
     for (int64_t q = 0; q < ntracks; ++q)
       if (tracks[q].t_s != 0.0) return IT_ENOTSUP;
   }
+  rc = check_exec(ch, exec);
+  if (rc) return rc;
   const Layout L = make_layout(ch, ntracks);
   if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
   double dt;
@@ -989,7 +1011,11 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   if (rc) return rc;
   const int rows = batch_rows(ch, ninst, exec);
   bool any_sc = false;
-  for (int q = 0; q < ninst; ++q) any_sc = any_sc || ch[q].space_charge != 0;
+  bool any_ab = false;
+  for (int q = 0; q < ninst; ++q) {
+    any_sc = any_sc || ch[q].space_charge != 0;
+    any_ab = any_ab || ch[q].lateral_bc != 0;
+  }
   int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
   if (!z_chunk_ok(exec)) return IT_EINVAL;
@@ -1050,6 +1076,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       sp.beta = c->alpha * dts[q];
       sp.gsp = screening_coef(c, dts[q], 0);
       sp.gsn = screening_coef(c, dts[q], 1);
+      sp.absorbing = c->lateral_bc;
       sp.dV = dV;
       sp.stop_tol = c->stop_tol;
       sp.step0 = 0;
@@ -1120,7 +1147,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
     hipError_t ce = hipSuccess;
     for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, any_sc, (parity0 + k) & 1, cs);
+      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, any_sc, any_ab, (parity0 + k) & 1,
+                             cs);
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
     if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;
@@ -1185,6 +1213,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* exec, double* d_pos,
                double* d_neg, void* d_workspace, size_t ws_bytes, void* stream_, double* h_trace) {
   int rc = check_chamber(ch);
+  if (rc) return rc;
+  rc = check_exec(ch, exec);
   if (rc) return rc;
   if (!d_pos || !d_neg || nsteps < 0 || nsteps > ch->max_steps) return IT_EINVAL;
   if (!(std::isfinite(dt) && dt > 0)) return IT_EINVAL;

@@ -30,8 +30,9 @@ struct PlaneRegs {
 // LDS holds plane k of the tile with a one-node rim: interior (r, x) sits at
 // [r + 1][x + 1]; the rim column/row that follows the last valid column/row
 // (w, h of the tile, smaller than 64/SY on the ragged edge of the grid)
-// holds the periodic neighbour, so every active node reads its four lateral
-// neighbours from LDS at fixed offsets.  Waves 0-3 load the rim from global
+// holds the periodic neighbour (or zero beyond an absorbing lateral
+// boundary), so every active node reads its four lateral neighbours from LDS
+// at fixed offsets.  Waves 0-3 load the rim from global
 // memory (wave-uniform branches), all other loads are unconditional.
 //
 // Pipelining: plane k+2 of the own column and the rim of plane k+1 are
@@ -42,8 +43,10 @@ struct PlaneRegs {
 // passed the barrier of plane k+1 and hence finished reading plane k.  The
 // barrier orders LDS only; it does not wait for the global loads in flight.
 // SC: with the space-charge term (its two extra tallies cost registers, so
-// runs without it use the instance without them).
-template <int SY, bool SC>
+// runs without it use the instance without them).  AB: honours
+// p.absorbing (absorbing lateral boundaries and the escaped tally, slots
+// 11-12); the instance without it is periodic only.
+template <int SY, bool SC, bool AB>
 __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, double* partial_out) {
   constexpr int kSNT = kTX * SY;
   __shared__ double sp[2][SY + 2][kTX + 2], sn[2][SY + 2][kTX + 2];
@@ -51,7 +54,7 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   // per-wave sums of n on the planes next to the electrodes (slots 1-4)
   __shared__ double edge[SY][4];
 
-  // running sums of slots 0 and 5-10 (slots 1-4 go through `edge`)
+  // running sums of slots 0 and 5-12 (slots 1-4 go through `edge`)
   double acc[kAcc];
 #pragma unroll
   for (int q = 0; q < kAcc; ++q) acc[q] = 0.0;
@@ -85,6 +88,19 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   if (ty == 2 && lane < h) { rim_off = (unsigned)((y0 + lane) * p.nx + i_left) * 8u; rim_r = lane + 1; rim_c = 0; }
   if (ty == 3 && lane < h) { rim_off = (unsigned)((y0 + lane) * p.nx + i_right) * 8u; rim_r = lane + 1; rim_c = w + 1; }
   const bool rim = t.valid && rim_r >= 0;
+  // absorbing lateral boundaries: a rim node beyond the cell is zero (never
+  // loaded; its registers stay 0), and each node next to the boundary loses
+  // ax (or ay) times its density per missing neighbour
+  const bool absorbing = AB && p.absorbing;
+  bool rim_outside = false;
+  double esc_p = 0.0, esc_n = 0.0;  // weights of the escaped tally
+  if (absorbing) {
+    rim_outside = (ty == 0 && y0 == 0) || (ty == 1 && y0 + h == p.ny) || (ty == 2 && x0 == 0) ||
+                  (ty == 3 && x0 + w == p.nx);
+    const double mx = (double)((i == 0) + (i == p.nx - 1)), my = (double)((j == 0) + (j == p.ny - 1));
+    esc_p = p.cp.ax * mx + p.cp.ay * my;
+    esc_n = p.cn.ax * mx + p.cn.ay * my;
+  }
 
   // plane pointers are block-uniform (scalar registers); threads add their
   // 32-bit in-plane byte offset
@@ -101,9 +117,11 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
     const int k2 = min(k + 2, nz);  // plane nz exists (the cathode, zero)
     q2.p = ld(in_p(k2), own);
     q2.n = ld(in_n(k2), own);
-    if (rim) {
-      rn.p = ld(in_p(k + 1), rim_off);
-      rn.n = ld(in_n(k + 1), rim_off);
+    if (rim) {  // one branch: the periodic instance keeps its loads and LDS stores together
+      if (!rim_outside) {
+        rn.p = ld(in_p(k + 1), rim_off);
+        rn.n = ld(in_n(k + 1), rim_off);
+      }
       sp[buf][rim_r][rim_c] = rc.p;
       sn[buf][rim_r][rim_c] = rc.n;
     }
@@ -141,6 +159,10 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
       acc[9] += active ? scp : 0.0;
       acc[10] += active ? scn : 0.0;
     }
+    if (AB) {
+      acc[11] += active ? esc_p * c.p : 0.0;
+      acc[12] += active ? esc_n * c.n : 0.0;
+    }
     if (k == 1 || k == nz - 1) {  // uniform over the block
       const double sp_ = wave_sum(active ? c.p : 0.0), sn_ = wave_sum(active ? c.n : 0.0);
       if (lane == 0) {
@@ -161,7 +183,7 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   // load may still be in flight.
   PlaneRegs r0, r1, r2, r3, ra, rb;
   ra.p = ra.n = rb.p = rb.n = 0.0;
-  if (rim) {
+  if (rim && !rim_outside) {
     ra.p = ld(in_p(k0), rim_off);
     ra.n = ld(in_n(k0), rim_off);
   }
@@ -188,7 +210,10 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
     acc[3] = edge[ty][2];
     acc[4] = edge[ty][3];
   }
-  block_sum_store<kAcc, kSNT>(acc, partial_out, lds);
+  // slots 9-10 (space charge) and 11-12 (escaped) are zero in instances
+  // without those terms
+  constexpr uint32_t kZero = (SC ? 0u : 3u << 9) | (AB ? 0u : 3u << 11);
+  block_sum_store<kAcc, kSNT, kZero>(acc, partial_out, lds);
 }
 
 }  // namespace it

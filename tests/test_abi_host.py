@@ -109,6 +109,40 @@ def test_launch_shape_checks(lib):
     assert e.value.code == lib.IT_EINVAL
 
 
+def _solve_status(lib, ch, tr, ex):
+    """it_solve's status for a call that must be refused before any device
+    work (no workspace, no stream)."""
+    B = lib.binding
+    c = B._chamber(ch)
+    rows, ptr = B._tracks(tr)
+    res = B.it_result()
+    return B.lib().it_solve(ctypes.byref(c), ptr, rows.shape[0], B._exec(ex), None, 0, None, None, None, None,
+                            ctypes.byref(res))
+
+
+def test_lateral_boundary_option_checks(lib, orc):
+    ch, tr = W.single_track()
+    lib.it_validate(dict(ch, lateral_bc=1), tr)
+    for bad in (2, -1):
+        with pytest.raises(lib.ItError) as e:
+            lib.it_validate(dict(ch, lateral_bc=bad), tr)
+        assert e.value.code == lib.IT_EINVAL
+    ab = dict(ch, lateral_bc=1)
+    # absorbing boundaries: the one-step kernel only, no free electrons
+    assert _solve_status(lib, ab, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_ENOTSUP
+    assert _solve_status(lib, dict(ab, mu_e=1000.0, D_e=25.0), tr, None) == lib.IT_ENOTSUP
+    assert _solve_status(lib, ab, tr, dict(kernel=1)) == lib.IT_EWORKSPACE  # accepted up to the workspace
+    assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_EWORKSPACE
+    # the recombination bound sums the tracks' profiles without periodic
+    # images: two dense tracks at opposite x edges overlap only through the wrap
+    ch2 = W.chamber(40, 40, 10, 2e-4, 10 * 2e-4, 20.0)
+    tr2 = W.tracks([[200.0, 6e-4, 1e-4, 4e-3, 0.0, 0.0, 0.0], [200.0, 6e-4, 40 * 2e-4 - 1e-4, 4e-3, 0.0, 0.0, 0.0]])
+    for bc in (0, 1):
+        c = dict(ch2, lateral_bc=bc)
+        assert lib.it_dt(c, tr2) == pytest.approx(orc.dt(c, tr2), rel=1e-14)
+    assert lib.it_dt(dict(ch2, lateral_bc=1), tr2) > lib.it_dt(ch2, tr2) * 1.01
+
+
 def test_strerror_names_codes(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.it_strerror(code) and lib.it_strerror(code) != "unknown status code"

@@ -109,3 +109,21 @@ def test_batch_rejects_later_tracks(gpu):
     with pytest.raises(gpu.ItError) as e:
         gpu.it_solve_batch(chs, trs)
     assert e.value.code == gpu.IT_ENOTSUP
+
+
+def test_batch_with_absorbing_boundaries_on_some_instances(gpu, orc):
+    """Absorbing and periodic lateral boundaries in one batch; tracks placed
+    near the edges so that charge escapes."""
+    chs, trs = small_sweep(n=5, seed=21)
+    for q in (0, 2, 3):
+        chs[q]["lateral_bc"] = 1
+        trs[q][:, 2] = np.minimum(trs[q][:, 2], 6e-4)  # next to the x = 0 edge
+    res = gpu.it_solve_batch(chs, trs, exec=dict(check_every=4))
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        assert g["steps"] == o["steps"] and g["flags"] == o["flags"]
+        assert g["f"] == pytest.approx(o["f"], rel=1e-9)
+        N = max(o["n_released"], 1.0)
+        for k in ("n_recombined", "col_pos_anode", "col_neg_cathode", "n_escaped_pos", "n_escaped_neg"):
+            assert abs(g[k] - o[k]) <= 1e-9 * N, k
+        assert (o["n_escaped_pos"] > 0.0) == bool(ch["lateral_bc"])  # every instance releases charge

@@ -39,7 +39,7 @@ def compare_results(g, o, rtol=RTOL):
     assert g["f"] == pytest.approx(o["f"], rel=rtol, abs=1e-300)
     assert g["n_released"] == pytest.approx(o["n_released"], rel=rtol, abs=1e-300)
     for k in ("n_recombined", "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode",
-              "n_inflight_pos", "n_inflight_neg"):
+              "n_inflight_pos", "n_inflight_neg", "n_escaped_pos", "n_escaped_neg"):
         assert abs(g[k] - o[k]) <= rtol * N, (k, g[k], o[k])
     assert g["dt"] == pytest.approx(o["dt"], rel=1e-14)
 
@@ -302,6 +302,63 @@ def test_advance_from_given_fields(gpu, orc, ex):
     compare_fields(gp, op)
     compare_fields(gn, on)
     compare_trace(gtr[:, :9], otr[:, :9], np.abs(p0).sum() * ch["dx"] * ch["dy"] * ch["gap"] / 21)
+
+
+# absorbing lateral boundaries: the one-step kernel (both tile shapes, short
+# z chunks); tracks next to the edges and corners so that charge escapes
+AB_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5)]
+AB_IDS = ["plain8", "plain16", "plain8z5"]
+
+
+@pytest.mark.parametrize("ex", AB_EXECS, ids=AB_IDS)
+def test_absorbing_ragged_case(gpu, orc, ex):
+    ch, tr = ragged_case()
+    ch["lateral_bc"] = 1
+    tr[0, 2], tr[0, 3] = 2e-4, 1e-4          # parallel track at the corner
+    tr[1, 2] = 70 * 3e-4 - 3e-4              # tilted track at the x = nx-1 edge
+    g, o = run_both(gpu, orc, ch, tr, exec=ex)
+    assert o["flags"] == 0 and o["n_escaped_pos"] > 1e-3 * o["n_released"]
+    compare_fields(g["pos"], o["pos"])
+    compare_fields(g["neg"], o["neg"])
+
+
+@pytest.mark.parametrize("ex", AB_EXECS, ids=AB_IDS)
+def test_absorbing_advance_from_given_fields(gpu, orc, ex):
+    import torch
+    ch = W.chamber(67, 9, 21, 3e-4, 21 * 2e-4, 20.0, dy=4e-4, lateral_bc=1)
+    dt = orc.dt(ch)
+    p0, n0 = W.perturbed_field((22, 9, 67), seed=13, scale=1e11)
+    op, on, otr = orc.advance(ch, dt, p0, n0, 9, with_trace=True)
+    gp = torch.tensor(p0, device="cuda")
+    gn = torch.tensor(n0, device="cuda")
+    gtr = gpu.it_advance(ch, dt, gp, gn, 9, exec=ex, trace=True)
+    compare_fields(gp, op)
+    compare_fields(gn, on)
+    N = np.abs(p0).sum() * ch["dx"] * ch["dy"] * ch["gap"] / 21
+    cols = list(range(9)) + [13, 14]
+    compare_trace(gtr[:, cols], otr[:, cols], N)
+    assert np.all(otr[:, 13] > 0)
+
+
+@pytest.mark.parametrize("geom", [(1, 1, 40), (1, 7, 12), (5, 1, 12)])
+def test_absorbing_one_node_wide_cells(gpu, orc, geom):
+    """Cells one node wide in x and/or y: each node misses both neighbours
+    of that direction."""
+    nx, ny, nz = geom
+    ch = W.chamber(nx, ny, nz, 3e-4, nz * 3e-4, 10.0, uniform_n0=3e9, lateral_bc=1)
+    g, o = run_both(gpu, orc, ch, W.no_tracks())
+    assert o["n_escaped_pos"] > 0.01 * o["n_released"]
+
+
+def test_absorbing_far_from_edges_matches_periodic_run(gpu, orc):
+    ch, tr = W.single_track()
+    ch_a = dict(ch, lateral_bc=1, max_steps=40)
+    g_a = gpu.it_solve(ch_a, tr, trace=True)
+    g_p = gpu.it_solve(dict(ch_a, lateral_bc=0), tr, trace=True)
+    N = g_p["n_released"]
+    assert g_a["steps"] == g_p["steps"] == 40
+    assert np.max(np.abs(g_a["trace"][:, :13] - g_p["trace"][:, :13])) <= 1e-12 * N
+    assert np.max(np.abs(g_a["trace"][:, 13:])) <= 1e-12 * N
 
 
 def test_error_paths(gpu):
