@@ -50,7 +50,8 @@ def parse():
                          "(uniform dose, electron phase then ions) on the workload grid")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 96-chamber sweep")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
-    ap.add_argument("--surrogate-train", type=int, default=8192)
+    ap.add_argument("--surrogate-train", type=int, default=32768, help="surrogate training samples")
+    ap.add_argument("--surrogate-steps", type=int, default=300000, help="surrogate training steps")
     ap.add_argument("--continuous-ms", type=float, default=0.4,
                     help="beam-on time of the continuous-beam run (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -134,6 +135,11 @@ def continuous_run(it, W, beam_s):
             "current_trace_points": int(len(cur))}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -193,6 +199,7 @@ def main():
     voxel_steps = sum(r["steps"] for r in results) * nint
     r0 = results[0]
     value = voxel_steps / elapsed
+    progress(f"pulsed beam: {a.steps} timed runs of {r0['steps']} steps, {elapsed / a.steps * 1e3:.1f} ms each")
 
     # Stepping kernel alone: K launches minus 1 launch of it_advance on the
     # same grid, bracketed by HIP events on the stream the kernel runs on.
@@ -231,6 +238,7 @@ def main():
     workload_name = "pulsed_256x256x200"
     shape = f"tile_y {16 if a.tile_y == 16 else 8} z_chunk {a.z_chunk}" if T_pass == 1 else f"T {T_pass}"
     traffic = read_traffic(kname, workload_name, kernel_source_hash(src), shape)
+    progress(f"{kname}: {per_launch * 1e6:.1f} us per launch")
 
     cpu = None
     if not a.no_cpu:
@@ -242,6 +250,7 @@ def main():
                "sample": f"single-threaded C oracle: deposit of 16 of the 400 tracks "
                          f"({t_dep * 16:.1f} s) and 40 steps of the full 256x256x200 grid "
                          f"({t_step * 40:.1f} s), scaled to one whole run of {steps_full} steps"}
+        progress("cpu baseline done")
 
     sweep = None
     if not a.no_sweep:
@@ -258,15 +267,17 @@ def main():
                  "seconds": sec, "voxel_steps": vs, "voxel_steps_per_s": vs / sec,
                  "ks_evals_per_s": len(chs) / sec, "max_steps": max(r["steps"] for r in res),
                  "flags": sorted({r["flags"] for r in res})}
+        progress(f"sweep: {sec:.1f} s")
 
     cont = None
     if a.continuous_ms > 0:
         cont = continuous_run(it, W, a.continuous_ms * 1e-3)
+        progress(f"continuous beam: {cont['seconds']:.1f} s")
 
     sur = None
     if not a.no_surrogate:
         from paper_1610_06749_amd import surrogate
-        sur = surrogate.evaluate(n_train=a.surrogate_train)
+        sur = surrogate.evaluate(n_train=a.surrogate_train, steps=a.surrogate_steps, log=progress)
 
     out = {
         "metric": METRIC,

@@ -268,11 +268,15 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
  * w4[128], b4.  Inputs per query: the six physical quantities (LET [keV/um],
  * b [cm], V [V], gap [cm], dose per pulse [mGy], pulse rate [Hz]), all > 0,
  * standardised on the device as z = (log x - mu)/sigma.  FP32 master
- * weights; the forward pass uses their BF16 copies (round to nearest even),
- * MFMA with FP32 accumulation for the 128x128 layers, and BF16 hidden
- * activations.  The network predicts (ln k_s - t_mu)/t_sigma.
+ * weights.  Two forward precisions, fixed when the model is initialised:
+ * IT_MLP_BF16 uses BF16 copies of the weights (round to nearest even), MFMA
+ * with FP32 accumulation for the 128x128 layers and BF16 hidden activations;
+ * IT_MLP_FP32 uses the FP32 weights and activations throughout (FP32 MFMA).
+ * The network predicts (ln k_s - t_mu)/t_sigma.
  * ------------------------------------------------------------------------ */
 #define IT_MLP_PARAMS 34049
+#define IT_MLP_BF16 0
+#define IT_MLP_FP32 1
 
 /* Device bytes of a model buffer for `members` members (1..64).  Host only. */
 int it_mlp_model_bytes(int32_t members, size_t* bytes);
@@ -284,10 +288,12 @@ int it_mlp_model_bytes(int32_t members, size_t* bytes);
  * averaged mu, alpha, W [eV], mu+ + mu-, ion pairs per cm^3 and mGy: then the
  * network predicts the residual of ln k_s over the analytic baseline
  * -ln f_Jaffe - ln f_Boag (eq. Jaffe_noangle for one track parallel to the
- * field; ln(1+u)/u for the dose), which the query adds back.  Clears the
- * optimiser state.  Synchronises `stream`.  Errors: IT_EINVAL, IT_EHIP. */
+ * field; ln(1+u)/u for the dose), which the query adds back.  precision:
+ * IT_MLP_BF16 or IT_MLP_FP32 (the forward arithmetic of training and
+ * queries).  Clears the optimiser state.  Synchronises `stream`.  Errors:
+ * IT_EINVAL, IT_EHIP. */
 int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm,
-                const double* h_phys, void* stream);
+                const double* h_phys, int32_t precision, void* stream);
 
 /* The analytic baseline of the model (device d_X [n][6] -> d_out [n],
  * FP64), for checking.  Asynchronous on `stream`. */
@@ -299,7 +305,8 @@ int it_mlp_train_ws_bytes(int32_t members, int64_t n, size_t* bytes);
 /* Full-batch gradient of the mean squared error of every member on
  * (d_X [n][6], d_t [n] = ln k_s targets), device buffers; d_grad device
  * [members][IT_MLP_PARAMS]; h_loss NULL or host [members] (loss before any
- * update).  The BF16 casts pass gradients straight through.  Synchronises.
+ * update).  With IT_MLP_BF16 the casts pass gradients straight through.
+ * Synchronises.
  * Errors: IT_EINVAL, IT_EWORKSPACE, IT_EHIP. */
 int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n,
                 float* d_grad, float* h_loss, void* d_workspace, size_t ws_bytes, void* stream);

@@ -9,6 +9,6 @@ from .binding import (IT_EHIP, IT_EINVAL, IT_ENODT, IT_ENOTSUP, IT_EWORKSPACE, I
                       IT_FLAG_MAX_STEPS, IT_FLAG_NONFINITE, IT_FLAG_REACTION, IT_KERNEL_AUTO,
                       IT_KERNEL_BLOCKED, IT_KERNEL_PLAIN, IT_OK, IT_TRACE_COLS, TRACE_KEYS, ItError,
                       it_advance, it_dt, it_solve, it_solve_batch, it_strerror, it_validate, it_workspace_size,
-                      it_workspace_size_batch, lib, IT_MLP_PARAMS, it_mlp_model_bytes, it_mlp_init,
+                      it_workspace_size_batch, lib, IT_MLP_PARAMS, IT_MLP_BF16, IT_MLP_FP32, it_mlp_model_bytes, it_mlp_init,
                       it_mlp_grad, it_mlp_train, it_mlp_query, it_mlp_baseline,
                       workspace, KernelTimer)

@@ -89,7 +89,7 @@ def lib():
                                      vp, vp]
         szp = ctypes.POINTER(ctypes.c_size_t)
         L.it_mlp_model_bytes.argtypes = [ctypes.c_int32, szp]
-        L.it_mlp_init.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
+        L.it_mlp_init.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp]
         L.it_mlp_baseline.argtypes = [vp, vp, i64, vp, vp]
         L.it_mlp_train_ws_bytes.argtypes = [ctypes.c_int32, i64, szp]
         L.it_mlp_grad.argtypes = [vp, ctypes.c_int32, vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
@@ -324,6 +324,7 @@ def it_solve_batch(chambers, track_lists, exec=None, ws=None, stream=None) -> li
 # Surrogate network
 # --------------------------------------------------------------------------
 IT_MLP_PARAMS = 34049
+IT_MLP_BF16, IT_MLP_FP32 = 0, 1
 
 
 def _dptr(t):
@@ -336,15 +337,17 @@ def it_mlp_model_bytes(members: int) -> int:
     return out.value
 
 
-def it_mlp_init(model, members, params, norm, phys=None, stream=None):
+def it_mlp_init(model, members, params, norm, phys=None, stream=None, precision=None):
     """model: device uint8 tensor of it_mlp_model_bytes; params float32
     [members, IT_MLP_PARAMS]; norm float32 [26]; phys None or 6 floats (the
-    analytic-baseline constants)."""
+    analytic-baseline constants); precision IT_MLP_BF16 (default) or
+    IT_MLP_FP32."""
     p = np.ascontiguousarray(params, dtype=np.float32).reshape(members, IT_MLP_PARAMS)
     nm = np.ascontiguousarray(norm, dtype=np.float32).reshape(26)
     ph = None if phys is None else np.ascontiguousarray(phys, dtype=np.float64).reshape(6)
+    prec = IT_MLP_BF16 if precision is None else int(precision)
     _check(lib().it_mlp_init(_dptr(model), int(members), p.ctypes.data, nm.ctypes.data,
-                             None if ph is None else ph.ctypes.data, _stream(stream)), "it_mlp_init")
+                             None if ph is None else ph.ctypes.data, prec, _stream(stream)), "it_mlp_init")
 
 
 def it_mlp_baseline(model, X, stream=None):

@@ -1,19 +1,23 @@
 // Surrogate network for ln k_s: an ensemble of MLPs 6 -> 128 -> 128 -> 128 -> 1
 // (SiLU), trained and queried with the kernels below.
 //
-// Numerics: FP32 master weights; BF16 copies (round to nearest even) feed
-// the forward pass.  The two 128x128 layers run on MFMA
-// (v_mfma_f32_16x16x16_bf16: BF16 inputs, FP32 accumulation); the 6-wide
-// input layer and the 128-wide output dot run in FP32.  Hidden activations
-// are rounded to BF16 before entering the next layer.  Inputs are the six
+// Numerics, two precisions chosen per model: FP32 master weights always.
+//  - BF16: BF16 copies of the weights (round to nearest even) feed the
+//    forward pass; the two 128x128 layers run on v_mfma_f32_16x16x16_bf16
+//    (BF16 inputs, FP32 accumulation); hidden activations are rounded to
+//    BF16 before entering the next layer.
+//  - FP32: the master weights and FP32 activations throughout; the 128x128
+//    layers run on v_mfma_f32_16x16x4_f32.
+// In both the 6-wide input layer and the 128-wide output dot run in FP32.  Inputs are the six
 // physical quantities (LET, b, V, gap, dose per pulse, pulse rate),
 // standardised as (log x - mu) / sigma.  Optionally the network learns the
 // residual of ln k_s over an analytic baseline, -ln f_Jaffe - ln f_Boag:
 // Jaffe's collection efficiency of a track parallel to the field (eq.
 // Jaffe_noangle, with the averaged D and mu) times Boag's ln(1+u)/u for the
 // uniform dose; the baseline is evaluated here in FP64.  The output is the
-// standardised residual.  Training: full-batch mean squared error, backward
-// in FP32 with the BF16 casts passed straight through, Adam.
+// standardised residual.  Training: mean squared error over each minibatch,
+// backward in FP32 (with BF16 the casts pass gradients straight through),
+// Adam.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,7 +47,8 @@ struct Header {
   int32_t members, step;
   float mu[kIn], sigma[kIn], lo[kIn], hi[kIn];
   float t_mu, t_sigma;
-  int32_t use_baseline, pad;
+  int32_t use_baseline;
+  int32_t precision;  // IT_MLP_BF16 or IT_MLP_FP32
   // averaged diffusion and mobility, alpha, W [eV], mu+ + mu-, ion pairs
   // per cm^3 and mGy
   double D, mu_avg, alpha, W, mu_sum, pairs_per_mGy;
@@ -153,17 +158,92 @@ __device__ inline float dsilu(float a) {
   return s * (1.0f + a * (1.0f - s));
 }
 
+// Hidden activations as the next layer reads them: BF16 bits or FP32.
+template <bool F32>
+struct ActT {
+  typedef unsigned short type;
+  static __device__ inline type put(float v) { return to_bf16(v); }
+  static __device__ inline float get(type h) { return from_bf16(h); }
+};
+template <>
+struct ActT<true> {
+  typedef float type;
+  static __device__ inline type put(float v) { return v; }
+  static __device__ inline float get(type h) { return h; }
+};
+
+// Weight q of a member as the forward pass uses it.
+template <bool F32>
+__device__ inline float weight(const float* __restrict__ master, const unsigned short* __restrict__ w, int q) {
+  return F32 ? master[q] : from_bf16(w[q]);
+}
+
 struct ForwardOut {  // optional stores of the training forward (member slices)
   float *z, *a1, *a2, *a3, *h1, *h2, *h3, *y;
 };
 
+// Layers 2 and 3 in FP32 (v_mfma_f32_16x16x4_f32, A[i][k]: lane i + 16 k,
+// B[k][j]: lane j + 16 k, D[i][j]: lane j + 16 (i/4), item i % 4).  Wave w
+// owns samples 16w..16w+15; each pass computes four 16-wide output tiles,
+// sharing the activation operand, with the 128 inputs taken 4 at a time in
+// increasing order.  act[0] holds h1 on entry and h3 on return.
+template <bool STORE>
+__device__ void mlp_layers_f32(const float* __restrict__ master, float (*act)[kTileS][kActStride], int64_t n,
+                               int64_t s0, const ForwardOut& st) {
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int arow = wave * 16 + (lane & 15);  // A: sample row of this lane
+  const int kq = lane >> 4;                  // A/B: k within the 4-wide step
+  constexpr int kNT = 4;                     // output tiles per pass
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int oW = layer == 0 ? oW2 : oW3, ob = layer == 0 ? ob2 : ob3;
+    const float (*in)[kActStride] = act[layer];
+    float (*out)[kActStride] = act[1 - layer];
+    float* sa = layer == 0 ? st.a2 : st.a3;
+    float* sh = layer == 0 ? st.h2 : st.h3;
+#pragma unroll 1
+    for (int nt0 = 0; nt0 < kH / 16; nt0 += kNT) {
+      float4_t acc[kNT];
+#pragma unroll
+      for (int u = 0; u < kNT; ++u) acc[u] = {0.0f, 0.0f, 0.0f, 0.0f};
+      const float* wr = master + oW + (nt0 * 16 + (lane & 15)) * kH + kq;  // B: row of output column
+#pragma unroll 8
+      for (int kk = 0; kk < kH / 4; ++kk) {
+        const float a = in[arow][4 * kk + kq];
+#pragma unroll
+        for (int u = 0; u < kNT; ++u)
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wr[u * 16 * kH + 4 * kk], acc[u], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < kNT; ++u) {
+        const int bo = (nt0 + u) * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int s = wave * 16 + 4 * (lane >> 4) + v;
+          const float a = acc[u][v] + master[ob + bo];
+          const float h = silu(a);
+          out[s][bo] = h;
+          const int64_t gs = s0 + s;
+          if (STORE && gs < n) {
+            sa[gs * kH + bo] = a;
+            sh[gs * kH + bo] = h;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Forward pass of one member over samples [s0, s0 + 64) (256 threads).
 // Leaves the standardised outputs in ys[64] (LDS).
-template <bool STORE>
+template <bool STORE, bool F32>
 __device__ void forward_tile(const Header& H, const float* __restrict__ master,
                              const unsigned short* __restrict__ w, const float* __restrict__ X, int64_t n,
-                             int64_t s0, float* zs /*[64][6]*/, unsigned short (*act)[kTileS][kActStride],
-                             float* ys, const ForwardOut& st) {
+                             int64_t s0, float* zs /*[64][6]*/,
+                             typename ActT<F32>::type (*act)[kTileS][kActStride], float* ys, const ForwardOut& st) {
+  typedef ActT<F32> A;
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   // standardised inputs
@@ -176,22 +256,25 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
     if (STORE && gs < n) st.z[gs * kIn + i] = zv;
   }
   __syncthreads();
-  // layer 1 (FP32, BF16 weights)
+  // layer 1 (FP32 arithmetic)
   for (int q = tid; q < kTileS * kH; q += 256) {
     const int s = q / kH, o = q % kH;
     float a = master[ob1 + o];
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) a += from_bf16(w[oW1 + o * kIn + i]) * zs[s * kIn + i];
-    const unsigned short h = to_bf16(silu(a));
+    for (int i = 0; i < kIn; ++i) a += weight<F32>(master, w, oW1 + o * kIn + i) * zs[s * kIn + i];
+    const typename A::type h = A::put(silu(a));
     act[0][s][o] = h;
     const int64_t gs = s0 + s;
     if (STORE && gs < n) {
       st.a1[gs * kH + o] = a;
-      st.h1[gs * kH + o] = from_bf16(h);
+      st.h1[gs * kH + o] = A::get(h);
     }
   }
   __syncthreads();
-  // layers 2 and 3 on MFMA: wave w owns samples 16w..16w+15
+  if constexpr (F32) {  // layers 2 and 3 on FP32 MFMA
+    mlp_layers_f32<STORE>(master, act, n, s0, st);
+  } else {
+  // layers 2 and 3 on BF16 MFMA: wave w owns samples 16w..16w+15
 #pragma unroll
   for (int layer = 0; layer < 2; ++layer) {
     const int oW = layer == 0 ? oW2 : oW3, ob = layer == 0 ? ob2 : ob3;
@@ -236,10 +319,11 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
     }
     __syncthreads();
   }
-  // output layer (FP32 dot of BF16 values); act[0] holds h3
+  }
+  // output layer (FP32 dot); act[0] holds h3
   if (tid < kTileS) {
     float y = master[ob4];
-    for (int i = 0; i < kH; ++i) y += from_bf16(w[ow4 + i]) * from_bf16(act[0][tid][i]);
+    for (int i = 0; i < kH; ++i) y += weight<F32>(master, w, ow4 + i) * A::get(act[0][tid][i]);
     ys[tid] = y;
     const int64_t gs = s0 + tid;
     if (STORE && gs < n) st.y[gs] = y;
@@ -247,46 +331,49 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
   __syncthreads();
 }
 
+template <bool F32>
 __global__ __launch_bounds__(256) void forward_train_kernel(Model md, const float* X, int64_t n, TrainWs ws) {
   if (blockIdx.y == 0 && threadIdx.x < kTileS) {  // baseline of each sample (member independent)
     const int64_t gs = (int64_t)blockIdx.x * kTileS + threadIdx.x;
     if (gs < n) ws.base[gs] = md.hdr->use_baseline ? (float)baseline(*md.hdr, X + gs * kIn) : 0.0f;
   }
   __shared__ float zs[kTileS * kIn];
-  __shared__ unsigned short act[2][kTileS][kActStride];
+  __shared__ typename ActT<F32>::type act[2][kTileS][kActStride];
   __shared__ float ys[kTileS];
   const int m = blockIdx.y;
   const size_t nh = (size_t)n * kH;
   ForwardOut st{ws.z + (size_t)m * n * kIn, ws.a1 + m * nh, ws.a2 + m * nh, ws.a3 + m * nh,
                 ws.h1 + m * nh, ws.h2 + m * nh, ws.h3 + m * nh, ws.y + (size_t)m * n};
-  forward_tile<true>(*md.hdr, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n,
+  forward_tile<true, F32>(*md.hdr, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n,
                      (int64_t)blockIdx.x * kTileS, zs, act, ys, st);
 }
 
 // Per-sample deltas: dy = 2 (y - t)/n, then the pre-activation gradients of
 // the three hidden layers (block of 128 threads = hidden units).
+template <bool F32>
 __global__ __launch_bounds__(128) void delta_kernel(Model md, const float* t, int64_t n, TrainWs ws) {
   __shared__ float d[kH];
   const int m = blockIdx.y, o = threadIdx.x;
   const int64_t s = blockIdx.x;
   const size_t nh = (size_t)n * kH, row = m * nh + (size_t)s * kH;
   const unsigned short* w = md.w + (size_t)m * kPpad;
+  const float* master = md.master + (size_t)m * kP;
   const float ty = (t[s] - ws.base[s] - md.hdr->t_mu) / md.hdr->t_sigma;
   const float dy = 2.0f * (ws.y[(size_t)m * n + s] - ty) / (float)n;
   if (o == 0) ws.dy[(size_t)m * n + s] = dy;
-  float da = dy * from_bf16(w[ow4 + o]) * dsilu(ws.a3[row + o]);
+  float da = dy * weight<F32>(master, w, ow4 + o) * dsilu(ws.a3[row + o]);
   ws.d3[row + o] = da;
   d[o] = da;
   __syncthreads();
   float g = 0.0f;
-  for (int j = 0; j < kH; ++j) g += from_bf16(w[oW3 + j * kH + o]) * d[j];
+  for (int j = 0; j < kH; ++j) g += weight<F32>(master, w, oW3 + j * kH + o) * d[j];
   da = g * dsilu(ws.a2[row + o]);
   ws.d2[row + o] = da;
   __syncthreads();
   d[o] = da;
   __syncthreads();
   g = 0.0f;
-  for (int j = 0; j < kH; ++j) g += from_bf16(w[oW2 + j * kH + o]) * d[j];
+  for (int j = 0; j < kH; ++j) g += weight<F32>(master, w, oW2 + j * kH + o) * d[j];
   ws.d1[row + o] = g * dsilu(ws.a1[row + o]);
 }
 
@@ -402,11 +489,12 @@ __global__ __launch_bounds__(1024) void loss_kernel(Model md, const float* t, in
 // Ensemble query: mean and spread (max - min) of ln k_s over the members,
 // out-of-box test of the standardised inputs, fallback flag and the number
 // of flagged queries per block.
+template <bool F32>
 __global__ __launch_bounds__(256) void query_kernel(Model md, const float* X, int64_t n, float spread_tol,
                                                     float* mean, float* spread, unsigned char* fallback,
                                                     int* block_count) {
   __shared__ float zs[kTileS * kIn];
-  __shared__ unsigned short act[2][kTileS][kActStride];
+  __shared__ typename ActT<F32>::type act[2][kTileS][kActStride];
   __shared__ float ys[kTileS], ymin[kTileS], ymax[kTileS], ysum[kTileS];
   __shared__ int cnt;
   const Header& H = *md.hdr;
@@ -415,8 +503,8 @@ __global__ __launch_bounds__(256) void query_kernel(Model md, const float* X, in
   if (tid == 0) cnt = 0;
   ForwardOut none{};
   for (int m = 0; m < H.members; ++m) {
-    forward_tile<false>(H, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n, s0, zs, act, ys,
-                        none);
+    forward_tile<false, F32>(H, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n, s0, zs, act, ys,
+                             none);
     if (tid < kTileS) {
       const float v = ys[tid] * H.t_sigma + H.t_mu;
       ysum[tid] = m == 0 ? v : ysum[tid] + v;
@@ -527,13 +615,15 @@ int it_mlp_model_bytes(int32_t members, size_t* bytes) {
 }
 
 int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, const double* h_phys,
-                void* stream_) {
+                int32_t precision, void* stream_) {
   if (!d_model || !h_params || !h_norm || members < 1 || members > 64) return IT_EINVAL;
+  if (precision != IT_MLP_BF16 && precision != IT_MLP_FP32) return IT_EINVAL;
   hipStream_t s = (hipStream_t)stream_;
   Model md = carve_model(d_model, members);
   Header h;
   std::memset(&h, 0, sizeof(h));
   h.members = members;
+  h.precision = precision;
   for (int i = 0; i < kIn; ++i) {
     h.mu[i] = h_norm[i];
     h.sigma[i] = h_norm[kIn + i];
@@ -572,11 +662,16 @@ int it_mlp_train_ws_bytes(int32_t members, int64_t n, size_t* bytes) {
   return IT_OK;
 }
 
-static int launch_grad(const Model& md, int M, const float* X, const float* t, int64_t n, const TrainWs& w,
-                       hipStream_t s) {
+static int launch_grad(const Model& md, int M, bool f32, const float* X, const float* t, int64_t n,
+                       const TrainWs& w, hipStream_t s) {
   const int nb = (int)((n + kTileS - 1) / kTileS);
-  hipLaunchKernelGGL(forward_train_kernel, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
-  hipLaunchKernelGGL(delta_kernel, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
+  if (f32) {
+    hipLaunchKernelGGL(forward_train_kernel<true>, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
+    hipLaunchKernelGGL(delta_kernel<true>, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
+  } else {
+    hipLaunchKernelGGL(forward_train_kernel<false>, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
+    hipLaunchKernelGGL(delta_kernel<false>, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
+  }
   const size_t nh = (size_t)n * kH;
   const GradJob jobs[4] = {
       {w.d3, kH, w.h2, kH, kH, oW3, ob3},
@@ -601,7 +696,11 @@ int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const fl
   hipStream_t s = (hipStream_t)stream_;
   Model md = carve_model((void*)d_model, members);
   TrainWs w = carve_train(d_ws, members, n);
-  int rc = launch_grad(md, members, d_X, d_t, n, w, s);
+  Header h;
+  if (hipMemcpyAsync(&h, md.hdr, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IT_EHIP;
+  int rc = launch_grad(md, members, h.precision == IT_MLP_FP32, d_X, d_t, n, w, s);
   if (rc) return rc;
   if (hipMemcpyAsync(d_grad, w.grad, (size_t)members * kP * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return IT_EHIP;
@@ -633,7 +732,7 @@ int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* 
     const int64_t b0 = ((h.step + k) % nbatch) * rows;
     const float* X = d_X + b0 * kIn;
     const float* t = d_t + b0;
-    int rc = launch_grad(md, members, X, t, rows, w, s);
+    int rc = launch_grad(md, members, h.precision == IT_MLP_FP32, X, t, rows, w, s);
     if (rc) return rc;
     if (h_loss && log_every > 0 && k % log_every == 0) {
       hipLaunchKernelGGL(loss_kernel, dim3(members), dim3(1024), 0, s, md, t, rows, w);
@@ -694,8 +793,12 @@ int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread
   int* counts = (int*)p;
   int* offs = (int*)(p + align256((size_t)nb * 4));
   int64_t* total = (int64_t*)(p + 2 * align256((size_t)nb * 4));
-  hipLaunchKernelGGL(query_kernel, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
-                     d_fallback, counts);
+  if (h.precision == IT_MLP_FP32)
+    hipLaunchKernelGGL(query_kernel<true>, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
+                       d_fallback, counts);
+  else
+    hipLaunchKernelGGL(query_kernel<false>, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
+                       d_fallback, counts);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, nb, offs, total);
   if (d_fallback_idx)
     hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(kTileS), 0, s, d_fallback, nq, offs, d_fallback_idx);

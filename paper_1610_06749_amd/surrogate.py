@@ -3,11 +3,13 @@
 Pipeline (every numerical step runs in the library's kernels):
 
 1. Training data: each sample (LET, b, V, gap, dose per pulse, pulse rate)
-   becomes one chamber (one centred track parallel to the field plus the
-   dose as uniform pre-ionisation, see ``workloads.surrogate_chamber``) and
-   ln k_s comes from the batched solver (``it_solve_batch``).  Samples are
-   grouped by their expected number of time steps so that the chambers of
-   one batched run finish together.
+   becomes a chamber (one centred track parallel to the field plus the
+   dose as uniform pre-ionisation, see ``workloads.surrogate_chamber``) at
+   the two gap resolutions around its real plane count, and its reference
+   ln k_s is their weighted blend (``workloads.surrogate_resolutions``), so
+   that the target is continuous in the inputs; both come from the batched
+   solver (``it_solve_batch``).  Runs are grouped by their expected number
+   of time steps so that the chambers of one batched run finish together.
 2. Training: an ensemble of MLPs learns the residual of ln k_s over the
    analytic baseline -ln f_Jaffe - ln f_Boag (``it_mlp_train``).
 3. Queries (``it_mlp_query``): ensemble mean; a query whose inputs leave the
@@ -45,37 +47,44 @@ def expected_steps(ch, tr):
     return 1.5 * ch["gap"] / (min(ch["mu_pos"], ch["mu_neg"]) * E) / dt + 50
 
 
-def solver_lnks(X, group=512, stream=None):
-    """ln k_s of every input row from the batched solver; returns (lnks,
-    total voxel-steps, seconds)."""
+def solver_lnks(X, group=512, stream=None, log=None):
+    """Reference ln k_s of every input row from the batched solver (the
+    blend of the two gap resolutions); returns (lnks, total voxel-steps,
+    seconds).  ``log``: None or a callable taking a progress message."""
     import torch
-    chs, trs, est = [], [], []
-    for x in X:
-        ch, tr = W.surrogate_chamber(x)
-        chs.append(ch)
-        trs.append(tr)
-        est.append(expected_steps(ch, tr))
-    order = np.argsort(est)
-    out = np.empty(len(X))
+    chs, trs, est, owner, weight = [], [], [], [], []
+    for q, x in enumerate(X):
+        for nz, w in W.surrogate_resolutions(x):
+            ch, tr = W.surrogate_chamber(x, nz=nz)
+            chs.append(ch)
+            trs.append(tr)
+            est.append(expected_steps(ch, tr))
+            owner.append(q)
+            weight.append(w)
+    order = np.argsort(est, kind="stable")
+    out = np.zeros(len(X))
     vs = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for g0 in range(0, len(X), group):
+    for g0 in range(0, len(chs), group):
+        if log and g0 and g0 % (32 * group) == 0:
+            log(f"solver runs: {g0} of {len(chs)}")
         idx = order[g0:g0 + group]
         res = B.it_solve_batch([chs[i] for i in idx], [trs[i] for i in idx], stream=stream)
         for i, r in zip(idx, res):
             if r["flags"] & (B.IT_FLAG_NONFINITE | B.IT_FLAG_MAX_STEPS):
                 raise RuntimeError(f"solver run {i} did not finish cleanly (flags {r['flags']})")
-            out[i] = math.log(r["ks"])
+            out[owner[i]] += weight[i] * math.log(r["ks"])
             vs += r["steps"] * chs[i]["nx"] * chs[i]["ny"] * (chs[i]["nz"] - 1)
     torch.cuda.synchronize()
     return out, vs, time.perf_counter() - t0
 
 
 class Surrogate:
-    def __init__(self, members=4, seed=W.SEED_BASE + 5 if W else 0):
+    def __init__(self, members=4, seed=W.SEED_BASE + 5 if W else 0, precision=B.IT_MLP_FP32):
         self.members = members
         self.seed = seed
+        self.precision = precision
         self.model = None
 
     def fit(self, X, lnks, steps=150000, lr=2e-3, lr_final=1e-5, batch=2048, log_every=1000, margin=1e-3):
@@ -94,12 +103,12 @@ class Surrogate:
         self.model = torch.empty(B.it_mlp_model_bytes(self.members), dtype=torch.uint8, device="cuda")
         norm0 = np.concatenate([mu, sd, Z.min(0) - margin, Z.max(0) + margin, [0.0, 1.0]])
         params = W.mlp_init(self.seed, self.members)
-        B.it_mlp_init(self.model, self.members, params, norm0, phys_constants())
+        B.it_mlp_init(self.model, self.members, params, norm0, phys_constants(), precision=self.precision)
         Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
         base = B.it_mlp_baseline(self.model, Xd).cpu().numpy()
         resid = lnks - base
         norm = np.concatenate([mu, sd, Z.min(0) - margin, Z.max(0) + margin, [resid.mean(), resid.std()]])
-        B.it_mlp_init(self.model, self.members, params, norm, phys_constants())
+        B.it_mlp_init(self.model, self.members, params, norm, phys_constants(), precision=self.precision)
         n = len(X)
         if batch <= 0 or batch >= n or n % batch:
             batch = 0  # full batch
@@ -133,62 +142,93 @@ class Surrogate:
         return out, mask
 
 
-def evaluate(n_train=8192, n_hold=512, n_query=65536, spread_tol=1e-3, members=4, steps=150000, seed=None):
-    """The surrogate experiment: train on n_train solver runs, judge on
-    n_hold held-out solver runs, time n_query queries.  Returns a dict."""
-    import torch
+def solver_data(n_train=32768, n_hold=1024, seed=None, log=None):
+    """Training and held-out data from the solver: a dict of the inputs,
+    ln k_s, voxel-steps and seconds of each set."""
     base_seed = W.SEED_BASE + 5 if seed is None else seed
     Xtr = W.surrogate_inputs(base_seed, n_train)
-    ytr, vs_tr, sec_tr = solver_lnks(Xtr)
-    s = Surrogate(members=members, seed=base_seed + 100)
-    s.fit(Xtr, ytr, steps=steps)
+    ytr, vs_tr, sec_tr = solver_lnks(Xtr, log=log)
     Xh = W.surrogate_inputs(base_seed + 1, n_hold)
-    yh, vs_h, sec_h = solver_lnks(Xh)
-    mean, spread, fb, idx, n_fb = s.query(Xh, spread_tol)
-    m = mean.double().cpu().numpy()
-    mask = fb.cpu().numpy().astype(bool)
-    rel = np.abs(np.expm1(m - yh))  # relative error of k_s
+    yh, vs_h, sec_h = solver_lnks(Xh, log=log)
+    return dict(seed=base_seed, Xtr=Xtr, ytr=ytr, vs_tr=vs_tr, sec_tr=sec_tr, Xh=Xh, yh=yh, vs_h=vs_h, sec_h=sec_h)
+
+
+def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members=4, steps=300000, seed=None,
+             precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None):
+    """The surrogate experiment: train on n_train solver runs, judge on
+    n_hold held-out solver runs, time n_query queries (``data`` from
+    ``solver_data`` reuses solver runs).  The figures are taken at the
+    spread tolerance ``spread_tol``; ``at_spread_tol`` repeats the accuracy
+    and throughput figures at each of ``extra_tols``.  ``log``: None or a
+    callable taking a progress message.  Returns a dict."""
+    import torch
+    say = log or (lambda msg: None)
+    d = data if data is not None else solver_data(n_train, n_hold, seed, log=log)
+    base_seed = d["seed"]
+    Xtr, ytr, vs_tr, sec_tr = d["Xtr"], d["ytr"], d["vs_tr"], d["sec_tr"]
+    Xh, yh, sec_h = d["Xh"], d["yh"], d["sec_h"]
+    n_train, n_hold = len(Xtr), len(Xh)
+    say(f"surrogate: {n_train} training and {n_hold} held-out samples from the solver in {sec_tr + sec_h:.0f} s")
+    s = Surrogate(members=members, seed=base_seed + 100, precision=precision)
+    s.fit(Xtr, ytr, steps=steps)
+    say(f"surrogate: {steps} training steps in {s.train_seconds:.0f} s")
     Xhd = torch.tensor(Xh, dtype=torch.float32, device="cuda")
     base = B.it_mlp_baseline(s.model, Xhd).cpu().numpy()
     rel_base = np.abs(np.expm1(base - yh))
-    acc = ~mask
-    # query throughput at the full batch (inputs resident, fallback excluded)
     Xq = torch.tensor(W.surrogate_inputs(base_seed + 2, n_query), dtype=torch.float32, device="cuda")
     out = (torch.empty(n_query, dtype=torch.float32, device="cuda"),
            torch.empty(n_query, dtype=torch.float32, device="cuda"),
            torch.empty(n_query, dtype=torch.uint8, device="cuda"),
            torch.empty(n_query, dtype=torch.int64, device="cuda"))
-    B.it_mlp_query(s.model, Xq, spread_tol, out=out)
-    torch.cuda.synchronize()
-    reps = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        _, _, _, _, nq_fb = B.it_mlp_query(s.model, Xq, spread_tol, out=out)
-    e1.record()
-    e1.synchronize()
-    q_sec = e0.elapsed_time(e1) * 1e-3 / reps
-    solver_rate = n_hold / sec_h  # k_s evaluations per second by the batched solver
-    fb_frac_q = nq_fb / n_query
-    # surrogate plus solver fallback at equal (solver) accuracy on the flagged part
-    combined = 1.0 / (q_sec / n_query + fb_frac_q / solver_rate)
-    return {
+    solver_rate = n_hold / sec_h  # reference k_s evaluations per second by the batched solver
+
+    def at_tol(tol):
+        mean, spread, fb, idx, n_fb = s.query(Xh, tol)
+        m = mean.double().cpu().numpy()
+        mask = fb.cpu().numpy().astype(bool)
+        rel = np.abs(np.expm1(m - yh))  # relative error of k_s
+        acc = ~mask
+        # query throughput at the full batch (inputs resident, fallback excluded)
+        B.it_mlp_query(s.model, Xq, tol, out=out)
+        torch.cuda.synchronize()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            _, _, _, _, nq_fb = B.it_mlp_query(s.model, Xq, tol, out=out)
+        e1.record()
+        e1.synchronize()
+        q_sec = e0.elapsed_time(e1) * 1e-3 / reps
+        fb_frac_q = nq_fb / n_query
+        # surrogate plus solver fallback at equal (solver) accuracy on the flagged part
+        combined = 1.0 / (q_sec / n_query + fb_frac_q / solver_rate)
+        return rel, acc, {
+            "spread_tol_ln": tol,
+            "holdout_accepted_fraction": float(acc.mean()),
+            "holdout_rel_err_accepted_max": float(rel[acc].max()) if acc.any() else None,
+            "holdout_rel_err_accepted_p99": float(np.quantile(rel[acc], 0.99)) if acc.any() else None,
+            "holdout_accepted_beyond_0.1pct": int(np.sum(rel[acc] > 1e-3)),
+            "query_seconds": q_sec, "query_rate": n_query / q_sec,
+            "query_fallback_fraction": fb_frac_q,
+            "surrogate_over_solver": (n_query / q_sec) / solver_rate,
+            "surrogate_with_fallback_over_solver": combined / solver_rate,
+        }
+
+    rel, acc, main = at_tol(spread_tol)
+    res = {
         "n_train": n_train, "n_holdout": n_hold, "n_query": n_query, "members": members,
-        "spread_tol_ln": spread_tol,
+        "precision": "fp32" if precision == B.IT_MLP_FP32 else "bf16",
         "train_data_seconds": sec_tr, "train_data_voxel_steps": vs_tr, "train_seconds": s.train_seconds,
         "train_steps": s.train_steps, "train_batch": s.batch,
         "final_loss": float(s.loss_log[-1].max()) if s.loss_log is not None and len(s.loss_log) else None,
-        "holdout_accepted_fraction": float(acc.mean()),
-        "holdout_rel_err_accepted_max": float(rel[acc].max()) if acc.any() else None,
-        "holdout_rel_err_accepted_p99": float(np.quantile(rel[acc], 0.99)) if acc.any() else None,
         "holdout_frac_within_0.1pct_all": float(np.mean(rel < 1e-3)),
         "holdout_rel_err_all_median": float(np.median(rel)),
         "holdout_rel_err_all_p90": float(np.quantile(rel, 0.9)),
         "baseline_rel_err_median": float(np.median(rel_base)),
         "baseline_rel_err_p90": float(np.quantile(rel_base, 0.9)),
-        "query_seconds": q_sec, "query_rate": n_query / q_sec,
-        "query_fallback_fraction": fb_frac_q,
         "solver_ks_rate": solver_rate,
-        "surrogate_over_solver": (n_query / q_sec) / solver_rate,
-        "surrogate_with_fallback_over_solver": combined / solver_rate,
     }
+    res.update(main)
+    res["at_spread_tol"] = [at_tol(t)[2] for t in extra_tols]
+    say("surrogate: queries timed")
+    return res

@@ -1,11 +1,15 @@
 """Surrogate kernels on the GPU against the FP64 reference network.
 
-Both sides round weights and hidden activations to BF16 at the same points.
-The FP32 (GPU) and FP64 (reference) pre-activations can land on opposite
-sides of a BF16 rounding boundary; such a flip moves one activation by one
-BF16 step (2^-8 relative).  So the forward bar is 2e-4 on the median and
-99th percentile sample and 3e-2 on the worst, and gradients are compared
-per parameter block in the 2-norm.
+BF16 models: both sides round weights and hidden activations to BF16 at the
+same points.  The FP32 (GPU) and FP64 (reference) pre-activations can land
+on opposite sides of a BF16 rounding boundary; such a flip moves one
+activation by one BF16 step (2^-8 relative).  So the forward bar is 2e-4 on
+the median and 99th percentile sample and 3e-2 on the worst, and gradients
+are compared per parameter block in the 2-norm.
+
+FP32 models: the reference runs without casts; the GPU's FP32 arithmetic
+(sums of 128 products, expf in SiLU) stays within a few 1e-6 of it, so the
+forward bar is 2e-5 on every sample and the gradient bar 1e-4 per block.
 """
 import numpy as np
 import pytest
@@ -36,21 +40,21 @@ def make_norm(X, t, margin=1e-3):
                            [t.mean(), t.std()]]).astype(np.float32)
 
 
-def setup(gpu, members, n, seed=1, scale=1.0):
+def setup(gpu, members, n, seed=1, scale=1.0, precision=None):
     import torch
     X = W.surrogate_inputs(seed, n).astype(np.float32)
     t = (np.sin(np.log(X)).sum(axis=1) * 0.3 + 0.1 * np.log(X[:, 0])).astype(np.float32)
     norm = make_norm(X.astype(np.float64), t.astype(np.float64))
     params = W.mlp_init(seed + 10, members) * np.float32(scale)
     model = torch.empty(gpu.it_mlp_model_bytes(members), dtype=torch.uint8, device="cuda")
-    gpu.it_mlp_init(model, members, params, norm)
+    gpu.it_mlp_init(model, members, params, norm, precision=precision)
     return model, X, t, norm, params
 
 
-def ref_forward(params, X, norm, members):
+def ref_forward(params, X, norm, members, cast=True):
     n = dict(mu=norm[0:6].astype(np.float64), sigma=norm[6:12].astype(np.float64))
     Z = mlp.standardise(X.astype(np.float64), n)
-    ys = [mlp.forward(params[m].astype(np.float64), Z, cast=True)[0] * float(norm[25]) + float(norm[24])
+    ys = [mlp.forward(params[m].astype(np.float64), Z, cast=cast)[0] * float(norm[25]) + float(norm[24])
           for m in range(members)]
     return np.stack(ys), Z
 
@@ -86,6 +90,55 @@ def test_gradient_matches_reference(gpu):
             a, b = g[m, off:off + k], rg[off:off + k]
             assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b) + 1e-7, name
             off += k
+
+
+def test_fp32_forward_matches_reference(gpu):
+    import torch
+    members, n = 3, 4000
+    model, X, t, norm, params = setup(gpu, members, n, precision=gpu.IT_MLP_FP32)
+    mean, spread, fb, idx, cnt = gpu.it_mlp_query(model, torch.tensor(X, device="cuda"), 1e30)
+    ys, _ = ref_forward(params, X, norm, members, cast=False)
+    err = np.abs(mean.cpu().numpy() - ys.mean(axis=0)) / (1 + np.abs(ys.mean(axis=0)))
+    assert err.max() < 2e-5
+    ref_sp = ys.max(axis=0) - ys.min(axis=0)
+    assert np.max(np.abs(spread.cpu().numpy() - ref_sp) / (1 + ref_sp)) < 2e-5
+    # the BF16 model of the same weights is measurably further from the
+    # exact network
+    model_b, _, _, _, _ = setup(gpu, members, n, precision=gpu.IT_MLP_BF16)
+    mean_b = gpu.it_mlp_query(model_b, torch.tensor(X, device="cuda"), 1e30)[0].cpu().numpy()
+    err_b = np.abs(mean_b - ys.mean(axis=0)) / (1 + np.abs(ys.mean(axis=0)))
+    assert np.median(err_b) > 10 * np.median(err)
+
+
+def test_fp32_gradient_matches_reference(gpu):
+    import torch
+    members, n = 2, 2048
+    model, X, t, norm, params = setup(gpu, members, n, seed=3, precision=gpu.IT_MLP_FP32)
+    grad, loss = gpu.it_mlp_grad(model, members, torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"))
+    g = grad.cpu().numpy()
+    _, Z = ref_forward(params, X, norm, members, cast=False)
+    ts = (t.astype(np.float64) - float(norm[24])) / float(norm[25])
+    for m in range(members):
+        rl, rg = mlp.loss_and_grad(params[m].astype(np.float64), Z, ts, cast=False)
+        assert loss[m] == pytest.approx(rl, rel=1e-5)
+        off = 0
+        for name, shape in mlp.SIZES:
+            k = int(np.prod(shape))
+            a, b = g[m, off:off + k], rg[off:off + k]
+            assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b) + 1e-8, name
+            off += k
+
+
+def test_fp32_minibatch_training_and_bad_precision(gpu):
+    import torch
+    members, n = 2, 2048
+    model, X, t, norm, params = setup(gpu, members, n, seed=5, precision=gpu.IT_MLP_FP32)
+    Xd, td = torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda")
+    losses = gpu.it_mlp_train(model, members, Xd, td, steps=300, lr=2e-3, log_every=50, batch=512)
+    assert np.all(losses[-1] < 0.2 * losses[0])
+    with pytest.raises(gpu.ItError) as e:
+        setup(gpu, 1, 64, precision=7)
+    assert e.value.code == gpu.IT_EINVAL
 
 
 def test_training_reduces_loss(gpu):

@@ -44,3 +44,26 @@ def test_shaped_pulse_disc_region_and_values():
     # uniform over the disc: the mean squared radius is r^2/2
     assert np.mean(d**2) == pytest.approx(r * r / 2, rel=0.15)
     assert np.all((tr[:, 0] >= 1) & (tr[:, 0] <= 2)) and np.all(tr[:, 1] == 8e-4) and np.all(tr[:, 4] == 0.3)
+
+
+def test_surrogate_resolutions_blend_is_continuous(orc):
+    """The two gap resolutions around the real plane count: weights sum to
+    one, and the blended ln k_s does not jump where the plane count steps
+    (a single resolution jumps by a few 1e-4 there)."""
+    import math
+    for x in W.surrogate_inputs(3, 50):
+        res = W.surrogate_resolutions(x)
+        assert res[1][0] == res[0][0] + 1 and res[0][0] >= 8
+        assert abs(res[0][1] + res[1][1] - 1.0) < 1e-15 and 0.0 <= res[1][1] < 1.0
+
+    def blended(x):
+        return sum(w * math.log(orc.solve(*W.surrogate_chamber(x, nz=nz), with_fields=False)["ks"])
+                   for nz, w in W.surrogate_resolutions(x))
+
+    def single(x):
+        return math.log(orc.solve(*W.surrogate_chamber(x), with_fields=False)["ks"])
+
+    lo = [50.0, 1e-3, 200.0, 0.030 * (1 - 1e-7), 0.1, 100.0]  # 50 planes of 6e-4 cm end at d = 0.03
+    hi = [50.0, 1e-3, 200.0, 0.030 * (1 + 1e-7), 0.1, 100.0]
+    assert abs(single(hi) - single(lo)) > 2e-4
+    assert abs(blended(hi) - blended(lo)) < 1e-5

@@ -7,7 +7,7 @@ sharing any code of the method.
 
 A chamber is a plain ``dict`` whose keys mirror the C struct ``it_chamber``:
 
-    nx, ny      transverse node counts (periodic lateral boundaries)
+    nx, ny      transverse node counts
     nz          number of gap intervals; planes k=0 (anode) and k=nz (cathode)
                 are the electrodes, interior planes are 1..nz-1
     dx, dy      transverse node spacing [cm]; the gap spacing is gap/nz
@@ -23,6 +23,7 @@ A chamber is a plain ``dict`` whose keys mirror the C struct ``it_chamber``:
     max_steps   hard limit on the number of time steps
     uniform_n0  uniform ion-pair density added to both species at t=0 [cm^-3]
     space_charge  1 adds the space-charge screening term, 0 leaves it out
+    lateral_bc  0 periodic lateral boundaries, 1 absorbing ones
     reaction_limit  rho >= 0: the time step is also bounded by
                 alpha dt n_ref <= rho, n_ref the reference peak density of
                 the inputs (0 leaves only the transport bound)
@@ -281,19 +282,35 @@ def surrogate_inputs(seed: int, n: int) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
-def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: float = 1.5):
+def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: float = 1.5, nz=None):
     """Chamber and track of one surrogate sample: one Gaussian track parallel
     to the field through the centre of a periodic cell of cells x cells nodes
     at spacing b / b_over_dx, gap intervals of about dz_over_dx times that
     spacing (much coarser gap intervals let Lax-Wendroff ripples at the ion
-    column fronts drive the recombination sink unstable), the dose as
-    uniform pre-ionisation, everything at t = 0 (one pulse)."""
+    column fronts drive the recombination sink unstable) or exactly nz of
+    them, the dose as uniform pre-ionisation, everything at t = 0 (one
+    pulse)."""
     let, b, V, d, dose, _rate = (float(v) for v in x)
     dx = b / b_over_dx
-    nz = max(8, int(math.ceil(d / (dz_over_dx * dx))))
-    ch = chamber(cells, cells, nz, dx, d, V, uniform_n0=dose * ion_pairs_per_mGy(AIR["W_eV"]))
+    if nz is None:
+        nz = max(8, int(math.ceil(d / (dz_over_dx * dx))))
+    ch = chamber(cells, cells, int(nz), dx, d, V, uniform_n0=dose * ion_pairs_per_mGy(AIR["W_eV"]))
     tr = tracks([[let, b, (cells // 2) * dx, (cells // 2) * dx, 0.0, 0.0, 0.0]])
     return ch, tr
+
+
+def surrogate_resolutions(x, b_over_dx: float = 2.5, dz_over_dx: float = 1.5):
+    """The two gap resolutions whose results define a surrogate sample's
+    reference ln k_s, with their weights: nz0 = floor(nu) and nz0 + 1 around
+    the real plane count nu = d / (dz_over_dx b / b_over_dx), weights
+    1 - (nu - nz0) and nu - nz0.  A run at one integer plane count jumps by a
+    few 1e-4 in k_s where the count steps; the blend is continuous in the
+    inputs."""
+    b, d = float(x[1]), float(x[3])
+    nu = max(8.0, d / (dz_over_dx * b / b_over_dx))
+    n0 = int(math.floor(nu))
+    w = nu - n0
+    return [(n0, 1.0 - w), (n0 + 1, w)]
 
 
 def mlp_init(seed: int, members: int) -> np.ndarray:
