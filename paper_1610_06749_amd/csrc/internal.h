@@ -159,8 +159,9 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hip
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
 // sc: some instance has the space-charge term on; ab: some instance has
-// absorbing lateral boundaries
+// absorbing lateral boundaries; record_prev: the launch also records the
+// previous pass's step of every instance (false only for the first pass)
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, bool ab,
-                             int parity, hipStream_t s);
+                             int parity, bool record_prev, hipStream_t s);
 
 }  // namespace it

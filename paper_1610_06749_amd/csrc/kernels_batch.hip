@@ -3,10 +3,14 @@
 // instance keeps its own grid, tiling, coefficients, fields and run state in
 // a device table); a block finds its instance by binary search, skips it
 // once the instance has stopped, and otherwise runs the same tile step as
-// the single-chamber kernel.  A second launch (one block per instance)
-// reduces each instance's partial tallies and takes its stop decision.
-// Kernel boundaries order the passes; the host captures a chain of passes
-// in a HIP graph and replays it until every instance has stopped.
+// the single-chamber kernel.  The same launch has one more block per
+// instance: it reduces that instance's partial tallies of the previous pass
+// (the partials alternate between two buffers) and records its step and stop
+// decision while the tile blocks compute the next step.  Blocks that read the
+// stop flag while it is being set only decide whether to compute one step
+// past the stop, which no result reads.  Kernel boundaries order the passes;
+// the host captures a chain of passes in a HIP graph and replays it until
+// every instance has stopped.
 #include "stencil_plain.h"
 
 namespace it {
@@ -22,11 +26,33 @@ __device__ inline int find_instance(const BatchInstance* inst, int ninst, int L)
   return lo;
 }
 
+// Records the previous pass's step of instance q (its partials are in the
+// buffer of the other parity).
+template <int NT>
+__device__ void record_previous(const BatchInstance& bi, int parity) {
+  const StepParams& p = bi.sp[parity ^ 1];
+  if (p.state->done) return;
+  __shared__ double totals[kAcc];
+  reduce_partials<NT>(p.partials, bi.ntiles, kAcc, kAcc, totals);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const int64_t step = p.state->steps;
+    finalize_steps(p.state, p.trace, totals, 1, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
+    if (!p.state->done && p.state->steps >= bi.max_steps) {
+      p.state->done = 1;
+      p.state->by_limit = 1;
+    }
+  }
+}
+
 template <int SY, bool SC, bool AB>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                        int parity) {
   const int b = blockIdx.x;
+  if (b >= 8 * per_xcd) {  // the recording blocks, one per instance
+    record_previous<kTX * SY>(inst[b - 8 * per_xcd], parity);
+    return;
+  }
   const int L = (b & 7) * per_xcd + (b >> 3);  // XCD-aware order over the whole list
   if (L >= total_tiles) return;
   const int q = find_instance(inst, ninst, L);
@@ -38,49 +64,34 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
   plain_tile_step<SY, SC, AB>(p, t, p.partials + (size_t)l * kAcc);
 }
 
-__global__ __launch_bounds__(1024) void batch_reduce_kernel(const BatchInstance* __restrict__ inst,
-                                                            int parity) {
-  const BatchInstance& bi = inst[blockIdx.x];
-  const StepParams& p = bi.sp[parity];
-  if (p.state->done) return;
-  __shared__ double totals[kAcc];
-  reduce_partials<1024>(p.partials, bi.ntiles, kAcc, kAcc, totals);
-  if (threadIdx.x == 0) {
-    const int64_t step = p.state->steps;
-    finalize_steps(p.state, p.trace, totals, 1, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
-    if (!p.state->done && p.state->steps >= bi.max_steps) {
-      p.state->done = 1;
-      p.state->by_limit = 1;
-    }
-  }
+}  // namespace
+
+namespace {
+
+template <int SY, bool SC, bool AB>
+void launch_batch_instance(const BatchInstance* inst, int nrecord, int ninst, int total_tiles, int per_xcd,
+                           int parity, hipStream_t s) {
+  hipLaunchKernelGGL((batch_step_kernel<SY, SC, AB>), dim3(8 * per_xcd + nrecord), dim3(kTX, SY), 0, s, inst,
+                     ninst, total_tiles, per_xcd, parity);
 }
 
 }  // namespace
 
-template <int SY, bool SC, bool AB>
-void launch_batch_instance(const BatchInstance* inst, int ninst, int total_tiles, int per_xcd, int parity,
-                           hipStream_t s) {
-  hipLaunchKernelGGL((batch_step_kernel<SY, SC, AB>), dim3(8 * per_xcd), dim3(kTX, SY), 0, s, inst, ninst,
-                     total_tiles, per_xcd, parity);
-}
-
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, bool ab,
-                             int parity, hipStream_t s) {
+                             int parity, bool record_prev, hipStream_t s) {
   const BatchInstance* inst = (const BatchInstance*)table;
   const int per_xcd = (total_tiles + 7) / 8;
+  const int nr = record_prev ? ninst : 0;
   switch ((plain_tile_rows(tile_y) == 16 ? 4 : 0) + (sc ? 2 : 0) + (ab ? 1 : 0)) {
-    case 0: launch_batch_instance<8, false, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    case 1: launch_batch_instance<8, false, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    case 2: launch_batch_instance<8, true, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    case 3: launch_batch_instance<8, true, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    case 4: launch_batch_instance<16, false, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    case 5: launch_batch_instance<16, false, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    case 6: launch_batch_instance<16, true, false>(inst, ninst, total_tiles, per_xcd, parity, s); break;
-    default: launch_batch_instance<16, true, true>(inst, ninst, total_tiles, per_xcd, parity, s); break;
+    case 0: launch_batch_instance<8, false, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    case 1: launch_batch_instance<8, false, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    case 2: launch_batch_instance<8, true, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    case 3: launch_batch_instance<8, true, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    case 4: launch_batch_instance<16, false, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    case 5: launch_batch_instance<16, false, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    case 6: launch_batch_instance<16, true, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
+    default: launch_batch_instance<16, true, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batch_reduce_kernel, dim3(ninst), dim3(1024), 0, s, inst, parity);
   return hipGetLastError();
 }
 

@@ -646,8 +646,8 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
     const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows, z_chunk);
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.ntiles = ts.ntiles;
-    L.off_partials = off;
-    off = align_up(off + std::max((size_t)ts.ntiles * kAcc, (size_t)td.grid * 5) * sizeof(double));
+    L.off_partials = off;  // two halves of step partials (alternate passes); the deposit uses the start
+    off = align_up(off + std::max((size_t)2 * ts.ntiles * kAcc, (size_t)td.grid * 5) * sizeof(double));
     L.off_counter = off;
     off = align_up(off + 64 * sizeof(unsigned));
     L.off_tracks = off;
@@ -1081,7 +1081,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       sp.stop_tol = c->stop_tol;
       sp.step0 = 0;
       sp.min_stop_step = 0;
-      sp.partials = (double*)(ws + L.off_partials);
+      sp.partials = (double*)(ws + L.off_partials) + (size_t)par * L.ntiles * kAcc;
       sp.counter = (unsigned*)(ws + L.off_counter);
       sp.state = states + q;
       sp.trace = nullptr;
@@ -1148,16 +1148,28 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     hipError_t ce = hipSuccess;
     for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
       ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, any_sc, any_ab, (parity0 + k) & 1,
-                             cs);
+                             true, cs);
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
     if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;
     return IT_OK;
   };
-  rc = build(0);
+  // Pass p computes step p of every running instance and records step p-1
+  // (the extra blocks of its launch reduce the previous pass's partials), so
+  // a first pass that only steps primes the chain; the graph's passes
+  // continue from parity 1.
+  rc = build(1);
   if (rc) {
     release_graph();
     return rc;
+  }
+  {
+    int tiles = 0;
+    for (int q = 0; q < ninst; ++q) tiles += table[q].ntiles;
+    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, any_sc, any_ab, 0, false, stream) != hipSuccess) {
+      release_graph();
+      return IT_EHIP;
+    }
   }
   (void)total_tiles;
   // Replays until every instance has stopped; two replays in flight so the
@@ -1166,7 +1178,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   hipEvent_t evs[2];
   HIP_TRY(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
-  int issued = 0;
+  int issued = 1;  // the priming pass
   int64_t replays_since_build = 0;
   rc = IT_OK;
   for (int64_t r = 0; r < max_replays; ++r) {
