@@ -186,10 +186,15 @@ typedef struct {
    * events[2i+1] just after the i-th stepping-kernel launch of the call, for
    * i < n_timing_events / 2 (later launches are not instrumented).  The
    * events bracket the stepping kernel alone, not the tally reduction that
-   * follows it.  The computation is unchanged.  Ignored by it_solve_batch. */
+   * follows it.  With timing_span = 1 instead (n_timing_events >= 2), only
+   * events[0] is recorded, before the first stepping launch, and events[1]
+   * after the last one: the span of all stepping launches of the call,
+   * without events between them.  The computation is unchanged.  Ignored by
+   * it_solve_batch. */
   void* const* timing_events;
   int32_t n_timing_events;
   int32_t z_chunk;         /* planes per tile of the one-step kernel, 4..512 (0 = default) */
+  int32_t timing_span;     /* see timing_events */
 } it_exec;
 
 /* Time step of a run: dt_safety times the smaller of

@@ -58,7 +58,7 @@ class it_exec(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
-                ("z_chunk", ctypes.c_int32)]
+                ("z_chunk", ctypes.c_int32), ("timing_span", ctypes.c_int32)]
 
 
 _lib = None
@@ -154,6 +154,7 @@ def _exec(ex):
     if tev is not None:  # a KernelTimer
         e.timing_events = tev.handles
         e.n_timing_events = len(tev.handles)
+        e.timing_span = 1 if tev.span else 0
     return ctypes.byref(e)
 
 
@@ -190,10 +191,15 @@ def it_workspace_size(ch, ntracks: int) -> int:
 class KernelTimer:
     """Timing events for the stepping kernel: pass as ``exec["timing_events"]``
     to it_solve / it_advance; the library records a pair around each of the
-    first ``launches`` stepping-kernel launches of the call.  ``durations()``
-    returns the measured kernel times in seconds (after the call returned)."""
+    first ``launches`` stepping-kernel launches of the call, or, with
+    ``span=True``, one event before the first and one after the last
+    stepping launch.  ``durations()`` returns the measured times in seconds
+    (after the call returned): one per launch, or the one span."""
 
-    def __init__(self, launches):
+    def __init__(self, launches=1, span=False):
+        self.span = bool(span)
+        if self.span:
+            launches = 1
         L = lib()
         self._L = L
         L.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]

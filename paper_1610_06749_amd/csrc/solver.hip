@@ -428,7 +428,8 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const int T = exec_steps_per_pass(ex);
   const int tile_y = ex ? ex->tile_y : 0;
   int64_t check_every = ex && ex->check_every > 0 ? ex->check_every : 64;
-  const int n_timing = ex && ex->timing_events ? std::max(ex->n_timing_events, 0) / 2 : 0;
+  const bool span = ex && ex->timing_events && ex->timing_span && ex->n_timing_events >= 2;
+  const int n_timing = ex && ex->timing_events && !span ? std::max(ex->n_timing_events, 0) / 2 : 0;
 
   double* field[4];
   for (int f = 0; f < 4; ++f) field[f] = (double*)(ws + L.off_field[f]);
@@ -484,6 +485,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   int pending = 0, slot_head = 0;
   // caller's timing events of the launch about to be issued (null when none)
   auto ev_pair = [&](int which) -> hipEvent_t {
+    if (span) return which == 0 && issued == 0 ? (hipEvent_t)ex->timing_events[0] : nullptr;
     return issued < n_timing ? (hipEvent_t)ex->timing_events[2 * issued + which] : nullptr;
   };
   hipEvent_t evs[4];
@@ -580,6 +582,8 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       }
     }
   }
+  if (rc == IT_OK && span && issued > 0 && hipEventRecord((hipEvent_t)ex->timing_events[1], stream) != hipSuccess)
+    fail(IT_EHIP);
   if (rc == IT_OK && close_step() != hipSuccess) fail(IT_EHIP);
   if (rc == IT_OK) {
     if (hipMemcpyAsync(&slots[slot_head], state, sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||

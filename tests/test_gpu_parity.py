@@ -392,3 +392,11 @@ def test_timing_events_leave_results_unchanged(gpu, orc, ex):
     compare_fields(g["pos"], o["pos"])
     d = timer.durations()
     assert d.shape == (4,) and np.all(d > 0.0) and np.all(d < 1.0)
+    # the span of all stepping launches: one pair of events, same results,
+    # at least as long as the four bracketed launches together
+    span = gpu.KernelTimer(span=True)
+    g2 = gpu.it_solve(ch, tr, exec=dict(ex, timing_events=span), trace=True, fields=True)
+    compare_results(g2, o)
+    compare_fields(g2["pos"], o["pos"])
+    ds = span.durations()
+    assert ds.shape == (1,) and d.sum() < ds[0] < 1.0
