@@ -185,8 +185,10 @@ typedef struct {
    * and it_advance record events[2i] on the run's stream just before and
    * events[2i+1] just after the i-th stepping-kernel launch of the call, for
    * i < n_timing_events / 2 (later launches are not instrumented).  The
-   * events bracket the stepping kernel alone, not the tally reduction that
-   * follows it.  With timing_span = 1 instead (n_timing_events >= 2), only
+   * events bracket the stepping kernel launch (with one step per launch it
+   * also records the previous step's tallies in an extra block; the blocked
+   * kernel's tally reduction is a separate launch outside the events).  With
+   * timing_span = 1 instead (n_timing_events >= 2), only
    * events[0] is recorded, before the first stepping launch, and events[1]
    * after the last one: the span of all stepping launches of the call,
    * without events between them.  The computation is unchanged.  Ignored by
@@ -256,7 +258,8 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
  * ch: host [ninst]; tracks of instance q are tracks[track_offsets[q] ..
  * track_offsets[q+1]) (host); every track must be due at step 0 (one pulse
  * per instance, IT_ENOTSUP otherwise).  Each pass is one launch over the
- * tiles of all running instances plus one reduction launch; the library
+ * tiles of all running instances, plus one block per instance that records
+ * the instance's previous step; the library
  * captures exec->check_every passes (default 32, rounded up to even) in a
  * HIP graph and replays it on `stream` until every instance has stopped.
  * out: host [ninst].  No per-step traces or fields are kept.
