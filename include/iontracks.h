@@ -178,7 +178,7 @@ typedef struct {
 typedef struct {
   int32_t kernel;          /* IT_KERNEL_* */
   int32_t steps_per_pass;  /* T for the blocked kernel, 1..8 (0 = default) */
-  int32_t tile_y;          /* rows per tile of the blocked kernel (0 = default) */
+  int32_t tile_y;          /* rows per tile of the one-step kernels, 8 or 16 (0 = default) */
   int32_t check_every;     /* steps between host checks of the stop criterion (0 = default) */
   /* Optional instrumentation (NULL / 0 = none): caller-created hipEvent_t
    * handles, created with timing enabled on the device of the run.  it_solve
@@ -197,6 +197,9 @@ typedef struct {
   int32_t n_timing_events;
   int32_t z_chunk;         /* planes per tile of the one-step kernel, 4..512 (0 = default) */
   int32_t timing_span;     /* see timing_events */
+  int32_t tile_x;          /* columns per tile of the one-step kernels: 64, or 32 (32 x 16 tiles of
+                            * 8 waves, two rows each; tile_y must then be 0 or 16, and the
+                            * blocked kernel does not take it); 0 = default */
 } it_exec;
 
 /* Time step of a run: dt_safety times the smaller of

@@ -58,7 +58,7 @@ class it_exec(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
-                ("z_chunk", ctypes.c_int32), ("timing_span", ctypes.c_int32)]
+                ("z_chunk", ctypes.c_int32), ("timing_span", ctypes.c_int32), ("tile_x", ctypes.c_int32)]
 
 
 _lib = None
@@ -148,7 +148,7 @@ def _exec(ex):
     if ex is None:
         return None
     e = it_exec()
-    for k in ("kernel", "steps_per_pass", "tile_y", "check_every", "z_chunk"):
+    for k in ("kernel", "steps_per_pass", "tile_y", "check_every", "z_chunk", "tile_x"):
         setattr(e, k, int(ex.get(k, 0)))
     tev = ex.get("timing_events")
     if tev is not None:  # a KernelTimer

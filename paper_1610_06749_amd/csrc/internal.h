@@ -149,19 +149,24 @@ struct Step3Params {
 hipError_t launch_step3(const Step3Params& p, hipStream_t s);
 
 // Launchers (stream-ordered, no synchronisation).
-int plain_tile_rows(int tile_y);
+// Tile shape of the one-step kernels: tile_x 32 gives 32 x 16 tiles (8 waves,
+// two rows each); otherwise 64 columns by tile_y = 16 or 8 rows (one wave
+// per row).
+inline int plain_tile_cols(int tile_x) { return tile_x == 32 ? 32 : 64; }
+int plain_tile_rows(int tile_y, int tile_x);
+int plain_tile_waves(int tile_y, int tile_x);
 // ev_begin / ev_end (may be null) are recorded around the stepping kernel
 // alone, before the tally reduction is launched.
 // fused: leave this step's partials to the next launch's extra block (or a
 // closing launch_reduce_steps) instead of launching the reduction now.
-hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin = nullptr,
-                             hipEvent_t ev_end = nullptr, bool fused = false);
+hipError_t launch_step_plain(const StepParams& p, int tile_y, int tile_x, hipStream_t s,
+                             hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr, bool fused = false);
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
 // sc: some instance has the space-charge term on; ab: some instance has
 // absorbing lateral boundaries; record_prev: the launch also records the
 // previous pass's step of every instance (false only for the first pass)
-hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, bool ab,
-                             int parity, bool record_prev, hipStream_t s);
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
+                             bool ab, int parity, bool record_prev, hipStream_t s);
 
 }  // namespace it

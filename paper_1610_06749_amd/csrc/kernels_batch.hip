@@ -44,7 +44,7 @@ __device__ void record_previous(const BatchInstance& bi, int parity) {
   }
 }
 
-template <int SY, bool SC, bool AB>
+template <int SY, bool SC, bool AB, int TX>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                        int parity) {
@@ -61,37 +61,44 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
   const int l = L - inst[q].tile_begin;
   TileCoord t = tile_of(l, p.tiles_x, p.tiles_y);
   t.valid = true;
-  plain_tile_step<SY, SC, AB>(p, t, p.partials + (size_t)l * kAcc);
+  plain_tile_step<SY, SC, AB, TX>(p, t, p.partials + (size_t)l * kAcc);
 }
 
 }  // namespace
 
 namespace {
 
-template <int SY, bool SC, bool AB>
+template <int SY, bool SC, bool AB, int TX>
 void launch_batch_instance(const BatchInstance* inst, int nrecord, int ninst, int total_tiles, int per_xcd,
                            int parity, hipStream_t s) {
-  hipLaunchKernelGGL((batch_step_kernel<SY, SC, AB>), dim3(8 * per_xcd + nrecord), dim3(kTX, SY), 0, s, inst,
+  hipLaunchKernelGGL((batch_step_kernel<SY, SC, AB, TX>), dim3(8 * per_xcd + nrecord), dim3(kTX, SY), 0, s, inst,
                      ninst, total_tiles, per_xcd, parity);
+}
+
+template <int SY, int TX>
+void launch_batch_terms(const BatchInstance* inst, int nrecord, int ninst, int total_tiles, int per_xcd,
+                        int parity, bool sc, bool ab, hipStream_t s) {
+  switch ((sc ? 2 : 0) + (ab ? 1 : 0)) {
+    case 0: launch_batch_instance<SY, false, false, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
+    case 1: launch_batch_instance<SY, false, true, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
+    case 2: launch_batch_instance<SY, true, false, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
+    default: launch_batch_instance<SY, true, true, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, bool sc, bool ab,
-                             int parity, bool record_prev, hipStream_t s) {
+hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
+                             bool ab, int parity, bool record_prev, hipStream_t s) {
   const BatchInstance* inst = (const BatchInstance*)table;
   const int per_xcd = (total_tiles + 7) / 8;
   const int nr = record_prev ? ninst : 0;
-  switch ((plain_tile_rows(tile_y) == 16 ? 4 : 0) + (sc ? 2 : 0) + (ab ? 1 : 0)) {
-    case 0: launch_batch_instance<8, false, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    case 1: launch_batch_instance<8, false, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    case 2: launch_batch_instance<8, true, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    case 3: launch_batch_instance<8, true, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    case 4: launch_batch_instance<16, false, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    case 5: launch_batch_instance<16, false, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    case 6: launch_batch_instance<16, true, false>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-    default: launch_batch_instance<16, true, true>(inst, nr, ninst, total_tiles, per_xcd, parity, s); break;
-  }
+  if (plain_tile_cols(tile_x) == 32)
+    launch_batch_terms<8, 32>(inst, nr, ninst, total_tiles, per_xcd, parity, sc, ab, s);
+  else if (plain_tile_rows(tile_y, tile_x) == 16)
+    launch_batch_terms<16, 64>(inst, nr, ninst, total_tiles, per_xcd, parity, sc, ab, s);
+  else
+    launch_batch_terms<8, 64>(inst, nr, ninst, total_tiles, per_xcd, parity, sc, ab, s);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 // state it writes is read by the next launch.  Stepping blocks that read
 // `done` while it is being set only decide whether to compute a step past
 // the stop, whose output goes to the field pair not holding the stop step.
-template <int SY, bool SC, bool AB>
+template <int SY, bool SC, bool AB, int TX>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_plain_kernel(StepParams p) {
   if (p.prev_partials && blockIdx.x == gridDim.x - 1) {
     if (p.state->done) return;
@@ -36,8 +36,8 @@ __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))
     return;
   }
   if (p.state->done) return;  // set by an earlier launch: every block skips
-  plain_tile_step<SY, SC, AB>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
-                              p.partials + (size_t)blockIdx.x * kAcc);
+  plain_tile_step<SY, SC, AB, TX>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
+                                  p.partials + (size_t)blockIdx.x * kAcc);
 }
 
 // One block: sums the per-block partial tallies of a stepping launch in a
@@ -58,40 +58,44 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
   return hipGetLastError();
 }
 
-int plain_tile_rows(int tile_y) { return tile_y == 16 ? 16 : 8; }
+int plain_tile_rows(int tile_y, int tile_x) { return tile_x == 32 || tile_y == 16 ? 16 : 8; }
+int plain_tile_waves(int tile_y, int tile_x) { return plain_tile_rows(tile_y, tile_x) * plain_tile_cols(tile_x) / kTX; }
 
 namespace {
 
-template <int SY, bool SC, bool AB>
+template <int SY, bool SC, bool AB, int TX>
 void launch_plain_instance(const StepParams& p, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((step_plain_kernel<SY, SC, AB>), g, dim3(kTX, SY), 0, s, p);
+  hipLaunchKernelGGL((step_plain_kernel<SY, SC, AB, TX>), g, dim3(kTX, SY), 0, s, p);
 }
 
-// the kernel instance for the tile rows, the space-charge term and the
-// lateral boundary option of the run
-void launch_plain_variant(const StepParams& p, int rows, dim3 g, hipStream_t s) {
+template <int SY, int TX>
+void launch_plain_terms(const StepParams& p, dim3 g, hipStream_t s) {
   const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
   const bool ab = p.absorbing != 0;
-  switch ((rows == 16 ? 4 : 0) + (sc ? 2 : 0) + (ab ? 1 : 0)) {
-    case 0: launch_plain_instance<8, false, false>(p, g, s); break;
-    case 1: launch_plain_instance<8, false, true>(p, g, s); break;
-    case 2: launch_plain_instance<8, true, false>(p, g, s); break;
-    case 3: launch_plain_instance<8, true, true>(p, g, s); break;
-    case 4: launch_plain_instance<16, false, false>(p, g, s); break;
-    case 5: launch_plain_instance<16, false, true>(p, g, s); break;
-    case 6: launch_plain_instance<16, true, false>(p, g, s); break;
-    default: launch_plain_instance<16, true, true>(p, g, s); break;
+  switch ((sc ? 2 : 0) + (ab ? 1 : 0)) {
+    case 0: launch_plain_instance<SY, false, false, TX>(p, g, s); break;
+    case 1: launch_plain_instance<SY, false, true, TX>(p, g, s); break;
+    case 2: launch_plain_instance<SY, true, false, TX>(p, g, s); break;
+    default: launch_plain_instance<SY, true, true, TX>(p, g, s); break;
   }
+}
+
+// the kernel instance for the tile shape, the space-charge term and the
+// lateral boundary option of the run
+void launch_plain_variant(const StepParams& p, int tile_y, int tile_x, dim3 g, hipStream_t s) {
+  if (plain_tile_cols(tile_x) == 32) launch_plain_terms<8, 32>(p, g, s);
+  else if (plain_tile_rows(tile_y, tile_x) == 16) launch_plain_terms<16, 64>(p, g, s);
+  else launch_plain_terms<8, 64>(p, g, s);
 }
 
 }  // namespace
 
-hipError_t launch_step_plain(const StepParams& p, int tile_y, hipStream_t s, hipEvent_t ev_begin,
+hipError_t launch_step_plain(const StepParams& p, int tile_y, int tile_x, hipStream_t s, hipEvent_t ev_begin,
                              hipEvent_t ev_end, bool fused) {
   const int grid = 8 * p.per_xcd;
   if (ev_begin && hipEventRecord(ev_begin, s) != hipSuccess) return hipErrorInvalidValue;
   const dim3 g(grid + (p.prev_partials ? 1 : 0));
-  launch_plain_variant(p, plain_tile_rows(tile_y), g, s);
+  launch_plain_variant(p, tile_y, tile_x, g, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_end && hipEventRecord(ev_end, s) != hipSuccess) return hipErrorInvalidValue;

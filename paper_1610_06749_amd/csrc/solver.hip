@@ -186,10 +186,10 @@ struct Tiling {
 // Tiling of the interior: tile_x x tile_y columns by chunks of z planes.
 // The stepping kernel marches 32 planes per block (down to 4 on small grids,
 // to keep several hundred blocks); the deposit kernel aims at ~2048 blocks.
-Tiling make_tiling(int nx, int ny, int nz, int tile_y, int zc) {
+Tiling make_tiling(int nx, int ny, int nz, int tile_y, int zc, int tile_x = 64) {
   Tiling t;
   const int nint = nz - 1;
-  t.tiles_x = (nx + 63) / 64;
+  t.tiles_x = (nx + tile_x - 1) / tile_x;
   t.tiles_y = (ny + tile_y - 1) / tile_y;
   const long cols = (long)t.tiles_x * t.tiles_y;
   t.zc = std::max(1, std::min(zc, nint));
@@ -205,15 +205,15 @@ Tiling make_tiling(int nx, int ny, int nz, int tile_y, int zc) {
 // 256 CUs), all resident at once: the launch then takes as long as one
 // chunk, so chunks of equal length and as few chunk starts (each re-reads
 // two planes) as the occupancy allows are what count.
-Tiling step_tiling(int nx, int ny, int nz, int rows, int z_chunk) {
-  if (z_chunk > 0) return make_tiling(nx, ny, nz, rows, z_chunk);
+Tiling step_tiling(int nx, int ny, int nz, int rows, int z_chunk, int tile_x = 64) {
+  if (z_chunk > 0) return make_tiling(nx, ny, nz, rows, z_chunk, tile_x);
   const int nint = nz - 1;
-  const long cols = (long)((nx + 63) / 64) * ((ny + rows - 1) / rows);
-  const long target = 4096 / rows;  // tiles of `rows` waves
+  const long cols = (long)((nx + tile_x - 1) / tile_x) * ((ny + rows - 1) / rows);
+  const long target = 4096 / (rows * tile_x / 64);  // tiles of rows * tile_x / 64 waves
   long chunks = std::max<long>(1, (target + cols / 2) / cols);
   chunks = std::min<long>(chunks, std::max(1, nint / 4));  // at least 4 planes per chunk
   const int zc = (int)((nint + chunks - 1) / chunks);
-  return make_tiling(nx, ny, nz, rows, zc);
+  return make_tiling(nx, ny, nz, rows, zc, tile_x);
 }
 
 // Rows of the one-step kernel's tiles: 8 or 16 as requested, else 8 (on
@@ -226,6 +226,31 @@ int resolve_rows(int tile_y, int ny) {
 constexpr int kMinZChunk = 4, kMaxZChunk = 512;
 
 int exec_z_chunk(const it_exec* ex) { return ex ? ex->z_chunk : 0; }
+
+// Tile width of the one-step kernels for chambers ch[0..n): as asked, else
+// (tile_x and tile_y both 0) 32 x 16 tiles where they cover the planes with
+// at least a quarter fewer padded nodes than 64 x 8 tiles (narrow grids, where
+// most lanes of a 64-wide tile would idle), else 64.  On MI355X 32 x 16 tiles
+// take 1.5 % longer per node on a 256-wide grid and 12 % longer on the
+// 64..256-wide batched sweep, and 20 % less on 24-wide chambers.
+int exec_tile_x(const it_exec* ex, const it_chamber* ch, int n) {
+  if (ex && ex->tile_x != 0) return plain_tile_cols(ex->tile_x);
+  if (ex && ex->tile_y != 0) return 64;
+  double pad64 = 0.0, pad32 = 0.0;
+  for (int q = 0; q < n; ++q) {
+    const double planes = ch[q].nz - 1;
+    pad64 += planes * (double)((ch[q].nx + 63) / 64 * 64) * (double)((ch[q].ny + 7) / 8 * 8);
+    pad32 += planes * (double)((ch[q].nx + 31) / 32 * 32) * (double)((ch[q].ny + 15) / 16 * 16);
+  }
+  return pad32 <= 0.75 * pad64 ? 32 : 64;
+}
+
+// Tile shape fields: tile_x 0, 32 or 64; 32-wide tiles have 16 rows.
+bool tile_shape_ok(const it_exec* ex) {
+  if (!ex) return true;
+  if (ex->tile_x != 0 && ex->tile_x != 32 && ex->tile_x != 64) return false;
+  return ex->tile_x != 32 || ex->tile_y == 0 || ex->tile_y == 16;
+}
 
 bool z_chunk_ok(const it_exec* ex) {
   const int z = exec_z_chunk(ex);
@@ -246,6 +271,7 @@ int check_exec(const it_chamber* ch, const it_exec* ex) {
   if (T > 1 && !blocked_supported(T, ex ? ex->tile_y : 0)) return IT_ENOTSUP;
   if (T > 1 && ch->lateral_bc) return IT_ENOTSUP;  // the blocked kernel is periodic only
   if (!z_chunk_ok(ex)) return IT_EINVAL;
+  if (!tile_shape_ok(ex) || (ex && ex->tile_x == 32 && T > 1)) return IT_EINVAL;
   return IT_OK;
 }
 
@@ -275,6 +301,7 @@ size_t max_grid(const it_chamber* ch) {
   // the smallest z chunk gives the most stepping blocks of any launch shape
   size_t g = std::max((size_t)step_tiling(ch->nx, ch->ny, ch->nz, 8, kMinZChunk).grid,
                       (size_t)deposit_tiling(ch->nx, ch->ny, ch->nz).grid);
+  g = std::max(g, (size_t)step_tiling(ch->nx, ch->ny, ch->nz, 16, kMinZChunk, 32).grid);
   for (int T = 2; T <= kMaxT; ++T) {
     if (!blocked_supported(T, 0)) continue;
     int grid, per, tx, ty, nt, zc, zch;
@@ -443,8 +470,9 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const Coef cp = species_coef(ch, dt, 0), cn = species_coef(ch, dt, 1);
   const double dz = ch->gap / ch->nz;
   const double dV = ch->dx * ch->dy * dz;
-  const int rows = resolve_rows(tile_y, ch->ny);
-  const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, rows, exec_z_chunk(ex));
+  const int tx = T == 1 ? exec_tile_x(ex, ch, 1) : 64;
+  const int rows = tx == 32 ? 16 : resolve_rows(tile_y, ch->ny);
+  const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, rows, exec_z_chunk(ex), tx);
   const Tiling td = deposit_tiling(ch->nx, ch->ny, ch->nz);
 
   RunState* slots = pinned_slots();
@@ -553,11 +581,11 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
         sp.prev_partials = unrecorded ? part_buf[unrecorded_step & 1] : nullptr;
         sp.prev_nblocks = grid_plain;
         sp.prev_step = unrecorded_step;
-        e = launch_step_plain(sp, rows, stream, ev_pair(0), ev_pair(1), true);
+        e = launch_step_plain(sp, rows, tx, stream, ev_pair(0), ev_pair(1), true);
         unrecorded = true;
         unrecorded_step = l;
       } else {
-        e = launch_step_plain(sp, rows, stream, ev_pair(0), ev_pair(1));
+        e = launch_step_plain(sp, rows, tx, stream, ev_pair(0), ev_pair(1));
       }
     } else {
       e = launch_step_blocked(sp, (int)todo, tile_y, stream, ev_pair(0), ev_pair(1));
@@ -630,12 +658,14 @@ int batch_z_chunk(const it_exec* exec) {
 
 // One tile shape serves every instance of a batch.
 int batch_rows(const it_chamber* ch, int ninst, const it_exec* exec) {
+  if (exec_tile_x(exec, ch, ninst) == 32) return 16;
   int min_ny = ch[0].ny;
   for (int q = 1; q < ninst; ++q) min_ny = std::min(min_ny, ch[q].ny);
   return resolve_rows(exec ? exec->tile_y : 0, min_ny);
 }
 
-BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows, int z_chunk) {
+BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows, int z_chunk,
+                              int tile_x) {
   BatchLayout B;
   size_t off = 0;
   B.inst.resize(ninst);
@@ -647,7 +677,7 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
       L.off_field[f] = off;
       off = align_up(off + L.field_elems * sizeof(double));
     }
-    const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows, z_chunk);
+    const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows, z_chunk, tile_x);
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.ntiles = ts.ntiles;
     L.off_partials = off;  // two halves of step partials (alternate passes); the deposit uses the start
@@ -1001,9 +1031,9 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
     if (rc) return rc;
     if (track_offsets[q + 1] < track_offsets[q]) return IT_EINVAL;
   }
-  if (!z_chunk_ok(exec)) return IT_EINVAL;
+  if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
   const int rows = batch_rows(ch, ninst, exec);
-  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec)).total;
+  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst)).total;
   return IT_OK;
 }
 
@@ -1022,8 +1052,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   }
   int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
-  if (!z_chunk_ok(exec)) return IT_EINVAL;
-  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec));
+  if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
+  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst));
   if (!d_workspace || ws_bytes < B.total) return IT_EWORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
   char* ws = (char*)d_workspace;
@@ -1056,7 +1086,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 
     const Coef cp = species_coef(c, dts[q], 0), cn = species_coef(c, dts[q], 1);
     const double dz = c->gap / c->nz, dV = c->dx * c->dy * dz;
-    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows, batch_z_chunk(exec));
+    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst));
     const Tiling td = deposit_tiling(c->nx, c->ny, c->nz);
     BatchInstance& bi = table[q];
     for (int par = 0; par < 2; ++par) {
@@ -1151,8 +1181,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
     hipError_t ce = hipSuccess;
     for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, any_sc, any_ab, (parity0 + k) & 1,
-                             true, cs);
+      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, exec_tile_x(exec, ch, ninst), any_sc, any_ab,
+                             (parity0 + k) & 1, true, cs);
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
     if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;
@@ -1170,7 +1200,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   {
     int tiles = 0;
     for (int q = 0; q < ninst; ++q) tiles += table[q].ntiles;
-    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, any_sc, any_ab, 0, false, stream) != hipSuccess) {
+    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, exec_tile_x(exec, ch, ninst), any_sc, any_ab, 0, false,
+                          stream) != hipSuccess) {
       release_graph();
       return IT_EHIP;
     }

@@ -26,7 +26,9 @@ struct PlaneRegs {
   double p, n;
 };
 
-// Stepping tile: 64 x SY columns (SY = 8 or 16 rows, one wave per row).
+// Stepping tile: TX x (SY * 64 / TX) columns with SY waves: TX = 64 gives one
+// row per wave (64 x 8 or 64 x 16), TX = 32 two rows of 32 per wave (32 x 16
+// with 8 waves: less rim per node, and fewer idle lanes on narrow grids).
 // LDS holds plane k of the tile with a one-node rim: interior (r, x) sits at
 // [r + 1][x + 1]; the rim column/row that follows the last valid column/row
 // (w, h of the tile, smaller than 64/SY on the ragged edge of the grid)
@@ -46,10 +48,12 @@ struct PlaneRegs {
 // runs without it use the instance without them).  AB: honours
 // p.absorbing (absorbing lateral boundaries and the escaped tally, slots
 // 11-12); the instance without it is periodic only.
-template <int SY, bool SC, bool AB>
+template <int SY, bool SC, bool AB, int TX = kTX>
 __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, double* partial_out) {
+  static_assert(TX == 64 || TX == 32, "tile width");
   constexpr int kSNT = kTX * SY;
-  __shared__ double sp[2][SY + 2][kTX + 2], sn[2][SY + 2][kTX + 2];
+  constexpr int SR = SY * (kTX / TX);  // rows of the tile
+  __shared__ double sp[2][SR + 2][TX + 2], sn[2][SR + 2][TX + 2];
   __shared__ double lds[(kSNT / kWave) * kAcc];
   // per-wave sums of n on the planes next to the electrodes (slots 1-4)
   __shared__ double edge[SY][4];
@@ -59,12 +63,13 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
 #pragma unroll
   for (int q = 0; q < kAcc; ++q) acc[q] = 0.0;
 
-  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int lane = threadIdx.x, ty = threadIdx.y;  // ty: the wave
   if (lane < 4) edge[ty][lane] = 0.0;
-  const int x0 = t.tx * kTX, y0 = t.ty * SY;
-  const int w = min(kTX, p.nx - x0), h = min(SY, p.ny - y0);  // valid extent of the tile
-  const int i = x0 + lane, j = y0 + ty;
-  const bool active = t.valid && lane < w && ty < h;
+  const int xl = lane % TX, rl = ty * (kTX / TX) + lane / TX;  // column and row of this thread in the tile
+  const int x0 = t.tx * TX, y0 = t.ty * SR;
+  const int w = min(TX, p.nx - x0), h = min(SR, p.ny - y0);  // valid extent of the tile
+  const int i = x0 + xl, j = y0 + rl;
+  const bool active = t.valid && xl < w && rl < h;
   const int nz = p.nz;
   const int k0 = 1 + t.zc * p.zc;
   const int k1 = t.valid ? min(k0 + p.zc, nz) : k0;
@@ -126,14 +131,14 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
       sn[buf][rim_r][rim_c] = rc.n;
     }
     if (active) {  // inactive threads must not touch the rim slots past the valid extent
-      sp[buf][ty + 1][lane + 1] = c.p;
-      sn[buf][ty + 1][lane + 1] = c.n;
+      sp[buf][rl + 1][xl + 1] = c.p;
+      sn[buf][rl + 1][xl + 1] = c.n;
     }
     lds_barrier();
-    const double pxl = sp[buf][ty + 1][lane], pxr = sp[buf][ty + 1][lane + 2];
-    const double pyl = sp[buf][ty][lane + 1], pyr = sp[buf][ty + 2][lane + 1];
-    const double nxl = sn[buf][ty + 1][lane], nxr = sn[buf][ty + 1][lane + 2];
-    const double nyl = sn[buf][ty][lane + 1], nyr = sn[buf][ty + 2][lane + 1];
+    const double pxl = sp[buf][rl + 1][xl], pxr = sp[buf][rl + 1][xl + 2];
+    const double pyl = sp[buf][rl][xl + 1], pyr = sp[buf][rl + 2][xl + 1];
+    const double nxl = sn[buf][rl + 1][xl], nxr = sn[buf][rl + 1][xl + 2];
+    const double nyl = sn[buf][rl][xl + 1], nyr = sn[buf][rl + 2][xl + 1];
     const double sink = beta * c.p * c.n;
     const double net = c.p - c.n;  // div E in units of q/eps0 (space charge)
     const double scp = SC ? gsp * c.p * net : 0.0, scn = SC ? gsn * c.n * net : 0.0;

@@ -103,6 +103,12 @@ def test_launch_shape_checks(lib):
         with pytest.raises(lib.ItError) as e:
             lib.it_workspace_size_batch(chs, trs, dict(z_chunk=z))
         assert e.value.code == lib.IT_EINVAL
+    # tile shapes: 64 or 32 columns; 32-column tiles have 16 rows
+    assert lib.it_workspace_size_batch(chs, trs, dict(tile_x=32)) > 0
+    for bad in (dict(tile_x=48), dict(tile_x=16), dict(tile_x=32, tile_y=8)):
+        with pytest.raises(lib.ItError) as e:
+            lib.it_workspace_size_batch(chs, trs, bad)
+        assert e.value.code == lib.IT_EINVAL
     # in-plane offsets are 32-bit byte offsets: planes above 2^28 nodes are refused
     with pytest.raises(lib.ItError) as e:
         lib.it_validate(W.chamber(1 << 15, 1 << 14, 2, 1e-4, 2e-4, 10.0), np.zeros((0, 7)))
@@ -133,6 +139,9 @@ def test_lateral_boundary_option_checks(lib, orc):
     assert _solve_status(lib, dict(ab, mu_e=1000.0, D_e=25.0), tr, None) == lib.IT_ENOTSUP
     assert _solve_status(lib, ab, tr, dict(kernel=1)) == lib.IT_EWORKSPACE  # accepted up to the workspace
     assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_EWORKSPACE
+    # 32-column tiles belong to the one-step kernels
+    assert _solve_status(lib, ch, tr, dict(kernel=1, tile_x=32)) == lib.IT_EWORKSPACE
+    assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4, tile_x=32)) == lib.IT_EINVAL
     # the recombination bound sums the tracks' profiles without periodic
     # images: two dense tracks at opposite x edges overlap only through the wrap
     ch2 = W.chamber(40, 40, 10, 2e-4, 10 * 2e-4, 20.0)

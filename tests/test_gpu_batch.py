@@ -38,10 +38,10 @@ def small_sweep(n=7, seed=5):
     return chs, trs
 
 
-@pytest.mark.parametrize("tile_y", [8, 16])
-def test_batch_matches_oracle_per_instance(gpu, orc, tile_y):
+@pytest.mark.parametrize("shape", [dict(tile_y=8), dict(tile_y=16), dict(tile_x=32)], ids=["64x8", "64x16", "32x16"])
+def test_batch_matches_oracle_per_instance(gpu, orc, shape):
     chs, trs = small_sweep()
-    res = gpu.it_solve_batch(chs, trs, exec=dict(tile_y=tile_y, check_every=6))
+    res = gpu.it_solve_batch(chs, trs, exec=dict(shape, check_every=6))
     for ch, tr, g in zip(chs, trs, res):
         o = orc.solve(ch, tr, with_fields=False)
         assert g["steps"] == o["steps"] and g["flags"] == o["flags"]

@@ -17,9 +17,11 @@ RTOL = 1e-9
 
 # every stepping kernel the library offers: the one-step kernel with both
 # tile shapes, and the temporally blocked kernel at each supported depth
-EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5)] + \
+EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5),
+         dict(kernel=1, tile_x=32), dict(kernel=1, tile_x=32, z_chunk=6)] + \
     [dict(kernel=2, steps_per_pass=T) for T in (2, 3, 4, 5)]
-EXEC_IDS = ["plain8", "plain16", "plain8z5", "blocked2", "blocked3", "blocked4", "blocked5"]
+EXEC_IDS = ["plain8", "plain16", "plain8z5", "plain32x16", "plain32x16z6", "blocked2", "blocked3", "blocked4",
+            "blocked5"]
 
 
 @pytest.fixture(scope="module")
@@ -93,8 +95,9 @@ def test_single_track_full_run(gpu, orc, ex):
     assert o["flags"] == 0 and 0.1 < o["f"] < 0.3
 
 
-SC_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16, z_chunk=6), dict(kernel=2, steps_per_pass=3)]
-SC_IDS = ["plain8", "plain16z6", "blocked3"]
+SC_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16, z_chunk=6), dict(kernel=1, tile_x=32),
+            dict(kernel=2, steps_per_pass=3)]
+SC_IDS = ["plain8", "plain16z6", "plain32x16", "blocked3"]
 
 
 @pytest.mark.parametrize("ex", SC_EXECS, ids=SC_IDS)
@@ -306,8 +309,9 @@ def test_advance_from_given_fields(gpu, orc, ex):
 
 # absorbing lateral boundaries: the one-step kernel (both tile shapes, short
 # z chunks); tracks next to the edges and corners so that charge escapes
-AB_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5)]
-AB_IDS = ["plain8", "plain16", "plain8z5"]
+AB_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5),
+            dict(kernel=1, tile_x=32)]
+AB_IDS = ["plain8", "plain16", "plain8z5", "plain32x16"]
 
 
 @pytest.mark.parametrize("ex", AB_EXECS, ids=AB_IDS)
