@@ -154,7 +154,6 @@ hipError_t launch_step3(const Step3Params& p, hipStream_t s);
 // per row).
 inline int plain_tile_cols(int tile_x) { return tile_x == 32 ? 32 : 64; }
 int plain_tile_rows(int tile_y, int tile_x);
-int plain_tile_waves(int tile_y, int tile_x);
 // ev_begin / ev_end (may be null) are recorded around the stepping kernel
 // alone, before the tally reduction is launched.
 // fused: leave this step's partials to the next launch's extra block (or a

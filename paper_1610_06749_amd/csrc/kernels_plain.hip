@@ -59,7 +59,6 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
 }
 
 int plain_tile_rows(int tile_y, int tile_x) { return tile_x == 32 || tile_y == 16 ? 16 : 8; }
-int plain_tile_waves(int tile_y, int tile_x) { return plain_tile_rows(tile_y, tile_x) * plain_tile_cols(tile_x) / kTX; }
 
 namespace {
 
