@@ -1,0 +1,27 @@
+"""The benchmark's command-line contract that needs no GPU: one GPU only."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    line = json.loads(p.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"] and line["n_gpus"] == 2
+
+
+def test_traffic_summary_lookup(tmp_path):
+    """The roofline's traffic figure is read only when the summary was taken
+    on the same kernel sources and launch shape."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = ["kernels_plain.hip", "stencil_plain.h", "reduce.h", "internal.h"]
+    h = bench.kernel_source_hash(src)
+    assert len(h) == 16
+    assert bench.read_traffic("step_plain", "pulsed_256x256x200", "0" * 16, "tile_y 8 z_chunk 0") is None
+    assert bench.read_traffic("step_plain", "no_such_workload", h, "tile_y 8 z_chunk 0") is None
