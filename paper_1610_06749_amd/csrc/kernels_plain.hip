@@ -2,8 +2,10 @@
 //
 // Step kernel: one explicit time step of both ion species (eq. theEquation
 // with the Appendix's difference scheme, written as per-node coefficients),
-// plus the per-step tallies.  Each block (8 or 16 waves) owns a 64 x 8 or
-// 64 x 16 column tile and a chunk of planes and marches up it: every thread
+// plus the per-step tallies.  Each block (8 or 16 waves) owns a 64 x 8,
+// 64 x 16 or 32 x 16 column tile and a chunk of planes and marches up it
+// (plain_tile_step); with one step per launch an extra block records the
+// previous step from its partials.  Every thread
 // keeps n_{k-1}, n_k, n_{k+1} of its column in registers, the block stages
 // plane k of the tile in LDS for the lateral neighbours, and neighbours
 // outside the tile (its one-node rim, or a periodic wrap) are read from

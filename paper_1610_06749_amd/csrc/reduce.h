@@ -58,7 +58,8 @@ __device__ inline void block_sum_store(double (&acc)[N], double* out, double* ld
 // Returns true in exactly one block: the last to arrive.  That block then
 // sees every other block's partials.  (Used only by the rare deposit launch:
 // the device-scope fence of every block costs an L2 write-back, so the
-// stepping kernels hand their partials to a separate reduction launch.)
+// stepping kernels leave their partials to the next launch, whose kernel
+// boundary makes them visible.)
 template <int NT>
 __device__ inline bool arrive_last(unsigned* counter) {
   __shared__ int last;

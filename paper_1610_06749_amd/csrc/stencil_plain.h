@@ -39,8 +39,8 @@ struct PlaneRegs {
 //
 // Pipelining: plane k+2 of the own column and the rim of plane k+1 are
 // requested while plane k is computed, so two planes of loads are in flight
-// per thread (about 78 VGPRs: six waves per SIMD, more than the 16 waves per
-// CU the default tiling places).  The LDS plane is double-buffered, so one barrier per plane
+// per thread (70 VGPRs without the optional terms: seven waves per SIMD, more
+// than the 16 waves per CU the default tiling places).  The LDS plane is double-buffered, so one barrier per plane
 // suffices: buffer k&1 is rewritten at plane k+2, after every thread has
 // passed the barrier of plane k+1 and hence finished reading plane k.  The
 // barrier orders LDS only; it does not wait for the global loads in flight.
