@@ -3,13 +3,14 @@
 Times every candidate execution choice on the caller's grid and keeps the
 fastest per voxel-step:
 
-* single chambers (``tune``): the plain kernel with 8- or 16-row tiles and
-  the temporally blocked kernel at each depth T, each timed over whole passes
+* single chambers (``tune``): the plain kernel with 64 x 8, 64 x 16 or
+  32 x 16 tiles and the temporally blocked kernel at each depth T, each timed
+  over whole passes
   (the stepping kernel plus its tally reduction) on a perturbed field of the
   chamber's shape;
-* batched sweeps (``tune_batch``): the tile rows of the batched kernel and
-  the passes per captured graph, each timed on the batch itself with the
-  step count capped.
+* batched sweeps (``tune_batch``): the tile shape and planes per tile of the
+  batched kernel and the passes per captured graph, each timed on the batch
+  itself with the step count capped.
 
 Results are cached per (grid, device) in memory and, when a path is given,
 in a JSON file, so one tuning serves every later run of that shape.
@@ -25,7 +26,8 @@ import numpy as np
 
 from . import binding as B
 
-PLAIN = [dict(kernel=B.IT_KERNEL_PLAIN, tile_y=8), dict(kernel=B.IT_KERNEL_PLAIN, tile_y=16)]
+PLAIN = [dict(kernel=B.IT_KERNEL_PLAIN, tile_y=8), dict(kernel=B.IT_KERNEL_PLAIN, tile_y=16),
+         dict(kernel=B.IT_KERNEL_PLAIN, tile_x=32)]
 BLOCKED = [dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=T) for T in (2, 3, 4, 5)]
 
 _memo: dict = {}
@@ -119,10 +121,11 @@ def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
 
 
 def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), z_chunks=(8, 16, 32),
-               cache=None, verbose=False):
-    """Best ``exec`` for it_solve_batch on these chambers: tile rows, planes
-    per tile and the passes per captured graph, each timed on the batch with
-    every instance's step count capped at ``steps``."""
+               narrow=True, cache=None, verbose=False):
+    """Best ``exec`` for it_solve_batch on these chambers: tile shape (64
+    columns by each of ``rows``, and 32 x 16 when ``narrow``), planes per tile
+    and the passes per captured graph, each timed on the batch with every
+    instance's step count capped at ``steps``."""
     import torch
     sig = "|".join(f"{c['nx']}x{c['ny']}x{c['nz']}" for c in chs)
     key = f"batch:{len(chs)}:{hashlib.sha256(sig.encode()).hexdigest()[:12]}@{_device_name()}"
@@ -135,8 +138,9 @@ def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), z_ch
     capped = [dict(c, max_steps=steps) for c in chs]
     vs = sum(c["nx"] * c["ny"] * (c["nz"] - 1) for c in chs) * steps
     timings = []
-    for r, g, z in ((r, g, z) for r in rows for g in graph_passes for z in z_chunks):
-        ex = dict(kernel=B.IT_KERNEL_PLAIN, tile_y=r, check_every=g, z_chunk=z)
+    shapes = [dict(tile_y=r, tile_x=64) for r in rows] + ([dict(tile_y=16, tile_x=32)] if narrow else [])
+    for shape, g, z in ((sh, g, z) for sh in shapes for g in graph_passes for z in z_chunks):
+        ex = dict(kernel=B.IT_KERNEL_PLAIN, check_every=g, z_chunk=z, **shape)
         B.it_solve_batch(capped, trs, exec=ex)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -62,7 +62,11 @@ def test_tune_batch_returns_a_working_shape(gpu, tuner, tmp_path):
     trs = [W.tracks([[20.0, 1e-3, 0.5 * c["nx"] * 5e-4, 0.5 * c["ny"] * 5e-4, 0.0, 0.0, 0.0]]) for c in chs]
     ex = tuner.tune_batch(chs, trs, steps=24, rows=(8, 16), graph_passes=(4, 8), z_chunks=(8,),
                           cache=str(tmp_path / "tb.json"))
-    assert ex["tile_y"] in (8, 16) and ex["check_every"] in (4, 8) and ex["z_chunk"] == 8
+    assert (ex["tile_x"], ex["tile_y"]) in ((64, 8), (64, 16), (32, 16))
+    assert ex["check_every"] in (4, 8) and ex["z_chunk"] == 8
+    table = __import__("json").load(open(str(tmp_path / "tb.json")))
+    (entry,) = table.values()
+    assert len(entry["all"]) == 3 * 2  # shapes x passes per graph
     a = gpu.it_solve_batch(chs, trs, exec=ex)
     b = gpu.it_solve_batch(chs, trs)
     for ra, rb in zip(a, b):
