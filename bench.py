@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 96-chamber sweep")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
     ap.add_argument("--surrogate-train", type=int, default=32768, help="surrogate training samples")
-    ap.add_argument("--surrogate-steps", type=int, default=300000, help="surrogate training steps")
+    ap.add_argument("--surrogate-steps", type=int, default=600000, help="surrogate training steps")
     ap.add_argument("--continuous-ms", type=float, default=0.4,
                     help="beam-on time of the continuous-beam run (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",

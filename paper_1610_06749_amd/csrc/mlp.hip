@@ -126,24 +126,62 @@ TrainWs carve_train(void* base, int M, int64_t n) {
 // f_J = (y1/y2) e^{-y1} [Ei(y1 + ln(1+y2)) - Ei(y1)], written as
 // (y1/y2) int_0^{ln(1 + ln(1+y2)/y1)} exp(y1 (e^w - 1)) dw (no overflow for
 // large y1), y1 = 8 pi D/(alpha N0), y2 = 2 d D/(mu b^2 E), N0 = LET/W, and
-// f_B = ln(1+u)/u with u = alpha/(mu+ + mu-) n0 d^2/V.
-__device__ double baseline(const Header& H, const float* x) {
-  const double let = x[0], b = x[1], V = x[2], d = x[3], dose = x[4];
+// f_B = ln(1+u)/u with u = alpha/(mu+ + mu-) n0 d^2/V.  The quadrature is
+// summed in four parts of kGL/4 nodes (added in order), so that four
+// threads can share a query.
+struct BaseArgs {
+  double y1, y2, upper;
+};
+
+__device__ inline BaseArgs base_args(const Header& H, const float* x) {
+  const double let = x[0], b = x[1], V = x[2], d = x[3];
   const double E = V / d;
   const double N0 = let * 1.0e7 / H.W;
-  const double y1 = 8.0 * M_PI * H.D / (H.alpha * N0);
-  const double y2 = 2.0 * d * H.D / (H.mu_avg * b * b * E);
-  const double upper = log1p(log1p(y2) / y1);
-  double integral = 0.0;
-  for (int q = 0; q < kGL; ++q) {
-    const double w = 0.5 * upper * (H.gl_x[q] + 1.0);
-    integral += H.gl_w[q] * exp(y1 * expm1(w));
+  BaseArgs a;
+  a.y1 = 8.0 * M_PI * H.D / (H.alpha * N0);
+  a.y2 = 2.0 * d * H.D / (H.mu_avg * b * b * E);
+  a.upper = log1p(log1p(a.y2) / a.y1);
+  return a;
+}
+
+__device__ inline double base_part(const Header& H, const BaseArgs& a, int part) {
+  double s = 0.0;
+  for (int q = part * (kGL / 4); q < (part + 1) * (kGL / 4); ++q) {
+    const double w = 0.5 * a.upper * (H.gl_x[q] + 1.0);
+    s += H.gl_w[q] * exp(a.y1 * expm1(w));
   }
-  integral *= 0.5 * upper;
-  const double fJ = y1 / y2 * integral;
+  return s;
+}
+
+__device__ inline double base_finish(const Header& H, const float* x, const BaseArgs& a, double sum) {
+  const double V = x[2], d = x[3], dose = x[4];
+  const double fJ = a.y1 / a.y2 * (sum * 0.5 * a.upper);
   const double u = H.alpha / H.mu_sum * dose * H.pairs_per_mGy * d * d / V;
   const double fB = u > 0.0 ? log1p(u) / u : 1.0;
   return -log(fJ) - log(fB);
+}
+
+__device__ double baseline(const Header& H, const float* x) {
+  const BaseArgs a = base_args(H, x);
+  const double p0 = base_part(H, a, 0), p1 = base_part(H, a, 1), p2 = base_part(H, a, 2), p3 = base_part(H, a, 3);
+  return base_finish(H, x, a, ((p0 + p1) + p2) + p3);
+}
+
+// Baseline of the 64 samples of a tile with all 256 threads: wave p sums
+// quadrature part p of sample s0 + lane into part[p][lane]; after a barrier
+// thread s < 64 calls base_of.
+__device__ inline void base_parts(const Header& H, const float* __restrict__ X, int64_t n, int64_t s0,
+                                  double (*part)[kTileS]) {
+  const int p = threadIdx.x / 64, s = threadIdx.x % 64;
+  const int64_t gs = s0 + s;
+  part[p][s] = H.use_baseline && gs < n ? base_part(H, base_args(H, X + gs * kIn), p) : 0.0;
+}
+
+__device__ inline double base_of(const Header& H, const float* __restrict__ X, int64_t gs,
+                                 const double (*part)[kTileS], int s) {
+  if (!H.use_baseline) return 0.0;
+  const float* x = X + gs * kIn;
+  return base_finish(H, x, base_args(H, x), ((part[0][s] + part[1][s]) + part[2][s]) + part[3][s]);
 }
 
 __device__ inline unsigned short to_bf16(float f) {  // round to nearest even
@@ -158,92 +196,317 @@ __device__ inline float dsilu(float a) {
   return s * (1.0f + a * (1.0f - s));
 }
 
-// Hidden activations as the next layer reads them: BF16 bits or FP32.
-template <bool F32>
-struct ActT {
-  typedef unsigned short type;
-  static __device__ inline type put(float v) { return to_bf16(v); }
-  static __device__ inline float get(type h) { return from_bf16(h); }
-};
-template <>
-struct ActT<true> {
-  typedef float type;
-  static __device__ inline type put(float v) { return v; }
-  static __device__ inline float get(type h) { return h; }
-};
-
-// Weight q of a member as the forward pass uses it.
-template <bool F32>
-__device__ inline float weight(const float* __restrict__ master, const unsigned short* __restrict__ w, int q) {
-  return F32 ? master[q] : from_bf16(w[q]);
-}
-
 struct ForwardOut {  // optional stores of the training forward (member slices)
   float *z, *a1, *a2, *a3, *h1, *h2, *h3, *y;
 };
 
-// Layers 2 and 3 in FP32 (v_mfma_f32_16x16x4_f32, A[i][k]: lane i + 16 k,
-// B[k][j]: lane j + 16 k, D[i][j]: lane j + 16 (i/4), item i % 4).  Wave w
-// owns samples 16w..16w+15; each pass computes four 16-wide output tiles,
-// sharing the activation operand, with the 128 inputs taken 4 at a time in
-// increasing order.  act[0] holds h1 on entry and h3 on return.
-template <bool STORE>
-__device__ void mlp_layers_f32(const float* __restrict__ master, float (*act)[kTileS][kActStride], int64_t n,
-                               int64_t s0, const ForwardOut& st) {
+// ---------------------------------------------------------------------------
+// FP32 models.  Every kernel runs 256 threads on a tile of 64 samples of one
+// member; wave w owns samples 16w..16w+15 of the tile.  The 128 x 128
+// weights of a layer are staged in LDS (wl[o][i], rows padded to kWS), read
+// from global memory into registers one layer ahead (64 values per thread,
+// element tid + 256 u of the matrix), so that their latency hides behind the
+// previous layer.  Products run on v_mfma_f32_16x16x4f32 (A[i][k]: lane
+// i + 16 k, B[k][j]: lane j + 16 k, D[i][j]: lane j + 16 (i/4), item i % 4),
+// four 16-wide output tiles per pass sharing the A operand, k taken 4 at a
+// time in increasing order.  Every per-element value a thread computes sits
+// at (sample 16w + 4 (lane/16) + v, unit 16 t + lane % 16), v = 0..3, t =
+// 0..7, the D layout, in every layer: so the pre-activations a thread
+// stores in the forward pass are read back, in the backward pass, by that
+// same thread.
+constexpr int kWS = kH + 4;
+
+// The small parameters of a member (W1 and b1, b2, b3, w4, b4), staged in
+// LDS once per tile: three contiguous runs of the parameter vector.
+struct SmallP {
+  float w1b1[kH * kIn + kH];  // W1 [128][6], then b1
+  float b2[kH];
+  float b3w4b4[2 * kH + 1];   // b3, w4, b4
+};
+
+__device__ inline void sload(const float* __restrict__ master, SmallP& sp) {
   const int tid = threadIdx.x;
-  const int wave = tid / 64, lane = tid % 64;
-  const int arow = wave * 16 + (lane & 15);  // A: sample row of this lane
-  const int kq = lane >> 4;                  // A/B: k within the 4-wide step
-  constexpr int kNT = 4;                     // output tiles per pass
 #pragma unroll
-  for (int layer = 0; layer < 2; ++layer) {
-    const int oW = layer == 0 ? oW2 : oW3, ob = layer == 0 ? ob2 : ob3;
-    const float (*in)[kActStride] = act[layer];
-    float (*out)[kActStride] = act[1 - layer];
-    float* sa = layer == 0 ? st.a2 : st.a3;
-    float* sh = layer == 0 ? st.h2 : st.h3;
-#pragma unroll 1
-    for (int nt0 = 0; nt0 < kH / 16; nt0 += kNT) {
-      float4_t acc[kNT];
+  for (int u = 0; u < 4; ++u) {
+    const int q = tid + 256 * u;
+    if (q < kH * kIn + kH) sp.w1b1[q] = master[oW1 + q];
+  }
+  if (tid < kH) sp.b2[tid] = master[ob2 + tid];
 #pragma unroll
-      for (int u = 0; u < kNT; ++u) acc[u] = {0.0f, 0.0f, 0.0f, 0.0f};
-      const float* wr = master + oW + (nt0 * 16 + (lane & 15)) * kH + kq;  // B: row of output column
-#pragma unroll 8
-      for (int kk = 0; kk < kH / 4; ++kk) {
-        const float a = in[arow][4 * kk + kq];
-#pragma unroll
-        for (int u = 0; u < kNT; ++u)
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wr[u * 16 * kH + 4 * kk], acc[u], 0, 0, 0);
-      }
-#pragma unroll
-      for (int u = 0; u < kNT; ++u) {
-        const int bo = (nt0 + u) * 16 + (lane & 15);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int s = wave * 16 + 4 * (lane >> 4) + v;
-          const float a = acc[u][v] + master[ob + bo];
-          const float h = silu(a);
-          out[s][bo] = h;
-          const int64_t gs = s0 + s;
-          if (STORE && gs < n) {
-            sa[gs * kH + bo] = a;
-            sh[gs * kH + bo] = h;
-          }
-        }
-      }
-    }
-    __syncthreads();
+  for (int u = 0; u < 2; ++u) {
+    const int q = tid + 256 * u;
+    if (q < 2 * kH + 1) sp.b3w4b4[q] = master[ob3 + q];
   }
 }
 
+struct WRegs {
+  float v[64];
+};
+
+__device__ inline void wload(WRegs& r, const float* __restrict__ W) {
+#pragma unroll
+  for (int u = 0; u < 64; ++u) r.v[u] = W[threadIdx.x + 256 * u];
+}
+
+__device__ inline void wstore(const WRegs& r, float (*wl)[kWS]) {
+#pragma unroll
+  for (int u = 0; u < 64; ++u) {
+    const int q = threadIdx.x + 256 * u;
+    wl[q / kH][q % kH] = r.v[u];
+  }
+}
+
+// acc[u] += in[16w + i][k] * B[k][16 (t0 + u) + j] over k = 0..127, with
+// B[k][j] = wl[j][k] (forward: out = in W^T) or wl[k][j] (backward:
+// out = in W).
+template <bool BWD>
+__device__ inline void mfma_pass(const float (*in)[kActStride], const float (*wl)[kWS], int t0, float4_t* acc) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int arow = wave * 16 + (lane & 15), kq = lane >> 4, j = lane & 15;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+  for (int kk = 0; kk < kH / 4; ++kk) {
+    const int k = 4 * kk + kq;
+    const float a = in[arow][k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = (t0 + u) * 16 + j;
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, BWD ? wl[k][c] : wl[c][k], acc[u], 0, 0, 0);
+    }
+  }
+}
+
+// Hidden layer 2 or 3: out = silu(in W^T + b), optional stores of the
+// pre-activations and activations.  Ends with a barrier.
+template <bool STORE>
+__device__ void layer_fwd_f32(const float (*in)[kActStride], float (*out)[kActStride], const float (*wl)[kWS],
+                              const float* __restrict__ bias, int64_t n, int64_t s0, float* sa, float* sh) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll 1
+  for (int t0 = 0; t0 < kH / 16; t0 += 4) {
+    float4_t acc[4];
+    mfma_pass<false>(in, wl, t0, acc);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = (t0 + u) * 16 + (lane & 15);
+      const float b = bias[o];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = wave * 16 + 4 * (lane >> 4) + v;
+        const float a = acc[u][v] + b;
+        const float h = silu(a);
+        out[s][o] = h;
+        const int64_t gs = s0 + s;
+        if (STORE && gs < n) {
+          sa[gs * kH + o] = a;
+          sh[gs * kH + o] = h;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Backward through a hidden layer: dprev = (d W) * silu'(a_prev), where
+// a_prev are the pre-activations this thread stored in the forward pass
+// (read before the pass's products, so that the loads overlap them).
+// Optional LDS copy (the next layer's input); stores for the weight
+// gradients.  Ends with a barrier.
+__device__ void layer_bwd_f32(const float (*d)[kActStride], float (*dout)[kActStride], const float (*wl)[kWS],
+                              const float* apre, int64_t n, int64_t s0, float* dstore) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll 1
+  for (int t0 = 0; t0 < kH / 16; t0 += 4) {
+    float ap[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gs = s0 + wave * 16 + 4 * (lane >> 4) + v;
+        ap[u][v] = gs < n ? apre[gs * kH + (t0 + u) * 16 + (lane & 15)] : 0.0f;
+      }
+    float4_t acc[4];
+    mfma_pass<true>(d, wl, t0, acc);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = (t0 + u) * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = wave * 16 + 4 * (lane >> 4) + v;
+        const int64_t gs = s0 + s;
+        float dv = 0.0f;
+        if (gs < n) {
+          dv = acc[u][v] * dsilu(ap[u][v]);
+          dstore[gs * kH + o] = dv;
+        }
+        if (dout) dout[s][o] = dv;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Forward pass of one FP32 member over samples [s0, s0 + 64).  On entry
+// `pf` holds (or is loading) this member's W2; on return it is loading
+// `next` (when not null).  Leaves the standardised outputs in ys[64] and h3
+// in act[0].
+template <bool STORE>
+__device__ void forward_tile_f32(const Header& H, const float* __restrict__ master, const float* __restrict__ X,
+                                 int64_t n, int64_t s0, float* zs, float (*act)[kTileS][kActStride],
+                                 float (*wl)[kWS], SmallP& sp, float (*yp)[kTileS], float* ys, WRegs& pf,
+                                 const float* next, const ForwardOut& st) {
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  sload(master, sp);  // its last readers passed a barrier
+  // standardised inputs
+  for (int q = tid; q < kTileS * kIn; q += 256) {
+    const int s = q / kIn, i = q % kIn;
+    const int64_t gs = s0 + s;
+    float zv = 0.0f;
+    if (gs < n) zv = (logf(X[gs * kIn + i]) - H.mu[i]) / H.sigma[i];
+    zs[q] = zv;
+    if (STORE && gs < n) st.z[gs * kIn + i] = zv;
+  }
+  __syncthreads();
+  // layer 1 (FP32 FMAs, D layout)
+#pragma unroll 2
+  for (int t = 0; t < kH / 16; ++t) {
+    const int o = t * 16 + (lane & 15);
+    float w1[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) w1[i] = sp.w1b1[o * kIn + i];
+    const float b = sp.w1b1[kH * kIn + o];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = wave * 16 + 4 * (lane >> 4) + v;
+      float a = b;
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) a += w1[i] * zs[s * kIn + i];
+      const float h = silu(a);
+      act[0][s][o] = h;
+      const int64_t gs = s0 + s;
+      if (STORE && gs < n) {
+        st.a1[gs * kH + o] = a;
+        st.h1[gs * kH + o] = h;
+      }
+    }
+  }
+  wstore(pf, wl);  // W2 (wl's last readers passed a barrier)
+  __syncthreads();
+  wload(pf, master + oW3);
+  layer_fwd_f32<STORE>(act[0], act[1], wl, sp.b2, n, s0, st.a2, st.h2);
+  wstore(pf, wl);  // W3
+  __syncthreads();
+  if (next) wload(pf, next);
+  layer_fwd_f32<STORE>(act[1], act[0], wl, sp.b3w4b4, n, s0, st.a3, st.h3);
+  // output layer: four partial dot products of 32 terms per sample
+  {
+    const int s = lane, p = wave;
+    float y = 0.0f;
+#pragma unroll 8
+    for (int i = 32 * p; i < 32 * p + 32; ++i) y += sp.b3w4b4[kH + i] * act[0][s][i];
+    yp[p][s] = y;
+  }
+  __syncthreads();
+  if (tid < kTileS) {
+    const float y = sp.b3w4b4[2 * kH] + (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]);
+    ys[tid] = y;
+    const int64_t gs = s0 + tid;
+    if (STORE && gs < n) st.y[gs] = y;
+  }
+  __syncthreads();
+}
+
+// One FP32 training step's per-sample work for a tile of 64 samples of one
+// member: the forward pass (storing what the weight gradients need), the
+// loss gradient dy = 2 (y - t_std) / n, and the pre-activation gradients of
+// the three hidden layers.  The baseline of each sample is written by the
+// member-0 blocks (the loss kernel reads it).
+__global__ __launch_bounds__(256) void train_tile_f32_kernel(Model md, const float* __restrict__ X,
+                                                             const float* __restrict__ t, int64_t n, TrainWs ws) {
+  __shared__ float zs[kTileS * kIn];
+  __shared__ float act[2][kTileS][kActStride];
+  __shared__ float wl[kH][kWS];
+  __shared__ SmallP sp;
+  __shared__ float yp[4][kTileS];
+  __shared__ float ys[kTileS], dys[kTileS];
+  __shared__ double bp[4][kTileS];
+  const Header& H = *md.hdr;
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int m = blockIdx.y;
+  const int64_t s0 = (int64_t)blockIdx.x * kTileS;
+  const float* master = md.master + (size_t)m * kP;
+  const size_t nh = (size_t)n * kH;
+  const ForwardOut st{ws.z + (size_t)m * n * kIn, ws.a1 + m * nh, ws.a2 + m * nh, ws.a3 + m * nh,
+                      ws.h1 + m * nh, ws.h2 + m * nh, ws.h3 + m * nh, ws.y + (size_t)m * n};
+  WRegs pf;
+  wload(pf, master + oW2);
+  // the baseline and target of each sample, while W2 is on its way
+  base_parts(H, X, n, s0, bp);
+  __syncthreads();
+  const int64_t gt = s0 + tid;
+  float ty = 0.0f;
+  if (tid < kTileS && gt < n) {
+    const float base = (float)base_of(H, X, gt, bp, tid);
+    if (m == 0) ws.base[gt] = base;
+    ty = (t[gt] - base - H.t_mu) / H.t_sigma;
+  }
+  forward_tile_f32<true>(H, master, X, n, s0, zs, act, wl, sp, yp, ys, pf, master + oW2, st);
+  if (tid < kTileS) {
+    float dy = 0.0f;
+    if (gt < n) {
+      dy = 2.0f * (ys[tid] - ty) / (float)n;
+      ws.dy[(size_t)m * n + gt] = dy;
+    }
+    dys[tid] = dy;
+  }
+  __syncthreads();
+  // d3 = dy w4 silu'(a3) -> act[1]; the pre-activations are read first
+  float* d3 = ws.d3 + m * nh;
+  float a3[kH / 16][4];
+#pragma unroll
+  for (int tt = 0; tt < kH / 16; ++tt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gs = s0 + wave * 16 + 4 * (lane >> 4) + v;
+      a3[tt][v] = gs < n ? st.a3[gs * kH + tt * 16 + (lane & 15)] : 0.0f;
+    }
+#pragma unroll
+  for (int tt = 0; tt < kH / 16; ++tt) {
+    const int o = tt * 16 + (lane & 15);
+    const float w4 = sp.b3w4b4[kH + o];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = wave * 16 + 4 * (lane >> 4) + v;
+      const int64_t gs = s0 + s;
+      float dv = 0.0f;
+      if (gs < n) {
+        dv = dys[s] * w4 * dsilu(a3[tt][v]);
+        d3[gs * kH + o] = dv;
+      }
+      act[1][s][o] = dv;
+    }
+  }
+  __syncthreads();
+  layer_bwd_f32(act[1], act[0], wl, st.a2, n, s0, ws.d2 + m * nh);  // wl holds W3
+  wstore(pf, wl);                                                   // W2
+  __syncthreads();
+  layer_bwd_f32(act[0], nullptr, wl, st.a1, n, s0, ws.d1 + m * nh);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 models: hidden activations rounded to BF16 before the next layer,
+// the 128 x 128 layers on v_mfma_f32_16x16x16_bf16.
+//
 // Forward pass of one member over samples [s0, s0 + 64) (256 threads).
 // Leaves the standardised outputs in ys[64] (LDS).
-template <bool STORE, bool F32>
-__device__ void forward_tile(const Header& H, const float* __restrict__ master,
-                             const unsigned short* __restrict__ w, const float* __restrict__ X, int64_t n,
-                             int64_t s0, float* zs /*[64][6]*/,
-                             typename ActT<F32>::type (*act)[kTileS][kActStride], float* ys, const ForwardOut& st) {
-  typedef ActT<F32> A;
+template <bool STORE>
+__device__ void forward_tile_bf16(const Header& H, const float* __restrict__ master,
+                                  const unsigned short* __restrict__ w, const float* __restrict__ X, int64_t n,
+                                  int64_t s0, float* zs /*[64][6]*/, unsigned short (*act)[kTileS][kActStride],
+                                  float* ys, const ForwardOut& st) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   // standardised inputs
@@ -256,25 +519,22 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
     if (STORE && gs < n) st.z[gs * kIn + i] = zv;
   }
   __syncthreads();
-  // layer 1 (FP32 arithmetic)
+  // layer 1 (FP32 arithmetic on the BF16 weights)
   for (int q = tid; q < kTileS * kH; q += 256) {
     const int s = q / kH, o = q % kH;
     float a = master[ob1 + o];
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) a += weight<F32>(master, w, oW1 + o * kIn + i) * zs[s * kIn + i];
-    const typename A::type h = A::put(silu(a));
+    for (int i = 0; i < kIn; ++i) a += from_bf16(w[oW1 + o * kIn + i]) * zs[s * kIn + i];
+    const unsigned short h = to_bf16(silu(a));
     act[0][s][o] = h;
     const int64_t gs = s0 + s;
     if (STORE && gs < n) {
       st.a1[gs * kH + o] = a;
-      st.h1[gs * kH + o] = A::get(h);
+      st.h1[gs * kH + o] = from_bf16(h);
     }
   }
   __syncthreads();
-  if constexpr (F32) {  // layers 2 and 3 on FP32 MFMA
-    mlp_layers_f32<STORE>(master, act, n, s0, st);
-  } else {
-  // layers 2 and 3 on BF16 MFMA: wave w owns samples 16w..16w+15
+  // layers 2 and 3: wave w owns samples 16w..16w+15
 #pragma unroll
   for (int layer = 0; layer < 2; ++layer) {
     const int oW = layer == 0 ? oW2 : oW3, ob = layer == 0 ? ob2 : ob3;
@@ -319,11 +579,10 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
     }
     __syncthreads();
   }
-  }
   // output layer (FP32 dot); act[0] holds h3
   if (tid < kTileS) {
     float y = master[ob4];
-    for (int i = 0; i < kH; ++i) y += weight<F32>(master, w, ow4 + i) * A::get(act[0][tid][i]);
+    for (int i = 0; i < kH; ++i) y += from_bf16(w[ow4 + i]) * from_bf16(act[0][tid][i]);
     ys[tid] = y;
     const int64_t gs = s0 + tid;
     if (STORE && gs < n) st.y[gs] = y;
@@ -331,55 +590,54 @@ __device__ void forward_tile(const Header& H, const float* __restrict__ master,
   __syncthreads();
 }
 
-template <bool F32>
-__global__ __launch_bounds__(256) void forward_train_kernel(Model md, const float* X, int64_t n, TrainWs ws) {
+__global__ __launch_bounds__(256) void forward_train_bf16_kernel(Model md, const float* X, int64_t n, TrainWs ws) {
   if (blockIdx.y == 0 && threadIdx.x < kTileS) {  // baseline of each sample (member independent)
     const int64_t gs = (int64_t)blockIdx.x * kTileS + threadIdx.x;
     if (gs < n) ws.base[gs] = md.hdr->use_baseline ? (float)baseline(*md.hdr, X + gs * kIn) : 0.0f;
   }
   __shared__ float zs[kTileS * kIn];
-  __shared__ typename ActT<F32>::type act[2][kTileS][kActStride];
+  __shared__ unsigned short act[2][kTileS][kActStride];
   __shared__ float ys[kTileS];
   const int m = blockIdx.y;
   const size_t nh = (size_t)n * kH;
   ForwardOut st{ws.z + (size_t)m * n * kIn, ws.a1 + m * nh, ws.a2 + m * nh, ws.a3 + m * nh,
                 ws.h1 + m * nh, ws.h2 + m * nh, ws.h3 + m * nh, ws.y + (size_t)m * n};
-  forward_tile<true, F32>(*md.hdr, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n,
-                     (int64_t)blockIdx.x * kTileS, zs, act, ys, st);
+  forward_tile_bf16<true>(*md.hdr, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n,
+                          (int64_t)blockIdx.x * kTileS, zs, act, ys, st);
 }
 
-// Per-sample deltas: dy = 2 (y - t)/n, then the pre-activation gradients of
-// the three hidden layers (block of 128 threads = hidden units).
-template <bool F32>
-__global__ __launch_bounds__(128) void delta_kernel(Model md, const float* t, int64_t n, TrainWs ws) {
+// Per-sample deltas of a BF16 model: dy = 2 (y - t)/n, then the
+// pre-activation gradients of the three hidden layers (block of 128
+// threads = hidden units; the casts pass gradients straight through).
+__global__ __launch_bounds__(128) void delta_bf16_kernel(Model md, const float* t, int64_t n, TrainWs ws) {
   __shared__ float d[kH];
   const int m = blockIdx.y, o = threadIdx.x;
   const int64_t s = blockIdx.x;
   const size_t nh = (size_t)n * kH, row = m * nh + (size_t)s * kH;
   const unsigned short* w = md.w + (size_t)m * kPpad;
-  const float* master = md.master + (size_t)m * kP;
   const float ty = (t[s] - ws.base[s] - md.hdr->t_mu) / md.hdr->t_sigma;
   const float dy = 2.0f * (ws.y[(size_t)m * n + s] - ty) / (float)n;
   if (o == 0) ws.dy[(size_t)m * n + s] = dy;
-  float da = dy * weight<F32>(master, w, ow4 + o) * dsilu(ws.a3[row + o]);
+  float da = dy * from_bf16(w[ow4 + o]) * dsilu(ws.a3[row + o]);
   ws.d3[row + o] = da;
   d[o] = da;
   __syncthreads();
   float g = 0.0f;
-  for (int j = 0; j < kH; ++j) g += weight<F32>(master, w, oW3 + j * kH + o) * d[j];
+  for (int j = 0; j < kH; ++j) g += from_bf16(w[oW3 + j * kH + o]) * d[j];
   da = g * dsilu(ws.a2[row + o]);
   ws.d2[row + o] = da;
   __syncthreads();
   d[o] = da;
   __syncthreads();
   g = 0.0f;
-  for (int j = 0; j < kH; ++j) g += weight<F32>(master, w, oW2 + j * kH + o) * d[j];
+  for (int j = 0; j < kH; ++j) g += from_bf16(w[oW2 + j * kH + o]) * d[j];
   ws.d1[row + o] = g * dsilu(ws.a1[row + o]);
 }
 
+// ---------------------------------------------------------------------------
 // Weight gradients G[o][i] = sum_s delta[s][o] * in[s][i] (in[s][K] = 1
-// gives the bias), one 16 x 16 tile of (o, i) per block, samples in fixed
-// order through LDS: deterministic.
+// gives the bias) of the four layers, in one launch: block x of the grid
+// walks the jobs' 16 x 16 tiles of (o, i) in turn, block y is the member.
 struct GradJob {
   const float* delta;  // [n][rows_d]
   int rows_d;          // width of delta rows (128 or 1)
@@ -387,6 +645,12 @@ struct GradJob {
   int K;
   int nO;              // outputs (128 or 1)
   int w_off, b_off;    // parameter offsets of weights [nO][K] and bias [nO]
+  size_t delta_stride, in_stride;  // member strides
+  int tiles_x, first;  // tiles along i; first block of the job
+};
+
+struct GradJobs {
+  GradJob job[4];
 };
 
 // One 16 x 16 tile of G per block on FP32 MFMA (v_mfma_f32_16x16x4f32,
@@ -395,13 +659,18 @@ struct GradJob {
 // the column after the last input is 1 for the bias).  The block's 4 waves
 // take interleaved groups of 4 samples, sum them in fixed order through LDS:
 // deterministic.
-__global__ __launch_bounds__(256) void wgrad_kernel(GradJob job, int64_t n, size_t delta_stride,
-                                                    size_t in_stride, float* grad) {
+__global__ __launch_bounds__(256) void wgrad_kernel(GradJobs jobs, int64_t n, float* grad) {
   __shared__ float part[4][16][16];
-  const int m = blockIdx.z;
-  const float* __restrict__ delta = job.delta + m * delta_stride;
-  const float* __restrict__ in = job.in + m * in_stride;
-  const int o0 = blockIdx.y * 16, i0 = blockIdx.x * 16;
+  int jn = 0;
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if ((int)blockIdx.x >= jobs.job[q].first) jn = q;
+  const GradJob& job = jobs.job[jn];
+  const int m = blockIdx.y;
+  const float* __restrict__ delta = job.delta + m * job.delta_stride;
+  const float* __restrict__ in = job.in + m * job.in_stride;
+  const int tile = blockIdx.x - job.first;
+  const int o0 = (tile / job.tiles_x) * 16, i0 = (tile % job.tiles_x) * 16;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int r = lane & 15, k = lane >> 4;
   const int o = o0 + r, i = i0 + r;  // A row (output) and B column (input) of this lane
@@ -410,7 +679,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(GradJob job, int64_t n, size
   float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
   // samples sb + k with the wave-uniform base sb = 16 g + 4 wave, g = 0, 1,
   // ...: each MFMA takes 4 samples; loop bounds are uniform over the wave
-  constexpr int kU = 4;  // MFMAs per unrolled group (loads issued ahead)
+  constexpr int kU = 32;  // MFMAs per unrolled group (loads issued ahead)
   int64_t sb = 4 * wave;
   for (; sb + 16 * (kU - 1) + 3 < n; sb += 16 * kU) {
     float a[kU], b[kU];
@@ -433,7 +702,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(GradJob job, int64_t n, size
 #pragma unroll
   for (int v = 0; v < 4; ++v) part[wave][4 * k + v][r] = acc[v];  // D[4k + v][r]
   __syncthreads();
-  if (threadIdx.x < 256) {
+  {
     const int oo = threadIdx.x / 16, ii = threadIdx.x % 16;
     const float g = ((part[0][oo][ii] + part[1][oo][ii]) + part[2][oo][ii]) + part[3][oo][ii];
     const int og = o0 + oo, ig = i0 + ii;
@@ -444,7 +713,6 @@ __global__ __launch_bounds__(256) void wgrad_kernel(GradJob job, int64_t n, size
     }
   }
 }
-
 __global__ void adam_kernel(Model md, const float* grad, int M, float lr, int step) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)M * kP) return;
@@ -488,34 +756,18 @@ __global__ __launch_bounds__(1024) void loss_kernel(Model md, const float* t, in
 
 // Ensemble query: mean and spread (max - min) of ln k_s over the members,
 // out-of-box test of the standardised inputs, fallback flag and the number
-// of flagged queries per block.
-template <bool F32>
-__global__ __launch_bounds__(256) void query_kernel(Model md, const float* X, int64_t n, float spread_tol,
-                                                    float* mean, float* spread, unsigned char* fallback,
-                                                    int* block_count) {
-  __shared__ float zs[kTileS * kIn];
-  __shared__ typename ActT<F32>::type act[2][kTileS][kActStride];
-  __shared__ float ys[kTileS], ymin[kTileS], ymax[kTileS], ysum[kTileS];
-  __shared__ int cnt;
-  const Header& H = *md.hdr;
-  const int64_t s0 = (int64_t)blockIdx.x * kTileS;
+// of flagged queries per block.  Per tile of 64 queries, after the members'
+// forward passes (LDS ys, summed into ysum/ymin/ymax).
+__device__ inline void query_finish(const Header& H, const float* __restrict__ X, int64_t n, int64_t s0,
+                                    float spread_tol, const float* zs, float* ysum, float* ymin, float* ymax,
+                                    double (*bp)[kTileS], float* mean, float* spread, unsigned char* fallback,
+                                    int* cnt, int* block_count) {
   const int tid = threadIdx.x;
-  if (tid == 0) cnt = 0;
-  ForwardOut none{};
-  for (int m = 0; m < H.members; ++m) {
-    forward_tile<false, F32>(H, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n, s0, zs, act, ys,
-                             none);
-    if (tid < kTileS) {
-      const float v = ys[tid] * H.t_sigma + H.t_mu;
-      ysum[tid] = m == 0 ? v : ysum[tid] + v;
-      ymin[tid] = m == 0 ? v : fminf(ymin[tid], v);
-      ymax[tid] = m == 0 ? v : fmaxf(ymax[tid], v);
-    }
-    __syncthreads();
-  }
+  base_parts(H, X, n, s0, bp);
+  __syncthreads();
   if (tid < kTileS && s0 + tid < n) {
     const int64_t gs = s0 + tid;
-    const float base = H.use_baseline ? (float)baseline(H, X + gs * kIn) : 0.0f;
+    const float base = (float)base_of(H, X, gs, bp, tid);
     ysum[tid] += (float)H.members * base;
     ymin[tid] += base;
     ymax[tid] += base;
@@ -529,12 +781,69 @@ __global__ __launch_bounds__(256) void query_kernel(Model md, const float* X, in
     spread[gs] = sp;
     const bool fb = out || !(sp <= spread_tol);
     fallback[gs] = fb ? 1 : 0;
-    if (fb) atomicAdd(&cnt, 1);
+    if (fb) atomicAdd(cnt, 1);
   }
   __syncthreads();
-  if (tid == 0) block_count[blockIdx.x] = cnt;
+  if (tid == 0) block_count[blockIdx.x] = *cnt;
 }
 
+__device__ inline void query_accumulate(const Header& H, int m, const float* ys, float* ysum, float* ymin,
+                                        float* ymax) {
+  const int tid = threadIdx.x;
+  if (tid < kTileS) {
+    const float v = ys[tid] * H.t_sigma + H.t_mu;
+    ysum[tid] = m == 0 ? v : ysum[tid] + v;
+    ymin[tid] = m == 0 ? v : fminf(ymin[tid], v);
+    ymax[tid] = m == 0 ? v : fmaxf(ymax[tid], v);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void query_f32_kernel(Model md, const float* __restrict__ X, int64_t n,
+                                                        float spread_tol, float* mean, float* spread,
+                                                        unsigned char* fallback, int* block_count) {
+  __shared__ float zs[kTileS * kIn];
+  __shared__ float act[2][kTileS][kActStride];
+  __shared__ float wl[kH][kWS];
+  __shared__ SmallP sp;
+  __shared__ float yp[4][kTileS];
+  __shared__ float ys[kTileS], ymin[kTileS], ymax[kTileS], ysum[kTileS];
+  __shared__ double bp[4][kTileS];
+  __shared__ int cnt;
+  const Header& H = *md.hdr;
+  const int64_t s0 = (int64_t)blockIdx.x * kTileS;
+  if (threadIdx.x == 0) cnt = 0;
+  const ForwardOut none{};
+  WRegs pf;
+  wload(pf, md.master + oW2);
+  for (int m = 0; m < H.members; ++m) {
+    const float* master = md.master + (size_t)m * kP;
+    const float* next = m + 1 < H.members ? master + kP + oW2 : nullptr;
+    forward_tile_f32<false>(H, master, X, n, s0, zs, act, wl, sp, yp, ys, pf, next, none);
+    query_accumulate(H, m, ys, ysum, ymin, ymax);
+  }
+  query_finish(H, X, n, s0, spread_tol, zs, ysum, ymin, ymax, bp, mean, spread, fallback, &cnt, block_count);
+}
+
+__global__ __launch_bounds__(256) void query_bf16_kernel(Model md, const float* __restrict__ X, int64_t n,
+                                                         float spread_tol, float* mean, float* spread,
+                                                         unsigned char* fallback, int* block_count) {
+  __shared__ float zs[kTileS * kIn];
+  __shared__ unsigned short act[2][kTileS][kActStride];
+  __shared__ float ys[kTileS], ymin[kTileS], ymax[kTileS], ysum[kTileS];
+  __shared__ double bp[4][kTileS];
+  __shared__ int cnt;
+  const Header& H = *md.hdr;
+  const int64_t s0 = (int64_t)blockIdx.x * kTileS;
+  if (threadIdx.x == 0) cnt = 0;
+  const ForwardOut none{};
+  for (int m = 0; m < H.members; ++m) {
+    forward_tile_bf16<false>(H, md.master + (size_t)m * kP, md.w + (size_t)m * kPpad, X, n, s0, zs, act, ys,
+                             none);
+    query_accumulate(H, m, ys, ysum, ymin, ymax);
+  }
+  query_finish(H, X, n, s0, spread_tol, zs, ysum, ymin, ymax, bp, mean, spread, fallback, &cnt, block_count);
+}
 // Ordered compaction of the flagged query indices: an exclusive scan of the
 // per-block counts (one block), then each block writes its flagged indices
 // in order.
@@ -666,26 +975,25 @@ static int launch_grad(const Model& md, int M, bool f32, const float* X, const f
                        const TrainWs& w, hipStream_t s) {
   const int nb = (int)((n + kTileS - 1) / kTileS);
   if (f32) {
-    hipLaunchKernelGGL(forward_train_kernel<true>, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
-    hipLaunchKernelGGL(delta_kernel<true>, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
+    hipLaunchKernelGGL(train_tile_f32_kernel, dim3(nb, M), dim3(256), 0, s, md, X, t, n, w);
   } else {
-    hipLaunchKernelGGL(forward_train_kernel<false>, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
-    hipLaunchKernelGGL(delta_kernel<false>, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
+    hipLaunchKernelGGL(forward_train_bf16_kernel, dim3(nb, M), dim3(256), 0, s, md, X, n, w);
+    hipLaunchKernelGGL(delta_bf16_kernel, dim3((unsigned)n, M), dim3(kH), 0, s, md, t, n, w);
   }
   const size_t nh = (size_t)n * kH;
-  const GradJob jobs[4] = {
-      {w.d3, kH, w.h2, kH, kH, oW3, ob3},
-      {w.d2, kH, w.h1, kH, kH, oW2, ob2},
-      {w.d1, kH, w.z, kIn, kH, oW1, ob1},
-      {w.dy, 1, w.h3, kH, 1, ow4, ob4},
-  };
-  for (int j = 0; j < 4; ++j) {
-    const GradJob& g = jobs[j];
-    const size_t dstride = g.rows_d == 1 ? (size_t)n : nh;
-    const size_t istride = g.K == kIn ? (size_t)n * kIn : nh;
-    dim3 grid((g.K + 1 + 15) / 16, (g.nO + 15) / 16, M);
-    hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, s, g, n, dstride, istride, w.grad);
+  GradJobs jobs = {{
+      {w.d3, kH, w.h2, kH, kH, oW3, ob3, nh, nh, 0, 0},
+      {w.d2, kH, w.h1, kH, kH, oW2, ob2, nh, nh, 0, 0},
+      {w.d1, kH, w.z, kIn, kH, oW1, ob1, nh, (size_t)n * kIn, 0, 0},
+      {w.dy, 1, w.h3, kH, 1, ow4, ob4, (size_t)n, nh, 0, 0},
+  }};
+  int blocks = 0;
+  for (GradJob& g : jobs.job) {
+    g.tiles_x = (g.K + 1 + 15) / 16;
+    g.first = blocks;
+    blocks += g.tiles_x * ((g.nO + 15) / 16);
   }
+  hipLaunchKernelGGL(wgrad_kernel, dim3(blocks, M), dim3(256), 0, s, jobs, n, w.grad);
   return hipGetLastError() == hipSuccess ? IT_OK : IT_EHIP;
 }
 
@@ -794,10 +1102,10 @@ int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread
   int* offs = (int*)(p + align256((size_t)nb * 4));
   int64_t* total = (int64_t*)(p + 2 * align256((size_t)nb * 4));
   if (h.precision == IT_MLP_FP32)
-    hipLaunchKernelGGL(query_kernel<true>, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
+    hipLaunchKernelGGL(query_f32_kernel, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
                        d_fallback, counts);
   else
-    hipLaunchKernelGGL(query_kernel<false>, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
+    hipLaunchKernelGGL(query_bf16_kernel, dim3(nb), dim3(256), 0, s, md, d_X, nq, spread_tol, d_mean, d_spread,
                        d_fallback, counts);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, nb, offs, total);
   if (d_fallback_idx)

@@ -153,7 +153,7 @@ def solver_data(n_train=32768, n_hold=1024, seed=None, log=None):
     return dict(seed=base_seed, Xtr=Xtr, ytr=ytr, vs_tr=vs_tr, sec_tr=sec_tr, Xh=Xh, yh=yh, vs_h=vs_h, sec_h=sec_h)
 
 
-def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members=4, steps=300000, seed=None,
+def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members=4, steps=600000, seed=None,
              precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None):
     """The surrogate experiment: train on n_train solver runs, judge on
     n_hold held-out solver runs, time n_query queries (``data`` from
