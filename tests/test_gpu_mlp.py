@@ -129,6 +129,30 @@ def test_fp32_gradient_matches_reference(gpu):
             off += k
 
 
+@pytest.mark.parametrize("precision,loss_rel,bar", [("fp32", 1e-5, 1e-4), ("bf16", 2e-3, 2e-3)])
+def test_gradient_on_a_ragged_sample_count(gpu, precision, loss_rel, bar):
+    """1000 samples (15 full tiles of 64 and one of 40; the weight-gradient
+    loop's tail) and an odd member count."""
+    import torch
+    members, n = 3, 1000
+    prec = gpu.IT_MLP_FP32 if precision == "fp32" else gpu.IT_MLP_BF16
+    model, X, t, norm, params = setup(gpu, members, n, seed=17, precision=prec)
+    grad, loss = gpu.it_mlp_grad(model, members, torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"))
+    g = grad.cpu().numpy()
+    cast = precision == "bf16"
+    _, Z = ref_forward(params, X, norm, members, cast=cast)
+    ts = (t.astype(np.float64) - float(norm[24])) / float(norm[25])
+    for m in range(members):
+        rl, rg = mlp.loss_and_grad(params[m].astype(np.float64), Z, ts, cast=cast)
+        assert loss[m] == pytest.approx(rl, rel=loss_rel)
+        off = 0
+        for name, shape in mlp.SIZES:
+            k = int(np.prod(shape))
+            a, b = g[m, off:off + k], rg[off:off + k]
+            assert np.linalg.norm(a - b) <= bar * np.linalg.norm(b) + 1e-8, (m, name)
+            off += k
+
+
 def test_fp32_minibatch_training_and_bad_precision(gpu):
     import torch
     members, n = 2, 2048
