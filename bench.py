@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--kernel", choices=("auto", "plain", "blocked"), default="auto")
     ap.add_argument("--T", type=int, default=0, help="steps per pass of the blocked kernel")
     ap.add_argument("--tile-y", type=int, default=0, help="tile rows (0 = default)")
+    ap.add_argument("--tile-x", type=int, default=0,
+                    help="tile columns of the one-step kernel: 32, 64 or 128 (column pairs); 0 = default")
     ap.add_argument("--z-chunk", type=int, default=0, help="planes per tile of the one-step kernel (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-steps", type=int, default=200,
@@ -164,7 +166,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
         return
     kernel = {"auto": it.IT_KERNEL_AUTO, "plain": it.IT_KERNEL_PLAIN, "blocked": it.IT_KERNEL_BLOCKED}[a.kernel]
-    ex = {"kernel": kernel, "steps_per_pass": a.T, "tile_y": a.tile_y, "z_chunk": a.z_chunk}
+    ex = {"kernel": kernel, "steps_per_pass": a.T, "tile_y": a.tile_y, "tile_x": a.tile_x, "z_chunk": a.z_chunk}
     ws = it.workspace(ch, tr.shape[0])
     nint = (ch["nz"] - 1) * ch["nx"] * ch["ny"]
     stream = torch.cuda.current_stream()
@@ -240,7 +242,8 @@ def main():
     bytes_per_launch = BYTES_PER_VOXEL_STEP * nint * T_pass  # compulsory traffic of one pass
     achieved = bytes_per_launch / per_launch / 1e9
     workload_name = "pulsed_256x256x200"
-    shape = f"tile_y {16 if a.tile_y == 16 else 8} z_chunk {a.z_chunk}" if T_pass == 1 else f"T {T_pass}"
+    shape = f"tile_x {a.tile_x} tile_y {16 if a.tile_y == 16 else 8} z_chunk {a.z_chunk}" if T_pass == 1 else \
+        f"T {T_pass}"
     traffic = read_traffic(kname, workload_name, kernel_source_hash(src), shape)
     progress(f"{kname}: {per_launch * 1e6:.1f} us per launch")
 

@@ -199,6 +199,9 @@ typedef struct {
   int32_t timing_span;     /* see timing_events */
   int32_t tile_x;          /* columns per tile of the one-step kernels: 64, or 32 (32 x 16 tiles of
                             * 8 waves, two rows each; tile_y must then be 0 or 16, and the
+                            * blocked kernel does not take it), or 128 (tiles of tile_y rows of
+                            * 64 column pairs, one pair per lane: single chambers with an even
+                            * nx only, IT_EINVAL otherwise; batches return IT_ENOTSUP, and the
                             * blocked kernel does not take it); 0 = default */
 } it_exec;
 

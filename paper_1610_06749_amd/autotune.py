@@ -4,7 +4,8 @@ Times every candidate execution choice on the caller's grid and keeps the
 fastest per voxel-step:
 
 * single chambers (``tune``): the plain kernel with 64 x 8, 64 x 16 or
-  32 x 16 tiles and the temporally blocked kernel at each depth T, each timed
+  32 x 16 tiles, or 128 x 8 tiles of column pairs (even nx), and the
+  temporally blocked kernel at each depth T, each timed
   over whole passes
   (the stepping kernel plus its tally reduction) on a perturbed field of the
   chamber's shape;
@@ -28,6 +29,7 @@ from . import binding as B
 
 PLAIN = [dict(kernel=B.IT_KERNEL_PLAIN, tile_y=8), dict(kernel=B.IT_KERNEL_PLAIN, tile_y=16),
          dict(kernel=B.IT_KERNEL_PLAIN, tile_x=32)]
+PAIR = [dict(kernel=B.IT_KERNEL_PLAIN, tile_x=128)]  # tiles of column pairs: grids with an even nx
 BLOCKED = [dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=T) for T in (2, 3, 4, 5)]
 
 _memo: dict = {}
@@ -98,7 +100,7 @@ def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
     if key in table:
         _memo[key] = table[key]["exec"]
         return dict(_memo[key])
-    cands = candidates if candidates is not None else PLAIN + BLOCKED
+    cands = candidates if candidates is not None else PLAIN + (PAIR if ch["nx"] % 2 == 0 else []) + BLOCKED
     timings = []
     for ex in cands:
         try:

@@ -150,9 +150,10 @@ hipError_t launch_step3(const Step3Params& p, hipStream_t s);
 
 // Launchers (stream-ordered, no synchronisation).
 // Tile shape of the one-step kernels: tile_x 32 gives 32 x 16 tiles (8 waves,
-// two rows each); otherwise 64 columns by tile_y = 16 or 8 rows (one wave
-// per row).
-inline int plain_tile_cols(int tile_x) { return tile_x == 32 ? 32 : 64; }
+// two rows each); tile_x 128 tiles of 128 columns (each lane a pair of
+// columns) by tile_y = 16 or 8 rows; otherwise 64 columns by tile_y = 16 or
+// 8 rows (one wave per row).
+inline int plain_tile_cols(int tile_x) { return tile_x == 32 || tile_x == 128 ? tile_x : 64; }
 int plain_tile_rows(int tile_y, int tile_x);
 // ev_begin / ev_end (may be null) are recorded around the stepping kernel
 // alone, before the tally reduction is launched.

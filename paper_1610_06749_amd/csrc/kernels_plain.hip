@@ -3,8 +3,9 @@
 // Step kernel: one explicit time step of both ion species (eq. theEquation
 // with the Appendix's difference scheme, written as per-node coefficients),
 // plus the per-step tallies.  Each block (8 or 16 waves) owns a 64 x 8,
-// 64 x 16 or 32 x 16 column tile and a chunk of planes and marches up it
-// (plain_tile_step); with one step per launch an extra block records the
+// 64 x 16 or 32 x 16 column tile (plain_tile_step), or a 128 x 8 or
+// 128 x 16 tile of column pairs (pair_tile_step), and a chunk of planes and
+// marches up it; with one step per launch an extra block records the
 // previous step from its partials.  Every thread
 // keeps n_{k-1}, n_k, n_{k+1} of its column in registers, the block stages
 // plane k of the tile in LDS for the lateral neighbours, and neighbours
@@ -27,8 +28,10 @@ constexpr int kTY = 4, kNT = kTX * kTY;  // deposition tile
 // state it writes is read by the next launch.  Stepping blocks that read
 // `done` while it is being set only decide whether to compute a step past
 // the stop, whose output goes to the field pair not holding the stop step.
+// Tiles of column pairs aim at 8 waves per CU, so they may use more
+// registers (at least 2 waves per SIMD instead of 4).
 template <int SY, bool SC, bool AB, int TX>
-__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_plain_kernel(StepParams p) {
+__global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(TX == 2 * kTX ? 2 : 4, 8))) void step_plain_kernel(StepParams p) {
   if (p.prev_partials && blockIdx.x == gridDim.x - 1) {
     if (p.state->done) return;
     __shared__ double totals[kAcc];
@@ -38,8 +41,11 @@ __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8))
     return;
   }
   if (p.state->done) return;  // set by an earlier launch: every block skips
-  plain_tile_step<SY, SC, AB, TX>(p, decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd),
-                                  p.partials + (size_t)blockIdx.x * kAcc);
+  const TileCoord t = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
+  if constexpr (TX == 2 * kTX)
+    pair_tile_step<SY, SC, AB>(p, t, p.partials + (size_t)blockIdx.x * kAcc);
+  else
+    plain_tile_step<SY, SC, AB, TX>(p, t, p.partials + (size_t)blockIdx.x * kAcc);
 }
 
 // One block: sums the per-block partial tallies of a stepping launch in a
@@ -84,7 +90,10 @@ void launch_plain_terms(const StepParams& p, dim3 g, hipStream_t s) {
 // the kernel instance for the tile shape, the space-charge term and the
 // lateral boundary option of the run
 void launch_plain_variant(const StepParams& p, int tile_y, int tile_x, dim3 g, hipStream_t s) {
-  if (plain_tile_cols(tile_x) == 32) launch_plain_terms<8, 32>(p, g, s);
+  if (plain_tile_cols(tile_x) == 128) {
+    if (plain_tile_rows(tile_y, tile_x) == 16) launch_plain_terms<16, 128>(p, g, s);
+    else launch_plain_terms<8, 128>(p, g, s);
+  } else if (plain_tile_cols(tile_x) == 32) launch_plain_terms<8, 32>(p, g, s);
   else if (plain_tile_rows(tile_y, tile_x) == 16) launch_plain_terms<16, 64>(p, g, s);
   else launch_plain_terms<8, 64>(p, g, s);
 }

@@ -205,11 +205,13 @@ Tiling make_tiling(int nx, int ny, int nz, int tile_y, int zc, int tile_x = 64) 
 // 256 CUs), all resident at once: the launch then takes as long as one
 // chunk, so chunks of equal length and as few chunk starts (each re-reads
 // two planes) as the occupancy allows are what count.
+// Tiles of column pairs (tile_x 128) have one wave per row with twice the
+// bytes in flight per wave, so they aim at half as many waves.
 Tiling step_tiling(int nx, int ny, int nz, int rows, int z_chunk, int tile_x = 64) {
   if (z_chunk > 0) return make_tiling(nx, ny, nz, rows, z_chunk, tile_x);
   const int nint = nz - 1;
   const long cols = (long)((nx + tile_x - 1) / tile_x) * ((ny + rows - 1) / rows);
-  const long target = 4096 / (rows * tile_x / 64);  // tiles of rows * tile_x / 64 waves
+  const long target = tile_x == 128 ? 2048 / rows : 4096 / (rows * tile_x / 64);  // tiles
   long chunks = std::max<long>(1, (target + cols / 2) / cols);
   chunks = std::min<long>(chunks, std::max(1, nint / 4));  // at least 4 planes per chunk
   const int zc = (int)((nint + chunks - 1) / chunks);
@@ -230,10 +232,14 @@ int exec_z_chunk(const it_exec* ex) { return ex ? ex->z_chunk : 0; }
 // Tile width of the one-step kernels for chambers ch[0..n): as asked, else
 // (tile_x and tile_y both 0) 32 x 16 tiles where they cover the planes with
 // at least a quarter fewer padded nodes than 64 x 8 tiles (narrow grids, where
-// most lanes of a 64-wide tile would idle), else 64.  On MI355X 32 x 16 tiles
-// take 1.5 % longer per node on a 256-wide grid and 12 % longer on the
-// 64..256-wide batched sweep, and 20 % less on 24-wide chambers.
-int exec_tile_x(const it_exec* ex, const it_chamber* ch, int n) {
+// most lanes of a 64-wide tile would idle); else, for a single chamber
+// (pairs: the caller runs the one-step kernel on one chamber) with an even
+// nx, 128 x 8 tiles of column pairs where they pad no more than 64 x 8 tiles
+// do; else 64.  On MI355X 32 x 16 tiles take 1.5 % longer per node on a
+// 256-wide grid and 12 % longer on the 64..256-wide batched sweep, and 20 %
+// less on 24-wide chambers; 128 x 8 tiles take 4.7 % less on the 256-wide
+// grid.
+int exec_tile_x(const it_exec* ex, const it_chamber* ch, int n, bool pairs) {
   if (ex && ex->tile_x != 0) return plain_tile_cols(ex->tile_x);
   if (ex && ex->tile_y != 0) return 64;
   double pad64 = 0.0, pad32 = 0.0;
@@ -242,14 +248,22 @@ int exec_tile_x(const it_exec* ex, const it_chamber* ch, int n) {
     pad64 += planes * (double)((ch[q].nx + 63) / 64 * 64) * (double)((ch[q].ny + 7) / 8 * 8);
     pad32 += planes * (double)((ch[q].nx + 31) / 32 * 32) * (double)((ch[q].ny + 15) / 16 * 16);
   }
-  return pad32 <= 0.75 * pad64 ? 32 : 64;
+  if (pad32 <= 0.75 * pad64) return 32;
+  if (pairs && n == 1 && ch->nx % 2 == 0 && (ch->nx + 127) / 128 * 128 <= (ch->nx + 63) / 64 * 64) return 128;
+  return 64;
 }
 
-// Tile shape fields: tile_x 0, 32 or 64; 32-wide tiles have 16 rows.
+// Tile shape fields: tile_x 0, 32, 64 or 128; 32-wide tiles have 16 rows.
 bool tile_shape_ok(const it_exec* ex) {
   if (!ex) return true;
-  if (ex->tile_x != 0 && ex->tile_x != 32 && ex->tile_x != 64) return false;
+  if (ex->tile_x != 0 && ex->tile_x != 32 && ex->tile_x != 64 && ex->tile_x != 128) return false;
   return ex->tile_x != 32 || ex->tile_y == 0 || ex->tile_y == 16;
+}
+
+// Tiles of column pairs need an even nx (a pair never straddles the edge of
+// the grid) and 16-byte aligned fields.
+bool pair_tiles_ok(const it_chamber* ch, const void* a, const void* b) {
+  return ch->nx % 2 == 0 && (uintptr_t)a % 16 == 0 && (uintptr_t)b % 16 == 0;
 }
 
 bool z_chunk_ok(const it_exec* ex) {
@@ -271,7 +285,8 @@ int check_exec(const it_chamber* ch, const it_exec* ex) {
   if (T > 1 && !blocked_supported(T, ex ? ex->tile_y : 0)) return IT_ENOTSUP;
   if (T > 1 && ch->lateral_bc) return IT_ENOTSUP;  // the blocked kernel is periodic only
   if (!z_chunk_ok(ex)) return IT_EINVAL;
-  if (!tile_shape_ok(ex) || (ex && ex->tile_x == 32 && T > 1)) return IT_EINVAL;
+  if (!tile_shape_ok(ex) || (ex && (ex->tile_x == 32 || ex->tile_x == 128) && T > 1)) return IT_EINVAL;
+  if (ex && ex->tile_x == 128 && ch->nx % 2) return IT_EINVAL;
   return IT_OK;
 }
 
@@ -470,7 +485,11 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const Coef cp = species_coef(ch, dt, 0), cn = species_coef(ch, dt, 1);
   const double dz = ch->gap / ch->nz;
   const double dV = ch->dx * ch->dy * dz;
-  const int tx = T == 1 ? exec_tile_x(ex, ch, 1) : 64;
+  int tx = T == 1 ? exec_tile_x(ex, ch, 1, true) : 64;
+  if (tx == 128 && !pair_tiles_ok(ch, field[0], field[1])) {
+    if (ex && ex->tile_x == 128) return IT_EINVAL;
+    tx = 64;  // the automatic choice falls back on unaligned fields
+  }
   const int rows = tx == 32 ? 16 : resolve_rows(tile_y, ch->ny);
   const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, rows, exec_z_chunk(ex), tx);
   const Tiling td = deposit_tiling(ch->nx, ch->ny, ch->nz);
@@ -658,7 +677,7 @@ int batch_z_chunk(const it_exec* exec) {
 
 // One tile shape serves every instance of a batch.
 int batch_rows(const it_chamber* ch, int ninst, const it_exec* exec) {
-  if (exec_tile_x(exec, ch, ninst) == 32) return 16;
+  if (exec_tile_x(exec, ch, ninst, false) == 32) return 16;
   int min_ny = ch[0].ny;
   for (int q = 1; q < ninst; ++q) min_ny = std::min(min_ny, ch[q].ny);
   return resolve_rows(exec ? exec->tile_y : 0, min_ny);
@@ -1032,8 +1051,9 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
     if (track_offsets[q + 1] < track_offsets[q]) return IT_EINVAL;
   }
   if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
+  if (exec && exec->tile_x == 128) return IT_ENOTSUP;  // the batched kernel has no tiles of column pairs
   const int rows = batch_rows(ch, ninst, exec);
-  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst)).total;
+  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst, false)).total;
   return IT_OK;
 }
 
@@ -1053,7 +1073,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
   if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
-  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst));
+  if (exec && exec->tile_x == 128) return IT_ENOTSUP;  // the batched kernel has no tiles of column pairs
+  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst, false));
   if (!d_workspace || ws_bytes < B.total) return IT_EWORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
   char* ws = (char*)d_workspace;
@@ -1086,7 +1107,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 
     const Coef cp = species_coef(c, dts[q], 0), cn = species_coef(c, dts[q], 1);
     const double dz = c->gap / c->nz, dV = c->dx * c->dy * dz;
-    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst));
+    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst, false));
     const Tiling td = deposit_tiling(c->nx, c->ny, c->nz);
     BatchInstance& bi = table[q];
     for (int par = 0; par < 2; ++par) {
@@ -1181,7 +1202,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
     hipError_t ce = hipSuccess;
     for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, exec_tile_x(exec, ch, ninst), any_sc, any_ab,
+      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, exec_tile_x(exec, ch, ninst, false), any_sc, any_ab,
                              (parity0 + k) & 1, true, cs);
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
@@ -1200,7 +1221,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   {
     int tiles = 0;
     for (int q = 0; q < ninst; ++q) tiles += table[q].ntiles;
-    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, exec_tile_x(exec, ch, ninst), any_sc, any_ab, 0, false,
+    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, exec_tile_x(exec, ch, ninst, false), any_sc, any_ab, 0, false,
                           stream) != hipSuccess) {
       release_graph();
       return IT_EHIP;

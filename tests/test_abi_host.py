@@ -109,6 +109,10 @@ def test_launch_shape_checks(lib):
         with pytest.raises(lib.ItError) as e:
             lib.it_workspace_size_batch(chs, trs, bad)
         assert e.value.code == lib.IT_EINVAL
+    # tiles of column pairs are for single chambers
+    with pytest.raises(lib.ItError) as e:
+        lib.it_workspace_size_batch(chs, trs, dict(tile_x=128))
+    assert e.value.code == lib.IT_ENOTSUP
     # in-plane offsets are 32-bit byte offsets: planes above 2^28 nodes are refused
     with pytest.raises(lib.ItError) as e:
         lib.it_validate(W.chamber(1 << 15, 1 << 14, 2, 1e-4, 2e-4, 10.0), np.zeros((0, 7)))
@@ -142,6 +146,12 @@ def test_lateral_boundary_option_checks(lib, orc):
     # 32-column tiles belong to the one-step kernels
     assert _solve_status(lib, ch, tr, dict(kernel=1, tile_x=32)) == lib.IT_EWORKSPACE
     assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4, tile_x=32)) == lib.IT_EINVAL
+    # so do tiles of column pairs, which need an even nx
+    assert ch["nx"] % 2 == 0
+    for ty in (0, 8, 16):
+        assert _solve_status(lib, ch, tr, dict(kernel=1, tile_x=128, tile_y=ty)) == lib.IT_EWORKSPACE
+    assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4, tile_x=128)) == lib.IT_EINVAL
+    assert _solve_status(lib, dict(ch, nx=ch["nx"] - 1), tr, dict(kernel=1, tile_x=128)) == lib.IT_EINVAL
     # the recombination bound sums the tracks' profiles without periodic
     # images: two dense tracks at opposite x edges overlap only through the wrap
     ch2 = W.chamber(40, 40, 10, 2e-4, 10 * 2e-4, 20.0)

@@ -23,5 +23,5 @@ def test_traffic_summary_lookup(tmp_path):
     src = ["kernels_plain.hip", "stencil_plain.h", "reduce.h", "internal.h"]
     h = bench.kernel_source_hash(src)
     assert len(h) == 16
-    assert bench.read_traffic("step_plain", "pulsed_256x256x200", "0" * 16, "tile_y 8 z_chunk 0") is None
-    assert bench.read_traffic("step_plain", "no_such_workload", h, "tile_y 8 z_chunk 0") is None
+    assert bench.read_traffic("step_plain", "pulsed_256x256x200", "0" * 16, "tile_x 0 tile_y 8 z_chunk 0") is None
+    assert bench.read_traffic("step_plain", "no_such_workload", h, "tile_x 0 tile_y 8 z_chunk 0") is None

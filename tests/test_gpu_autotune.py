@@ -33,11 +33,11 @@ def test_tune_picks_a_timed_candidate_and_caches_it(gpu, orc, tuner, tmp_path):
     ch = W.chamber(70, 13, 37, 3e-4, 37 * 3e-4, 25.0, dy=2.5e-4)
     cache = str(tmp_path / "tune.json")
     ex = tuner.tune(ch, steps=16, cache=cache)
-    assert ex in tuner.PLAIN + tuner.BLOCKED
+    assert ex in tuner.PLAIN + tuner.PAIR + tuner.BLOCKED
     table = json.load(open(cache))
     (key, entry), = table.items()
     assert key.startswith("70x13x37@") and entry["exec"] == ex
-    assert len(entry["all"]) == len(tuner.PLAIN + tuner.BLOCKED)
+    assert len(entry["all"]) == len(tuner.PLAIN + tuner.PAIR + tuner.BLOCKED)  # nx even: pairs included
     assert all(v > 0 for _, v in entry["all"])
     assert entry["voxel_steps_per_s"] == max(v for _, v in entry["all"])
     # a second tuner process would read the file; the memo answers here
@@ -54,7 +54,11 @@ def test_tune_skips_unsupported_candidates(gpu, tuner):
     # absorbing lateral boundaries: the blocked kernel refuses them
     ch = W.chamber(40, 24, 20, 3e-4, 20 * 3e-4, 25.0, lateral_bc=1)
     ex = tuner.tune(ch, steps=8)
-    assert ex in tuner.PLAIN
+    assert ex in tuner.PLAIN + tuner.PAIR
+    # an odd nx: no tiles of column pairs
+    ch = W.chamber(41, 24, 20, 3e-4, 20 * 3e-4, 25.0)
+    ex = tuner.tune(ch, steps=8)
+    assert ex not in tuner.PAIR
 
 
 def test_tune_batch_returns_a_working_shape(gpu, tuner, tmp_path):

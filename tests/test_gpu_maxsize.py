@@ -62,8 +62,8 @@ def check_window(torch, g, ref):
 
 
 @pytest.mark.parametrize("ex", [None, dict(kernel=1, tile_y=16), dict(kernel=1, tile_x=32),
-                                dict(kernel=2, steps_per_pass=4)],
-                         ids=["default", "plain16", "plain32x16", "blocked4"])
+                                dict(kernel=1, tile_x=128), dict(kernel=2, steps_per_pass=4)],
+                         ids=["default", "plain16", "plain32x16", "pair128x8", "blocked4"])
 def test_advance_on_largest_plane(gpu, orc, ex):
     import torch
     steps = 8
