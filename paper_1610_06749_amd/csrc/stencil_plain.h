@@ -1,6 +1,8 @@
-// One explicit time step of both species on one 64 x SY column tile and a
-// chunk of planes, with the per-block partial tallies (shared by the
-// single-chamber and the batched stepping kernels).
+// One explicit time step of both species on one column tile and a chunk of
+// planes, with the per-block partial tallies: plain_tile_step (64 x SY or
+// 32 x 16 tiles, one column per lane; the single-chamber and the batched
+// stepping kernels) and pair_tile_step (128 x SY tiles, two columns per
+// lane; single chambers).
 #pragma once
 
 #include "reduce.h"
@@ -231,7 +233,9 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
 // rows are 132 doubles, so every pair sits on a 16-byte boundary.  The rest
 // (pipelining, rim loads by waves 0-3, double-buffered LDS plane, tallies)
 // is as in plain_tile_step, and the update of each column is written in the
-// same order.
+// same order, so both give the same fields bit for bit.  112 VGPRs without
+// the optional terms: four waves per SIMD, twice the 8 waves per CU that the
+// default tiling of column pairs places.
 typedef double double2_t __attribute__((ext_vector_type(2)));
 
 struct PairRegs {
