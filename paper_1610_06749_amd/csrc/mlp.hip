@@ -210,11 +210,12 @@ struct ForwardOut {  // optional stores of the training forward (member slices)
 
 // ---------------------------------------------------------------------------
 // FP32 models.  Every kernel runs 256 threads on a tile of 64 samples of one
-// member; wave w owns samples 16w..16w+15 of the tile.  The 128 x 128
-// weights of a layer are staged in LDS (wl[o][i], rows padded to kWS), read
-// from global memory into registers one layer ahead (64 values per thread,
-// element tid + 256 u of the matrix), so that their latency hides behind the
-// previous layer.  Products run on v_mfma_f32_16x16x4f32 (A[i][k]: lane
+// member; wave w owns samples 16w..16w+15 of the tile.  The training kernel
+// stages the 128 x 128 weights of a layer in LDS (wl[o][i], rows padded to
+// kWS), read from global memory into registers one layer ahead (64 values
+// per thread, element tid + 256 u of the matrix), so that their latency
+// hides behind the previous layer; the query kernel stages them in halves
+// (forward_query_f32).  Products run on v_mfma_f32_16x16x4f32 (A[i][k]: lane
 // i + 16 k, B[k][j]: lane j + 16 k, D[i][j]: lane j + 16 (i/4), item i % 4),
 // four 16-wide output tiles per pass sharing the A operand, k taken 4 at a
 // time in increasing order.  Every per-element value a thread computes sits
@@ -285,9 +286,8 @@ __device__ inline void mfma_pass(const float (*in)[kActStride], const float (*wl
   }
 }
 
-// Hidden layer 2 or 3: out = silu(in W^T + b), optional stores of the
-// pre-activations and activations.  Ends with a barrier.
-template <bool STORE>
+// Hidden layer 2 or 3 of the training forward pass: out = silu(in W^T + b),
+// with stores of the pre-activations and activations.  Ends with a barrier.
 __device__ void layer_fwd_f32(const float (*in)[kActStride], float (*out)[kActStride], const float (*wl)[kWS],
                               const float* __restrict__ bias, int64_t n, int64_t s0, float* sa, float* sh) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -306,7 +306,7 @@ __device__ void layer_fwd_f32(const float (*in)[kActStride], float (*out)[kActSt
         const float h = silu(a);
         out[s][o] = h;
         const int64_t gs = s0 + s;
-        if (STORE && gs < n) {
+        if (gs < n) {
           sa[gs * kH + o] = a;
           sh[gs * kH + o] = h;
         }
@@ -355,11 +355,11 @@ __device__ void layer_bwd_f32(const float (*d)[kActStride], float (*dout)[kActSt
   __syncthreads();
 }
 
-// Forward pass of one FP32 member over samples [s0, s0 + 64).  On entry
+// Training forward pass of one FP32 member over samples [s0, s0 + 64),
+// storing what the backward pass and the weight gradients read.  On entry
 // `pf` holds (or is loading) this member's W2; on return it is loading
 // `next` (when not null).  Leaves the standardised outputs in ys[64] and h3
 // in act[0].
-template <bool STORE>
 __device__ void forward_tile_f32(const Header& H, const float* __restrict__ master, const float* __restrict__ X,
                                  int64_t n, int64_t s0, float* zs, float (*act)[kTileS][kActStride],
                                  float (*wl)[kWS], SmallP& sp, float (*yp)[kTileS], float* ys, WRegs& pf,
@@ -374,7 +374,7 @@ __device__ void forward_tile_f32(const Header& H, const float* __restrict__ mast
     float zv = 0.0f;
     if (gs < n) zv = (logf(X[gs * kIn + i]) - H.mu[i]) / H.sigma[i];
     zs[q] = zv;
-    if (STORE && gs < n) st.z[gs * kIn + i] = zv;
+    if (gs < n) st.z[gs * kIn + i] = zv;
   }
   __syncthreads();
   // layer 1 (FP32 FMAs, D layout)
@@ -394,7 +394,7 @@ __device__ void forward_tile_f32(const Header& H, const float* __restrict__ mast
       const float h = silu(a);
       act[0][s][o] = h;
       const int64_t gs = s0 + s;
-      if (STORE && gs < n) {
+      if (gs < n) {
         st.a1[gs * kH + o] = a;
         st.h1[gs * kH + o] = h;
       }
@@ -403,11 +403,11 @@ __device__ void forward_tile_f32(const Header& H, const float* __restrict__ mast
   wstore(pf, wl);  // W2 (wl's last readers passed a barrier)
   __syncthreads();
   wload(pf, master + oW3);
-  layer_fwd_f32<STORE>(act[0], act[1], wl, sp.b2, n, s0, st.a2, st.h2);
+  layer_fwd_f32(act[0], act[1], wl, sp.b2, n, s0, st.a2, st.h2);
   wstore(pf, wl);  // W3
   __syncthreads();
   if (next) wload(pf, next);
-  layer_fwd_f32<STORE>(act[1], act[0], wl, sp.b3w4b4, n, s0, st.a3, st.h3);
+  layer_fwd_f32(act[1], act[0], wl, sp.b3w4b4, n, s0, st.a3, st.h3);
   // output layer: four partial dot products of 32 terms per sample
   {
     const int s = lane, p = wave;
@@ -421,8 +421,106 @@ __device__ void forward_tile_f32(const Header& H, const float* __restrict__ mast
     const float y = sp.b3w4b4[2 * kH] + (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]);
     ys[tid] = y;
     const int64_t gs = s0 + tid;
-    if (STORE && gs < n) st.y[gs] = y;
+    if (gs < n) st.y[gs] = y;
   }
+  __syncthreads();
+}
+
+// Query form of the FP32 forward pass, sized for two blocks per CU (78 KB of
+// LDS): one activation buffer, updated in place (every wave reads and writes
+// only its own 16 rows, so a layer's two passes keep their results in
+// registers until both have read the input), and each 128 x 128 matrix
+// staged in two halves of 64 output rows, one per pass (32 values per
+// thread in flight, element tid + 256 u of the half).  Every output is summed
+// in the same order as in forward_tile_f32, so both give the same values.
+struct WHalf {
+  float v[32];
+};
+
+__device__ inline void wload_half(WHalf& r, const float* __restrict__ W, int half) {
+#pragma unroll
+  for (int u = 0; u < 32; ++u) r.v[u] = W[half * 64 * kH + threadIdx.x + 256 * u];
+}
+
+__device__ inline void wstore_half(const WHalf& r, float (*wl)[kWS]) {
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int q = threadIdx.x + 256 * u;
+    wl[q / kH][q % kH] = r.v[u];
+  }
+}
+
+// One hidden layer of the query form: act = silu(act W^T + b).  On entry pf
+// holds half 0 of W and wl is free (its last readers passed a barrier); on
+// return pf is loading half 0 of `next` (when not null).  Ends with a
+// barrier.
+__device__ void layer_query_f32(float (*act)[kActStride], float (*wl)[kWS], const float* bias,
+                                const float* __restrict__ W, WHalf& pf, const float* next) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  float4_t acc[2][4];
+  wstore_half(pf, wl);
+  __syncthreads();
+  wload_half(pf, W, 1);
+  mfma_pass<false>(act, wl, 0, acc[0]);
+  __syncthreads();  // every wave is done with half 0
+  wstore_half(pf, wl);
+  __syncthreads();
+  if (next) wload_half(pf, next, 0);
+  mfma_pass<false>(act, wl, 0, acc[1]);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = h * 64 + u * 16 + (lane & 15);
+      const float b = bias[o];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) act[wave * 16 + 4 * (lane >> 4) + v][o] = silu(acc[h][u][v] + b);
+    }
+  __syncthreads();
+}
+
+// Query forward pass of one FP32 member over samples [s0, s0 + 64): pf holds
+// (or is loading) half 0 of this member's W2 on entry and is loading `next`
+// on return.  Leaves the standardised outputs in ys[64].
+__device__ void forward_query_f32(const Header& H, const float* __restrict__ master, const float* __restrict__ X,
+                                  int64_t n, int64_t s0, float* zs, float (*act)[kActStride], float (*wl)[kWS],
+                                  SmallP& sp, float (*yp)[kTileS], float* ys, WHalf& pf, const float* next) {
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  sload(master, sp);  // its last readers passed a barrier
+  for (int q = tid; q < kTileS * kIn; q += 256) {
+    const int s = q / kIn, i = q % kIn;
+    const int64_t gs = s0 + s;
+    zs[q] = gs < n ? (logf(X[gs * kIn + i]) - H.mu[i]) / H.sigma[i] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll 2
+  for (int t = 0; t < kH / 16; ++t) {
+    const int o = t * 16 + (lane & 15);
+    float w1[kIn];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) w1[i] = sp.w1b1[o * kIn + i];
+    const float b = sp.w1b1[kH * kIn + o];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = wave * 16 + 4 * (lane >> 4) + v;
+      float a = b;
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) a += w1[i] * zs[s * kIn + i];
+      act[s][o] = silu(a);
+    }
+  }
+  layer_query_f32(act, wl, sp.b2, master + oW2, pf, master + oW3);
+  layer_query_f32(act, wl, sp.b3w4b4, master + oW3, pf, next);
+  {
+    const int s = lane, p = wave;
+    float y = 0.0f;
+#pragma unroll 8
+    for (int i = 32 * p; i < 32 * p + 32; ++i) y += sp.b3w4b4[kH + i] * act[s][i];
+    yp[p][s] = y;
+  }
+  __syncthreads();
+  if (tid < kTileS) ys[tid] = sp.b3w4b4[2 * kH] + (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]);
   __syncthreads();
 }
 
@@ -461,7 +559,7 @@ __global__ __launch_bounds__(256) void train_tile_f32_kernel(Model md, const flo
     if (m == 0) ws.base[gt] = base;
     ty = (t[gt] - base - H.t_mu) / H.t_sigma;
   }
-  forward_tile_f32<true>(H, master, X, n, s0, zs, act, wl, sp, yp, ys, pf, master + oW2, st);
+  forward_tile_f32(H, master, X, n, s0, zs, act, wl, sp, yp, ys, pf, master + oW2, st);
   if (tid < kTileS) {
     float dy = 0.0f;
     if (gt < n) {
@@ -807,12 +905,13 @@ __device__ inline void query_accumulate(const Header& H, int m, const float* ys,
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void query_f32_kernel(Model md, const float* __restrict__ X, int64_t n,
-                                                        float spread_tol, float* mean, float* spread,
-                                                        unsigned char* fallback, int* block_count) {
+// Two blocks per CU (78 KB of LDS each, at most 256 registers per lane).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void query_f32_kernel(
+    Model md, const float* __restrict__ X, int64_t n, float spread_tol, float* mean, float* spread,
+    unsigned char* fallback, int* block_count) {
   __shared__ float zs[kTileS * kIn];
-  __shared__ float act[2][kTileS][kActStride];
-  __shared__ float wl[kH][kWS];
+  __shared__ float act[kTileS][kActStride];
+  __shared__ float wl[kH / 2][kWS];
   __shared__ SmallP sp;
   __shared__ float yp[4][kTileS];
   __shared__ float ys[kTileS], ymin[kTileS], ymax[kTileS], ysum[kTileS];
@@ -821,13 +920,12 @@ __global__ __launch_bounds__(256) void query_f32_kernel(Model md, const float* _
   const Header& H = *md.hdr;
   const int64_t s0 = (int64_t)blockIdx.x * kTileS;
   if (threadIdx.x == 0) cnt = 0;
-  const ForwardOut none{};
-  WRegs pf;
-  wload(pf, md.master + oW2);
+  WHalf pf;
+  wload_half(pf, md.master + oW2, 0);
   for (int m = 0; m < H.members; ++m) {
     const float* master = md.master + (size_t)m * kP;
     const float* next = m + 1 < H.members ? master + kP + oW2 : nullptr;
-    forward_tile_f32<false>(H, master, X, n, s0, zs, act, wl, sp, yp, ys, pf, next, none);
+    forward_query_f32(H, master, X, n, s0, zs, act, wl, sp, yp, ys, pf, next);
     query_accumulate(H, m, ys, ysum, ymin, ymax);
   }
   query_finish(H, X, n, s0, spread_tol, zs, ysum, ymin, ymax, bp, mean, spread, fallback, &cnt, block_count);
