@@ -247,6 +247,18 @@ def test_one_dimensional_uniform(gpu, orc, ex):
     run_both(gpu, orc, ch, W.no_tracks(), exec=ex)
 
 
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "absorbing"])
+@pytest.mark.parametrize("ex", [None, dict(kernel=1, tile_x=128), dict(kernel=1, tile_x=128, tile_y=16),
+                                dict(kernel=1, tile_x=32)], ids=["default", "pair128x8", "pair128x16", "plain32x16"])
+def test_two_node_wide_cells(gpu, orc, ex, bc):
+    """nx = 2: one column pair per row, whose left and right neighbours are
+    its own two columns through the periodic wrap (or missing, absorbing);
+    ny = 5 leaves a partial tile in y."""
+    ch = W.chamber(2, 5, 12, 3e-4, 12 * 3e-4, 10.0, uniform_n0=3e9, lateral_bc=bc)
+    tr = W.tracks([[5.0, 4e-4, 3e-4, 7e-4, 0.0, 0.0, 0.0]])
+    run_both(gpu, orc, ch, tr, exec=ex)
+
+
 @pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
 def test_single_interior_plane(gpu, orc, ex):
     ch = W.chamber(6, 6, 2, 2e-4, 4e-4, 5.0)
