@@ -259,6 +259,25 @@ def test_two_node_wide_cells(gpu, orc, ex, bc):
     run_both(gpu, orc, ch, tr, exec=ex)
 
 
+def test_pair_tiles_fall_back_on_unaligned_workspace(gpu, orc):
+    """Tiles of column pairs need 16-byte aligned fields: on a workspace that
+    starts 8 bytes past such a boundary the automatic choice falls back to
+    64-wide tiles (same results), and asking for pairs is refused."""
+    import torch
+    ch, tr = ragged_case(max_steps=30, stop_tol=0.0)  # nx = 70: pairs by default
+    big = torch.empty(gpu.it_workspace_size(ch, tr.shape[0]) + 8, dtype=torch.uint8, device="cuda")
+    ws = big[8:]
+    assert ws.data_ptr() % 16 == 8
+    g = gpu.it_solve(ch, tr, ws=ws, trace=True, fields=True)
+    o = orc.solve(ch, tr, with_trace=True, with_fields=True)
+    compare_results(g, o)
+    compare_fields(g["pos"], o["pos"])
+    compare_fields(g["neg"], o["neg"])
+    with pytest.raises(gpu.ItError) as e:
+        gpu.it_solve(ch, tr, exec=dict(kernel=1, tile_x=128), ws=ws)
+    assert e.value.code == gpu.IT_EINVAL
+
+
 @pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
 def test_single_interior_plane(gpu, orc, ex):
     ch = W.chamber(6, 6, 2, 2e-4, 4e-4, 5.0)
