@@ -21,6 +21,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# Timing build of the same source: the plane loops shared among OpenMP
+# threads.  Every grid sum goes through per-plane partial sums added in plane
+# order, so it returns the same bits as the single-threaded build (a CPU test
+# checks this).
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared"]
 
 P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
           "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit",
@@ -43,24 +49,49 @@ NT = len(TRACE_KEYS)
 FLAG_MAX_STEPS, FLAG_NONFINITE, FLAG_REACTION, FLAG_EMPTY = 1, 2, 4, 8
 
 
+def _stale(path):
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, IEEE arithmetic, no FMA)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain -O2, IEEE arithmetic, no FMA):
+    the single-threaded build and the OpenMP timing build."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or _stale(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *_CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB
 
 
-_lib = None
+_libs = {}
+_threaded = False
+
+
+def use_threads(flag: bool) -> None:
+    """Route every following call to the OpenMP build (True) or to the
+    single-threaded build (False, the default).  Both give the same bits."""
+    global _threaded
+    _threaded = bool(flag)
+
+
+def threads() -> int:
+    """Threads the current build's plane loops use."""
+    return int(lib().orc_threads())
 
 
 def lib():
-    global _lib
-    if _lib is None:
+    key = "omp" if _threaded else "plain"
+    if key not in _libs:
         build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIB_OMP if _threaded else _LIB)
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_electron_dt.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
+        L.orc_electron_dt.restype = ctypes.c_double
+        L.orc_step3.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.c_double] + [ctypes.POINTER(ctypes.c_double)] * 7
+        L.orc_step3.restype = None
         dp = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64
         L.orc_dt.argtypes = [dp, i64, i64, i64, dp, i64, dp]
@@ -83,8 +114,8 @@ def lib():
         L.orc_solve_free_electrons.restype = ctypes.c_int
         L.orc_free_fraction.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_free_fraction.restype = ctypes.c_double
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _ptr(a):
@@ -137,6 +168,22 @@ def dt(ch, tracks=None) -> float:
 def free_fraction(a, d) -> float:
     """p of eq. free_elec."""
     return lib().orc_free_fraction(float(a), float(d))
+
+
+def electron_dt(ch) -> float:
+    """Largest electron step of eq. vNeum (mu_e, D_e), without kappa."""
+    return float(lib().orc_electron_dt(_ptr(_params(ch)), ch["nz"]))
+
+
+def step3(ch, dt_, pos, neg, ele):
+    """One electron-phase step of the three carriers; returns (new_pos,
+    new_neg, new_ele, tally dict with keys E_TRACE_KEYS)."""
+    pos, neg, ele = (np.ascontiguousarray(a, dtype=np.float64) for a in (pos, neg, ele))
+    outs = [np.zeros_like(pos) for _ in range(3)]
+    tally = np.zeros(len(E_TRACE_KEYS))
+    lib().orc_step3(_ptr(_params(ch)), ch["nx"], ch["ny"], ch["nz"], dt_, _ptr(pos), _ptr(neg), _ptr(ele),
+                    _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), _ptr(tally))
+    return outs[0], outs[1], outs[2], dict(zip(E_TRACE_KEYS, tally))
 
 
 def weights(ch, dt_, species: int):

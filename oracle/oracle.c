@@ -7,7 +7,13 @@
  * only see the same input dictionaries and track arrays.
  *
  * The arithmetic follows the paper step by step, written for clarity, not
- * speed: single-threaded triple loops, no blocking, no fusion.
+ * speed: plain triple loops, no blocking, no fusion.  Every grid sum (the
+ * per-step tallies, the released counts of a deposit) is taken plane by
+ * plane into per-plane partial sums, which are then added in plane order.
+ * The order of every floating-point operation is therefore fixed by the
+ * grid alone: the default build is single-threaded, and a timing build with
+ * OpenMP (-fopenmp: the plane loops are shared among threads) returns the
+ * same bits.
  *
  *   - linear ion-pair density N0 = LET / W                    (eq. linear_density)
  *   - Gaussian radial track profile n0(r) = N0/(pi b^2) e^{-r^2/b^2}   (eq. Gaussian),
@@ -59,6 +65,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* parameter vector (mirrors the chamber dictionary) */
 enum {
@@ -90,6 +99,16 @@ enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_I
 #define FLAG_EMPTY 8
 
 #define IDX(k, j, i) (((size_t)(k) * (size_t)ny + (size_t)(j)) * (size_t)nx + (size_t)(i))
+
+/* Threads the plane loops use: 1 in the default build. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* Largest dt satisfying eq. vNeum for both species (no safety factor).
  * With the field along z only, cx = cy = 0: the product condition holds
@@ -271,25 +290,37 @@ void orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
 {
   const double dV = p[P_DX] * p[P_DY] * (p[P_GAP] / (double)nz);
   released[0] = released[1] = 0.0;
+  double *plane_sum = (double *)calloc((size_t)(nz + 1) * 2, sizeof(double));
+  if (!plane_sum) { released[0] = released[1] = NAN; return; }
   for (int64_t t = 0; t < ntr; ++t) {
     const double *tr = trk + TRK * t;
     if (orc_deposit_step(dt, tr) != step) continue;
     double u[3];
     track_axis(tr, u);
-    double sum[2] = {0.0, 0.0};
-    for (int64_t k = 1; k < nz; ++k)
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 1; k < nz; ++k) {
+      double sp = 0.0, sn = 0.0;
       for (int64_t j = 0; j < ny; ++j)
         for (int64_t i = 0; i < nx; ++i) {
           const double dp = track_density(p, nx, ny, nz, tr, u, 0, i, j, k);
           const double dn = track_density(p, nx, ny, nz, tr, u, 1, i, j, k);
           pos[IDX(k, j, i)] += dp;
           neg[IDX(k, j, i)] += dn;
-          sum[0] += dp;
-          sum[1] += dn;
+          sp += dp;
+          sn += dn;
         }
+      plane_sum[2 * k] = sp;
+      plane_sum[2 * k + 1] = sn;
+    }
+    double sum[2] = {0.0, 0.0};
+    for (int64_t k = 1; k < nz; ++k) {
+      sum[0] += plane_sum[2 * k];
+      sum[1] += plane_sum[2 * k + 1];
+    }
     released[0] += sum[0] * dV;
     released[1] += sum[1] * dV;
   }
+  free(plane_sum);
 }
 
 /* Uniform pre-ionisation n0 of both species at every interior node. */
@@ -348,14 +379,23 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
   orc_weights(p, nz, dt, 1, w[1]);
   const double *in[2] = {pos, neg};
   double *out[2] = {npos, nneg};
-  double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0}, screen[2] = {0.0, 0.0};
-  double escaped[2] = {0.0, 0.0};
   const int absorbing = p[P_LATERAL_BC] != 0.0;
+  /* per-plane partial sums: recombined, then in flight, |n|, space-charge
+   * change and escaped for each species */
+  enum { S_REC, S_IN0, S_IN1, S_ABS0, S_ABS1, S_SC0, S_SC1, S_ESC0, S_ESC1, S_N };
+  double *part = (double *)calloc((size_t)(nz + 1) * S_N, sizeof(double));
+  if (!part) {
+    for (int q = 0; q < T_COUNT; ++q) tally[q] = NAN;
+    return;
+  }
   /* mu dt q/eps0 per species, signed as the term enters n' (- for n+, + for n-) */
   const double sc_on = p[P_SPACE_CHARGE] != 0.0 ? 1.0 : 0.0;
   const double gsc[2] = {-sc_on * p[P_MU_POS] * dt * Q_E / EPS0, sc_on * p[P_MU_NEG] * dt * Q_E / EPS0};
 
-  for (int64_t k = 1; k < nz; ++k)
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 1; k < nz; ++k) {
+    double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0}, screen[2] = {0.0, 0.0};
+    double escaped[2] = {0.0, 0.0};
     for (int64_t j = 0; j < ny; ++j)
       for (int64_t i = 0; i < nx; ++i) {
         const double np_ = pos[IDX(k, j, i)], nn_ = neg[IDX(k, j, i)];
@@ -387,6 +427,31 @@ void orc_step(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
           absolute[s] += fabs(v);
         }
       }
+    double *pk = part + (size_t)k * S_N;
+    pk[S_REC] = recomb;
+    pk[S_IN0] = inflight[0];
+    pk[S_IN1] = inflight[1];
+    pk[S_ABS0] = absolute[0];
+    pk[S_ABS1] = absolute[1];
+    pk[S_SC0] = screen[0];
+    pk[S_SC1] = screen[1];
+    pk[S_ESC0] = escaped[0];
+    pk[S_ESC1] = escaped[1];
+  }
+  /* the planes' partial sums in plane order */
+  double recomb = 0.0, inflight[2] = {0.0, 0.0}, absolute[2] = {0.0, 0.0}, screen[2] = {0.0, 0.0};
+  double escaped[2] = {0.0, 0.0};
+  for (int64_t k = 1; k < nz; ++k) {
+    const double *pk = part + (size_t)k * S_N;
+    recomb += pk[S_REC];
+    for (int s = 0; s < 2; ++s) {
+      inflight[s] += pk[S_IN0 + s];
+      absolute[s] += pk[S_ABS0 + s];
+      screen[s] += pk[S_SC0 + s];
+      escaped[s] += pk[S_ESC0 + s];
+    }
+  }
+  free(part);
 
   /* Collected in this step: what the electrode planes would receive from
    * their interior neighbours.  Plane 0 gets the weight of n_{k+1} from node
@@ -604,8 +669,11 @@ double orc_free_fraction(double a, double d)
   return x == 0.0 ? 1.0 : -expm1(-x) / x;
 }
 
-/* Largest dt of eq. vNeum for the electrons (field along z). */
-static double electron_dt(const double *p, int64_t nz)
+/* Largest dt of eq. vNeum for the electrons (field along z): the positive
+ * root of A dt + B dt^2 = 1 with A = 2 D_e (1/dx^2 + 1/dy^2 + 1/dz^2) and
+ * B = (mu_e E / dz)^2, without the safety factor.  INFINITY if the electrons
+ * neither drift nor diffuse. */
+double orc_electron_dt(const double *p, int64_t nz)
 {
   const double dz = p[P_GAP] / (double)nz;
   const double E = p[P_VOLT] / p[P_GAP];
@@ -617,10 +685,16 @@ static double electron_dt(const double *p, int64_t nz)
   return INFINITY;
 }
 
-/* One phase-1 step of the three carriers from the old densities. */
-static void step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
-                  const double *pos, const double *neg, const double *ele,
-                  double *npos, double *nneg, double *nele, double *tally)
+/* One phase-1 step of the three carriers (n+, n-, n_e) from the old
+ * densities, each with the Appendix's weights for its own signed drift
+ * velocity (+mu+ E, -mu- E, -mu_e E) and diffusion constant; the positive
+ * ions lose beta n+ (n- + n_e), the negative ions beta n+ n-, the electrons
+ * beta n+ n_e.  tally: E_COUNT values (recombined pairs n+n- and n+n_e,
+ * collected at the anode and the cathode per carrier, in flight and the sum
+ * of |n| per carrier after the step), in counts (density times dV). */
+void orc_step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
+               const double *pos, const double *neg, const double *ele,
+               double *npos, double *nneg, double *nele, double *tally)
 {
   const double dz = p[P_GAP] / (double)nz;
   const double dV = p[P_DX] * p[P_DY] * dz;
@@ -638,8 +712,15 @@ static void step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt
   }
   const double *in[3] = {pos, neg, ele};
   double *out[3] = {npos, nneg, nele};
-  double rpn = 0.0, rpe = 0.0, inflight[3] = {0, 0, 0}, absolute[3] = {0, 0, 0};
-  for (int64_t k = 1; k < nz; ++k)
+  /* per-plane partial sums: rpn, rpe, in flight and |n| of each carrier */
+  double *part = (double *)calloc((size_t)(nz + 1) * 8, sizeof(double));
+  if (!part) {
+    for (int q = 0; q < E_COUNT; ++q) tally[q] = NAN;
+    return;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 1; k < nz; ++k) {
+    double rpn = 0.0, rpe = 0.0, inflight[3] = {0, 0, 0}, absolute[3] = {0, 0, 0};
     for (int64_t j = 0; j < ny; ++j)
       for (int64_t i = 0; i < nx; ++i) {
         const int64_t ip = (i + 1) % nx, im = (i + nx - 1) % nx;
@@ -664,6 +745,25 @@ static void step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt
           absolute[s] += fabs(v);
         }
       }
+    double *pk = part + (size_t)k * 8;
+    pk[0] = rpn;
+    pk[1] = rpe;
+    for (int s = 0; s < 3; ++s) {
+      pk[2 + s] = inflight[s];
+      pk[5 + s] = absolute[s];
+    }
+  }
+  double rpn = 0.0, rpe = 0.0, inflight[3] = {0, 0, 0}, absolute[3] = {0, 0, 0};
+  for (int64_t k = 1; k < nz; ++k) {
+    const double *pk = part + (size_t)k * 8;
+    rpn += pk[0];
+    rpe += pk[1];
+    for (int s = 0; s < 3; ++s) {
+      inflight[s] += pk[2 + s];
+      absolute[s] += pk[5 + s];
+    }
+  }
+  free(part);
   for (int s = 0; s < 3; ++s) {
     const double c = w[s][0], sz = w[s][3];
     const double w_up = sz + 0.5 * c * c - 0.5 * c, w_down = sz + 0.5 * c * c + 0.5 * c;
@@ -702,7 +802,7 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
   double dt;
   int rc = orc_dt(p, nx, ny, nz, trk, ntr, &dt);
   if (rc) return rc;
-  double dt1 = p[P_KAPPA] * electron_dt(p, nz);
+  double dt1 = p[P_KAPPA] * orc_electron_dt(p, nz);
   if (dt < dt1) dt1 = dt;
   const int64_t n = (nz + 1) * ny * nx;
   const double dz = p[P_GAP] / (double)nz;
@@ -762,7 +862,7 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
   int cur = 0;
   while (rel_e > 0.0 && steps_e < max_steps) {
     double tally[E_COUNT];
-    step3(p, nx, ny, nz, dt1, a[3 * cur], a[3 * cur + 1], a[3 * cur + 2],
+    orc_step3(p, nx, ny, nz, dt1, a[3 * cur], a[3 * cur + 1], a[3 * cur + 2],
           a[3 * (1 - cur)], a[3 * (1 - cur) + 1], a[3 * (1 - cur) + 2], tally);
     cur = 1 - cur;
     if (trace_e) memcpy(trace_e + E_COUNT * steps_e, tally, sizeof(tally));

@@ -6,9 +6,11 @@ touches the GPU library.  Each case writes one JSON file next to this script:
     python tests/golden/make_golden.py single_track pulsed_full pulsed_fields \
         continuous_window sweep:0-95        (or sweep:3,17,40 for a list)
 
-Runtime (single core): single_track ~1 s, pulsed_fields ~2 min,
-continuous_window ~2 min, pulsed_full ~45 min, sweep instances from seconds
-to an hour each (run them in parallel processes).
+The oracle runs in its OpenMP build, which returns the same bits as the
+single-threaded one (tests/test_oracle_threads.py).  Runtime on 8 host
+cores: single_track ~1 s, pulsed_fields ~1 min, continuous_window (2000
+steps of 512 x 512 x 256) ~30 min, pulsed_full ~30 min, sweep instances from
+seconds to twenty minutes each.
 """
 from __future__ import annotations
 
@@ -25,6 +27,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
+
+oracle.use_threads(True)
 
 RESULT_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos", "n_inflight_neg",
                "col_pos_anode", "col_pos_cathode", "col_neg_anode", "col_neg_cathode", "dt", "steps",
@@ -96,27 +100,23 @@ def case_pulsed_fields():
 
 
 def case_continuous_window():
-    """The continuous-beam grid (512 x 512 x 256) for a fixed window: four
-    tilted tracks at t = 0 and two more arriving mid-window, so that the
-    window contains three deposit events."""
-    ch, tr = W.continuous_beam(duration_s=0.0, forced=6)
-    dt = oracle.dt(ch, tr)
-    tr[4, 6] = 11.5 * dt
-    tr[5, 6] = 37.25 * dt
-    assert oracle.dt(ch, tr) == dt
-    ch.update(max_steps=64, stop_tol=0.0)
+    """The continuous-beam window (512 x 512 x 256, 2000 steps): four tilted
+    tracks at t = 0 and four more arriving inside the window, five deposit
+    events in all."""
+    ch, tr = W.continuous_window()
+    t0 = time.time()
     r = oracle.solve(ch, tr, with_trace=True, with_fields=True)
+    assert r["steps"] == W.WINDOW_STEPS
     _write("continuous_window", {"chamber": ch, "tracks": tr.tolist(), "result": _result(r),
                                  "trace": r["trace"].tolist(),
-                                 "fields": _field_summary(r["pos"], r["neg"], seed=13)})
+                                 "fields": _field_summary(r["pos"], r["neg"], seed=13),
+                                 "seconds": time.time() - t0})
 
 
 def case_sweep(instances):
     chs, trs = W.batched_sweep()
     for q in instances:
         name = f"sweep_{q:03d}"
-        if os.path.exists(os.path.join(HERE, name + ".json")):
-            continue
         t0 = time.time()
         r = oracle.solve(chs[q], trs[q], with_trace=False, with_fields=False)
         _write(name, {"instance": q, "result": _result(r), "seconds": time.time() - t0})

@@ -266,6 +266,47 @@ def test_drift_diffusion_moments_exact(orc):
         assert vb - va == pytest.approx(2 * D * dt * steps, rel=1e-9)
 
 
+def _spread_track_error(orc, refine):
+    """Max-norm error, relative to the peak, of the mid-gap profile of a
+    track column after pure diffusion to b^2 + 4 D t = 2 b^2, against the
+    spread Gaussian N0/(pi (b^2 + 4 D t)) exp(-r^2/(b^2 + 4 D t)) (eq.
+    Gaussian with the radius of a diffusing column), for both species."""
+    b = 1e-3
+    h = b / (4 * refine)
+    n = 40 * refine
+    D = {"pos": 0.03, "neg": 0.05}
+    ch = W.chamber(n, n, n, h, n * 2 * h, 0.0, alpha=0.0, D_pos=D["pos"], D_neg=D["neg"],
+                   dt_safety=0.5, stop_tol=0.0)
+    tr = W.tracks([[10.0, b, (n // 2) * h, (n // 2) * h, 0.0, 0.0, 0.0]])
+    dt = orc.dt(ch)
+    steps = 36 * refine * refine        # t = b^2/(4 D_neg) at both resolutions
+    ch["max_steps"] = steps
+    r = orc.solve(ch, tr)
+    t = steps * dt
+    j, i = np.indices((n, n))
+    r2 = ((i - n // 2) * h) ** 2 + ((j - n // 2) * h) ** 2
+    N0 = 10.0 * 1e7 / 34.0
+    err = {}
+    for s in ("pos", "neg"):
+        w2 = b * b + 4 * D[s] * t
+        exact = N0 / (math.pi * w2) * np.exp(-r2 / w2)
+        err[s] = np.max(np.abs(r[s][n // 2] - exact)) / exact.max()
+    return err, dt
+
+
+def test_gaussian_track_spreading_converges_at_second_order(orc):
+    """P3b: a Gaussian column under pure diffusion stays Gaussian with
+    b^2 -> b^2 + 4 D t.  The explicit scheme reaches that profile with an
+    O(dx^2) + O(dt) error, so halving every spacing (dt / 4, four times the
+    steps) divides the error by about 4."""
+    e1, dt1 = _spread_track_error(orc, 1)
+    e2, dt2 = _spread_track_error(orc, 2)
+    assert dt2 == pytest.approx(dt1 / 4, rel=1e-14)
+    for s in ("pos", "neg"):
+        assert e1[s] < 2e-2
+        assert 3.6 < e1[s] / e2[s] < 4.4, (s, e1[s], e2[s])
+
+
 # ---------------------------------------------------------------------------
 # deposition: eqs. linear_density, Gaussian, created; requirement (i)
 # ---------------------------------------------------------------------------

@@ -163,6 +163,26 @@ def continuous_beam(seed: int = SEED_BASE + 3, duration_s: float = 0.0, forced: 
     return ch, tracks(np.stack([let, b, x, y, theta, phi, np.asarray(times)], axis=1))
 
 
+# Arrival times [s] of the continuous-beam window's tracks: four at t = 0
+# and one at each of four later instants inside the window.
+WINDOW_TIMES = (0.0, 0.0, 0.0, 0.0, 8.0e-6, 2.0e-5, 3.4e-5, 4.6e-5)
+WINDOW_STEPS = 2000
+
+
+def continuous_window(steps: int = WINDOW_STEPS):
+    """A fixed window of the continuous beam on its 512x512x256 grid: the
+    first eight tracks the continuous-beam generator draws (tilted 0-30 deg,
+    LET log-uniform on [1, 300] keV/um), four arriving at t = 0 and one at
+    each of 8, 20, 34 and 46 us, stepped for exactly ``steps`` time steps
+    (stop_tol = 0).  The densest track bounds the time step (reaction
+    limit), and at that step the four later arrivals fall inside a
+    2000-step window, so the window holds five deposit events."""
+    ch, tr = continuous_beam(duration_s=0.0, forced=len(WINDOW_TIMES))
+    tr[:, 6] = WINDOW_TIMES
+    ch.update(max_steps=int(steps), stop_tol=0.0)
+    return ch, tr
+
+
 def shaped_pulse(ch, seed: int, fluence_cm2: float, shape, t_end: float, shape_max: float, let=50.0,
                  b=1e-3, theta=0.0, region: str = "cell", r_min: float | None = None) -> np.ndarray:
     """Tracks of a pulse of finite length (section "Distribution of ion
