@@ -28,12 +28,19 @@
  *
  * Conventions of every entry point:
  *   - return 0 (IT_OK) on success or a negative IT_E* code; nothing is thrown
- *     across the ABI; it_strerror() names the code;
+ *     across the ABI; it_strerror() names the code.  Entry points that
+ *     launch device work first clear the HIP runtime's last-error state of
+ *     the calling thread (hipGetLastError), so that an error an earlier,
+ *     unrelated HIP call left there is not taken for one of theirs;
  *   - the caller owns every buffer.  "host" pointers are ordinary CPU memory,
- *     "device" pointers are HIP device memory of the current device;
+ *     "device" pointers are HIP device memory of the current device.  The
+ *     library allocates no memory, device or host: scratch space comes from
+ *     the caller's workspace and, optionally, its page-locked host buffer
+ *     (it_exec.host_buffer).  Within a call it creates and destroys HIP
+ *     events and, in it_solve_batch, one HIP graph and its executable;
  *   - device work runs on the HIP stream passed as `stream` (a hipStream_t,
- *     NULL = the default stream).  Calls that return host results
- *     synchronise that stream before returning;
+ *     NULL = the default stream) and on no other stream.  Calls that return
+ *     host results synchronise that stream before returning;
  *   - the workspace is device memory of at least it_workspace_size() bytes;
  *     its contents need not be initialised and are clobbered.  Calls that
  *     share one workspace must not overlap in time.
@@ -188,10 +195,12 @@ typedef struct {
    * events bracket the stepping kernel launch (with one step per launch it
    * also records the previous step's tallies in an extra block; the blocked
    * kernel's tally reduction is a separate launch outside the events).  With
-   * timing_span = 1 instead (n_timing_events >= 2), only
-   * events[0] is recorded, before the first stepping launch, and events[1]
-   * after the last one: the span of all stepping launches of the call,
-   * without events between them.  The computation is unchanged.  Ignored by
+   * timing_span = 1 instead (n_timing_events >= 2), events bracket runs of
+   * consecutive stepping launches, with no events inside a run: a run ends
+   * where a deposit interrupts the stepping (and at the end of the call);
+   * events[2r] is recorded before the first stepping launch of run r and
+   * events[2r+1] after its last one, for r < n_timing_events / 2 (later runs
+   * are not timed).  The computation is unchanged.  Ignored by
    * it_solve_batch. */
   void* const* timing_events;
   int32_t n_timing_events;
@@ -203,7 +212,20 @@ typedef struct {
                             * 64 column pairs, one pair per lane: single chambers with an even
                             * nx only, IT_EINVAL otherwise; batches return IT_ENOTSUP, and the
                             * blocked kernel does not take it); 0 = default */
+  /* Optional page-locked host memory (hipHostMalloc, or a pinned tensor) of
+   * at least it_host_buffer_size() bytes, owned by the caller and clobbered
+   * by the call: the run state the host reads back to decide when to stop
+   * lands there while the device keeps stepping (two read-backs in flight).
+   * NULL (or too small): the library reads into ordinary host memory, which
+   * makes every read-back synchronous, so the device idles while the host
+   * decides on the next launches. */
+  void* host_buffer;
+  size_t host_buffer_bytes;
 } it_exec;
+
+/* Bytes of it_exec.host_buffer for a single run (ninst = 1) or a batch of
+ * ninst chambers.  Host only.  Errors: IT_EINVAL (ninst < 1). */
+int it_host_buffer_size(int32_t ninst, size_t* bytes);
 
 /* Time step of a run: dt_safety times the smaller of
  *   - the largest dt satisfying eq. vNeum for both species (with the field

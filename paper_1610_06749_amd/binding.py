@@ -58,7 +58,8 @@ class it_exec(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("timing_events", ctypes.POINTER(ctypes.c_void_p)), ("n_timing_events", ctypes.c_int32),
-                ("z_chunk", ctypes.c_int32), ("timing_span", ctypes.c_int32), ("tile_x", ctypes.c_int32)]
+                ("z_chunk", ctypes.c_int32), ("timing_span", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("host_buffer", ctypes.c_void_p), ("host_buffer_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -79,6 +80,7 @@ def lib():
         L.it_dt.argtypes = [chp, vp, i64, dp]
         L.it_validate.argtypes = [chp, vp, i64]
         L.it_workspace_size.argtypes = [chp, i64, ctypes.POINTER(ctypes.c_size_t)]
+        L.it_host_buffer_size.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.it_solve.argtypes = [chp, vp, i64, ctypes.POINTER(it_exec), vp, ctypes.c_size_t, vp, vp, vp, vp,
                                ctypes.POINTER(it_result)]
         L.it_advance.argtypes = [chp, ctypes.c_double, i64, ctypes.POINTER(it_exec), vp, vp, vp,
@@ -97,7 +99,7 @@ def lib():
                                    ctypes.c_float, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
         L.it_mlp_query_ws_bytes.argtypes = [i64, szp]
         L.it_mlp_query.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
-        for name in ("it_dt", "it_validate", "it_workspace_size", "it_solve", "it_advance",
+        for name in ("it_dt", "it_validate", "it_workspace_size", "it_host_buffer_size", "it_solve", "it_advance",
                      "it_workspace_size_batch", "it_solve_batch", "it_mlp_model_bytes", "it_mlp_init",
                      "it_mlp_train_ws_bytes", "it_mlp_grad", "it_mlp_train", "it_mlp_query_ws_bytes",
                      "it_mlp_query", "it_mlp_baseline"):
@@ -144,10 +146,34 @@ def _tracks(tracks):
     return tr, (tr.ctypes.data if tr.shape[0] else None)
 
 
-def _exec(ex):
-    if ex is None:
-        return None
+def it_host_buffer_size(ninst: int = 1) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().it_host_buffer_size(int(ninst), ctypes.byref(out)), "it_host_buffer_size")
+    return out.value
+
+
+_host_buffers = {}
+
+
+def host_buffer(ninst: int = 1):
+    """A page-locked host tensor of it_host_buffer_size(ninst) bytes (the
+    caller-owned read-back buffer of it_exec), kept for reuse by calls of the
+    same size that do not overlap."""
+    import torch
+    need = it_host_buffer_size(ninst)
+    buf = _host_buffers.get(need)
+    if buf is None:
+        buf = torch.empty(need, dtype=torch.uint8, pin_memory=True)
+        _host_buffers[need] = buf
+    return buf
+
+
+def _exec(ex, ninst: int = 1, host: bool = True):
+    """it_exec for the call: the caller's options (dict or None) plus, when
+    ``host``, a page-locked read-back buffer (``host_buffer``: a pinned
+    tensor, False for none, or absent for the binding's own)."""
     e = it_exec()
+    ex = ex or {}
     for k in ("kernel", "steps_per_pass", "tile_y", "check_every", "z_chunk", "tile_x"):
         setattr(e, k, int(ex.get(k, 0)))
     tev = ex.get("timing_events")
@@ -155,6 +181,12 @@ def _exec(ex):
         e.timing_events = tev.handles
         e.n_timing_events = len(tev.handles)
         e.timing_span = 1 if tev.span else 0
+    hb = ex.get("host_buffer") if host else False
+    if hb is None:
+        hb = host_buffer(ninst)
+    if hb is not False:
+        e.host_buffer = ctypes.c_void_p(hb.data_ptr())
+        e.host_buffer_bytes = hb.numel() * hb.element_size()
     return ctypes.byref(e)
 
 
@@ -192,20 +224,20 @@ class KernelTimer:
     """Timing events for the stepping kernel: pass as ``exec["timing_events"]``
     to it_solve / it_advance; the library records a pair around each of the
     first ``launches`` stepping-kernel launches of the call, or, with
-    ``span=True``, one event before the first and one after the last
-    stepping launch.  ``durations()`` returns the measured times in seconds
-    (after the call returned): one per launch, or the one span."""
+    ``span=True``, a pair around each of the first ``launches`` runs of
+    consecutive stepping launches (a deposit ends a run).  ``durations()``
+    returns the measured times in seconds (after the call returned): one per
+    launch, or one per run."""
 
     def __init__(self, launches=1, span=False):
         self.span = bool(span)
-        if self.span:
-            launches = 1
         L = lib()
         self._L = L
         L.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
         L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         L.hipEventSynchronize.argtypes = [ctypes.c_void_p]
         L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        L.hipGetLastError.argtypes = []
         self.handles = (ctypes.c_void_p * (2 * int(launches)))()
         for k in range(2 * int(launches)):
             h = ctypes.c_void_p()
@@ -220,7 +252,10 @@ class KernelTimer:
             if self._L.hipEventSynchronize(self.handles[k + 1]) != 0:
                 raise RuntimeError("hipEventSynchronize failed")
             if self._L.hipEventElapsedTime(ctypes.byref(ms), self.handles[k], self.handles[k + 1]) != 0:
-                break  # launches beyond the ones the call issued were not recorded
+                # launches beyond the ones the call issued were not recorded;
+                # clear the error the query left in the runtime's state
+                self._L.hipGetLastError()
+                break
             out.append(ms.value * 1e-3)
         return np.array(out)
 
@@ -306,7 +341,7 @@ def _batch_args(chambers, track_lists):
 def it_workspace_size_batch(chambers, track_lists, exec=None) -> int:
     n, chs, offsets, _ = _batch_args(chambers, track_lists)
     out = ctypes.c_size_t()
-    _check(lib().it_workspace_size_batch(ctypes.addressof(chs), offsets.ctypes.data, n, _exec(exec),
+    _check(lib().it_workspace_size_batch(ctypes.addressof(chs), offsets.ctypes.data, n, _exec(exec, host=False),
                                          ctypes.byref(out)), "it_workspace_size_batch")
     return out.value
 
@@ -320,7 +355,7 @@ def it_solve_batch(chambers, track_lists, exec=None, ws=None, stream=None) -> li
         ws = torch.empty(it_workspace_size_batch(chambers, track_lists, exec), dtype=torch.uint8,
                          device="cuda")
     res = (it_result * n)()
-    rc = lib().it_solve_batch(ctypes.addressof(chs), offsets.ctypes.data, tracks.ctypes.data, n, _exec(exec),
+    rc = lib().it_solve_batch(ctypes.addressof(chs), offsets.ctypes.data, tracks.ctypes.data, n, _exec(exec, n),
                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream), ctypes.addressof(res))
     _check(rc, "it_solve_batch")
     return [_result(r) for r in res]

@@ -148,6 +148,12 @@ struct Step3Params {
 };
 hipError_t launch_step3(const Step3Params& p, hipStream_t s);
 
+// Launch errors are read with hipGetLastError(), which also returns an error
+// left by any earlier HIP call of the thread (the caller's included).  Entry
+// points that launch kernels clear that state first, so a stale error is not
+// reported as theirs.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // Launchers (stream-ordered, no synchronisation).
 // Tile shape of the one-step kernels: tile_x 32 gives 32 x 16 tiles (8 waves,
 // two rows each); tile_x 128 tiles of 128 columns (each lane a pair of
@@ -168,5 +174,9 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
 // previous pass's step of every instance (false only for the first pass)
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
                              bool ab, int parity, bool record_prev, hipStream_t s);
+// The same pass (recording the previous one) as a kernel node of `graph`
+// that depends on `dep` (null: none).
+hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNode_t* node, const void* table,
+                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, int parity);
 
 }  // namespace it

@@ -88,6 +88,52 @@ void launch_batch_terms(const BatchInstance* inst, int nrecord, int ninst, int t
 
 }  // namespace
 
+namespace {
+
+// The kernel instance of a pass and its block shape.
+template <int SY, int TX>
+const void* batch_kernel_terms(bool sc, bool ab) {
+  switch ((sc ? 2 : 0) + (ab ? 1 : 0)) {
+    case 0: return reinterpret_cast<const void*>(&batch_step_kernel<SY, false, false, TX>);
+    case 1: return reinterpret_cast<const void*>(&batch_step_kernel<SY, false, true, TX>);
+    case 2: return reinterpret_cast<const void*>(&batch_step_kernel<SY, true, false, TX>);
+    default: return reinterpret_cast<const void*>(&batch_step_kernel<SY, true, true, TX>);
+  }
+}
+
+const void* batch_kernel(int tile_y, int tile_x, bool sc, bool ab, int* sy) {
+  if (plain_tile_cols(tile_x) == 32) {
+    *sy = 8;
+    return batch_kernel_terms<8, 32>(sc, ab);
+  }
+  if (plain_tile_rows(tile_y, tile_x) == 16) {
+    *sy = 16;
+    return batch_kernel_terms<16, 64>(sc, ab);
+  }
+  *sy = 8;
+  return batch_kernel_terms<8, 64>(sc, ab);
+}
+
+}  // namespace
+
+hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNode_t* node, const void* table,
+                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, int parity) {
+  const BatchInstance* inst = (const BatchInstance*)table;
+  int per_xcd = (total_tiles + 7) / 8;
+  int sy = 8;
+  const void* fn = batch_kernel(tile_y, tile_x, sc, ab, &sy);
+  // the node copies the argument values when it is added
+  void* args[] = {(void*)&inst, (void*)&ninst, (void*)&total_tiles, (void*)&per_xcd, (void*)&parity};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(fn);
+  kp.gridDim = dim3(8 * per_xcd + ninst);  // tile blocks, then one recording block per instance
+  kp.blockDim = dim3(kTX, sy);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(node, graph, dep ? &dep : nullptr, dep ? 1 : 0, &kp);
+}
+
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
                              bool ab, int parity, bool record_prev, hipStream_t s) {
   const BatchInstance* inst = (const BatchInstance*)table;

@@ -1031,6 +1031,7 @@ int it_mlp_model_bytes(int32_t members, size_t* bytes) {
 
 int it_mlp_init(void* d_model, int32_t members, const float* h_params, const float* h_norm, const double* h_phys,
                 int32_t precision, void* stream_) {
+  clear_stale_error();
   if (!d_model || !h_params || !h_norm || members < 1 || members > 64) return IT_EINVAL;
   if (precision != IT_MLP_BF16 && precision != IT_MLP_FP32) return IT_EINVAL;
   hipStream_t s = (hipStream_t)stream_;
@@ -1105,6 +1106,7 @@ static int launch_grad(const Model& md, int M, bool f32, const float* X, const f
 
 int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n,
                 float* d_grad, float* h_loss, void* d_ws, size_t ws_bytes, void* stream_) {
+  clear_stale_error();
   if (!d_model || !d_X || !d_t || !d_grad || n < 1 || members < 1 || members > 64) return IT_EINVAL;
   if (!d_ws || ws_bytes < train_ws_bytes(members, n)) return IT_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream_;
@@ -1128,6 +1130,7 @@ int it_mlp_grad(const void* d_model, int32_t members, const float* d_X, const fl
 int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* d_t, int64_t n, int64_t batch,
                  int32_t steps, float lr, float lr_final, int32_t log_every, float* h_loss, void* d_ws,
                  size_t ws_bytes, void* stream_) {
+  clear_stale_error();
   if (!d_model || !d_X || !d_t || n < 1 || steps < 0 || members < 1 || members > 64 || !(lr > 0.0f) ||
       !(lr_final > 0.0f) || batch < 0 || batch > n)
     return IT_EINVAL;
@@ -1138,7 +1141,9 @@ int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* 
   Model md = carve_model(d_model, members);
   TrainWs w = carve_train(d_ws, members, rows);
   Header h;
-  if (hipMemcpy(&h, md.hdr, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return IT_EHIP;
+  if (hipMemcpyAsync(&h, md.hdr, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return IT_EHIP;
   const int64_t nbatch = n / rows;
   int nlog = 0;
   for (int k = 0; k < steps; ++k) {
@@ -1169,6 +1174,7 @@ int it_mlp_train(void* d_model, int32_t members, const float* d_X, const float* 
 }
 
 int it_mlp_baseline(const void* d_model, const float* d_X, int64_t n, double* d_out, void* stream_) {
+  clear_stale_error();
   if (!d_model || n < 0 || (n > 0 && (!d_X || !d_out))) return IT_EINVAL;
   if (n == 0) return IT_OK;
   hipStream_t s = (hipStream_t)stream_;
@@ -1187,6 +1193,7 @@ int it_mlp_query_ws_bytes(int64_t nq, size_t* bytes) {
 int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
                  float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
                  void* d_ws, size_t ws_bytes, void* stream_) {
+  clear_stale_error();
   if (!d_model || nq < 0 || (nq > 0 && (!d_X || !d_mean || !d_spread || !d_fallback))) return IT_EINVAL;
   size_t need;
   it_mlp_query_ws_bytes(nq, &need);

@@ -290,6 +290,16 @@ int check_exec(const it_chamber* ch, const it_exec* ex) {
   return IT_OK;
 }
 
+// The same check plus what depends on the workspace: an explicit request for
+// tiles of column pairs needs 16-byte aligned fields, and every field sits
+// at a 256-byte offset from the workspace's start.
+int check_exec_ws(const it_chamber* ch, const it_exec* ex, const void* ws) {
+  const int rc = check_exec(ch, ex);
+  if (rc) return rc;
+  if (ex && ex->tile_x == 128 && (uintptr_t)ws % 16 != 0) return IT_EINVAL;
+  return IT_OK;
+}
+
 Tiling deposit_tiling(int nx, int ny, int nz) {
   const long cols = (long)((nx + 63) / 64) * ((ny + 3) / 4);
   const int nint = nz - 1;
@@ -378,18 +388,32 @@ int64_t deposit_step(double t, double dt) {
   return (int64_t)s;
 }
 
-// Pinned host slots for reading the run state back: 4 per host thread and
-// device, allocated on first use and kept for the life of the process.
-RunState* pinned_slots() {
-  thread_local RunState* slots[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-  if (!slots[dev]) {
-    void* p = nullptr;
-    if (hipHostMalloc(&p, 4 * sizeof(RunState), hipHostMallocDefault) != hipSuccess) return nullptr;
-    slots[dev] = (RunState*)p;
+// Host memory the run states are read back into: the caller's page-locked
+// buffer when it is given and large enough (the device keeps stepping while
+// a copy is in flight), else ordinary memory held here for the call (the
+// copies then complete before the host goes on, so every read-back is
+// synchronous).
+constexpr size_t kHostSlots = 4;  // read-back slots of a single run
+
+size_t host_slots_needed(int ninst) { return std::max<size_t>(kHostSlots, 2 * (size_t)ninst); }
+
+struct HostSlots {
+  RunState* p = nullptr;
+  bool pinned = false;
+  std::vector<RunState> own;
+};
+
+void host_slots(const it_exec* ex, int ninst, HostSlots& h) {
+  const size_t n = host_slots_needed(ninst);
+  if (ex && ex->host_buffer && ex->host_buffer_bytes >= n * sizeof(RunState) &&
+      (uintptr_t)ex->host_buffer % alignof(RunState) == 0) {
+    h.p = (RunState*)ex->host_buffer;
+    h.pinned = true;
+  } else {
+    h.own.assign(n, RunState{});
+    h.p = h.own.data();
+    h.pinned = false;
   }
-  return slots[dev];
 }
 
 #define HIP_TRY(expr)                               \
@@ -463,7 +487,7 @@ struct Event {
 // flagged completion.
 int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const Layout& L,
              const std::vector<Event>& events, const std::vector<DepTrack>& dev_tracks, int same_r,
-             int64_t nsteps, int64_t min_stop_step, double stop_tol, hipStream_t stream,
+             int64_t nsteps, int64_t min_stop_step, double stop_tol, hipStream_t stream, HostSlots& hs,
              RunState* final_state, int* passes_issued) {
   const int exec_rc = check_exec(ch, ex);
   if (exec_rc) return exec_rc;
@@ -494,8 +518,10 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   const Tiling tp = step_tiling(ch->nx, ch->ny, ch->nz, rows, exec_z_chunk(ex), tx);
   const Tiling td = deposit_tiling(ch->nx, ch->ny, ch->nz);
 
-  RunState* slots = pinned_slots();
-  if (!slots) return IT_EHIP;
+  RunState* slots = hs.p;
+  // read-backs in flight: two with the caller's page-locked buffer, else one
+  // (an ordinary host buffer is filled before the copy call returns)
+  const int depth = hs.pinned ? 2 : 1;
 
   StepParams sp;
   sp.nx = ch->nx;
@@ -530,10 +556,25 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   int issued = 0;
   int64_t since_check = 0;
   int pending = 0, slot_head = 0;
+  // Span timing: one event pair per run of consecutive stepping launches
+  // (runs are separated by deposits), as long as the caller gave events for
+  // it; seg_open: the current run's first event is recorded.
+  const int n_spans = span ? ex->n_timing_events / 2 : 0;
+  int seg = 0;
+  bool seg_open = false;
   // caller's timing events of the launch about to be issued (null when none)
   auto ev_pair = [&](int which) -> hipEvent_t {
-    if (span) return which == 0 && issued == 0 ? (hipEvent_t)ex->timing_events[0] : nullptr;
+    if (span) {
+      if (which != 0 || seg_open || seg >= n_spans) return nullptr;
+      seg_open = true;
+      return (hipEvent_t)ex->timing_events[2 * seg];
+    }
     return issued < n_timing ? (hipEvent_t)ex->timing_events[2 * issued + which] : nullptr;
+  };
+  auto close_span = [&]() -> hipError_t {
+    if (!seg_open) return hipSuccess;
+    seg_open = false;
+    return hipEventRecord((hipEvent_t)ex->timing_events[2 * seg++ + 1], stream);
   };
   hipEvent_t evs[4];
   for (int q = 0; q < 4; ++q)
@@ -569,7 +610,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   while (l < nsteps && !stopped) {
     if (ev < events.size() && events[ev].step == l) {
       const Event& e = events[ev];
-      if (close_step() != hipSuccess) { fail(IT_EHIP); break; }
+      if (close_span() != hipSuccess || close_step() != hipSuccess) { fail(IT_EHIP); break; }
       dp.pos = field[2 * cur];
       dp.neg = field[2 * cur + 1];
       dp.uniform = e.uniform ? ch->uniform_n0 : 0.0;
@@ -621,7 +662,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
           hipEventRecord(evs[slot_head], stream) != hipSuccess) { fail(IT_EHIP); break; }
       slot_head = (slot_head + 1) & 3;
       ++pending;
-      if (pending >= 2) {
+      if (pending >= depth) {
         const int oldest = (slot_head + 4 - pending) & 3;
         if (hipEventSynchronize(evs[oldest]) != hipSuccess) { fail(IT_EHIP); break; }
         --pending;
@@ -629,8 +670,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       }
     }
   }
-  if (rc == IT_OK && span && issued > 0 && hipEventRecord((hipEvent_t)ex->timing_events[1], stream) != hipSuccess)
-    fail(IT_EHIP);
+  if (rc == IT_OK && close_span() != hipSuccess) fail(IT_EHIP);
   if (rc == IT_OK && close_step() != hipSuccess) fail(IT_EHIP);
   if (rc == IT_OK) {
     if (hipMemcpyAsync(&slots[slot_head], state, sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -729,31 +769,6 @@ int check_batch(const it_chamber* ch, const int64_t* toff, const it_track* track
   return IT_OK;
 }
 
-// Pinned host buffer for reading all instance states back (grown on demand,
-// kept per host thread for the life of the process).
-RunState* pinned_states(int n) {
-  thread_local RunState* buf = nullptr;
-  thread_local int cap = 0;
-  if (n > cap) {
-    if (buf) (void)hipHostFree(buf);
-    buf = nullptr;
-    cap = 0;
-    void* p = nullptr;
-    if (hipHostMalloc(&p, (size_t)n * 2 * sizeof(RunState), hipHostMallocDefault) != hipSuccess) return nullptr;
-    buf = (RunState*)p;
-    cap = n;
-  }
-  return buf;
-}
-
-hipStream_t capture_stream() {
-  thread_local hipStream_t s[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-  if (!s[dev] && hipStreamCreateWithFlags(&s[dev], hipStreamNonBlocking) != hipSuccess) return nullptr;
-  return s[dev];
-}
-
 void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, it_result* out) {
   std::memset(out, 0, sizeof(*out));
   const double collected = fin.sums[1] + fin.sums[2] + fin.sums[3] + fin.sums[4];
@@ -819,6 +834,12 @@ const char* it_strerror(int code) {
   }
 }
 
+int it_host_buffer_size(int32_t ninst, size_t* bytes) {
+  if (!bytes || ninst < 1) return IT_EINVAL;
+  *bytes = host_slots_needed(ninst) * sizeof(RunState);
+  return IT_OK;
+}
+
 int it_dt(const it_chamber* ch, const it_track* tracks, int64_t ntracks, double* dt) {
   if (!dt) return IT_EINVAL;
   int rc = check_chamber(ch);
@@ -846,7 +867,7 @@ int it_workspace_size(const it_chamber* ch, int64_t ntracks, size_t* bytes) {
 // flags the electrons collected, then leaves the ions in field pair 0.
 // Returns the phase's step count in *e_steps.
 int electron_phase(const it_chamber* ch, double dt_ion, char* ws, const Layout& L, hipStream_t stream,
-                   int64_t* e_steps) {
+                   RunState* slot, int64_t* e_steps) {
   const double dt1 = std::min(dt_ion, ch->dt_safety * electron_dt(ch));
   Step3Params p;
   std::memset(&p, 0, sizeof(p));
@@ -870,8 +891,6 @@ int electron_phase(const it_chamber* ch, double dt_ion, char* ws, const Layout& 
   p.state = (RunState*)(ws + L.off_state);
   double* pair[2][3] = {{(double*)(ws + L.off_field[0]), (double*)(ws + L.off_field[1]), (double*)(ws + L.off_ele[0])},
                         {(double*)(ws + L.off_field[2]), (double*)(ws + L.off_field[3]), (double*)(ws + L.off_ele[1])}};
-  RunState* slot = pinned_slots();
-  if (!slot) return IT_EHIP;
   // released electrons (set by the deposit): none means no electron phase
   HIP_TRY(hipMemcpyAsync(slot, p.state, sizeof(RunState), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -907,6 +926,7 @@ int electron_phase(const it_chamber* ch, double dt_ion, char* ws, const Layout& 
 int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, const it_exec* exec,
              void* d_workspace, size_t ws_bytes, void* stream_, double* h_trace, double* d_pos_out,
              double* d_neg_out, it_result* out) {
+  clear_stale_error();
   if (!out) return IT_EINVAL;
   int rc = it_validate(ch, tracks, ntracks);
   if (rc) return rc;
@@ -916,12 +936,14 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     for (int64_t q = 0; q < ntracks; ++q)
       if (tracks[q].t_s != 0.0) return IT_ENOTSUP;
   }
-  rc = check_exec(ch, exec);
+  rc = check_exec_ws(ch, exec, d_workspace);
   if (rc) return rc;
   const Layout L = make_layout(ch, ntracks);
   if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
   double dt;
   compute_dt(ch, tracks, ntracks, &dt);
+  HostSlots hs;
+  host_slots(exec, 1, hs);
   hipStream_t stream = (hipStream_t)stream_;
   char* ws = (char*)d_workspace;
 
@@ -1008,7 +1030,7 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     dp.counter = (unsigned*)(ws + L.off_counter);
     dp.state = (RunState*)(ws + L.off_state);
     if (!events.empty()) HIP_TRY(launch_deposit(dp, stream));
-    rc = electron_phase(ch, dt, ws, L, stream, &e_steps);
+    rc = electron_phase(ch, dt, ws, L, stream, hs.p, &e_steps);
     if (rc) return rc;
     events.clear();
     last_dep = 0;
@@ -1019,18 +1041,22 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
   const int64_t ion_steps = ch->max_steps - e_steps;
   if (ion_steps > 0) {
     rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ion_steps,
-                  std::max<int64_t>(last_dep, 0), ch->stop_tol, stream, &fin, &issued);
+                  std::max<int64_t>(last_dep, 0), ch->stop_tol, stream, hs, &fin, &issued);
     if (rc) return rc;
   } else {
-    HIP_TRY(hipMemcpy(&fin, ws + L.off_state, sizeof(fin), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(hs.p, ws + L.off_state, sizeof(fin), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    fin = *hs.p;
   }
 
   fill_result(fin, dt, ion_steps, issued, out);
   if (fe) out->e_dt = std::min(dt, ch->dt_safety * electron_dt(ch));
 
-  if (h_trace && fin.steps > 0)
-    HIP_TRY(hipMemcpy(h_trace, ws + L.off_trace, (size_t)fin.steps * IT_TRACE_COLS * sizeof(double),
-                      hipMemcpyDeviceToHost));
+  if (h_trace && fin.steps > 0) {
+    HIP_TRY(hipMemcpyAsync(h_trace, ws + L.off_trace, (size_t)fin.steps * IT_TRACE_COLS * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
   const int last = fin.passes & 1;  // field pair holding the latest densities
   if (d_pos_out)
     HIP_TRY(hipMemcpyAsync(d_pos_out, ws + L.off_field[2 * last], L.field_elems * sizeof(double),
@@ -1060,6 +1086,7 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
 int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_track* tracks,
                    int32_t ninst, const it_exec* exec, void* d_workspace, size_t ws_bytes, void* stream_,
                    it_result* out) {
+  clear_stale_error();
   if (!out) return IT_EINVAL;
   int rc = check_batch(ch, track_offsets, tracks, ninst);
   if (rc) return rc;
@@ -1171,9 +1198,10 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   // instances have stopped, so finished chambers cost no dispatches.  All
   // running instances have executed the same number of passes, so they
   // share the field parity and a rebuilt table keeps the graph's pattern.
-  RunState* host = pinned_states(ninst);
-  hipStream_t cs = capture_stream();
-  if (!host || !cs) return IT_EHIP;
+  HostSlots hs;
+  host_slots(exec, ninst, hs);
+  RunState* host = hs.p;
+  const int tile_x = exec_tile_x(exec, ch, ninst, false);
   std::vector<int> active(ninst);
   for (int q = 0; q < ninst; ++q) active[q] = q;
   hipGraph_t graph = nullptr;
@@ -1199,13 +1227,16 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
         hipStreamSynchronize(stream) != hipSuccess)  // t is pageable and local
       return IT_EHIP;
     release_graph();
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return IT_EHIP;
-    hipError_t ce = hipSuccess;
-    for (int k = 0; k < passes_per_graph && ce == hipSuccess; ++k)
-      ce = launch_batch_pass(ws + B.off_table, (int)t.size(), tiles, rows, exec_tile_x(exec, ch, ninst, false), any_sc, any_ab,
-                             (parity0 + k) & 1, true, cs);
-    const hipError_t ee = hipStreamEndCapture(cs, &graph);
-    if (ce != hipSuccess || ee != hipSuccess) return IT_EHIP;
+    // a chain of kernel nodes, each pass depending on the one before
+    if (hipGraphCreate(&graph, 0) != hipSuccess) return IT_EHIP;
+    hipGraphNode_t prev = nullptr;
+    for (int k = 0; k < passes_per_graph; ++k) {
+      hipGraphNode_t node = nullptr;
+      if (add_batch_pass_node(graph, prev, &node, ws + B.off_table, (int)t.size(), tiles, rows, tile_x, any_sc,
+                              any_ab, (parity0 + k) & 1) != hipSuccess)
+        return IT_EHIP;
+      prev = node;
+    }
     if (hipGraphInstantiate(&exec_graph, graph, nullptr, nullptr, 0) != hipSuccess) return IT_EHIP;
     return IT_OK;
   };
@@ -1221,8 +1252,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   {
     int tiles = 0;
     for (int q = 0; q < ninst; ++q) tiles += table[q].ntiles;
-    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, exec_tile_x(exec, ch, ninst, false), any_sc, any_ab, 0, false,
-                          stream) != hipSuccess) {
+    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, tile_x, any_sc, any_ab, 0, false, stream) !=
+        hipSuccess) {
       release_graph();
       return IT_EHIP;
     }
@@ -1244,6 +1275,12 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     RunState* slot = host + (r & 1) * ninst;
     if (hipMemcpyAsync(slot, states, (size_t)ninst * sizeof(RunState), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipEventRecord(evs[r & 1], stream) != hipSuccess) { rc = IT_EHIP; break; }
+    if (!hs.pinned) {  // an ordinary host buffer: the copy of this replay completes first
+      if (hipStreamSynchronize(stream) != hipSuccess) { rc = IT_EHIP; break; }
+      bool any = false;
+      for (int q : active) any = any || !slot[q].done;
+      if (!any) break;
+    }
     if (r >= 1) {
       RunState* prev = host + ((r - 1) & 1) * ninst;
       if (hipEventSynchronize(evs[(r - 1) & 1]) != hipSuccess) { rc = IT_EHIP; break; }
@@ -1280,9 +1317,10 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 
 int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* exec, double* d_pos,
                double* d_neg, void* d_workspace, size_t ws_bytes, void* stream_, double* h_trace) {
+  clear_stale_error();
   int rc = check_chamber(ch);
   if (rc) return rc;
-  rc = check_exec(ch, exec);
+  rc = check_exec_ws(ch, exec, d_workspace);
   if (rc) return rc;
   if (!d_pos || !d_neg || nsteps < 0 || nsteps > ch->max_steps) return IT_EINVAL;
   if (!(std::isfinite(dt) && dt > 0)) return IT_EINVAL;
@@ -1308,15 +1346,17 @@ int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* e
   std::vector<DepTrack> nodev;
   RunState fin;
   int issued = 0;
-  rc = run_loop(ch, dt, exec, ws, L, none, nodev, 1, nsteps, INT64_MAX, 0.0, stream, &fin, &issued);
+  HostSlots hs;
+  host_slots(exec, 1, hs);
+  rc = run_loop(ch, dt, exec, ws, L, none, nodev, 1, nsteps, INT64_MAX, 0.0, stream, hs, &fin, &issued);
   if (rc) return rc;
   const int last = fin.passes & 1;
   HIP_TRY(hipMemcpyAsync(d_pos, ws + L.off_field[2 * last], bytes, hipMemcpyDeviceToDevice, stream));
   HIP_TRY(hipMemcpyAsync(d_neg, ws + L.off_field[2 * last + 1], bytes, hipMemcpyDeviceToDevice, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
   if (h_trace)
-    HIP_TRY(hipMemcpy(h_trace, ws + L.off_trace, (size_t)nsteps * IT_TRACE_COLS * sizeof(double),
-                      hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(h_trace, ws + L.off_trace, (size_t)nsteps * IT_TRACE_COLS * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
   return IT_OK;
 }
 

@@ -126,7 +126,7 @@ def _solve_status(lib, ch, tr, ex):
     c = B._chamber(ch)
     rows, ptr = B._tracks(tr)
     res = B.it_result()
-    return B.lib().it_solve(ctypes.byref(c), ptr, rows.shape[0], B._exec(ex), None, 0, None, None, None, None,
+    return B.lib().it_solve(ctypes.byref(c), ptr, rows.shape[0], B._exec(ex, host=False), None, 0, None, None, None, None,
                             ctypes.byref(res))
 
 
@@ -160,6 +160,18 @@ def test_lateral_boundary_option_checks(lib, orc):
         c = dict(ch2, lateral_bc=bc)
         assert lib.it_dt(c, tr2) == pytest.approx(orc.dt(c, tr2), rel=1e-14)
     assert lib.it_dt(dict(ch2, lateral_bc=1), tr2) > lib.it_dt(ch2, tr2) * 1.01
+
+
+def test_host_buffer_size(lib):
+    """The caller's read-back buffer: slots for a single run, two per
+    chamber of a batch; refused for no chambers."""
+    one = lib.binding.it_host_buffer_size(1)
+    assert one > 0 and one % 8 == 0
+    assert lib.binding.it_host_buffer_size(96) == 2 * 96 * one // 4
+    assert lib.binding.it_host_buffer_size(2) == one  # at least the single-run slots
+    with pytest.raises(lib.ItError) as e:
+        lib.binding.it_host_buffer_size(0)
+    assert e.value.code == lib.IT_EINVAL
 
 
 def test_strerror_names_codes(lib):
