@@ -109,7 +109,9 @@ def test_pulsed_beam_fields_at_full_size(gpu, ex):
 
 @pytest.mark.parametrize("ex", EXECS, ids=EXEC_IDS)
 def test_continuous_beam_window_at_full_size(gpu, ex):
-    """512 x 512 x 256 nodes, tilted tracks, three deposit events in 64 steps."""
+    """512 x 512 x 256 nodes, eight tilted tracks, five deposit events in 2000 steps
+    (the benchmark's window): results, every per-step record and sampled fields
+    at the end."""
     gd = load("continuous_window")
     g = gpu.it_solve(gd["chamber"], np.asarray(gd["tracks"]), exec=ex, trace=True, fields=True)
     check_result(g, gd["result"])
