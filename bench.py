@@ -182,6 +182,33 @@ def window_run(it, W, a, ex):
     return ch, tr, results, elapsed, spans
 
 
+def one_step_roofline(it, W, ch, dt, ex, launches=200):
+    """The one-step kernel alone on the window's grid: `launches` steps of
+    it_advance from the window's initial state (its first deposit), the
+    stepping launches bracketed by one pair of HIP events."""
+    import torch
+    chk = dict(ch, max_steps=launches, stop_tol=0.0)
+    ws = it.workspace(chk, 0)
+    shape = (ch["nz"] + 1, ch["ny"], ch["nx"])
+    pos0, neg0 = W.perturbed_field(shape, seed=5, scale=1e9)
+    gp, gn = torch.tensor(pos0, device="cuda"), torch.tensor(neg0, device="cuda")
+    exk = dict(ex, kernel=it.IT_KERNEL_PLAIN, steps_per_pass=0)
+    it.it_advance(chk, dt, gp, gn, 20, exec=exk, ws=ws)
+    timer = it.KernelTimer(1, span=True)
+    it.it_advance(chk, dt, gp, gn, launches, exec=dict(exk, timing_events=timer), ws=ws)
+    torch.cuda.synchronize()
+    per_launch = float(timer.durations()[0]) / launches
+    nint = (ch["nz"] - 1) * ch["nx"] * ch["ny"]
+    achieved = BYTES_PER_VOXEL_STEP * nint / per_launch / 1e9
+    src = ["kernels_plain.hip", "stencil_plain.h", "reduce.h", "internal.h"]
+    traffic = read_traffic("step_plain", "continuous_512x512x256", kernel_source_hash(src), "tile_x 0 tile_y 8 z_chunk 0")
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": "step_plain",
+            "launch_ms": per_launch * 1e3, "launches_timed": launches,
+            "algorithmic_bytes_per_launch": BYTES_PER_VOXEL_STEP * nint,
+            "timing": f"{launches} launches of the one-step kernel on the window's grid, one pair of HIP events"}
+
+
 def pulsed_runs(it, W, ex, nruns=3):
     """The pulsed beam (256 x 256 x 200, 400 parallel tracks) to full
     collection: whole-run rate and the stepping launches' average time."""
@@ -261,21 +288,26 @@ def main():
              f"{elapsed / a.steps * 1e3:.1f} ms each")
 
     # stepping launches: their time (every run between deposits, summed) over
-    # their count; T steps per launch with the blocked kernel
+    # their count.  A launch reads and writes every interior node's two
+    # densities once (32 B per node, the compulsory HBM bytes of a pass)
+    # and advances them by steps / launches steps on average.
     launches = sum(r["passes"] for r in results)
+    steps_all = sum(r["steps"] for r in results)
     kern_sec = float(sum(sp.sum() for sp in spans))
     per_launch = kern_sec / launches
-    T_pass = max(1, round(sum(r["steps"] for r in results) / launches))
+    T_pass = max(1, round(steps_all / launches))
     kname = "step_plain" if T_pass == 1 else f"step_blocked_T{T_pass}"
     src = ["kernels_plain.hip", "stencil_plain.h", "reduce.h", "internal.h"] if T_pass == 1 else \
         ["kernels_blocked.hip", "reduce.h", "internal.h"]
-    bytes_per_launch = BYTES_PER_VOXEL_STEP * nint * T_pass  # compulsory traffic of one pass
+    bytes_per_launch = BYTES_PER_VOXEL_STEP * nint
     achieved = bytes_per_launch / per_launch / 1e9
+    effective = BYTES_PER_VOXEL_STEP * nint * steps_all / kern_sec / 1e9
     workload_name = "continuous_512x512x256"
     shape = f"tile_x {a.tile_x} tile_y {16 if a.tile_y == 16 else 8} z_chunk {a.z_chunk}" if T_pass == 1 else \
-        f"T {T_pass}"
+        f"T {T_pass} tile_y {a.tile_y}"
     traffic = read_traffic(kname, workload_name, kernel_source_hash(src), shape)
     progress(f"{kname}: {per_launch * 1e6:.1f} us per launch ({launches // a.steps} launches per run)")
+    one_step = one_step_roofline(it, W, ch, r0["dt"], ex) if T_pass > 1 else None
 
     cpu = None
     if not a.no_cpu:
@@ -347,8 +379,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": kname, "launch_ms": per_launch * 1e3, "launches_timed": launches,
+                     "steps_per_launch": steps_all / launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "effective_GBs": effective, "effective_frac": effective / PEAK_HBM_GBS,
                      "timing": "HIP events around every run of stepping launches of the timed solves"},
+        "roofline_one_step": one_step,
         "cpu_baseline": cpu,
         "pulsed": pulsed,
         "sweep": sweep,

@@ -179,13 +179,19 @@ typedef struct {
 } it_result;
 
 /* Kernel selection for the stepping.  NULL means "defaults". */
-#define IT_KERNEL_AUTO 0     /* the default choice: the plain kernel */
+#define IT_KERNEL_AUTO 0     /* the library's choice: passes of 3 fused steps (the blocked kernel)
+                              * on periodic grids of at least 4e6 interior nodes, 64 x 32 nodes
+                              * per plane or more, when no final fields are asked for and no
+                              * one-step tile option is set; else one step per launch.  A
+                              * steps_per_pass > 0 is taken as given. */
 #define IT_KERNEL_PLAIN 1    /* one time step per launch */
-#define IT_KERNEL_BLOCKED 2  /* steps_per_pass fused steps per launch (temporal blocking) */
+#define IT_KERNEL_BLOCKED 2  /* steps_per_pass (default 3) fused steps per launch (temporal blocking) */
 typedef struct {
   int32_t kernel;          /* IT_KERNEL_* */
-  int32_t steps_per_pass;  /* T for the blocked kernel, 1..8 (0 = default) */
-  int32_t tile_y;          /* rows per tile of the one-step kernels, 8 or 16 (0 = default) */
+  int32_t steps_per_pass;  /* T for the blocked kernel: 2..4 (1: the one-step kernel; 0 = default) */
+  int32_t tile_y;          /* rows per tile of the one-step kernels, 8 or 16; with the blocked
+                            * kernel the rows of its extended tiles, 24, 32, 40 or 48 (three
+                            * to six rows per thread, IT_EINVAL otherwise); 0 = default */
   int32_t check_every;     /* steps between host checks of the stop criterion (0 = default) */
   /* Optional instrumentation (NULL / 0 = none): caller-created hipEvent_t
    * handles, created with timing enabled on the device of the run.  it_solve
@@ -193,8 +199,8 @@ typedef struct {
    * events[2i+1] just after the i-th stepping-kernel launch of the call, for
    * i < n_timing_events / 2 (later launches are not instrumented).  The
    * events bracket the stepping kernel launch (with one step per launch it
-   * also records the previous step's tallies in an extra block; the blocked
-   * kernel's tally reduction is a separate launch outside the events).  With
+   * also records the previous launch's tallies in an extra block, as a blocked
+   * pass does).  With
    * timing_span = 1 instead (n_timing_events >= 2), events bracket runs of
    * consecutive stepping launches, with no events inside a run: a run ends
    * where a deposit interrupts the stepping (and at the end of the call);

@@ -30,7 +30,11 @@ from . import binding as B
 PLAIN = [dict(kernel=B.IT_KERNEL_PLAIN, tile_y=8), dict(kernel=B.IT_KERNEL_PLAIN, tile_y=16),
          dict(kernel=B.IT_KERNEL_PLAIN, tile_x=32)]
 PAIR = [dict(kernel=B.IT_KERNEL_PLAIN, tile_x=128)]  # tiles of column pairs: grids with an even nx
-BLOCKED = [dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=T) for T in (2, 3, 4, 5)]
+# the temporally blocked kernel at each depth with its default rows per
+# thread, and the next larger tile that still fits the registers
+BLOCKED = [dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=T) for T in (2, 3, 4)] + \
+    [dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=2, tile_y=40),
+     dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=3, tile_y=24)]
 
 _memo: dict = {}
 

@@ -94,11 +94,12 @@ struct StepParams {
   unsigned* counter;
   RunState* state;
   double* trace;            // [max_steps][IT_TRACE_COLS]
-  // one-step kernel only: when set, one extra block of the launch reduces
-  // the partials of the previous step (prev_nblocks blocks) and records step
-  // prev_step, overlapping the reduction with this step's stencil
+  // when set, one extra block of the launch reduces the partials of the
+  // previous launch (prev_nblocks blocks, prev_T steps) and records its steps
+  // from prev_step on, overlapping the reduction with this launch's stencil
   const double* prev_partials;
   int prev_nblocks;
+  int prev_T;
   int64_t prev_step;
 };
 

@@ -34,10 +34,11 @@ template <int SY, bool SC, bool AB, int TX>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(TX == 2 * kTX ? 2 : 4, 8))) void step_plain_kernel(StepParams p) {
   if (p.prev_partials && blockIdx.x == gridDim.x - 1) {
     if (p.state->done) return;
-    __shared__ double totals[kAcc];
-    reduce_partials<kTX * SY>(p.prev_partials, p.prev_nblocks, kAcc, kAcc, totals);
+    __shared__ double totals[kAcc * kMaxT];
+    reduce_partials<kTX * SY>(p.prev_partials, p.prev_nblocks, kAcc * p.prev_T, kAcc * p.prev_T, totals);
     if (threadIdx.x == 0 && threadIdx.y == 0)
-      finalize_steps(p.state, p.trace, totals, 1, p.prev_step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
+      finalize_steps(p.state, p.trace, totals, p.prev_T, p.prev_step, p.cp, p.cn, p.dV, p.stop_tol,
+                     p.min_stop_step);
     return;
   }
   if (p.state->done) return;  // set by an earlier launch: every block skips

@@ -11,16 +11,20 @@
 
 namespace it {
 
-hipError_t launch_step_blocked(const StepParams& p, int T, int tile_y, hipStream_t s, hipEvent_t ev_begin,
-                               hipEvent_t ev_end);
+// Temporally blocked kernel (kernels_blocked.hip): T steps per pass on
+// tiles of 64 columns by 8 R rows (R rows per thread).
+hipError_t launch_step_blocked(const StepParams& p, int T, int R, hipStream_t s, hipEvent_t ev_begin,
+                               hipEvent_t ev_end, int* nblocks);
 int blocked_supported(int T, int tile_y);
-void blocked_tiling(int nx, int ny, int nz, int T, int tile_y, int* grid, int* per_xcd,
+int blocked_rows(int T, int tile_y);
+void blocked_tiling(int nx, int ny, int nz, int T, int R, int* grid, int* per_xcd,
                     int* tiles_x, int* tiles_y, int* ntiles, int* zc, int* zchunks);
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDefaultT = 1;
+constexpr int kBlockedT = 3;                // steps per pass of the blocked kernel when none is given
+constexpr double kBlockedMinNodes = 4.0e6;  // interior nodes from which the library chooses it
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -271,18 +275,41 @@ bool z_chunk_ok(const it_exec* ex) {
   return z == 0 || (z >= kMinZChunk && z <= kMaxZChunk);
 }
 
-// Steps per launch of an execution choice (1: the one-step kernel).
-int exec_steps_per_pass(const it_exec* ex) {
+// Steps per launch the caller asked for: 1 (the one-step kernel), T > 1 (the
+// blocked kernel), or 0 (the library's choice).
+int requested_steps(const it_exec* ex) {
   if (ex && ex->kernel == IT_KERNEL_PLAIN) return 1;
-  return ex && ex->steps_per_pass > 0 ? ex->steps_per_pass : kDefaultT;
+  if (ex && ex->steps_per_pass > 0) return ex->steps_per_pass;
+  if (ex && ex->kernel == IT_KERNEL_BLOCKED) return kBlockedT;
+  return 0;
 }
 
-// Host check of an execution choice for a chamber, made before any device
-// work.
-int check_exec(const it_chamber* ch, const it_exec* ex) {
-  const int T = exec_steps_per_pass(ex);
+// The library's choice: passes of kBlockedT steps of the blocked kernel on a
+// periodic grid large enough to fill the machine (on MI355X 1.8x faster per
+// step than one step per launch at 13 M and 67 M interior nodes), else one
+// step per launch.  Not when the caller sets a one-step tile option, and not
+// when the final fields are asked for: a blocked pass that contains the step
+// meeting the collection criterion still computes the pass's later steps,
+// so its fields would be up to kBlockedT - 1 steps past the result's.
+int auto_steps(const it_chamber* ch, const it_exec* ex, bool exact_fields) {
+  if (ch->lateral_bc || exact_fields) return 1;
+  if (ex && (ex->tile_x || ex->tile_y || ex->z_chunk)) return 1;
+  const double nodes = (double)ch->nx * ch->ny * (double)(ch->nz - 1);
+  if (nodes < kBlockedMinNodes || ch->nx < 64 || ch->ny < 32) return 1;
+  return kBlockedT;
+}
+
+// Steps per launch of a run.
+int exec_steps(const it_chamber* ch, const it_exec* ex, bool exact_fields) {
+  const int T = requested_steps(ex);
+  return T > 0 ? T : auto_steps(ch, ex, exact_fields);
+}
+
+// Host check of an execution choice (T steps per launch) for a chamber,
+// made before any device work.
+int check_exec(const it_chamber* ch, const it_exec* ex, int T) {
   if (T < 1 || T > kMaxT) return IT_EINVAL;
-  if (T > 1 && !blocked_supported(T, ex ? ex->tile_y : 0)) return IT_ENOTSUP;
+  if (T > 1 && !blocked_supported(T, ex ? ex->tile_y : 0)) return ex && ex->tile_y ? IT_EINVAL : IT_ENOTSUP;
   if (T > 1 && ch->lateral_bc) return IT_ENOTSUP;  // the blocked kernel is periodic only
   if (!z_chunk_ok(ex)) return IT_EINVAL;
   if (!tile_shape_ok(ex) || (ex && (ex->tile_x == 32 || ex->tile_x == 128) && T > 1)) return IT_EINVAL;
@@ -293,8 +320,8 @@ int check_exec(const it_chamber* ch, const it_exec* ex) {
 // The same check plus what depends on the workspace: an explicit request for
 // tiles of column pairs needs 16-byte aligned fields, and every field sits
 // at a 256-byte offset from the workspace's start.
-int check_exec_ws(const it_chamber* ch, const it_exec* ex, const void* ws) {
-  const int rc = check_exec(ch, ex);
+int check_exec_ws(const it_chamber* ch, const it_exec* ex, int T, const void* ws) {
+  const int rc = check_exec(ch, ex, T);
   if (rc) return rc;
   if (ex && ex->tile_x == 128 && (uintptr_t)ws % 16 != 0) return IT_EINVAL;
   return IT_OK;
@@ -327,12 +354,13 @@ size_t max_grid(const it_chamber* ch) {
   size_t g = std::max((size_t)step_tiling(ch->nx, ch->ny, ch->nz, 8, kMinZChunk).grid,
                       (size_t)deposit_tiling(ch->nx, ch->ny, ch->nz).grid);
   g = std::max(g, (size_t)step_tiling(ch->nx, ch->ny, ch->nz, 16, kMinZChunk, 32).grid);
-  for (int T = 2; T <= kMaxT; ++T) {
-    if (!blocked_supported(T, 0)) continue;
-    int grid, per, tx, ty, nt, zc, zch;
-    blocked_tiling(ch->nx, ch->ny, ch->nz, T, 0, &grid, &per, &tx, &ty, &nt, &zc, &zch);
-    g = std::max(g, (size_t)grid * T);
-  }
+  for (int T = 2; T <= kMaxT; ++T)
+    for (int R = 1; R <= 8; ++R) {  // every rows-per-thread choice the caller can make
+      if (!blocked_supported(T, 8 * R)) continue;
+      int grid, per, tx, ty, nt, zc, zch;
+      blocked_tiling(ch->nx, ch->ny, ch->nz, T, R, &grid, &per, &tx, &ty, &nt, &zc, &zch);
+      g = std::max(g, (size_t)grid * T);
+    }
   return g;
 }
 
@@ -487,11 +515,10 @@ struct Event {
 // flagged completion.
 int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const Layout& L,
              const std::vector<Event>& events, const std::vector<DepTrack>& dev_tracks, int same_r,
-             int64_t nsteps, int64_t min_stop_step, double stop_tol, hipStream_t stream, HostSlots& hs,
+             int64_t nsteps, int64_t min_stop_step, double stop_tol, int T, hipStream_t stream, HostSlots& hs,
              RunState* final_state, int* passes_issued) {
-  const int exec_rc = check_exec(ch, ex);
+  const int exec_rc = check_exec(ch, ex, T);
   if (exec_rc) return exec_rc;
-  const int T = exec_steps_per_pass(ex);
   const int tile_y = ex ? ex->tile_y : 0;
   int64_t check_every = ex && ex->check_every > 0 ? ex->check_every : 64;
   const bool span = ex && ex->timing_events && ex->timing_span && ex->n_timing_events >= 2;
@@ -542,6 +569,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
   sp.trace = trace;
   sp.prev_partials = nullptr;
   sp.prev_nblocks = 0;
+  sp.prev_T = 1;
   sp.prev_step = 0;
 
   DepositParams dp = base_deposit(ch, dt, td);
@@ -588,24 +616,25 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
     rc = code;
     return code;
   };
-  // One-step runs record step l during launch l+1 (an extra block reduces
-  // step l's partials while the others compute step l+1); the partials
-  // alternate between two buffers.  A step still unrecorded is closed by a
-  // reduction launch before a deposit (so that its record does not count the
-  // deposit) and at the end.
-  const bool fused = T == 1;
+  // Launch i records the steps of launch i-1 (an extra block reduces its
+  // partials while the others compute the next step or pass); the partials
+  // alternate between two buffers by launch.  Steps still unrecorded are
+  // closed by a reduction launch before a deposit (so that their records do
+  // not count the deposit) and at the end.
   const int grid_plain = 8 * tp.per_xcd;
+  const int R = T > 1 ? blocked_rows(T, tile_y) : 0;  // rows per thread of the blocked passes
   double* part_buf[2] = {partials, partials + L.partial_doubles / 2};
   bool unrecorded = false;
   int64_t unrecorded_step = 0;
+  int unrecorded_T = 1, unrecorded_blocks = 0, unrecorded_buf = 0;
   auto close_step = [&]() -> hipError_t {
     if (!unrecorded) return hipSuccess;
     unrecorded = false;
     StepParams q = sp;
-    q.partials = part_buf[unrecorded_step & 1];
+    q.partials = part_buf[unrecorded_buf];
     q.step0 = unrecorded_step;
     q.prev_partials = nullptr;
-    return launch_reduce_steps(q, grid_plain, 1, stream);
+    return launch_reduce_steps(q, unrecorded_blocks, unrecorded_T, stream);
   };
   while (l < nsteps && !stopped) {
     if (ev < events.size() && events[ev].step == l) {
@@ -628,7 +657,15 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
     sp.pout = field[2 * (1 - cur)];
     sp.nout = field[2 * (1 - cur) + 1];
     sp.step0 = l;
+    // this launch's partials, and the previous launch's for its extra block
+    const int buf = issued & 1;
+    sp.partials = part_buf[buf];
+    sp.prev_partials = unrecorded ? part_buf[unrecorded_buf] : nullptr;
+    sp.prev_nblocks = unrecorded_blocks;
+    sp.prev_T = unrecorded_T;
+    sp.prev_step = unrecorded_step;
     hipError_t e;
+    int nblocks = grid_plain;
     if (todo == 1) {
       sp.tiles_x = tp.tiles_x;
       sp.tiles_y = tp.tiles_y;
@@ -636,20 +673,15 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
       sp.zc = tp.zc;
       sp.ntiles = tp.ntiles;
       sp.per_xcd = tp.per_xcd;
-      if (fused) {
-        sp.partials = part_buf[l & 1];
-        sp.prev_partials = unrecorded ? part_buf[unrecorded_step & 1] : nullptr;
-        sp.prev_nblocks = grid_plain;
-        sp.prev_step = unrecorded_step;
-        e = launch_step_plain(sp, rows, tx, stream, ev_pair(0), ev_pair(1), true);
-        unrecorded = true;
-        unrecorded_step = l;
-      } else {
-        e = launch_step_plain(sp, rows, tx, stream, ev_pair(0), ev_pair(1));
-      }
+      e = launch_step_plain(sp, rows, tx, stream, ev_pair(0), ev_pair(1), true);
     } else {
-      e = launch_step_blocked(sp, (int)todo, tile_y, stream, ev_pair(0), ev_pair(1));
+      e = launch_step_blocked(sp, (int)todo, R, stream, ev_pair(0), ev_pair(1), &nblocks);
     }
+    unrecorded = true;
+    unrecorded_step = l;
+    unrecorded_T = (int)todo;
+    unrecorded_blocks = nblocks;
+    unrecorded_buf = buf;
     if (e != hipSuccess) { fail(IT_EHIP); break; }
     ++issued;
     cur = 1 - cur;
@@ -936,7 +968,8 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     for (int64_t q = 0; q < ntracks; ++q)
       if (tracks[q].t_s != 0.0) return IT_ENOTSUP;
   }
-  rc = check_exec_ws(ch, exec, d_workspace);
+  const int T = exec_steps(ch, exec, d_pos_out || d_neg_out);
+  rc = check_exec_ws(ch, exec, T, d_workspace);
   if (rc) return rc;
   const Layout L = make_layout(ch, ntracks);
   if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
@@ -1041,7 +1074,7 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
   const int64_t ion_steps = ch->max_steps - e_steps;
   if (ion_steps > 0) {
     rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ion_steps,
-                  std::max<int64_t>(last_dep, 0), ch->stop_tol, stream, hs, &fin, &issued);
+                  std::max<int64_t>(last_dep, 0), ch->stop_tol, T, stream, hs, &fin, &issued);
     if (rc) return rc;
   } else {
     HIP_TRY(hipMemcpyAsync(hs.p, ws + L.off_state, sizeof(fin), hipMemcpyDeviceToHost, stream));
@@ -1320,7 +1353,9 @@ int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* e
   clear_stale_error();
   int rc = check_chamber(ch);
   if (rc) return rc;
-  rc = check_exec_ws(ch, exec, d_workspace);
+  // the fields come back after exactly nsteps steps with either kernel
+  const int T = exec_steps(ch, exec, false);
+  rc = check_exec_ws(ch, exec, T, d_workspace);
   if (rc) return rc;
   if (!d_pos || !d_neg || nsteps < 0 || nsteps > ch->max_steps) return IT_EINVAL;
   if (!(std::isfinite(dt) && dt > 0)) return IT_EINVAL;
@@ -1348,7 +1383,7 @@ int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* e
   int issued = 0;
   HostSlots hs;
   host_slots(exec, 1, hs);
-  rc = run_loop(ch, dt, exec, ws, L, none, nodev, 1, nsteps, INT64_MAX, 0.0, stream, hs, &fin, &issued);
+  rc = run_loop(ch, dt, exec, ws, L, none, nodev, 1, nsteps, INT64_MAX, 0.0, T, stream, hs, &fin, &issued);
   if (rc) return rc;
   const int last = fin.passes & 1;
   HIP_TRY(hipMemcpyAsync(d_pos, ws + L.off_field[2 * last], bytes, hipMemcpyDeviceToDevice, stream));

@@ -143,6 +143,12 @@ def test_lateral_boundary_option_checks(lib, orc):
     assert _solve_status(lib, dict(ab, mu_e=1000.0, D_e=25.0), tr, None) == lib.IT_ENOTSUP
     assert _solve_status(lib, ab, tr, dict(kernel=1)) == lib.IT_EWORKSPACE  # accepted up to the workspace
     assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_EWORKSPACE
+    # the blocked kernel: 2..4 steps per pass, extended tiles of 24..48 rows
+    for T, ty in ((2, 24), (3, 32), (4, 40), (2, 48)):
+        assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=T, tile_y=ty)) == lib.IT_EWORKSPACE
+    assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=5)) == lib.IT_ENOTSUP
+    for ty in (8, 16, 20, 56):
+        assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=3, tile_y=ty)) == lib.IT_EINVAL
     # 32-column tiles belong to the one-step kernels
     assert _solve_status(lib, ch, tr, dict(kernel=1, tile_x=32)) == lib.IT_EWORKSPACE
     assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4, tile_x=32)) == lib.IT_EINVAL

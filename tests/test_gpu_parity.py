@@ -23,9 +23,10 @@ RTOL = 1e-9
 EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5),
          dict(kernel=1, tile_x=32), dict(kernel=1, tile_x=32, z_chunk=6), dict(kernel=1, tile_x=128),
          dict(kernel=1, tile_x=128, tile_y=16, z_chunk=5)] + \
-    [dict(kernel=2, steps_per_pass=T) for T in (2, 3, 4, 5)]
+    [dict(kernel=2, steps_per_pass=T) for T in (2, 3, 4)] + \
+    [dict(kernel=2, steps_per_pass=2, tile_y=32), dict(kernel=2, steps_per_pass=4, tile_y=48)]
 EXEC_IDS = ["plain8", "plain16", "plain8z5", "plain32x16", "plain32x16z6", "pair128x8", "pair128x16z5", "blocked2",
-            "blocked3", "blocked4", "blocked5"]
+            "blocked3", "blocked4", "blocked2r4", "blocked4r6"]
 
 
 @pytest.fixture(scope="module")
