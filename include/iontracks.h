@@ -382,6 +382,23 @@ int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread
                  float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
                  void* d_workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): it_mlp_query
+ * without a workspace argument.  The query's scratch (per-tile fallback
+ * counts and offsets, their total) lives in a file-scope device array of
+ * the library, about 1 MiB, one copy per GPU, held until the process ends;
+ * its address is looked up once per device on the first call there.  nq
+ * may be at most IT_MLP_QUERY_STATIC_MAX (IT_EINVAL beyond).  Arguments and
+ * results otherwise as it_mlp_query.  Allocates nothing (no hipMalloc,
+ * hipFree or allocating library call).  Every call on a GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (other streams or
+ * host threads) race; calls on one stream, one after the other, do not.
+ * Errors: IT_EINVAL, IT_EHIP. */
+#define IT_MLP_QUERY_STATIC_MAX (1 << 23)
+int it_mlp_query_static(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
+                        float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx,
+                        int64_t* h_nfallback, void* stream);
+
 /* Message for a status code (static string). */
 const char* it_strerror(int code);
 

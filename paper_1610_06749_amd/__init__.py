@@ -11,4 +11,5 @@ from .binding import (IT_EHIP, IT_EINVAL, IT_ENODT, IT_ENOTSUP, IT_EWORKSPACE, I
                       it_advance, it_dt, it_solve, it_solve_batch, it_strerror, it_validate, it_workspace_size,
                       it_workspace_size_batch, lib, IT_MLP_PARAMS, IT_MLP_BF16, IT_MLP_FP32, it_mlp_model_bytes, it_mlp_init,
                       it_mlp_grad, it_mlp_train, it_mlp_query, it_mlp_baseline,
+                      it_mlp_query_static, IT_MLP_QUERY_STATIC_MAX, it_host_buffer_size, host_buffer,
                       workspace, KernelTimer)

@@ -99,10 +99,11 @@ def lib():
                                    ctypes.c_float, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
         L.it_mlp_query_ws_bytes.argtypes = [i64, szp]
         L.it_mlp_query.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.it_mlp_query_static.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp]
         for name in ("it_dt", "it_validate", "it_workspace_size", "it_host_buffer_size", "it_solve", "it_advance",
                      "it_workspace_size_batch", "it_solve_batch", "it_mlp_model_bytes", "it_mlp_init",
                      "it_mlp_train_ws_bytes", "it_mlp_grad", "it_mlp_train", "it_mlp_query_ws_bytes",
-                     "it_mlp_query", "it_mlp_baseline"):
+                     "it_mlp_query", "it_mlp_query_static", "it_mlp_baseline"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -452,3 +453,18 @@ def it_mlp_query(model, X, spread_tol, stream=None, ws=None, out=None):
                               _dptr(fb), _dptr(idx), ctypes.byref(cnt), _dptr(ws), ws.numel(), _stream(stream)),
            "it_mlp_query")
     return mean, spread, fb, idx[: cnt.value], cnt.value
+
+
+IT_MLP_QUERY_STATIC_MAX = 1 << 23
+
+
+def it_mlp_query_static(model, X, spread_tol, out, stream=None):
+    """The allocation-free query: results into ``out`` = (mean, spread,
+    fallback mask, fallback indices), device tensors the caller made, with
+    the library's own scratch; returns the fallback count."""
+    mean, spread, fb, idx = out
+    cnt = ctypes.c_int64()
+    _check(lib().it_mlp_query_static(_dptr(model), _dptr(X), int(X.shape[0]), float(spread_tol), _dptr(mean),
+                                     _dptr(spread), _dptr(fb), _dptr(idx), ctypes.byref(cnt), _stream(stream)),
+           "it_mlp_query_static")
+    return cnt.value

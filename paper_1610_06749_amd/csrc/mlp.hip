@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -1190,15 +1191,15 @@ int it_mlp_query_ws_bytes(int64_t nq, size_t* bytes) {
   return IT_OK;
 }
 
-int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
-                 float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
-                 void* d_ws, size_t ws_bytes, void* stream_) {
-  clear_stale_error();
-  if (!d_model || nq < 0 || (nq > 0 && (!d_X || !d_mean || !d_spread || !d_fallback))) return IT_EINVAL;
-  size_t need;
-  it_mlp_query_ws_bytes(nq, &need);
-  if (!d_ws || ws_bytes < need) return IT_EWORKSPACE;
-  hipStream_t s = (hipStream_t)stream_;
+}  // extern "C"
+
+namespace it {
+namespace {
+
+// The query with its scratch (per-tile fallback counts and offsets, the
+// total) at d_ws, it_mlp_query_ws_bytes(nq) bytes.
+int query(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean, float* d_spread,
+          unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback, void* d_ws, hipStream_t s) {
   if (nq == 0) {
     if (h_nfallback) *h_nfallback = 0;
     return IT_OK;
@@ -1230,6 +1231,64 @@ int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread
       return IT_EHIP;
   }
   return IT_OK;
+}
+
+// Scratch of the allocation-free query: a file-scope device array, one copy
+// per GPU, held until the process ends.  Its device address is taken once
+// per device (with that device current) and kept: in host code the array's
+// name is only a stand-in for it.  Nothing in it needs to start at zero
+// (every query tile writes its own count, the scan writes the offsets and
+// the total).
+constexpr int64_t kStaticQueries = IT_MLP_QUERY_STATIC_MAX;
+constexpr size_t kStaticScratchBytes = 2 * (((size_t)kStaticQueries / kTileS * 4 + 255) / 256 * 256) + 256;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+void* static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace it
+
+extern "C" {
+
+int it_mlp_query(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
+                 float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
+                 void* d_ws, size_t ws_bytes, void* stream_) {
+  clear_stale_error();
+  if (!d_model || nq < 0 || (nq > 0 && (!d_X || !d_mean || !d_spread || !d_fallback))) return IT_EINVAL;
+  size_t need;
+  it_mlp_query_ws_bytes(nq, &need);
+  if (!d_ws || ws_bytes < need) return IT_EWORKSPACE;
+  return query(d_model, d_X, nq, spread_tol, d_mean, d_spread, d_fallback, d_fallback_idx, h_nfallback, d_ws,
+               (hipStream_t)stream_);
+}
+
+int it_mlp_query_static(const void* d_model, const float* d_X, int64_t nq, float spread_tol, float* d_mean,
+                        float* d_spread, unsigned char* d_fallback, int64_t* d_fallback_idx, int64_t* h_nfallback,
+                        void* stream_) {
+  clear_stale_error();
+  if (!d_model || nq < 0 || nq > kStaticQueries || (nq > 0 && (!d_X || !d_mean || !d_spread || !d_fallback)))
+    return IT_EINVAL;
+  size_t need;
+  it_mlp_query_ws_bytes(nq, &need);
+  if (need > kStaticScratchBytes) return IT_EINVAL;
+  void* ws = static_scratch();
+  if (!ws) return IT_EHIP;
+  return query(d_model, d_X, nq, spread_tol, d_mean, d_spread, d_fallback, d_fallback_idx, h_nfallback, ws,
+               (hipStream_t)stream_);
 }
 
 }  // extern "C"
