@@ -126,12 +126,24 @@ def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
     return dict(ex_best)
 
 
-def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), z_chunks=(8, 16, 32),
-               narrow=True, cache=None, verbose=False):
-    """Best ``exec`` for it_solve_batch on these chambers: tile shape (64
-    columns by each of ``rows``, and 32 x 16 when ``narrow``), planes per tile
-    and the passes per captured graph, each timed on the batch with every
-    instance's step count capped at ``steps``."""
+def batch_candidates(rows=(8,), graph_passes=(32,), z_chunks=(16,), narrow=False,
+                     blocked_T=(2, 3), blocked_z=(16, 24, 32, 48), blocked_graph=(32,)):
+    """Execution choices tried for a batch: the one-step batched kernel with
+    64-column tiles of each of ``rows`` (and 32 x 16 when ``narrow``), each
+    planes-per-tile and passes-per-graph choice; and the temporally blocked
+    batched kernel at each depth, chunk length and passes per graph."""
+    shapes = [dict(tile_y=r, tile_x=64) for r in rows] + ([dict(tile_y=16, tile_x=32)] if narrow else [])
+    out = [dict(kernel=B.IT_KERNEL_PLAIN, check_every=g, z_chunk=z, **sh)
+           for sh in shapes for g in graph_passes for z in z_chunks]
+    out += [dict(kernel=B.IT_KERNEL_BLOCKED, steps_per_pass=T, check_every=g, z_chunk=z)
+            for T in blocked_T for g in blocked_graph for z in blocked_z]
+    return out
+
+
+def tune_batch(chs, trs, steps=96, candidates=None, cache=None, verbose=False, **kw):
+    """Best ``exec`` for it_solve_batch on these chambers among
+    ``candidates`` (default: batch_candidates(**kw)), each timed on the batch
+    with every instance's step count capped at ``steps``."""
     import torch
     sig = "|".join(f"{c['nx']}x{c['ny']}x{c['nz']}" for c in chs)
     key = f"batch:{len(chs)}:{hashlib.sha256(sig.encode()).hexdigest()[:12]}@{_device_name()}"
@@ -144,9 +156,10 @@ def tune_batch(chs, trs, steps=96, rows=(8, 16), graph_passes=(16, 32, 64), z_ch
     capped = [dict(c, max_steps=steps) for c in chs]
     vs = sum(c["nx"] * c["ny"] * (c["nz"] - 1) for c in chs) * steps
     timings = []
-    shapes = [dict(tile_y=r, tile_x=64) for r in rows] + ([dict(tile_y=16, tile_x=32)] if narrow else [])
-    for shape, g, z in ((sh, g, z) for sh in shapes for g in graph_passes for z in z_chunks):
-        ex = dict(kernel=B.IT_KERNEL_PLAIN, check_every=g, z_chunk=z, **shape)
+    cands = candidates if candidates is not None else batch_candidates(**kw)
+    if any(c.get("lateral_bc", 0) for c in chs):  # the blocked pass is periodic only
+        cands = [ex for ex in cands if ex.get("kernel") != B.IT_KERNEL_BLOCKED]
+    for ex in cands:
         B.it_solve_batch(capped, trs, exec=ex)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -173,11 +173,14 @@ hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStrea
 // sc: some instance has the space-charge term on; ab: some instance has
 // absorbing lateral boundaries; record_prev: the launch also records the
 // previous pass's step of every instance (false only for the first pass)
+// T > 1: T steps per launch with the blocked tile pass, R rows per thread
+// (tile_y and tile_x are then unused)
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
-                             bool ab, int parity, bool record_prev, hipStream_t s);
+                             bool ab, int parity, bool record_prev, int T, int R, hipStream_t s);
 // The same pass (recording the previous one) as a kernel node of `graph`
 // that depends on `dep` (null: none).
 hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNode_t* node, const void* table,
-                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, int parity);
+                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, int parity,
+                               int T, int R);
 
 }  // namespace it

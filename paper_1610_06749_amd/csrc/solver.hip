@@ -19,6 +19,8 @@ int blocked_supported(int T, int tile_y);
 int blocked_rows(int T, int tile_y);
 void blocked_tiling(int nx, int ny, int nz, int T, int R, int* grid, int* per_xcd,
                     int* tiles_x, int* tiles_y, int* ntiles, int* zc, int* zchunks);
+void blocked_tiling_zc(int nx, int ny, int nz, int T, int R, int zc, int* tiles_x, int* tiles_y, int* ntiles,
+                       int* zc_out, int* zchunks_out);
 
 namespace {
 
@@ -755,8 +757,55 @@ int batch_rows(const it_chamber* ch, int ninst, const it_exec* exec) {
   return resolve_rows(exec ? exec->tile_y : 0, min_ny);
 }
 
-BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows, int z_chunk,
-                              int tile_x) {
+// Steps per pass of a batch: as asked, else passes of kBlockedT steps of the
+// blocked tile pass unless an instance has absorbing lateral boundaries or a
+// one-step tile option is set (then one step per launch).
+int batch_steps(const it_chamber* ch, int ninst, const it_exec* ex) {
+  const int T = requested_steps(ex);
+  if (T > 0) return T;
+  for (int q = 0; q < ninst; ++q)
+    if (ch[q].lateral_bc) return 1;
+  if (ex && (ex->tile_x || ex->tile_y || ex->z_chunk)) return 1;
+  return kBlockedT;
+}
+
+// Checks of a batch's steps per pass: the blocked pass needs a supported
+// depth and rows and periodic lateral boundaries in every instance, and
+// takes no one-step tile width.
+int check_batch_steps(const it_chamber* ch, int ninst, const it_exec* ex, int T) {
+  if (T < 1 || T > kMaxT) return IT_EINVAL;
+  if (T == 1) return IT_OK;
+  if (!blocked_supported(T, ex ? ex->tile_y : 0)) return ex && ex->tile_y ? IT_EINVAL : IT_ENOTSUP;
+  if (ex && ex->tile_x) return IT_EINVAL;
+  for (int q = 0; q < ninst; ++q)
+    if (ch[q].lateral_bc) return IT_ENOTSUP;
+  return IT_OK;
+}
+
+// Planes per chunk of the blocked batch tiles: as requested, else 24 (each
+// chunk recomputes T planes of halo at both ends; shorter chunks keep the
+// tail of the sweep, where few small chambers run, on more CUs: the
+// 96-chamber sweep takes 7.46 s with 24 planes, 7.58 s with 32 and 7.51 s
+// with 48 on MI355X).
+int batch_blocked_z_chunk(const it_exec* exec) {
+  const int z = exec_z_chunk(exec);
+  return z > 0 ? z : 24;
+}
+
+// Stepping tiles of one chamber of a batch (T > 1: blocked tiles, R rows per
+// thread).
+Tiling batch_tiling(const it_chamber& c, int T, int R, int rows, const it_exec* exec, int tile_x) {
+  if (T == 1) return step_tiling(c.nx, c.ny, c.nz, rows, batch_z_chunk(exec), tile_x);
+  Tiling t;
+  blocked_tiling_zc(c.nx, c.ny, c.nz, T, R, batch_blocked_z_chunk(exec), &t.tiles_x, &t.tiles_y, &t.ntiles, &t.zc,
+                    &t.zchunks);
+  t.per_xcd = (t.ntiles + 7) / 8;
+  t.grid = 8 * t.per_xcd;
+  return t;
+}
+
+BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows, const it_exec* exec,
+                              int tile_x, int T, int R) {
   BatchLayout B;
   size_t off = 0;
   B.inst.resize(ninst);
@@ -768,11 +817,11 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
       L.off_field[f] = off;
       off = align_up(off + L.field_elems * sizeof(double));
     }
-    const Tiling ts = step_tiling(c.nx, c.ny, c.nz, rows, z_chunk, tile_x);
+    const Tiling ts = batch_tiling(c, T, R, rows, exec, tile_x);
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.ntiles = ts.ntiles;
     L.off_partials = off;  // two halves of step partials (alternate passes); the deposit uses the start
-    off = align_up(off + std::max((size_t)2 * ts.ntiles * kAcc, (size_t)td.grid * 5) * sizeof(double));
+    off = align_up(off + std::max((size_t)2 * ts.ntiles * kAcc * T, (size_t)td.grid * 5) * sizeof(double));
     L.off_counter = off;
     off = align_up(off + 64 * sizeof(unsigned));
     L.off_tracks = off;
@@ -1111,8 +1160,12 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
   }
   if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
   if (exec && exec->tile_x == 128) return IT_ENOTSUP;  // the batched kernel has no tiles of column pairs
+  const int T = batch_steps(ch, ninst, exec);
+  const int rc = check_batch_steps(ch, ninst, exec, T);
+  if (rc) return rc;
   const int rows = batch_rows(ch, ninst, exec);
-  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst, false)).total;
+  const int R = T > 1 ? blocked_rows(T, exec ? exec->tile_y : 0) : 0;
+  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, exec, exec_tile_x(exec, ch, ninst, false), T, R).total;
   return IT_OK;
 }
 
@@ -1134,7 +1187,12 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
   if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
   if (exec && exec->tile_x == 128) return IT_ENOTSUP;  // the batched kernel has no tiles of column pairs
-  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst, false));
+  const int T = batch_steps(ch, ninst, exec);  // steps per pass
+  rc = check_batch_steps(ch, ninst, exec, T);
+  if (rc) return rc;
+  const int R = T > 1 ? blocked_rows(T, exec ? exec->tile_y : 0) : 0;
+  const int tile_x = exec_tile_x(exec, ch, ninst, false);
+  const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, exec, tile_x, T, R);
   if (!d_workspace || ws_bytes < B.total) return IT_EWORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
   char* ws = (char*)d_workspace;
@@ -1167,7 +1225,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 
     const Coef cp = species_coef(c, dts[q], 0), cn = species_coef(c, dts[q], 1);
     const double dz = c->gap / c->nz, dV = c->dx * c->dy * dz;
-    const Tiling ts = step_tiling(c->nx, c->ny, c->nz, rows, batch_z_chunk(exec), exec_tile_x(exec, ch, ninst, false));
+    const Tiling ts = batch_tiling(*c, T, R, rows, exec, tile_x);
     const Tiling td = deposit_tiling(c->nx, c->ny, c->nz);
     BatchInstance& bi = table[q];
     for (int par = 0; par < 2; ++par) {
@@ -1196,7 +1254,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       sp.stop_tol = c->stop_tol;
       sp.step0 = 0;
       sp.min_stop_step = 0;
-      sp.partials = (double*)(ws + L.off_partials) + (size_t)par * L.ntiles * kAcc;
+      sp.partials = (double*)(ws + L.off_partials) + (size_t)par * L.ntiles * kAcc * T;
       sp.counter = (unsigned*)(ws + L.off_counter);
       sp.state = states + q;
       sp.trace = nullptr;
@@ -1234,7 +1292,6 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   HostSlots hs;
   host_slots(exec, ninst, hs);
   RunState* host = hs.p;
-  const int tile_x = exec_tile_x(exec, ch, ninst, false);
   std::vector<int> active(ninst);
   for (int q = 0; q < ninst; ++q) active[q] = q;
   hipGraph_t graph = nullptr;
@@ -1266,7 +1323,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     for (int k = 0; k < passes_per_graph; ++k) {
       hipGraphNode_t node = nullptr;
       if (add_batch_pass_node(graph, prev, &node, ws + B.off_table, (int)t.size(), tiles, rows, tile_x, any_sc,
-                              any_ab, (parity0 + k) & 1) != hipSuccess)
+                              any_ab, (parity0 + k) & 1, T, R) != hipSuccess)
         return IT_EHIP;
       prev = node;
     }
@@ -1285,7 +1342,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   {
     int tiles = 0;
     for (int q = 0; q < ninst; ++q) tiles += table[q].ntiles;
-    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, tile_x, any_sc, any_ab, 0, false, stream) !=
+    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, tile_x, any_sc, any_ab, 0, false, T, R, stream) !=
         hipSuccess) {
       release_graph();
       return IT_EHIP;
@@ -1294,7 +1351,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   (void)total_tiles;
   // Replays until every instance has stopped; two replays in flight so the
   // GPU never idles on the read-back.
-  const int64_t max_replays = (max_steps_all + passes_per_graph - 1) / passes_per_graph;
+  const int64_t steps_per_replay = (int64_t)passes_per_graph * T;
+  const int64_t max_replays = (max_steps_all + steps_per_replay - 1) / steps_per_replay + 1;
   hipEvent_t evs[2];
   HIP_TRY(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));

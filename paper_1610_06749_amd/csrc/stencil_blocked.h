@@ -1,0 +1,279 @@
+// One temporally blocked pass (T explicit time steps) of one block over one
+// extended tile: the device code shared by the single-chamber blocked
+// kernel and the batched one.
+//
+// A block of 8 waves owns an extended tile of 64 columns by 8 R rows: lane l
+// holds column l, and wave w the R consecutive rows w R .. w R + R - 1, in
+// registers.  Every lane loads its periodically wrapped column, so lane and
+// row neighbours are always the periodic x and y neighbours.  Each of the T
+// steps (levels) is exact on one node less on every side, so after T steps
+// the centre (64 - 2T) x (8 R - 2T) columns are exact: the block's owned
+// columns.  The block marches up a chunk of planes with a software pipeline
+// over the levels: at iteration K it loads level 0 on plane K and computes
+// level t on plane K - t for t = 1..T from level t-1 on planes K-t-1, K-t and
+// K-t+1, which the thread keeps in registers (two planes per level plus the
+// one just computed).
+//
+// Lateral neighbours of level t-1 on plane K-t: x from the adjacent lanes
+// (whole-wave DPP shifts), y from the thread's own rows; only the first and
+// the last row of a wave's strip need the row of the wave above or below,
+// which the waves exchange through LDS: at the end of an iteration every
+// wave writes the edge rows of each level's newest plane into one of two
+// buffers, and a single barrier at the top of the next iteration makes them
+// visible (the other buffer is being read meanwhile).  Only level T goes
+// back to HBM (non-temporal stores), so a pass reads and writes each owned
+// node once for T steps; the price is the redundant work on the tile's rim
+// and on the T planes of z halo at each end of a chunk.
+//
+// The per-step tallies (the same quantities as the one-step kernel, one
+// record per level) are taken on owned columns and on the block's own chunk
+// of planes only, so every node and electrode face is counted once.
+#pragma once
+
+#include "stencil_plain.h"
+
+namespace it {
+
+constexpr int kBW = 8;                // waves per block
+constexpr int kBX = 64;               // columns of the extended tile
+constexpr int kBNT = kBW * kWave;     // threads per block
+
+typedef __attribute__((address_space(1))) double gdouble;
+
+// Values of the neighbouring lanes (whole-wave DPP shifts by one lane); the
+// lane at the wave's edge, which has no such neighbour, gets 0.
+__device__ inline double lane_from_left(double v) {  // value of lane - 1
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double lane_from_right(double v) {  // value of lane + 1
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// One pass of the block over tile tc (tc.valid false: an idle block, which
+// still stores zero partials); the block's T records of kAcc partial
+// tallies go to partial_out.  The caller has checked the run's stop flag.
+template <int T, int R, bool SC>
+__device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const TileCoord tc, double* partial_out) {
+  constexpr int EY = kBW * R;             // rows of the extended tile
+  constexpr int OX = kBX - 2 * T, OY = EY - 2 * T;
+  constexpr int NA = SC ? 7 : 5;          // tallies kept per level
+  // edge rows of each level's newest plane: [buffer][level][wave][first/last][species][lane]
+  __shared__ double edge_rows[2][T][kBW][2][2][kWave];
+  __shared__ double edge_sum[T][kBW][4];  // per-wave sums of n on the planes next to the electrodes
+  __shared__ double lds[(kBNT / kWave) * kAcc * T];
+
+  const int lane = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);  // the wave (uniform)
+  const int x0 = tc.tx * OX, y0 = tc.ty * OY;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  // wrapped position of this lane's column and of the thread's rows
+  int xs = (x0 - T + lane) % nx;
+  if (xs < 0) xs += nx;
+  const bool own_x = lane >= T && lane < kBX - T && x0 + (lane - T) < nx;
+  unsigned off[R];  // in-plane byte offsets of the thread's nodes
+  bool own_y[R];    // the row is owned (wave-uniform)
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int g = w * R + r;  // row in the extended tile
+    int ys = (y0 - T + g) % ny;
+    if (ys < 0) ys += ny;
+    off[r] = (unsigned)(ys * nx + xs) * 8u;
+    own_y[r] = tc.valid && g >= T && g < EY - T && y0 + (g - T) < ny;
+  }
+  const int za = 1 + tc.zc * p.zc;
+  const int zb = tc.valid ? min(za + p.zc, nz) : za;
+  const size_t plane = (size_t)nx * ny;
+  const Coef cp = p.cp, cn = p.cn;
+  const double beta = p.beta, gsp = p.gsp, gsn = p.gsn;
+
+  if (lane < 4)
+#pragma unroll
+    for (int t = 0; t < T; ++t) edge_sum[t][w][lane] = 0.0;
+
+  // level t (0..T-1): mp/mn its plane K-t-2, cpv/cnv its plane K-t-1 at the
+  // start of iteration K
+  double mp[T][R], mn[T][R], cpv[T][R], cnv[T][R];
+  double acc[T][NA];  // tallies of the owned rows, all columns (masked at the end)
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) mp[t][r] = mn[t][r] = cpv[t][r] = cnv[t][r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[t][q] = 0.0;
+  }
+
+  const int Klo = za - T, Khi = zb + T - 1;
+  // Level 0 of plane K.  Planes before the anode and beyond the cathode read
+  // the electrode plane itself, which always holds zero: the loads need no
+  // branch or select, so they stay in flight across the iteration (a
+  // branch around them made the compiler wait for them at once).
+  double np0[R], nn0[R];
+  auto load0 = [&](int K) {
+    const int Kc = min(max(K, 0), nz);
+    const gchar* bp = uniform_ptr(p.pin + (size_t)Kc * plane);
+    const gchar* bn = uniform_ptr(p.nin + (size_t)Kc * plane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      np0[r] = *(const gdouble*)(bp + off[r]);
+      nn0[r] = *(const gdouble*)(bn + off[r]);
+    }
+  };
+  // the zero planes' edge rows held at the start
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      edge_rows[Klo & 1][t][w][0][s][lane] = 0.0;
+      edge_rows[Klo & 1][t][w][1][s][lane] = 0.0;
+    }
+  const int wu = w > 0 ? w - 1 : 0, wd = w < kBW - 1 ? w + 1 : kBW - 1;
+
+  // One iteration: planes K - t of levels t = 1..T, then the edge rows of
+  // every level's newest plane for the next iteration.  (One copy of this
+  // body: the register allocator keeps the pipeline's state in registers
+  // only when the loop body is not duplicated.)
+  auto iterate = [&](int K) {
+    const int buf = K & 1;
+    lds_barrier();  // the edge rows written at the end of the previous iteration
+    double vp[R], vn[R];  // the newest level's values, plane K - t
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      vp[r] = np0[r];
+      vn[r] = nn0[r];
+    }
+    if (K + 1 <= Khi) load0(K + 1);
+#pragma unroll
+    for (int t = 1; t <= T; ++t) {
+      const int q = K - t;  // plane of level t in this iteration (block-uniform)
+      const bool interior = q >= 1 && q <= nz - 1;
+      const bool counted = q >= za && q < zb;
+      if (counted && (q == 1 || q == nz - 1)) {  // the old values of step t next to an electrode
+        double sp_ = 0.0, sn_ = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (own_y[r]) {
+            sp_ += cpv[t - 1][r];
+            sn_ += cnv[t - 1][r];
+          }
+        sp_ = wave_sum(own_x ? sp_ : 0.0);
+        sn_ = wave_sum(own_x ? sn_ : 0.0);
+        if (lane == 0) {
+          if (q == 1) {
+            edge_sum[t - 1][w][0] += sp_;
+            edge_sum[t - 1][w][2] += sn_;
+          }
+          if (q == nz - 1) {
+            edge_sum[t - 1][w][1] += sp_;
+            edge_sum[t - 1][w][3] += sn_;
+          }
+        }
+      }
+      // neighbours above the strip's first row and below its last, level t-1
+      // on plane q (the other waves' edge rows)
+      const double up_p = edge_rows[buf][t - 1][wu][1][0][lane], up_n = edge_rows[buf][t - 1][wu][1][1][lane];
+      const double dn_p = edge_rows[buf][t - 1][wd][0][0][lane], dn_n = edge_rows[buf][t - 1][wd][0][1][lane];
+      double np[R], nn[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) np[r] = nn[r] = 0.0;  // electrode planes and beyond hold zero
+      if (interior)  // block-uniform
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double pc = cpv[t - 1][r], nc = cnv[t - 1][r];
+        const double pxl = lane_from_left(pc), pxr = lane_from_right(pc);
+        const double nxl = lane_from_left(nc), nxr = lane_from_right(nc);
+        const double pyl = r > 0 ? cpv[t - 1][r - 1] : up_p, pyr = r < R - 1 ? cpv[t - 1][r + 1] : dn_p;
+        const double nyl = r > 0 ? cnv[t - 1][r - 1] : up_n, nyr = r < R - 1 ? cnv[t - 1][r + 1] : dn_n;
+        const double sink = beta * pc * nc;
+        const double net = pc - nc;
+        const double scp = SC ? gsp * pc * net : 0.0, scn = SC ? gsn * nc * net : 0.0;
+        const double a = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[r] +
+                         cp.azm * mp[t - 1][r] - sink + scp;
+        const double b = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[r] +
+                         cn.azm * mn[t - 1][r] - sink + scn;
+        np[r] = a;
+        nn[r] = b;
+        if (counted && own_y[r]) {  // wave-uniform; the columns are masked at the end
+          acc[t - 1][0] += sink;
+          acc[t - 1][1] += a;
+          acc[t - 1][2] += b;
+          acc[t - 1][3] += fabs(a);
+          acc[t - 1][4] += fabs(b);
+          if constexpr (SC) {
+            acc[t - 1][5] += scp;
+            acc[t - 1][6] += scn;
+          }
+        }
+      }
+      // level t-1 moves on: plane K-t becomes its older plane, K-t+1 its current one
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        mp[t - 1][r] = cpv[t - 1][r];
+        mn[t - 1][r] = cnv[t - 1][r];
+        cpv[t - 1][r] = vp[r];
+        cnv[t - 1][r] = vn[r];
+        vp[r] = np[r];
+        vn[r] = nn[r];
+      }
+    }
+    // level T on plane K - T: the pass's output
+    const int q = K - T;
+    if (q >= za && q < zb) {
+      gchar* op = uniform_ptr(p.pout + (size_t)q * plane);
+      gchar* on = uniform_ptr(p.nout + (size_t)q * plane);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (own_y[r] && own_x) {
+          __builtin_nontemporal_store(vp[r], (gdouble*)(op + off[r]));
+          __builtin_nontemporal_store(vn[r], (gdouble*)(on + off[r]));
+        }
+    }
+    // edge rows of every level's current plane, for the next iteration
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      edge_rows[buf ^ 1][t][w][0][0][lane] = cpv[t][0];
+      edge_rows[buf ^ 1][t][w][0][1][lane] = cnv[t][0];
+      edge_rows[buf ^ 1][t][w][1][0][lane] = cpv[t][R - 1];
+      edge_rows[buf ^ 1][t][w][1][1][lane] = cnv[t][R - 1];
+    }
+  };
+
+  if (tc.valid) {
+    load0(Klo);
+    for (int K = Klo; K <= Khi; ++K) iterate(K);
+  }
+
+  __syncthreads();  // edge sums of the last planes
+  // block reduction of T records of kAcc slots (layout [level][slot]); the
+  // tallies of columns outside the owned ones are selected away here
+  double a[kAcc * T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    a[t * kAcc + 0] = own_x ? acc[t][0] : 0.0;
+    a[t * kAcc + 1] = lane == 0 ? edge_sum[t][w][0] : 0.0;
+    a[t * kAcc + 2] = lane == 0 ? edge_sum[t][w][1] : 0.0;
+    a[t * kAcc + 3] = lane == 0 ? edge_sum[t][w][2] : 0.0;
+    a[t * kAcc + 4] = lane == 0 ? edge_sum[t][w][3] : 0.0;
+    a[t * kAcc + 5] = own_x ? acc[t][1] : 0.0;
+    a[t * kAcc + 6] = own_x ? acc[t][2] : 0.0;
+    a[t * kAcc + 7] = own_x ? acc[t][3] : 0.0;
+    a[t * kAcc + 8] = own_x ? acc[t][4] : 0.0;
+    if constexpr (SC) {
+      a[t * kAcc + 9] = own_x ? acc[t][5] : 0.0;
+      a[t * kAcc + 10] = own_x ? acc[t][6] : 0.0;
+    } else {
+      a[t * kAcc + 9] = 0.0;
+      a[t * kAcc + 10] = 0.0;
+    }
+    a[t * kAcc + 11] = 0.0;  // escaped: the blocked kernel is periodic only
+    a[t * kAcc + 12] = 0.0;
+  }
+  block_sum_store<kAcc * T, kBNT>(a, partial_out, lds);
+}
+
+
+}  // namespace it

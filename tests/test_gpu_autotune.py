@@ -64,13 +64,16 @@ def test_tune_skips_unsupported_candidates(gpu, tuner):
 def test_tune_batch_returns_a_working_shape(gpu, tuner, tmp_path):
     chs = [W.chamber(n, n - 7, z, 5e-4, z * 5e-4, 100.0, uniform_n0=1e9) for n, z in ((40, 20), (72, 33), (96, 12))]
     trs = [W.tracks([[20.0, 1e-3, 0.5 * c["nx"] * 5e-4, 0.5 * c["ny"] * 5e-4, 0.0, 0.0, 0.0]]) for c in chs]
-    ex = tuner.tune_batch(chs, trs, steps=24, rows=(8, 16), graph_passes=(4, 8), z_chunks=(8,),
-                          cache=str(tmp_path / "tb.json"))
-    assert (ex["tile_x"], ex["tile_y"]) in ((64, 8), (64, 16), (32, 16))
-    assert ex["check_every"] in (4, 8) and ex["z_chunk"] == 8
+    ex = tuner.tune_batch(chs, trs, steps=24, rows=(8, 16), graph_passes=(4, 8), z_chunks=(8,), narrow=True,
+                          blocked_T=(2, 3), blocked_z=(8, 16), blocked_graph=(4,), cache=str(tmp_path / "tb.json"))
+    if ex["kernel"] == gpu.IT_KERNEL_PLAIN:
+        assert (ex["tile_x"], ex["tile_y"]) in ((64, 8), (64, 16), (32, 16))
+        assert ex["check_every"] in (4, 8) and ex["z_chunk"] == 8
+    else:
+        assert ex["steps_per_pass"] in (2, 3) and ex["z_chunk"] in (8, 16) and ex["check_every"] == 4
     table = __import__("json").load(open(str(tmp_path / "tb.json")))
     (entry,) = table.values()
-    assert len(entry["all"]) == 3 * 2  # shapes x passes per graph
+    assert len(entry["all"]) == 3 * 2 + 2 * 2  # one-step shapes x passes per graph, blocked depths x chunks
     a = gpu.it_solve_batch(chs, trs, exec=ex)
     b = gpu.it_solve_batch(chs, trs)
     for ra, rb in zip(a, b):
