@@ -126,6 +126,22 @@ typedef struct {
    * one-step kernel (IT_KERNEL_AUTO / IT_KERNEL_PLAIN) and in batches, not
    * with the blocked kernel or free electrons (IT_ENOTSUP). */
   int32_t lateral_bc;
+  /* Pulse train (the beam's time structure as pulses, Distribution of ion
+   * tracks; a repetition rate read as a periodic train of identical
+   * pulses): n_pulses >= 2 repeats the chamber's deposits -- uniform_n0 and
+   * every track, each of which must be due at t = 0 (IT_ENOTSUP otherwise)
+   * -- n_pulses times, one pulse every pulse_period_s seconds.  A period is
+   * m = ceil(pulse_period_s / dt1) whole steps, dt1 the single-pulse step
+   * (dt_safety times the bound below), and the run steps at
+   * dt = pulse_period_s / m, so that every period has the same steps and
+   * the train can settle into an exactly periodic state; pulse k is
+   * deposited at the start of step k m.  The run covers steps
+   * 0 .. n_pulses m - 1 with no collection test, and f, ks and f_R describe
+   * its last period (see it_result).  0 or 1: a single pulse (the tracks at
+   * their own times; pulse_period_s is ignored).  Not with free electrons
+   * (IT_ENOTSUP). */
+  int32_t n_pulses;
+  double pulse_period_s;  /* [s], finite and > 0 when n_pulses >= 2 */
 } it_chamber;
 
 /* One ion track.  The axis passes through (x, y, gap/2) with direction
@@ -176,6 +192,19 @@ typedef struct {
   int64_t steps;        /* steps counted in the result */
   int32_t flags;        /* IT_FLAG_* */
   int32_t passes;       /* stepping kernel launches issued (diagnostic) */
+  /* Pulse train (n_pulses >= 2; all 0 otherwise): pulses deposited, and
+   * the last period, steps (n_pulses-1) m .. n_pulses m - 1, in ions of both
+   * signs: period_released what its pulse released, period_collected what
+   * reached the electrodes during it, period_recombined the pairs that
+   * recombined during it.  f = period_collected / period_released, ks =
+   * 1/f and f_R = 1 - 2 period_recombined / period_released then describe
+   * one pulse of the train: in a periodic steady state one period collects
+   * or recombines what one pulse releases.  The other counts cover the
+   * whole run.  A run that stops before its last pulse (max_steps, a
+   * non-finite tally) reports f, ks and f_R of the whole run. */
+  int32_t pulses;
+  int32_t reserved;
+  double period_released, period_collected, period_recombined;
 } it_result;
 
 /* Kernel selection for the stepping.  NULL means "defaults". */
@@ -242,6 +271,8 @@ int it_host_buffer_size(int32_t ninst, size_t* bytes);
  *     k dt n exceeds about 1 at dense track cores.  n_ref is uniform_n0 plus the
  *     largest density found on any track's axis at mid-gap from all tracks
  *     with the same arrival time (host array; may be NULL if ntracks = 0).
+ * With a pulse train (n_pulses >= 2) that step dt1 is shortened to
+ * pulse_period_s / ceil(pulse_period_s / dt1), the step the run takes.
  * Host only: touches no device.  Errors: IT_EINVAL, IT_ENODT. */
 int it_dt(const it_chamber* ch, const it_track* tracks, int64_t ntracks, double* dt);
 
@@ -291,7 +322,11 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
  * (same time step rule, deposition, stepping, tallies and stop criterion).
  * ch: host [ninst]; tracks of instance q are tracks[track_offsets[q] ..
  * track_offsets[q+1]) (host); every track must be due at step 0 (one pulse
- * per instance, IT_ENOTSUP otherwise).  Each pass is one launch over the
+ * per instance, or a train of them, IT_ENOTSUP otherwise).  An instance
+ * with a pulse train keeps its first pulse's densities in the workspace;
+ * the pass that computes the step before each later pulse adds them to its
+ * outputs.  A batch with a pulse train steps one step per pass
+ * (steps_per_pass > 1 with the blocked kernel: IT_ENOTSUP).  Each pass is one launch over the
  * tiles of all running instances, plus one block per instance that records
  * the instance's previous step; the library
  * captures exec->check_every passes (default 32, rounded up to even) in a

@@ -30,8 +30,9 @@ _CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared"]
 
 P_KEYS = ("dx", "dy", "gap", "voltage", "mu_pos", "mu_neg", "D_pos", "D_neg",
           "alpha", "W_eV", "dt_safety", "stop_tol", "uniform_n0", "space_charge", "reaction_limit",
-          "attach_coeff", "mu_e", "D_e", "lateral_bc")
-_OPTIONAL = ("space_charge", "reaction_limit", "attach_coeff", "mu_e", "D_e", "lateral_bc")
+          "attach_coeff", "mu_e", "D_e", "lateral_bc", "n_pulses", "pulse_period_s")
+_OPTIONAL = ("space_charge", "reaction_limit", "attach_coeff", "mu_e", "D_e", "lateral_bc", "n_pulses",
+             "pulse_period_s")
 E_KEYS = ("e_released", "e_collected_anode", "e_collected_cathode", "e_recombined", "e_steps", "e_dt",
           "e_left", "released_neg_charge")
 E_TRACE_KEYS = ("recombined_pn", "recombined_pe", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
@@ -40,7 +41,8 @@ E_TRACE_KEYS = ("recombined_pn", "recombined_pe", "pos_anode", "pos_cathode", "n
 R_KEYS = ("f", "ks", "f_R", "n_released", "n_recombined", "n_inflight_pos",
           "n_inflight_neg", "col_pos_anode", "col_pos_cathode", "col_neg_anode",
           "col_neg_cathode", "dt", "steps", "flags", "max_beta_n", "n_space_charge_pos",
-          "n_space_charge_neg", "n_released_neg", "n_escaped_pos", "n_escaped_neg")
+          "n_space_charge_neg", "n_released_neg", "n_escaped_pos", "n_escaped_neg", "pulses",
+          "period_released", "period_collected", "period_recombined")
 TRACE_KEYS = ("recombined", "pos_anode", "pos_cathode", "neg_anode", "neg_cathode",
               "pos_inflight", "neg_inflight", "pos_abs", "neg_abs", "released", "pos_space_charge",
               "neg_space_charge", "released_neg", "pos_escaped", "neg_escaped")
@@ -260,8 +262,10 @@ def solve(ch, tracks, with_trace: bool = False, with_fields: bool = True):
     if rc == -2:
         raise ValueError("no stable time step")
     if rc == -3:
-        raise ValueError("free electrons need an instantaneous pulse, no space charge and periodic "
-                         "lateral boundaries")
+        raise ValueError("free electrons need an instantaneous pulse, no space charge, periodic lateral "
+                         "boundaries and no pulse train; a pulse train needs every track at t = 0")
+    if rc == -1 and not fe:
+        raise ValueError("invalid pulse train: the period must be positive and at least one step")
     if rc:
         raise MemoryError("oracle solve failed")
     out = dict(zip(R_KEYS, res.tolist()))
@@ -272,6 +276,7 @@ def solve(ch, tracks, with_trace: bool = False, with_fields: bool = True):
             out["trace_e"] = trace_e[: out["e_steps"]].copy()
     out["steps"] = int(out["steps"])
     out["flags"] = int(out["flags"])
+    out["pulses"] = int(out["pulses"])
     if with_trace:
         out["trace"] = trace[: out["steps"]].copy()
     if with_fields:

@@ -57,6 +57,20 @@
  *     deposited and, for both species, the sum of |n| dV over the grid is
  *     <= stop_tol * N_released (the signed sum can dip below zero while
  *     Lax-Wendroff undershoots are still in flight, so it is not used).
+ *   - a pulsed beam of repetition period P (Distribution of ion tracks: a
+ *     beam in time as instantaneous pulses): with n_pulses = N >= 2 the
+ *     chamber's deposits -- the uniform pre-ionisation and every track, all
+ *     due at t = 0 -- repeat every period, N times.  A period is m =
+ *     ceil(P / dt) whole steps, the time step shortened to P / m (so every
+ *     period has the same steps and a periodic state can be reached
+ *     exactly), and pulse k is deposited at the start of step k m.  The run
+ *     covers steps 0 .. N m - 1, with no collection test.  The last period,
+ *     steps (N-1) m .. N m - 1, gives the result:
+ *     f = charge collected in it / charge one pulse releases (both signs),
+ *     f_R = 1 - pairs recombined in it / pairs one pulse releases.  Once the
+ *     pulses have reached a periodic steady state, what one pulse releases
+ *     is collected or recombined within one period, so both are the
+ *     collection efficiency of a pulse in the train.
  *
  * Layout: each species is an array [nz+1][ny][nx] (x fastest) whose planes
  * k = 0 and k = nz are the electrodes and always hold zero.
@@ -73,13 +87,14 @@
 enum {
   P_DX, P_DY, P_GAP, P_VOLT, P_MU_POS, P_MU_NEG, P_D_POS, P_D_NEG,
   P_ALPHA, P_W, P_KAPPA, P_STOP_TOL, P_UNIFORM_N0, P_SPACE_CHARGE, P_REACTION_LIMIT,
-  P_ATTACH, P_MU_E, P_D_E, P_LATERAL_BC, P_COUNT
+  P_ATTACH, P_MU_E, P_D_E, P_LATERAL_BC, P_N_PULSES, P_PULSE_PERIOD, P_COUNT
 };
 /* result vector */
 enum {
   R_F, R_KS, R_F_RECOMB, R_RELEASED, R_RECOMBINED, R_INFLIGHT_POS, R_INFLIGHT_NEG,
   R_COL_POS_ANODE, R_COL_POS_CATHODE, R_COL_NEG_ANODE, R_COL_NEG_CATHODE,
-  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_RELEASED_NEG, R_ESC_POS, R_ESC_NEG, R_COUNT
+  R_DT, R_STEPS, R_FLAGS, R_MAX_BETA_N, R_SC_POS, R_SC_NEG, R_RELEASED_NEG, R_ESC_POS, R_ESC_NEG,
+  R_PULSES, R_PERIOD_RELEASED, R_PERIOD_COLLECTED, R_PERIOD_RECOMBINED, R_COUNT
 };
 /* per-step record */
 enum { T_RECOMB, T_POS_ANODE, T_POS_CATHODE, T_NEG_ANODE, T_NEG_CATHODE, T_POS_INFLIGHT, T_NEG_INFLIGHT,
@@ -280,13 +295,14 @@ int64_t orc_deposit_step(double dt, const double *tr)
   return (int64_t)s;
 }
 
-/* Add every track due at step `step` (list order) to both species.
- * released[0], released[1]: ions of each species released (sum of density
- * times dV); equal unless the track gives the negative ions their own
- * radius. */
-void orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
-                 const double *trk, int64_t ntr, int64_t step, double dt,
-                 double *pos, double *neg, double *released)
+/* Add every track due at step `step` (list order) to both species, or
+ * every track when `all` is set (a pulse of a pulse train, whose tracks are
+ * all due at its start).  released[0], released[1]: ions of each species
+ * released (sum of density times dV); equal unless the track gives the
+ * negative ions their own radius. */
+static void deposit_tracks(const double *p, int64_t nx, int64_t ny, int64_t nz,
+                           const double *trk, int64_t ntr, int64_t step, double dt, int all,
+                           double *pos, double *neg, double *released)
 {
   const double dV = p[P_DX] * p[P_DY] * (p[P_GAP] / (double)nz);
   released[0] = released[1] = 0.0;
@@ -294,7 +310,7 @@ void orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
   if (!plane_sum) { released[0] = released[1] = NAN; return; }
   for (int64_t t = 0; t < ntr; ++t) {
     const double *tr = trk + TRK * t;
-    if (orc_deposit_step(dt, tr) != step) continue;
+    if (!all && orc_deposit_step(dt, tr) != step) continue;
     double u[3];
     track_axis(tr, u);
 #pragma omp parallel for schedule(static)
@@ -321,6 +337,14 @@ void orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
     released[1] += sum[1] * dV;
   }
   free(plane_sum);
+}
+
+/* Add every track due at step `step` (list order) to both species. */
+void orc_deposit(const double *p, int64_t nx, int64_t ny, int64_t nz,
+                 const double *trk, int64_t ntr, int64_t step, double dt,
+                 double *pos, double *neg, double *released)
+{
+  deposit_tracks(p, nx, ny, nz, trk, ntr, step, dt, 0, pos, neg, released);
 }
 
 /* Uniform pre-ionisation n0 of both species at every interior node. */
@@ -500,7 +524,9 @@ static double field_max(int64_t n, const double *a, const double *b)
 /* Full run: deposit, step, tally, stop (see the file header).
  * pos/neg: caller-provided (nz+1)*ny*nx arrays, overwritten; hold the final
  * densities on return.  trace: NULL or max_steps*T_COUNT doubles.
- * res: R_COUNT doubles.  Returns 0 or a negative error. */
+ * res: R_COUNT doubles.  Returns 0 or a negative error (-1 invalid pulse
+ * train, -2 no stable dt, -3 a pulse train with a track not due at t = 0,
+ * -4 out of memory). */
 int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
               const double *trk, int64_t ntr, int64_t max_steps,
               double *pos, double *neg, double *trace, double *res)
@@ -508,10 +534,29 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   double dt;
   int rc = orc_dt(p, nx, ny, nz, trk, ntr, &dt);
   if (rc) return rc;
+
+  /* pulse train: m steps per period (dt shortened to P/m), pulse k at the
+   * start of step k m; the run ends before step N m */
+  const int64_t npulses = p[P_N_PULSES] >= 2.0 ? (int64_t)p[P_N_PULSES] : 1;
+  const double period = p[P_PULSE_PERIOD];
+  const int train = npulses > 1;
+  int64_t end = max_steps, last_pulse = -1, m = 0;
+  if (train) {
+    if (!(period > 0.0) || !isfinite(period)) return -1;
+    for (int64_t t = 0; t < ntr; ++t)
+      if (trk[TRK * t + 6] != 0.0) return -3;
+    const double per = ceil(period / dt);
+    if (!(per <= 1.0e15 / (double)npulses)) return -1;  /* steps of the train beyond range */
+    m = (int64_t)per;
+    dt = period / (double)m;
+    if (npulses * m < end) end = npulses * m;
+    last_pulse = (npulses - 1) * m;
+  }
+
   const int64_t n = (nz + 1) * ny * nx;
   double *npos = (double *)calloc((size_t)n, sizeof(double));
   double *nneg = (double *)calloc((size_t)n, sizeof(double));
-  if (!npos || !nneg) { free(npos); free(nneg); return -1; }
+  if (!npos || !nneg) { free(npos); free(nneg); return -4; }
   memset(pos, 0, (size_t)n * sizeof(double));
   memset(neg, 0, (size_t)n * sizeof(double));
 
@@ -525,22 +570,36 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
   double esc[2] = {0, 0};
   double last[T_COUNT] = {0};
   double max_beta_n = 0.0;
+  /* the last period of a pulse train: running sums at its start and the
+   * ions its pulse released */
+  double period_sums[5] = {0, 0, 0, 0, 0}, period_rel[2] = {0, 0};
+  int period_started = 0;
+  int64_t next_pulse = 0;
   int flags = 0;
   int64_t steps = 0;
-  for (int64_t l = 0; l < max_steps; ++l) {
-    int deposited = 0;
-    double released_now = 0.0, released_now_neg = 0.0;
-    if (l == 0 && p[P_UNIFORM_N0] != 0.0) {
-      const double u0 = orc_uniform(p, nx, ny, nz, p[P_UNIFORM_N0], pos, neg);
-      released_now += u0;
-      released_now_neg += u0;
-      deposited = 1;
+  for (int64_t l = 0; l < end; ++l) {
+    /* what is deposited at the start of this step: pulse k of a train, or
+     * the single pulse's uniform pre-ionisation and the tracks due now */
+    int deposit = 0;
+    if (train) {
+      if (next_pulse < npulses && next_pulse * m == l) {
+        deposit = 1;
+        ++next_pulse;
+      }
+    } else {
+      deposit = l == 0 && p[P_UNIFORM_N0] != 0.0;
+      for (int64_t t = 0; t < ntr && !deposit; ++t)
+        if (orc_deposit_step(dt, trk + TRK * t) == l) deposit = 1;
     }
-    for (int64_t t = 0; t < ntr; ++t)
-      if (orc_deposit_step(dt, trk + TRK * t) == l) { deposited = 1; break; }
-    if (deposited) {
+    double released_now = 0.0, released_now_neg = 0.0;
+    if (deposit) {
+      if (p[P_UNIFORM_N0] != 0.0 && (train || l == 0)) {
+        const double u0 = orc_uniform(p, nx, ny, nz, p[P_UNIFORM_N0], pos, neg);
+        released_now += u0;
+        released_now_neg += u0;
+      }
       double rel[2];
-      orc_deposit(p, nx, ny, nz, trk, ntr, l, dt, pos, neg, rel);
+      deposit_tracks(p, nx, ny, nz, trk, ntr, l, dt, train, pos, neg, rel);
       released_now += rel[0];
       released_now_neg += rel[1];
       const double m = beta * field_max(n, pos, neg);
@@ -548,6 +607,12 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
     }
     released += released_now;
     released_neg += released_now_neg;
+    if (train && l == last_pulse) {
+      memcpy(period_sums, sums, sizeof(sums));
+      period_rel[0] = released_now;
+      period_rel[1] = released_now_neg;
+      period_started = 1;
+    }
     double tally[T_COUNT];
     orc_step(p, nx, ny, nz, dt, pos, neg, npos, nneg, tally);
     tally[T_RELEASED] = released_now;
@@ -565,7 +630,7 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
     int finite = 1;
     for (int q = 0; q < T_COUNT; ++q) finite &= isfinite(tally[q]) != 0;
     if (!finite) { flags |= FLAG_NONFINITE; break; }
-    if (l >= last_deposit && tally[T_POS_ABS] <= p[P_STOP_TOL] * released &&
+    if (!train && l >= last_deposit && tally[T_POS_ABS] <= p[P_STOP_TOL] * released &&
         tally[T_NEG_ABS] <= p[P_STOP_TOL] * released_neg)
       break;
     if (steps == max_steps) flags |= FLAG_MAX_STEPS;
@@ -582,17 +647,39 @@ int orc_solve(const double *p, int64_t nx, int64_t ny, int64_t nz,
 
   if (max_beta_n > 1.0) flags |= FLAG_REACTION;
   const double collected = sums[1] + sums[2] + sums[3] + sums[4];
-  double f;
+  double f, f_R;
   if (released + released_neg > 0.0) {
     f = collected / (released + released_neg);
+    /* recombined pairs against the mean number released per species */
+    f_R = 1.0 - 2.0 * sums[0] / (released + released_neg);
   } else {
     f = 1.0;
+    f_R = 1.0;
     flags |= FLAG_EMPTY;
+  }
+  res[R_PULSES] = 0.0;
+  res[R_PERIOD_RELEASED] = res[R_PERIOD_COLLECTED] = res[R_PERIOD_RECOMBINED] = 0.0;
+  if (train) {
+    const int64_t delivered = (steps + m - 1) / m;  /* pulses at steps 0, m, 2m, ... below `steps` */
+    res[R_PULSES] = (double)(delivered < npulses ? delivered : npulses);
+  }
+  if (period_started) {
+    /* the last period of the train */
+    double pc = 0.0;
+    for (int q = 1; q < 5; ++q) pc += sums[q] - period_sums[q];
+    const double prel = period_rel[0] + period_rel[1];
+    const double prec = sums[0] - period_sums[0];
+    res[R_PERIOD_RELEASED] = prel;
+    res[R_PERIOD_COLLECTED] = pc;
+    res[R_PERIOD_RECOMBINED] = prec;
+    if (prel > 0.0) {
+      f = pc / prel;
+      f_R = 1.0 - 2.0 * prec / prel;
+    }
   }
   res[R_F] = f;
   res[R_KS] = 1.0 / f;
-  /* recombined pairs against the mean number released per species */
-  res[R_F_RECOMB] = released + released_neg > 0.0 ? 1.0 - 2.0 * sums[0] / (released + released_neg) : 1.0;
+  res[R_F_RECOMB] = f_R;
   res[R_RELEASED] = released;
   res[R_RECOMBINED] = sums[0];
   res[R_INFLIGHT_POS] = last[T_POS_INFLIGHT];
@@ -789,8 +876,8 @@ void orc_step3(const double *p, int64_t nx, int64_t ny, int64_t nz, double dt,
  * the positive plus negative charge released); res_e: RE_COUNT values of the
  * electron phase; trace: NULL or max_steps * T_COUNT phase-2 records;
  * trace_e: NULL or max_steps * E_COUNT phase-1 records.  Returns 0, -2 (no
- * step), -3 (a track not at t = 0, space charge on, or absorbing lateral
- * boundaries) or -1. */
+ * step), -3 (a track not at t = 0, space charge on, absorbing lateral
+ * boundaries or a pulse train) or -1. */
 int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz,
                              const double *trk, int64_t ntr, int64_t max_steps,
                              double *pos_out, double *neg_out, double *trace, double *res,
@@ -798,7 +885,7 @@ int orc_solve_free_electrons(const double *p, int64_t nx, int64_t ny, int64_t nz
 {
   for (int64_t t = 0; t < ntr; ++t)
     if (trk[TRK * t + 6] != 0.0) return -3;
-  if (p[P_SPACE_CHARGE] != 0.0 || p[P_LATERAL_BC] != 0.0) return -3;
+  if (p[P_SPACE_CHARGE] != 0.0 || p[P_LATERAL_BC] != 0.0 || p[P_N_PULSES] >= 2.0) return -3;
   double dt;
   int rc = orc_dt(p, nx, ny, nz, trk, ntr, &dt);
   if (rc) return rc;

@@ -40,7 +40,8 @@ class it_chamber(ctypes.Structure):
                 ("W_eV", ctypes.c_double), ("dt_safety", ctypes.c_double), ("stop_tol", ctypes.c_double),
                 ("uniform_n0", ctypes.c_double), ("reaction_limit", ctypes.c_double),
                 ("attach_coeff", ctypes.c_double), ("mu_e", ctypes.c_double), ("D_e", ctypes.c_double),
-                ("max_steps", ctypes.c_int64), ("lateral_bc", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int64), ("lateral_bc", ctypes.c_int32), ("n_pulses", ctypes.c_int32),
+                ("pulse_period_s", ctypes.c_double)]
 
 
 class it_result(ctypes.Structure):
@@ -51,7 +52,9 @@ class it_result(ctypes.Structure):
         "e_collected_cathode", "e_recombined", "e_left", "e_dt", "released_neg_charge", "n_escaped_pos",
         "n_escaped_neg")] + \
         [("e_steps", ctypes.c_int64), ("steps", ctypes.c_int64), ("flags", ctypes.c_int32),
-         ("passes", ctypes.c_int32)]
+         ("passes", ctypes.c_int32), ("pulses", ctypes.c_int32), ("reserved", ctypes.c_int32),
+         ("period_released", ctypes.c_double), ("period_collected", ctypes.c_double),
+         ("period_recombined", ctypes.c_double)]
 
 
 class it_exec(ctypes.Structure):
@@ -124,6 +127,8 @@ def _chamber(ch) -> it_chamber:
         setattr(c, k, float(ch.get(k, 0.0)))
     c.space_charge = int(ch.get("space_charge", 0))
     c.lateral_bc = int(ch.get("lateral_bc", 0))
+    c.n_pulses = int(ch.get("n_pulses", 0))
+    c.pulse_period_s = float(ch.get("pulse_period_s", 0.0))
     return c
 
 
@@ -277,6 +282,8 @@ def _result(r: it_result) -> dict:
     out["e_steps"] = int(out["e_steps"])
     out["flags"] = int(out["flags"])
     out["passes"] = int(out["passes"])
+    out["pulses"] = int(out["pulses"])
+    del out["reserved"]
     return out
 
 

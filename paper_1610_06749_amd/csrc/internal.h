@@ -60,7 +60,30 @@ struct RunState {
   int32_t flags;            // IT_FLAG_NONFINITE
   int32_t passes;           // stepping launches that ran (not skipped)
   int32_t by_limit;         // 1 if a batched run stopped the instance at max_steps
+  // pulse train: the last period begins at step period_step (INT64_MAX:
+  // no train); when its step is recorded, the running sums and the ions its
+  // pulse released are kept
+  int64_t period_step;
+  double period_sums[5];
+  double period_rel[2];
+  int32_t period_started;
+  // batched pulse trains: a pass of parity p adds the pulse to its outputs
+  // when pulse_add[p] is set (a pulse is due at the next step); the release
+  // of each later pulse (pulse_q, the first pulse's) is recorded with its step
+  int32_t pulse_add[2];
+  int32_t pulses_counted;   // pulses whose release is recorded
+  int32_t pulses_flagged;   // pulses whose pulse_add flag has been set
+  int32_t pulse_pad;
+  double pulse_q[2];
 };
+
+// A run state before any deposit (no pulse train).
+inline RunState initial_run_state() {
+  RunState s;
+  __builtin_memset(&s, 0, sizeof(s));
+  s.period_step = INT64_MAX;
+  return s;
+}
 
 // Track prepared on the host for the deposit kernel.
 struct DepTrack {
@@ -133,6 +156,12 @@ struct BatchInstance {
   int tile_begin;    // first entry of this instance in the batch's tile list
   int ntiles;
   int64_t max_steps;
+  // pulse train (npulses >= 2; 0 otherwise): pulse k is due at step
+  // k * period_steps; pulse_pos/pulse_neg hold the first pulse's densities
+  int npulses;
+  int64_t period_steps;
+  const double* pulse_pos;
+  const double* pulse_neg;
 };
 
 // One electron-phase step of the three carriers (free-electron component).
@@ -171,16 +200,17 @@ hipError_t launch_step_plain(const StepParams& p, int tile_y, int tile_x, hipStr
 hipError_t launch_deposit(const DepositParams& p, hipStream_t s);
 hipError_t launch_reduce_steps(const StepParams& p, int nblocks, int T, hipStream_t s);
 // sc: some instance has the space-charge term on; ab: some instance has
-// absorbing lateral boundaries; record_prev: the launch also records the
-// previous pass's step of every instance (false only for the first pass)
+// absorbing lateral boundaries; pu: some instance has a pulse train (one
+// step per pass); record_prev: the launch also records the previous pass's
+// step of every instance (false only for the first pass)
 // T > 1: T steps per launch with the blocked tile pass, R rows per thread
 // (tile_y and tile_x are then unused)
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
-                             bool ab, int parity, bool record_prev, int T, int R, hipStream_t s);
+                             bool ab, bool pu, int parity, bool record_prev, int T, int R, hipStream_t s);
 // The same pass (recording the previous one) as a kernel node of `graph`
 // that depends on `dep` (null: none).
 hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNode_t* node, const void* table,
-                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, int parity,
-                               int T, int R);
+                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, bool pu,
+                               int parity, int T, int R);
 
 }  // namespace it

@@ -29,6 +29,14 @@ __device__ inline int find_instance(const BatchInstance* inst, int ninst, int L)
 // Records the previous pass's T steps of instance q (its partials are in
 // the buffer of the other parity), up to the instance's step limit: a pass
 // may run past it, and those steps are not recorded.
+//
+// Pulse trains (one step per pass): pass p computes step p, and the pass
+// before a pulse step adds the pulse to its outputs.  The recording block of
+// pass p (recording step r = p - 1) first books the release of a pulse
+// deposited before step r (the first pulse's, kept when step 0 is
+// recorded), then sets the flag of pass p + 1, whose outputs take a pulse
+// due at step r + 3.  The flags alternate by pass parity, so the tile
+// blocks of pass p read a flag that pass p - 1 wrote.
 template <int NT>
 __device__ void record_previous(const BatchInstance& bi, int parity, int T) {
   const StepParams& p = bi.sp[parity ^ 1];
@@ -36,17 +44,44 @@ __device__ void record_previous(const BatchInstance& bi, int parity, int T) {
   __shared__ double totals[kAcc * kMaxT];
   reduce_partials<NT>(p.partials, bi.ntiles, kAcc * T, kAcc * T, totals);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
-    const int64_t step = p.state->steps;
+    RunState* st = p.state;
+    const int64_t step = st->steps;
+    const bool train = bi.npulses >= 2;
+    if (train) {
+      if (step == 0) {
+        st->pulse_q[0] = st->released;
+        st->pulse_q[1] = st->released_neg;
+      }
+      const int k = st->pulses_counted;
+      if (k < bi.npulses && (int64_t)k * bi.period_steps == step) {
+        st->released += st->pulse_q[0];
+        st->released_pending += st->pulse_q[0];
+        st->released_neg += st->pulse_q[1];
+        st->released_pending_neg += st->pulse_q[1];
+        st->released_q += st->pulse_q[1];  // negative charge: the ions (no free electrons in a train)
+        st->pulses_counted = k + 1;
+      }
+    }
     const int Te = (int)min((int64_t)T, bi.max_steps - step);
-    finalize_steps(p.state, p.trace, totals, Te, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
-    if (!p.state->done && p.state->steps >= bi.max_steps) {
-      p.state->done = 1;
-      p.state->by_limit = 1;
+    finalize_steps(st, p.trace, totals, Te, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
+    if (!st->done && st->steps >= bi.max_steps) {
+      st->done = 1;
+      st->by_limit = 1;
+    }
+    if (train) {
+      // (a pulse at or past the run's last step is never deposited)
+      const int kf = st->pulses_flagged;
+      const int64_t s_due = (int64_t)kf * bi.period_steps;
+      const bool due = kf < bi.npulses && s_due == step + 3 && s_due < bi.max_steps;
+      st->pulse_add[parity ^ 1] = due ? 1 : 0;
+      if (due) st->pulses_flagged = kf + 1;
     }
   }
 }
 
-template <int SY, bool SC, bool AB, int TX>
+// PU: some instance of the batch has a pulse train (its tile blocks add
+// the pulse when their instance's flag for this pass is set).
+template <int SY, bool SC, bool AB, int TX, bool PU>
 __global__ __launch_bounds__(kTX * SY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                        int parity) {
@@ -63,7 +98,15 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
   const int l = L - inst[q].tile_begin;
   TileCoord t = tile_of(l, p.tiles_x, p.tiles_y);
   t.valid = true;
-  plain_tile_step<SY, SC, AB, TX>(p, t, p.partials + (size_t)l * kAcc);
+  if (PU) {
+    const BatchInstance& bi = inst[q];
+    // written by the previous pass's recording block; one value for the block
+    const int add = bi.npulses >= 2 ? __builtin_amdgcn_readfirstlane(p.state->pulse_add[parity]) : 0;
+    plain_tile_step<SY, SC, AB, TX, true>(p, t, p.partials + (size_t)l * kAcc, add ? bi.pulse_pos : nullptr,
+                                          add ? bi.pulse_neg : nullptr);
+  } else {
+    plain_tile_step<SY, SC, AB, TX>(p, t, p.partials + (size_t)l * kAcc);
+  }
 }
 
 // T steps per launch: the temporally blocked tile pass of stencil_blocked.h
@@ -97,37 +140,20 @@ void batch_blocked_kernel(const BatchInstance* __restrict__ inst, int ninst, int
 
 namespace {
 
-template <int SY, bool SC, bool AB, int TX>
-void launch_batch_instance(const BatchInstance* inst, int nrecord, int ninst, int total_tiles, int per_xcd,
-                           int parity, hipStream_t s) {
-  hipLaunchKernelGGL((batch_step_kernel<SY, SC, AB, TX>), dim3(8 * per_xcd + nrecord), dim3(kTX, SY), 0, s, inst,
-                     ninst, total_tiles, per_xcd, parity);
-}
-
-template <int SY, int TX>
-void launch_batch_terms(const BatchInstance* inst, int nrecord, int ninst, int total_tiles, int per_xcd,
-                        int parity, bool sc, bool ab, hipStream_t s) {
+// The kernel instance of a one-step pass.
+template <int SY, int TX, bool PU>
+const void* batch_kernel_pu(bool sc, bool ab) {
   switch ((sc ? 2 : 0) + (ab ? 1 : 0)) {
-    case 0: launch_batch_instance<SY, false, false, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
-    case 1: launch_batch_instance<SY, false, true, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
-    case 2: launch_batch_instance<SY, true, false, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
-    default: launch_batch_instance<SY, true, true, TX>(inst, nrecord, ninst, total_tiles, per_xcd, parity, s); break;
+    case 0: return reinterpret_cast<const void*>(&batch_step_kernel<SY, false, false, TX, PU>);
+    case 1: return reinterpret_cast<const void*>(&batch_step_kernel<SY, false, true, TX, PU>);
+    case 2: return reinterpret_cast<const void*>(&batch_step_kernel<SY, true, false, TX, PU>);
+    default: return reinterpret_cast<const void*>(&batch_step_kernel<SY, true, true, TX, PU>);
   }
 }
 
-}  // namespace
-
-namespace {
-
-// The kernel instance of a pass and its block shape.
 template <int SY, int TX>
-const void* batch_kernel_terms(bool sc, bool ab) {
-  switch ((sc ? 2 : 0) + (ab ? 1 : 0)) {
-    case 0: return reinterpret_cast<const void*>(&batch_step_kernel<SY, false, false, TX>);
-    case 1: return reinterpret_cast<const void*>(&batch_step_kernel<SY, false, true, TX>);
-    case 2: return reinterpret_cast<const void*>(&batch_step_kernel<SY, true, false, TX>);
-    default: return reinterpret_cast<const void*>(&batch_step_kernel<SY, true, true, TX>);
-  }
+const void* batch_kernel_terms(bool sc, bool ab, bool pu) {
+  return pu ? batch_kernel_pu<SY, TX, true>(sc, ab) : batch_kernel_pu<SY, TX, false>(sc, ab);
 }
 
 template <int T, int R>
@@ -156,28 +182,30 @@ const void* batch_blocked(int T, int R, bool sc) {
   }
 }
 
-const void* batch_kernel(int tile_y, int tile_x, bool sc, bool ab, int* sy) {
+// The one-step kernel of a pass and its waves per block.
+const void* batch_kernel(int tile_y, int tile_x, bool sc, bool ab, bool pu, int* sy) {
   if (plain_tile_cols(tile_x) == 32) {
     *sy = 8;
-    return batch_kernel_terms<8, 32>(sc, ab);
+    return batch_kernel_terms<8, 32>(sc, ab, pu);
   }
   if (plain_tile_rows(tile_y, tile_x) == 16) {
     *sy = 16;
-    return batch_kernel_terms<16, 64>(sc, ab);
+    return batch_kernel_terms<16, 64>(sc, ab, pu);
   }
   *sy = 8;
-  return batch_kernel_terms<8, 64>(sc, ab);
+  return batch_kernel_terms<8, 64>(sc, ab, pu);
 }
 
 }  // namespace
 
 hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNode_t* node, const void* table,
-                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, int parity,
-                               int T, int R) {
+                               int ninst, int total_tiles, int tile_y, int tile_x, bool sc, bool ab, bool pu,
+                               int parity, int T, int R) {
   const BatchInstance* inst = (const BatchInstance*)table;
   int per_xcd = (total_tiles + 7) / 8;
   int sy = 8;
-  const void* fn = T > 1 ? batch_blocked(T, R, sc) : batch_kernel(tile_y, tile_x, sc, ab, &sy);
+  if (T > 1 && (ab || pu)) return hipErrorInvalidValue;  // the blocked pass: periodic, single pulses
+  const void* fn = T > 1 ? batch_blocked(T, R, sc) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
   if (!fn) return hipErrorInvalidValue;
   if (T > 1) sy = kBW;  // blocks of 8 waves
   // the node copies the argument values when it is added
@@ -193,24 +221,17 @@ hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNod
 }
 
 hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int tile_y, int tile_x, bool sc,
-                             bool ab, int parity, bool record_prev, int T, int R, hipStream_t s) {
+                             bool ab, bool pu, int parity, bool record_prev, int T, int R, hipStream_t s) {
   const BatchInstance* inst = (const BatchInstance*)table;
-  const int per_xcd = (total_tiles + 7) / 8;
+  int per_xcd = (total_tiles + 7) / 8;
   const int nr = record_prev ? ninst : 0;
-  if (T > 1) {
-    const void* fn = batch_blocked(T, R, sc);
-    if (!fn || ab) return hipErrorInvalidValue;  // the blocked pass is periodic only
-    void* args[] = {(void*)&inst, (void*)&ninst, (void*)&total_tiles, (void*)const_cast<int*>(&per_xcd),
-                    (void*)&parity};
-    return hipLaunchKernel(fn, dim3(8 * per_xcd + nr), dim3(kWave, kBW), args, 0, s);
-  }
-  if (plain_tile_cols(tile_x) == 32)
-    launch_batch_terms<8, 32>(inst, nr, ninst, total_tiles, per_xcd, parity, sc, ab, s);
-  else if (plain_tile_rows(tile_y, tile_x) == 16)
-    launch_batch_terms<16, 64>(inst, nr, ninst, total_tiles, per_xcd, parity, sc, ab, s);
-  else
-    launch_batch_terms<8, 64>(inst, nr, ninst, total_tiles, per_xcd, parity, sc, ab, s);
-  return hipGetLastError();
+  int sy = 8;
+  if (T > 1 && (ab || pu)) return hipErrorInvalidValue;  // the blocked pass: periodic, single pulses
+  const void* fn = T > 1 ? batch_blocked(T, R, sc) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
+  if (!fn) return hipErrorInvalidValue;
+  if (T > 1) sy = kBW;
+  void* args[] = {(void*)&inst, (void*)&ninst, (void*)&total_tiles, (void*)&per_xcd, (void*)&parity};
+  return hipLaunchKernel(fn, dim3(8 * per_xcd + nr), dim3(kTX, sy), args, 0, s);
 }
 
 }  // namespace it

@@ -126,6 +126,7 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
   for (int q = 0; q < 4; ++q) last[q] = gst->last[q];
   int64_t steps = gst->steps;
   int done = gst->done, flags = gst->flags;
+  const int64_t period_step = gst->period_step;
   for (int s = 0; s < T && !done; ++s) {
     const int64_t l = step0 + s;
     const double* a = tot + s * kAcc;
@@ -147,6 +148,13 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
     rec[14] = a[12] * dV;
     pending = 0.0;
     pending_neg = 0.0;
+    if (l == period_step) {  // the last period of a pulse train begins with this step
+#pragma unroll
+      for (int q = 0; q < 5; ++q) gst->period_sums[q] = sums[q];
+      gst->period_rel[0] = rec[9];
+      gst->period_rel[1] = rec[12];
+      gst->period_started = 1;
+    }
     bool finite = true;
 #pragma unroll
     for (int q = 0; q < IT_TRACE_COLS; ++q) {

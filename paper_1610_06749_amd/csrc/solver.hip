@@ -32,6 +32,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
+constexpr int32_t kMaxPulses = 1 << 20;  // pulses of a pulse train
+
 int check_chamber(const it_chamber* ch) {
   if (!ch) return IT_EINVAL;
   if (ch->nx < 1 || ch->ny < 1 || ch->nz < 2) return IT_EINVAL;
@@ -52,6 +54,8 @@ int check_chamber(const it_chamber* ch) {
   if (!finite_nonneg(ch->reaction_limit)) return IT_EINVAL;
   if (!finite_nonneg(ch->attach_coeff) || !finite_nonneg(ch->mu_e) || !finite_nonneg(ch->D_e)) return IT_EINVAL;
   if (ch->max_steps < 1) return IT_EINVAL;
+  if (ch->n_pulses < 0 || ch->n_pulses > kMaxPulses) return IT_EINVAL;
+  if (ch->n_pulses >= 2 && !(std::isfinite(ch->pulse_period_s) && ch->pulse_period_s > 0)) return IT_EINVAL;
   return IT_OK;
 }
 
@@ -129,7 +133,10 @@ double screening_coef(const it_chamber* ch, double dt, int s) {
   return s == 0 ? -ch->mu_pos * g : ch->mu_neg * g;
 }
 
-int compute_dt(const it_chamber* ch, const it_track* tr, int64_t n, double* dt) {
+// The run's time step; with a pulse train, also the steps per period
+// (period_steps, may be null; 0 without a train): the single-pulse step is
+// shortened so that a period is a whole number of steps.
+int compute_dt(const it_chamber* ch, const it_track* tr, int64_t n, double* dt, int64_t* period_steps = nullptr) {
   double best = transport_dt(ch);
   const double rate = pointwise_rate(ch);
   if (ch->reaction_limit > 0.0 && rate > 0.0) {
@@ -138,6 +145,23 @@ int compute_dt(const it_chamber* ch, const it_track* tr, int64_t n, double* dt) 
   }
   if (!(best < INFINITY)) return IT_ENODT;
   *dt = ch->dt_safety * best;
+  if (period_steps) *period_steps = 0;
+  if (ch->n_pulses >= 2) {
+    const double per = std::ceil(ch->pulse_period_s / *dt);
+    if (!(per <= 1.0e15 / (double)ch->n_pulses)) return IT_EINVAL;  // steps of the train out of range
+    *dt = ch->pulse_period_s / per;
+    if (period_steps) *period_steps = (int64_t)per;
+  }
+  return IT_OK;
+}
+
+// A pulse train repeats one instantaneous pulse: every track due at t = 0,
+// and no free electrons.
+int check_train(const it_chamber* ch, const it_track* tr, int64_t n) {
+  if (ch->n_pulses < 2) return IT_OK;
+  if (ch->mu_e > 0.0) return IT_ENOTSUP;
+  for (int64_t q = 0; q < n; ++q)
+    if (tr[q].t_s != 0.0) return IT_ENOTSUP;
   return IT_OK;
 }
 
@@ -728,6 +752,7 @@ int run_loop(const it_chamber* ch, double dt, const it_exec* ex, char* ws, const
 struct InstLayout {
   size_t off_field[4], field_elems;
   size_t off_partials, off_counter, off_tracks;
+  size_t off_pulse[2];  // the first pulse's densities (pulse trains only)
   int ntiles;       // stepping tiles (plain kernel)
 };
 
@@ -764,7 +789,7 @@ int batch_steps(const it_chamber* ch, int ninst, const it_exec* ex) {
   const int T = requested_steps(ex);
   if (T > 0) return T;
   for (int q = 0; q < ninst; ++q)
-    if (ch[q].lateral_bc) return 1;
+    if (ch[q].lateral_bc || ch[q].n_pulses >= 2) return 1;
   if (ex && (ex->tile_x || ex->tile_y || ex->z_chunk)) return 1;
   return kBlockedT;
 }
@@ -778,7 +803,7 @@ int check_batch_steps(const it_chamber* ch, int ninst, const it_exec* ex, int T)
   if (!blocked_supported(T, ex ? ex->tile_y : 0)) return ex && ex->tile_y ? IT_EINVAL : IT_ENOTSUP;
   if (ex && ex->tile_x) return IT_EINVAL;
   for (int q = 0; q < ninst; ++q)
-    if (ch[q].lateral_bc) return IT_ENOTSUP;
+    if (ch[q].lateral_bc || ch[q].n_pulses >= 2) return IT_ENOTSUP;
   return IT_OK;
 }
 
@@ -826,6 +851,12 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
     off = align_up(off + 64 * sizeof(unsigned));
     L.off_tracks = off;
     off = align_up(off + (size_t)std::max<int64_t>(toff[q + 1] - toff[q], 1) * sizeof(DepTrack));
+    L.off_pulse[0] = L.off_pulse[1] = 0;
+    if (c.n_pulses >= 2)
+      for (int f = 0; f < 2; ++f) {
+        L.off_pulse[f] = off;
+        off = align_up(off + L.field_elems * sizeof(double));
+      }
   }
   B.off_states = off;
   off = align_up(off + (size_t)ninst * sizeof(RunState));
@@ -846,6 +877,8 @@ int check_batch(const it_chamber* ch, const int64_t* toff, const it_track* track
     rc = check_tracks(n ? tracks + toff[q] : nullptr, n);
     if (rc) return rc;
     if (ch[q].mu_e > 0.0) return IT_ENOTSUP;  // free electrons: single runs only
+    rc = check_train(&ch[q], n ? tracks + toff[q] : nullptr, n);
+    if (rc) return rc;
   }
   return IT_OK;
 }
@@ -894,6 +927,27 @@ void fill_result(const RunState& fin, double dt, int64_t max_steps, int issued, 
   out->steps = fin.steps;
   out->flags = flags;
   out->passes = issued;
+}
+
+// The pulse-train part of a result (period_steps m > 0): pulses deposited,
+// and f, ks, f_R and the period counts from the last period once it began.
+void train_result(const RunState& fin, const it_chamber* ch, int64_t m, it_result* out) {
+  if (ch->n_pulses < 2 || m <= 0) return;
+  const int64_t delivered = (fin.steps + m - 1) / m;  // pulses at steps 0, m, 2m, ... below fin.steps
+  out->pulses = (int32_t)std::min<int64_t>(delivered, ch->n_pulses);
+  if (!fin.period_started) return;
+  double collected = 0.0;
+  for (int q = 1; q < 5; ++q) collected += fin.sums[q] - fin.period_sums[q];
+  const double released = fin.period_rel[0] + fin.period_rel[1];
+  const double recombined = fin.sums[0] - fin.period_sums[0];
+  out->period_released = released;
+  out->period_collected = collected;
+  out->period_recombined = recombined;
+  if (released > 0.0) {
+    out->f = collected / released;
+    out->ks = 1.0 / out->f;
+    out->f_R = 1.0 - 2.0 * recombined / released;
+  }
 }
 
 }  // namespace
@@ -1017,13 +1071,18 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     for (int64_t q = 0; q < ntracks; ++q)
       if (tracks[q].t_s != 0.0) return IT_ENOTSUP;
   }
+  rc = check_train(ch, tracks, ntracks);
+  if (rc) return rc;
+  const bool train = ch->n_pulses >= 2;
   const int T = exec_steps(ch, exec, d_pos_out || d_neg_out);
   rc = check_exec_ws(ch, exec, T, d_workspace);
   if (rc) return rc;
   const Layout L = make_layout(ch, ntracks);
   if (!d_workspace || ws_bytes < L.total) return IT_EWORKSPACE;
   double dt;
-  compute_dt(ch, tracks, ntracks, &dt);
+  int64_t period_steps = 0;
+  rc = compute_dt(ch, tracks, ntracks, &dt, &period_steps);
+  if (rc) return rc;
   HostSlots hs;
   host_slots(exec, 1, hs);
   hipStream_t stream = (hipStream_t)stream_;
@@ -1075,12 +1134,22 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     }
     last_dep = std::max<int64_t>(last_dep, 0);
   }
+  // a pulse train: pulse k repeats the deposit of step 0 (every track is due
+  // then) at step k m
+  if (train && !events.empty()) {
+    const Event first = events[0];
+    for (int64_t k = 1; k < ch->n_pulses && k * period_steps < ch->max_steps; ++k) {
+      Event e = first;
+      e.step = k * period_steps;
+      events.push_back(e);
+    }
+  }
 
   for (int f = 0; f < 4; ++f)
     HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, L.field_elems * sizeof(double), stream));
   HIP_TRY(hipMemsetAsync(ws + L.off_counter, 0, 64 * sizeof(unsigned), stream));
-  RunState init;
-  std::memset(&init, 0, sizeof(init));
+  RunState init = initial_run_state();
+  if (train) init.period_step = (ch->n_pulses - 1) * period_steps;
   HIP_TRY(hipMemcpyAsync(ws + L.off_state, &init, sizeof(init), hipMemcpyHostToDevice, stream));
   if (!dev.empty())
     HIP_TRY(hipMemcpyAsync(ws + L.off_tracks, dev.data(), dev.size() * sizeof(DepTrack),
@@ -1120,10 +1189,13 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
 
   RunState fin;
   int issued = 0;
-  const int64_t ion_steps = ch->max_steps - e_steps;
+  const int64_t limit = ch->max_steps - e_steps;
+  // a pulse train ends with its last period, with no collection test
+  const int64_t ion_steps = train ? std::min<int64_t>(ch->n_pulses * period_steps, limit) : limit;
+  const int64_t min_stop = train ? INT64_MAX : std::max<int64_t>(last_dep, 0);
   if (ion_steps > 0) {
-    rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ion_steps,
-                  std::max<int64_t>(last_dep, 0), ch->stop_tol, T, stream, hs, &fin, &issued);
+    rc = run_loop(ch, dt, exec, ws, L, events, dev, same_radii(tracks, ntracks), ion_steps, min_stop,
+                  ch->stop_tol, T, stream, hs, &fin, &issued);
     if (rc) return rc;
   } else {
     HIP_TRY(hipMemcpyAsync(hs.p, ws + L.off_state, sizeof(fin), hipMemcpyDeviceToHost, stream));
@@ -1131,7 +1203,8 @@ int it_solve(const it_chamber* ch, const it_track* tracks, int64_t ntracks, cons
     fin = *hs.p;
   }
 
-  fill_result(fin, dt, ion_steps, issued, out);
+  fill_result(fin, dt, limit, issued, out);
+  train_result(fin, ch, period_steps, out);
   if (fe) out->e_dt = std::min(dt, ch->dt_safety * electron_dt(ch));
 
   if (h_trace && fin.steps > 0) {
@@ -1179,9 +1252,11 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   const int rows = batch_rows(ch, ninst, exec);
   bool any_sc = false;
   bool any_ab = false;
+  bool any_pu = false;
   for (int q = 0; q < ninst; ++q) {
     any_sc = any_sc || ch[q].space_charge != 0;
     any_ab = any_ab || ch[q].lateral_bc != 0;
+    any_pu = any_pu || ch[q].n_pulses >= 2;
   }
   int passes_per_graph = exec && exec->check_every > 0 ? exec->check_every : 32;
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
@@ -1199,6 +1274,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   RunState* states = (RunState*)(ws + B.off_states);
 
   std::vector<double> dts(ninst);
+  std::vector<int64_t> period_steps(ninst);
   std::vector<BatchInstance> table(ninst);
   int total_tiles = 0;
   int64_t max_steps_all = 0;
@@ -1206,8 +1282,10 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     const it_chamber* c = &ch[q];
     const int64_t n = track_offsets[q + 1] - track_offsets[q];
     const it_track* tq = n ? tracks + track_offsets[q] : nullptr;
-    rc = compute_dt(c, tq, n, &dts[q]);
+    rc = compute_dt(c, tq, n, &dts[q], &period_steps[q]);
     if (rc) return rc;
+    const bool train = c->n_pulses >= 2;
+    const int64_t m = period_steps[q];
     for (int64_t k = 0; k < n; ++k)
       if (deposit_step(tq[k].t_s, dts[q]) != 0) return IT_ENOTSUP;  // one pulse per instance
     const InstLayout& L = B.inst[q];
@@ -1253,7 +1331,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       sp.dV = dV;
       sp.stop_tol = c->stop_tol;
       sp.step0 = 0;
-      sp.min_stop_step = 0;
+      sp.min_stop_step = train ? INT64_MAX : 0;  // a pulse train ends with its last period
       sp.partials = (double*)(ws + L.off_partials) + (size_t)par * L.ntiles * kAcc * T;
       sp.counter = (unsigned*)(ws + L.off_counter);
       sp.state = states + q;
@@ -1261,12 +1339,28 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     }
     bi.tile_begin = total_tiles;
     bi.ntiles = ts.ntiles;
-    bi.max_steps = c->max_steps;
+    bi.max_steps = train ? std::min<int64_t>(c->max_steps, c->n_pulses * m) : c->max_steps;
+    bi.npulses = train ? c->n_pulses : 0;
+    bi.period_steps = m;
+    bi.pulse_pos = train ? (const double*)(ws + L.off_pulse[0]) : nullptr;
+    bi.pulse_neg = train ? (const double*)(ws + L.off_pulse[1]) : nullptr;
     total_tiles += ts.ntiles;
-    max_steps_all = std::max(max_steps_all, c->max_steps);
+    max_steps_all = std::max(max_steps_all, bi.max_steps);
     // the pulse: uniform pre-ionisation and the tracks, deposited before step 0
-    RunState init;
-    std::memset(&init, 0, sizeof(init));
+    RunState init = initial_run_state();
+    if (train) {
+      // pulse 0 is deposited and booked here; the passes before steps 1 and
+      // 2 (the first two, whose flags no recording block sets) take the
+      // pulses due at those steps
+      init.period_step = (c->n_pulses - 1) * m;
+      init.pulses_counted = 1;
+      init.pulses_flagged = 1;
+      for (int64_t s = 1; s <= 2; ++s)
+        if (s % m == 0 && s / m < c->n_pulses && s < bi.max_steps) {
+          init.pulse_add[s - 1] = 1;
+          ++init.pulses_flagged;
+        }
+    }
     HIP_TRY(hipMemcpyAsync(states + q, &init, sizeof(init), hipMemcpyHostToDevice, stream));
     if (n || c->uniform_n0 > 0.0) {
       DepositParams dp = base_deposit(c, dts[q], td);
@@ -1283,6 +1377,10 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       dp.state = states + q;
       HIP_TRY(launch_deposit(dp, stream));
     }
+    if (train)  // the first pulse's densities (the fields held zero before it)
+      for (int f = 0; f < 2; ++f)
+        HIP_TRY(hipMemcpyAsync(ws + L.off_pulse[f], ws + L.off_field[f], L.field_elems * sizeof(double),
+                               hipMemcpyDeviceToDevice, stream));
   }
   // The pass chain runs on the tile list of the running instances only: the
   // table is rebuilt (and the graph re-captured) whenever a quarter of its
@@ -1323,7 +1421,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     for (int k = 0; k < passes_per_graph; ++k) {
       hipGraphNode_t node = nullptr;
       if (add_batch_pass_node(graph, prev, &node, ws + B.off_table, (int)t.size(), tiles, rows, tile_x, any_sc,
-                              any_ab, (parity0 + k) & 1, T, R) != hipSuccess)
+                              any_ab, any_pu, (parity0 + k) & 1, T, R) != hipSuccess)
         return IT_EHIP;
       prev = node;
     }
@@ -1342,7 +1440,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   {
     int tiles = 0;
     for (int q = 0; q < ninst; ++q) tiles += table[q].ntiles;
-    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, tile_x, any_sc, any_ab, 0, false, T, R, stream) !=
+    if (launch_batch_pass(ws + B.off_table, ninst, tiles, rows, tile_x, any_sc, any_ab, any_pu, 0, false, T, R,
+                          stream) !=
         hipSuccess) {
       release_graph();
       return IT_EHIP;
@@ -1402,7 +1501,10 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   (void)hipEventDestroy(evs[1]);
   release_graph();
   if (rc) return rc;
-  for (int q = 0; q < ninst; ++q) fill_result(host[q], dts[q], ch[q].max_steps, issued, &out[q]);
+  for (int q = 0; q < ninst; ++q) {
+    fill_result(host[q], dts[q], ch[q].max_steps, issued, &out[q]);
+    train_result(host[q], &ch[q], period_steps[q], &out[q]);
+  }
   return IT_OK;
 }
 
@@ -1432,8 +1534,7 @@ int it_advance(const it_chamber* ch, double dt, int64_t nsteps, const it_exec* e
   }
   for (int f = 2; f < 4; ++f) HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, bytes, stream));
   HIP_TRY(hipMemsetAsync(ws + L.off_counter, 0, 64 * sizeof(unsigned), stream));
-  RunState init;
-  std::memset(&init, 0, sizeof(init));
+  const RunState init = initial_run_state();
   HIP_TRY(hipMemcpyAsync(ws + L.off_state, &init, sizeof(init), hipMemcpyHostToDevice, stream));
   std::vector<Event> none;
   std::vector<DepTrack> nodev;

@@ -49,9 +49,14 @@ struct PlaneRegs {
 // SC: with the space-charge term (its two extra tallies cost registers, so
 // runs without it use the instance without them).  AB: honours
 // p.absorbing (absorbing lateral boundaries and the escaped tally, slots
-// 11-12); the instance without it is periodic only.
-template <int SY, bool SC, bool AB, int TX = kTX>
-__device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, double* partial_out) {
+// 11-12); the instance without it is periodic only.  PU: when add_p and
+// add_n are given (block-uniform), a pulse of a pulse train is due at the
+// next step: those densities are added to the stored outputs after the
+// tallies of this step are taken, and beta times the largest density the
+// outputs then hold enters the run's max_beta_n, as a deposit does.
+template <int SY, bool SC, bool AB, int TX = kTX, bool PU = false>
+__device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, double* partial_out,
+                                       const double* add_p = nullptr, const double* add_n = nullptr) {
   static_assert(TX == 64 || TX == 32, "tile width");
   constexpr int kSNT = kTX * SY;
   constexpr int SR = SY * (kTX / TX);  // rows of the tile
@@ -84,6 +89,8 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   const int j_bot = y0 + h == p.ny ? 0 : y0 + h;
   const Coef cp = p.cp, cn = p.cn;
   const double beta = p.beta, gsp = p.gsp, gsn = p.gsn;
+  const bool add = PU && add_p != nullptr;
+  double add_max = 0.0;  // largest output density after the pulse is added
   // in-plane byte offsets (a plane holds at most 2^28 nodes, checked on the
   // host, so they fit 32 bits and the loads take a scalar base address)
   const unsigned own = (unsigned)(jc * p.nx + ic) * 8u;
@@ -150,8 +157,14 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
                       cn.azm * m.n - sink + scn;
     if (active) {
       const size_t o = (size_t)k * plane;
-      __builtin_nontemporal_store(vp, (__attribute__((address_space(1))) double*)(uniform_ptr(p.pout + o) + own));
-      __builtin_nontemporal_store(vn, (__attribute__((address_space(1))) double*)(uniform_ptr(p.nout + o) + own));
+      double sp_ = vp, sn_ = vn;
+      if (add) {  // the pulse due at the next step joins the outputs
+        sp_ += ld(uniform_ptr(add_p + o), own);
+        sn_ += ld(uniform_ptr(add_n + o), own);
+        add_max = fmax(add_max, fmax(sp_, sn_));
+      }
+      __builtin_nontemporal_store(sp_, (__attribute__((address_space(1))) double*)(uniform_ptr(p.pout + o) + own));
+      __builtin_nontemporal_store(sn_, (__attribute__((address_space(1))) double*)(uniform_ptr(p.nout + o) + own));
     }
     // Threads outside the tile's valid extent read LDS slots that this
     // block never wrote (whatever an earlier workgroup left, possibly NaN),
@@ -221,6 +234,20 @@ __device__ inline void plain_tile_step(const StepParams& p, const TileCoord t, d
   // without those terms
   constexpr uint32_t kZero = (SC ? 0u : 3u << 9) | (AB ? 0u : 3u << 11);
   block_sum_store<kAcc, kSNT, kZero>(acc, partial_out, lds);
+  if (add) {  // block-uniform
+    __shared__ double wave_maxima[SY];
+    const double m = wave_max(add_max);
+    if (lane == 0) wave_maxima[ty] = m;
+    __syncthreads();
+    if (lane == 0 && ty == 0) {
+      double b = wave_maxima[0];
+      for (int w = 1; w < SY; ++w) b = fmax(b, wave_maxima[w]);
+      const double v = beta * b;
+      // non-negative doubles order like their bit patterns
+      atomicMax((unsigned long long*)&p.state->max_beta_n,
+                (unsigned long long)__double_as_longlong(v > 0.0 ? v : 0.0));
+    }
+  }
 }
 
 // Paired tile: 128 x SY columns with SY waves; lane l of wave r owns the

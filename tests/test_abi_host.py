@@ -2,6 +2,7 @@
 every function the header declares, and its host-only entry points agree
 with the oracle's time step and reject bad input."""
 import ctypes
+import math
 import os
 import re
 
@@ -194,3 +195,48 @@ def test_product_path_does_not_import_oracle():
                 src = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle", src, flags=re.M), fn
                 assert "liboracle" not in src and "oracle.c" not in src, fn
+
+
+def test_struct_layouts_match_the_header(lib, tmp_path):
+    """The binding's ctypes structures have the C header's field offsets and
+    sizes (a C program built against the header prints them)."""
+    import subprocess
+    B = lib.binding
+    structs = {"it_chamber": B.it_chamber, "it_result": B.it_result, "it_exec": B.it_exec}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "iontracks.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_pulse_train_checks_and_step(lib, orc):
+    """n_pulses >= 2 needs a finite positive period; it_dt then gives the
+    shortened step P / ceil(P / dt1), the oracle's."""
+    ch, tr = W.single_track()
+    dt1 = lib.it_dt(ch, tr)
+    for P in (7.3 * dt1, dt1, 0.4 * dt1):
+        c = dict(ch, n_pulses=3, pulse_period_s=P)
+        assert lib.it_dt(c, tr) == P / math.ceil(P / dt1)
+        o = orc.solve(dict(c, max_steps=1), tr, with_fields=False)
+        assert lib.it_dt(c, tr) == o["dt"]
+    assert lib.it_dt(dict(ch, n_pulses=1, pulse_period_s=-1.0), tr) == dt1  # a single pulse ignores the period
+    for bad in (dict(n_pulses=-1), dict(n_pulses=3, pulse_period_s=0.0), dict(n_pulses=3, pulse_period_s=-1e-6),
+                dict(n_pulses=3, pulse_period_s=float("nan")), dict(n_pulses=2, pulse_period_s=1e30),
+                dict(n_pulses=(1 << 20) + 1, pulse_period_s=1e-6)):
+        with pytest.raises(lib.ItError) as e:
+            lib.it_validate(dict(ch, **bad), tr)
+        assert e.value.code == lib.IT_EINVAL, bad

@@ -1,4 +1,5 @@
-"""Input generators: the shaped pulse's arrival process and placement."""
+"""Input generators: the shaped pulse's arrival process and placement, and the
+surrogate samples (gap resolutions, pulse trains)."""
 import math
 
 import numpy as np
@@ -67,3 +68,31 @@ def test_surrogate_resolutions_blend_is_continuous(orc):
     hi = [50.0, 1e-3, 200.0, 0.030 * (1 + 1e-7), 0.1, 100.0]
     assert abs(single(hi) - single(lo)) > 2e-4
     assert abs(blended(hi) - blended(lo)) < 1e-5
+
+
+def test_surrogate_rate_moves_ks_and_is_continuous_at_the_train_threshold(orc):
+    """The sixth input: below the train threshold (period at least twice the
+    slower ion's gap transit) a sample is one pulse, so k_s is the same at
+    10 Hz and just below the threshold.  Just above it the sample becomes a
+    pulse train whose last period is the single pulse at the train's step
+    (shortened to a whole number of steps per period, which alone moves k_s
+    by a few 1e-5 here).  At 100 kHz the pulses overlap and k_s rises well
+    above the single pulse's."""
+    base = [20.0, 1e-3, 60.0, 0.05, 0.5]
+    T = 2 * 0.05 ** 2 / (min(W.AIR["mu_pos"], W.AIR["mu_neg"]) * 60.0)
+
+    def run(rate):
+        ch, tr = W.surrogate_chamber(base + [rate])
+        return orc.solve(ch, tr, with_fields=False), ch, tr
+
+    r10, ch10, tr = run(10.0)
+    r_below, ch_below, _ = run((1 - 1e-6) / T)
+    r_above, ch_above, _ = run((1 + 1e-6) / T)
+    r_fast, ch_fast, _ = run(1e5)
+    assert "n_pulses" not in ch10 and "n_pulses" not in ch_below
+    assert ch_above["n_pulses"] == 3 and ch_fast["n_pulses"] == 6
+    assert r_below["ks"] == r10["ks"]
+    single_at_train_dt = orc.solve(dict(ch10, dt_safety=r_above["dt"] / orc.dt(ch10, tr)), tr, with_fields=False)
+    assert r_above["ks"] == pytest.approx(single_at_train_dt["ks"], rel=1e-9)
+    assert r_above["ks"] == pytest.approx(r_below["ks"], rel=1e-4)
+    assert r_fast["ks"] > 1.05 * r10["ks"]

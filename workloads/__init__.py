@@ -279,11 +279,11 @@ def perturbed_field(shape, seed: int, scale: float = 1e9):
 # Surrogate inputs
 # --------------------------------------------------------------------------
 # Ranges of the six surrogate inputs: LET [keV/um], b [cm], V [V], gap [cm],
-# dose per pulse [mGy], pulse repetition rate [Hz].  The rate range keeps the
-# pulse period (>= 1 ms) longer than the longest ion collection time in this
-# box (~0.2 ms at 50 V over 0.125 cm), so pulses do not overlap and k_s is
-# the single-pulse value at every rate in the box.
-SURROGATE_RANGES = ((1.0, 500.0), (5e-4, 2e-3), (50.0, 400.0), (0.025, 0.125), (0.01, 1.0), (10.0, 1000.0))
+# dose per pulse [mGy], pulse repetition rate [Hz].  Where the pulse period
+# is shorter than the ions' collection (up to ~0.2 ms at 50 V over
+# 0.125 cm; rates above ~2.8 kHz there) the sample is a pulse train
+# (surrogate_train), so the rate moves k_s.
+SURROGATE_RANGES = ((1.0, 500.0), (5e-4, 2e-3), (50.0, 400.0), (0.025, 0.125), (0.01, 1.0), (10.0, 1.0e5))
 SURROGATE_LOG = (True, False, True, False, True, True)
 MLP_PARAMS = 34049
 MLP_HIDDEN = 128
@@ -302,6 +302,21 @@ def surrogate_inputs(seed: int, n: int) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
+def surrogate_train(x):
+    """Pulse train of a surrogate sample, (n_pulses, period): with the
+    pulse period P = 1 / rate at least T = 2 d^2 / (min(mu+, mu-) V), twice
+    the slower ion's transit of the whole gap, a pulse is collected before
+    the next arrives and the sample is one pulse, (0, 0.0); otherwise
+    N = ceil(T / P) + 1 pulses, so that the last period still holds every
+    earlier pulse whose ions are in flight."""
+    V, d, rate = float(x[2]), float(x[3]), float(x[5])
+    T = 2.0 * d * d / (min(AIR["mu_pos"], AIR["mu_neg"]) * V)
+    P = 1.0 / rate
+    if P >= T:
+        return 0, 0.0
+    return int(math.ceil(T / P)) + 1, P
+
+
 def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: float = 1.5, nz=None):
     """Chamber and track of one surrogate sample: one Gaussian track parallel
     to the field through the centre of a periodic cell of cells x cells nodes
@@ -309,12 +324,16 @@ def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: fl
     spacing (much coarser gap intervals let Lax-Wendroff ripples at the ion
     column fronts drive the recombination sink unstable) or exactly nz of
     them, the dose as uniform pre-ionisation, everything at t = 0 (one
-    pulse)."""
+    pulse), repeated as the pulse train of surrogate_train when the rate
+    makes pulses overlap."""
     let, b, V, d, dose, _rate = (float(v) for v in x)
     dx = b / b_over_dx
     if nz is None:
         nz = max(8, int(math.ceil(d / (dz_over_dx * dx))))
     ch = chamber(cells, cells, int(nz), dx, d, V, uniform_n0=dose * ion_pairs_per_mGy(AIR["W_eV"]))
+    n, P = surrogate_train(x)
+    if n:
+        ch.update(n_pulses=n, pulse_period_s=P)
     tr = tracks([[let, b, (cells // 2) * dx, (cells // 2) * dx, 0.0, 0.0, 0.0]])
     return ch, tr
 
