@@ -55,7 +55,10 @@ def expected_steps(ch, tr):
 def solver_lnks(X, group=512, stream=None, log=None):
     """Reference ln k_s of every input row from the batched solver (the
     blend of the two gap resolutions); returns (lnks, total voxel-steps,
-    seconds).  ``log``: None or a callable taking a progress message."""
+    seconds).  A row whose run ends non-finite (the explicit scheme's
+    recombination term can blow up in the corner of the input box where
+    fast trains stack dense tracks) gets NaN.  ``log``: None or a callable
+    taking a progress message."""
     import torch
     chs, trs, est, owner, weight = [], [], [], [], []
     for q, x in enumerate(X):
@@ -77,8 +80,11 @@ def solver_lnks(X, group=512, stream=None, log=None):
         idx = order[g0:g0 + group]
         res = B.it_solve_batch([chs[i] for i in idx], [trs[i] for i in idx], stream=stream)
         for i, r in zip(idx, res):
-            if r["flags"] & (B.IT_FLAG_NONFINITE | B.IT_FLAG_MAX_STEPS):
-                raise RuntimeError(f"solver run {i} did not finish cleanly (flags {r['flags']})")
+            if r["flags"] & B.IT_FLAG_MAX_STEPS:
+                raise RuntimeError(f"solver run {i} stopped at max_steps (flags {r['flags']})")
+            if r["flags"] & B.IT_FLAG_NONFINITE:
+                out[owner[i]] = math.nan
+                continue
             out[owner[i]] += weight[i] * math.log(r["ks"])
             vs += r["steps"] * chs[i]["nx"] * chs[i]["ny"] * (chs[i]["nz"] - 1)
     torch.cuda.synchronize()
@@ -136,9 +142,10 @@ class Surrogate:
 
     def answer(self, Xq, spread_tol, Xq_host=None, out=None):
         """ln k_s for every query: the ensemble mean where it is trusted, the
-        solver elsewhere.  Xq_host: the queries in float64 on the host
-        (default: read back from Xq); out: the query's output buffers (see
-        ``binding.it_mlp_query``).  Returns (lnks, fallback mask)."""
+        solver elsewhere (NaN where the solver's run ends non-finite).
+        Xq_host: the queries in float64 on the host (default: read back from
+        Xq); out: the query's output buffers (see ``binding.it_mlp_query``).
+        Returns (lnks, fallback mask)."""
         import torch
         Xd = Xq if isinstance(Xq, torch.Tensor) else torch.tensor(np.asarray(Xq), dtype=torch.float32,
                                                                  device="cuda")
@@ -155,23 +162,29 @@ class Surrogate:
 
 def solver_data(n_train=32768, n_hold=1024, seed=None, log=None):
     """Training and held-out data from the solver: a dict of the inputs,
-    ln k_s, voxel-steps and seconds of each set."""
+    ln k_s, voxel-steps and seconds of each set.  Rows the solver could not
+    compute (non-finite) are left out and counted (``*_nonfinite``)."""
     base_seed = W.SEED_BASE + 5 if seed is None else seed
     Xtr = W.surrogate_inputs(base_seed, n_train)
     ytr, vs_tr, sec_tr = solver_lnks(Xtr, log=log)
     Xh = W.surrogate_inputs(base_seed + 1, n_hold)
     yh, vs_h, sec_h = solver_lnks(Xh, log=log)
-    return dict(seed=base_seed, Xtr=Xtr, ytr=ytr, vs_tr=vs_tr, sec_tr=sec_tr, Xh=Xh, yh=yh, vs_h=vs_h, sec_h=sec_h)
+    ktr, kh = np.isfinite(ytr), np.isfinite(yh)
+    return dict(seed=base_seed, Xtr=Xtr[ktr], ytr=ytr[ktr], vs_tr=vs_tr, sec_tr=sec_tr, Xh=Xh[kh], yh=yh[kh],
+                vs_h=vs_h, sec_h=sec_h, train_nonfinite=int(np.sum(~ktr)), holdout_nonfinite=int(np.sum(~kh)))
 
 
 def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members=4, steps=600000, seed=None,
-             precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None):
+             precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None, time_extra=False):
     """The surrogate experiment: train on n_train solver runs, judge on
     n_hold held-out solver runs, time n_query queries (``data`` from
     ``solver_data`` reuses solver runs).  The figures are taken at the
-    spread tolerance ``spread_tol``; ``at_spread_tol`` repeats the accuracy
-    and throughput figures at each of ``extra_tols``.  ``log``: None or a
-    callable taking a progress message.  Returns a dict."""
+    spread tolerance ``spread_tol``, where the queries are also answered end
+    to end (the query plus the solver on the queries it flags, timed
+    together); ``at_spread_tol`` repeats the accuracy, query throughput and
+    fallback figures at each of ``extra_tols`` (the end-to-end answer is
+    timed there only with ``time_extra``).  ``log``: None or a callable
+    taking a progress message.  Returns a dict."""
     import torch
     say = log or (lambda msg: None)
     d = data if data is not None else solver_data(n_train, n_hold, seed, log=log)
@@ -194,7 +207,7 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
            torch.empty(n_query, dtype=torch.int64, device="cuda"))
     solver_rate = n_hold / sec_h  # reference k_s evaluations per second by the batched solver
 
-    def at_tol(tol):
+    def at_tol(tol, timed):
         mean, spread, fb, idx, n_fb = s.query(Xh, tol)
         m = mean.double().cpu().numpy()
         mask = fb.cpu().numpy().astype(bool)
@@ -212,18 +225,7 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
         e1.synchronize()
         q_sec = e0.elapsed_time(e1) * 1e-3 / reps
         fb_frac_q = nq_fb / n_query
-        # surrogate plus solver fallback, timed end to end: the query, its
-        # answers read back, and the batched solver on the queries it flagged
-        # (the solver's accuracy on that part)
-        secs = []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.answer(Xq, tol, Xq_host=Xq_h, out=out)
-            torch.cuda.synchronize()
-            secs.append(time.perf_counter() - t0)
-        combined_sec = float(np.median(secs))
-        return rel, acc, {
+        fig = {
             "spread_tol_ln": tol,
             "holdout_accepted_fraction": float(acc.mean()),
             "holdout_rel_err_accepted_max": float(rel[acc].max()) if acc.any() else None,
@@ -232,13 +234,28 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
             "query_seconds": q_sec, "query_rate": n_query / q_sec,
             "query_fallback_fraction": fb_frac_q, "query_fallbacks": int(nq_fb),
             "surrogate_over_solver": (n_query / q_sec) / solver_rate,
-            "with_fallback_seconds": combined_sec, "with_fallback_rate": n_query / combined_sec,
-            "surrogate_with_fallback_over_solver": (n_query / combined_sec) / solver_rate,
         }
+        if timed:
+            # surrogate plus solver fallback, timed end to end: the query, its
+            # answers read back, and the batched solver on the queries it
+            # flagged (the solver's accuracy on that part)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lnks, _ = s.answer(Xq, tol, Xq_host=Xq_h, out=out)
+            torch.cuda.synchronize()
+            combined_sec = time.perf_counter() - t0
+            say(f"surrogate: {n_query} queries with {nq_fb} solver fallbacks in {combined_sec:.2f} s")
+            fig.update({
+                "with_fallback_seconds": combined_sec, "with_fallback_rate": n_query / combined_sec,
+                "fallback_nonfinite": int(np.sum(~np.isfinite(lnks))),
+                "surrogate_with_fallback_over_solver": (n_query / combined_sec) / solver_rate,
+            })
+        return rel, acc, fig
 
-    rel, acc, main = at_tol(spread_tol)
+    rel, acc, main = at_tol(spread_tol, True)
     res = {
         "n_train": n_train, "n_holdout": n_hold, "n_query": n_query, "members": members,
+        "train_nonfinite": d.get("train_nonfinite", 0), "holdout_nonfinite": d.get("holdout_nonfinite", 0),
         "precision": "fp32" if precision == B.IT_MLP_FP32 else "bf16",
         "train_data_seconds": sec_tr, "train_data_voxel_steps": vs_tr, "train_seconds": s.train_seconds,
         "train_steps": s.train_steps, "train_batch": s.batch,
@@ -251,6 +268,6 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
         "solver_ks_rate": solver_rate,
     }
     res.update(main)
-    res["at_spread_tol"] = [at_tol(t)[2] for t in extra_tols]
+    res["at_spread_tol"] = [at_tol(t, time_extra)[2] for t in extra_tols]
     say("surrogate: queries timed")
     return res

@@ -64,7 +64,7 @@ def test_surrogate_resolutions_blend_is_continuous(orc):
     def single(x):
         return math.log(orc.solve(*W.surrogate_chamber(x), with_fields=False)["ks"])
 
-    lo = [50.0, 1e-3, 200.0, 0.030 * (1 - 1e-7), 0.1, 100.0]  # 50 planes of 6e-4 cm end at d = 0.03
+    lo = [50.0, 1e-3, 200.0, 0.030 * (1 - 1e-7), 0.1, 100.0]  # 60 planes of 5e-4 cm end at d = 0.03
     hi = [50.0, 1e-3, 200.0, 0.030 * (1 + 1e-7), 0.1, 100.0]
     assert abs(single(hi) - single(lo)) > 2e-4
     assert abs(blended(hi) - blended(lo)) < 1e-5

@@ -317,13 +317,14 @@ def surrogate_train(x):
     return int(math.ceil(T / P)) + 1, P
 
 
-def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: float = 1.5, nz=None):
+def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: float = 1.25, nz=None):
     """Chamber and track of one surrogate sample: one Gaussian track parallel
     to the field through the centre of a periodic cell of cells x cells nodes
     at spacing b / b_over_dx, gap intervals of about dz_over_dx times that
-    spacing (much coarser gap intervals let Lax-Wendroff ripples at the ion
-    column fronts drive the recombination sink unstable) or exactly nz of
-    them, the dose as uniform pre-ionisation, everything at t = 0 (one
+    spacing (coarser gap intervals let Lax-Wendroff ripples at the ion
+    column fronts drive the recombination sink unstable: at 1.5 a few
+    fast pulse trains of dense tracks, whose ripples pile up pulse after
+    pulse, end non-finite) or exactly nz of them, the dose as uniform pre-ionisation, everything at t = 0 (one
     pulse), repeated as the pulse train of surrogate_train when the rate
     makes pulses overlap."""
     let, b, V, d, dose, _rate = (float(v) for v in x)
@@ -338,7 +339,7 @@ def surrogate_chamber(x, cells: int = 24, b_over_dx: float = 2.5, dz_over_dx: fl
     return ch, tr
 
 
-def surrogate_resolutions(x, b_over_dx: float = 2.5, dz_over_dx: float = 1.5):
+def surrogate_resolutions(x, b_over_dx: float = 2.5, dz_over_dx: float = 1.25):
     """The two gap resolutions whose results define a surrogate sample's
     reference ln k_s, with their weights: nz0 = floor(nu) and nz0 + 1 around
     the real plane count nu = d / (dz_over_dx b / b_over_dx), weights
