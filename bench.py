@@ -298,7 +298,7 @@ def main():
     T_pass = max(1, round(steps_all / launches))
     kname = "step_plain" if T_pass == 1 else f"step_blocked_T{T_pass}"
     src = ["kernels_plain.hip", "stencil_plain.h", "reduce.h", "internal.h"] if T_pass == 1 else \
-        ["kernels_blocked.hip", "reduce.h", "internal.h"]
+        ["kernels_blocked.hip", "stencil_blocked.h", "stencil_plain.h", "reduce.h", "internal.h"]
     bytes_per_launch = BYTES_PER_VOXEL_STEP * nint
     achieved = bytes_per_launch / per_launch / 1e9
     effective = BYTES_PER_VOXEL_STEP * nint * steps_all / kern_sec / 1e9
