@@ -75,7 +75,7 @@ def solver_lnks(X, group=512, stream=None, log=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g0 in range(0, len(chs), group):
-        if log and g0 and g0 % (32 * group) == 0:
+        if log and g0 and g0 % (8 * group) == 0:
             log(f"solver runs: {g0} of {len(chs)}")
         idx = order[g0:g0 + group]
         res = B.it_solve_batch([chs[i] for i in idx], [trs[i] for i in idx], stream=stream)
