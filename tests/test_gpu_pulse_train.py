@@ -76,6 +76,27 @@ def test_train_single_run_matches_oracle(gpu, orc, ex):
         assert np.max(np.abs(gf - o[name])) <= RTOL * np.max(np.abs(o[name]))
 
 
+@pytest.mark.parametrize("variant", ["space_charge", "absorbing"])
+@pytest.mark.parametrize("ex", [dict(kernel=1, tile_y=8), dict(kernel=1, tile_x=32)], ids=["plain8", "plain32x16"])
+def test_train_single_run_with_options(gpu, orc, variant, ex):
+    """The train of the test above with the space-charge term, or with
+    absorbing lateral boundaries and a track next to the x = 0 edge."""
+    ch, tr = ragged(**({"space_charge": 1} if variant == "space_charge" else {"lateral_bc": 1}))
+    if variant == "absorbing":
+        tr = tr.copy()
+        tr[0, 2] = 3e-4
+    ch = train(ch, 5, 7.3 * orc.dt(ch, tr))
+    g = gpu.it_solve(ch, tr, exec=ex, trace=True)
+    o = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    compare(g, o)
+    assert o["flags"] == 0 and o["pulses"] == 5
+    assert (o["n_space_charge_pos"] != 0.0) == (variant == "space_charge")
+    assert (o["n_escaped_pos"] > 0.0) == (variant == "absorbing")
+    for k in ("n_space_charge_pos", "n_space_charge_neg"):
+        assert abs(g[k] - o[k]) <= RTOL * o["n_released"], k
+    assert np.max(np.abs(g["trace"] - o["trace"])) <= RTOL * o["n_released"]
+
+
 @pytest.mark.parametrize("mult", [0.6, 1.0, 1.7, 2.4], ids=["m1", "m1exact", "m2", "m3"])
 def test_short_periods_single_and_batch(gpu, orc, mult):
     """Periods of one to three steps: a pulse at every step (the batch's
