@@ -73,7 +73,9 @@ struct RunState {
   int32_t pulse_add[2];
   int32_t pulses_counted;   // pulses whose release is recorded
   int32_t pulses_flagged;   // pulses whose pulse_add flag has been set
-  int32_t pulse_pad;
+  // batches: the tiles whose partials the next recording block reduces (the
+  // previous pass's tiling, which a rebuilt table may have changed since)
+  int32_t rec_ntiles;
   double pulse_q[2];
 };
 

@@ -41,8 +41,13 @@ template <int NT>
 __device__ void record_previous(const BatchInstance& bi, int parity, int T) {
   const StepParams& p = bi.sp[parity ^ 1];
   if (p.state->done) return;
+  // the previous pass's tile count, which its own recording block stored
+  // (the host may have re-tiled the running instances since)
+  __shared__ int nprev;
+  if (threadIdx.x == 0 && threadIdx.y == 0) nprev = p.state->rec_ntiles;
+  __syncthreads();
   __shared__ double totals[kAcc * kMaxT];
-  reduce_partials<NT>(p.partials, bi.ntiles, kAcc * T, kAcc * T, totals);
+  reduce_partials<NT>(p.partials, nprev, kAcc * T, kAcc * T, totals);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     RunState* st = p.state;
     const int64_t step = st->steps;
@@ -68,6 +73,7 @@ __device__ void record_previous(const BatchInstance& bi, int parity, int T) {
       st->done = 1;
       st->by_limit = 1;
     }
+    st->rec_ntiles = bi.ntiles;  // this pass's tiles, for the next recording block
     if (train) {
       // (a pulse at or past the run's last step is never deposited)
       const int kf = st->pulses_flagged;

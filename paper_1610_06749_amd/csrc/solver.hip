@@ -753,7 +753,7 @@ struct InstLayout {
   size_t off_field[4], field_elems;
   size_t off_partials, off_counter, off_tracks;
   size_t off_pulse[2];  // the first pulse's densities (pulse trains only)
-  int ntiles;       // stepping tiles (plain kernel)
+  int slots;        // partial slots per pass: the most stepping tiles the run can use
 };
 
 struct BatchLayout {
@@ -817,16 +817,46 @@ int batch_blocked_z_chunk(const it_exec* exec) {
   return z > 0 ? z : 24;
 }
 
-// Stepping tiles of one chamber of a batch (T > 1: blocked tiles, R rows per
-// thread).
-Tiling batch_tiling(const it_chamber& c, int T, int R, int rows, const it_exec* exec, int tile_x) {
-  if (T == 1) return step_tiling(c.nx, c.ny, c.nz, rows, batch_z_chunk(exec), tile_x);
+// Blocked tiles of one chamber of a batch in chunks of zc planes (T steps,
+// R rows per thread).
+Tiling batch_blocked_tiling(const it_chamber& c, int T, int R, int zc) {
   Tiling t;
-  blocked_tiling_zc(c.nx, c.ny, c.nz, T, R, batch_blocked_z_chunk(exec), &t.tiles_x, &t.tiles_y, &t.ntiles, &t.zc,
-                    &t.zchunks);
+  blocked_tiling_zc(c.nx, c.ny, c.nz, T, R, zc, &t.tiles_x, &t.tiles_y, &t.ntiles, &t.zc, &t.zchunks);
   t.per_xcd = (t.ntiles + 7) / 8;
   t.grid = 8 * t.per_xcd;
   return t;
+}
+
+// Stepping tiles of one chamber of a batch (T > 1: blocked tiles, R rows per
+// thread, in chunks of zc planes, or of the caller's or default chunk when
+// zc is 0).
+Tiling batch_tiling(const it_chamber& c, int T, int R, int rows, const it_exec* exec, int tile_x, int zc = 0) {
+  if (T == 1) return step_tiling(c.nx, c.ny, c.nz, rows, batch_z_chunk(exec), tile_x);
+  return batch_blocked_tiling(c, T, R, zc > 0 ? zc : batch_blocked_z_chunk(exec));
+}
+
+// Chunk length of the blocked batch tiles for the running instances `set`:
+// the caller's (or default) chunk z0 while the batch fills the machine, a
+// shorter one once it leaves CUs idle.  One blocked block occupies a CU, so
+// a launch takes about ceil(blocks / CUs) rounds of one block's march
+// (its chunk plus T planes of halo at each end); the chunk minimises that,
+// between 4T planes and z0.  On MI355X's 256 CUs the 96-chamber sweep's
+// tail, where a few chambers run, otherwise idles most of the machine.
+int batch_blocked_retile_z(const it_chamber* ch, const int* set, int n, int T, int R, int z0) {
+  constexpr long kCUs = 256;
+  const int zmin = std::min(z0, 4 * T);
+  int best_z = z0;
+  double best = 1e300;
+  for (int z = z0; z >= zmin; --z) {
+    long blocks = 0;
+    for (int i = 0; i < n; ++i) blocks += batch_blocked_tiling(ch[set[i]], T, R, z).ntiles;
+    const double cost = (double)((blocks + kCUs - 1) / kCUs) * (z + 2.0 * T);
+    if (cost < best - 1e-9) {
+      best = cost;
+      best_z = z;
+    }
+  }
+  return best_z;
 }
 
 BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int ninst, int rows, const it_exec* exec,
@@ -842,9 +872,12 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
       L.off_field[f] = off;
       off = align_up(off + L.field_elems * sizeof(double));
     }
-    const Tiling ts = batch_tiling(c, T, R, rows, exec, tile_x);
+    // partial slots for the most tiles any chunk length of the run can give
+    // (blocked tiles are re-chunked down to 4T planes as instances stop)
+    const int zmin = T > 1 ? std::min(batch_blocked_z_chunk(exec), 4 * T) : 0;
+    const Tiling ts = batch_tiling(c, T, R, rows, exec, tile_x, zmin);
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
-    L.ntiles = ts.ntiles;
+    L.slots = ts.ntiles;
     L.off_partials = off;  // two halves of step partials (alternate passes); the deposit uses the start
     off = align_up(off + std::max((size_t)2 * ts.ntiles * kAcc * T, (size_t)td.grid * 5) * sizeof(double));
     L.off_counter = off;
@@ -1276,6 +1309,13 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   std::vector<double> dts(ninst);
   std::vector<int64_t> period_steps(ninst);
   std::vector<BatchInstance> table(ninst);
+  std::vector<int> active(ninst);
+  for (int q = 0; q < ninst; ++q) active[q] = q;
+  // blocked tiles: chunks of the caller's (or default) length while the
+  // batch fills the machine, shorter ones when it does not (re-chosen for
+  // the running instances whenever the table is rebuilt)
+  const int z0 = T > 1 ? batch_blocked_z_chunk(exec) : 0;
+  const int zc_run = T > 1 ? batch_blocked_retile_z(ch, active.data(), ninst, T, R, z0) : 0;
   int total_tiles = 0;
   int64_t max_steps_all = 0;
   for (int q = 0; q < ninst; ++q) {
@@ -1303,7 +1343,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
 
     const Coef cp = species_coef(c, dts[q], 0), cn = species_coef(c, dts[q], 1);
     const double dz = c->gap / c->nz, dV = c->dx * c->dy * dz;
-    const Tiling ts = batch_tiling(*c, T, R, rows, exec, tile_x);
+    const Tiling ts = batch_tiling(*c, T, R, rows, exec, tile_x, zc_run);
     const Tiling td = deposit_tiling(c->nx, c->ny, c->nz);
     BatchInstance& bi = table[q];
     for (int par = 0; par < 2; ++par) {
@@ -1332,7 +1372,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
       sp.stop_tol = c->stop_tol;
       sp.step0 = 0;
       sp.min_stop_step = train ? INT64_MAX : 0;  // a pulse train ends with its last period
-      sp.partials = (double*)(ws + L.off_partials) + (size_t)par * L.ntiles * kAcc * T;
+      sp.partials = (double*)(ws + L.off_partials) + (size_t)par * L.slots * kAcc * T;
       sp.counter = (unsigned*)(ws + L.off_counter);
       sp.state = states + q;
       sp.trace = nullptr;
@@ -1348,6 +1388,7 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     max_steps_all = std::max(max_steps_all, bi.max_steps);
     // the pulse: uniform pre-ionisation and the tracks, deposited before step 0
     RunState init = initial_run_state();
+    init.rec_ntiles = ts.ntiles;  // the priming pass's tiles
     if (train) {
       // pulse 0 is deposited and booked here; the passes before steps 1 and
       // 2 (the first two, whose flags no recording block sets) take the
@@ -1390,8 +1431,6 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   HostSlots hs;
   host_slots(exec, ninst, hs);
   RunState* host = hs.p;
-  std::vector<int> active(ninst);
-  for (int q = 0; q < ninst; ++q) active[q] = q;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec_graph = nullptr;
   auto release_graph = [&]() {
@@ -1400,7 +1439,29 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     exec_graph = nullptr;
     graph = nullptr;
   };
+  // Blocked tiles of the running instances in the chunk length that suits
+  // them (a pass computed with the previous tiling is still reduced over its
+  // own tiles: each recording block leaves its pass's tile count in the run
+  // state for the next).
+  auto retile = [&]() {
+    if (T == 1) return;
+    const int z = batch_blocked_retile_z(ch, active.data(), (int)active.size(), T, R, z0);
+    for (int q : active) {
+      const Tiling ts = batch_blocked_tiling(ch[q], T, R, z);
+      for (int par = 0; par < 2; ++par) {
+        StepParams& sp = table[q].sp[par];
+        sp.tiles_x = ts.tiles_x;
+        sp.tiles_y = ts.tiles_y;
+        sp.zchunks = ts.zchunks;
+        sp.zc = ts.zc;
+        sp.ntiles = ts.ntiles;
+        sp.per_xcd = ts.per_xcd;
+      }
+      table[q].ntiles = ts.ntiles;
+    }
+  };
   auto build = [&](int parity0) -> int {
+    retile();
     std::vector<BatchInstance> t;
     t.reserve(active.size());
     int tiles = 0;

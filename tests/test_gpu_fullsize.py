@@ -132,14 +132,22 @@ def test_pulsed_beam_full_run(gpu):
     check_conservation(g["trace"], gd["result"]["n_released"])
 
 
-def test_batched_sweep_against_stored(gpu):
+# the library's default (blocked passes of three steps, 24-plane chunks) and
+# the other executions the autotuner can pick for the timed sweep
+SWEEP_EXECS = [None, dict(kernel=2, steps_per_pass=3, z_chunk=48), dict(kernel=2, steps_per_pass=2, z_chunk=16),
+               dict(kernel=1)]
+SWEEP_IDS = ["default", "blocked3z48", "blocked2z16", "plain"]
+
+
+@pytest.mark.parametrize("ex", SWEEP_EXECS, ids=SWEEP_IDS)
+def test_batched_sweep_against_stored(gpu, ex):
     """The 96-chamber sweep in one batched run; every instance whose oracle
     result is stored is compared."""
     files = sorted(glob.glob(os.path.join(GOLDEN, "sweep_*.json")))
     if not files:
         pytest.skip("no sweep instances generated")
     chs, trs = W.batched_sweep()
-    res = gpu.it_solve_batch(chs, trs)
+    res = gpu.it_solve_batch(chs, trs, exec=ex)
     for fn in files:
         gd = json.load(open(fn))
         check_result(res[gd["instance"]], gd["result"])
