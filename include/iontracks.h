@@ -61,7 +61,7 @@ extern "C" {
 #define IT_ENODT -2       /* neither drift nor diffusion bounds the time step (E = 0 and D = 0) */
 #define IT_EWORKSPACE -3  /* workspace NULL or smaller than it_workspace_size() */
 #define IT_EHIP -4        /* a HIP runtime call failed (no device, launch failure, ...) */
-#define IT_ENOTSUP -5     /* option not supported by this build */
+#define IT_ENOTSUP -5     /* an option or a combination of options that is not supported */
 
 /* ---- result flags ---- */
 #define IT_FLAG_MAX_STEPS 1  /* stopped by max_steps, not by the collection criterion */

@@ -997,7 +997,7 @@ const char* it_strerror(int code) {
     case IT_ENODT: return "no stable time step: neither drift nor diffusion bounds dt";
     case IT_EWORKSPACE: return "workspace missing or smaller than it_workspace_size()";
     case IT_EHIP: return "HIP runtime error";
-    case IT_ENOTSUP: return "option not supported by this build";
+    case IT_ENOTSUP: return "option or combination of options not supported";
     default: return "unknown status code";
   }
 }

@@ -1,4 +1,4 @@
-"""Learned surrogate for ln k_s with the solver as its judge and fallback.
+"""Learned surrogate for ln k_s with the solver as its reference and fallback.
 
 Pipeline (every numerical step runs in the library's kernels):
 
@@ -176,7 +176,7 @@ def solver_data(n_train=32768, n_hold=1024, seed=None, log=None):
 
 def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members=4, steps=600000, seed=None,
              precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None, time_extra=False):
-    """The surrogate experiment: train on n_train solver runs, judge on
+    """The surrogate experiment: train on n_train solver runs, check on
     n_hold held-out solver runs, time n_query queries (``data`` from
     ``solver_data`` reuses solver runs).  The figures are taken at the
     spread tolerance ``spread_tol``, where the queries are also answered end
