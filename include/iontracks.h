@@ -328,9 +328,11 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
  * track_offsets[q+1]) (host); every track must be due at step 0 (one pulse
  * per instance, or a train of them, IT_ENOTSUP otherwise).  An instance
  * with a pulse train keeps its first pulse's densities in the workspace;
- * the pass that computes the step before each later pulse adds them to its
- * outputs.  A batch with a pulse train steps one step per pass
- * (steps_per_pass > 1 with the blocked kernel: IT_ENOTSUP).  Each pass is one launch over the
+ * the pass in which each later pulse falls due adds them to the outputs of
+ * the step before it.  A pass of T steps takes at most one pulse: with a
+ * train whose period is shorter than T steps the library's choice is one
+ * step per pass (a request for blocked passes then returns IT_ENOTSUP;
+ * it_workspace_size_batch covers both).  Each pass is one launch over the
  * tiles of all running instances, plus one block per instance that records
  * the instance's previous step; the library
  * captures exec->check_every passes (default 32, rounded up to even) in a

@@ -30,13 +30,17 @@ __device__ inline int find_instance(const BatchInstance* inst, int ninst, int L)
 // the buffer of the other parity), up to the instance's step limit: a pass
 // may run past it, and those steps are not recorded.
 //
-// Pulse trains (one step per pass): pass p computes step p, and the pass
-// before a pulse step adds the pulse to its outputs.  The recording block of
-// pass p (recording step r = p - 1) first books the release of a pulse
-// deposited before step r (the first pulse's, kept when step 0 is
-// recorded), then sets the flag of pass p + 1, whose outputs take a pulse
-// due at step r + 3.  The flags alternate by pass parity, so the tile
-// blocks of pass p read a flag that pass p - 1 wrote.
+// Pulse trains (a period of at least T steps, so at most one pulse in a
+// pass): a pass computes steps c0 .. c0 + T - 1, and the pass in which a
+// pulse falls due adds it to the outputs of the level that computes the
+// step before it (pulse_add = j for a pulse at step c0 + j, j = 1..T; one
+// at c0 + T is thus added by the pass before the one it precedes).  The
+// recording block of a pass, which records the previous pass's steps
+// r0 .. r0 + T - 1, books the release of a pulse deposited before one of
+// them with that step (the first pulse's release, from the deposit, is
+// kept when step 0 is recorded), then sets the flag of the next pass, which
+// computes steps r0 + 2T .. r0 + 3T - 1.  The flags alternate by pass
+// parity, so the tile blocks of a pass read a flag the previous pass wrote.
 template <int NT>
 __device__ void record_previous(const BatchInstance& bi, int parity, int T) {
   const StepParams& p = bi.sp[parity ^ 1];
@@ -51,35 +55,36 @@ __device__ void record_previous(const BatchInstance& bi, int parity, int T) {
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     RunState* st = p.state;
     const int64_t step = st->steps;
+    const int Te = (int)min((int64_t)T, bi.max_steps - step);
     const bool train = bi.npulses >= 2;
+    int inject = -1;
     if (train) {
       if (step == 0) {
         st->pulse_q[0] = st->released;
         st->pulse_q[1] = st->released_neg;
       }
       const int k = st->pulses_counted;
-      if (k < bi.npulses && (int64_t)k * bi.period_steps == step) {
-        st->released += st->pulse_q[0];
-        st->released_pending += st->pulse_q[0];
-        st->released_neg += st->pulse_q[1];
-        st->released_pending_neg += st->pulse_q[1];
-        st->released_q += st->pulse_q[1];  // negative charge: the ions (no free electrons in a train)
+      const int64_t s_k = (int64_t)k * bi.period_steps;
+      if (k < bi.npulses && s_k >= step && s_k < step + Te) {
+        inject = (int)(s_k - step);
         st->pulses_counted = k + 1;
       }
     }
-    const int Te = (int)min((int64_t)T, bi.max_steps - step);
-    finalize_steps(st, p.trace, totals, Te, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step);
+    finalize_steps(st, p.trace, totals, Te, step, p.cp, p.cn, p.dV, p.stop_tol, p.min_stop_step, inject,
+                   train ? st->pulse_q[0] : 0.0, train ? st->pulse_q[1] : 0.0);
     if (!st->done && st->steps >= bi.max_steps) {
       st->done = 1;
       st->by_limit = 1;
     }
     st->rec_ntiles = bi.ntiles;  // this pass's tiles, for the next recording block
     if (train) {
-      // (a pulse at or past the run's last step is never deposited)
+      // the next pass computes steps c1 .. c1 + T - 1; a pulse at or past
+      // the run's last step is never deposited
+      const int64_t c1 = step + 2 * T;
       const int kf = st->pulses_flagged;
       const int64_t s_due = (int64_t)kf * bi.period_steps;
-      const bool due = kf < bi.npulses && s_due == step + 3 && s_due < bi.max_steps;
-      st->pulse_add[parity ^ 1] = due ? 1 : 0;
+      const bool due = kf < bi.npulses && s_due > c1 && s_due <= c1 + T && s_due < bi.max_steps;
+      st->pulse_add[parity ^ 1] = due ? (int)(s_due - c1) : 0;
       if (due) st->pulses_flagged = kf + 1;
     }
   }
@@ -117,8 +122,10 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
 
 // T steps per launch: the temporally blocked tile pass of stencil_blocked.h
 // on each running instance's tiles (64 x 8R extended tiles, chunks of
-// planes), one recording block per instance as above.
-template <int T, int R, bool SC>
+// planes), one recording block per instance as above.  PU: some instance
+// has a pulse train (its tile blocks add the pulse to the level its flag
+// for this pass names).
+template <int T, int R, bool SC, bool PU>
 __global__ __launch_bounds__(kBNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void batch_blocked_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                           int parity) {
@@ -139,7 +146,14 @@ void batch_blocked_kernel(const BatchInstance* __restrict__ inst, int ninst, int
   const int l = L - inst[q].tile_begin;
   TileCoord t = tile_of(l, p.tiles_x, p.tiles_y);
   t.valid = true;
-  blocked_tile_pass<T, R, SC>(p, t, p.partials + (size_t)l * kAcc * T);
+  if (PU) {
+    const BatchInstance& bi = inst[q];
+    // written by the previous pass's recording block; one value for the block
+    const int j = bi.npulses >= 2 ? __builtin_amdgcn_readfirstlane(p.state->pulse_add[parity]) : 0;
+    blocked_tile_pass<T, R, SC, true>(p, t, p.partials + (size_t)l * kAcc * T, j, bi.pulse_pos, bi.pulse_neg);
+  } else {
+    blocked_tile_pass<T, R, SC>(p, t, p.partials + (size_t)l * kAcc * T);
+  }
 }
 
 }  // namespace
@@ -163,27 +177,31 @@ const void* batch_kernel_terms(bool sc, bool ab, bool pu) {
 }
 
 template <int T, int R>
-const void* batch_blocked_ptr(bool sc) {
-  return sc ? reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true>)
-            : reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false>);
+const void* batch_blocked_ptr(bool sc, bool pu) {
+  switch ((sc ? 2 : 0) + (pu ? 1 : 0)) {
+    case 0: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false, false>);
+    case 1: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false, true>);
+    case 2: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true, false>);
+    default: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true, true>);
+  }
 }
 
 // The blocked batch kernel for T steps and R rows per thread (null if not
 // offered): the depths and row counts the single-chamber kernel offers.
-const void* batch_blocked(int T, int R, bool sc) {
+const void* batch_blocked(int T, int R, bool sc, bool pu) {
   switch (T * 16 + R) {
-    case 2 * 16 + 3: return batch_blocked_ptr<2, 3>(sc);
-    case 2 * 16 + 4: return batch_blocked_ptr<2, 4>(sc);
-    case 2 * 16 + 5: return batch_blocked_ptr<2, 5>(sc);
-    case 2 * 16 + 6: return batch_blocked_ptr<2, 6>(sc);
-    case 3 * 16 + 3: return batch_blocked_ptr<3, 3>(sc);
-    case 3 * 16 + 4: return batch_blocked_ptr<3, 4>(sc);
-    case 3 * 16 + 5: return batch_blocked_ptr<3, 5>(sc);
-    case 3 * 16 + 6: return batch_blocked_ptr<3, 6>(sc);
-    case 4 * 16 + 3: return batch_blocked_ptr<4, 3>(sc);
-    case 4 * 16 + 4: return batch_blocked_ptr<4, 4>(sc);
-    case 4 * 16 + 5: return batch_blocked_ptr<4, 5>(sc);
-    case 4 * 16 + 6: return batch_blocked_ptr<4, 6>(sc);
+    case 2 * 16 + 3: return batch_blocked_ptr<2, 3>(sc, pu);
+    case 2 * 16 + 4: return batch_blocked_ptr<2, 4>(sc, pu);
+    case 2 * 16 + 5: return batch_blocked_ptr<2, 5>(sc, pu);
+    case 2 * 16 + 6: return batch_blocked_ptr<2, 6>(sc, pu);
+    case 3 * 16 + 3: return batch_blocked_ptr<3, 3>(sc, pu);
+    case 3 * 16 + 4: return batch_blocked_ptr<3, 4>(sc, pu);
+    case 3 * 16 + 5: return batch_blocked_ptr<3, 5>(sc, pu);
+    case 3 * 16 + 6: return batch_blocked_ptr<3, 6>(sc, pu);
+    case 4 * 16 + 3: return batch_blocked_ptr<4, 3>(sc, pu);
+    case 4 * 16 + 4: return batch_blocked_ptr<4, 4>(sc, pu);
+    case 4 * 16 + 5: return batch_blocked_ptr<4, 5>(sc, pu);
+    case 4 * 16 + 6: return batch_blocked_ptr<4, 6>(sc, pu);
     default: return nullptr;
   }
 }
@@ -210,8 +228,8 @@ hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNod
   const BatchInstance* inst = (const BatchInstance*)table;
   int per_xcd = (total_tiles + 7) / 8;
   int sy = 8;
-  if (T > 1 && (ab || pu)) return hipErrorInvalidValue;  // the blocked pass: periodic, single pulses
-  const void* fn = T > 1 ? batch_blocked(T, R, sc) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
+  if (T > 1 && ab) return hipErrorInvalidValue;  // the blocked pass is periodic only
+  const void* fn = T > 1 ? batch_blocked(T, R, sc, pu) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
   if (!fn) return hipErrorInvalidValue;
   if (T > 1) sy = kBW;  // blocks of 8 waves
   // the node copies the argument values when it is added
@@ -232,8 +250,8 @@ hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int 
   int per_xcd = (total_tiles + 7) / 8;
   const int nr = record_prev ? ninst : 0;
   int sy = 8;
-  if (T > 1 && (ab || pu)) return hipErrorInvalidValue;  // the blocked pass: periodic, single pulses
-  const void* fn = T > 1 ? batch_blocked(T, R, sc) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
+  if (T > 1 && ab) return hipErrorInvalidValue;  // the blocked pass is periodic only
+  const void* fn = T > 1 ? batch_blocked(T, R, sc, pu) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
   if (!fn) return hipErrorInvalidValue;
   if (T > 1) sy = kBW;
   void* args[] = {(void*)&inst, (void*)&ninst, (void*)&total_tiles, (void*)&per_xcd, (void*)&parity};

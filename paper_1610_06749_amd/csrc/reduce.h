@@ -108,11 +108,14 @@ __device__ inline void reduce_partials(const double* partials, int nblocks, int 
 // (tot[s * kAcc + q]) into trace records and updates the run state and the
 // stop decision (trace may be NULL: no per-step records kept).  Works on
 // register copies of the fields it updates (a whole-struct copy would pass
-// the untouched fields through private memory).
+// the untouched fields through private memory).  inject_at >= 0: a pulse of
+// a batched pulse train released inj_pos and inj_neg ions before the step
+// step0 + inject_at, which are booked with that step.
 __device__ inline void finalize_steps(RunState* gst, double* trace, const double* tot, int T,
                                       int64_t step0, const Coef& cp, const Coef& cn, double dV,
-                                      double stop_tol, int64_t min_stop_step) {
-  const double released = gst->released, released_neg = gst->released_neg;
+                                      double stop_tol, int64_t min_stop_step, int inject_at = -1,
+                                      double inj_pos = 0.0, double inj_neg = 0.0) {
+  double released = gst->released, released_neg = gst->released_neg;
   double pending = gst->released_pending, pending_neg = gst->released_pending_neg;
   double sums[5], last[4], screened[2], escaped[2];
 #pragma unroll
@@ -127,9 +130,17 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
   int64_t steps = gst->steps;
   int done = gst->done, flags = gst->flags;
   const int64_t period_step = gst->period_step;
+  bool injected = false;
   for (int s = 0; s < T && !done; ++s) {
     const int64_t l = step0 + s;
     const double* a = tot + s * kAcc;
+    if (s == inject_at) {
+      released += inj_pos;
+      released_neg += inj_neg;
+      pending += inj_pos;
+      pending_neg += inj_neg;
+      injected = true;
+    }
     double rec[IT_TRACE_COLS];
     rec[0] = a[0] * dV;
     rec[1] = cp.azp * a[1] * dV;
@@ -179,6 +190,11 @@ __device__ inline void finalize_steps(RunState* gst, double* trace, const double
   }
   gst->released_pending = pending;
   gst->released_pending_neg = pending_neg;
+  if (injected) {
+    gst->released = released;
+    gst->released_neg = released_neg;
+    gst->released_q += inj_neg;  // negative charge: the ions (no free electrons in a train)
+  }
 #pragma unroll
   for (int q = 0; q < 5; ++q) gst->sums[q] = sums[q];
 #pragma unroll

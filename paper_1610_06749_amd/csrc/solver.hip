@@ -789,7 +789,7 @@ int batch_steps(const it_chamber* ch, int ninst, const it_exec* ex) {
   const int T = requested_steps(ex);
   if (T > 0) return T;
   for (int q = 0; q < ninst; ++q)
-    if (ch[q].lateral_bc || ch[q].n_pulses >= 2) return 1;
+    if (ch[q].lateral_bc) return 1;
   if (ex && (ex->tile_x || ex->tile_y || ex->z_chunk)) return 1;
   return kBlockedT;
 }
@@ -803,7 +803,7 @@ int check_batch_steps(const it_chamber* ch, int ninst, const it_exec* ex, int T)
   if (!blocked_supported(T, ex ? ex->tile_y : 0)) return ex && ex->tile_y ? IT_EINVAL : IT_ENOTSUP;
   if (ex && ex->tile_x) return IT_EINVAL;
   for (int q = 0; q < ninst; ++q)
-    if (ch[q].lateral_bc || ch[q].n_pulses >= 2) return IT_ENOTSUP;
+    if (ch[q].lateral_bc) return IT_ENOTSUP;
   return IT_OK;
 }
 
@@ -845,11 +845,23 @@ Tiling batch_tiling(const it_chamber& c, int T, int R, int rows, const it_exec* 
 int batch_blocked_retile_z(const it_chamber* ch, const int* set, int n, int T, int R, int z0) {
   constexpr long kCUs = 256;
   const int zmin = std::min(z0, 4 * T);
+  // tile columns and interior planes of each instance (the chunk count is
+  // ceil(planes / min(z, planes)), as blocked_tiling_zc takes it)
+  std::vector<long> cols(n);
+  std::vector<int> planes(n);
+  for (int i = 0; i < n; ++i) {
+    const Tiling t = batch_blocked_tiling(ch[set[i]], T, R, 1);
+    cols[i] = (long)t.tiles_x * t.tiles_y;
+    planes[i] = ch[set[i]].nz - 1;
+  }
   int best_z = z0;
   double best = 1e300;
   for (int z = z0; z >= zmin; --z) {
     long blocks = 0;
-    for (int i = 0; i < n; ++i) blocks += batch_blocked_tiling(ch[set[i]], T, R, z).ntiles;
+    for (int i = 0; i < n; ++i) {
+      const int zz = std::min(z, planes[i]);
+      blocks += cols[i] * ((planes[i] + zz - 1) / zz);
+    }
     const double cost = (double)((blocks + kCUs - 1) / kCUs) * (z + 2.0 * T);
     if (cost < best - 1e-9) {
       best = cost;
@@ -1271,7 +1283,15 @@ int it_workspace_size_batch(const it_chamber* ch, const int64_t* track_offsets, 
   if (rc) return rc;
   const int rows = batch_rows(ch, ninst, exec);
   const int R = T > 1 ? blocked_rows(T, exec ? exec->tile_y : 0) : 0;
-  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, exec, exec_tile_x(exec, ch, ninst, false), T, R).total;
+  const int tile_x = exec_tile_x(exec, ch, ninst, false);
+  *bytes = make_batch_layout(ch, track_offsets, ninst, rows, exec, tile_x, T, R).total;
+  // with a pulse train the library's choice falls back to one step per pass
+  // when a period is shorter than T steps (known only once the time steps
+  // are): room for both
+  bool train = false;
+  for (int q = 0; q < ninst; ++q) train = train || ch[q].n_pulses >= 2;
+  if (train && T > 1 && requested_steps(exec) == 0)
+    *bytes = std::max(*bytes, make_batch_layout(ch, track_offsets, ninst, rows, exec, tile_x, 1, 0).total);
   return IT_OK;
 }
 
@@ -1295,9 +1315,28 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   passes_per_graph += passes_per_graph & 1;  // even: the field parity repeats
   if (!z_chunk_ok(exec) || !tile_shape_ok(exec)) return IT_EINVAL;
   if (exec && exec->tile_x == 128) return IT_ENOTSUP;  // the batched kernel has no tiles of column pairs
-  const int T = batch_steps(ch, ninst, exec);  // steps per pass
+  int T = batch_steps(ch, ninst, exec);  // steps per pass
   rc = check_batch_steps(ch, ninst, exec, T);
   if (rc) return rc;
+  // every instance's time step (and a train's steps per period) before any
+  // device work: a pass of T steps takes at most one pulse, so a train with
+  // a shorter period needs one step per pass
+  std::vector<double> dts(ninst);
+  std::vector<int64_t> period_steps(ninst);
+  bool short_period = false;
+  for (int q = 0; q < ninst; ++q) {
+    const int64_t n = track_offsets[q + 1] - track_offsets[q];
+    const it_track* tq = n ? tracks + track_offsets[q] : nullptr;
+    rc = compute_dt(&ch[q], tq, n, &dts[q], &period_steps[q]);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n; ++k)
+      if (deposit_step(tq[k].t_s, dts[q]) != 0) return IT_ENOTSUP;  // one pulse (or a train of it) per instance
+    short_period = short_period || (ch[q].n_pulses >= 2 && period_steps[q] < T);
+  }
+  if (short_period) {
+    if (requested_steps(exec) > 0) return IT_ENOTSUP;
+    T = 1;
+  }
   const int R = T > 1 ? blocked_rows(T, exec ? exec->tile_y : 0) : 0;
   const int tile_x = exec_tile_x(exec, ch, ninst, false);
   const BatchLayout B = make_batch_layout(ch, track_offsets, ninst, rows, exec, tile_x, T, R);
@@ -1306,8 +1345,6 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
   char* ws = (char*)d_workspace;
   RunState* states = (RunState*)(ws + B.off_states);
 
-  std::vector<double> dts(ninst);
-  std::vector<int64_t> period_steps(ninst);
   std::vector<BatchInstance> table(ninst);
   std::vector<int> active(ninst);
   for (int q = 0; q < ninst; ++q) active[q] = q;
@@ -1322,12 +1359,8 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     const it_chamber* c = &ch[q];
     const int64_t n = track_offsets[q + 1] - track_offsets[q];
     const it_track* tq = n ? tracks + track_offsets[q] : nullptr;
-    rc = compute_dt(c, tq, n, &dts[q], &period_steps[q]);
-    if (rc) return rc;
     const bool train = c->n_pulses >= 2;
     const int64_t m = period_steps[q];
-    for (int64_t k = 0; k < n; ++k)
-      if (deposit_step(tq[k].t_s, dts[q]) != 0) return IT_ENOTSUP;  // one pulse per instance
     const InstLayout& L = B.inst[q];
     for (int f = 0; f < 4; ++f)
       HIP_TRY(hipMemsetAsync(ws + L.off_field[f], 0, L.field_elems * sizeof(double), stream));
@@ -1390,17 +1423,20 @@ int it_solve_batch(const it_chamber* ch, const int64_t* track_offsets, const it_
     RunState init = initial_run_state();
     init.rec_ntiles = ts.ntiles;  // the priming pass's tiles
     if (train) {
-      // pulse 0 is deposited and booked here; the passes before steps 1 and
-      // 2 (the first two, whose flags no recording block sets) take the
-      // pulses due at those steps
+      // pulse 0 is deposited and booked here; the first two passes (steps
+      // 0 .. T-1 and T .. 2T-1), whose flags no recording block sets, take
+      // the pulses due at steps 1 .. T and T+1 .. 2T (a pass adds a pulse
+      // at step c0 + j to the outputs of its level j)
       init.period_step = (c->n_pulses - 1) * m;
       init.pulses_counted = 1;
       init.pulses_flagged = 1;
-      for (int64_t s = 1; s <= 2; ++s)
-        if (s % m == 0 && s / m < c->n_pulses && s < bi.max_steps) {
-          init.pulse_add[s - 1] = 1;
+      for (int pass = 0; pass < 2; ++pass) {
+        const int64_t c0 = (int64_t)pass * T, s = (int64_t)init.pulses_flagged * m;
+        if (init.pulses_flagged < c->n_pulses && s > c0 && s <= c0 + T && s < bi.max_steps) {
+          init.pulse_add[pass] = (int)(s - c0);
           ++init.pulses_flagged;
         }
+      }
     }
     HIP_TRY(hipMemcpyAsync(states + q, &init, sizeof(init), hipMemcpyHostToDevice, stream));
     if (n || c->uniform_n0 > 0.0) {

@@ -57,8 +57,15 @@ __device__ inline double lane_from_right(double v) {  // value of lane + 1
 // One pass of the block over tile tc (tc.valid false: an idle block, which
 // still stores zero partials); the block's T records of kAcc partial
 // tallies go to partial_out.  The caller has checked the run's stop flag.
-template <int T, int R, bool SC>
-__device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const TileCoord tc, double* partial_out) {
+// PU: with add_j in 1..T (block-uniform), a pulse of a pulse train falls due
+// after the step of level add_j: the densities add_p and add_n join that
+// level's outputs once its tallies are taken (on every node the tile
+// computes, so the later levels step from them), and beta times the largest
+// owned output enters the run's max_beta_n, as a deposit does.
+template <int T, int R, bool SC, bool PU = false>
+__device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const TileCoord tc, double* partial_out,
+                                                  int add_j = 0, const double* add_p = nullptr,
+                                                  const double* add_n = nullptr) {
   constexpr int EY = kBW * R;             // rows of the extended tile
   constexpr int OX = kBX - 2 * T, OY = EY - 2 * T;
   constexpr int NA = SC ? 7 : 5;          // tallies kept per level
@@ -90,6 +97,7 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
   const size_t plane = (size_t)nx * ny;
   const Coef cp = p.cp, cn = p.cn;
   const double beta = p.beta, gsp = p.gsp, gsn = p.gsn;
+  double add_max = 0.0;  // largest owned output density after a pulse is added
 
   if (lane < 4)
 #pragma unroll
@@ -209,6 +217,16 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
           }
         }
       }
+      if (PU && t == add_j && interior) {  // block-uniform: the pulse due after this level's step
+        const gchar* pp = uniform_ptr(add_p + (size_t)q * plane);
+        const gchar* pn = uniform_ptr(add_n + (size_t)q * plane);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          np[r] += *(const gdouble*)(pp + off[r]);
+          nn[r] += *(const gdouble*)(pn + off[r]);
+          if (counted && own_y[r] && own_x) add_max = fmax(add_max, fmax(np[r], nn[r]));
+        }
+      }
       // level t-1 moves on: plane K-t becomes its older plane, K-t+1 its current one
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -273,6 +291,20 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
     a[t * kAcc + 12] = 0.0;
   }
   block_sum_store<kAcc * T, kBNT>(a, partial_out, lds);
+  if (PU && add_j > 0) {  // block-uniform
+    __shared__ double wave_maxima[kBW];
+    const double m = wave_max(add_max);
+    if (lane == 0) wave_maxima[w] = m;
+    __syncthreads();
+    if (lane == 0 && w == 0) {
+      double b = wave_maxima[0];
+      for (int i = 1; i < kBW; ++i) b = fmax(b, wave_maxima[i]);
+      const double v = beta * b;
+      // non-negative doubles order like their bit patterns
+      atomicMax((unsigned long long*)&p.state->max_beta_n,
+                (unsigned long long)__double_as_longlong(v > 0.0 ? v : 0.0));
+    }
+  }
 }
 
 

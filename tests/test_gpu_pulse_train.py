@@ -161,11 +161,73 @@ def test_batch_trains_equal_single_runs(gpu):
         assert g["f_R"] == pytest.approx(s["f_R"], rel=1e-12)
 
 
-def test_batch_with_train_refuses_blocked_passes(gpu):
+def test_batch_with_short_period_refuses_blocked_passes(gpu):
+    """The mixed sweep has periods of one and two steps: a pass of three
+    steps would hold two pulses."""
     chs, trs = mixed_sweep()
     with pytest.raises(gpu.ItError) as e:
         gpu.it_solve_batch(chs, trs, exec=dict(kernel=2, steps_per_pass=3))
     assert e.value.code == gpu.IT_ENOTSUP
+
+
+def blocked_train_sweep(T):
+    """Trains whose periods are T, T + 1, 2T + 1 and 13 steps (at most one
+    pulse in a pass of T steps; a period of exactly T puts a pulse on the
+    same level of every pass), single pulses, a train with space charge and
+    one cut by max_steps before its last pulse."""
+    rng = np.random.default_rng(91)
+    chs, trs = [], []
+    periods = [T, 0, T + 1, 2 * T + 1, 13, 0, T + 1, T]
+    for q, m in enumerate(periods):
+        nx, ny, nz = int(rng.integers(24, 90)), int(rng.integers(14, 60)), int(rng.integers(8, 36))
+        ch = W.chamber(nx, ny, nz, 3e-4, nz * 3e-4, float(rng.uniform(15, 60)),
+                       uniform_n0=float(rng.uniform(5e8, 4e9)), space_charge=1 if q == 6 else 0)
+        k = int(rng.integers(1, 5))
+        lx, ly = nx * 3e-4, ny * 3e-4
+        tr = W.tracks(np.stack([rng.uniform(2, 20, k), rng.uniform(6e-4, 1.2e-3, k), rng.uniform(0, lx, k),
+                                rng.uniform(0, ly, k), rng.uniform(0, 0.6, k), rng.uniform(0, 6.2, k),
+                                np.zeros(k)], axis=1))
+        if m:
+            ch = train(ch, 6, (m - 0.5) * single_pulse_dt(ch, tr))  # ceil gives m steps a period
+        if q == 7:
+            ch["max_steps"] = 4 * T + 1  # cut before its last pulse
+        chs.append(ch)
+        trs.append(tr)
+    return chs, trs
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+def test_batch_trains_with_blocked_passes(gpu, orc, T):
+    """A pass of T steps adds a pulse to the outputs of the level before it
+    and its recording block books the release with the pulse's step: every
+    instance matches the oracle, max_beta_n and the last period included."""
+    chs, trs = blocked_train_sweep(T)
+    res = gpu.it_solve_batch(chs, trs, exec=dict(kernel=2, steps_per_pass=T, check_every=4))
+    longest = 0
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        compare(g, o)
+        longest = max(longest, o["steps"])
+    # the batch's launches: a priming pass, then graphs of four passes, one
+    # more graph in flight when the host sees the last instance stop
+    assert res[0]["passes"] <= (longest + T - 1) // T + 9
+    assert res[0]["pulses"] == 6 and res[7]["flags"] & gpu.IT_FLAG_MAX_STEPS
+
+
+def test_batch_trains_take_blocked_passes_by_default(gpu, orc):
+    """With every period at least three steps the library's choice is the
+    blocked pass of three steps, and the results match the oracle."""
+    chs, trs = blocked_train_sweep(3)
+    res = gpu.it_solve_batch(chs, trs)
+    longest = 0
+    for ch, tr, g in zip(chs, trs, res):
+        o = orc.solve(ch, tr, with_fields=False)
+        compare(g, o)
+        longest = max(longest, o["steps"])
+    # 78 steps: 26 passes of three steps fit in one graph of 32 passes after
+    # the priming pass (65 launches with the next graph in flight); one step
+    # per pass would have needed three graphs and 129 launches
+    assert res[0]["passes"] <= 65 < longest
 
 
 def test_train_refuses_late_tracks_and_free_electrons(gpu):
