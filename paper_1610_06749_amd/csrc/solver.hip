@@ -835,16 +835,22 @@ Tiling batch_tiling(const it_chamber& c, int T, int R, int rows, const it_exec* 
   return batch_blocked_tiling(c, T, R, zc > 0 ? zc : batch_blocked_z_chunk(exec));
 }
 
+// Shortest chunk the blocked batch tiles are re-chunked to: T planes (a
+// chunk then computes three times its planes, which pays only when it puts
+// blocks on otherwise idle CUs; the search below weighs exactly that).
+int batch_blocked_min_z(int z0, int T) { return std::min(z0, T); }
+
 // Chunk length of the blocked batch tiles for the running instances `set`:
 // the caller's (or default) chunk z0 while the batch fills the machine, a
 // shorter one once it leaves CUs idle.  One blocked block occupies a CU, so
 // a launch takes about ceil(blocks / CUs) rounds of one block's march
 // (its chunk plus T planes of halo at each end); the chunk minimises that,
-// between 4T planes and z0.  On MI355X's 256 CUs the 96-chamber sweep's
-// tail, where a few chambers run, otherwise idles most of the machine.
+// between batch_blocked_min_z(z0, T) planes and z0.  On MI355X's 256 CUs the
+// 96-chamber sweep's tail, where a few chambers run, otherwise idles most of
+// the machine.
 int batch_blocked_retile_z(const it_chamber* ch, const int* set, int n, int T, int R, int z0) {
   constexpr long kCUs = 256;
-  const int zmin = std::min(z0, 4 * T);
+  const int zmin = batch_blocked_min_z(z0, T);
   // tile columns and interior planes of each instance (the chunk count is
   // ceil(planes / min(z, planes)), as blocked_tiling_zc takes it)
   std::vector<long> cols(n);
@@ -885,8 +891,8 @@ BatchLayout make_batch_layout(const it_chamber* ch, const int64_t* toff, int nin
       off = align_up(off + L.field_elems * sizeof(double));
     }
     // partial slots for the most tiles any chunk length of the run can give
-    // (blocked tiles are re-chunked down to 4T planes as instances stop)
-    const int zmin = T > 1 ? std::min(batch_blocked_z_chunk(exec), 4 * T) : 0;
+    // (blocked tiles are re-chunked as instances stop)
+    const int zmin = T > 1 ? batch_blocked_min_z(batch_blocked_z_chunk(exec), T) : 0;
     const Tiling ts = batch_tiling(c, T, R, rows, exec, tile_x, zmin);
     const Tiling td = deposit_tiling(c.nx, c.ny, c.nz);
     L.slots = ts.ntiles;

@@ -190,7 +190,8 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
       for (int r = 0; r < R; ++r) np[r] = nn[r] = 0.0;  // electrode planes and beyond hold zero
       if (interior)  // block-uniform
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int i = 0; i < R; ++i) {
+        const int r = (i + 1) % R;  // the strip's first row last: its upper neighbour comes from LDS
         const double pc = cpv[t - 1][r], nc = cnv[t - 1][r];
         const double pxl = lane_from_left(pc), pxr = lane_from_right(pc);
         const double nxl = lane_from_left(nc), nxr = lane_from_right(nc);
@@ -199,10 +200,14 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
         const double sink = beta * pc * nc;
         const double net = pc - nc;
         const double scp = SC ? gsp * pc * net : 0.0, scn = SC ? gsn * nc * net : 0.0;
-        const double a = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[r] +
-                         cp.azm * mp[t - 1][r] - sink + scp;
-        const double b = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[r] +
-                         cn.azm * mn[t - 1][r] - sink + scn;
+        double a = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[r] +
+                   cp.azm * mp[t - 1][r] - sink;
+        double b = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[r] +
+                   cn.azm * mn[t - 1][r] - sink;
+        if constexpr (SC) {  // (not "+ 0.0" without it: x + 0 is not folded away, as -0 + 0 = +0)
+          a += scp;
+          b += scn;
+        }
         np[r] = a;
         nn[r] = b;
         if (counted && own_y[r]) {  // wave-uniform; the columns are masked at the end
