@@ -103,8 +103,10 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
 #pragma unroll
     for (int t = 0; t < T; ++t) edge_sum[t][w][lane] = 0.0;
 
-  // level t (0..T-1): mp/mn its plane K-t-2, cpv/cnv its plane K-t-1 at the
-  // start of iteration K
+  // level t (0..T-1) at the start of iteration K: cpv/cnv its plane K-t-1,
+  // mp/mn the lower z-neighbour term of the next step's update on that plane,
+  // a_{z-} times its plane K-t-2 (kept instead of the plane itself, so the
+  // march shifts one register pair less per node, level and species)
   double mp[T][R], mn[T][R], cpv[T][R], cnv[T][R];
   double acc[T][NA];  // tallies of the owned rows, all columns (masked at the end)
 #pragma unroll
@@ -200,10 +202,8 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
         const double sink = beta * pc * nc;
         const double net = pc - nc;
         const double scp = SC ? gsp * pc * net : 0.0, scn = SC ? gsn * nc * net : 0.0;
-        double a = cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[r] +
-                   cp.azm * mp[t - 1][r] - sink;
-        double b = cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[r] +
-                   cn.azm * mn[t - 1][r] - sink;
+        double a = mp[t - 1][r] + cp.a0 * pc + cp.ax * (pxr + pxl) + cp.ay * (pyr + pyl) + cp.azp * vp[r] - sink;
+        double b = mn[t - 1][r] + cn.a0 * nc + cn.ax * (nxr + nxl) + cn.ay * (nyr + nyl) + cn.azp * vn[r] - sink;
         if constexpr (SC) {  // (not "+ 0.0" without it: x + 0 is not folded away, as -0 + 0 = +0)
           a += scp;
           b += scn;
@@ -232,11 +232,12 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
           if (counted && own_y[r] && own_x) add_max = fmax(add_max, fmax(np[r], nn[r]));
         }
       }
-      // level t-1 moves on: plane K-t becomes its older plane, K-t+1 its current one
+      // level t-1 moves on: plane K-t gives the lower-neighbour term, K-t+1
+      // becomes its current plane
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        mp[t - 1][r] = cpv[t - 1][r];
-        mn[t - 1][r] = cnv[t - 1][r];
+        mp[t - 1][r] = cp.azm * cpv[t - 1][r];
+        mn[t - 1][r] = cn.azm * cnv[t - 1][r];
         cpv[t - 1][r] = vp[r];
         cnv[t - 1][r] = vn[r];
         vp[r] = np[r];
