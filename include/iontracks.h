@@ -240,10 +240,12 @@ typedef struct {
   void* const* timing_events;
   int32_t n_timing_events;
   int32_t z_chunk;         /* planes per tile of the one-step kernel, 4..512 (0 = default); in
-                            * it_solve_batch with blocked passes, the planes per tile while the
-                            * running instances fill the machine (default 24): the library
-                            * shortens the chunks, down to 4 x steps_per_pass planes, whenever
-                            * the running set leaves compute units idle */
+                            * it_solve_batch with blocked passes, the most planes per tile
+                            * (default 512): the library picks the chunk, between
+                            * steps_per_pass planes and this, that runs the running instances'
+                            * tiles in the fewest rounds of one block per compute unit times
+                            * the planes a block marches, and picks it again as instances
+                            * finish */
   int32_t timing_span;     /* see timing_events */
   int32_t tile_x;          /* columns per tile of the one-step kernels: 64, or 32 (32 x 16 tiles of
                             * 8 waves, two rows each; tile_y must then be 0 or 16, and the

@@ -127,11 +127,12 @@ def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
 
 
 def batch_candidates(rows=(8,), graph_passes=(32,), z_chunks=(16,), narrow=False,
-                     blocked_T=(2, 3), blocked_z=(16, 24, 32, 48), blocked_graph=(32,)):
+                     blocked_T=(2, 3), blocked_z=(0, 32), blocked_graph=(32,)):
     """Execution choices tried for a batch: the one-step batched kernel with
     64-column tiles of each of ``rows`` (and 32 x 16 when ``narrow``), each
     planes-per-tile and passes-per-graph choice; and the temporally blocked
-    batched kernel at each depth, chunk length and passes per graph."""
+    batched kernel at each depth, chunk length (0: the library's choice, no
+    cap) and passes per graph."""
     shapes = [dict(tile_y=r, tile_x=64) for r in rows] + ([dict(tile_y=16, tile_x=32)] if narrow else [])
     out = [dict(kernel=B.IT_KERNEL_PLAIN, check_every=g, z_chunk=z, **sh)
            for sh in shapes for g in graph_passes for z in z_chunks]

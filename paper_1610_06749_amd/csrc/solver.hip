@@ -807,14 +807,16 @@ int check_batch_steps(const it_chamber* ch, int ninst, const it_exec* ex, int T)
   return IT_OK;
 }
 
-// Planes per chunk of the blocked batch tiles: as requested, else 24 (each
-// chunk recomputes T planes of halo at both ends; shorter chunks keep the
-// tail of the sweep, where few small chambers run, on more CUs: the
-// 96-chamber sweep takes 7.46 s with 24 planes, 7.58 s with 32 and 7.51 s
-// with 48 on MI355X).
+// Most planes per chunk of the blocked batch tiles: as requested, else 512
+// (no cap in practice): batch_blocked_retile_z picks the chunk for the
+// running instances below it.  Each chunk recomputes T planes of halo at
+// both ends, so with many chambers running the longer chunks the search
+// takes pay (the 96-chamber sweep: 6.55 s with a 24-plane cap, 6.34 s with
+// 32, 6.00 s with 48, 5.98 s with 64 or more, where the search takes 49
+// planes while all chambers run).
 int batch_blocked_z_chunk(const it_exec* exec) {
   const int z = exec_z_chunk(exec);
-  return z > 0 ? z : 24;
+  return z > 0 ? z : 512;
 }
 
 // Blocked tiles of one chamber of a batch in chunks of zc planes (T steps,
@@ -850,6 +852,9 @@ int batch_blocked_min_z(int z0, int T) { return std::min(z0, T); }
 // the machine.
 int batch_blocked_retile_z(const it_chamber* ch, const int* set, int n, int T, int R, int z0) {
   constexpr long kCUs = 256;
+  int most = 1;  // longer chunks than the deepest instance's planes change nothing
+  for (int i = 0; i < n; ++i) most = std::max(most, ch[set[i]].nz - 1);
+  z0 = std::min(z0, most);
   const int zmin = batch_blocked_min_z(z0, T);
   // tile columns and interior planes of each instance (the chunk count is
   // ceil(planes / min(z, planes)), as blocked_tiling_zc takes it)

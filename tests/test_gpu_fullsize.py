@@ -132,7 +132,7 @@ def test_pulsed_beam_full_run(gpu):
     check_conservation(g["trace"], gd["result"]["n_released"])
 
 
-# the library's default (blocked passes of three steps, 24-plane chunks) and
+# the library's default (blocked passes of three steps, chunks of its choosing) and
 # the other executions the autotuner can pick for the timed sweep
 SWEEP_EXECS = [None, dict(kernel=2, steps_per_pass=3, z_chunk=48), dict(kernel=2, steps_per_pass=2, z_chunk=16),
                dict(kernel=1)]
