@@ -134,7 +134,7 @@ void batch_blocked_kernel(const BatchInstance* __restrict__ inst, int ninst, int
     record_previous<kBNT>(inst[b - 8 * per_xcd], parity, T);
     return;
   }
-  const int L = (b & 7) * per_xcd + (b >> 3);  // XCD-aware order over the whole list
+  const int L = blocked_tile_index(b, per_xcd);  // XCD-aware order over the whole list
   if (L >= total_tiles) return;
   const int q = find_instance(inst, ninst, L);
   const StepParams& p = inst[q].sp[parity];

@@ -40,7 +40,9 @@ __global__ __launch_bounds__(kBNT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
   if (threadIdx.x == 0 && threadIdx.y == 0) stopped = p.state->done;
   __syncthreads();
   if (stopped) return;
-  const TileCoord tc = decode_tile(p.tiles_x, p.tiles_y, p.ntiles, p.per_xcd);
+  const int L = blocked_tile_index(blockIdx.x, p.per_xcd);
+  TileCoord tc = tile_of(L < p.ntiles ? L : 0, p.tiles_x, p.tiles_y);
+  tc.valid = L < p.ntiles;
   blocked_tile_pass<T, R, SC>(p, tc, p.partials + (size_t)blockIdx.x * kAcc * T);
 }
 
