@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -70,11 +71,20 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash(names):
+def kernel_source_hash(names, csrc=None):
+    """First 16 hex digits of the SHA-256 of the named kernel sources with
+    comments, trailing blanks and empty lines removed: a counter summary
+    stays valid across edits of comments and goes stale with any edit of
+    code."""
+    csrc = csrc or os.path.join(ROOT, "paper_1610_06749_amd", "csrc")
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(ROOT, "paper_1610_06749_amd", "csrc", n), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, n), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode("utf-8") + b"\0")
     return h.hexdigest()[:16]
 
 

@@ -9,10 +9,11 @@
 // steps (levels) is exact on one node less on every side, so after T steps
 // the centre (64 - 2T) x (8 R - 2T) columns are exact: the block's owned
 // columns.  The block marches up a chunk of planes with a software pipeline
-// over the levels: at iteration K it loads level 0 on plane K and computes
-// level t on plane K - t for t = 1..T from level t-1 on planes K-t-1, K-t and
-// K-t+1, which the thread keeps in registers (two planes per level plus the
-// one just computed).
+// over the levels: at iteration K it has level 0 on plane K (loaded one or
+// two iterations ahead) and computes level t on plane K - t for t = 1..T
+// from level t-1 on planes K-t-1, K-t and K-t+1, which the thread keeps in
+// registers (per level the current plane and a_{z-} times the one below it,
+// plus the plane just computed).
 //
 // Lateral neighbours of level t-1 on plane K-t: x from the adjacent lanes
 // (whole-wave DPP shifts), y from the thread's own rows; only the first and

@@ -25,3 +25,16 @@ def test_traffic_summary_lookup(tmp_path):
     assert len(h) == 16
     assert bench.read_traffic("step_plain", "pulsed_256x256x200", "0" * 16, "tile_x 0 tile_y 8 z_chunk 0") is None
     assert bench.read_traffic("step_plain", "no_such_workload", h, "tile_x 0 tile_y 8 z_chunk 0") is None
+
+
+def test_source_hash_ignores_comments(tmp_path):
+    """A counter summary survives an edit of a comment, not of code."""
+    sys.path.insert(0, ROOT)
+    import bench
+    code = "__global__ void k(double* x) {  // one store\n  x[0] = 1.0; /* the value */\n}\n"
+    (tmp_path / "k.hip").write_text(code)
+    h = bench.kernel_source_hash(["k.hip"], str(tmp_path))
+    (tmp_path / "k.hip").write_text("// a kernel\n" + code.replace("one store", "a store") + "\n\n")
+    assert bench.kernel_source_hash(["k.hip"], str(tmp_path)) == h
+    (tmp_path / "k.hip").write_text(code.replace("1.0", "2.0"))
+    assert bench.kernel_source_hash(["k.hip"], str(tmp_path)) != h
