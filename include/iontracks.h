@@ -123,8 +123,9 @@ typedef struct {
    * (ax or ay times the density of each node next to the boundary, per
    * missing neighbour) leaves the chamber and is counted as escaped; track
    * offsets are then not wrapped.  Absorbing boundaries work with the
-   * one-step kernel (IT_KERNEL_AUTO / IT_KERNEL_PLAIN) and in batches, not
-   * with the blocked kernel or free electrons (IT_ENOTSUP). */
+   * one-step and the blocked kernel of single runs and with the one-step
+   * passes of batches, not with blocked batch passes or free electrons
+   * (IT_ENOTSUP). */
   int32_t lateral_bc;
   /* Pulse train (the beam's time structure as pulses, Distribution of ion
    * tracks; a repetition rate read as a periodic train of identical

@@ -26,8 +26,9 @@ __device__ void record_previous_pass(const StepParams& p) {
                    p.min_stop_step);
 }
 
-// SC: with the space-charge term (two more tallies per level).
-template <int T, int R, bool SC>
+// SC: with the space-charge term (two more tallies per level); AB: absorbing
+// lateral boundaries (the escaped tallies).
+template <int T, int R, bool SC, bool AB>
 __global__ __launch_bounds__(kBNT) __attribute__((amdgpu_waves_per_eu(2, 2))) void step_blocked_kernel(StepParams p) {
   if (p.prev_partials && blockIdx.x == gridDim.x - 1) {
     record_previous_pass(p);
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(kBNT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
   const int L = blocked_tile_index(blockIdx.x, p.per_xcd);
   TileCoord tc = tile_of(L < p.ntiles ? L : 0, p.tiles_x, p.tiles_y);
   tc.valid = L < p.ntiles;
-  blocked_tile_pass<T, R, SC>(p, tc, p.partials + (size_t)blockIdx.x * kAcc * T);
+  blocked_tile_pass<T, R, SC, false, AB>(p, tc, p.partials + (size_t)blockIdx.x * kAcc * T);
 }
 
 // Rows per thread for T fused steps when the caller does not choose: the
@@ -78,10 +79,12 @@ template <int T, int R>
 void launch_rows(const StepParams& p, dim3 g, hipStream_t s) {
   const dim3 block(kWave, kBW);
   const bool sc = p.gsp != 0.0 || p.gsn != 0.0;
-  if (sc)
-    hipLaunchKernelGGL((step_blocked_kernel<T, R, true>), g, block, 0, s, p);
-  else
-    hipLaunchKernelGGL((step_blocked_kernel<T, R, false>), g, block, 0, s, p);
+  switch ((sc ? 2 : 0) + (p.absorbing ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((step_blocked_kernel<T, R, false, false>), g, block, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((step_blocked_kernel<T, R, false, true>), g, block, 0, s, p); break;
+    case 2: hipLaunchKernelGGL((step_blocked_kernel<T, R, true, false>), g, block, 0, s, p); break;
+    default: hipLaunchKernelGGL((step_blocked_kernel<T, R, true, true>), g, block, 0, s, p); break;
+  }
 }
 
 }  // namespace

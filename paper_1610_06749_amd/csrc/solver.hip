@@ -311,14 +311,14 @@ int requested_steps(const it_exec* ex) {
 }
 
 // The library's choice: passes of kBlockedT steps of the blocked kernel on a
-// periodic grid large enough to fill the machine (on MI355X 1.8x faster per
+// grid large enough to fill the machine (on MI355X 1.8x faster per
 // step than one step per launch at 13 M and 67 M interior nodes), else one
 // step per launch.  Not when the caller sets a one-step tile option, and not
 // when the final fields are asked for: a blocked pass that contains the step
 // meeting the collection criterion still computes the pass's later steps,
 // so its fields would be up to kBlockedT - 1 steps past the result's.
 int auto_steps(const it_chamber* ch, const it_exec* ex, bool exact_fields) {
-  if (ch->lateral_bc || exact_fields) return 1;
+  if (exact_fields) return 1;
   if (ex && (ex->tile_x || ex->tile_y || ex->z_chunk)) return 1;
   const double nodes = (double)ch->nx * ch->ny * (double)(ch->nz - 1);
   if (nodes < kBlockedMinNodes || ch->nx < 64 || ch->ny < 32) return 1;
@@ -336,7 +336,6 @@ int exec_steps(const it_chamber* ch, const it_exec* ex, bool exact_fields) {
 int check_exec(const it_chamber* ch, const it_exec* ex, int T) {
   if (T < 1 || T > kMaxT) return IT_EINVAL;
   if (T > 1 && !blocked_supported(T, ex ? ex->tile_y : 0)) return ex && ex->tile_y ? IT_EINVAL : IT_ENOTSUP;
-  if (T > 1 && ch->lateral_bc) return IT_ENOTSUP;  // the blocked kernel is periodic only
   if (!z_chunk_ok(ex)) return IT_EINVAL;
   if (!tile_shape_ok(ex) || (ex && (ex->tile_x == 32 || ex->tile_x == 128) && T > 1)) return IT_EINVAL;
   if (ex && ex->tile_x == 128 && ch->nx % 2) return IT_EINVAL;

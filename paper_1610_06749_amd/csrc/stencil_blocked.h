@@ -80,13 +80,18 @@ __device__ inline double lane_from_right(double v) {  // value of lane + 1
 // level's outputs once its tallies are taken (on every node the tile
 // computes, so the later levels step from them), and beta times the largest
 // owned output enters the run's max_beta_n, as a deposit does.
-template <int T, int R, bool SC, bool PU = false>
+// AB: absorbing lateral boundaries (R1): the tile's nodes beyond the cell
+// hold zero at every level instead of the periodic image, and each owned
+// node next to the boundary adds a_x (a_y) times its old density per missing
+// neighbour to the escaped tally of its species, as in the one-step kernel.
+template <int T, int R, bool SC, bool PU = false, bool AB = false>
 __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const TileCoord tc, double* partial_out,
                                                   int add_j = 0, const double* add_p = nullptr,
                                                   const double* add_n = nullptr) {
   constexpr int EY = kBW * R;             // rows of the extended tile
   constexpr int OX = kBX - 2 * T, OY = EY - 2 * T;
-  constexpr int NA = SC ? 7 : 5;          // tallies kept per level
+  constexpr int NE = SC ? 7 : 5;          // index of the escaped tallies (AB)
+  constexpr int NA = NE + (AB ? 2 : 0);   // tallies kept per level
   // edge rows of each level's newest plane: [buffer][level][wave][first/last][species][lane]
   __shared__ double edge_rows[2][T][kBW][2][2][kWave];
   __shared__ double edge_sum[T][kBW][4];  // per-wave sums of n on the planes next to the electrodes
@@ -102,6 +107,13 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
   const bool own_x = lane >= T && lane < kBX - T && x0 + (lane - T) < nx;
   unsigned off[R];  // in-plane byte offsets of the thread's nodes
   bool own_y[R];    // the row is owned (wave-uniform)
+  // absorbing: the node lies in the cell (else it holds zero), and the
+  // missing neighbours of the lane's column and of each row
+  const int gx = x0 - T + lane;
+  const bool in_x = !AB || (gx >= 0 && gx < nx);
+  const double miss_x = AB ? (double)((gx == 0) + (gx == nx - 1)) : 0.0;
+  bool in_y[R];
+  double miss_y[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int g = w * R + r;  // row in the extended tile
@@ -109,6 +121,9 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
     if (ys < 0) ys += ny;
     off[r] = (unsigned)(ys * nx + xs) * 8u;
     own_y[r] = tc.valid && g >= T && g < EY - T && y0 + (g - T) < ny;
+    const int gy = y0 - T + g;
+    in_y[r] = !AB || (gy >= 0 && gy < ny);
+    miss_y[r] = AB ? (double)((gy == 0) + (gy == ny - 1)) : 0.0;
   }
   const int za = 1 + tc.zc * p.zc;
   const int zb = tc.valid ? min(za + p.zc, nz) : za;
@@ -145,7 +160,7 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
   // alternate and each plane is loaded two iterations ahead, the march taking
   // two iterations per loop trip (1 % faster on the 512 x 512 x 256 grid, 2 %
   // on the 96-chamber sweep); otherwise one buffer, one plane ahead.
-  constexpr bool kTwoBuffers = T * R <= 12 && R <= 4;
+  constexpr bool kTwoBuffers = T * R <= 12 && R <= 4 && !AB;
   constexpr int kAhead = kTwoBuffers ? 2 : 1;
   double pa[R], na[R], pb[R], nb[R];
   auto load0 = [&](int K, double (&lp)[R], double (&ln)[R]) {
@@ -156,6 +171,7 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
     for (int r = 0; r < R; ++r) {
       lp[r] = *(const gdouble*)(bp + off[r]);
       ln[r] = *(const gdouble*)(bn + off[r]);
+      if (AB && !(in_x && in_y[r])) lp[r] = ln[r] = 0.0;  // beyond an absorbing boundary
     }
   };
   // the zero planes' edge rows held at the start
@@ -233,6 +249,7 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
           a += scp;
           b += scn;
         }
+        if (AB && !(in_x && in_y[r])) a = b = 0.0;  // beyond an absorbing boundary
         np[r] = a;
         nn[r] = b;
         if (counted && own_y[r]) {  // wave-uniform; the columns are masked at the end
@@ -244,6 +261,10 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
           if constexpr (SC) {
             acc[t - 1][5] += scp;
             acc[t - 1][6] += scn;
+          }
+          if constexpr (AB) {
+            acc[t - 1][NE] += (cp.ax * miss_x + cp.ay * miss_y[r]) * pc;
+            acc[t - 1][NE + 1] += (cn.ax * miss_x + cn.ay * miss_y[r]) * nc;
           }
         }
       }
@@ -328,8 +349,13 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
       a[t * kAcc + 9] = 0.0;
       a[t * kAcc + 10] = 0.0;
     }
-    a[t * kAcc + 11] = 0.0;  // escaped: the blocked kernel is periodic only
-    a[t * kAcc + 12] = 0.0;
+    if constexpr (AB) {  // escaped (absorbing boundaries)
+      a[t * kAcc + 11] = own_x ? acc[t][NE] : 0.0;
+      a[t * kAcc + 12] = own_x ? acc[t][NE + 1] : 0.0;
+    } else {
+      a[t * kAcc + 11] = 0.0;
+      a[t * kAcc + 12] = 0.0;
+    }
   }
   block_sum_store<kAcc * T, kBNT>(a, partial_out, lds);
   if (PU && add_j > 0) {  // block-uniform

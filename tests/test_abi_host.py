@@ -139,8 +139,8 @@ def test_lateral_boundary_option_checks(lib, orc):
             lib.it_validate(dict(ch, lateral_bc=bad), tr)
         assert e.value.code == lib.IT_EINVAL
     ab = dict(ch, lateral_bc=1)
-    # absorbing boundaries: the one-step kernel only, no free electrons
-    assert _solve_status(lib, ab, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_ENOTSUP
+    # absorbing boundaries: the one-step and the blocked kernel, no free electrons
+    assert _solve_status(lib, ab, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_EWORKSPACE
     assert _solve_status(lib, dict(ab, mu_e=1000.0, D_e=25.0), tr, None) == lib.IT_ENOTSUP
     assert _solve_status(lib, ab, tr, dict(kernel=1)) == lib.IT_EWORKSPACE  # accepted up to the workspace
     assert _solve_status(lib, ch, tr, dict(kernel=2, steps_per_pass=4)) == lib.IT_EWORKSPACE

@@ -390,10 +390,12 @@ def test_advance_from_given_fields(gpu, orc, ex):
 
 
 # absorbing lateral boundaries: the one-step kernel (both tile shapes, short
-# z chunks); tracks next to the edges and corners so that charge escapes
+# z chunks) and the blocked kernel at T = 2, 3, 4; tracks next to the edges
+# and corners so that charge escapes
 AB_EXECS = [dict(kernel=1, tile_y=8), dict(kernel=1, tile_y=16), dict(kernel=1, tile_y=8, z_chunk=5),
-            dict(kernel=1, tile_x=32), dict(kernel=1, tile_x=128, tile_y=16)]
-AB_IDS = ["plain8", "plain16", "plain8z5", "plain32x16", "pair128x16"]
+            dict(kernel=1, tile_x=32), dict(kernel=1, tile_x=128, tile_y=16),
+            dict(kernel=2, steps_per_pass=2), dict(kernel=2, steps_per_pass=3), dict(kernel=2, steps_per_pass=4)]
+AB_IDS = ["plain8", "plain16", "plain8z5", "plain32x16", "pair128x16", "blocked2", "blocked3", "blocked4"]
 
 
 @pytest.mark.parametrize("ex", AB_EXECS, ids=AB_IDS)
@@ -402,8 +404,13 @@ def test_absorbing_ragged_case(gpu, orc, ex):
     ch["lateral_bc"] = 1
     tr[0, 2], tr[0, 3] = 2e-4, 1e-4          # parallel track at the corner
     tr[1, 2] = 70 * 3e-4 - 3e-4              # tilted track at the x = nx-1 edge
-    g, o = run_both(gpu, orc, ch, tr, exec=ex)
+    # a blocked pass ends up to T - 1 steps past a collection stop, so its
+    # fields are compared on a run cut by max_steps instead
+    blocked = ex.get("kernel") == 2
+    g, o = run_both(gpu, orc, ch, tr, exec=ex, fields=not blocked)
     assert o["flags"] == 0 and o["n_escaped_pos"] > 1e-3 * o["n_released"]
+    if blocked:
+        g, o = run_both(gpu, orc, dict(ch, max_steps=70, stop_tol=0.0), tr, exec=ex)
     compare_fields(g["pos"], o["pos"])
     compare_fields(g["neg"], o["neg"])
 
@@ -428,21 +435,23 @@ def test_absorbing_advance_from_given_fields(gpu, orc, ex):
     assert np.all(otr[:, 13] > 0)
 
 
+@pytest.mark.parametrize("ex", [None, dict(kernel=2, steps_per_pass=3)], ids=["default", "blocked3"])
 @pytest.mark.parametrize("geom", [(1, 1, 40), (1, 7, 12), (5, 1, 12)])
-def test_absorbing_one_node_wide_cells(gpu, orc, geom):
+def test_absorbing_one_node_wide_cells(gpu, orc, geom, ex):
     """Cells one node wide in x and/or y: each node misses both neighbours
     of that direction."""
     nx, ny, nz = geom
     ch = W.chamber(nx, ny, nz, 3e-4, nz * 3e-4, 10.0, uniform_n0=3e9, lateral_bc=1)
-    g, o = run_both(gpu, orc, ch, W.no_tracks())
+    g, o = run_both(gpu, orc, ch, W.no_tracks(), exec=ex, fields=ex is None)
     assert o["n_escaped_pos"] > 0.01 * o["n_released"]
 
 
-def test_absorbing_far_from_edges_matches_periodic_run(gpu, orc):
+@pytest.mark.parametrize("ex", [None, dict(kernel=2, steps_per_pass=3)], ids=["default", "blocked3"])
+def test_absorbing_far_from_edges_matches_periodic_run(gpu, orc, ex):
     ch, tr = W.single_track()
     ch_a = dict(ch, lateral_bc=1, max_steps=40)
-    g_a = gpu.it_solve(ch_a, tr, trace=True)
-    g_p = gpu.it_solve(dict(ch_a, lateral_bc=0), tr, trace=True)
+    g_a = gpu.it_solve(ch_a, tr, trace=True, exec=ex)
+    g_p = gpu.it_solve(dict(ch_a, lateral_bc=0), tr, trace=True, exec=ex)
     N = g_p["n_released"]
     assert g_a["steps"] == g_p["steps"] == 40
     assert np.max(np.abs(g_a["trace"][:, :13] - g_p["trace"][:, :13])) <= 1e-12 * N
