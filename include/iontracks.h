@@ -122,10 +122,9 @@ typedef struct {
    * hold zero, like the electrodes, and what they would receive in a step
    * (ax or ay times the density of each node next to the boundary, per
    * missing neighbour) leaves the chamber and is counted as escaped; track
-   * offsets are then not wrapped.  Absorbing boundaries work with the
-   * one-step and the blocked kernel of single runs and with the one-step
-   * passes of batches, not with blocked batch passes or free electrons
-   * (IT_ENOTSUP). */
+   * offsets are then not wrapped.  Absorbing boundaries work with every
+   * stepping kernel, in single runs and in batches (where they may be mixed
+   * with periodic instances), not with free electrons (IT_ENOTSUP). */
   int32_t lateral_bc;
   /* Pulse train (the beam's time structure as pulses, Distribution of ion
    * tracks; a repetition rate read as a periodic train of identical

@@ -97,7 +97,9 @@ def time_exec(ch, ex, steps=64, reps=3, dt=None):
 def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
     """Best execution choice (an ``exec`` dict for it_solve / it_advance) for
     the chamber's grid.  ``cache``: optional JSON path."""
-    key = f"{ch['nx']}x{ch['ny']}x{ch['nz']}@{_device_name()}"
+    # the grid, and the options that change the kernel instance
+    opts = ("a" if ch.get("lateral_bc", 0) else "") + ("s" if ch.get("space_charge", 0) else "")
+    key = f"{ch['nx']}x{ch['ny']}x{ch['nz']}{opts}@{_device_name()}"
     if key in _memo:
         return dict(_memo[key])
     table = _load(cache)
@@ -158,8 +160,6 @@ def tune_batch(chs, trs, steps=96, candidates=None, cache=None, verbose=False, *
     vs = sum(c["nx"] * c["ny"] * (c["nz"] - 1) for c in chs) * steps
     timings = []
     cands = candidates if candidates is not None else batch_candidates(**kw)
-    if any(c.get("lateral_bc", 0) for c in chs):  # the blocked pass is periodic only
-        cands = [ex for ex in cands if ex.get("kernel") != B.IT_KERNEL_BLOCKED]
     for ex in cands:
         B.it_solve_batch(capped, trs, exec=ex)  # warm-up
         torch.cuda.synchronize()

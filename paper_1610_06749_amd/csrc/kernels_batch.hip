@@ -124,8 +124,8 @@ void batch_step_kernel(const BatchInstance* __restrict__ inst, int ninst, int to
 // on each running instance's tiles (64 x 8R extended tiles, chunks of
 // planes), one recording block per instance as above.  PU: some instance
 // has a pulse train (its tile blocks add the pulse to the level its flag
-// for this pass names).
-template <int T, int R, bool SC, bool PU>
+// for this pass names); AB: some instance has absorbing lateral boundaries.
+template <int T, int R, bool SC, bool PU, bool AB>
 __global__ __launch_bounds__(kBNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void batch_blocked_kernel(const BatchInstance* __restrict__ inst, int ninst, int total_tiles, int per_xcd,
                           int parity) {
@@ -150,9 +150,9 @@ void batch_blocked_kernel(const BatchInstance* __restrict__ inst, int ninst, int
     const BatchInstance& bi = inst[q];
     // written by the previous pass's recording block; one value for the block
     const int j = bi.npulses >= 2 ? __builtin_amdgcn_readfirstlane(p.state->pulse_add[parity]) : 0;
-    blocked_tile_pass<T, R, SC, true>(p, t, p.partials + (size_t)l * kAcc * T, j, bi.pulse_pos, bi.pulse_neg);
+    blocked_tile_pass<T, R, SC, true, AB>(p, t, p.partials + (size_t)l * kAcc * T, j, bi.pulse_pos, bi.pulse_neg);
   } else {
-    blocked_tile_pass<T, R, SC>(p, t, p.partials + (size_t)l * kAcc * T);
+    blocked_tile_pass<T, R, SC, false, AB>(p, t, p.partials + (size_t)l * kAcc * T);
   }
 }
 
@@ -176,32 +176,37 @@ const void* batch_kernel_terms(bool sc, bool ab, bool pu) {
   return pu ? batch_kernel_pu<SY, TX, true>(sc, ab) : batch_kernel_pu<SY, TX, false>(sc, ab);
 }
 
-template <int T, int R>
-const void* batch_blocked_ptr(bool sc, bool pu) {
+template <int T, int R, bool AB>
+const void* batch_blocked_terms(bool sc, bool pu) {
   switch ((sc ? 2 : 0) + (pu ? 1 : 0)) {
-    case 0: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false, false>);
-    case 1: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false, true>);
-    case 2: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true, false>);
-    default: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true, true>);
+    case 0: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false, false, AB>);
+    case 1: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, false, true, AB>);
+    case 2: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true, false, AB>);
+    default: return reinterpret_cast<const void*>(&batch_blocked_kernel<T, R, true, true, AB>);
   }
+}
+
+template <int T, int R>
+const void* batch_blocked_ptr(bool sc, bool pu, bool ab) {
+  return ab ? batch_blocked_terms<T, R, true>(sc, pu) : batch_blocked_terms<T, R, false>(sc, pu);
 }
 
 // The blocked batch kernel for T steps and R rows per thread (null if not
 // offered): the depths and row counts the single-chamber kernel offers.
-const void* batch_blocked(int T, int R, bool sc, bool pu) {
+const void* batch_blocked(int T, int R, bool sc, bool pu, bool ab) {
   switch (T * 16 + R) {
-    case 2 * 16 + 3: return batch_blocked_ptr<2, 3>(sc, pu);
-    case 2 * 16 + 4: return batch_blocked_ptr<2, 4>(sc, pu);
-    case 2 * 16 + 5: return batch_blocked_ptr<2, 5>(sc, pu);
-    case 2 * 16 + 6: return batch_blocked_ptr<2, 6>(sc, pu);
-    case 3 * 16 + 3: return batch_blocked_ptr<3, 3>(sc, pu);
-    case 3 * 16 + 4: return batch_blocked_ptr<3, 4>(sc, pu);
-    case 3 * 16 + 5: return batch_blocked_ptr<3, 5>(sc, pu);
-    case 3 * 16 + 6: return batch_blocked_ptr<3, 6>(sc, pu);
-    case 4 * 16 + 3: return batch_blocked_ptr<4, 3>(sc, pu);
-    case 4 * 16 + 4: return batch_blocked_ptr<4, 4>(sc, pu);
-    case 4 * 16 + 5: return batch_blocked_ptr<4, 5>(sc, pu);
-    case 4 * 16 + 6: return batch_blocked_ptr<4, 6>(sc, pu);
+    case 2 * 16 + 3: return batch_blocked_ptr<2, 3>(sc, pu, ab);
+    case 2 * 16 + 4: return batch_blocked_ptr<2, 4>(sc, pu, ab);
+    case 2 * 16 + 5: return batch_blocked_ptr<2, 5>(sc, pu, ab);
+    case 2 * 16 + 6: return batch_blocked_ptr<2, 6>(sc, pu, ab);
+    case 3 * 16 + 3: return batch_blocked_ptr<3, 3>(sc, pu, ab);
+    case 3 * 16 + 4: return batch_blocked_ptr<3, 4>(sc, pu, ab);
+    case 3 * 16 + 5: return batch_blocked_ptr<3, 5>(sc, pu, ab);
+    case 3 * 16 + 6: return batch_blocked_ptr<3, 6>(sc, pu, ab);
+    case 4 * 16 + 3: return batch_blocked_ptr<4, 3>(sc, pu, ab);
+    case 4 * 16 + 4: return batch_blocked_ptr<4, 4>(sc, pu, ab);
+    case 4 * 16 + 5: return batch_blocked_ptr<4, 5>(sc, pu, ab);
+    case 4 * 16 + 6: return batch_blocked_ptr<4, 6>(sc, pu, ab);
     default: return nullptr;
   }
 }
@@ -228,8 +233,7 @@ hipError_t add_batch_pass_node(hipGraph_t graph, hipGraphNode_t dep, hipGraphNod
   const BatchInstance* inst = (const BatchInstance*)table;
   int per_xcd = (total_tiles + 7) / 8;
   int sy = 8;
-  if (T > 1 && ab) return hipErrorInvalidValue;  // the blocked pass is periodic only
-  const void* fn = T > 1 ? batch_blocked(T, R, sc, pu) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
+  const void* fn = T > 1 ? batch_blocked(T, R, sc, pu, ab) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
   if (!fn) return hipErrorInvalidValue;
   if (T > 1) sy = kBW;  // blocks of 8 waves
   // the node copies the argument values when it is added
@@ -250,8 +254,7 @@ hipError_t launch_batch_pass(const void* table, int ninst, int total_tiles, int 
   int per_xcd = (total_tiles + 7) / 8;
   const int nr = record_prev ? ninst : 0;
   int sy = 8;
-  if (T > 1 && ab) return hipErrorInvalidValue;  // the blocked pass is periodic only
-  const void* fn = T > 1 ? batch_blocked(T, R, sc, pu) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
+  const void* fn = T > 1 ? batch_blocked(T, R, sc, pu, ab) : batch_kernel(tile_y, tile_x, sc, ab, pu, &sy);
   if (!fn) return hipErrorInvalidValue;
   if (T > 1) sy = kBW;
   void* args[] = {(void*)&inst, (void*)&ninst, (void*)&total_tiles, (void*)&per_xcd, (void*)&parity};

@@ -782,27 +782,22 @@ int batch_rows(const it_chamber* ch, int ninst, const it_exec* exec) {
 }
 
 // Steps per pass of a batch: as asked, else passes of kBlockedT steps of the
-// blocked tile pass unless an instance has absorbing lateral boundaries or a
-// one-step tile option is set (then one step per launch).
-int batch_steps(const it_chamber* ch, int ninst, const it_exec* ex) {
+// blocked tile pass unless a one-step tile option is set (then one step per
+// launch).
+int batch_steps(const it_chamber*, int, const it_exec* ex) {
   const int T = requested_steps(ex);
   if (T > 0) return T;
-  for (int q = 0; q < ninst; ++q)
-    if (ch[q].lateral_bc) return 1;
   if (ex && (ex->tile_x || ex->tile_y || ex->z_chunk)) return 1;
   return kBlockedT;
 }
 
 // Checks of a batch's steps per pass: the blocked pass needs a supported
-// depth and rows and periodic lateral boundaries in every instance, and
-// takes no one-step tile width.
-int check_batch_steps(const it_chamber* ch, int ninst, const it_exec* ex, int T) {
+// depth and rows, and takes no one-step tile width.
+int check_batch_steps(const it_chamber*, int, const it_exec* ex, int T) {
   if (T < 1 || T > kMaxT) return IT_EINVAL;
   if (T == 1) return IT_OK;
   if (!blocked_supported(T, ex ? ex->tile_y : 0)) return ex && ex->tile_y ? IT_EINVAL : IT_ENOTSUP;
   if (ex && ex->tile_x) return IT_EINVAL;
-  for (int q = 0; q < ninst; ++q)
-    if (ch[q].lateral_bc) return IT_ENOTSUP;
   return IT_OK;
 }
 

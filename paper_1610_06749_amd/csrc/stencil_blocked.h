@@ -80,10 +80,11 @@ __device__ inline double lane_from_right(double v) {  // value of lane + 1
 // level's outputs once its tallies are taken (on every node the tile
 // computes, so the later levels step from them), and beta times the largest
 // owned output enters the run's max_beta_n, as a deposit does.
-// AB: absorbing lateral boundaries (R1): the tile's nodes beyond the cell
-// hold zero at every level instead of the periodic image, and each owned
-// node next to the boundary adds a_x (a_y) times its old density per missing
-// neighbour to the escaped tally of its species, as in the one-step kernel.
+// AB: honours p.absorbing (absorbing lateral boundaries, R1; a batch mixes
+// both kinds): the tile's nodes beyond the cell hold zero at every level
+// instead of the periodic image, and each owned node next to the boundary
+// adds a_x (a_y) times its old density per missing neighbour to the escaped
+// tally of its species, as in the one-step kernel.
 template <int T, int R, bool SC, bool PU = false, bool AB = false>
 __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const TileCoord tc, double* partial_out,
                                                   int add_j = 0, const double* add_p = nullptr,
@@ -109,9 +110,10 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
   bool own_y[R];    // the row is owned (wave-uniform)
   // absorbing: the node lies in the cell (else it holds zero), and the
   // missing neighbours of the lane's column and of each row
+  const bool absorbing = AB && p.absorbing;
   const int gx = x0 - T + lane;
-  const bool in_x = !AB || (gx >= 0 && gx < nx);
-  const double miss_x = AB ? (double)((gx == 0) + (gx == nx - 1)) : 0.0;
+  const bool in_x = !absorbing || (gx >= 0 && gx < nx);
+  const double miss_x = absorbing ? (double)((gx == 0) + (gx == nx - 1)) : 0.0;
   bool in_y[R];
   double miss_y[R];
 #pragma unroll
@@ -122,8 +124,8 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
     off[r] = (unsigned)(ys * nx + xs) * 8u;
     own_y[r] = tc.valid && g >= T && g < EY - T && y0 + (g - T) < ny;
     const int gy = y0 - T + g;
-    in_y[r] = !AB || (gy >= 0 && gy < ny);
-    miss_y[r] = AB ? (double)((gy == 0) + (gy == ny - 1)) : 0.0;
+    in_y[r] = !absorbing || (gy >= 0 && gy < ny);
+    miss_y[r] = absorbing ? (double)((gy == 0) + (gy == ny - 1)) : 0.0;
   }
   const int za = 1 + tc.zc * p.zc;
   const int zb = tc.valid ? min(za + p.zc, nz) : za;

@@ -51,14 +51,15 @@ def test_tune_picks_a_timed_candidate_and_caches_it(gpu, orc, tuner, tmp_path):
 
 
 def test_tune_skips_unsupported_candidates(gpu, tuner):
-    # absorbing lateral boundaries: the blocked kernel refuses them
-    ch = W.chamber(40, 24, 20, 3e-4, 20 * 3e-4, 25.0, lateral_bc=1)
-    ex = tuner.tune(ch, steps=8)
-    assert ex in tuner.PLAIN + tuner.PAIR
     # an odd nx: no tiles of column pairs
     ch = W.chamber(41, 24, 20, 3e-4, 20 * 3e-4, 25.0)
     ex = tuner.tune(ch, steps=8)
     assert ex not in tuner.PAIR
+    # absorbing lateral boundaries are tuned apart from the periodic grid of
+    # the same size (every candidate takes them)
+    tuner._memo.clear()
+    ex_a = tuner.tune(dict(ch, lateral_bc=1), steps=8)
+    assert len(tuner._memo) == 1 and ex_a in tuner.PLAIN + tuner.BLOCKED
 
 
 def test_tune_batch_returns_a_working_shape(gpu, tuner, tmp_path):

@@ -111,14 +111,17 @@ def test_batch_rejects_later_tracks(gpu):
     assert e.value.code == gpu.IT_ENOTSUP
 
 
-def test_batch_with_absorbing_boundaries_on_some_instances(gpu, orc):
-    """Absorbing and periodic lateral boundaries in one batch; tracks placed
-    near the edges so that charge escapes."""
+@pytest.mark.parametrize("ex", [dict(check_every=4), dict(kernel=1, check_every=4),
+                                dict(kernel=2, steps_per_pass=2, check_every=4)],
+                         ids=["default", "plain", "blocked2"])
+def test_batch_with_absorbing_boundaries_on_some_instances(gpu, orc, ex):
+    """Absorbing and periodic lateral boundaries in one batch (one-step and
+    blocked passes); tracks placed near the edges so that charge escapes."""
     chs, trs = small_sweep(n=5, seed=21)
     for q in (0, 2, 3):
         chs[q]["lateral_bc"] = 1
         trs[q][:, 2] = np.minimum(trs[q][:, 2], 6e-4)  # next to the x = 0 edge
-    res = gpu.it_solve_batch(chs, trs, exec=dict(check_every=4))
+    res = gpu.it_solve_batch(chs, trs, exec=ex)
     for ch, tr, g in zip(chs, trs, res):
         o = orc.solve(ch, tr, with_fields=False)
         assert g["steps"] == o["steps"] and g["flags"] == o["flags"]
@@ -135,7 +138,7 @@ def test_batch_blocked_rebuilds_match_oracle(gpu, orc, T):
     soon as a quarter of the instances stop, so the pass before each rebuild
     is recorded by the first pass after it, with the tile count the run
     state carries; every instance still matches the oracle.  (These small
-    chambers never fill the machine, so the chunk stays at its 4T minimum;
+    chambers never fill the machine, so the chunks are short from the start;
     the 96-chamber sweep against its stored results covers chunks that
     change at rebuilds.)"""
     chs, trs = small_sweep(n=9, seed=33)
