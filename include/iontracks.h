@@ -85,7 +85,7 @@ extern "C" {
 
 /* Chamber, field, transport constants and run control. */
 typedef struct {
-  int32_t nx, ny;       /* transverse node counts (>= 1), periodic */
+  int32_t nx, ny;       /* transverse node counts (>= 1), periodic unless lateral_bc = 1 */
   int32_t nz;           /* gap intervals (>= 2): interior planes 1..nz-1 */
   int32_t space_charge; /* 1: include the space-charge screening term mu n div E of eq.
                          * theEquation, with div E = q (n+ - n-)/eps0 at each node
@@ -209,7 +209,7 @@ typedef struct {
 
 /* Kernel selection for the stepping.  NULL means "defaults". */
 #define IT_KERNEL_AUTO 0     /* the library's choice: passes of 3 fused steps (the blocked kernel)
-                              * on periodic grids of at least 4e6 interior nodes, 64 x 32 nodes
+                              * on grids of at least 4e6 interior nodes, 64 x 32 nodes
                               * per plane or more, when no final fields are asked for and no
                               * one-step tile option is set; else one step per launch.  A
                               * steps_per_pass > 0 is taken as given. */
