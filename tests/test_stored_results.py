@@ -32,7 +32,7 @@ def test_single_track_reproduces(orc):
     assert np.array_equal(r["trace"], np.asarray(g["trace"]))
 
 
-@pytest.mark.parametrize("q", [94, 18, 91])
+@pytest.mark.parametrize("q", [94, 18, 91, 93, 86])
 def test_sweep_instances_reproduce(orc, q):
     g = load(f"sweep_{q:03d}")
     assert g["instance"] == q
