@@ -275,6 +275,7 @@ __device__ __forceinline__ void blocked_tile_pass(const StepParams& p, const Til
         const gchar* pn = uniform_ptr(add_n + (size_t)q * plane);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+          if (AB && !(in_x && in_y[r])) continue;  // beyond an absorbing boundary: stays zero
           np[r] += *(const gdouble*)(pp + off[r]);
           nn[r] += *(const gdouble*)(pn + off[r]);
           if (counted && own_y[r] && own_x) add_max = fmax(add_max, fmax(np[r], nn[r]));

@@ -415,6 +415,19 @@ def test_absorbing_ragged_case(gpu, orc, ex):
     compare_fields(g["neg"], o["neg"])
 
 
+@pytest.mark.parametrize("ex", [dict(kernel=1, tile_y=8), dict(kernel=2, steps_per_pass=3)], ids=["plain8", "blocked3"])
+def test_absorbing_with_space_charge(gpu, orc, ex):
+    """Both options at once: the escaped and the space-charge tallies of every
+    step, and the fields after a run cut by max_steps."""
+    ch, tr = ragged_case(max_steps=60, stop_tol=0.0)
+    ch = dict(ch, lateral_bc=1, space_charge=1)
+    tr[0, 2], tr[0, 3] = 2e-4, 1e-4          # parallel track at the corner
+    g, o = run_both(gpu, orc, ch, tr, exec=ex)
+    assert o["n_escaped_pos"] > 0.0 and np.any(o["trace"][:, 10] != 0.0)
+    compare_fields(g["pos"], o["pos"])
+    compare_fields(g["neg"], o["neg"])
+
+
 @pytest.mark.parametrize("ex", AB_EXECS, ids=AB_IDS)
 def test_absorbing_advance_from_given_fields(gpu, orc, ex):
     import torch

@@ -173,20 +173,24 @@ def test_batch_with_short_period_refuses_blocked_passes(gpu):
 def blocked_train_sweep(T):
     """Trains whose periods are T, T + 1, 2T + 1 and 13 steps (at most one
     pulse in a pass of T steps; a period of exactly T puts a pulse on the
-    same level of every pass), single pulses, a train with space charge and
-    one cut by max_steps before its last pulse."""
+    same level of every pass), single pulses, a train with space charge, one
+    with absorbing lateral boundaries and a track at the x = 0 edge, and one
+    cut by max_steps before its last pulse."""
     rng = np.random.default_rng(91)
     chs, trs = [], []
     periods = [T, 0, T + 1, 2 * T + 1, 13, 0, T + 1, T]
     for q, m in enumerate(periods):
         nx, ny, nz = int(rng.integers(24, 90)), int(rng.integers(14, 60)), int(rng.integers(8, 36))
         ch = W.chamber(nx, ny, nz, 3e-4, nz * 3e-4, float(rng.uniform(15, 60)),
-                       uniform_n0=float(rng.uniform(5e8, 4e9)), space_charge=1 if q == 6 else 0)
+                       uniform_n0=float(rng.uniform(5e8, 4e9)), space_charge=1 if q == 6 else 0,
+                       lateral_bc=1 if q == 4 else 0)
         k = int(rng.integers(1, 5))
         lx, ly = nx * 3e-4, ny * 3e-4
         tr = W.tracks(np.stack([rng.uniform(2, 20, k), rng.uniform(6e-4, 1.2e-3, k), rng.uniform(0, lx, k),
                                 rng.uniform(0, ly, k), rng.uniform(0, 0.6, k), rng.uniform(0, 6.2, k),
                                 np.zeros(k)], axis=1))
+        if q == 4:
+            tr[0, 2] = 3e-4  # next to the absorbing x = 0 edge
         if m:
             ch = train(ch, 6, (m - 0.5) * single_pulse_dt(ch, tr))  # ceil gives m steps a period
         if q == 7:
