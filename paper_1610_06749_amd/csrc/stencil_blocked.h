@@ -78,10 +78,11 @@ __device__ inline double lane_from_right(double v) {  // value of lane + 1
 // PU: with add_j in 1..T (block-uniform), a pulse of a pulse train falls due
 // after the step of level add_j: the densities add_p and add_n join that
 // level's outputs once its tallies are taken (on every node the tile
-// computes, so the later levels step from them), and beta times the largest
-// owned output enters the run's max_beta_n, as a deposit does.
-// AB: honours p.absorbing (absorbing lateral boundaries, R1; a batch mixes
-// both kinds): the tile's nodes beyond the cell hold zero at every level
+// computes but those beyond an absorbing boundary, so the later levels step
+// from them), and beta times the largest owned output enters the run's
+// max_beta_n, as a deposit does.
+// AB: honours p.absorbing (absorbing lateral boundaries; a batch mixes both
+// kinds): the tile's nodes beyond the cell hold zero at every level
 // instead of the periodic image, and each owned node next to the boundary
 // adds a_x (a_y) times its old density per missing neighbour to the escaped
 // tally of its species, as in the one-step kernel.
