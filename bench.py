@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
     ap.add_argument("--surrogate-train", type=int, default=32768, help="surrogate training samples")
     ap.add_argument("--surrogate-steps", type=int, default=600000, help="surrogate training steps")
+    ap.add_argument("--surrogate-overlap", type=int, default=4096,
+                    help="extra surrogate training samples from the deep pulse-train part of the box")
     ap.add_argument("--continuous-ms", type=float, default=0.4,
                     help="beam-on time of the continuous-beam run (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -375,7 +377,7 @@ def main():
         # the answer timed at the default spread tolerance (1e-3 in ln k_s) and,
         # for the trade-off, at tighter and looser ones
         sur = surrogate.evaluate(n_train=a.surrogate_train, steps=a.surrogate_steps, log=progress,
-                                 extra_tols=(5e-4, 2e-3, 4e-3), time_extra=True)
+                                 extra_tols=(5e-4, 2e-3, 4e-3), time_extra=True, n_overlap=a.surrogate_overlap)
 
     out = {
         "metric": METRIC,

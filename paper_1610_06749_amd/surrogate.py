@@ -91,6 +91,19 @@ def solver_lnks(X, group=512, stream=None, log=None):
     return out, vs, time.perf_counter() - t0
 
 
+def minibatch_order(n, batch, seed):
+    """Row order and minibatch size for training on n rows: one shuffle of
+    the rows, continued from its start up to the next multiple of ``batch``
+    (the library's minibatches tile the data it is given), so that every
+    row is used and fewer than ``batch`` of them twice per pass; a full
+    batch (0) when ``batch`` is not positive or not below n."""
+    perm = np.random.default_rng(seed).permutation(n)
+    if batch <= 0 or batch >= n:
+        return perm, 0
+    pad = -n % batch
+    return np.concatenate([perm, perm[:pad]]), batch
+
+
 class Surrogate:
     def __init__(self, members=4, seed=W.SEED_BASE + 5 if W else 0, precision=B.IT_MLP_FP32):
         self.members = members
@@ -102,7 +115,8 @@ class Surrogate:
         """Standardisation from the training inputs (log space), training box
         with a small margin, targets standardised around the residual; then
         ``steps`` Adam steps on minibatches of ``batch`` rows of the data
-        shuffled once, the rate decaying from lr to lr_final (half cosine)."""
+        shuffled once (``minibatch_order``), the rate decaying from lr to
+        lr_final (half cosine)."""
         import torch
         X = np.asarray(X, dtype=np.float64)
         lnks = np.asarray(lnks, dtype=np.float64)
@@ -120,10 +134,7 @@ class Surrogate:
         resid = lnks - base
         norm = np.concatenate([mu, sd, Z.min(0) - margin, Z.max(0) + margin, [resid.mean(), resid.std()]])
         B.it_mlp_init(self.model, self.members, params, norm, phys_constants(), precision=self.precision)
-        n = len(X)
-        if batch <= 0 or batch >= n or n % batch:
-            batch = 0  # full batch
-        perm = np.random.default_rng(self.seed + 1).permutation(n)
+        perm, batch = minibatch_order(len(X), batch, self.seed + 1)
         Xd = torch.tensor(X[perm], dtype=torch.float32, device="cuda")
         td = torch.tensor(lnks[perm], dtype=torch.float32, device="cuda")
         t0 = time.perf_counter()
@@ -131,7 +142,7 @@ class Surrogate:
                                        lr_final=lr_final)
         self.train_seconds = time.perf_counter() - t0
         self.train_steps = steps
-        self.batch = batch or n
+        self.batch = batch or len(X)
         return self
 
     def query(self, Xq, spread_tol):
@@ -160,12 +171,18 @@ class Surrogate:
         return lnks, mask
 
 
-def solver_data(n_train=32768, n_hold=1024, seed=None, log=None):
+def solver_data(n_train=32768, n_hold=1024, seed=None, log=None, n_overlap=0, min_overlap=3.0):
     """Training and held-out data from the solver: a dict of the inputs,
-    ln k_s, voxel-steps and seconds of each set.  Rows the solver could not
-    compute (non-finite) are left out and counted (``*_nonfinite``)."""
+    ln k_s, voxel-steps and seconds of each set.  ``n_overlap`` more
+    training rows come from the deep pulse-train part of the box (rate x
+    twice the slower ion's transit at least ``min_overlap``,
+    ``workloads.surrogate_inputs_overlapping``); the held-out rows stay
+    uniform.  Rows the solver could not compute (non-finite) are left out
+    and counted (``*_nonfinite``)."""
     base_seed = W.SEED_BASE + 5 if seed is None else seed
     Xtr = W.surrogate_inputs(base_seed, n_train)
+    if n_overlap:
+        Xtr = np.concatenate([Xtr, W.surrogate_inputs_overlapping(base_seed + 3, n_overlap, min_overlap)])
     ytr, vs_tr, sec_tr = solver_lnks(Xtr, log=log)
     Xh = W.surrogate_inputs(base_seed + 1, n_hold)
     yh, vs_h, sec_h = solver_lnks(Xh, log=log)
@@ -175,9 +192,11 @@ def solver_data(n_train=32768, n_hold=1024, seed=None, log=None):
 
 
 def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members=4, steps=600000, seed=None,
-             precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None, time_extra=False):
-    """The surrogate experiment: train on n_train solver runs, check on
-    n_hold held-out solver runs, time n_query queries (``data`` from
+             precision=B.IT_MLP_FP32, data=None, extra_tols=(5e-4,), log=None, time_extra=False, n_overlap=0):
+    """The surrogate experiment: train on n_train solver runs (plus
+    ``n_overlap`` from the deep pulse-train part of the box, see
+    ``solver_data``), check on n_hold held-out solver runs, time n_query
+    uniform queries (``data`` from
     ``solver_data`` reuses solver runs).  The figures are taken at the
     spread tolerance ``spread_tol``, where the queries are also answered end
     to end (the query plus the solver on the queries it flags, timed
@@ -187,7 +206,7 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
     taking a progress message.  Returns a dict."""
     import torch
     say = log or (lambda msg: None)
-    d = data if data is not None else solver_data(n_train, n_hold, seed, log=log)
+    d = data if data is not None else solver_data(n_train, n_hold, seed, log=log, n_overlap=n_overlap)
     base_seed = d["seed"]
     Xtr, ytr, vs_tr, sec_tr = d["Xtr"], d["ytr"], d["vs_tr"], d["sec_tr"]
     Xh, yh, sec_h = d["Xh"], d["yh"], d["sec_h"]
@@ -254,7 +273,8 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
 
     rel, acc, main = at_tol(spread_tol, True)
     res = {
-        "n_train": n_train, "n_holdout": n_hold, "n_query": n_query, "members": members,
+        "n_train": n_train, "n_train_overlap": int(np.sum([W.surrogate_overlap(x) >= 3.0 for x in Xtr])),
+        "n_holdout": n_hold, "n_query": n_query, "members": members,
         "train_nonfinite": d.get("train_nonfinite", 0), "holdout_nonfinite": d.get("holdout_nonfinite", 0),
         "precision": "fp32" if precision == B.IT_MLP_FP32 else "bf16",
         "train_data_seconds": sec_tr, "train_data_voxel_steps": vs_tr, "train_seconds": s.train_seconds,

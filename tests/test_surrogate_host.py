@@ -63,3 +63,30 @@ def test_solver_data_leaves_nonfinite_rows_out(sur, monkeypatch):
     assert d["train_nonfinite"] == 1 and d["holdout_nonfinite"] == 0
     assert len(d["Xtr"]) == 7 and np.all(np.isfinite(d["ytr"]))
     assert not np.any(np.all(d["Xtr"] == Xtr[3], axis=1))
+
+
+@pytest.mark.parametrize("n,batch", [(45055, 2048), (32768, 2048), (4097, 512), (300, 512), (300, 0)])
+def test_minibatch_order_tiles_every_row(n, batch):
+    from paper_1610_06749_amd import surrogate
+    order, b = surrogate.minibatch_order(n, batch, 11)
+    if batch <= 0 or batch >= n:
+        assert b == 0 and np.array_equal(np.sort(order), np.arange(n))
+        return
+    assert b == batch and len(order) % batch == 0 and len(order) - n < batch
+    assert np.array_equal(np.sort(order[:n]), np.arange(n))  # one full shuffle first
+    assert np.array_equal(order[n:], order[: len(order) - n])  # then its start again
+
+
+def test_overlapping_inputs_are_deep_trains_of_the_box():
+    X = W.surrogate_inputs_overlapping(7, 500, min_overlap=3.0)
+    assert X.shape == (500, 6)
+    ov = np.array([W.surrogate_overlap(x) for x in X])
+    assert ov.min() >= 3.0
+    for j, (lo, hi) in enumerate(W.SURROGATE_RANGES):
+        assert X[:, j].min() >= lo and X[:, j].max() <= hi
+    # a train of ceil(overlap) + 1 pulses for every row
+    for x, o in zip(X[:20], ov[:20]):
+        n, P = W.surrogate_train(x)
+        assert n == math.ceil(o) + 1 and P == pytest.approx(1.0 / x[5])
+    # the same seed, the same rows
+    assert np.array_equal(X, W.surrogate_inputs_overlapping(7, 500, min_overlap=3.0))

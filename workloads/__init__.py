@@ -302,6 +302,28 @@ def surrogate_inputs(seed: int, n: int) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
+def surrogate_overlap(x) -> float:
+    """How many pulse periods the ions of one pulse stay in flight for a
+    surrogate sample: rate x T with T = 2 d^2 / (min(mu+, mu-) V) as in
+    surrogate_train (below 1 the sample is a single pulse)."""
+    V, d, rate = float(x[2]), float(x[3]), float(x[5])
+    return rate * 2.0 * d * d / (min(AIR["mu_pos"], AIR["mu_neg"]) * V)
+
+
+def surrogate_inputs_overlapping(seed: int, n: int, min_overlap: float = 3.0) -> np.ndarray:
+    """n input rows drawn as surrogate_inputs draws them, kept only where
+    surrogate_overlap is at least min_overlap (deep pulse trains), by
+    rejection in the order drawn."""
+    rng_seed, out, have = seed, [], 0
+    while have < n:
+        X = surrogate_inputs(rng_seed, max(4 * n, 4096))
+        keep = X[np.array([surrogate_overlap(x) >= min_overlap for x in X])]
+        out.append(keep)
+        have += len(keep)
+        rng_seed += 7919
+    return np.concatenate(out)[:n]
+
+
 def surrogate_train(x):
     """Pulse train of a surrogate sample, (n_pulses, period): with the
     pulse period P = 1 / rate at least T = 2 d^2 / (min(mu+, mu-) V), twice
