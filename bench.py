@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--no-pulsed", action="store_true", help="skip the pulsed-beam runs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 96-chamber sweep")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate experiment")
-    ap.add_argument("--surrogate-train", type=int, default=32768, help="surrogate training samples")
+    ap.add_argument("--surrogate-train", type=int, default=32768, help="surrogate training samples uniform over the input box")
     ap.add_argument("--surrogate-steps", type=int, default=600000, help="surrogate training steps")
     ap.add_argument("--surrogate-overlap", type=int, default=4096,
                     help="extra surrogate training samples from the deep pulse-train part of the box")
