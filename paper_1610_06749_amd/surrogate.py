@@ -273,6 +273,7 @@ def evaluate(n_train=32768, n_hold=1024, n_query=65536, spread_tol=1e-3, members
 
     rel, acc, main = at_tol(spread_tol, True)
     res = {
+        # training rows holding three or more pulses in flight (deep trains)
         "n_train": n_train, "n_train_overlap": int(np.sum([W.surrogate_overlap(x) >= 3.0 for x in Xtr])),
         "n_holdout": n_hold, "n_query": n_query, "members": members,
         "train_nonfinite": d.get("train_nonfinite", 0), "holdout_nonfinite": d.get("holdout_nonfinite", 0),
