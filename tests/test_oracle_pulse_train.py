@@ -84,11 +84,13 @@ def test_train_rejects_late_tracks_and_bad_periods(orc):
             orc.solve(_train(ch, 3, P), None)
 
 
-def test_superposition_without_recombination(orc):
+@pytest.mark.parametrize("lateral_bc", [0, 1])
+def test_superposition_without_recombination(orc, lateral_bc):
     """alpha = 0 (and no space charge) makes the stepping linear, so the
     train's final fields are the sum over pulses k of the pulse advanced
-    alone from its step k m to the end, N m - k m steps."""
-    ch = _small(nz=20, n0=2e9, alpha=0.0)
+    alone from its step k m to the end, N m - k m steps; on a periodic
+    cell and on an absorbing one."""
+    ch = _small(nz=20, n0=2e9, alpha=0.0, lateral_bc=lateral_bc)
     tr = W.tracks([[30.0, 1e-3, 2 * 2.5e-4, 3 * 2.5e-4, 0.5, 1.1, 0.0]])
     dt1 = _dt1(orc, ch, tr)
     n, P = 4, 9.4 * dt1
@@ -107,6 +109,37 @@ def test_superposition_without_recombination(orc):
     assert np.max(np.abs(r["pos"] - sp)) <= 1e-12 * scale
     assert np.max(np.abs(r["neg"] - sn)) <= 1e-12 * scale
     assert r["f_R"] == 1.0 and r["period_recombined"] == 0.0
+
+
+def test_absorbing_train_balances_with_escape(orc):
+    """A train on an absorbing cell (the lateral option with pulses): over
+    the whole run, what the pulses released is collected, escapes through
+    the sides, recombines (one of each sign per pair) or is still in
+    flight; the escape is the per-step escaped column summed; the last
+    period's f falls below its f_R by what escapes in it, and the same
+    train on a periodic cell escapes nothing."""
+    ch = _small(nz=24, n0=2e9, V=30.0, gap=0.06, lateral_bc=1)
+    tr = W.tracks([[2.0, 1e-3, 0.3e-4, 0.2e-4, 0.0, 0.0, 0.0]])
+    T = ch["gap"] ** 2 / (min(AIR["mu_pos"], AIR["mu_neg"]) * ch["voltage"])
+
+    def balance(r):
+        col = r["col_pos_anode"] + r["col_pos_cathode"] + r["col_neg_anode"] + r["col_neg_cathode"]
+        esc = r["n_escaped_pos"] + r["n_escaped_neg"]
+        inflight = r["n_inflight_pos"] + r["n_inflight_neg"]
+        released = r["n_released"] + r["n_released_neg"]
+        assert col + esc + 2 * r["n_recombined"] + inflight == pytest.approx(released, rel=1e-10)
+        return esc / released
+
+    r = orc.solve(_train(ch, 6, T / 3.0), tr, with_trace=True, with_fields=False)
+    assert r["flags"] == 0 and r["pulses"] == 6
+    assert balance(r) > 1e-3
+    assert r["n_escaped_pos"] == pytest.approx(r["trace"][:, 13].sum(), rel=1e-12)
+    assert r["n_escaped_neg"] == pytest.approx(r["trace"][:, 14].sum(), rel=1e-12)
+    assert r["f"] < r["f_R"] - 1e-3
+    rp = orc.solve(_train(dict(ch, lateral_bc=0), 6, T / 3.0), tr, with_fields=False)
+    assert rp["flags"] == 0 and rp["pulses"] == 6 and rp["dt"] == r["dt"]
+    assert rp["n_escaped_pos"] == 0.0 and rp["n_escaped_neg"] == 0.0
+    assert balance(rp) == 0.0
 
 
 def test_pulses_that_never_overlap_match_the_single_pulse(orc):
