@@ -863,19 +863,25 @@ def _dense_step_absorbing(ch, dt, pos, neg):
     backward = (Iz - down) / dz
     central = (up - down) / (2 * dz)
     P, N = pad(pos), pad(neg)
-    out, esc = [], []
+    out, esc, sc = [], [], []
     for s, (mu, D, sign) in enumerate([(ch["mu_pos"], ch["D_pos"], 1.0), (ch["mu_neg"], ch["D_neg"], -1.0)]):
         v = sign * mu * E
         c = v * dt / dz
         Dz = np.kron(np.kron(c * backward + (1 - c) * central, Iy), Ix)
         M = np.eye((nz + 1) * Y * X) + dt * (D * (Dxx + Dyy + Dzz) - v * Dz)
         n_new = (M @ (P, N)[s].ravel() - ch["alpha"] * dt * P.ravel() * N.ravel()).reshape(nz + 1, Y, X)
+        if ch.get("space_charge", 0):
+            # the local screening term of each species, -+ mu dt (q/eps0) n (n+ - n-),
+            # zero on the ghosts, so it changes no escape
+            sc_term = -sign * mu * dt * Q_OVER_EPS0 * (P, N)[s] * (P - N)
+            n_new += sc_term
+            sc.append(sc_term[1:nz, 1:-1, 1:-1].sum() * dx * dy * dz)
         ghost = n_new[1:nz].sum() - n_new[1:nz, 1:-1, 1:-1].sum()
         esc.append(ghost * dx * dy * dz)
         out.append(n_new[:, 1:-1, 1:-1].copy())
         out[-1][0] = 0.0
         out[-1][nz] = 0.0
-    return out[0], out[1], esc
+    return out[0], out[1], esc, sc
 
 
 @pytest.mark.parametrize("geom", [(4, 4, 5), (3, 5, 2), (1, 1, 7), (6, 2, 4)])
@@ -886,7 +892,7 @@ def test_absorbing_step_matches_dense_matrix_scheme(orc, geom):
     dt = orc.dt(ch)
     pos, neg = W.perturbed_field((nz + 1, ny, nx), seed=8, scale=3e11)
     p1, n1, tally = orc.step(ch, dt, pos, neg)
-    p2, n2, esc = _dense_step_absorbing(ch, dt, pos, neg)
+    p2, n2, esc, _ = _dense_step_absorbing(ch, dt, pos, neg)
     scale = max(np.abs(pos).max(), np.abs(neg).max())
     assert np.max(np.abs(p1 - p2)) <= 1e-14 * scale
     assert np.max(np.abs(n1 - n2)) <= 1e-14 * scale
@@ -894,6 +900,30 @@ def test_absorbing_step_matches_dense_matrix_scheme(orc, geom):
     assert esc[0] > 0 and esc[1] > 0
     assert tally["pos_escaped"] == pytest.approx(esc[0], abs=1e-13 * tot)
     assert tally["neg_escaped"] == pytest.approx(esc[1], abs=1e-13 * tot)
+
+
+@pytest.mark.parametrize("geom", [(4, 4, 5), (3, 5, 2), (6, 2, 4)])
+def test_absorbing_step_with_space_charge_matches_dense_matrix_scheme(orc, geom):
+    """Both options at once: the absorbing transport of the dense ghost-node
+    scheme plus the local screening term of each species; escape and
+    space-charge tallies from the same sums."""
+    nx, ny, nz = geom
+    ch = W.chamber(nx, ny, nz, 3e-4, nz * 2.5e-4, 40.0, dy=4e-4, D_pos=0.03, D_neg=0.05,
+                   alpha=1.6e-6, lateral_bc=1, space_charge=1)
+    dt = orc.dt(ch)
+    pos, neg = W.perturbed_field((nz + 1, ny, nx), seed=9, scale=3e11)
+    p1, n1, tally = orc.step(ch, dt, pos, neg)
+    p2, n2, esc, sc = _dense_step_absorbing(ch, dt, pos, neg)
+    p0, n0, _, _ = _dense_step_absorbing(dict(ch, space_charge=0), dt, pos, neg)
+    scale = max(np.abs(pos).max(), np.abs(neg).max())
+    assert np.max(np.abs(p2 - p0)) > 1e-4 * scale  # the screening term matters here
+    assert np.max(np.abs(p1 - p2)) <= 1e-14 * scale
+    assert np.max(np.abs(n1 - n2)) <= 1e-14 * scale
+    tot = (pos.sum() + neg.sum()) * ch["dx"] * ch["dy"] * ch["gap"] / nz
+    assert tally["pos_escaped"] == pytest.approx(esc[0], abs=1e-13 * tot)
+    assert tally["neg_escaped"] == pytest.approx(esc[1], abs=1e-13 * tot)
+    assert tally["pos_space_charge"] == pytest.approx(sc[0], abs=1e-13 * tot)
+    assert tally["neg_space_charge"] == pytest.approx(sc[1], abs=1e-13 * tot)
 
 
 def test_absorbing_pure_diffusion_eigenmode(orc):
