@@ -142,6 +142,33 @@ def test_absorbing_train_balances_with_escape(orc):
     assert balance(rp) == 0.0
 
 
+@pytest.mark.parametrize("lateral_bc", [0, 1])
+def test_train_with_space_charge_balances_step_by_step(orc, lateral_bc):
+    """Every step of a train with the space-charge term (periodic and
+    absorbing cells): each species' charge in flight changes by what was
+    released before the step (each pulse at the start of its period's
+    first step), minus what reached either electrode, recombined or
+    escaped, plus the screening term's change; the released column sums
+    to the run's release and holds exactly the pulse steps."""
+    ch = _small(nz=24, n0=2e9, V=30.0, gap=0.06, lateral_bc=lateral_bc, space_charge=1)
+    tr = W.tracks([[2.0, 1e-3, 0.3e-4, 0.2e-4, 0.0, 0.0, 0.0]])
+    T = ch["gap"] ** 2 / (min(AIR["mu_pos"], AIR["mu_neg"]) * ch["voltage"])
+    n = 5
+    r = orc.solve(_train(ch, n, T / 3.0), tr, with_trace=True, with_fields=False)
+    assert r["flags"] == 0 and r["pulses"] == n
+    t = r["trace"]
+    m = r["steps"] // n
+    assert np.array_equal(np.flatnonzero(t[:, 9]), np.arange(n) * m)
+    assert t[:, 9].sum() == pytest.approx(r["n_released"], rel=1e-14)
+    assert t[:, 12].sum() == pytest.approx(r["n_released_neg"], rel=1e-14)
+    assert r["n_space_charge_pos"] != 0.0 and r["n_space_charge_neg"] != 0.0
+    for a, c, S, Q, rel, X in ((1, 2, 5, 10, 9, 13), (3, 4, 6, 11, 12, 14)):
+        prev = np.concatenate([[0.0], t[:-1, S]]) + t[:, rel]
+        err = prev - t[:, a] - t[:, c] - t[:, 0] + t[:, Q] - t[:, X] - t[:, S]
+        assert np.max(np.abs(err)) <= 1e-12 * r["n_released"]
+    assert (r["n_escaped_pos"] > 0.0) == bool(lateral_bc)
+
+
 def test_pulses_that_never_overlap_match_the_single_pulse(orc):
     """A period several collection times long: each pulse is collected
     before the next arrives, so the last period's f is the single pulse's
