@@ -1,0 +1,165 @@
+"""The oracle's pins catch plausible mistakes in it.
+
+Each case compiles a copy of ``oracle/oracle.c`` with one mistake planted
+(a one-line slip: a dropped factor, a flipped sign, a wrong index or
+neighbour, a unit slip), loads that copy in place of the oracle for the
+length of the case, and requires every pin named for the mistake to fail.
+The same pins pass on the oracle itself (the control case, and the pin
+files).  Nothing here touches the committed oracle or its built library.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as P
+import test_oracle_pulse_train as PT
+
+SRC = os.path.join(os.path.dirname(os.path.abspath(oracle.__file__)), "oracle.c")
+
+
+def dense(orc):
+    P.test_one_step_matches_dense_matrix_scheme(orc, (4, 4, 5))
+
+
+def dense_absorbing(orc):
+    P.test_absorbing_step_matches_dense_matrix_scheme(orc, (4, 4, 5))
+
+
+def dense_absorbing_sc(orc):
+    P.test_absorbing_step_with_space_charge_matches_dense_matrix_scheme(orc, (4, 4, 5))
+
+
+def diffusion_moments(orc):
+    P.test_pure_diffusion_moments_exact(orc)
+
+
+def drift_moments(orc):
+    P.test_drift_diffusion_moments_exact(orc)
+
+
+def dt_value(orc):
+    P.test_dt_single_track_value(orc)
+
+
+def released_count(orc):
+    P.test_released_count_matches_poisson_summation(orc, 1.0, 0.37)
+
+
+def released_count_wide(orc):
+    # a track as wide as the cell: the lattice sum sees the periodic images
+    P.test_released_count_matches_poisson_summation(orc, 5.0, 0.0)
+
+
+def gaussian_profile(orc):
+    P.test_deposit_profile_is_gaussian_in_perpendicular_distance(orc)
+
+
+def space_charge_map(orc):
+    P.test_space_charge_pointwise_map(orc)
+
+
+def absorbing_balance(orc):
+    P.test_absorbing_conservation_and_escape(orc)
+
+
+def boag(orc):
+    P.test_boag_pulsed_general_recombination(orc, 1.0)
+
+
+def train_periods(orc):
+    PT.test_train_steps_whole_periods(orc)
+
+
+def train_superposition(orc):
+    PT.test_superposition_without_recombination(orc, 0)
+
+
+# name: (text in oracle.c, its replacement, occurrence to change, pins that must fail)
+MUTANTS = {
+    "x diffusion weight halved": (
+        "w[1] = D * dt / (p[P_DX] * p[P_DX]);", "w[1] = 0.5 * D * dt / (p[P_DX] * p[P_DX]);", 1,
+        [dense, diffusion_moments]),
+    "negative ions drift with the positive ones": (
+        "const double v = s == 0 ? mu * E : -mu * E;", "const double v = s == 0 ? mu * E : mu * E;", 1,
+        [dense, drift_moments]),
+    "upwind difference taken on the downwind side": (
+        "const double drift = c * (c * (nc - n[IDX(k - 1, j, i)])",
+        "const double drift = c * (c * (n[IDX(k + 1, j, i)] - nc)", 1,
+        [dense, drift_moments]),
+    "z Laplacian reads the upper neighbour twice": (
+        "const double lap_z = n[IDX(k + 1, j, i)] - 2.0 * nc + n[IDX(k - 1, j, i)];",
+        "const double lap_z = n[IDX(k + 1, j, i)] - 2.0 * nc + n[IDX(k + 1, j, i)];", 1,
+        [dense, drift_moments]),
+    "recombination sink halved": (
+        "const double sink = beta * np_ * nn_;", "const double sink = 0.5 * beta * np_ * nn_;", 1,
+        [dense, boag]),
+    "anode weight with the drift term's sign flipped": (
+        "const double w_up = sz + 0.5 * c * c - 0.5 * c;", "const double w_up = sz + 0.5 * c * c + 0.5 * c;", 1,
+        [dense]),
+    "von Neumann diffusion term without its factor 2": (
+        "const double A = 2.0 * Ds[s] * inv2;", "const double A = Ds[s] * inv2;", 1,
+        [dt_value]),
+    "LET unit slip (keV/um taken as 0.1 keV/um)": (
+        "const double N0 = tr[0] * 1.0e7 / p[P_W]; /* keV/um", "const double N0 = tr[0] * 1.0e6 / p[P_W]; /* keV/um", 1,
+        [released_count]),
+    "Gaussian exponent with 2 b^2": (
+        "return N0 / (M_PI * b * b) * exp(-r2 / (b * b));", "return N0 / (M_PI * b * b) * exp(-r2 / (2.0 * b * b));", 1,
+        [released_count, gaussian_profile]),
+    "periodic offset wrapped to [0, L) instead of the nearest image": (
+        "return d - L * floor(d / L + 0.5);", "return d - L * floor(d / L);", 1,
+        [released_count_wide]),
+    "space-charge term with the wrong sign": (
+        "const double gsc[2] = {-sc_on * p[P_MU_POS]", "const double gsc[2] = {sc_on * p[P_MU_POS]", 1,
+        [space_charge_map, dense_absorbing_sc]),
+    "escape through the y sides not tallied": (
+        "escaped[s] += (sx * miss_x + sy * miss_y) * nc;", "escaped[s] += sx * miss_x * nc;", 1,
+        [dense_absorbing, absorbing_balance]),
+    "train period one step longer than its steps": (
+        "dt = period / (double)m;", "dt = period / (double)(m + 1);", 1,
+        [train_periods]),
+    "train pulses one step late": (
+        "if (next_pulse < npulses && next_pulse * m == l) {", "if (next_pulse < npulses && next_pulse * m + 1 == l) {", 1,
+        [train_superposition]),
+    "last period opened a step after its pulse": (
+        "last_pulse = (npulses - 1) * m;", "last_pulse = (npulses - 1) * m + 1;", 1,
+        [train_periods]),
+}
+
+
+def _use_mutant(tmp_path, monkeypatch, old, new, nth):
+    src = open(SRC).read()
+    assert src.count(old) >= nth, old
+    at = -1
+    for _ in range(nth):
+        at = src.index(old, at + 1)
+    path = tmp_path / "oracle_mutant.c"
+    path.write_text(src[:at] + new + src[at + len(old):])
+    so = tmp_path / "liboracle_mutant.so"
+    subprocess.check_call(["gcc", *oracle._CFLAGS, "-o", str(so), str(path), "-lm"])
+    monkeypatch.setattr(oracle, "_LIB", str(so))
+    monkeypatch.setattr(oracle, "_libs", {})
+    monkeypatch.setattr(oracle, "_threaded", False)
+    monkeypatch.setattr(oracle, "build", lambda force=False: str(so))
+    return oracle
+
+
+def test_control_every_named_pin_passes_on_the_oracle(orc):
+    pins = {pin for *_, named in MUTANTS.values() for pin in named}
+    for pin in sorted(pins, key=lambda f: f.__name__):
+        pin(orc)
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path, monkeypatch):
+    old, new, nth, pins = MUTANTS[name]
+    orc = _use_mutant(tmp_path, monkeypatch, old, new, nth)
+    missed = []
+    for pin in pins:
+        try:
+            pin(orc)
+        except Exception:  # an assertion, or an error the mistake provokes
+            continue
+        missed.append(pin.__name__)
+    assert not missed, f"{name}: not caught by {missed}"
