@@ -68,6 +68,26 @@ def boag(orc):
     P.test_boag_pulsed_general_recombination(orc, 1.0)
 
 
+def stop_rule(orc):
+    P.test_stop_rule_first_step_below_tolerance_after_the_last_deposit(orc)
+
+
+def reaction_limit(orc):
+    P.test_reaction_limit_single_track(orc)
+
+
+def space_charge_dt(orc):
+    P.test_space_charge_dt_bound(orc)
+
+
+def electron_split(orc):
+    P.test_free_electron_initial_split(orc)
+
+
+def electron_split_field(orc):
+    P.test_free_electron_split_field_node_by_node(orc)
+
+
 def train_periods(orc):
     PT.test_train_steps_whole_periods(orc)
 
@@ -116,6 +136,30 @@ MUTANTS = {
     "escape through the y sides not tallied": (
         "escaped[s] += (sx * miss_x + sy * miss_y) * nc;", "escaped[s] += sx * miss_x * nc;", 1,
         [dense_absorbing, absorbing_balance]),
+    "stop test on the signed in-flight sums": (
+        "tally[T_POS_ABS] <= p[P_STOP_TOL] * released &&\n        tally[T_NEG_ABS] <= p[P_STOP_TOL] * released_neg)",
+        "tally[T_POS_INFLIGHT] <= p[P_STOP_TOL] * released &&\n        tally[T_NEG_INFLIGHT] <= p[P_STOP_TOL] * released_neg)", 1,
+        [stop_rule]),
+    "stop test before the last deposit": (
+        "if (!train && l >= last_deposit && tally[T_POS_ABS]", "if (!train && tally[T_POS_ABS]", 1,
+        [stop_rule]),
+    "reaction bound twice as loose": (
+        "const double dtr = rho / (rate * nref);", "const double dtr = 2.0 * rho / (rate * nref);", 1,
+        [reaction_limit]),
+    "reaction bound without the screening rate": (
+        "rate += mu_max * Q_E / EPS0;", "rate += 0.0 * mu_max * Q_E / EPS0;", 1,
+        [space_charge_dt]),
+    "attachment measured from the cathode": (
+        "const double att = -expm1(-p[P_ATTACH] * (double)k * dz);",
+        "const double att = -expm1(-p[P_ATTACH] * (double)(nz - k) * dz);", 1,
+        [electron_split_field]),
+    "free fraction without its 1/(a d)": (
+        "return x == 0.0 ? 1.0 : -expm1(-x) / x;", "return x == 0.0 ? 1.0 : -expm1(-x);", 1,
+        [electron_split]),
+    "plane of the split one off (z from plane -1)": (
+        "const double att = -expm1(-p[P_ATTACH] * (double)k * dz);",
+        "const double att = -expm1(-p[P_ATTACH] * (double)(k + 1) * dz);", 1,
+        [electron_split, electron_split_field]),
     "train period one step longer than its steps": (
         "dt = period / (double)m;", "dt = period / (double)(m + 1);", 1,
         [train_periods]),

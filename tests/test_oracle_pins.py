@@ -737,6 +737,29 @@ def test_single_interior_plane(orc):
     assert 0.0 < r["f"] <= 1.0
 
 
+def test_stop_rule_first_step_below_tolerance_after_the_last_deposit(orc):
+    """R8 read off the per-step records: the run ends at the first step at
+    or after its last deposit whose sums of |n| dV are within stop_tol of
+    each species' release.  Here the chamber already falls below the
+    tolerance before a late track arrives (the rule waits for it), and the
+    signed in-flight sums fall below it a few steps before the absolute
+    ones (the rule uses the absolute sums)."""
+    ch = W.chamber(12, 10, 16, 3e-4, 16 * 3e-4, 20.0, stop_tol=1e-3)
+    tr = W.tracks([[20.0, 8e-4, 1.8e-3, 1.5e-3, 0.0, 0.0, 0.0],
+                   [10.0, 6e-4, 1e-3, 1e-3, 0.3, 1.0, 3e-6]])
+    r = orc.solve(ch, tr, with_trace=True, with_fields=False)
+    assert r["flags"] == 0
+    t = r["trace"]
+    tol = ch["stop_tol"]
+    last = int(np.flatnonzero(t[:, 9])[-1])
+    assert last == int(math.floor(3e-6 / r["dt"]))
+    below = (t[:, 7] <= tol * r["n_released"]) & (t[:, 8] <= tol * r["n_released_neg"])
+    assert below[-1] and not below[last:-1].any()
+    assert below[:last].any()
+    signed = (t[:, 5] <= tol * r["n_released"]) & (t[:, 6] <= tol * r["n_released_neg"])
+    assert signed[last:-1].any()
+
+
 def test_max_steps_flag(orc):
     ch, tr = W.single_track(max_steps=10)
     r = orc.solve(ch, tr, with_fields=False)
@@ -780,6 +803,23 @@ def test_free_electron_initial_split(orc):
     k = np.arange(1, nz)
     col = ch["uniform_n0"] * ch["dx"] * ch["dy"] * dz * ch["nx"] * ch["ny"]
     assert r["n_released_neg"] == pytest.approx(col * np.sum(-np.expm1(-a * k * dz)), rel=1e-13)
+
+
+def test_free_electron_split_field_node_by_node(orc):
+    """Before any step (max_steps = 0) the fields hold the split itself: a
+    uniform dose gives positive ions n0 at every interior node and negative
+    ions n0 (1 - e^{-a z}) with z the node's distance from the anode, the
+    plane k = 0 that collects the negative carriers (eq.
+    ion_elec_distribution), so they grow towards the cathode."""
+    ch = _fe_chamber(0.3, 200.0)
+    r = orc.solve(dict(ch, max_steps=0), W.no_tracks(), with_fields=True)
+    assert r["steps"] == 0
+    n0, a, nz = ch["uniform_n0"], ch["attach_coeff"], ch["nz"]
+    z = np.arange(1, nz) * ch["gap"] / nz
+    expect = n0 * -np.expm1(-a * z)
+    assert np.allclose(r["neg"][1:nz], expect[:, None, None], rtol=1e-13, atol=0.0)
+    assert np.all(r["pos"][1:nz] == n0)
+    assert r["neg"][1, 0, 0] < r["neg"][nz - 1, 0, 0]
 
 
 def test_free_electron_phase_conservation(orc):
