@@ -88,6 +88,26 @@ def electron_split_field(orc):
     P.test_free_electron_split_field_node_by_node(orc)
 
 
+def deposit_step(orc):
+    P.test_track_deposited_at_floor_of_time_over_dt(orc)
+
+
+def tilted_profile(orc):
+    P.test_deposit_profile_is_gaussian_in_perpendicular_distance(orc)
+
+
+def separate_radii(orc):
+    P.test_separate_radii_conservation_and_released(orc)
+
+
+def absorbing_deposit(orc):
+    P.test_absorbing_deposit_is_the_unwrapped_profile(orc)
+
+
+def absorbing_eigenmode(orc):
+    P.test_absorbing_pure_diffusion_eigenmode(orc)
+
+
 def train_periods(orc):
     PT.test_train_steps_whole_periods(orc)
 
@@ -160,6 +180,22 @@ MUTANTS = {
         "const double att = -expm1(-p[P_ATTACH] * (double)k * dz);",
         "const double att = -expm1(-p[P_ATTACH] * (double)(k + 1) * dz);", 1,
         [electron_split, electron_split_field]),
+    "track deposited at the nearest step instead of the floor": (
+        "const double s = floor(tr[6] / dt);", "const double s = floor(tr[6] / dt + 0.5);", 1,
+        [deposit_step]),
+    "tilted axis through the anode instead of mid-gap": (
+        "const double wz = (double)k * dz - 0.5 * p[P_GAP];", "const double wz = (double)k * dz;", 1,
+        [tilted_profile]),
+    "separate radius given to the positive ions": (
+        "return s == 1 && tr[7] > 0.0 ? tr[7] : tr[1];", "return s == 0 && tr[7] > 0.0 ? tr[7] : tr[1];", 1,
+        [separate_radii]),
+    "absorbing cell still wraps the track offsets": (
+        "return p[P_LATERAL_BC] != 0.0 ? d : wrap(d, L);", "return wrap(d, L);", 1,
+        [absorbing_deposit]),
+    "absorbing cell reads the wrapped neighbour": (
+        "if (jj < 0 || jj >= ny || ii < 0 || ii >= nx) return 0.0;",
+        "if (jj < 0 || jj >= ny || ii < 0 || ii >= nx) { jj = (jj + ny) % ny; ii = (ii + nx) % nx; }", 1,
+        [dense_absorbing, absorbing_eigenmode]),
     "train period one step longer than its steps": (
         "dt = period / (double)m;", "dt = period / (double)(m + 1);", 1,
         [train_periods]),
