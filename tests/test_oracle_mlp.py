@@ -63,3 +63,37 @@ def test_forward_casts_only_round():
     # BF16 keeps 8 bits: the two differ, but only at the percent level
     assert np.max(np.abs(y1 - y0)) <= 0.05 * (1 + np.max(np.abs(y0)))
     assert np.max(np.abs(y1 - y0)) > 0
+
+
+def test_forward_and_gradient_match_a_torch_network():
+    """The reference network against the same network assembled from
+    torch's own layers (Linear, SiLU, mean squared error) in float64 on the
+    CPU, weights taken from the flat vector in the documented order, and
+    torch's autograd for the gradient: pins the layer order, the
+    activation, the output layer and the loss, which finite differences of
+    the reference itself cannot."""
+    torch = pytest.importorskip("torch")
+    Z, t = _data(48, seed=3)
+    flat = W.mlp_init(5, 1)[0].astype(np.float64)
+    flat += np.random.default_rng(6).normal(scale=0.05, size=flat.shape)
+    P = mlp.unpack(flat)
+    net = torch.nn.Sequential(
+        torch.nn.Linear(6, 128), torch.nn.SiLU(), torch.nn.Linear(128, 128), torch.nn.SiLU(),
+        torch.nn.Linear(128, 128), torch.nn.SiLU(), torch.nn.Linear(128, 1)).double()
+    with torch.no_grad():
+        for layer, (w, b) in zip((net[0], net[2], net[4], net[6]),
+                                 (("W1", "b1"), ("W2", "b2"), ("W3", "b3"), ("w4", "b4"))):
+            layer.weight.copy_(torch.tensor(P[w]).reshape(layer.weight.shape))
+            layer.bias.copy_(torch.tensor(P[b]))
+    y_t = net(torch.tensor(Z))[:, 0]
+    loss_t = torch.nn.functional.mse_loss(y_t, torch.tensor(t))
+    loss_t.backward()
+    y, _ = mlp.forward(flat, Z, cast=False)
+    loss, g = mlp.loss_and_grad(flat, Z, t, cast=False)
+    assert np.allclose(y, y_t.detach().numpy(), rtol=1e-12, atol=1e-12)
+    assert loss == pytest.approx(float(loss_t.detach()), rel=1e-12)
+    G = mlp.unpack(g)
+    for layer, (w, b) in zip((net[0], net[2], net[4], net[6]),
+                             (("W1", "b1"), ("W2", "b2"), ("W3", "b3"), ("w4", "b4"))):
+        assert np.allclose(G[w].reshape(layer.weight.shape), layer.weight.grad.numpy(), rtol=1e-10, atol=1e-14)
+        assert np.allclose(G[b], layer.bias.grad.numpy(), rtol=1e-10, atol=1e-14)

@@ -10,6 +10,7 @@ files).  Nothing here touches the committed oracle or its built library.
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -243,3 +244,36 @@ def test_pins_catch_planted_mistake(name, tmp_path, monkeypatch):
             continue
         missed.append(pin.__name__)
     assert not missed, f"{name}: not caught by {missed}"
+
+
+# The FP64 reference network (oracle/mlp.py): mistakes that keep its
+# forward pass and its analytic gradient consistent with each other, so the
+# finite-difference pin cannot see them; the torch-layer pin must.
+def _silu_steep(a):
+    return a / (1.0 + np.exp(-2.0 * a))
+
+
+def _dsilu_steep(a):
+    s = 1.0 / (1.0 + np.exp(-2.0 * a))
+    return s * (1.0 + 2.0 * a * (1.0 - s))
+
+
+def _summed_loss(original):
+    def loss_and_grad(flat, Z, t, cast=True):
+        loss, g = original(flat, Z, t, cast)
+        return loss * Z.shape[0], g * Z.shape[0]
+    return loss_and_grad
+
+
+@pytest.mark.parametrize("mistake", ["steeper activation", "summed instead of mean loss"])
+def test_reference_network_mistakes_fail_the_torch_pin(mistake, monkeypatch):
+    import test_oracle_mlp as M
+    from oracle import mlp
+    if mistake == "steeper activation":
+        monkeypatch.setattr(mlp, "silu", _silu_steep)
+        monkeypatch.setattr(mlp, "dsilu", _dsilu_steep)
+    else:
+        monkeypatch.setattr(mlp, "loss_and_grad", _summed_loss(mlp.loss_and_grad))
+    M.test_backward_matches_finite_differences()  # still self-consistent
+    with pytest.raises(AssertionError):
+        M.test_forward_and_gradient_match_a_torch_network()
