@@ -94,12 +94,26 @@ def time_exec(ch, ex, steps=64, reps=3, dt=None):
     return best / (steps * nint)
 
 
+def _kernel_options(ch):
+    """The chamber options that select another kernel instance: absorbing
+    sides ("a") and the space-charge term ("s")."""
+    return ("a" if ch.get("lateral_bc", 0) else "") + ("s" if ch.get("space_charge", 0) else "")
+
+
+def _batch_options(ch):
+    """The kernel options plus a pulse train's pulse count and period, which
+    decide the passes a batch can take (a blocked pass holds at most one
+    pulse)."""
+    opts = _kernel_options(ch)
+    if ch.get("n_pulses", 0) >= 2:
+        opts += f"p{int(ch['n_pulses'])}/{float(ch['pulse_period_s']):.9g}"
+    return opts
+
+
 def tune(ch, candidates=None, steps=64, cache=None, verbose=False):
     """Best execution choice (an ``exec`` dict for it_solve / it_advance) for
     the chamber's grid.  ``cache``: optional JSON path."""
-    # the grid, and the options that change the kernel instance
-    opts = ("a" if ch.get("lateral_bc", 0) else "") + ("s" if ch.get("space_charge", 0) else "")
-    key = f"{ch['nx']}x{ch['ny']}x{ch['nz']}{opts}@{_device_name()}"
+    key = f"{ch['nx']}x{ch['ny']}x{ch['nz']}{_kernel_options(ch)}@{_device_name()}"
     if key in _memo:
         return dict(_memo[key])
     table = _load(cache)
@@ -146,9 +160,12 @@ def batch_candidates(rows=(8,), graph_passes=(32,), z_chunks=(16,), narrow=False
 def tune_batch(chs, trs, steps=96, candidates=None, cache=None, verbose=False, **kw):
     """Best ``exec`` for it_solve_batch on these chambers among
     ``candidates`` (default: batch_candidates(**kw)), each timed on the batch
-    with every instance's step count capped at ``steps``."""
+    with every instance's step count capped at ``steps``; a choice the
+    batch does not support (IT_ENOTSUP, e.g. blocked passes for a train
+    whose period is shorter than a pass) is skipped.  Cached per grids and
+    options of the instances."""
     import torch
-    sig = "|".join(f"{c['nx']}x{c['ny']}x{c['nz']}" for c in chs)
+    sig = "|".join(f"{c['nx']}x{c['ny']}x{c['nz']}{_batch_options(c)}" for c in chs)
     key = f"batch:{len(chs)}:{hashlib.sha256(sig.encode()).hexdigest()[:12]}@{_device_name()}"
     if key in _memo:
         return dict(_memo[key])
@@ -161,7 +178,12 @@ def tune_batch(chs, trs, steps=96, candidates=None, cache=None, verbose=False, *
     timings = []
     cands = candidates if candidates is not None else batch_candidates(**kw)
     for ex in cands:
-        B.it_solve_batch(capped, trs, exec=ex)  # warm-up
+        try:
+            B.it_solve_batch(capped, trs, exec=ex)  # warm-up
+        except B.ItError as e:
+            if e.code != B.IT_ENOTSUP:
+                raise
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B.it_solve_batch(capped, trs, exec=ex)
@@ -170,6 +192,8 @@ def tune_batch(chs, trs, steps=96, candidates=None, cache=None, verbose=False, *
         timings.append((t, ex))
         if verbose:
             print(f"autotune {key}: {ex} -> {1.0 / t:.4g} voxel-steps/s", flush=True)
+    if not timings:
+        raise RuntimeError(f"no candidate execution ran on {key}")
     t_best, ex_best = min(timings, key=lambda p: p[0])
     _memo[key] = dict(ex_best)
     table[key] = {"exec": dict(ex_best), "voxel_steps_per_s": 1.0 / t_best,
