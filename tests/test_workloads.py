@@ -96,3 +96,10 @@ def test_surrogate_rate_moves_ks_and_is_continuous_at_the_train_threshold(orc):
     assert r_above["ks"] == pytest.approx(single_at_train_dt["ks"], rel=1e-9)
     assert r_above["ks"] == pytest.approx(r_below["ks"], rel=1e-4)
     assert r_fast["ks"] > 1.05 * r10["ks"]
+
+
+def test_chamber_refuses_unknown_keywords():
+    ch = W.chamber(8, 8, 6, 3e-4, 6 * 3e-4, 10.0, mu_pos=1.5, alpha=0.0)
+    assert ch["mu_pos"] == 1.5 and ch["alpha"] == 0.0
+    with pytest.raises(TypeError):
+        W.chamber(8, 8, 6, 3e-4, 6 * 3e-4, 10.0, n_pulses=3)

@@ -76,6 +76,12 @@ REACTION_LIMIT = 0.5
 def chamber(nx, ny, nz, dx, gap, voltage, dy=None, *, dt_safety=1.0, stop_tol=1e-12,
             max_steps=1_000_000, uniform_n0=0.0, space_charge=0, reaction_limit=REACTION_LIMIT,
             lateral_bc=0, **consts) -> dict:
+    """A chamber dict with air's constants (AIR), any of which ``consts``
+    may replace; other keywords are refused rather than dropped (options
+    such as a pulse train's n_pulses go into the dict afterwards)."""
+    unknown = set(consts) - set(AIR)
+    if unknown:
+        raise TypeError(f"chamber(): unknown keywords {sorted(unknown)}")
     c = dict(AIR)
     c.update(consts)
     return dict(nx=int(nx), ny=int(ny), nz=int(nz), dx=float(dx),
