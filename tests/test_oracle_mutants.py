@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_electron_phase as PE
 import test_oracle_pins as P
 import test_oracle_pulse_train as PT
 
@@ -109,6 +110,18 @@ def absorbing_eigenmode(orc):
     P.test_absorbing_pure_diffusion_eigenmode(orc)
 
 
+def electron_dense(orc):
+    PE.test_electron_step_matches_dense_matrix_scheme(orc, (4, 4, 5))
+
+
+def electron_dt_drift(orc):
+    PE.test_electron_dt_pure_drift_is_one_cell_per_step(orc)
+
+
+def electron_dt_diffusion(orc):
+    PE.test_electron_dt_pure_diffusion_closed_form(orc)
+
+
 def train_periods(orc):
     PT.test_train_steps_whole_periods(orc)
 
@@ -197,6 +210,21 @@ MUTANTS = {
         "if (jj < 0 || jj >= ny || ii < 0 || ii >= nx) return 0.0;",
         "if (jj < 0 || jj >= ny || ii < 0 || ii >= nx) { jj = (jj + ny) % ny; ii = (ii + nx) % nx; }", 1,
         [dense_absorbing, absorbing_eigenmode]),
+    "positive ions spared the electron sink": (
+        "const double sinks[3] = {sink_n + sink_e, sink_n, sink_e};",
+        "const double sinks[3] = {sink_n, sink_n, sink_e};", 1,
+        [electron_dense]),
+    "electrons drift with the positive ions": (
+        "const double mus[3] = {p[P_MU_POS], -p[P_MU_NEG], -p[P_MU_E]};",
+        "const double mus[3] = {p[P_MU_POS], -p[P_MU_NEG], p[P_MU_E]};", 1,
+        [electron_dense]),
+    "electron step without the diffusion factor 2": (
+        "const double A = 2.0 * p[P_D_E] * (1.0 / (p[P_DX] * p[P_DX])",
+        "const double A = p[P_D_E] * (1.0 / (p[P_DX] * p[P_DX])", 1,
+        [electron_dt_diffusion]),
+    "electron step from the ion mobility": (
+        "const double v = p[P_MU_E] * E / dz;", "const double v = p[P_MU_NEG] * E / dz;", 1,
+        [electron_dt_drift]),
     "train period one step longer than its steps": (
         "dt = period / (double)m;", "dt = period / (double)(m + 1);", 1,
         [train_periods]),
