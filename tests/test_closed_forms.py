@@ -101,3 +101,22 @@ def test_heavy_ions_recombine_more_than_protons():
     fs = {k: cf.jaffe_parallel(v["let_keV_um"], v["b_um"] * 1e-4, 2000.0, 0.2, D, mu, t2["alpha_cm3_s"])
           for k, v in t1.items()}
     assert fs["Fe40"] < fs["Ne60"] < fs["C90"] < fs["p100"]
+
+
+@pytest.mark.parametrize("p", [0.1, 0.5, 0.9])
+def test_boag_models_small_and_large_dose_expansions(p):
+    """Expansions of the three free-electron models, worked out by hand from
+    their formulas: at small u the loss is linear, 1 - f = k u / 2 with
+    k = 1 - p (model 1), (1 - p)^2 (model 2), (1 - p)^(3/2) (model 3, whose
+    lambda = 1 - sqrt(1 - p)); at large u only the free electrons survive,
+    f -> p, with the first correction -ln(p)/u (model 1), ln((1 - p) u)/u
+    (model 2) and -ln(lambda)/u (model 3)."""
+    u = 1e-6
+    for m, k in ((cf.boag_model1, 1 - p), (cf.boag_model2, (1 - p) ** 2), (cf.boag_model3, (1 - p) ** 1.5)):
+        assert (1.0 - m(u, p)) / u == pytest.approx(k / 2, rel=1e-4)
+    lam = 1.0 - math.sqrt(1.0 - p)
+    u = 400.0 / p  # e^{p u} stays finite
+    assert cf.boag_model1(u, p) - p == pytest.approx(-math.log(p) / u, rel=1e-6)
+    u2 = 1e8  # model 2 has no exponential: a dose far out on the asymptote
+    assert cf.boag_model2(u2, p) - p == pytest.approx(math.log((1 - p) * u2) / u2, rel=1e-6)
+    assert cf.boag_model3(u, p) - p == pytest.approx(-math.log(lam) / u, rel=1e-6)

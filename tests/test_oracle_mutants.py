@@ -7,6 +7,7 @@ length of the case, and requires every pin named for the mistake to fail.
 The same pins pass on the oracle itself (the control case, and the pin
 files).  Nothing here touches the committed oracle or its built library.
 """
+import math
 import os
 import subprocess
 
@@ -305,3 +306,23 @@ def test_reference_network_mistakes_fail_the_torch_pin(mistake, monkeypatch):
     M.test_backward_matches_finite_differences()  # still self-consistent
     with pytest.raises(AssertionError):
         M.test_forward_and_gradient_match_a_torch_network()
+
+
+# The closed forms (oracle/closed_forms.py): a version of Boag's second
+# free-electron model that keeps both limits p = 0 (the two-voltage
+# formula) and p = 1 (everything collected) yet differs in between; the
+# expansion pin sees it.
+def _model2_linear(u, p):
+    return p + (1.0 - p) * math.log1p(u) / u
+
+
+@pytest.mark.parametrize("name,fn", [("boag_model2", _model2_linear)])
+def test_closed_form_mistakes_fail_the_expansion_pin(name, fn, monkeypatch):
+    import test_closed_forms as C
+    from oracle import closed_forms
+    monkeypatch.setattr(closed_forms, name, fn)
+    C.test_boag_models_reduce_to_two_voltage_method_at_p0()  # the old limits still hold
+    C.test_boag_models_all_free_electrons_collect_everything()
+    with pytest.raises(AssertionError):
+        for p in (0.1, 0.5, 0.9):
+            C.test_boag_models_small_and_large_dose_expansions(p)
