@@ -19,6 +19,11 @@ def _cases():
     yield "space_charge", dict(ch, space_charge=1, uniform_n0=0.0), W.tracks([[5.0, 8e-4, 5e-3, 1.5e-3, 0, 0, 0]])
     fe = dict(ch, mu_e=1500.0, D_e=37.9, attach_coeff=5.0, max_steps=400)
     yield "free_electrons", fe, tr[:2]
+    dt1 = oracle.dt(ch, tr[:2])
+    train = dict(ch, n_pulses=4, pulse_period_s=17.3 * dt1, max_steps=10**6)
+    yield "pulse_train", train, tr[:2]
+    yield "absorbing_train_space_charge", dict(train, lateral_bc=1, space_charge=1, uniform_n0=0.0), \
+        W.tracks([[5.0, 8e-4, 5e-3, 1.5e-3, 0, 0, 0]])
 
 
 @pytest.mark.parametrize("name,ch,tr", list(_cases()), ids=[c[0] for c in _cases()])
@@ -31,6 +36,8 @@ def test_openmp_build_gives_the_same_bits(name, ch, tr):
         finally:
             oracle.use_threads(False)
     a, b = out[False], out[True]
+    if ch.get("n_pulses", 0) >= 2:
+        assert a["pulses"] == ch["n_pulses"] and a["flags"] == 0
     assert a.keys() == b.keys()
     for k in a:
         if isinstance(a[k], np.ndarray):
