@@ -166,6 +166,16 @@ def continuous_run(it, W, beam_s):
             "current_trace_points": int(len(cur))}
 
 
+def run_section(name, fn):
+    """The dict of one extra section of the line, or {"error": ...} when it
+    raised (after its message went to stderr)."""
+    try:
+        return fn()
+    except Exception as e:  # reported in the line itself
+        progress(f"{name}: failed: {e!r}")
+        return {"error": repr(e)}
+
+
 def progress(msg):
     """A progress line on stderr (stdout carries only the result line)."""
     print(msg, file=sys.stderr, flush=True)
@@ -338,13 +348,15 @@ def main():
                                            f"scaled the same way"}}
         progress("cpu baseline done")
 
-    pulsed = None
-    if not a.no_pulsed:
-        pulsed = pulsed_runs(it, W, ex)
-        progress(f"pulsed beam: {pulsed['seconds_per_run']:.3f} s per run")
+    # The sections below extend the line beyond the headline; one that raises
+    # is reported in its own field ({"error": ...}) so that the measured
+    # headline above is still printed.
+    def pulsed_section():
+        r = pulsed_runs(it, W, ex)
+        progress(f"pulsed beam: {r['seconds_per_run']:.3f} s per run")
+        return r
 
-    sweep = None
-    if not a.no_sweep:
+    def sweep_section():
         from paper_1610_06749_amd import autotune
         chs, trs = W.batched_sweep()
         it.it_solve_batch(chs[:4], trs[:4])  # warm-up (graph instantiation path)
@@ -357,27 +369,31 @@ def main():
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         vs = sum(r["steps"] * c["nx"] * c["ny"] * (c["nz"] - 1) for r, c in zip(res, chs))
-        sweep = {"workload": "96 chambers, transverse 64-256, gap 50-250 intervals, 50-400 V, "
-                             "LET 1-500 keV/um, 1-500 tracks and 0.01-1 mGy per pulse",
-                 "seconds": sec, "voxel_steps": vs, "voxel_steps_per_s": vs / sec,
-                 "frac_of_hbm_peak": vs / sec * BYTES_PER_VOXEL_STEP / 1e9 / PEAK_HBM_GBS,
-                 "ks_evals_per_s": len(chs) / sec, "max_steps": max(r["steps"] for r in res),
-                 "flags": sorted({r["flags"] for r in res}), "exec": ex_sweep,
-                 "tuning_seconds": tune_sec}
         progress(f"sweep: {sec:.1f} s")
+        return {"workload": "96 chambers, transverse 64-256, gap 50-250 intervals, 50-400 V, "
+                            "LET 1-500 keV/um, 1-500 tracks and 0.01-1 mGy per pulse",
+                "seconds": sec, "voxel_steps": vs, "voxel_steps_per_s": vs / sec,
+                "frac_of_hbm_peak": vs / sec * BYTES_PER_VOXEL_STEP / 1e9 / PEAK_HBM_GBS,
+                "ks_evals_per_s": len(chs) / sec, "max_steps": max(r["steps"] for r in res),
+                "flags": sorted({r["flags"] for r in res}), "exec": ex_sweep,
+                "tuning_seconds": tune_sec}
 
-    cont = None
-    if a.continuous_ms > 0:
-        cont = continuous_run(it, W, a.continuous_ms * 1e-3)
-        progress(f"continuous beam: {cont['seconds']:.1f} s")
+    def continuous_section():
+        r = continuous_run(it, W, a.continuous_ms * 1e-3)
+        progress(f"continuous beam: {r['seconds']:.1f} s")
+        return r
 
-    sur = None
-    if not a.no_surrogate:
+    def surrogate_section():
         from paper_1610_06749_amd import surrogate
         # the answer timed at the default spread tolerance (1e-3 in ln k_s) and,
         # for the trade-off, at tighter and looser ones
-        sur = surrogate.evaluate(n_train=a.surrogate_train, steps=a.surrogate_steps, log=progress,
-                                 extra_tols=(5e-4, 2e-3, 4e-3), time_extra=True, n_overlap=a.surrogate_overlap)
+        return surrogate.evaluate(n_train=a.surrogate_train, steps=a.surrogate_steps, log=progress,
+                                  extra_tols=(5e-4, 2e-3, 4e-3), time_extra=True, n_overlap=a.surrogate_overlap)
+
+    pulsed = None if a.no_pulsed else run_section("pulsed", pulsed_section)
+    sweep = None if a.no_sweep else run_section("sweep", sweep_section)
+    cont = run_section("continuous", continuous_section) if a.continuous_ms > 0 else None
+    sur = None if a.no_surrogate else run_section("surrogate", surrogate_section)
 
     out = {
         "metric": METRIC,

@@ -38,3 +38,19 @@ def test_source_hash_ignores_comments(tmp_path):
     assert bench.kernel_source_hash(["k.hip"], str(tmp_path)) == h
     (tmp_path / "k.hip").write_text(code.replace("1.0", "2.0"))
     assert bench.kernel_source_hash(["k.hip"], str(tmp_path)) != h
+
+
+def test_a_failing_extra_section_is_reported_in_the_line(capsys):
+    """An extra section that raises becomes {"error": ...} in its field (the
+    headline measured before it is still printed); one that works returns
+    its dict."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    def broken():
+        raise RuntimeError("it_solve_batch: stand-in failure")
+    assert bench.run_section("sweep", lambda: {"seconds": 1.0}) == {"seconds": 1.0}
+    out = bench.run_section("sweep", broken)
+    assert "stand-in failure" in out["error"]
+    assert "sweep: failed" in capsys.readouterr().err
+    json.dumps(out)
